@@ -1,0 +1,256 @@
+"""CPU oracle for the shallow-basin PCG solves.  TEST INFRASTRUCTURE ONLY.
+
+Only the test suite, the smoke check and the CPU-baseline leg of the benchmark
+may import this package.  It shares no code with the HIP library: the
+arithmetic lives in `hns_oracle.c` (plain FP64 C, compiled by `build()`), and
+this module only marshals arrays to it.  See the header of `hns_oracle.c` for
+the paper passages each routine follows.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "hns_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+OK, NOT_CONVERGED, ERR_INVALID, ERR_NOMEM, ERR_MESH, ERR_BREAKDOWN = 0, 1, -1, -3, -4, -5
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain -O2, no fused multiply-add contraction)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.run(["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fPIC", "-shared",
+                        "-Wall", "-o", tmp, _SRC, "-lm"], check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = C.CDLL(_LIB)
+        dp, ip, i64p, u8p = (C.POINTER(C.c_double), C.POINTER(C.c_int32),
+                             C.POINTER(C.c_int64), C.POINTER(C.c_uint8))
+        vp = C.c_void_p
+        L.or_element.restype = C.c_double
+        L.or_element.argtypes = [dp, dp, dp, dp, dp]
+        L.or_assemble.restype = C.c_int
+        L.or_assemble.argtypes = [C.c_int64, dp, C.c_int64, ip, C.c_int, C.c_double,
+                                  C.c_double, C.c_double, C.c_double, C.c_int, C.POINTER(vp)]
+        L.or_assemble_surface_mass.restype = C.c_int
+        L.or_assemble_surface_mass.argtypes = [C.c_int64, dp, C.c_int64, ip, C.POINTER(vp)]
+        L.or_csr_free.argtypes = [vp]
+        L.or_csr_n.restype = C.c_int64
+        L.or_csr_n.argtypes = [vp]
+        L.or_csr_nnz.restype = C.c_int64
+        L.or_csr_nnz.argtypes = [vp]
+        L.or_csr_copy_out.argtypes = [vp, i64p, ip, dp]
+        L.or_spmv.argtypes = [vp, dp, dp]
+        L.or_spmv_t.argtypes = [vp, dp, dp, C.c_int64]
+        L.or_pcg.restype = C.c_int
+        L.or_pcg.argtypes = [vp, u8p, C.c_int, dp, dp, dp, C.c_double, C.c_int,
+                             C.POINTER(C.c_int), dp, dp, dp, dp, dp]
+        L.or_relres.restype = C.c_double
+        L.or_relres.argtypes = [vp, u8p, dp, dp]
+        L.or_cholesky_solve.restype = C.c_int
+        L.or_cholesky_solve.argtypes = [C.c_int64, dp, dp, dp]
+        _lib = L
+    return _lib
+
+
+def _d(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _i(a):
+    return a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+def _u8(a):
+    return None if a is None else a.ctypes.data_as(C.POINTER(C.c_uint8))
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+class Matrix:
+    """An oracle-owned CSR matrix (freed with the object)."""
+
+    def __init__(self, handle):
+        self._h = C.c_void_p(handle)
+        self.n = int(lib().or_csr_n(self._h))
+        self.nnz = int(lib().or_csr_nnz(self._h))
+
+    def __del__(self):
+        if getattr(self, "_h", None) is not None and _lib is not None:
+            _lib.or_csr_free(self._h)
+            self._h = None
+
+    def arrays(self):
+        rowptr = np.empty(self.n + 1, np.int64)
+        col = np.empty(self.nnz, np.int32)
+        val = np.empty(self.nnz, np.float64)
+        lib().or_csr_copy_out(self._h, rowptr.ctypes.data_as(C.POINTER(C.c_int64)),
+                              _i(col), _d(val))
+        return rowptr, col, val
+
+    def to_scipy(self):
+        import scipy.sparse as sp
+        rowptr, col, val = self.arrays()
+        return sp.csr_matrix((val, col, rowptr), shape=(self.n, self.n))
+
+    def matvec(self, x):
+        x = _f64(x)
+        y = np.empty(self.n, np.float64)
+        lib().or_spmv(self._h, _d(x), _d(y))
+        return y
+
+    def rmatvec(self, x, ncols):
+        x = _f64(x)
+        y = np.empty(ncols, np.float64)
+        lib().or_spmv_t(self._h, _d(x), _d(y), ncols)
+        return y
+
+
+def element(X, nu=(1.0, 1.0, 1.0)):
+    """Element matrices of one tetrahedron: (vol, K 4x4, M 4x4, B 3x4x4)."""
+    X = _f64(X).reshape(4, 3)
+    nu = _f64(nu)
+    K = np.empty(16)
+    M = np.empty(16)
+    B = np.empty(48)
+    vol = lib().or_element(_d(X), _d(nu), _d(K), _d(M), _d(B))
+    return vol, K.reshape(4, 4), M.reshape(4, 4), B.reshape(3, 4, 4)
+
+
+class OracleError(RuntimeError):
+    def __init__(self, status, what):
+        super().__init__(f"{what}: oracle status {status}")
+        self.status = status
+
+
+def _assemble(xyz, tets, form, nu_h=0.0, nu_v=0.0, c_mass=0.0, c_stiff=0.0, comp=0):
+    xyz = _f64(xyz)
+    tets = np.ascontiguousarray(tets, dtype=np.int32)
+    h = C.c_void_p()
+    st = lib().or_assemble(xyz.shape[0], _d(xyz), tets.shape[0], _i(tets), form, nu_h, nu_v,
+                           c_mass, c_stiff, comp, C.byref(h))
+    if st != OK:
+        raise OracleError(st, "assemble")
+    return Matrix(h.value)
+
+
+def operator(mesh, nu_h, nu_v, c_mass, c_stiff):
+    """c_mass * M + c_stiff * K_nu over the mesh (volume forms of Sec. 4/5)."""
+    return _assemble(mesh.xyz, mesh.tets, 0, nu_h, nu_v, c_mass, c_stiff)
+
+
+def helmholtz(mesh, nu_h, nu_v, dt):
+    """Velocity-prediction operator M + dt*K_nu (one implicit Euler step)."""
+    return operator(mesh, nu_h, nu_v, 1.0, dt)
+
+
+def stiffness(mesh, nu_h, nu_v):
+    """Anisotropic stiffness K_nu (pressure-increment operator)."""
+    return operator(mesh, nu_h, nu_v, 0.0, 1.0)
+
+
+def mass(mesh):
+    return operator(mesh, 0.0, 0.0, 1.0, 0.0)
+
+
+def divergence(mesh, comp):
+    """B_c with (B_c)_ij = int phi_i d phi_j / d x_c."""
+    return _assemble(mesh.xyz, mesh.tets, 1, comp=comp)
+
+
+def surface_mass(mesh):
+    xyz = _f64(mesh.xyz)
+    tris = np.ascontiguousarray(mesh.surf_tris, dtype=np.int32)
+    h = C.c_void_p()
+    st = lib().or_assemble_surface_mass(xyz.shape[0], _d(xyz), tris.shape[0], _i(tris),
+                                        C.byref(h))
+    if st != OK:
+        raise OracleError(st, "surface mass")
+    return Matrix(h.value)
+
+
+@dataclass
+class PCGResult:
+    x: np.ndarray
+    status: int
+    iterations: int
+    relres: float
+    removed_mean: float
+    alphas: np.ndarray | None = None
+    betas: np.ndarray | None = None
+    x_hist: np.ndarray | None = None
+
+
+def pcg(A: Matrix, b, dirichlet=None, singular=False, weights=None, x0=None,
+        tol=1e-10, maxit=100000, history=False, x_history=False) -> PCGResult:
+    """Jacobi-PCG on A after eliminating `dirichlet` nodes (boolean (n,) or None)."""
+    n = A.n
+    b = _f64(b)
+    x = np.zeros(n) if x0 is None else _f64(x0).copy()
+    dmask = None if dirichlet is None else np.ascontiguousarray(dirichlet, dtype=np.uint8)
+    w = None if weights is None else _f64(weights)
+    it = C.c_int(0)
+    rel = np.zeros(1)
+    rm = np.zeros(1)
+    ah = np.zeros(maxit) if history else None
+    bh = np.zeros(maxit) if history else None
+    xh = np.zeros((maxit, n)) if x_history else None
+    st = lib().or_pcg(A._h, _u8(dmask), int(bool(singular)), None if w is None else _d(w),
+                      _d(b), _d(x), tol, maxit, C.byref(it), _d(rel), _d(rm),
+                      None if ah is None else _d(ah), None if bh is None else _d(bh),
+                      None if xh is None else _d(xh))
+    k = it.value
+    return PCGResult(x=x, status=st, iterations=k, relres=float(rel[0]), removed_mean=float(rm[0]),
+                     alphas=None if ah is None else ah[:k], betas=None if bh is None else bh[:k],
+                     x_hist=None if xh is None else xh[:k])
+
+
+def relres(A: Matrix, b, x, dirichlet=None) -> float:
+    b = _f64(b)
+    x = _f64(x)
+    dmask = None if dirichlet is None else np.ascontiguousarray(dirichlet, dtype=np.uint8)
+    return float(lib().or_relres(A._h, _u8(dmask), _d(b), _d(x)))
+
+
+def cholesky_solve(A_dense, b):
+    A_dense = _f64(A_dense)
+    b = _f64(b)
+    n = b.shape[0]
+    x = np.empty(n)
+    st = lib().or_cholesky_solve(n, _d(A_dense), _d(b), _d(x))
+    if st != OK:
+        raise OracleError(st, "cholesky")
+    return x
+
+
+def lanczos_condition(alphas, betas):
+    """Extreme-eigenvalue ratio of the preconditioned operator from the CG
+    coefficients (the Lanczos tridiagonal matrix built from alpha and beta)."""
+    k = len(alphas)
+    if k == 0:
+        return 1.0
+    T = np.zeros((k, k))
+    for j in range(k):
+        T[j, j] = 1.0 / alphas[j] + (betas[j - 1] / alphas[j - 1] if j > 0 else 0.0)
+        if j + 1 < k:
+            T[j, j + 1] = T[j + 1, j] = np.sqrt(max(betas[j], 0.0)) / alphas[j]
+    ev = np.linalg.eigvalsh(T)
+    return float(ev[-1] / ev[0])

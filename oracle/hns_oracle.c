@@ -1,0 +1,618 @@
+/*
+ * CPU oracle for the shallow-basin PCG solves.  TEST INFRASTRUCTURE ONLY.
+ *
+ * Only the test suite, the smoke check and the CPU-baseline leg of the
+ * benchmark may load this library.  It shares no source with the HIP library:
+ * it assembles the P1 operators itself, eliminates Dirichlet nodes explicitly
+ * and runs a textbook Jacobi-preconditioned conjugate gradient, all in plain
+ * FP64 with no blocking, fusion or reordering.
+ *
+ * What it computes (paper sections cited per function):
+ *   - P1 element matrices on a tetrahedron: the bilinear forms of the
+ *     velocity-prediction problem (Sec. 4/5, eq. fofa_velo_pred_h: mass
+ *     term and anisotropic viscous term with nu = diag(nu1,nu2,nu3)), of the
+ *     pressure-increment problem (eq. fofa_q_cor_h: gradient-gradient term)
+ *     and the divergence coupling int (d u_c / d x_c) phi (right-hand side
+ *     of eq. fofa_q_cor_h, and the pressure term int p div v of
+ *     eq. fofa_velo_pred_h through its transpose);
+ *   - assembly of those forms into compressed sparse rows;
+ *   - the surface-tension load int_{Gamma_s} theta v ds (eq. fofa_velo_pred_h);
+ *   - preconditioned conjugate gradients with a diagonal preconditioner
+ *     (Remark 1 and the DIAG part of Remark 2 at the end of Sec. 5);
+ *   - a dense Cholesky factorisation for tiny systems.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_OK 0
+#define OR_NOT_CONVERGED 1
+#define OR_ERR_INVALID (-1)
+#define OR_ERR_MESH (-4)
+#define OR_ERR_BREAKDOWN (-5)
+#define OR_ERR_NOMEM (-3)
+
+/* ------------------------------------------------------------------------ */
+/* Element matrices                                                          */
+/* ------------------------------------------------------------------------ */
+
+/* Gradients of the four barycentric (P1 hat) functions of a tetrahedron and
+ * its signed volume.  With J the 3x3 matrix whose columns are v1-v0, v2-v0,
+ * v3-v0, the barycentric coordinates l1,l2,l3 are J^{-1}(x - v0), so grad l_a
+ * (a = 1..3) is row a of J^{-1}, and grad l0 = -(grad l1 + grad l2 + grad l3).
+ * Returns the signed volume det(J)/6. */
+static double tet_gradients(const double X[4][3], double g[4][3])
+{
+    double J[3][3];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c)
+            J[r][c] = X[c + 1][r] - X[0][r];
+    double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1])
+               - J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0])
+               + J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+    if (det == 0.0) {
+        memset(g, 0, sizeof(double) * 12);
+        return 0.0;
+    }
+    /* inverse by the adjugate */
+    double inv[3][3];
+    inv[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) / det;
+    inv[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;
+    inv[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / det;
+    inv[1][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) / det;
+    inv[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / det;
+    inv[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det;
+    inv[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) / det;
+    inv[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / det;
+    inv[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
+    for (int a = 1; a < 4; ++a)
+        for (int d = 0; d < 3; ++d)
+            g[a][d] = inv[a - 1][d];
+    for (int d = 0; d < 3; ++d)
+        g[0][d] = -(g[1][d] + g[2][d] + g[3][d]);
+    return det / 6.0;
+}
+
+/* Element matrices of one tetrahedron.
+ *   K[a][b]    = vol * sum_d nu[d] g_a[d] g_b[d]     (int (nu grad phi_b).grad phi_a)
+ *   M[a][b]    = vol/20 * (1 + delta_ab)              (int phi_a phi_b, exact for P1)
+ *   B[c][a][b] = vol/4 * g_b[c]                       (int phi_a d phi_b / d x_c)
+ * Any output pointer may be NULL.  Returns the signed volume. */
+double or_element(const double *X12, const double *nu, double *K, double *M,
+                  double *B)
+{
+    double X[4][3], g[4][3];
+    memcpy(X, X12, sizeof(X));
+    double vol = tet_gradients(X, g);
+    for (int a = 0; a < 4; ++a)
+        for (int b = 0; b < 4; ++b) {
+            if (K) {
+                double s = 0.0;
+                for (int d = 0; d < 3; ++d)
+                    s += nu[d] * (g[a][d] * g[b][d]);
+                K[a * 4 + b] = vol * s;
+            }
+            if (M)
+                M[a * 4 + b] = vol / 20.0 * (a == b ? 2.0 : 1.0);
+            if (B)
+                for (int c = 0; c < 3; ++c)
+                    B[c * 16 + a * 4 + b] = vol / 4.0 * g[b][c];
+        }
+    return vol;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Assembly into CSR                                                         */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int64_t n, nnz;
+    int64_t *rowptr; /* n+1 */
+    int32_t *col;    /* nnz */
+    double *val;     /* nnz */
+} or_csr;
+
+void or_csr_free(or_csr *A)
+{
+    if (!A) return;
+    free(A->rowptr);
+    free(A->col);
+    free(A->val);
+    free(A);
+}
+
+int64_t or_csr_n(const or_csr *A) { return A->n; }
+int64_t or_csr_nnz(const or_csr *A) { return A->nnz; }
+void or_csr_copy_out(const or_csr *A, int64_t *rowptr, int32_t *col, double *val)
+{
+    memcpy(rowptr, A->rowptr, sizeof(int64_t) * (A->n + 1));
+    memcpy(col, A->col, sizeof(int32_t) * A->nnz);
+    memcpy(val, A->val, sizeof(double) * A->nnz);
+}
+
+/* Collects element contributions (row, col, value) bucketed by row, then sorts
+ * each row by column and sums duplicates.  `nloc` local dofs per element. */
+typedef struct {
+    int64_t n;
+    int64_t *start; /* n+1: bucket offsets */
+    int64_t *fill;  /* n: next free slot per bucket */
+    int32_t *c;
+    double *v;
+} triplets;
+
+static int trip_init(triplets *t, int64_t n, int64_t nel, int nloc, const int32_t *conn)
+{
+    t->n = n;
+    t->start = calloc((size_t)n + 1, sizeof(int64_t));
+    t->fill = malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    if (!t->start || !t->fill) return OR_ERR_NOMEM;
+    for (int64_t e = 0; e < nel; ++e)
+        for (int a = 0; a < nloc; ++a)
+            t->start[conn[e * nloc + a] + 1] += nloc;
+    for (int64_t i = 0; i < n; ++i)
+        t->start[i + 1] += t->start[i];
+    for (int64_t i = 0; i < n; ++i)
+        t->fill[i] = t->start[i];
+    int64_t tot = t->start[n];
+    t->c = malloc(sizeof(int32_t) * (size_t)(tot > 0 ? tot : 1));
+    t->v = malloc(sizeof(double) * (size_t)(tot > 0 ? tot : 1));
+    if (!t->c || !t->v) return OR_ERR_NOMEM;
+    return OR_OK;
+}
+
+static void trip_add(triplets *t, int32_t r, int32_t c, double v)
+{
+    int64_t s = t->fill[r]++;
+    t->c[s] = c;
+    t->v[s] = v;
+}
+
+static void trip_free(triplets *t)
+{
+    free(t->start);
+    free(t->fill);
+    free(t->c);
+    free(t->v);
+}
+
+/* Sort every bucket by column (insertion sort, buckets are short) and sum
+ * duplicate columns into a fresh CSR matrix. */
+static or_csr *trip_to_csr(triplets *t)
+{
+    int64_t n = t->n;
+    int64_t nnz = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t lo = t->start[i], hi = t->start[i + 1];
+        for (int64_t s = lo + 1; s < hi; ++s) {
+            int32_t c = t->c[s];
+            double v = t->v[s];
+            int64_t u = s - 1;
+            while (u >= lo && t->c[u] > c) {
+                t->c[u + 1] = t->c[u];
+                t->v[u + 1] = t->v[u];
+                --u;
+            }
+            t->c[u + 1] = c;
+            t->v[u + 1] = v;
+        }
+        for (int64_t s = lo; s < hi; ++s)
+            if (s == lo || t->c[s] != t->c[s - 1]) ++nnz;
+    }
+    or_csr *A = calloc(1, sizeof(or_csr));
+    if (!A) return NULL;
+    A->n = n;
+    A->nnz = nnz;
+    A->rowptr = malloc(sizeof(int64_t) * (size_t)(n + 1));
+    A->col = malloc(sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
+    A->val = malloc(sizeof(double) * (size_t)(nnz > 0 ? nnz : 1));
+    if (!A->rowptr || !A->col || !A->val) {
+        or_csr_free(A);
+        return NULL;
+    }
+    int64_t k = 0;
+    A->rowptr[0] = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t lo = t->start[i], hi = t->start[i + 1];
+        for (int64_t s = lo; s < hi; ++s) {
+            if (s == lo || t->c[s] != t->c[s - 1]) {
+                A->col[k] = t->c[s];
+                A->val[k] = t->v[s];
+                ++k;
+            } else {
+                A->val[k - 1] += t->v[s];
+            }
+        }
+        A->rowptr[i + 1] = k;
+    }
+    return A;
+}
+
+static int check_conn(int64_t n, int64_t nel, int nloc, const int32_t *conn)
+{
+    for (int64_t e = 0; e < nel * nloc; ++e)
+        if (conn[e] < 0 || conn[e] >= n) return OR_ERR_MESH;
+    return OR_OK;
+}
+
+/* Assemble one of the volume forms over the tetrahedral mesh.
+ *   form 0: c_mass * M + c_stiff * K_nu     with nu = (nu_h, nu_h, nu_v)
+ *   form 1: B_c  (c = comp in 0..2), the divergence coupling
+ * A tetrahedron with non-positive signed volume is a mesh error. */
+int or_assemble(int64_t n, const double *xyz, int64_t ntet, const int32_t *tets,
+                int form, double nu_h, double nu_v, double c_mass, double c_stiff,
+                int comp, or_csr **out)
+{
+    *out = NULL;
+    if (n <= 0 || ntet < 0) return OR_ERR_INVALID;
+    if (check_conn(n, ntet, 4, tets) != OR_OK) return OR_ERR_MESH;
+    triplets t;
+    memset(&t, 0, sizeof(t));
+    if (trip_init(&t, n, ntet, 4, tets) != OR_OK) {
+        trip_free(&t);
+        return OR_ERR_NOMEM;
+    }
+    const double nu[3] = {nu_h, nu_h, nu_v};
+    for (int64_t e = 0; e < ntet; ++e) {
+        double X[12], K[16], M[16], B[48];
+        for (int a = 0; a < 4; ++a)
+            for (int d = 0; d < 3; ++d)
+                X[a * 3 + d] = xyz[(int64_t)tets[e * 4 + a] * 3 + d];
+        double vol = or_element(X, nu, K, M, B);
+        if (!(vol > 0.0)) {
+            trip_free(&t);
+            return OR_ERR_MESH;
+        }
+        for (int a = 0; a < 4; ++a)
+            for (int b = 0; b < 4; ++b) {
+                double v = (form == 0) ? c_mass * M[a * 4 + b] + c_stiff * K[a * 4 + b]
+                                       : B[comp * 16 + a * 4 + b];
+                trip_add(&t, tets[e * 4 + a], tets[e * 4 + b], v);
+            }
+    }
+    *out = trip_to_csr(&t);
+    trip_free(&t);
+    return *out ? OR_OK : OR_ERR_NOMEM;
+}
+
+/* Mass matrix of the surface Gamma_s from its triangles: on a triangle of
+ * area A, int phi_a phi_b ds = A/12 * (1 + delta_ab). */
+int or_assemble_surface_mass(int64_t n, const double *xyz, int64_t ntri,
+                             const int32_t *tris, or_csr **out)
+{
+    *out = NULL;
+    if (check_conn(n, ntri, 3, tris) != OR_OK) return OR_ERR_MESH;
+    triplets t;
+    memset(&t, 0, sizeof(t));
+    if (trip_init(&t, n, ntri, 3, tris) != OR_OK) {
+        trip_free(&t);
+        return OR_ERR_NOMEM;
+    }
+    for (int64_t e = 0; e < ntri; ++e) {
+        const double *p0 = xyz + 3 * (int64_t)tris[3 * e];
+        const double *p1 = xyz + 3 * (int64_t)tris[3 * e + 1];
+        const double *p2 = xyz + 3 * (int64_t)tris[3 * e + 2];
+        double u[3], w[3], cr[3];
+        for (int d = 0; d < 3; ++d) {
+            u[d] = p1[d] - p0[d];
+            w[d] = p2[d] - p0[d];
+        }
+        cr[0] = u[1] * w[2] - u[2] * w[1];
+        cr[1] = u[2] * w[0] - u[0] * w[2];
+        cr[2] = u[0] * w[1] - u[1] * w[0];
+        double area = 0.5 * sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
+        if (!(area > 0.0)) {
+            trip_free(&t);
+            return OR_ERR_MESH;
+        }
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b)
+                trip_add(&t, tris[3 * e + a], tris[3 * e + b],
+                         area / 12.0 * (a == b ? 2.0 : 1.0));
+    }
+    *out = trip_to_csr(&t);
+    trip_free(&t);
+    return *out ? OR_OK : OR_ERR_NOMEM;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Sparse products and vector helpers                                        */
+/* ------------------------------------------------------------------------ */
+
+void or_spmv(const or_csr *A, const double *x, double *y)
+{
+    for (int64_t i = 0; i < A->n; ++i) {
+        double s = 0.0;
+        for (int64_t k = A->rowptr[i]; k < A->rowptr[i + 1]; ++k)
+            s += A->val[k] * x[A->col[k]];
+        y[i] = s;
+    }
+}
+
+/* y = A^T x */
+void or_spmv_t(const or_csr *A, const double *x, double *y, int64_t ncols)
+{
+    for (int64_t j = 0; j < ncols; ++j) y[j] = 0.0;
+    for (int64_t i = 0; i < A->n; ++i)
+        for (int64_t k = A->rowptr[i]; k < A->rowptr[i + 1]; ++k)
+            y[A->col[k]] += A->val[k] * x[i];
+}
+
+static double dot(int64_t n, const double *a, const double *b)
+{
+    double s = 0.0;
+    for (int64_t i = 0; i < n; ++i) s += a[i] * b[i];
+    return s;
+}
+
+/* v <- v - mean(v) * 1; returns the mean removed */
+static double remove_mean(int64_t n, double *v)
+{
+    double mean = 0.0;
+    for (int64_t i = 0; i < n; ++i) mean += v[i];
+    mean /= (double)n;
+    for (int64_t i = 0; i < n; ++i) v[i] -= mean;
+    return mean;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Dirichlet elimination                                                     */
+/* ------------------------------------------------------------------------ */
+
+/* Symmetric elimination of homogeneous Dirichlet nodes: a Dirichlet row
+ * becomes the identity row, and every entry in a Dirichlet column of a free
+ * row is removed, so the free block is unchanged and the matrix stays
+ * symmetric.  dirichlet[i] != 0 marks node i. */
+or_csr *or_eliminate(const or_csr *A, const uint8_t *dirichlet)
+{
+    or_csr *E = calloc(1, sizeof(or_csr));
+    if (!E) return NULL;
+    int64_t n = A->n;
+    E->n = n;
+    E->rowptr = malloc(sizeof(int64_t) * (size_t)(n + 1));
+    E->col = malloc(sizeof(int32_t) * (size_t)(A->nnz > 0 ? A->nnz : 1) + sizeof(int32_t) * (size_t)n);
+    E->val = malloc(sizeof(double) * (size_t)(A->nnz > 0 ? A->nnz : 1) + sizeof(double) * (size_t)n);
+    if (!E->rowptr || !E->col || !E->val) {
+        or_csr_free(E);
+        return NULL;
+    }
+    int64_t k = 0;
+    E->rowptr[0] = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (dirichlet && dirichlet[i]) {
+            E->col[k] = (int32_t)i;
+            E->val[k] = 1.0;
+            ++k;
+        } else {
+            for (int64_t s = A->rowptr[i]; s < A->rowptr[i + 1]; ++s) {
+                int32_t c = A->col[s];
+                if (dirichlet && dirichlet[c]) continue;
+                E->col[k] = c;
+                E->val[k] = A->val[s];
+                ++k;
+            }
+        }
+        E->rowptr[i + 1] = k;
+    }
+    E->nnz = k;
+    return E;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Jacobi-preconditioned conjugate gradient                                  */
+/* ------------------------------------------------------------------------ */
+
+/* Solves A x = b for the symmetric positive (semi-)definite matrix A after
+ * eliminating the nodes flagged in `dirichlet` (may be NULL), using
+ * conjugate gradients preconditioned by the inverse diagonal.
+ *
+ * singular != 0: A is the pure-Neumann pressure operator, whose null space is
+ * the constants; b is first projected onto the zero-sum vectors (its mean is
+ * returned in *removed_mean), every residual computed as b - A x is projected
+ * the same way (rounding in A x leaves a small constant part that CG on the
+ * singular system could not remove), and, after convergence, the solution is
+ * shifted so that its mass-weighted mean sum(m_i x_i) / sum(m_i) is zero,
+ * where m = `weights` (the row sums of the mass matrix).  This stands in for
+ * the zero-mean constraint of the pressure increment (Sec. 4, q in H^1/R;
+ * Remark 2 at the end of Sec. 5).
+ *
+ * Stopping rule: ||b - A x||_2 <= tol * ||b||_2 for the true residual; the
+ * recursively updated residual triggers the check and, if the true residual
+ * is still too large, replaces the recursive one (restart).
+ *
+ * x holds the initial guess on entry (Dirichlet entries are ignored and set to
+ * zero) and the last iterate on exit.  alpha_hist / beta_hist / x_hist may be
+ * NULL; otherwise they receive the step lengths, the direction updates and the
+ * iterates (maxit rows of n) of each iteration.
+ */
+int or_pcg(const or_csr *A0, const uint8_t *dirichlet, int singular,
+           const double *weights, const double *b0, double *x, double tol,
+           int maxit, int *iters_out, double *relres_out, double *removed_mean,
+           double *alpha_hist, double *beta_hist, double *x_hist)
+{
+    int64_t n = A0->n;
+    *iters_out = 0;
+    *relres_out = 0.0;
+    if (removed_mean) *removed_mean = 0.0;
+    for (int64_t i = 0; i < n; ++i)
+        if (!isfinite(b0[i])) return OR_ERR_INVALID;
+
+    or_csr *A = or_eliminate(A0, dirichlet);
+    double *b = malloc(sizeof(double) * (size_t)n);
+    double *r = malloc(sizeof(double) * (size_t)n);
+    double *z = malloc(sizeof(double) * (size_t)n);
+    double *p = malloc(sizeof(double) * (size_t)n);
+    double *q = malloc(sizeof(double) * (size_t)n);
+    double *dinv = malloc(sizeof(double) * (size_t)n);
+    int status = OR_NOT_CONVERGED;
+    if (!A || !b || !r || !z || !p || !q || !dinv) {
+        status = OR_ERR_NOMEM;
+        goto done;
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        int dir = dirichlet && dirichlet[i];
+        b[i] = dir ? 0.0 : b0[i];
+        if (dir) x[i] = 0.0;
+    }
+    if (singular) {
+        double mean = remove_mean(n, b);
+        if (removed_mean) *removed_mean = mean;
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        double d = 0.0;
+        for (int64_t s = A->rowptr[i]; s < A->rowptr[i + 1]; ++s)
+            if (A->col[s] == i) d = A->val[s];
+        if (!(d > 0.0)) {
+            status = OR_ERR_BREAKDOWN;
+            goto done;
+        }
+        dinv[i] = 1.0 / d;
+    }
+    double bnorm = sqrt(dot(n, b, b));
+    if (bnorm == 0.0) {
+        for (int64_t i = 0; i < n; ++i) x[i] = 0.0;
+        status = OR_OK;
+        goto done;
+    }
+    or_spmv(A, x, q);
+    for (int64_t i = 0; i < n; ++i) r[i] = b[i] - q[i];
+    if (singular) remove_mean(n, r);
+    for (int64_t i = 0; i < n; ++i) z[i] = dinv[i] * r[i];
+    for (int64_t i = 0; i < n; ++i) p[i] = z[i];
+    double rho = dot(n, r, z);
+    double relres = sqrt(dot(n, r, r)) / bnorm;
+    if (relres <= tol) {
+        status = OR_OK;
+        *relres_out = relres;
+        goto normalize;
+    }
+    int it = 0;
+    while (it < maxit) {
+        or_spmv(A, p, q);
+        double gamma = dot(n, p, q);
+        if (!(gamma > 0.0) || !isfinite(gamma)) {
+            status = OR_ERR_BREAKDOWN;
+            break;
+        }
+        double alpha = rho / gamma;
+        for (int64_t i = 0; i < n; ++i) x[i] += alpha * p[i];
+        for (int64_t i = 0; i < n; ++i) r[i] -= alpha * q[i];
+        if (alpha_hist) alpha_hist[it] = alpha;
+        if (x_hist) memcpy(x_hist + (int64_t)it * n, x, sizeof(double) * (size_t)n);
+        ++it;
+        relres = sqrt(dot(n, r, r)) / bnorm;
+        if (relres <= tol) {
+            or_spmv(A, x, q);
+            for (int64_t i = 0; i < n; ++i) q[i] = b[i] - q[i];
+            if (singular) remove_mean(n, q);
+            double true_rel = sqrt(dot(n, q, q)) / bnorm;
+            if (true_rel <= tol) {
+                relres = true_rel;
+                status = OR_OK;
+                if (beta_hist) beta_hist[it - 1] = 0.0;
+                break;
+            }
+            /* restart from the true residual */
+            memcpy(r, q, sizeof(double) * (size_t)n);
+            for (int64_t i = 0; i < n; ++i) z[i] = dinv[i] * r[i];
+            for (int64_t i = 0; i < n; ++i) p[i] = z[i];
+            rho = dot(n, r, z);
+            relres = true_rel;
+            if (beta_hist) beta_hist[it - 1] = 0.0;
+            continue;
+        }
+        for (int64_t i = 0; i < n; ++i) z[i] = dinv[i] * r[i];
+        double rho_new = dot(n, r, z);
+        double beta = rho_new / rho;
+        if (beta_hist) beta_hist[it - 1] = beta;
+        for (int64_t i = 0; i < n; ++i) p[i] = z[i] + beta * p[i];
+        rho = rho_new;
+    }
+    *iters_out = it;
+    *relres_out = relres;
+normalize:
+    if (singular && status >= 0 && weights) {
+        double wx = 0.0, ws = 0.0;
+        for (int64_t i = 0; i < n; ++i) {
+            wx += weights[i] * x[i];
+            ws += weights[i];
+        }
+        double shift = wx / ws;
+        for (int64_t i = 0; i < n; ++i) x[i] -= shift;
+    }
+done:
+    or_csr_free(A);
+    free(b);
+    free(r);
+    free(z);
+    free(p);
+    free(q);
+    free(dinv);
+    return status;
+}
+
+/* True relative residual ||mask(b - A x)|| / ||mask(b)|| with Dirichlet rows
+ * removed (a Dirichlet row's equation is x_i = 0, which the caller checks). */
+double or_relres(const or_csr *A, const uint8_t *dirichlet, const double *b,
+                 const double *x)
+{
+    double num = 0.0, den = 0.0;
+    for (int64_t i = 0; i < A->n; ++i) {
+        if (dirichlet && dirichlet[i]) continue;
+        double s = 0.0;
+        for (int64_t k = A->rowptr[i]; k < A->rowptr[i + 1]; ++k) {
+            int32_t c = A->col[k];
+            if (dirichlet && dirichlet[c]) continue;
+            s += A->val[k] * x[c];
+        }
+        double d = b[i] - s;
+        num += d * d;
+        den += b[i] * b[i];
+    }
+    return den > 0.0 ? sqrt(num / den) : sqrt(num);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Dense Cholesky for tiny systems                                           */
+/* ------------------------------------------------------------------------ */
+
+/* Solves the dense SPD system A x = b (row-major n x n) by A = L L^T.
+ * Returns OR_ERR_BREAKDOWN if a pivot is not positive. */
+int or_cholesky_solve(int64_t n, const double *A, const double *b, double *x)
+{
+    double *L = calloc((size_t)(n * n), sizeof(double));
+    double *y = malloc(sizeof(double) * (size_t)n);
+    if (!L || !y) {
+        free(L);
+        free(y);
+        return OR_ERR_NOMEM;
+    }
+    for (int64_t j = 0; j < n; ++j) {
+        double s = A[j * n + j];
+        for (int64_t k = 0; k < j; ++k) s -= L[j * n + k] * L[j * n + k];
+        if (!(s > 0.0)) {
+            free(L);
+            free(y);
+            return OR_ERR_BREAKDOWN;
+        }
+        L[j * n + j] = sqrt(s);
+        for (int64_t i = j + 1; i < n; ++i) {
+            double t = A[i * n + j];
+            for (int64_t k = 0; k < j; ++k) t -= L[i * n + k] * L[j * n + k];
+            L[i * n + j] = t / L[j * n + j];
+        }
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        double t = b[i];
+        for (int64_t k = 0; k < i; ++k) t -= L[i * n + k] * y[k];
+        y[i] = t / L[i * n + i];
+    }
+    for (int64_t i = n - 1; i >= 0; --i) {
+        double t = y[i];
+        for (int64_t k = i + 1; k < n; ++k) t -= L[k * n + i] * x[k];
+        x[i] = t / L[i * n + i];
+    }
+    free(L);
+    free(y);
+    return OR_OK;
+}
