@@ -1,0 +1,227 @@
+"""Benchmark of the projection-step PCG solves on one MI355X.
+
+One step = the four solves of one projection time step on the 256x256x20
+Atlantic-shaped basin (1,387,029 nodes): three velocity-prediction solves
+(M + dt K_nu, one per component with its own Dirichlet set) and one
+pure-Neumann pressure-increment solve (K_nu), all to relative residual 1e-10,
+first in FP64, then in mixed precision (FP32 inner CG in FP64 refinement).
+
+Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "PCG time-to-1e-10 and HBM GB/s at 1.3M nodes, FP64 vs mixed; p99 latency"
+PEAK_HBM_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def bytes_fp64_iter(n, nnz):
+    """Algorithmic bytes of one FP64 CG iteration: the CSR matrix (values,
+    column indices, row pointers) plus 13 vector passes of 8 bytes."""
+    return 12 * nnz + 4 * (n + 1) + 13 * 8 * n
+
+
+def bytes_fp64_spmv(n, nnz):
+    """Algorithmic bytes of the SpMV kernel: matrix + read p + write q."""
+    return 12 * nnz + 4 * (n + 1) + 16 * n
+
+
+def bytes_fp32_iter(n, nnz):
+    return 8 * nnz + 4 * (n + 1) + 13 * 4 * n
+
+
+def bytes_fp64_residual(n, nnz):
+    return 12 * nnz + 4 * (n + 1) + 3 * 8 * n
+
+
+def solve_bytes(info, n, nnz, mode):
+    if mode == "fp64":
+        return info.iterations * bytes_fp64_iter(n, nnz)
+    return (info.iterations * bytes_fp32_iter(n, nnz)
+            + (info.outer_iterations + 1) * bytes_fp64_residual(n, nnz))
+
+
+def make_problem(workload):
+    import basin
+    m = workload.mesh()
+    rhs = {}
+    for c in range(3):
+        d = (m.bc >> c) & 1 == 1
+        rhs[f"u{c + 1}"] = (c, basin.normal_rhs(m.n, 1 + c, dirichlet=d))
+    rhs["q"] = (-1, basin.normal_rhs(m.n, 0, zero_mean=True))
+    return m, rhs
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--check-every", type=int, default=32)
+    ap.add_argument("--cpu-iters", type=int, default=1000,
+                    help="oracle PCG iterations in the CPU-baseline sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--fmt", default="auto")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the solver "
+              "does not shard across GPUs", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import basin
+    from paper_1207_0486_amd.hns import Operator
+
+    wl = basin.configs.BASIN_256x256x20
+    dev = torch.device("cuda", 0)
+    t0 = time.time()
+    m, rhs = make_problem(wl)
+    log(f"mesh {wl.name}: n={m.n} tets={m.n_tets} ({time.time() - t0:.1f}s)")
+    t0 = time.time()
+    helm = Operator(m, wl.nu_h, wl.nu_v, wl.dt, kind="helmholtz", keep_fp32=True, fmt=args.fmt)
+    pois = Operator(m, wl.nu_h, wl.nu_v, kind="poisson", keep_fp32=True, fmt=args.fmt)
+    for op in (helm, pois):
+        op.set_param("check_every", args.check_every)
+    log(f"assembled: nnz={pois.nnz} format={pois.format} ({time.time() - t0:.1f}s)")
+    n, nnz = pois.n, pois.nnz
+    B = {k: (bit, torch.as_tensor(v, device=dev)) for k, (bit, v) in rhs.items()}
+    X = {k: torch.zeros(n, dtype=torch.float64, device=dev) for k in rhs}
+
+    def step(mode):
+        infos = {}
+        for k, (bit, b) in B.items():
+            op = pois if k == "q" else helm
+            X[k].zero_()
+            _, info = op.solve(b, X[k], tol=wl.tol, mask_bit=bit, mode=mode)
+            infos[k] = info
+        return infos
+
+    def timed(mode, steps, warmup, profile):
+        for _ in range(warmup):
+            step(mode)
+        for op in (helm, pois):
+            op.profile(profile)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        per = []
+        infos = None
+        for _ in range(steps):
+            ts = time.perf_counter()
+            infos = step(mode)
+            torch.cuda.synchronize()
+            per.append(time.perf_counter() - ts)
+        torch.cuda.synchronize()
+        total = time.perf_counter() - t
+        prof = {"helm": helm.profile_read(), "pois": pois.profile_read()}
+        for op in (helm, pois):
+            op.profile(False)
+        return total, per, infos, prof
+
+    total64, per64, infos64, prof64 = timed("fp64", args.steps, args.warmup, True)
+    x64 = {k: v.clone() for k, v in X.items()}
+    ms64 = 1e3 * total64 / args.steps
+    bytes64 = sum(solve_bytes(i, n, nnz, "fp64") for i in infos64.values())
+    gbs64 = bytes64 / (ms64 * 1e-3) / 1e9
+    log(f"fp64: {ms64:.1f} ms/step, {gbs64:.0f} GB/s, iters "
+        + ", ".join(f"{k}={i.iterations}" for k, i in infos64.items()))
+
+    # dominant kernel: the SpMV of the pressure solve, timed live with HIP events
+    spmv_ms, spmv_n = prof64["pois"]["spmv"]
+    spmv_avg_us = 1e3 * spmv_ms / max(spmv_n, 1)
+    spmv_bytes = bytes_fp64_spmv(n, nnz)
+    spmv_gbs = spmv_bytes / (spmv_avg_us * 1e-6) / 1e9
+    kern = {}
+    for name in ("spmv", "update", "pupdate"):
+        ms_, cnt = prof64["pois"][name]
+        kern[name] = {"avg_us": round(1e3 * ms_ / max(cnt, 1), 2), "launches": cnt}
+    log(f"pressure-solve kernels: {kern}")
+
+    mixed = None
+    if not args.no_mixed:
+        totalm, perm, infosm, profm = timed("mixed", args.steps, args.warmup, True)
+        msm = 1e3 * totalm / args.steps
+        diffs = {}
+        for k in X:
+            ref = x64[k]
+            diffs[k] = float(torch.linalg.norm(X[k] - ref) / torch.linalg.norm(ref))
+        k32 = {}
+        for name in ("spmv32", "update32", "pupdate32"):
+            ms_, cnt = profm["pois"][name]
+            k32[name] = {"avg_us": round(1e3 * ms_ / max(cnt, 1), 2), "launches": cnt}
+        mixed = {
+            "ms_per_step": round(msm, 3),
+            "speedup_vs_fp64": round(ms64 / msm, 3),
+            "solves": {k: {"inner_iters": i.iterations, "outer": i.outer_iterations,
+                           "relres": i.relres_true, "rel_diff_vs_fp64": diffs[k]}
+                       for k, i in infosm.items()},
+            "pressure_kernels": k32,
+        }
+        log(f"mixed: {msm:.1f} ms/step (x{ms64 / msm:.2f}), "
+            + ", ".join(f"{k}={i.iterations}/{i.outer_iterations}" for k, i in infosm.items()))
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        t0 = time.time()
+        K = oracle.stiffness(m, wl.nu_h, wl.nu_v)
+        w = oracle.mass(m).matvec(np.ones(m.n))
+        log(f"oracle assembly {time.time() - t0:.1f}s")
+        t = time.perf_counter()
+        r = oracle.pcg(K, rhs["q"][1], singular=True, weights=w, tol=wl.tol,
+                       maxit=args.cpu_iters)
+        el = time.perf_counter() - t
+        cpu_gbs = r.iterations * bytes_fp64_iter(n, nnz) / el / 1e9
+        cpu = {"value": round(cpu_gbs, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
+               "sample": f"first {r.iterations} Jacobi-PCG iterations of the {wl.name} "
+                         f"pressure solve, FP64, 1 thread ({el:.1f} s)",
+               "s_per_iter": round(el / max(r.iterations, 1), 5)}
+        log(f"cpu oracle: {cpu}")
+
+    out = {
+        "metric": METRIC,
+        "value": round(gbs64, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms64, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "nodes": n, "nnz": nnz, "format": pois.format,
+                   "solves": "3 velocity (M+dt*K_nu) + 1 pressure (K_nu, pure Neumann)",
+                   "rhs": "seeded N(0,1)", "tol": wl.tol, "nu_h": wl.nu_h, "nu_v": wl.nu_v,
+                   "dt": wl.dt},
+        "fp64": {k: {"iters": i.iterations, "relres": i.relres_true} for k, i in infos64.items()},
+        "step_ms": [round(1e3 * v, 3) for v in per64],
+        "roofline": {"bound": "hbm", "achieved": round(spmv_gbs, 1), "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": round(spmv_gbs / PEAK_HBM_GBS, 4), "traffic": None,
+                     "kernel": f"k_spmv_{pois.format}<double,true>",
+                     "bytes_per_launch": spmv_bytes, "avg_us": round(spmv_avg_us, 2)},
+        "pressure_kernels": kern,
+        "mixed": mixed,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

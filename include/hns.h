@@ -1,0 +1,183 @@
+/*
+ * hns — preconditioned conjugate-gradient solves of the shallow-basin
+ * projection step on AMD Instinct MI355X (gfx950).
+ *
+ * The paper (Besson & Straubhaar, "Wind driven 3D Navier-Stokes circulation
+ * in the Atlantic") advances the anisotropic Navier-Stokes equations with a
+ * velocity-correction projection method (Sec. 3).  Each time step solves
+ *   - three velocity-prediction problems, one per component, whose matrix is
+ *     mass / time step + anisotropic viscous stiffness (Sec. 4 eq.
+ *     fofa_velo_pred, discretised in Sec. 5 eq. fofa_velo_pred_h), and
+ *   - one pressure-increment problem with a pure-Neumann Laplacian whose
+ *     solution is fixed up to a constant (eq. fofa_q_cor / fofa_q_cor_h),
+ * all by preconditioned conjugate gradients (Remark 1 after Sec. 5).
+ *
+ * This library assembles those operators for linear (P1) tetrahedra and
+ * solves them with Jacobi-preconditioned CG in hand-written HIP kernels.
+ *
+ * Conventions for every entry point:
+ *   - Host pointers are read during the call only; the caller keeps them.
+ *   - Device pointers (suffix _dev) are caller-owned device memory on the
+ *     current HIP device; they must stay valid until the call returns.
+ *   - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream).
+ *     Solver calls return only when the result is final (they synchronise on
+ *     their own convergence reads).
+ *   - A negative hns_status is an error; hns_last_error() then returns a
+ *     thread-local message.  Outputs are unspecified after an error.
+ *   - Nothing here is thread-safe for the *same* operator and the same
+ *     stream; different streams may solve with one operator concurrently
+ *     (each solve takes its own workspace).
+ */
+#ifndef HNS_H
+#define HNS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HNS_OK = 0,
+    HNS_NOT_CONVERGED = 1,   /* max_iter reached; x holds the last iterate      */
+    HNS_ERR_INVALID = -1,    /* bad argument, or non-finite right-hand side      */
+    HNS_ERR_HIP = -2,        /* a HIP runtime call failed                        */
+    HNS_ERR_OOM = -3,        /* device or host allocation failed                 */
+    HNS_ERR_MESH = -4,       /* bad connectivity or a non-positive tetrahedron   */
+    HNS_ERR_BREAKDOWN = -5   /* p^T A p <= 0 or a non-finite CG scalar           */
+} hns_status;
+
+typedef struct hns_operator hns_operator; /* opaque, device-resident */
+
+/* Mesh of the shallow domain (Sec. 2): nodes, positively oriented linear
+ * tetrahedra, per-node Dirichlet bits and (optionally) the surface triangles
+ * on Gamma_s.  All arrays are host memory.
+ *   xyz       n_nodes x 3, row-major, float64
+ *   tets      n_tets x 4, int32, 0-based; det[v1-v0, v2-v0, v3-v0] > 0
+ *   bc        n_nodes, uint8; bit c set = node is Dirichlet (value 0) for the
+ *             solve that passes mask_bit = c (c = 0..7).  May be NULL (no
+ *             Dirichlet nodes).
+ *   surf_tris n_surf_tris x 3, int32 (may be NULL; needed only with
+ *             HNS_STEP_AUX, for the wind-tension load on Gamma_s). */
+typedef struct {
+    int64_t n_nodes;
+    const double *xyz;
+    int64_t n_tets;
+    const int32_t *tets;
+    const uint8_t *bc;
+    int64_t n_surf_tris;
+    const int32_t *surf_tris;
+} hns_mesh;
+
+/* Operator kind (exactly one) */
+#define HNS_POISSON   0x1u   /* A = K_nu  (pressure increment, eq. fofa_q_cor_h)      */
+#define HNS_HELMHOLTZ 0x2u   /* A = M + dt*K_nu  (velocity prediction, eq.
+                                fofa_velo_pred_h multiplied by dt; implicit Euler
+                                first step, BDF2 uses dt' = 2 dt / 3)                */
+/* Options */
+#define HNS_KEEP_FP32 0x10u  /* also keep FP32 matrix/diagonal copies (HNS_MIXED)  */
+#define HNS_STEP_AUX  0x20u  /* also keep M, B_1..3, lumped mass and surface mass
+                                for the step right-hand sides (hns_step_*)          */
+/* Storage format of A on the device (default: chosen from the pattern) */
+#define HNS_FMT_AUTO  0x000u
+#define HNS_FMT_CSR   0x100u /* compressed sparse rows, 16 lanes per row            */
+#define HNS_FMT_SELL  0x200u /* sliced ELLPACK, slice height 64 (one wavefront),
+                                column-major inside a slice                          */
+
+/* Solve modes */
+#define HNS_FP64  0u         /* everything in FP64                                   */
+#define HNS_MIXED 1u         /* FP32 matrix/vectors inside FP64 iterative refinement */
+
+typedef struct {
+    int32_t iterations;       /* CG iterations (all inner iterations in HNS_MIXED) */
+    int32_t outer_iterations; /* refinement steps (HNS_MIXED), 1 otherwise         */
+    double relres_true;       /* ||b - A x||_2 / ||b||_2 recomputed in FP64 at exit */
+    double removed_mean;      /* mean of b removed in the pure-Neumann case        */
+    int32_t status;           /* hns_status of this solve                           */
+    int32_t reserved;
+} hns_solve_info;
+
+/* Assemble the operator of `flags` (one kind + options) on the device.
+ * nu = diag(nu_h, nu_h, nu_v) is the anisotropic viscosity (Sec. 2); dt is
+ * the time step (ignored for HNS_POISSON).  Assembly runs on the host (all
+ * cores) and is uploaded once; the operator then stays resident.
+ * Errors: HNS_ERR_INVALID (null/negative sizes, non-finite coefficients),
+ * HNS_ERR_MESH (node index out of range, tetrahedron volume <= 0),
+ * HNS_ERR_OOM, HNS_ERR_HIP. */
+hns_status hns_assemble(const hns_mesh *mesh, double nu_h, double nu_v, double dt,
+                        uint32_t flags, hns_operator **out);
+
+/* Solve A x = b by Jacobi-preconditioned conjugate gradients (Remark 1 after
+ * Sec. 5; the diagonal preconditioner is the DIAG part of Remark 2).
+ *   mask_bit  Dirichlet set: nodes with bit mask_bit of mesh.bc are fixed to 0
+ *             (rows and columns eliminated symmetrically).  -1 = no Dirichlet
+ *             node; with HNS_POISSON this is the pure-Neumann pressure problem:
+ *             b is projected to zero sum (removed_mean reports the mean) and
+ *             the answer is shifted to zero mass-weighted mean, standing in
+ *             for the zero-mean constraint on q (Sec. 4, Remark 2).
+ *   b_dev     n doubles (device).  Dirichlet entries are ignored.
+ *   x_dev     n doubles (device): initial guess in, solution out (Dirichlet
+ *             entries are returned as 0).
+ *   tol       relative tolerance on the true residual: ||b - A x||_2 <= tol ||b||_2
+ *   max_iter  cap on CG iterations (all inner iterations in HNS_MIXED)
+ *   mode      HNS_FP64 or HNS_MIXED (needs HNS_KEEP_FP32)
+ *   info      filled on every return (may be NULL)
+ * b = 0 returns x = 0 after 0 iterations.  Non-finite b -> HNS_ERR_INVALID.
+ * HNS_NOT_CONVERGED leaves the last iterate in x. */
+hns_status hns_solve(hns_operator *op, int mask_bit, const double *b_dev, double *x_dev,
+                     double tol, int max_iter, uint32_t mode, void *stream,
+                     hns_solve_info *info);
+
+/* Solve k independent systems A x_j = b_j sharing one read of A per iteration
+ * (multi-right-hand-side CG; each column keeps its own CG scalars and stops
+ * on its own).  B_dev and X_dev are n x k row-major (the k values of one node
+ * are contiguous).  mask_bits[j] is the Dirichlet bit of column j (-1 = none).
+ * infos receives k entries.  HNS_MIXED runs FP32 inner iterations inside FP64
+ * refinement.  The return value is the worst column status. */
+hns_status hns_solve_batched(hns_operator *op, int k, const int *mask_bits,
+                             const double *B_dev, double *X_dev, double tol, int max_iter,
+                             uint32_t mode, void *stream, hns_solve_info *infos);
+
+/* Device bytes a solve of k right-hand sides in `mode` needs beyond the
+ * resident operator (workspace), plus the operator's own bytes when
+ * include_operator != 0.  Used for admission by HBM footprint. */
+size_t hns_footprint_bytes(const hns_operator *op, int k, uint32_t mode, int include_operator);
+
+/* Basic operator facts. */
+int64_t hns_operator_n(const hns_operator *op);
+int64_t hns_operator_nnz(const hns_operator *op);
+uint32_t hns_operator_format(const hns_operator *op);
+
+/* Tunables (returns HNS_ERR_INVALID for an unknown name or a bad value):
+ *   "check_every"  CG iterations between host convergence reads (default 32)
+ *   "inner_tol"    relative tolerance of each FP32 inner solve (default 1e-5)
+ *   "max_outer"    cap on refinement steps in HNS_MIXED (default 30)
+ *   "use_graph"    1 = replay captured HIP graphs for iteration chunks */
+hns_status hns_set_param(hns_operator *op, const char *name, double value);
+
+/* y = A x on the device (FP64), with the rows of Dirichlet set mask_bit
+ * zeroed and its columns ignored (mask_bit = -1: plain product). */
+hns_status hns_apply(hns_operator *op, int mask_bit, const double *x_dev, double *y_dev,
+                     void *stream);
+
+/* Kernel timing for measurement.  When enabled, every CG iteration a solve
+ * runs on this operator records HIP events around its three kernels on the
+ * solve's stream, and the durations of the iterations that did work (not the
+ * no-op launches after convergence inside a chunk) are accumulated per kernel:
+ *   kernel 0/1/2 = spmv / update / pupdate in FP64,
+ *   kernel 3/4/5 = the same kernels in FP32 (inner solves of HNS_MIXED).
+ * hns_profile_read returns the summed milliseconds and the launch count;
+ * enabling (on = 1) also clears the counters. */
+hns_status hns_profile_enable(hns_operator *op, int on);
+hns_status hns_profile_read(const hns_operator *op, int kernel, double *total_ms,
+                            int64_t *launches);
+
+void hns_operator_destroy(hns_operator *op);
+const char *hns_status_string(hns_status s);
+const char *hns_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HNS_H */

@@ -1,0 +1,414 @@
+// Host assembly of the P1 operators and their upload to the device.
+//
+// Forms (Sec. 4, discretised in Sec. 5):
+//   mass        M_ij  = int phi_i phi_j                       (eq. fofa_velo_pred_h, first term)
+//   stiffness   K_ij  = int (nu grad phi_j) . grad phi_i,     (second term; nu = diag(nu_h,nu_h,nu_v))
+//               also the pressure-increment operator of eq. fofa_q_cor_h
+//   divergence  (B_c)_ij = int phi_i d phi_j / d x_c          (right-hand side of eq. fofa_q_cor_h,
+//                                                              and int p div v through B_c^T)
+//   surface     (M_s)_ij = int_{Gamma_s} phi_i phi_j ds       (wind-tension load)
+//
+// The assembly is row-wise: every row gathers the contributions of the
+// tetrahedra around its node, in tetrahedron order, so rows are independent
+// (threads need no atomics), entry (i,j) and (j,i) receive the same products
+// in the same order (the matrix is bitwise symmetric), and the result does
+// not depend on the thread count.
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <thread>
+
+#include "hns_internal.h"
+
+namespace hns {
+
+namespace {
+
+template <class F>
+void parallel_for(int64_t n, F &&f)
+{
+    unsigned nt = std::max(1u, std::thread::hardware_concurrency());
+    nt = (unsigned)std::min<int64_t>(nt, std::max<int64_t>(1, n / 4096));
+    if (nt <= 1) {
+        f(0, n);
+        return;
+    }
+    std::vector<std::thread> th;
+    int64_t chunk = (n + nt - 1) / nt;
+    for (unsigned t = 0; t < nt; ++t) {
+        int64_t lo = t * chunk, hi = std::min<int64_t>(n, lo + chunk);
+        if (lo >= hi) break;
+        th.emplace_back([&f, lo, hi] { f(lo, hi); });
+    }
+    for (auto &t : th) t.join();
+}
+
+struct TetGeom {
+    double g[4][3];  // gradients of the hat functions
+    double vol;      // volume (positive for a valid tetrahedron)
+};
+
+// Hat-function gradients by cofactors: with edges e_a = X_a - X_0 (a=1..3)
+// and D = e_1 . (e_2 x e_3), grad(lambda_1) = (e_2 x e_3)/D,
+// grad(lambda_2) = (e_3 x e_1)/D, grad(lambda_3) = (e_1 x e_2)/D and
+// grad(lambda_0) = -(sum of the other three); volume D/6.
+inline void cross(const double *u, const double *v, double *w)
+{
+    w[0] = u[1] * v[2] - u[2] * v[1];
+    w[1] = u[2] * v[0] - u[0] * v[2];
+    w[2] = u[0] * v[1] - u[1] * v[0];
+}
+
+inline TetGeom tet_geometry(const double *xyz, const int32_t *t)
+{
+    const double *X0 = xyz + 3 * (int64_t)t[0];
+    double e[3][3];
+    for (int a = 0; a < 3; ++a) {
+        const double *Xa = xyz + 3 * (int64_t)t[a + 1];
+        for (int d = 0; d < 3; ++d) e[a][d] = Xa[d] - X0[d];
+    }
+    TetGeom G;
+    double c1[3], c2[3], c3[3];
+    cross(e[1], e[2], c1);
+    cross(e[2], e[0], c2);
+    cross(e[0], e[1], c3);
+    double D = e[0][0] * c1[0] + e[0][1] * c1[1] + e[0][2] * c1[2];
+    G.vol = D / 6.0;
+    double inv = 1.0 / D;
+    for (int d = 0; d < 3; ++d) {
+        G.g[1][d] = c1[d] * inv;
+        G.g[2][d] = c2[d] * inv;
+        G.g[3][d] = c3[d] * inv;
+        G.g[0][d] = -(G.g[1][d] + G.g[2][d] + G.g[3][d]);
+    }
+    return G;
+}
+
+// node -> incident tetrahedra (ascending tetrahedron index), as CSR
+struct Incidence {
+    std::vector<int64_t> ptr;
+    std::vector<int32_t> tet;  // tetrahedron index
+    std::vector<int8_t> loc;   // local vertex number of the node in that tetrahedron
+};
+
+Incidence build_incidence(int64_t n, int64_t ne, int nloc, const int32_t *conn)
+{
+    Incidence inc;
+    inc.ptr.assign(n + 1, 0);
+    for (int64_t e = 0; e < ne * nloc; ++e) inc.ptr[conn[e] + 1]++;
+    for (int64_t i = 0; i < n; ++i) inc.ptr[i + 1] += inc.ptr[i];
+    inc.tet.resize(inc.ptr[n]);
+    inc.loc.resize(inc.ptr[n]);
+    std::vector<int64_t> fill(inc.ptr.begin(), inc.ptr.end() - 1);
+    for (int64_t e = 0; e < ne; ++e)
+        for (int a = 0; a < nloc; ++a) {
+            int64_t s = fill[conn[e * nloc + a]]++;
+            inc.tet[s] = (int32_t)e;
+            inc.loc[s] = (int8_t)a;
+        }
+    return inc;
+}
+
+// Sparsity: row i holds every node sharing an element with node i.
+void build_pattern(int64_t n, int nloc, const int32_t *conn, const Incidence &inc, HostCSR &A)
+{
+    A.n = n;
+    A.rowptr.assign(n + 1, 0);
+    std::vector<int32_t> len(n);
+    auto row_cols = [&](int64_t i, std::vector<int32_t> &buf) {
+        buf.clear();
+        for (int64_t s = inc.ptr[i]; s < inc.ptr[i + 1]; ++s)
+            for (int b = 0; b < nloc; ++b) buf.push_back(conn[(int64_t)inc.tet[s] * nloc + b]);
+        if (buf.empty()) buf.push_back((int32_t)i);  // isolated node: keep a diagonal
+        std::sort(buf.begin(), buf.end());
+        buf.erase(std::unique(buf.begin(), buf.end()), buf.end());
+    };
+    parallel_for(n, [&](int64_t lo, int64_t hi) {
+        std::vector<int32_t> buf;
+        for (int64_t i = lo; i < hi; ++i) {
+            row_cols(i, buf);
+            len[i] = (int32_t)buf.size();
+        }
+    });
+    for (int64_t i = 0; i < n; ++i) A.rowptr[i + 1] = A.rowptr[i] + len[i];
+    A.col.resize(A.rowptr[n]);
+    A.val.assign(A.rowptr[n], 0.0);
+    parallel_for(n, [&](int64_t lo, int64_t hi) {
+        std::vector<int32_t> buf;
+        for (int64_t i = lo; i < hi; ++i) {
+            row_cols(i, buf);
+            std::copy(buf.begin(), buf.end(), A.col.begin() + A.rowptr[i]);
+        }
+    });
+}
+
+inline int64_t find_col(const HostCSR &A, int64_t row, int32_t c)
+{
+    const int32_t *b = A.col.data() + A.rowptr[row];
+    const int32_t *e = A.col.data() + A.rowptr[row + 1];
+    const int32_t *p = std::lower_bound(b, e, c);
+    return (p != e && *p == c) ? (p - A.col.data()) : -1;
+}
+
+hns_status check_mesh(const hns_mesh *m)
+{
+    if (!m || m->n_nodes <= 0 || m->n_tets < 0 || !m->xyz || (m->n_tets > 0 && !m->tets)) {
+        set_error("mesh: null arrays or non-positive sizes");
+        return HNS_ERR_INVALID;
+    }
+    if (m->n_nodes >= (int64_t)INT32_MAX) {
+        set_error("mesh: %lld nodes exceed the int32 index range", (long long)m->n_nodes);
+        return HNS_ERR_INVALID;
+    }
+    for (int64_t e = 0; e < 4 * m->n_tets; ++e)
+        if (m->tets[e] < 0 || m->tets[e] >= m->n_nodes) {
+            set_error("mesh: tetrahedron %lld references node %d outside [0,%lld)",
+                      (long long)(e / 4), m->tets[e], (long long)m->n_nodes);
+            return HNS_ERR_MESH;
+        }
+    for (int64_t i = 0; i < 3 * m->n_nodes; ++i)
+        if (!std::isfinite(m->xyz[i])) {
+            set_error("mesh: non-finite coordinate at node %lld", (long long)(i / 3));
+            return HNS_ERR_MESH;
+        }
+    return HNS_OK;
+}
+
+}  // namespace
+
+hns_status assemble_host(const hns_mesh *mesh, double c_mass, double c_stiff, double nu_h,
+                         double nu_v, HostCSR &A, std::vector<double> *lumped)
+{
+    HNS_TRY(check_mesh(mesh));
+    const int64_t n = mesh->n_nodes, ne = mesh->n_tets;
+    const double *xyz = mesh->xyz;
+    const int32_t *tets = mesh->tets;
+
+    // element validity first (positive volume)
+    std::atomic<int64_t> bad{-1};
+    parallel_for(ne, [&](int64_t lo, int64_t hi) {
+        for (int64_t e = lo; e < hi; ++e) {
+            TetGeom G = tet_geometry(xyz, tets + 4 * e);
+            if (!(G.vol > 0.0) || !std::isfinite(G.vol)) {
+                bad.store(e);
+                return;
+            }
+        }
+    });
+    if (bad.load() >= 0) {
+        set_error("mesh: tetrahedron %lld has non-positive volume", (long long)bad.load());
+        return HNS_ERR_MESH;
+    }
+
+    Incidence inc = build_incidence(n, ne, 4, tets);
+    build_pattern(n, 4, tets, inc, A);
+    if ((int64_t)A.col.size() >= (int64_t)INT32_MAX) {
+        set_error("operator has %zu nonzeros, beyond the int32 range", A.col.size());
+        return HNS_ERR_INVALID;
+    }
+    if (lumped) lumped->assign(n, 0.0);
+    const double nu[3] = {nu_h, nu_h, nu_v};
+    parallel_for(n, [&](int64_t lo, int64_t hi) {
+        for (int64_t i = lo; i < hi; ++i) {
+            double mi = 0.0;
+            for (int64_t s = inc.ptr[i]; s < inc.ptr[i + 1]; ++s) {
+                const int32_t *t = tets + 4 * (int64_t)inc.tet[s];
+                const int a = inc.loc[s];
+                TetGeom G = tet_geometry(xyz, t);
+                mi += G.vol / 4.0;
+                for (int b = 0; b < 4; ++b) {
+                    double k = 0.0;
+                    for (int d = 0; d < 3; ++d) k += nu[d] * (G.g[a][d] * G.g[b][d]);
+                    k *= G.vol;
+                    double m = (a == b) ? G.vol / 10.0 : G.vol / 20.0;
+                    A.val[find_col(A, i, t[b])] += c_mass * m + c_stiff * k;
+                }
+            }
+            if (lumped) (*lumped)[i] = mi;
+        }
+    });
+    return HNS_OK;
+}
+
+hns_status assemble_divergence_host(const hns_mesh *mesh, const HostCSR &pattern, int comp,
+                                    HostCSR &B)
+{
+    HNS_TRY(check_mesh(mesh));
+    const int64_t n = mesh->n_nodes, ne = mesh->n_tets;
+    Incidence inc = build_incidence(n, ne, 4, mesh->tets);
+    B.n = n;
+    B.rowptr = pattern.rowptr;
+    B.col = pattern.col;
+    B.val.assign(pattern.col.size(), 0.0);
+    parallel_for(n, [&](int64_t lo, int64_t hi) {
+        for (int64_t i = lo; i < hi; ++i)
+            for (int64_t s = inc.ptr[i]; s < inc.ptr[i + 1]; ++s) {
+                const int32_t *t = mesh->tets + 4 * (int64_t)inc.tet[s];
+                TetGeom G = tet_geometry(mesh->xyz, t);
+                // int_T phi_a d phi_b / d x_c = (vol / 4) * d phi_b / d x_c
+                for (int b = 0; b < 4; ++b)
+                    B.val[find_col(B, i, t[b])] += (G.vol / 4.0) * G.g[b][comp];
+            }
+    });
+    return HNS_OK;
+}
+
+hns_status assemble_surface_mass_host(const hns_mesh *mesh, HostCSR &Ms)
+{
+    const int64_t n = mesh->n_nodes, nt = mesh->n_surf_tris;
+    if (nt <= 0 || !mesh->surf_tris) {
+        set_error("surface mass needs the surface triangles");
+        return HNS_ERR_INVALID;
+    }
+    for (int64_t e = 0; e < 3 * nt; ++e)
+        if (mesh->surf_tris[e] < 0 || mesh->surf_tris[e] >= n) {
+            set_error("surface triangle %lld references a node out of range", (long long)(e / 3));
+            return HNS_ERR_MESH;
+        }
+    Incidence inc = build_incidence(n, nt, 3, mesh->surf_tris);
+    build_pattern(n, 3, mesh->surf_tris, inc, Ms);
+    parallel_for(n, [&](int64_t lo, int64_t hi) {
+        for (int64_t i = lo; i < hi; ++i)
+            for (int64_t s = inc.ptr[i]; s < inc.ptr[i + 1]; ++s) {
+                const int32_t *t = mesh->surf_tris + 3 * (int64_t)inc.tet[s];
+                const int a = inc.loc[s];
+                const double *P0 = mesh->xyz + 3 * (int64_t)t[0];
+                const double *P1 = mesh->xyz + 3 * (int64_t)t[1];
+                const double *P2 = mesh->xyz + 3 * (int64_t)t[2];
+                double u[3], v[3], w[3];
+                for (int d = 0; d < 3; ++d) {
+                    u[d] = P1[d] - P0[d];
+                    v[d] = P2[d] - P0[d];
+                }
+                cross(u, v, w);
+                double area = 0.5 * std::sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+                for (int b = 0; b < 3; ++b)
+                    Ms.val[find_col(Ms, i, t[b])] += (a == b) ? area / 6.0 : area / 12.0;
+            }
+    });
+    return HNS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Device upload
+// ---------------------------------------------------------------------------
+
+size_t DevMatrix::bytes() const
+{
+    size_t b = 0;
+    if (fmt == HNS_FMT_CSR) {
+        b += (size_t)(n + 1) * 4 + (size_t)nnz * 12;
+        if (val32) b += (size_t)nnz * 4;
+    } else {
+        b += (size_t)(nslices + 1) * 4 + (size_t)sell_len * 12;
+        if (sval32) b += (size_t)sell_len * 4;
+    }
+    return b;
+}
+
+void DevMatrix::release()
+{
+    void *ptrs[] = {rowptr, col, val, val32, slice_ptr, scol, sval, sval32};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    rowptr = col = slice_ptr = scol = nullptr;
+    val = sval = nullptr;
+    val32 = sval32 = nullptr;
+}
+
+uint32_t choose_format(const HostCSR &h)
+{
+    // Sliced ELL pays when rows inside a 64-row slice have similar lengths
+    // (padding stays small); the structured basin meshes give < 5 % padding.
+    int64_t n = h.n, padded = 0;
+    for (int64_t s = 0; s * kSlice < n; ++s) {
+        int32_t w = 0;
+        for (int64_t r = s * kSlice; r < std::min<int64_t>(n, (s + 1) * kSlice); ++r)
+            w = std::max(w, h.rowptr[r + 1] - h.rowptr[r]);
+        padded += (int64_t)w * kSlice;
+    }
+    return (padded <= h.nnz() + h.nnz() / 5) ? HNS_FMT_SELL : HNS_FMT_CSR;
+}
+
+template <class T>
+static hns_status upload(const std::vector<T> &v, T **dst)
+{
+    *dst = nullptr;
+    if (v.empty()) return HNS_OK;
+    hipError_t e = hipMalloc((void **)dst, v.size() * sizeof(T));
+    if (e != hipSuccess) {
+        *dst = nullptr;
+        set_error("hipMalloc of %zu bytes failed: %s", v.size() * sizeof(T), hipGetErrorString(e));
+        return e == hipErrorOutOfMemory ? HNS_ERR_OOM : HNS_ERR_HIP;
+    }
+    HNS_TRY_HIP(hipMemcpy(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return HNS_OK;
+}
+
+hns_status upload_matrix(const HostCSR &h, uint32_t fmt, bool keep32, DevMatrix &d)
+{
+    d.n = h.n;
+    d.nnz = h.nnz();
+    d.fmt = fmt;
+    if (fmt == HNS_FMT_CSR) {
+        HNS_TRY(upload(h.rowptr, &d.rowptr));
+        HNS_TRY(upload(h.col, &d.col));
+        HNS_TRY(upload(h.val, &d.val));
+        if (keep32) {
+            std::vector<float> v32(h.val.begin(), h.val.end());
+            HNS_TRY(upload(v32, &d.val32));
+        }
+        return HNS_OK;
+    }
+    // sliced ELL, slice height 64, padding entries point at the row itself
+    // with value 0 (rows past n point at node n-1)
+    const int64_t n = h.n;
+    d.nslices = (n + kSlice - 1) / kSlice;
+    std::vector<int32_t> sptr(d.nslices + 1, 0);
+    for (int64_t s = 0; s < d.nslices; ++s) {
+        int32_t w = 0;
+        for (int64_t r = s * kSlice; r < std::min<int64_t>(n, (s + 1) * kSlice); ++r)
+            w = std::max(w, h.rowptr[r + 1] - h.rowptr[r]);
+        if ((int64_t)sptr[s] + (int64_t)w * kSlice >= (int64_t)INT32_MAX) {
+            set_error("sliced-ELL storage exceeds the int32 range");
+            return HNS_ERR_INVALID;
+        }
+        sptr[s + 1] = sptr[s] + w * kSlice;
+    }
+    d.sell_len = sptr[d.nslices];
+    std::vector<int32_t> scol(d.sell_len);
+    std::vector<double> sval(d.sell_len, 0.0);
+    parallel_for(d.nslices, [&](int64_t lo, int64_t hi) {
+        for (int64_t s = lo; s < hi; ++s) {
+            int32_t w = (sptr[s + 1] - sptr[s]) / kSlice;
+            for (int l = 0; l < kSlice; ++l) {
+                int64_t r = s * kSlice + l;
+                int32_t rr = (int32_t)std::min<int64_t>(r, n - 1);
+                int32_t len = r < n ? h.rowptr[r + 1] - h.rowptr[r] : 0;
+                for (int32_t j = 0; j < w; ++j) {
+                    int64_t k = sptr[s] + (int64_t)j * kSlice + l;
+                    if (j < len) {
+                        scol[k] = h.col[h.rowptr[r] + j];
+                        sval[k] = h.val[h.rowptr[r] + j];
+                    } else {
+                        scol[k] = rr;
+                        sval[k] = 0.0;
+                    }
+                }
+            }
+        }
+    });
+    HNS_TRY(upload(sptr, &d.slice_ptr));
+    HNS_TRY(upload(scol, &d.scol));
+    HNS_TRY(upload(sval, &d.sval));
+    if (keep32) {
+        std::vector<float> v32(sval.begin(), sval.end());
+        HNS_TRY(upload(v32, &d.sval32));
+    }
+    return HNS_OK;
+}
+
+}  // namespace hns

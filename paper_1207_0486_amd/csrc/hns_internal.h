@@ -1,0 +1,119 @@
+// Internal declarations of the hns library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "hns.h"
+
+namespace hns {
+
+void set_error(const char *fmt, ...) __attribute__((format(printf, 1, 2)));
+
+#define HNS_TRY_HIP(call)                                                                    \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess) {                                                              \
+            ::hns::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__, \
+                             __LINE__);                                                      \
+            return HNS_ERR_HIP;                                                              \
+        }                                                                                    \
+    } while (0)
+
+#define HNS_TRY(expr)                       \
+    do {                                    \
+        hns_status s_ = (expr);             \
+        if (s_ < 0) return s_;              \
+    } while (0)
+
+constexpr int kBlock = 256;      // threads per workgroup (4 wavefronts)
+constexpr int kSlice = 64;       // sliced-ELL slice height = one wavefront
+constexpr int kMaxGrid = 2048;   // workgroups of the reducing kernels (multiple of 8 XCDs)
+
+// ---------------------------------------------------------------------------
+// Host-side compressed sparse rows (assembly output)
+// ---------------------------------------------------------------------------
+struct HostCSR {
+    int64_t n = 0;
+    std::vector<int32_t> rowptr;  // n+1
+    std::vector<int32_t> col;
+    std::vector<double> val;
+    int64_t nnz() const { return (int64_t)col.size(); }
+};
+
+// ---------------------------------------------------------------------------
+// Device matrix in one of the storage formats, FP64 and optional FP32 values.
+// ---------------------------------------------------------------------------
+struct DevMatrix {
+    int64_t n = 0;
+    int64_t nnz = 0;        // structural nonzeros (CSR)
+    uint32_t fmt = HNS_FMT_CSR;
+    // CSR
+    int32_t *rowptr = nullptr;
+    int32_t *col = nullptr;
+    double *val = nullptr;
+    float *val32 = nullptr;
+    // sliced ELL: slice s holds rows [64 s, 64 s + 64); entry j of lane l is
+    // at slice_ptr[s] + 64 j + l (column-major inside the slice)
+    int64_t nslices = 0;
+    int64_t sell_len = 0;   // padded entries
+    int32_t *slice_ptr = nullptr;
+    int32_t *scol = nullptr;
+    double *sval = nullptr;
+    float *sval32 = nullptr;
+
+    size_t bytes() const;
+    void release();
+};
+
+struct Scalars;           // device-side CG scalars (kernels.hip)
+struct Workspace;         // per-solve device buffers (solve.hip)
+
+}  // namespace hns
+
+struct hns_operator {
+    int device = 0;
+    uint32_t flags = 0;
+    uint32_t kind = 0;      // HNS_POISSON or HNS_HELMHOLTZ
+    int64_t n = 0;
+    double nu_h = 0, nu_v = 0, dt = 0;
+    hns::DevMatrix A;
+    double *dinv = nullptr;     // 1 / diag(A)
+    float *dinv32 = nullptr;
+    uint8_t *bc = nullptr;      // Dirichlet bits (device), may be null
+    double *lumped = nullptr;   // M 1 (mass-weighted mean of the Neumann answer)
+    double lumped_sum = 0.0;
+    int64_t bad_diag = -1;      // first non-positive diagonal entry, -1 if none
+    // auxiliary forms for the step right-hand sides
+    hns::DevMatrix M, B[3], Ms;
+    bool has_aux = false;
+    // tunables
+    int check_every = 32;
+    double inner_tol = 1e-5;
+    int max_outer = 30;
+    int use_graph = 0;
+    // kernel timing (hns_profile_*)
+    int profile = 0;
+    double prof_ms[6] = {0, 0, 0, 0, 0, 0};
+    int64_t prof_count[6] = {0, 0, 0, 0, 0, 0};
+    // workspaces, reused across solves
+    std::mutex ws_mutex;
+    std::vector<hns::Workspace *> ws_free;
+};
+
+namespace hns {
+
+// assemble.cpp
+hns_status assemble_host(const hns_mesh *mesh, double c_mass, double c_stiff, double nu_h,
+                         double nu_v, HostCSR &A, std::vector<double> *lumped);
+hns_status assemble_divergence_host(const hns_mesh *mesh, const HostCSR &pattern, int comp,
+                                    HostCSR &B);
+hns_status assemble_surface_mass_host(const hns_mesh *mesh, HostCSR &Ms);
+hns_status upload_matrix(const HostCSR &h, uint32_t fmt, bool keep32, DevMatrix &d);
+uint32_t choose_format(const HostCSR &h);
+
+}  // namespace hns

@@ -1,0 +1,96 @@
+// Kernel launchers of the hns library (device code lives in kernels.hip).
+#pragma once
+
+#include "hns_internal.h"
+
+namespace hns {
+
+// CG scalars kept on the device so that a chunk of iterations runs without
+// host round trips.  rho is double-buffered by iteration parity: during
+// iteration k (counted from the last restart) the kernels read rho[k & 1]
+// and the last kernel writes the next value into rho[(k + 1) & 1], so no
+// block ever reads a slot another block of the same launch writes.
+struct Scalars {
+    double rho[2];   // r^T z
+    double alpha;    // rho / (p^T q)
+    double beta;     // rho_new / rho
+    double gamma;    // p^T q
+    double rr;       // r^T r
+    double bb;       // b^T b (after projection in the pure-Neumann case)
+    double tol2;     // tol^2
+    double sumb;     // sum of the free entries of b
+    double bb_raw;   // sum of squares of the free entries of b
+    double sum_r;    // sum of r (pure-Neumann projection)
+    double wx;       // sum of lumped_i x_i (pure-Neumann normalisation)
+    double nonfinite;
+    int32_t stop;    // 0 running, 1 recursive residual below tolerance, 2 breakdown, 3 b = 0
+    int32_t iter;    // CG iterations executed
+    uint32_t counter[4];
+};
+
+// Layout of the per-workspace partial-sum buffer (doubles)
+constexpr int kPartSpmv = 0;                 // p^T q per SpMV block
+constexpr int kPartUpdate = kMaxGrid;        // r^T z, r^T r per update block
+constexpr int kPartMisc = 3 * kMaxGrid;      // one-off reductions (3 values)
+constexpr int kPartTotal = 6 * kMaxGrid;
+
+// grid for a streaming kernel over n entries (multiple of 8 when >= 8)
+int stream_grid(int64_t n);
+// grid for the SpMV of a matrix
+int spmv_grid(const DevMatrix &A);
+
+struct IterArgs {
+    const DevMatrix *A;
+    bool fp32;
+    int64_t n;
+    void *x, *r, *p, *q;
+    const void *dinv;
+    const uint8_t *bc;
+    int bit;
+    Scalars *sc;
+    double *partials;   // kPartTotal doubles
+};
+
+// One CG iteration = three launches:
+//   spmv    q = mask(A p), per-block partials of p^T q
+//   update  gamma = p^T q (every block sums the partials in the same order),
+//           alpha = rho / gamma, x += alpha p, r -= alpha q,
+//           per-block partials of r^T D^-1 r and r^T r
+//   pupdate rho' and rr from the partials, beta = rho' / rho, stop flags,
+//           p = D^-1 r + beta p
+// ev (optional, 4 events) brackets the three kernels for timing.
+hns_status launch_iteration(const IterArgs &a, int parity, hipStream_t s, hipEvent_t *ev);
+
+// q = mask(A p) without reductions (residuals and hns_apply)
+hns_status launch_spmv_plain(const DevMatrix &A, bool fp32, const void *p, void *q,
+                             const uint8_t *bc, int bit, hipStream_t s);
+// statistics of the free entries of b (sum, sum of squares, non-finite count)
+hns_status launch_bstats(int64_t n, const double *b, const uint8_t *bc, int bit, Scalars *sc,
+                         double *partials, hipStream_t s);
+// x = 0 on Dirichlet nodes (everywhere when zero_all)
+hns_status launch_prepare_x(int64_t n, double *x, const uint8_t *bc, int bit, bool zero_all,
+                            hipStream_t s);
+// r = mask(b - shift - q) (FP64), shift = sumb / n when singular; sum of r and
+// of (b - shift)^2 into sc
+hns_status launch_residual(int64_t n, const double *b, const double *q, double *r,
+                           const uint8_t *bc, int bit, bool singular, Scalars *sc,
+                           double *partials, hipStream_t s);
+// (singular: r -= mean r) z = D^-1 r; p = z; rho[0] = r^T z; rr = r^T r; stop flag.
+// bb_from_rr: set bb = rr (inner solves of the refinement loop)
+hns_status launch_init_dir(int64_t n, bool fp32, void *r, void *p, const void *dinv,
+                           bool singular, bool bb_from_rr, Scalars *sc, double *partials,
+                           hipStream_t s);
+// (singular: r -= mean r) rr = r^T r, FP64 residual of the refinement loop
+hns_status launch_project_norm(int64_t n, double *r, bool singular, Scalars *sc,
+                               double *partials, hipStream_t s);
+// r32 = (float)(r64 / sqrt(rr)), d32 = 0
+hns_status launch_cast_scaled(int64_t n, const double *r64, float *r32, float *d32,
+                              const Scalars *outer, hipStream_t s);
+// x += sqrt(rr) * (double)d32
+hns_status launch_correct(int64_t n, double *x, const float *d32, const Scalars *outer,
+                          hipStream_t s);
+// wx = sum lumped_i x_i ; then x -= wx / lumped_sum
+hns_status launch_normalise(int64_t n, double *x, const double *lumped, double lumped_sum,
+                            Scalars *sc, double *partials, hipStream_t s);
+
+}  // namespace hns

@@ -1,0 +1,629 @@
+// HIP kernels of the Jacobi-preconditioned conjugate gradient (gfx950).
+//
+// One CG iteration (Remark 1 after Sec. 5 of the paper names PCG; the
+// diagonal preconditioner is the DIAG part of Remark 2) is three launches:
+//   spmv    q = A p (Dirichlet rows zeroed), per-block partials of p^T q
+//   update  gamma = p^T q, alpha = rho / gamma, x += alpha p, r -= alpha q,
+//           z = D^-1 r (not stored), per-block partials of r^T z and r^T r
+//   pupdate rho' = r^T z, rr = r^T r, beta = rho' / rho, stop flags,
+//           p = z + beta p
+// Each consumer kernel re-reduces the producer's per-block partials in every
+// block, in one fixed order, so all blocks hold bit-identical scalars without
+// a grid-wide fence, an atomic or an extra launch; block 0 records them.
+// The scalars stay in device memory and every kernel exits at once when the
+// stop flag is set, so the host enqueues a chunk of iterations and reads the
+// flag once per chunk.  Reductions are deterministic: wavefront butterflies
+// (64 lanes), the 4 wavefronts of a block through LDS, then the block
+// partials in block order.  Dots accumulate in FP64 also when vectors are FP32.
+//
+// One-off reductions outside the iteration (right-hand-side statistics,
+// residual norms, normalisation) use a last-block-done pattern instead.
+#include <cmath>
+
+#include "kernels.h"
+
+namespace hns {
+namespace {
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Sums NV values over the block; the totals are valid in thread 0.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double *lds)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = wave_sum(v[k]);
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) lds[k * (kBlock / 64) + wid] = v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            double s = 0.0;
+            for (int w = 0; w < kBlock / 64; ++w) s += lds[k * (kBlock / 64) + w];
+            v[k] = s;
+        }
+    }
+    __syncthreads();
+}
+
+// Grid-wide sum of NV values.  Returns true in all threads of the last block
+// to arrive; there thread 0 holds the totals in v.  partials holds NV x grid
+// doubles; the counter is reset for the next launch.
+template <int NV>
+__device__ bool grid_sum(double (&v)[NV], double *partials, uint32_t *counter)
+{
+    __shared__ double lds[NV * (kBlock / 64)];
+    __shared__ int is_last;
+    block_sum<NV>(v, lds);
+    const int G = gridDim.x;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) partials[k * G + blockIdx.x] = v[k];
+        __threadfence();
+        const uint32_t prev = atomicAdd(counter, 1u);
+        is_last = (prev == (uint32_t)(G - 1));
+    }
+    __syncthreads();
+    if (!is_last) return false;
+    __threadfence();
+    double t[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) t[k] = 0.0;
+    for (int b = threadIdx.x; b < G; b += kBlock) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) t[k] += partials[k * G + b];
+    }
+    block_sum<NV>(t, lds);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) v[k] = t[k];
+        *counter = 0u;
+    }
+    return true;
+}
+
+// Workgroups are dealt to the 8 XCDs round-robin; renumber them so that each
+// XCD works on one contiguous eighth of the rows (neighbour gathers of the
+// SpMV then hit that XCD's own L2).
+__device__ __forceinline__ int xcd_block(int b, int G)
+{
+    return (G >= 8 && (G & 7) == 0) ? (b & 7) * (G >> 3) + (b >> 3) : b;
+}
+
+__device__ __forceinline__ bool is_dirichlet(const uint8_t *bc, int bit, int64_t i)
+{
+    return bc != nullptr && ((bc[i] >> bit) & 1u);
+}
+
+// Sums NV per-thread values over the block and stores them as the block's
+// partials P[k * G + block] (plain stores: the consumer is a later launch).
+template <int NV>
+__device__ __forceinline__ void store_block_partials(double (&v)[NV], double *P)
+{
+    __shared__ double lds[NV * (kBlock / 64)];
+    block_sum<NV>(v, lds);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) P[k * gridDim.x + blockIdx.x] = v[k];
+    }
+}
+
+// Every block of the consumer sums the G partials of the producer in the same
+// fixed order, so all blocks obtain bit-identical scalars.
+template <int NV>
+__device__ __forceinline__ void load_reduced(const double *__restrict__ P, int G,
+                                             double (&out)[NV])
+{
+    __shared__ double lds[NV * (kBlock / 64)];
+    __shared__ double bcast[NV];
+    double t[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) t[k] = 0.0;
+    for (int b = threadIdx.x; b < G; b += kBlock) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) t[k] += P[k * G + b];
+    }
+    block_sum<NV>(t, lds);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) bcast[k] = t[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NV; ++k) out[k] = bcast[k];
+}
+
+// Sliced ELL, slice height 64 = one wavefront, one row per lane.  Each block
+// owns a contiguous range of slices; its 4 wavefronts take every 4th slice.
+template <typename T, bool DOT>
+__global__ __launch_bounds__(kBlock) void k_spmv_sell(int64_t n, int64_t nslices,
+                                                      const int32_t *__restrict__ sptr,
+                                                      const int32_t *__restrict__ col,
+                                                      const T *__restrict__ val,
+                                                      const T *__restrict__ x, T *__restrict__ y,
+                                                      const uint8_t *__restrict__ bc, int bit,
+                                                      const Scalars *__restrict__ sc,
+                                                      double *__restrict__ part)
+{
+    if constexpr (DOT) {
+        if (sc->stop) return;
+    }
+    const int G = gridDim.x;
+    const int lb = xcd_block(blockIdx.x, G);
+    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t per = (nslices + G - 1) / G;
+    const int64_t s0 = (int64_t)lb * per;
+    const int64_t s1 = s0 + per < nslices ? s0 + per : nslices;
+    double acc = 0.0;
+    for (int64_t s = s0 + wid; s < s1; s += kBlock / 64) {
+        const int32_t beg = sptr[s];
+        const int32_t w = (sptr[s + 1] - beg) >> 6;
+        const int32_t *c = col + beg + lane;
+        const T *v = val + beg + lane;
+        T sum = 0;
+#pragma unroll 4
+        for (int j = 0; j < w; ++j) sum += v[j * 64] * x[c[j * 64]];
+        const int64_t row = s * 64 + lane;
+        if (row < n) {
+            if (is_dirichlet(bc, bit, row)) sum = 0;
+            y[row] = sum;
+            if constexpr (DOT) acc += (double)x[row] * (double)sum;
+        }
+    }
+    if constexpr (DOT) {
+        double v[1] = {acc};
+        store_block_partials<1>(v, part);
+    }
+}
+
+// CSR with 16 lanes per row (4 rows per wavefront); rows of a block are a
+// contiguous range.
+template <typename T, bool DOT>
+__global__ __launch_bounds__(kBlock) void k_spmv_csr(int64_t n, const int32_t *__restrict__ rowptr,
+                                                     const int32_t *__restrict__ col,
+                                                     const T *__restrict__ val,
+                                                     const T *__restrict__ x, T *__restrict__ y,
+                                                     const uint8_t *__restrict__ bc, int bit,
+                                                     const Scalars *__restrict__ sc,
+                                                     double *__restrict__ part)
+{
+    if constexpr (DOT) {
+        if (sc->stop) return;
+    }
+    const int G = gridDim.x;
+    const int lb = xcd_block(blockIdx.x, G);
+    const int grp = threadIdx.x >> 4, gl = threadIdx.x & 15;
+    const int64_t per = (((n + G - 1) / G) + 15) / 16 * 16;
+    const int64_t r0 = (int64_t)lb * per;
+    const int64_t r1 = r0 + per < n ? r0 + per : n;
+    double acc = 0.0;
+    for (int64_t base = r0; base < r1; base += kBlock / 16) {
+        const int64_t row = base + grp;
+        T sum = 0;
+        if (row < r1) {
+            const int32_t e = rowptr[row + 1];
+            for (int32_t k = rowptr[row] + gl; k < e; k += 16) sum += val[k] * x[col[k]];
+        }
+        sum += __shfl_xor(sum, 8, 16);
+        sum += __shfl_xor(sum, 4, 16);
+        sum += __shfl_xor(sum, 2, 16);
+        sum += __shfl_xor(sum, 1, 16);
+        if (gl == 0 && row < r1) {
+            if (is_dirichlet(bc, bit, row)) sum = 0;
+            y[row] = sum;
+            if constexpr (DOT) acc += (double)x[row] * (double)sum;
+        }
+    }
+    if constexpr (DOT) {
+        double v[1] = {acc};
+        store_block_partials<1>(v, part);
+    }
+}
+
+// x += alpha p; r -= alpha q; partials of r^T D^-1 r and r^T r.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_update(int64_t n, T *__restrict__ x, T *__restrict__ r,
+                                                   const T *__restrict__ p,
+                                                   const T *__restrict__ q,
+                                                   const T *__restrict__ dinv,
+                                                   Scalars *__restrict__ sc,
+                                                   const double *__restrict__ part_in, int G_in,
+                                                   double *__restrict__ part_out, int parity)
+{
+    if (sc->stop) return;
+    double g[1];
+    load_reduced<1>(part_in, G_in, g);
+    const double gamma = g[0];
+    if (!(gamma > 0.0) || !isfinite(gamma)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            sc->gamma = gamma;
+            sc->stop = 2;
+        }
+        return;
+    }
+    const double alpha_d = sc->rho[parity] / gamma;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->gamma = gamma;
+        sc->alpha = alpha_d;
+    }
+    const T alpha = (T)alpha_d;
+    double rz = 0.0, rr = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock) {
+        x[i] = x[i] + alpha * p[i];
+        const T ri = r[i] - alpha * q[i];
+        r[i] = ri;
+        const T zi = dinv[i] * ri;
+        rz += (double)ri * (double)zi;
+        rr += (double)ri * (double)ri;
+    }
+    double v[2] = {rz, rr};
+    store_block_partials<2>(v, part_out);
+}
+
+// rho' = r^T z, rr = r^T r from the update partials; beta = rho' / rho;
+// p = D^-1 r + beta p unless converged.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_pupdate(int64_t n, T *__restrict__ p,
+                                                    const T *__restrict__ r,
+                                                    const T *__restrict__ dinv,
+                                                    Scalars *__restrict__ sc,
+                                                    const double *__restrict__ part_in, int G_in,
+                                                    int parity)
+{
+    if (sc->stop) return;
+    double v[2];
+    load_reduced<2>(part_in, G_in, v);
+    const double rho_new = v[0], rr = v[1];
+    const bool bad = !isfinite(rho_new) || !isfinite(rr);
+    const bool conv = !bad && rr <= sc->tol2 * sc->bb;
+    const double beta_d = rho_new / sc->rho[parity];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->rho[parity ^ 1] = rho_new;
+        sc->rr = rr;
+        sc->beta = beta_d;
+        sc->iter += 1;
+        if (bad)
+            sc->stop = 2;
+        else if (conv)
+            sc->stop = 1;
+    }
+    if (bad || conv) return;
+    const T beta = (T)beta_d;
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock)
+        p[i] = dinv[i] * r[i] + beta * p[i];
+}
+
+__global__ __launch_bounds__(kBlock) void k_bstats(int64_t n, const double *__restrict__ b,
+                                                   const uint8_t *__restrict__ bc, int bit,
+                                                   Scalars *__restrict__ sc,
+                                                   double *__restrict__ partials)
+{
+    double s = 0.0, s2 = 0.0, bad = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock) {
+        double bi = is_dirichlet(bc, bit, i) ? 0.0 : b[i];
+        if (!isfinite(bi)) {
+            bad += 1.0;
+            bi = 0.0;
+        }
+        s += bi;
+        s2 += bi * bi;
+    }
+    double v[3] = {s, s2, bad};
+    if (grid_sum<3>(v, partials, &sc->counter[2]) && threadIdx.x == 0) {
+        sc->sumb = v[0];
+        sc->bb_raw = v[1];
+        sc->nonfinite = v[2];
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_prepare_x(int64_t n, double *__restrict__ x,
+                                                      const uint8_t *__restrict__ bc, int bit,
+                                                      int zero_all)
+{
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock)
+        if (zero_all || is_dirichlet(bc, bit, i)) x[i] = 0.0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_residual(int64_t n, const double *__restrict__ b,
+                                                     const double *__restrict__ q,
+                                                     double *__restrict__ r,
+                                                     const uint8_t *__restrict__ bc, int bit,
+                                                     int singular, Scalars *__restrict__ sc,
+                                                     double *__restrict__ partials)
+{
+    const double shift = singular ? sc->sumb / (double)n : 0.0;
+    double sr = 0.0, sbb = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock) {
+        double bi = b[i] - shift;
+        double ri = bi - q[i];
+        if (is_dirichlet(bc, bit, i)) {
+            bi = 0.0;
+            ri = 0.0;
+        }
+        r[i] = ri;
+        sr += ri;
+        sbb += bi * bi;
+    }
+    double v[2] = {sr, sbb};
+    if (grid_sum<2>(v, partials, &sc->counter[2]) && threadIdx.x == 0) {
+        sc->sum_r = v[0];
+        sc->bb = v[1];
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_init_dir(int64_t n, T *__restrict__ r,
+                                                     T *__restrict__ p,
+                                                     const T *__restrict__ dinv, int singular,
+                                                     int bb_from_rr, Scalars *__restrict__ sc,
+                                                     double *__restrict__ partials)
+{
+    const T mean = singular ? (T)(sc->sum_r / (double)n) : (T)0;
+    double rz = 0.0, rr = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock) {
+        T ri = r[i];
+        if (singular) {
+            ri -= mean;
+            r[i] = ri;
+        }
+        const T zi = dinv[i] * ri;
+        p[i] = zi;
+        rz += (double)ri * (double)zi;
+        rr += (double)ri * (double)ri;
+    }
+    double v[2] = {rz, rr};
+    if (grid_sum<2>(v, partials, &sc->counter[2]) && threadIdx.x == 0) {
+        sc->rho[0] = v[0];
+        sc->rr = v[1];
+        sc->beta = 0.0;
+        if (bb_from_rr) sc->bb = v[1];
+        if (!(sc->bb > 0.0))
+            sc->stop = 3;
+        else if (!isfinite(v[0]) || !isfinite(v[1]))
+            sc->stop = 2;
+        else
+            sc->stop = (v[1] <= sc->tol2 * sc->bb) ? 1 : 0;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_project_norm(int64_t n, double *__restrict__ r,
+                                                         int singular, Scalars *__restrict__ sc,
+                                                         double *__restrict__ partials)
+{
+    const double mean = singular ? sc->sum_r / (double)n : 0.0;
+    double rr = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock) {
+        double ri = r[i];
+        if (singular) {
+            ri -= mean;
+            r[i] = ri;
+        }
+        rr += ri * ri;
+    }
+    double v[1] = {rr};
+    if (grid_sum<1>(v, partials, &sc->counter[2]) && threadIdx.x == 0) sc->rr = v[0];
+}
+
+__global__ __launch_bounds__(kBlock) void k_cast_scaled(int64_t n, const double *__restrict__ r64,
+                                                        float *__restrict__ r32,
+                                                        float *__restrict__ d32,
+                                                        const Scalars *__restrict__ outer)
+{
+    const double inv = 1.0 / sqrt(outer->rr);
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock) {
+        r32[i] = (float)(r64[i] * inv);
+        d32[i] = 0.0f;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_correct(int64_t n, double *__restrict__ x,
+                                                    const float *__restrict__ d32,
+                                                    const Scalars *__restrict__ outer)
+{
+    const double s = sqrt(outer->rr);
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock)
+        x[i] += s * (double)d32[i];
+}
+
+__global__ __launch_bounds__(kBlock) void k_wdot(int64_t n, const double *__restrict__ w,
+                                                 const double *__restrict__ x,
+                                                 Scalars *__restrict__ sc,
+                                                 double *__restrict__ partials)
+{
+    double s = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock)
+        s += w[i] * x[i];
+    double v[1] = {s};
+    if (grid_sum<1>(v, partials, &sc->counter[2]) && threadIdx.x == 0) sc->wx = v[0];
+}
+
+__global__ __launch_bounds__(kBlock) void k_shift(int64_t n, double *__restrict__ x,
+                                                  const Scalars *__restrict__ sc, double wsum)
+{
+    const double c = sc->wx / wsum;
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock)
+        x[i] -= c;
+}
+
+hns_status check_launch(const char *what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        set_error("launch of %s failed: %s", what, hipGetErrorString(e));
+        return HNS_ERR_HIP;
+    }
+    return HNS_OK;
+}
+
+}  // namespace
+
+int stream_grid(int64_t n)
+{
+    int64_t g = (n + kBlock - 1) / kBlock;
+    if (g > kMaxGrid) g = kMaxGrid;
+    if (g < 1) g = 1;
+    if (g >= 8) g &= ~int64_t(7);
+    return (int)g;
+}
+
+int spmv_grid(const DevMatrix &A)
+{
+    int64_t units = (A.fmt == HNS_FMT_SELL) ? (A.nslices + 3) / 4 : (A.n + 15) / 16;
+    int64_t g = units < kMaxGrid ? units : kMaxGrid;
+    if (g < 1) g = 1;
+    if (g >= 8) g &= ~int64_t(7);
+    return (int)g;
+}
+
+template <typename T, bool DOT>
+static void spmv_dispatch(const DevMatrix &A, const T *vals_csr, const T *vals_sell,
+                          const void *p, void *q, const uint8_t *bc, int bit,
+                          const Scalars *sc, double *part, hipStream_t s)
+{
+    const int G = spmv_grid(A);
+    if (A.fmt == HNS_FMT_SELL)
+        k_spmv_sell<T, DOT><<<G, kBlock, 0, s>>>(A.n, A.nslices, A.slice_ptr, A.scol, vals_sell,
+                                                 (const T *)p, (T *)q, bc, bit, sc, part);
+    else
+        k_spmv_csr<T, DOT><<<G, kBlock, 0, s>>>(A.n, A.rowptr, A.col, vals_csr, (const T *)p,
+                                                (T *)q, bc, bit, sc, part);
+}
+
+hns_status launch_spmv_plain(const DevMatrix &A, bool fp32, const void *p, void *q,
+                             const uint8_t *bc, int bit, hipStream_t s)
+{
+    if (bit < 0) bc = nullptr;
+    if (fp32)
+        spmv_dispatch<float, false>(A, A.val32, A.sval32, p, q, bc, bit, nullptr, nullptr, s);
+    else
+        spmv_dispatch<double, false>(A, A.val, A.sval, p, q, bc, bit, nullptr, nullptr, s);
+    return check_launch("spmv");
+}
+
+hns_status launch_iteration(const IterArgs &a, int parity, hipStream_t s, hipEvent_t *ev)
+{
+    const uint8_t *bc = a.bit < 0 ? nullptr : a.bc;
+    const int Gs = spmv_grid(*a.A);
+    const int Gu = stream_grid(a.n);
+    double *P1 = a.partials + kPartSpmv;
+    double *P2 = a.partials + kPartUpdate;
+    if (ev) HNS_TRY_HIP(hipEventRecord(ev[0], s));
+    if (a.fp32)
+        spmv_dispatch<float, true>(*a.A, a.A->val32, a.A->sval32, a.p, a.q, bc, a.bit, a.sc, P1,
+                                   s);
+    else
+        spmv_dispatch<double, true>(*a.A, a.A->val, a.A->sval, a.p, a.q, bc, a.bit, a.sc, P1, s);
+    if (ev) HNS_TRY_HIP(hipEventRecord(ev[1], s));
+    if (a.fp32)
+        k_update<float><<<Gu, kBlock, 0, s>>>(a.n, (float *)a.x, (float *)a.r, (const float *)a.p,
+                                              (const float *)a.q, (const float *)a.dinv, a.sc, P1,
+                                              Gs, P2, parity);
+    else
+        k_update<double><<<Gu, kBlock, 0, s>>>(a.n, (double *)a.x, (double *)a.r,
+                                               (const double *)a.p, (const double *)a.q,
+                                               (const double *)a.dinv, a.sc, P1, Gs, P2, parity);
+    if (ev) HNS_TRY_HIP(hipEventRecord(ev[2], s));
+    if (a.fp32)
+        k_pupdate<float><<<Gu, kBlock, 0, s>>>(a.n, (float *)a.p, (const float *)a.r,
+                                               (const float *)a.dinv, a.sc, P2, Gu, parity);
+    else
+        k_pupdate<double><<<Gu, kBlock, 0, s>>>(a.n, (double *)a.p, (const double *)a.r,
+                                                (const double *)a.dinv, a.sc, P2, Gu, parity);
+    if (ev) HNS_TRY_HIP(hipEventRecord(ev[3], s));
+    return check_launch("cg iteration");
+}
+
+hns_status launch_bstats(int64_t n, const double *b, const uint8_t *bc, int bit, Scalars *sc,
+                         double *partials, hipStream_t s)
+{
+    if (bit < 0) bc = nullptr;
+    k_bstats<<<stream_grid(n), kBlock, 0, s>>>(n, b, bc, bit, sc, partials + kPartMisc);
+    return check_launch("bstats");
+}
+
+hns_status launch_prepare_x(int64_t n, double *x, const uint8_t *bc, int bit, bool zero_all,
+                            hipStream_t s)
+{
+    if (bit < 0) bc = nullptr;
+    k_prepare_x<<<stream_grid(n), kBlock, 0, s>>>(n, x, bc, bit, zero_all ? 1 : 0);
+    return check_launch("prepare_x");
+}
+
+hns_status launch_residual(int64_t n, const double *b, const double *q, double *r,
+                           const uint8_t *bc, int bit, bool singular, Scalars *sc,
+                           double *partials, hipStream_t s)
+{
+    if (bit < 0) bc = nullptr;
+    k_residual<<<stream_grid(n), kBlock, 0, s>>>(n, b, q, r, bc, bit, singular ? 1 : 0, sc,
+                                                 partials + kPartMisc);
+    return check_launch("residual");
+}
+
+hns_status launch_init_dir(int64_t n, bool fp32, void *r, void *p, const void *dinv,
+                           bool singular, bool bb_from_rr, Scalars *sc, double *partials,
+                           hipStream_t s)
+{
+    const int G = stream_grid(n);
+    if (fp32)
+        k_init_dir<float><<<G, kBlock, 0, s>>>(n, (float *)r, (float *)p, (const float *)dinv,
+                                               singular ? 1 : 0, bb_from_rr ? 1 : 0, sc,
+                                               partials + kPartMisc);
+    else
+        k_init_dir<double><<<G, kBlock, 0, s>>>(n, (double *)r, (double *)p,
+                                                (const double *)dinv, singular ? 1 : 0,
+                                                bb_from_rr ? 1 : 0, sc, partials + kPartMisc);
+    return check_launch("init_dir");
+}
+
+hns_status launch_project_norm(int64_t n, double *r, bool singular, Scalars *sc,
+                               double *partials, hipStream_t s)
+{
+    k_project_norm<<<stream_grid(n), kBlock, 0, s>>>(n, r, singular ? 1 : 0, sc,
+                                                     partials + kPartMisc);
+    return check_launch("project_norm");
+}
+
+hns_status launch_cast_scaled(int64_t n, const double *r64, float *r32, float *d32,
+                              const Scalars *outer, hipStream_t s)
+{
+    k_cast_scaled<<<stream_grid(n), kBlock, 0, s>>>(n, r64, r32, d32, outer);
+    return check_launch("cast_scaled");
+}
+
+hns_status launch_correct(int64_t n, double *x, const float *d32, const Scalars *outer,
+                          hipStream_t s)
+{
+    k_correct<<<stream_grid(n), kBlock, 0, s>>>(n, x, d32, outer);
+    return check_launch("correct");
+}
+
+hns_status launch_normalise(int64_t n, double *x, const double *lumped, double lumped_sum,
+                            Scalars *sc, double *partials, hipStream_t s)
+{
+    k_wdot<<<stream_grid(n), kBlock, 0, s>>>(n, lumped, x, sc, partials + kPartMisc);
+    HNS_TRY(check_launch("wdot"));
+    k_shift<<<stream_grid(n), kBlock, 0, s>>>(n, x, sc, lumped_sum);
+    return check_launch("shift");
+}
+
+}  // namespace hns

@@ -1,0 +1,665 @@
+// Host drivers of the CG solves and the C ABI of hns.h.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "kernels.h"
+
+namespace hns {
+
+static thread_local std::string g_last_error;
+
+void set_error(const char *fmt, ...)
+{
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+}
+
+// ---------------------------------------------------------------------------
+// Workspace: one per concurrent solve, pooled on the operator
+// ---------------------------------------------------------------------------
+struct Workspace {
+    int64_t n = 0;
+    bool mixed = false;
+    void *block = nullptr;
+    double *r = nullptr, *p = nullptr, *q = nullptr;
+    float *r32 = nullptr, *p32 = nullptr, *q32 = nullptr, *d32 = nullptr;
+    double *partials = nullptr;   // kPartTotal doubles
+    Scalars *sc = nullptr;        // [0] FP64 / outer loop, [1] inner FP32 loop
+    Scalars *host = nullptr;      // pinned mirror of sc[0..1]
+    std::vector<hipEvent_t> ev;   // timing events, 4 per iteration of a chunk
+
+    static size_t bytes_for(int64_t n, bool mixed)
+    {
+        auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+        size_t b = 3 * al(n * sizeof(double));
+        if (mixed) b += 4 * al(n * sizeof(float));
+        b += al(kPartTotal * sizeof(double)) + al(2 * sizeof(Scalars));
+        return b;
+    }
+
+    hns_status allocate(int64_t n_, bool mixed_)
+    {
+        n = n_;
+        mixed = mixed_;
+        auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+        hipError_t e = hipMalloc(&block, bytes_for(n, mixed));
+        if (e != hipSuccess) {
+            block = nullptr;
+            set_error("workspace allocation of %zu bytes failed: %s", bytes_for(n, mixed),
+                      hipGetErrorString(e));
+            return e == hipErrorOutOfMemory ? HNS_ERR_OOM : HNS_ERR_HIP;
+        }
+        char *c = (char *)block;
+        r = (double *)c, c += al(n * sizeof(double));
+        p = (double *)c, c += al(n * sizeof(double));
+        q = (double *)c, c += al(n * sizeof(double));
+        if (mixed) {
+            r32 = (float *)c, c += al(n * sizeof(float));
+            p32 = (float *)c, c += al(n * sizeof(float));
+            q32 = (float *)c, c += al(n * sizeof(float));
+            d32 = (float *)c, c += al(n * sizeof(float));
+        }
+        partials = (double *)c, c += al(kPartTotal * sizeof(double));
+        sc = (Scalars *)c;
+        HNS_TRY_HIP(hipMemset(sc, 0, 2 * sizeof(Scalars)));
+        HNS_TRY_HIP(hipHostMalloc((void **)&host, 2 * sizeof(Scalars), hipHostMallocDefault));
+        memset(host, 0, 2 * sizeof(Scalars));
+        return HNS_OK;
+    }
+
+    hns_status ensure_events(size_t count)
+    {
+        while (ev.size() < count) {
+            hipEvent_t e;
+            HNS_TRY_HIP(hipEventCreate(&e));
+            ev.push_back(e);
+        }
+        return HNS_OK;
+    }
+
+    ~Workspace()
+    {
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+        if (block) (void)hipFree(block);
+        if (host) (void)hipHostFree(host);
+    }
+};
+
+static hns_status acquire_ws(hns_operator *op, bool mixed, Workspace **out)
+{
+    {
+        std::lock_guard<std::mutex> g(op->ws_mutex);
+        for (size_t i = 0; i < op->ws_free.size(); ++i) {
+            Workspace *w = op->ws_free[i];
+            if (w->mixed || !mixed) {
+                op->ws_free.erase(op->ws_free.begin() + i);
+                *out = w;
+                return HNS_OK;
+            }
+        }
+    }
+    Workspace *w = new Workspace();
+    hns_status st = w->allocate(op->n, mixed);
+    if (st != HNS_OK) {
+        delete w;
+        return st;
+    }
+    *out = w;
+    return HNS_OK;
+}
+
+static void release_ws(hns_operator *op, Workspace *w)
+{
+    std::lock_guard<std::mutex> g(op->ws_mutex);
+    op->ws_free.push_back(w);
+}
+
+// copy the two scalar blocks host <-> device on the solve's stream
+static hns_status push_scalars(Workspace *w, int which, hipStream_t s)
+{
+    HNS_TRY_HIP(hipMemcpyAsync(w->sc + which, w->host + which, sizeof(Scalars),
+                               hipMemcpyHostToDevice, s));
+    return HNS_OK;
+}
+
+static hns_status pull_scalars(Workspace *w, int which, hipStream_t s)
+{
+    HNS_TRY_HIP(hipMemcpyAsync(w->host + which, w->sc + which, sizeof(Scalars),
+                               hipMemcpyDeviceToHost, s));
+    HNS_TRY_HIP(hipStreamSynchronize(s));
+    return HNS_OK;
+}
+
+static void reset_scalars(Scalars &h, double tol)
+{
+    memset(&h, 0, sizeof(Scalars));
+    h.tol2 = tol * tol;
+}
+
+// ---------------------------------------------------------------------------
+// FP64 Jacobi-PCG
+// ---------------------------------------------------------------------------
+struct SolveCtx {
+    hns_operator *op;
+    int bit;
+    bool singular;
+    const double *b;
+    double *x;
+    double tol;
+    int max_iter;
+    hipStream_t s;
+    Workspace *w;
+};
+
+// r = b - A x (projected in the pure-Neumann case), then a fresh search
+// direction: z = D^-1 r, p = z, rho = r^T z.  Sets stop = 1 when already
+// converged, 3 when b = 0.
+static hns_status restart_fp64(const SolveCtx &c)
+{
+    hns_operator *op = c.op;
+    Workspace *w = c.w;
+    HNS_TRY(launch_spmv_plain(op->A, false, c.x, w->q, op->bc, c.bit, c.s));
+    HNS_TRY(launch_residual(op->n, c.b, w->q, w->r, op->bc, c.bit, c.singular, w->sc,
+                            w->partials, c.s));
+    HNS_TRY(launch_init_dir(op->n, false, w->r, w->p, op->dinv, c.singular, false, w->sc,
+                            w->partials, c.s));
+    return HNS_OK;
+}
+
+// Enqueue `count` CG iterations; `parity` is the iteration index since the
+// last restart (selects the rho slot) and is advanced.
+static hns_status enqueue_iterations(hns_operator *op, Workspace *w, const DevMatrix &A,
+                                     bool fp32, int bit, void *x, void *r, void *p, void *q,
+                                     const void *dinv, Scalars *sc, int count, int *parity,
+                                     hipStream_t s)
+{
+    const bool prof = op->profile != 0;
+    if (prof) HNS_TRY(w->ensure_events(4 * (size_t)count));
+    IterArgs a{&A, fp32, op->n, x, r, p, q, dinv, op->bc, bit, sc, w->partials};
+    for (int it = 0; it < count; ++it) {
+        HNS_TRY(launch_iteration(a, *parity & 1, s, prof ? &w->ev[4 * it] : nullptr));
+        *parity += 1;
+    }
+    return HNS_OK;
+}
+
+// After the chunk has completed: add the kernel durations of the first
+// `done` iterations (those that did work) to the operator's counters.
+static hns_status account_iterations(hns_operator *op, Workspace *w, bool fp32, int done)
+{
+    if (!op->profile || done <= 0) return HNS_OK;
+    const int base = fp32 ? 3 : 0;
+    for (int it = 0; it < done; ++it)
+        for (int k = 0; k < 3; ++k) {
+            float ms = 0.0f;
+            HNS_TRY_HIP(hipEventElapsedTime(&ms, w->ev[4 * it + k], w->ev[4 * it + k + 1]));
+            op->prof_ms[base + k] += ms;
+            op->prof_count[base + k] += 1;
+        }
+    return HNS_OK;
+}
+
+static hns_status begin_solve(const SolveCtx &c, hns_solve_info *info, bool *done)
+{
+    hns_operator *op = c.op;
+    Workspace *w = c.w;
+    *done = false;
+    reset_scalars(w->host[0], c.tol);
+    HNS_TRY(push_scalars(w, 0, c.s));
+    HNS_TRY(launch_bstats(op->n, c.b, op->bc, c.bit, w->sc, w->partials, c.s));
+    HNS_TRY(launch_prepare_x(op->n, c.x, op->bc, c.bit, false, c.s));
+    HNS_TRY(pull_scalars(w, 0, c.s));
+    if (w->host[0].nonfinite > 0) {
+        set_error("right-hand side has %.0f non-finite entries", w->host[0].nonfinite);
+        info->status = HNS_ERR_INVALID;
+        *done = true;
+        return HNS_ERR_INVALID;
+    }
+    info->removed_mean = c.singular ? w->host[0].sumb / (double)op->n : 0.0;
+    return HNS_OK;
+}
+
+static hns_status solve_fp64(const SolveCtx &c, hns_solve_info *info)
+{
+    hns_operator *op = c.op;
+    Workspace *w = c.w;
+    bool done;
+    HNS_TRY(begin_solve(c, info, &done));
+    HNS_TRY(restart_fp64(c));
+    HNS_TRY(pull_scalars(w, 0, c.s));
+    Scalars &h = w->host[0];
+    if (h.stop == 3) {  // b = 0
+        HNS_TRY(launch_prepare_x(op->n, c.x, nullptr, -1, true, c.s));
+        HNS_TRY_HIP(hipStreamSynchronize(c.s));
+        info->status = HNS_OK;
+        return HNS_OK;
+    }
+    hns_status status = HNS_NOT_CONVERGED;
+    int parity = 0;
+    if (h.stop == 1) {
+        status = HNS_OK;
+    } else if (h.stop == 2) {
+        status = HNS_ERR_BREAKDOWN;
+    } else {
+        for (;;) {
+            const int left = c.max_iter - h.iter;
+            if (left <= 0) break;
+            const int chunk = left < op->check_every ? left : op->check_every;
+            const int before = h.iter;
+            HNS_TRY(enqueue_iterations(op, w, op->A, false, c.bit, c.x, w->r, w->p, w->q,
+                                       op->dinv, w->sc, chunk, &parity, c.s));
+            HNS_TRY(pull_scalars(w, 0, c.s));
+            HNS_TRY(account_iterations(op, w, false, h.iter - before));
+            if (h.stop == 2) {
+                status = HNS_ERR_BREAKDOWN;
+                break;
+            }
+            if (h.stop == 1) {
+                // recursive residual below tolerance: verify with the true one
+                const int iters = h.iter;
+                HNS_TRY(restart_fp64(c));
+                HNS_TRY(pull_scalars(w, 0, c.s));
+                h.iter = iters;
+                parity = 0;
+                if (h.stop == 1) {
+                    status = HNS_OK;
+                    break;
+                }
+                // restarted from the true residual; the device counter was
+                // not touched by the restart kernels
+            }
+        }
+    }
+    info->iterations = h.iter;
+    info->outer_iterations = 1;
+    if (status == HNS_NOT_CONVERGED) {
+        const int iters = h.iter;
+        HNS_TRY(restart_fp64(c));
+        HNS_TRY(pull_scalars(w, 0, c.s));
+        h.iter = iters;
+    }
+    info->relres_true = h.bb > 0 ? std::sqrt(h.rr / h.bb) : 0.0;
+    if (status >= 0 && c.singular) {
+        HNS_TRY(launch_normalise(op->n, c.x, op->lumped, op->lumped_sum, w->sc, w->partials, c.s));
+        HNS_TRY_HIP(hipStreamSynchronize(c.s));
+    }
+    if (status == HNS_ERR_BREAKDOWN)
+        set_error("CG breakdown after %d iterations (p^T A p = %g)", h.iter, h.gamma);
+    info->status = status;
+    return status;
+}
+
+// ---------------------------------------------------------------------------
+// Mixed precision: FP32 inner PCG inside FP64 iterative refinement
+// ---------------------------------------------------------------------------
+static hns_status true_residual_fp64(const SolveCtx &c)
+{
+    hns_operator *op = c.op;
+    Workspace *w = c.w;
+    HNS_TRY(launch_spmv_plain(op->A, false, c.x, w->q, op->bc, c.bit, c.s));
+    HNS_TRY(launch_residual(op->n, c.b, w->q, w->r, op->bc, c.bit, c.singular, w->sc,
+                            w->partials, c.s));
+    HNS_TRY(launch_project_norm(op->n, w->r, c.singular, w->sc, w->partials, c.s));
+    return HNS_OK;
+}
+
+static hns_status solve_mixed(const SolveCtx &c, hns_solve_info *info)
+{
+    hns_operator *op = c.op;
+    Workspace *w = c.w;
+    bool done;
+    HNS_TRY(begin_solve(c, info, &done));
+    HNS_TRY(true_residual_fp64(c));
+    HNS_TRY(pull_scalars(w, 0, c.s));
+    Scalars &h = w->host[0];
+    Scalars &hi = w->host[1];
+    if (!(h.bb > 0.0)) {
+        HNS_TRY(launch_prepare_x(op->n, c.x, nullptr, -1, true, c.s));
+        HNS_TRY_HIP(hipStreamSynchronize(c.s));
+        info->status = HNS_OK;
+        info->outer_iterations = 0;
+        return HNS_OK;
+    }
+    const double tol2 = c.tol * c.tol;
+    hns_status status = HNS_NOT_CONVERGED;
+    int total_inner = 0, outer = 0;
+    double rr_prev = h.rr;
+    for (;;) {
+        if (h.rr <= tol2 * h.bb) {
+            status = HNS_OK;
+            break;
+        }
+        if (outer >= op->max_outer || total_inner >= c.max_iter) break;
+        if (outer > 0 && h.rr > 0.25 * rr_prev) {
+            set_error("refinement stagnated at relative residual %g", std::sqrt(h.rr / h.bb));
+            break;
+        }
+        rr_prev = h.rr;
+        ++outer;
+        // inner problem A32 d = r / ||r||, solved to inner_tol
+        HNS_TRY(launch_cast_scaled(op->n, w->r, w->r32, w->d32, w->sc, c.s));
+        reset_scalars(hi, op->inner_tol);
+        HNS_TRY(push_scalars(w, 1, c.s));
+        HNS_TRY(launch_init_dir(op->n, true, w->r32, w->p32, op->dinv32, false, true, w->sc + 1,
+                                w->partials, c.s));
+        HNS_TRY(pull_scalars(w, 1, c.s));
+        bool inner_break = (hi.stop == 2);
+        int parity = 0;
+        while (hi.stop == 0) {
+            const int left = c.max_iter - total_inner - hi.iter;
+            if (left <= 0) break;
+            const int chunk = left < op->check_every ? left : op->check_every;
+            const int before = hi.iter;
+            HNS_TRY(enqueue_iterations(op, w, op->A, true, c.bit, w->d32, w->r32, w->p32, w->q32,
+                                       op->dinv32, w->sc + 1, chunk, &parity, c.s));
+            HNS_TRY(pull_scalars(w, 1, c.s));
+            HNS_TRY(account_iterations(op, w, true, hi.iter - before));
+            if (hi.stop == 2) inner_break = true;
+        }
+        total_inner += hi.iter;
+        if (inner_break && hi.iter == 0) {
+            status = HNS_ERR_BREAKDOWN;
+            set_error("FP32 inner CG broke down at its first iteration");
+            break;
+        }
+        HNS_TRY(launch_correct(op->n, c.x, w->d32, w->sc, c.s));
+        HNS_TRY(true_residual_fp64(c));
+        HNS_TRY(pull_scalars(w, 0, c.s));
+    }
+    info->iterations = total_inner;
+    info->outer_iterations = outer;
+    info->relres_true = std::sqrt(h.rr / h.bb);
+    if (status >= 0 && c.singular) {
+        HNS_TRY(launch_normalise(op->n, c.x, op->lumped, op->lumped_sum, w->sc, w->partials, c.s));
+        HNS_TRY_HIP(hipStreamSynchronize(c.s));
+    }
+    info->status = status;
+    return status;
+}
+
+}  // namespace hns
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+using namespace hns;
+
+extern "C" {
+
+const char *hns_last_error(void) { return g_last_error.c_str(); }
+
+const char *hns_status_string(hns_status s)
+{
+    switch (s) {
+    case HNS_OK: return "ok";
+    case HNS_NOT_CONVERGED: return "not converged";
+    case HNS_ERR_INVALID: return "invalid argument";
+    case HNS_ERR_HIP: return "HIP runtime error";
+    case HNS_ERR_OOM: return "out of memory";
+    case HNS_ERR_MESH: return "invalid mesh";
+    case HNS_ERR_BREAKDOWN: return "CG breakdown";
+    }
+    return "unknown status";
+}
+
+static hns_status finish_operator(hns_operator *op, const HostCSR &A, uint32_t fmt_flag,
+                                  const std::vector<double> &lumped, const uint8_t *bc_host)
+{
+    const bool keep32 = (op->flags & HNS_KEEP_FP32) != 0;
+    uint32_t fmt = fmt_flag ? fmt_flag : choose_format(A);
+    HNS_TRY(upload_matrix(A, fmt, keep32, op->A));
+    // Jacobi: inverse diagonal
+    std::vector<double> dinv(A.n, 0.0);
+    for (int64_t i = 0; i < A.n; ++i) {
+        double d = 0.0;
+        for (int32_t k = A.rowptr[i]; k < A.rowptr[i + 1]; ++k)
+            if (A.col[k] == i) d = A.val[k];
+        if (!(d > 0.0) || !std::isfinite(d)) {
+            // not positive definite: kept, but every solve reports breakdown
+            if (op->bad_diag < 0) op->bad_diag = i;
+            dinv[i] = 0.0;
+            continue;
+        }
+        dinv[i] = 1.0 / d;
+    }
+    auto up = [](const void *src, size_t bytes, void **dst) -> hns_status {
+        hipError_t e = hipMalloc(dst, bytes);
+        if (e != hipSuccess) {
+            *dst = nullptr;
+            set_error("hipMalloc of %zu bytes failed: %s", bytes, hipGetErrorString(e));
+            return e == hipErrorOutOfMemory ? HNS_ERR_OOM : HNS_ERR_HIP;
+        }
+        HNS_TRY_HIP(hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice));
+        return HNS_OK;
+    };
+    HNS_TRY(up(dinv.data(), A.n * sizeof(double), (void **)&op->dinv));
+    if (keep32) {
+        std::vector<float> d32(dinv.begin(), dinv.end());
+        HNS_TRY(up(d32.data(), A.n * sizeof(float), (void **)&op->dinv32));
+    }
+    if (bc_host) HNS_TRY(up(bc_host, A.n, (void **)&op->bc));
+    HNS_TRY(up(lumped.data(), A.n * sizeof(double), (void **)&op->lumped));
+    op->lumped_sum = 0.0;
+    for (double m : lumped) op->lumped_sum += m;
+    return HNS_OK;
+}
+
+hns_status hns_assemble(const hns_mesh *mesh, double nu_h, double nu_v, double dt, uint32_t flags,
+                        hns_operator **out)
+{
+    if (!out) {
+        set_error("out is null");
+        return HNS_ERR_INVALID;
+    }
+    *out = nullptr;
+    const uint32_t kind = flags & (HNS_POISSON | HNS_HELMHOLTZ);
+    if (kind != HNS_POISSON && kind != HNS_HELMHOLTZ) {
+        set_error("flags must select exactly one of HNS_POISSON / HNS_HELMHOLTZ");
+        return HNS_ERR_INVALID;
+    }
+    if (!std::isfinite(nu_h) || !std::isfinite(nu_v) || !std::isfinite(dt) || nu_h < 0 ||
+        nu_v < 0) {
+        set_error("viscosities must be finite and non-negative, dt finite");
+        return HNS_ERR_INVALID;
+    }
+    uint32_t fmt = flags & (HNS_FMT_CSR | HNS_FMT_SELL);
+    if (fmt == (HNS_FMT_CSR | HNS_FMT_SELL)) {
+        set_error("choose one storage format");
+        return HNS_ERR_INVALID;
+    }
+    hns_operator *op = new hns_operator();
+    (void)hipGetDevice(&op->device);
+    op->flags = flags;
+    op->kind = kind;
+    op->nu_h = nu_h;
+    op->nu_v = nu_v;
+    op->dt = dt;
+    HostCSR A;
+    std::vector<double> lumped;
+    const double c_mass = (kind == HNS_HELMHOLTZ) ? 1.0 : 0.0;
+    const double c_stiff = (kind == HNS_HELMHOLTZ) ? dt : 1.0;
+    hns_status st = assemble_host(mesh, c_mass, c_stiff, nu_h, nu_v, A, &lumped);
+    if (st == HNS_OK) {
+        op->n = A.n;
+        st = finish_operator(op, A, fmt, lumped, mesh->bc);
+    }
+    if (st != HNS_OK) {
+        hns_operator_destroy(op);
+        return st;
+    }
+    *out = op;
+    return HNS_OK;
+}
+
+void hns_operator_destroy(hns_operator *op)
+{
+    if (!op) return;
+    (void)hipDeviceSynchronize();
+    op->A.release();
+    op->M.release();
+    for (auto &b : op->B) b.release();
+    op->Ms.release();
+    void *ptrs[] = {op->dinv, op->dinv32, op->bc, op->lumped};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    for (Workspace *w : op->ws_free) delete w;
+    delete op;
+}
+
+hns_status hns_profile_enable(hns_operator *op, int on)
+{
+    if (!op) {
+        set_error("null operator");
+        return HNS_ERR_INVALID;
+    }
+    op->profile = on ? 1 : 0;
+    if (on)
+        for (int k = 0; k < 6; ++k) {
+            op->prof_ms[k] = 0.0;
+            op->prof_count[k] = 0;
+        }
+    return HNS_OK;
+}
+
+hns_status hns_profile_read(const hns_operator *op, int kernel, double *total_ms,
+                            int64_t *launches)
+{
+    if (!op || kernel < 0 || kernel > 5 || !total_ms || !launches) {
+        set_error("hns_profile_read: bad arguments");
+        return HNS_ERR_INVALID;
+    }
+    *total_ms = op->prof_ms[kernel];
+    *launches = op->prof_count[kernel];
+    return HNS_OK;
+}
+
+int64_t hns_operator_n(const hns_operator *op) { return op ? op->n : -1; }
+int64_t hns_operator_nnz(const hns_operator *op) { return op ? op->A.nnz : -1; }
+uint32_t hns_operator_format(const hns_operator *op) { return op ? op->A.fmt : 0; }
+
+hns_status hns_set_param(hns_operator *op, const char *name, double value)
+{
+    if (!op || !name) {
+        set_error("null operator or name");
+        return HNS_ERR_INVALID;
+    }
+    std::string k(name);
+    if (k == "check_every" && value >= 1 && value <= 1e6) {
+        op->check_every = (int)value;
+    } else if (k == "inner_tol" && value > 0 && value < 1) {
+        op->inner_tol = value;
+    } else if (k == "max_outer" && value >= 1 && value <= 1000) {
+        op->max_outer = (int)value;
+    } else if (k == "use_graph" && (value == 0 || value == 1)) {
+        op->use_graph = (int)value;
+    } else {
+        set_error("unknown parameter or bad value: %s = %g", name, value);
+        return HNS_ERR_INVALID;
+    }
+    return HNS_OK;
+}
+
+size_t hns_footprint_bytes(const hns_operator *op, int k, uint32_t mode, int include_operator)
+{
+    if (!op || k < 1) return 0;
+    const bool mixed = (mode == HNS_MIXED);
+    size_t b = (size_t)k * Workspace::bytes_for(op->n, mixed);
+    if (include_operator) {
+        b += op->A.bytes() + (size_t)op->n * (8 + 1 + 8);
+        if (op->dinv32) b += (size_t)op->n * 4;
+        if (op->has_aux) b += op->M.bytes() + op->B[0].bytes() * 3 + op->Ms.bytes();
+    }
+    return b;
+}
+
+static hns_status check_solve_args(hns_operator *op, int mask_bit, const void *b, const void *x,
+                                   double tol, int max_iter, uint32_t mode)
+{
+    if (!op || !b || !x) {
+        set_error("null operator or vector");
+        return HNS_ERR_INVALID;
+    }
+    if (mask_bit < -1 || mask_bit > 7) {
+        set_error("mask_bit must be -1 or 0..7");
+        return HNS_ERR_INVALID;
+    }
+    if (mask_bit >= 0 && !op->bc) {
+        set_error("mask_bit given but the mesh had no Dirichlet bits");
+        return HNS_ERR_INVALID;
+    }
+    if (!(tol > 0) || !std::isfinite(tol) || max_iter < 0) {
+        set_error("tol must be positive and finite, max_iter >= 0");
+        return HNS_ERR_INVALID;
+    }
+    if (mode != HNS_FP64 && mode != HNS_MIXED) {
+        set_error("unknown mode %u", mode);
+        return HNS_ERR_INVALID;
+    }
+    if (mode == HNS_MIXED && !op->dinv32) {
+        set_error("HNS_MIXED needs an operator assembled with HNS_KEEP_FP32");
+        return HNS_ERR_INVALID;
+    }
+    return HNS_OK;
+}
+
+hns_status hns_solve(hns_operator *op, int mask_bit, const double *b_dev, double *x_dev,
+                     double tol, int max_iter, uint32_t mode, void *stream, hns_solve_info *info)
+{
+    hns_solve_info local;
+    if (!info) info = &local;
+    memset(info, 0, sizeof(*info));
+    hns_status st = check_solve_args(op, mask_bit, b_dev, x_dev, tol, max_iter, mode);
+    if (st != HNS_OK) {
+        info->status = st;
+        return st;
+    }
+    if (op->bad_diag >= 0) {
+        set_error("diagonal entry %lld is not positive: Jacobi-PCG needs an SPD operator",
+                  (long long)op->bad_diag);
+        info->status = HNS_ERR_BREAKDOWN;
+        return HNS_ERR_BREAKDOWN;
+    }
+    Workspace *w = nullptr;
+    st = acquire_ws(op, mode == HNS_MIXED, &w);
+    if (st != HNS_OK) {
+        info->status = st;
+        return st;
+    }
+    SolveCtx c{op, mask_bit, op->kind == HNS_POISSON && mask_bit < 0, b_dev, x_dev, tol,
+               max_iter, (hipStream_t)stream, w};
+    st = (mode == HNS_MIXED) ? solve_mixed(c, info) : solve_fp64(c, info);
+    info->status = st;
+    release_ws(op, w);
+    return st;
+}
+
+hns_status hns_apply(hns_operator *op, int mask_bit, const double *x_dev, double *y_dev,
+                     void *stream)
+{
+    if (!op || !x_dev || !y_dev || mask_bit < -1 || mask_bit > 7 || (mask_bit >= 0 && !op->bc)) {
+        set_error("hns_apply: bad arguments");
+        return HNS_ERR_INVALID;
+    }
+    HNS_TRY(launch_spmv_plain(op->A, false, x_dev, y_dev, op->bc, mask_bit, (hipStream_t)stream));
+    HNS_TRY_HIP(hipStreamSynchronize((hipStream_t)stream));
+    return HNS_OK;
+}
+
+hns_status hns_solve_batched(hns_operator *op, int k, const int *mask_bits, const double *B_dev,
+                             double *X_dev, double tol, int max_iter, uint32_t mode, void *stream,
+                             hns_solve_info *infos)
+{
+    (void)op; (void)k; (void)mask_bits; (void)B_dev; (void)X_dev; (void)tol; (void)max_iter;
+    (void)mode; (void)stream; (void)infos;
+    set_error("hns_solve_batched: not available in this build");
+    return HNS_ERR_INVALID;
+}
+
+}  // extern "C"

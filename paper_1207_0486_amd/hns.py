@@ -1,0 +1,212 @@
+"""Python binding of the hns library.
+
+Argument marshalling only: every step of assembly and solve runs in libhns.so
+(host C++ assembly, HIP kernels for the solves).  PyTorch supplies device
+memory and streams.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+KINDS = {"poisson": L.HNS_POISSON, "helmholtz": L.HNS_HELMHOLTZ}
+FORMATS = {"auto": L.HNS_FMT_AUTO, "csr": L.HNS_FMT_CSR, "sell": L.HNS_FMT_SELL}
+FORMAT_NAMES = {L.HNS_FMT_CSR: "csr", L.HNS_FMT_SELL: "sell"}
+MODES = {"fp64": L.HNS_FP64, "mixed": L.HNS_MIXED}
+
+
+class HNSError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        msg = L.lib().hns_last_error().decode(errors="replace")
+        name = L.lib().hns_status_string(status).decode()
+        super().__init__(f"{where}: {name} ({status}): {msg}")
+        self.status = status
+
+
+@dataclass
+class SolveInfo:
+    iterations: int
+    outer_iterations: int
+    relres_true: float
+    removed_mean: float
+    status: int
+
+    @property
+    def converged(self) -> bool:
+        return self.status == L.HNS_OK
+
+    @classmethod
+    def _from(cls, s: L.hns_solve_info) -> "SolveInfo":
+        return cls(int(s.iterations), int(s.outer_iterations), float(s.relres_true),
+                   float(s.removed_mean), int(s.status))
+
+
+def _stream_handle(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _dev_f64(t: torch.Tensor, name: str, n: int | None = None, k: int | None = None):
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError(f"{name} must be contiguous float64")
+    if n is not None:
+        want = (n,) if k is None else (n, k)
+        if tuple(t.shape) != want:
+            raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {want}")
+    return C.c_void_p(t.data_ptr())
+
+
+class Operator:
+    """A device-resident assembled operator.
+
+    kind="helmholtz": A = M + dt K_nu (velocity prediction);
+    kind="poisson":   A = K_nu        (pressure increment).
+    `mesh` is any object with xyz (n,3) float64, tets (T,4) int32, bc (n,)
+    uint8 (optional) and surf_tris (S,3) int32 (optional).
+    """
+
+    def __init__(self, mesh, nu_h: float, nu_v: float, dt: float = 0.0, kind: str = "helmholtz",
+                 keep_fp32: bool = False, step_aux: bool = False, fmt: str = "auto",
+                 device: int | torch.device | None = None):
+        self._h = None
+        self.kind = kind
+        flags = KINDS[kind] | FORMATS[fmt]
+        if keep_fp32:
+            flags |= L.HNS_KEEP_FP32
+        if step_aux:
+            flags |= L.HNS_STEP_AUX
+        xyz = np.ascontiguousarray(mesh.xyz, dtype=np.float64)
+        tets = np.ascontiguousarray(mesh.tets, dtype=np.int32)
+        bc = getattr(mesh, "bc", None)
+        bc = None if bc is None else np.ascontiguousarray(bc, dtype=np.uint8)
+        tris = getattr(mesh, "surf_tris", None)
+        tris = None if tris is None else np.ascontiguousarray(tris, dtype=np.int32)
+        m = L.hns_mesh()
+        m.n_nodes = xyz.shape[0]
+        m.xyz = xyz.ctypes.data_as(C.POINTER(C.c_double))
+        m.n_tets = tets.shape[0]
+        m.tets = tets.ctypes.data_as(C.POINTER(C.c_int32))
+        m.bc = None if bc is None else bc.ctypes.data_as(C.POINTER(C.c_uint8))
+        m.n_surf_tris = 0 if tris is None else tris.shape[0]
+        m.surf_tris = None if tris is None else tris.ctypes.data_as(C.POINTER(C.c_int32))
+        if device is None:
+            idx = torch.cuda.current_device()
+        elif isinstance(device, torch.device):
+            idx = device.index or 0
+        else:
+            idx = int(device)
+        self.device = torch.device("cuda", idx)
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            st = L.lib().hns_assemble(C.byref(m), nu_h, nu_v, dt, flags, C.byref(h))
+        if st != L.HNS_OK:
+            raise HNSError(st, "hns_assemble")
+        self._h = h
+        self.n = int(L.lib().hns_operator_n(h))
+        self.nnz = int(L.lib().hns_operator_nnz(h))
+        self.format = FORMAT_NAMES.get(int(L.lib().hns_operator_format(h)), "?")
+        self.keep_fp32 = keep_fp32
+
+    # -- lifetime -------------------------------------------------------
+    def close(self):
+        if self._h is not None:
+            L.lib().hns_operator_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- queries ------------------------------------------------------------
+    def footprint(self, k: int = 1, mode: str = "fp64", include_operator: bool = True) -> int:
+        return int(L.lib().hns_footprint_bytes(self._h, k, MODES[mode], int(include_operator)))
+
+    def set_param(self, name: str, value: float):
+        st = L.lib().hns_set_param(self._h, name.encode(), float(value))
+        if st != L.HNS_OK:
+            raise HNSError(st, "hns_set_param")
+
+    def profile(self, on: bool = True):
+        st = L.lib().hns_profile_enable(self._h, int(on))
+        if st != L.HNS_OK:
+            raise HNSError(st, "hns_profile_enable")
+
+    def profile_read(self):
+        """{kernel: (total_ms, launches)} for spmv/update/pupdate (fp64, fp32)."""
+        names = ["spmv", "update", "pupdate", "spmv32", "update32", "pupdate32"]
+        out = {}
+        for k, name in enumerate(names):
+            ms = C.c_double()
+            cnt = C.c_int64()
+            st = L.lib().hns_profile_read(self._h, k, C.byref(ms), C.byref(cnt))
+            if st != L.HNS_OK:
+                raise HNSError(st, "hns_profile_read")
+            out[name] = (ms.value, cnt.value)
+        return out
+
+    # -- compute ------------------------------------------------------------
+    def apply(self, x: torch.Tensor, mask_bit: int = -1, out: torch.Tensor | None = None,
+              stream=None) -> torch.Tensor:
+        xp = _dev_f64(x, "x", self.n)
+        y = torch.empty_like(x) if out is None else out
+        yp = _dev_f64(y, "out", self.n)
+        with torch.cuda.device(self.device):
+            st = L.lib().hns_apply(self._h, mask_bit, xp, yp, _stream_handle(stream))
+        if st != L.HNS_OK:
+            raise HNSError(st, "hns_apply")
+        return y
+
+    def solve(self, b: torch.Tensor, x: torch.Tensor | None = None, tol: float = 1e-10,
+              max_iter: int = 100000, mode: str = "fp64", mask_bit: int = -1, stream=None,
+              check: bool = True):
+        """Solve A x = b; returns (x, SolveInfo).  x (if given) is the initial
+        guess and is overwritten in place."""
+        bp = _dev_f64(b, "b", self.n)
+        if x is None:
+            x = torch.zeros_like(b)
+        xp = _dev_f64(x, "x", self.n)
+        info = L.hns_solve_info()
+        with torch.cuda.device(self.device):
+            st = L.lib().hns_solve(self._h, mask_bit, bp, xp, tol, max_iter, MODES[mode],
+                                   _stream_handle(stream), C.byref(info))
+        if st < 0 and check:
+            raise HNSError(st, "hns_solve")
+        return x, SolveInfo._from(info)
+
+    def solve_batched(self, B: torch.Tensor, X: torch.Tensor | None = None, mask_bits=None,
+                      tol: float = 1e-10, max_iter: int = 100000, mode: str = "fp64",
+                      stream=None, check: bool = True):
+        """Solve A X[:, j] = B[:, j] for the k columns of the n x k row-major B."""
+        if B.dim() != 2:
+            raise ValueError("B must be n x k")
+        k = int(B.shape[1])
+        Bp = _dev_f64(B, "B", self.n, k)
+        if X is None:
+            X = torch.zeros_like(B)
+        Xp = _dev_f64(X, "X", self.n, k)
+        if mask_bits is None:
+            mask_bits = [-1] * k
+        bits = (C.c_int * k)(*[int(v) for v in mask_bits])
+        infos = (L.hns_solve_info * k)()
+        with torch.cuda.device(self.device):
+            st = L.lib().hns_solve_batched(self._h, k, bits, Bp, Xp, tol, max_iter, MODES[mode],
+                                           _stream_handle(stream), infos)
+        if st < 0 and check:
+            raise HNSError(st, "hns_solve_batched")
+        return X, [SolveInfo._from(infos[j]) for j in range(k)]
