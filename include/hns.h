@@ -152,7 +152,17 @@ uint32_t hns_operator_format(const hns_operator *op);
 /* Tunables (returns HNS_ERR_INVALID for an unknown name or a bad value):
  *   "check_every"  CG iterations between host convergence reads (default 32)
  *   "inner_tol"    relative tolerance of each FP32 inner solve (default 1e-5)
- *   "max_outer"    cap on refinement steps in HNS_MIXED (default 30)
+ *   "max_outer"    cap on refinement steps of the restarted variant (default 30)
+ *   "mixed_variant" HNS_MIXED algorithm:
+ *                  0 (default) one FP32 CG recurrence (FP32 matrix, vectors and
+ *                    diagonal) whose residual is replaced by the FP64 true
+ *                    residual, and whose iterate is added to the FP64
+ *                    solution, each time it has dropped by "replace_drop";
+ *                  1 classic refinement: a fresh FP32 CG to "inner_tol" per
+ *                    FP64 correction x += |r| d;
+ *                  2 FP32 matrix and diagonal with FP64 vectors, with the same
+ *                    FP64 residual replacement as 0
+ *   "replace_drop" residual drop between FP64 replacements (default 0.1)
  *   "use_graph"    1 = replay captured HIP graphs for iteration chunks */
 hns_status hns_set_param(hns_operator *op, const char *name, double value);
 
@@ -160,6 +170,57 @@ hns_status hns_set_param(hns_operator *op, const char *name, double value);
  * zeroed and its columns ignored (mask_bit = -1: plain product). */
 hns_status hns_apply(hns_operator *op, int mask_bit, const double *x_dev, double *y_dev,
                      void *stream);
+
+/* ------------------------------------------------------------------------
+ * Projection-step right-hand sides (Sec. 3 time discretisation, Sec. 4/5
+ * weak forms), on a HNS_HELMHOLTZ operator assembled with HNS_STEP_AUX
+ * (the mesh must carry its surface triangles).  The operator then also keeps
+ *   M    mass matrix,  M_ij = int phi_i phi_j
+ *   B_c  divergence coupling, (B_c)_ij = int phi_i d phi_j / d x_c, c = 1..3,
+ *        and its transpose
+ *   M_s  surface mass on Gamma_s, (M_s)_ij = int_{Gamma_s} phi_i phi_j ds
+ *   m_L  lumped mass, (m_L)_i = sum_j M_ij
+ * Velocity fields are 3 x n (component-major, one n-vector per component);
+ * component c uses Dirichlet bit c-1 of mesh.bc.  All pointers are device.
+ * The time step is the operator's dt (the implicit-Euler form of the
+ * prediction step; a BDF2 step assembles with dt' = 2 dt / 3).
+ * These calls use scratch memory of the operator: calls on one operator must
+ * not overlap (different operators may run concurrently).  They return after
+ * their work on `stream` has completed.
+ * ------------------------------------------------------------------------ */
+
+/* Velocity-prediction right-hand sides (eq. fofa_velo_pred_h multiplied by
+ * dt, implicit-Euler form, advection left out):
+ *   b_c = M u_c + dt (M_s theta_c + C_c + B_c^T p),
+ * C_1 = M (f .* u_2), C_2 = -M (f .* u_1), C_3 = 0 (explicit Coriolis term
+ * -2 omega x u with f = 2 omega_3), theta_3 = 0 (u_3 = 0 on Gamma_s).
+ *   u_dev      3 x n, velocity at the previous step
+ *   p_dev      n, pressure at the previous step (may be NULL: p = 0)
+ *   theta_dev  2 x n, nodal wind tensions theta_1, theta_2 (may be NULL)
+ *   f_dev      n, Coriolis parameter (may be NULL: no Coriolis term)
+ *   b_dev      3 x n, output; entries on each component's Dirichlet set are 0 */
+hns_status hns_step_velocity_rhs(hns_operator *helm, const double *u_dev, const double *p_dev,
+                                 const double *theta_dev, const double *f_dev, double *b_dev,
+                                 void *stream);
+
+/* Pressure-increment right-hand side (eq. fofa_q_cor_h, implicit-Euler
+ * form): b = -(1/dt) sum_c B_c u~_c for the predicted velocity ut_dev (3 x n). */
+hns_status hns_step_pressure_rhs(hns_operator *helm, const double *ut_dev, double *b_dev,
+                                 void *stream);
+
+/* Pressure and velocity correction (eqs. fofa_pres_cor_h, fofa_velo_cor_h with
+ * the lumped mass in place of M; u = u~ - dt grad q, the sign that follows
+ * from the correction equations of Sec. 3):
+ *   p += q;  u_c = u~_c - dt (B_c q) / m_L, set to 0 on the Dirichlet set of c.
+ * ut_dev, u_dev: 3 x n (may alias); q_dev: n; p_dev: n, updated in place
+ * (may be NULL). */
+hns_status hns_step_correct(hns_operator *helm, const double *ut_dev, const double *q_dev,
+                            double *p_dev, double *u_dev, void *stream);
+
+/* y = F x for one auxiliary form F of a HNS_STEP_AUX operator:
+ * which = 0 M, 1..3 B_c, 4..6 B_c^T, 7 M_s (testing and diagnostics). */
+hns_status hns_apply_aux(hns_operator *helm, int which, const double *x_dev, double *y_dev,
+                         void *stream);
 
 /* Kernel timing for measurement.  When enabled, every CG iteration a solve
  * runs on this operator records HIP events around its three kernels on the

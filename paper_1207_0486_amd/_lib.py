@@ -55,6 +55,12 @@ _SIGNATURES = {
     "hns_operator_format": (C.c_uint32, [C.c_void_p]),
     "hns_set_param": (C.c_int, [C.c_void_p, C.c_char_p, C.c_double]),
     "hns_apply": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "hns_step_velocity_rhs": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                        C.c_void_p, C.c_void_p, C.c_void_p]),
+    "hns_step_pressure_rhs": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "hns_step_correct": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                   C.c_void_p]),
+    "hns_apply_aux": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
     "hns_profile_enable": (C.c_int, [C.c_void_p, C.c_int]),
     "hns_profile_read": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_double),
                                    C.POINTER(C.c_int64)]),

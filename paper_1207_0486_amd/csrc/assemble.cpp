@@ -292,6 +292,19 @@ hns_status assemble_surface_mass_host(const hns_mesh *mesh, HostCSR &Ms)
     return HNS_OK;
 }
 
+void transpose_values(const HostCSR &A, HostCSR &At)
+{
+    At.n = A.n;
+    At.rowptr = A.rowptr;
+    At.col = A.col;
+    At.val.assign(A.val.size(), 0.0);
+    parallel_for(A.n, [&](int64_t lo, int64_t hi) {
+        for (int64_t i = lo; i < hi; ++i)
+            for (int32_t k = A.rowptr[i]; k < A.rowptr[i + 1]; ++k)
+                At.val[k] = A.val[find_col(A, A.col[k], (int32_t)i)];
+    });
+}
+
 // ---------------------------------------------------------------------------
 // Device upload
 // ---------------------------------------------------------------------------

@@ -89,12 +89,16 @@ struct hns_operator {
     double lumped_sum = 0.0;
     int64_t bad_diag = -1;      // first non-positive diagonal entry, -1 if none
     // auxiliary forms for the step right-hand sides
-    hns::DevMatrix M, B[3], Ms;
+    hns::DevMatrix M, B[3], Bt[3], Ms;
     bool has_aux = false;
+    double *step_tmp = nullptr;   // 3 n doubles of scratch for the step kernels
     // tunables
     int check_every = 32;
     double inner_tol = 1e-5;
     int max_outer = 30;
+    int mixed_variant = 0;        // 0 FP32 + replacement, 1 restarted refinement,
+                                  // 2 FP32 storage with FP64 vectors
+    double replace_drop = 0.1;    // FP32 residual drop that triggers a replacement
     int use_graph = 0;
     // kernel timing (hns_profile_*)
     int profile = 0;
@@ -114,6 +118,8 @@ hns_status assemble_divergence_host(const hns_mesh *mesh, const HostCSR &pattern
                                     HostCSR &B);
 hns_status assemble_surface_mass_host(const hns_mesh *mesh, HostCSR &Ms);
 hns_status upload_matrix(const HostCSR &h, uint32_t fmt, bool keep32, DevMatrix &d);
+// same pattern, transposed values (the pattern must be structurally symmetric)
+void transpose_values(const HostCSR &A, HostCSR &At);
 uint32_t choose_format(const HostCSR &h);
 
 }  // namespace hns

@@ -39,9 +39,16 @@ int stream_grid(int64_t n);
 // grid for the SpMV of a matrix
 int spmv_grid(const DevMatrix &A);
 
+// Precision of one CG recurrence: matrix values / vectors / Jacobi diagonal
+enum class Prec {
+    F64,       // double / double / double
+    F32,       // float  / float  / float   (inner iteration of the refinement)
+    F32Store,  // float  / double / float   (FP32 storage, FP64 vectors)
+};
+
 struct IterArgs {
     const DevMatrix *A;
-    bool fp32;
+    Prec prec;
     int64_t n;
     void *x, *r, *p, *q;
     const void *dinv;
@@ -77,7 +84,7 @@ hns_status launch_residual(int64_t n, const double *b, const double *q, double *
                            double *partials, hipStream_t s);
 // (singular: r -= mean r) z = D^-1 r; p = z; rho[0] = r^T z; rr = r^T r; stop flag.
 // bb_from_rr: set bb = rr (inner solves of the refinement loop)
-hns_status launch_init_dir(int64_t n, bool fp32, void *r, void *p, const void *dinv,
+hns_status launch_init_dir(int64_t n, Prec prec, void *r, void *p, const void *dinv,
                            bool singular, bool bb_from_rr, Scalars *sc, double *partials,
                            hipStream_t s);
 // (singular: r -= mean r) rr = r^T r, FP64 residual of the refinement loop
@@ -89,6 +96,19 @@ hns_status launch_cast_scaled(int64_t n, const double *r64, float *r32, float *d
 // x += sqrt(rr) * (double)d32
 hns_status launch_correct(int64_t n, double *x, const float *d32, const Scalars *outer,
                           hipStream_t s);
+// r32 = (float) r64, x32 = 0
+hns_status launch_cast(int64_t n, const double *r64, float *r32, float *x32, hipStream_t s);
+// x64 += x32, x32 = 0
+hns_status launch_accumulate(int64_t n, double *x64, float *x32, hipStream_t s);
+// sc->tol2 = tol2, sc->bb = bb, sc->stop = 0 (threshold of the next residual replacement)
+hns_status launch_set_threshold(Scalars *sc, double tol2, double bb, hipStream_t s);
+// The recurrence continues from the FP64 true residual r64: r = (TX) r64
+// (r is ignored when the vectors are FP64 and r64 is the working residual),
+// z = D^-1 r, rho' = r^T z, beta = rho' / rho[parity], p = z + beta p,
+// rho[parity ^ 1] = rho'.  parity is that of the last executed iteration.
+hns_status launch_replace_residual(int64_t n, Prec prec, const double *r64, void *r, void *p,
+                                   const void *dinv, Scalars *sc, double *partials, int parity,
+                                   hipStream_t s);
 // wx = sum lumped_i x_i ; then x -= wx / lumped_sum
 hns_status launch_normalise(int64_t n, double *x, const double *lumped, double lumped_sum,
                             Scalars *sc, double *partials, hipStream_t s);

@@ -16,9 +16,15 @@
 // (64 lanes), the 4 wavefronts of a block through LDS, then the block
 // partials in block order.  Dots accumulate in FP64 also when vectors are FP32.
 //
+// Precisions (template parameters): TV = matrix values, TX = vectors and
+// arithmetic, TD = Jacobi diagonal.  FP64 is <double,double,double>, the FP32
+// inner iteration <float,float,float>, and the FP32-storage variant
+// <float,double,float> (FP32 matrix and diagonal, FP64 vectors).
+//
 // One-off reductions outside the iteration (right-hand-side statistics,
 // residual norms, normalisation) use a last-block-done pattern instead.
 #include <cmath>
+#include <type_traits>
 
 #include "kernels.h"
 
@@ -55,9 +61,9 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double *lds)
     __syncthreads();
 }
 
-// Grid-wide sum of NV values.  Returns true in all threads of the last block
-// to arrive; there thread 0 holds the totals in v.  partials holds NV x grid
-// doubles; the counter is reset for the next launch.
+// Grid-wide sum of NV values for one-off reductions.  Returns true in all
+// threads of the last block to arrive; there thread 0 holds the totals in v.
+// partials holds NV x grid doubles; the counter is reset for the next launch.
 template <int NV>
 __device__ bool grid_sum(double (&v)[NV], double *partials, uint32_t *counter)
 {
@@ -89,19 +95,6 @@ __device__ bool grid_sum(double (&v)[NV], double *partials, uint32_t *counter)
         *counter = 0u;
     }
     return true;
-}
-
-// Workgroups are dealt to the 8 XCDs round-robin; renumber them so that each
-// XCD works on one contiguous eighth of the rows (neighbour gathers of the
-// SpMV then hit that XCD's own L2).
-__device__ __forceinline__ int xcd_block(int b, int G)
-{
-    return (G >= 8 && (G & 7) == 0) ? (b & 7) * (G >> 3) + (b >> 3) : b;
-}
-
-__device__ __forceinline__ bool is_dirichlet(const uint8_t *bc, int bit, int64_t i)
-{
-    return bc != nullptr && ((bc[i] >> bit) & 1u);
 }
 
 // Sums NV per-thread values over the block and stores them as the block's
@@ -142,14 +135,35 @@ __device__ __forceinline__ void load_reduced(const double *__restrict__ P, int G
     for (int k = 0; k < NV; ++k) out[k] = bcast[k];
 }
 
+// Workgroups are dealt to the 8 XCDs round-robin; renumber them so that each
+// XCD works on one contiguous eighth of the rows (neighbour gathers of the
+// SpMV then hit that XCD's own L2).
+__device__ __forceinline__ int xcd_block(int b, int G)
+{
+    return (G >= 8 && (G & 7) == 0) ? (b & 7) * (G >> 3) + (b >> 3) : b;
+}
+
+__device__ __forceinline__ bool is_dirichlet(const uint8_t *bc, int bit, int64_t i)
+{
+    return bc != nullptr && ((bc[i] >> bit) & 1u);
+}
+
+#define GRID_STRIDE(i, n)                                                   \
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < (n); \
+         i += (int64_t)gridDim.x * kBlock)
+
+// ---------------------------------------------------------------------------
+// SpMV
+// ---------------------------------------------------------------------------
+
 // Sliced ELL, slice height 64 = one wavefront, one row per lane.  Each block
 // owns a contiguous range of slices; its 4 wavefronts take every 4th slice.
-template <typename T, bool DOT>
+template <typename TV, typename TX, bool DOT>
 __global__ __launch_bounds__(kBlock) void k_spmv_sell(int64_t n, int64_t nslices,
                                                       const int32_t *__restrict__ sptr,
                                                       const int32_t *__restrict__ col,
-                                                      const T *__restrict__ val,
-                                                      const T *__restrict__ x, T *__restrict__ y,
+                                                      const TV *__restrict__ val,
+                                                      const TX *__restrict__ x, TX *__restrict__ y,
                                                       const uint8_t *__restrict__ bc, int bit,
                                                       const Scalars *__restrict__ sc,
                                                       double *__restrict__ part)
@@ -168,10 +182,10 @@ __global__ __launch_bounds__(kBlock) void k_spmv_sell(int64_t n, int64_t nslices
         const int32_t beg = sptr[s];
         const int32_t w = (sptr[s + 1] - beg) >> 6;
         const int32_t *c = col + beg + lane;
-        const T *v = val + beg + lane;
-        T sum = 0;
+        const TV *v = val + beg + lane;
+        TX sum = 0;
 #pragma unroll 4
-        for (int j = 0; j < w; ++j) sum += v[j * 64] * x[c[j * 64]];
+        for (int j = 0; j < w; ++j) sum += (TX)v[j * 64] * x[c[j * 64]];
         const int64_t row = s * 64 + lane;
         if (row < n) {
             if (is_dirichlet(bc, bit, row)) sum = 0;
@@ -187,11 +201,11 @@ __global__ __launch_bounds__(kBlock) void k_spmv_sell(int64_t n, int64_t nslices
 
 // CSR with 16 lanes per row (4 rows per wavefront); rows of a block are a
 // contiguous range.
-template <typename T, bool DOT>
+template <typename TV, typename TX, bool DOT>
 __global__ __launch_bounds__(kBlock) void k_spmv_csr(int64_t n, const int32_t *__restrict__ rowptr,
                                                      const int32_t *__restrict__ col,
-                                                     const T *__restrict__ val,
-                                                     const T *__restrict__ x, T *__restrict__ y,
+                                                     const TV *__restrict__ val,
+                                                     const TX *__restrict__ x, TX *__restrict__ y,
                                                      const uint8_t *__restrict__ bc, int bit,
                                                      const Scalars *__restrict__ sc,
                                                      double *__restrict__ part)
@@ -208,10 +222,10 @@ __global__ __launch_bounds__(kBlock) void k_spmv_csr(int64_t n, const int32_t *_
     double acc = 0.0;
     for (int64_t base = r0; base < r1; base += kBlock / 16) {
         const int64_t row = base + grp;
-        T sum = 0;
+        TX sum = 0;
         if (row < r1) {
             const int32_t e = rowptr[row + 1];
-            for (int32_t k = rowptr[row] + gl; k < e; k += 16) sum += val[k] * x[col[k]];
+            for (int32_t k = rowptr[row] + gl; k < e; k += 16) sum += (TX)val[k] * x[col[k]];
         }
         sum += __shfl_xor(sum, 8, 16);
         sum += __shfl_xor(sum, 4, 16);
@@ -229,12 +243,16 @@ __global__ __launch_bounds__(kBlock) void k_spmv_csr(int64_t n, const int32_t *_
     }
 }
 
+// ---------------------------------------------------------------------------
+// CG vector updates
+// ---------------------------------------------------------------------------
+
 // x += alpha p; r -= alpha q; partials of r^T D^-1 r and r^T r.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_update(int64_t n, T *__restrict__ x, T *__restrict__ r,
-                                                   const T *__restrict__ p,
-                                                   const T *__restrict__ q,
-                                                   const T *__restrict__ dinv,
+template <typename TX, typename TD>
+__global__ __launch_bounds__(kBlock) void k_update(int64_t n, TX *__restrict__ x,
+                                                   TX *__restrict__ r, const TX *__restrict__ p,
+                                                   const TX *__restrict__ q,
+                                                   const TD *__restrict__ dinv,
                                                    Scalars *__restrict__ sc,
                                                    const double *__restrict__ part_in, int G_in,
                                                    double *__restrict__ part_out, int parity)
@@ -255,14 +273,14 @@ __global__ __launch_bounds__(kBlock) void k_update(int64_t n, T *__restrict__ x,
         sc->gamma = gamma;
         sc->alpha = alpha_d;
     }
-    const T alpha = (T)alpha_d;
+    const TX alpha = (TX)alpha_d;
     double rz = 0.0, rr = 0.0;
-    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * kBlock) {
+    GRID_STRIDE(i, n)
+    {
         x[i] = x[i] + alpha * p[i];
-        const T ri = r[i] - alpha * q[i];
+        const TX ri = r[i] - alpha * q[i];
         r[i] = ri;
-        const T zi = dinv[i] * ri;
+        const TX zi = (TX)dinv[i] * ri;
         rz += (double)ri * (double)zi;
         rr += (double)ri * (double)ri;
     }
@@ -271,14 +289,15 @@ __global__ __launch_bounds__(kBlock) void k_update(int64_t n, T *__restrict__ x,
 }
 
 // rho' = r^T z, rr = r^T r from the update partials; beta = rho' / rho;
-// p = D^-1 r + beta p unless converged.
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_pupdate(int64_t n, T *__restrict__ p,
-                                                    const T *__restrict__ r,
-                                                    const T *__restrict__ dinv,
+// p = D^-1 r + beta p unless converged.  `count` is added to the iteration
+// counter (0 when used after a residual replacement).
+template <typename TX, typename TD>
+__global__ __launch_bounds__(kBlock) void k_pupdate(int64_t n, TX *__restrict__ p,
+                                                    const TX *__restrict__ r,
+                                                    const TD *__restrict__ dinv,
                                                     Scalars *__restrict__ sc,
                                                     const double *__restrict__ part_in, int G_in,
-                                                    int parity)
+                                                    int parity, int count)
 {
     if (sc->stop) return;
     double v[2];
@@ -291,18 +310,79 @@ __global__ __launch_bounds__(kBlock) void k_pupdate(int64_t n, T *__restrict__ p
         sc->rho[parity ^ 1] = rho_new;
         sc->rr = rr;
         sc->beta = beta_d;
-        sc->iter += 1;
+        sc->iter += count;
         if (bad)
             sc->stop = 2;
         else if (conv)
             sc->stop = 1;
     }
     if (bad || conv) return;
-    const T beta = (T)beta_d;
-    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * kBlock)
-        p[i] = dinv[i] * r[i] + beta * p[i];
+    const TX beta = (TX)beta_d;
+    GRID_STRIDE(i, n) p[i] = (TX)dinv[i] * r[i] + beta * p[i];
 }
+
+// (singular: r -= mean r) z = D^-1 r; p = z; rho[0] = r^T z; rr = r^T r.
+template <typename TX, typename TD>
+__global__ __launch_bounds__(kBlock) void k_init_dir(int64_t n, TX *__restrict__ r,
+                                                     TX *__restrict__ p,
+                                                     const TD *__restrict__ dinv, int singular,
+                                                     int bb_from_rr, Scalars *__restrict__ sc,
+                                                     double *__restrict__ partials)
+{
+    const TX mean = singular ? (TX)(sc->sum_r / (double)n) : (TX)0;
+    double rz = 0.0, rr = 0.0;
+    GRID_STRIDE(i, n)
+    {
+        TX ri = r[i];
+        if (singular) {
+            ri -= mean;
+            r[i] = ri;
+        }
+        const TX zi = (TX)dinv[i] * ri;
+        p[i] = zi;
+        rz += (double)ri * (double)zi;
+        rr += (double)ri * (double)ri;
+    }
+    double v[2] = {rz, rr};
+    if (grid_sum<2>(v, partials, &sc->counter[2]) && threadIdx.x == 0) {
+        sc->rho[0] = v[0];
+        sc->rr = v[1];
+        sc->beta = 0.0;
+        if (bb_from_rr) sc->bb = v[1];
+        if (!(sc->bb > 0.0))
+            sc->stop = 3;
+        else if (!isfinite(v[0]) || !isfinite(v[1]))
+            sc->stop = 2;
+        else
+            sc->stop = (v[1] <= sc->tol2 * sc->bb) ? 1 : 0;
+    }
+}
+
+// Residual replacement: the working residual becomes the FP64 true residual
+// (converted to TX when dst is given, else src is the working residual), with
+// per-block partials of r^T D^-1 r and r^T r for the k_pupdate that follows.
+template <typename TX, typename TD>
+__global__ __launch_bounds__(kBlock) void k_replace_rz(int64_t n, const double *__restrict__ src,
+                                                       TX *__restrict__ dst,
+                                                       const TD *__restrict__ dinv,
+                                                       double *__restrict__ part_out)
+{
+    double rz = 0.0, rr = 0.0;
+    GRID_STRIDE(i, n)
+    {
+        const TX ri = (TX)src[i];
+        if (dst) dst[i] = ri;
+        const TX zi = (TX)dinv[i] * ri;
+        rz += (double)ri * (double)zi;
+        rr += (double)ri * (double)ri;
+    }
+    double v[2] = {rz, rr};
+    store_block_partials<2>(v, part_out);
+}
+
+// ---------------------------------------------------------------------------
+// One-off kernels
+// ---------------------------------------------------------------------------
 
 __global__ __launch_bounds__(kBlock) void k_bstats(int64_t n, const double *__restrict__ b,
                                                    const uint8_t *__restrict__ bc, int bit,
@@ -310,8 +390,8 @@ __global__ __launch_bounds__(kBlock) void k_bstats(int64_t n, const double *__re
                                                    double *__restrict__ partials)
 {
     double s = 0.0, s2 = 0.0, bad = 0.0;
-    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * kBlock) {
+    GRID_STRIDE(i, n)
+    {
         double bi = is_dirichlet(bc, bit, i) ? 0.0 : b[i];
         if (!isfinite(bi)) {
             bad += 1.0;
@@ -332,9 +412,8 @@ __global__ __launch_bounds__(kBlock) void k_prepare_x(int64_t n, double *__restr
                                                       const uint8_t *__restrict__ bc, int bit,
                                                       int zero_all)
 {
-    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * kBlock)
-        if (zero_all || is_dirichlet(bc, bit, i)) x[i] = 0.0;
+    GRID_STRIDE(i, n)
+    if (zero_all || is_dirichlet(bc, bit, i)) x[i] = 0.0;
 }
 
 __global__ __launch_bounds__(kBlock) void k_residual(int64_t n, const double *__restrict__ b,
@@ -346,8 +425,8 @@ __global__ __launch_bounds__(kBlock) void k_residual(int64_t n, const double *__
 {
     const double shift = singular ? sc->sumb / (double)n : 0.0;
     double sr = 0.0, sbb = 0.0;
-    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * kBlock) {
+    GRID_STRIDE(i, n)
+    {
         double bi = b[i] - shift;
         double ri = bi - q[i];
         if (is_dirichlet(bc, bit, i)) {
@@ -365,50 +444,14 @@ __global__ __launch_bounds__(kBlock) void k_residual(int64_t n, const double *__
     }
 }
 
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_init_dir(int64_t n, T *__restrict__ r,
-                                                     T *__restrict__ p,
-                                                     const T *__restrict__ dinv, int singular,
-                                                     int bb_from_rr, Scalars *__restrict__ sc,
-                                                     double *__restrict__ partials)
-{
-    const T mean = singular ? (T)(sc->sum_r / (double)n) : (T)0;
-    double rz = 0.0, rr = 0.0;
-    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * kBlock) {
-        T ri = r[i];
-        if (singular) {
-            ri -= mean;
-            r[i] = ri;
-        }
-        const T zi = dinv[i] * ri;
-        p[i] = zi;
-        rz += (double)ri * (double)zi;
-        rr += (double)ri * (double)ri;
-    }
-    double v[2] = {rz, rr};
-    if (grid_sum<2>(v, partials, &sc->counter[2]) && threadIdx.x == 0) {
-        sc->rho[0] = v[0];
-        sc->rr = v[1];
-        sc->beta = 0.0;
-        if (bb_from_rr) sc->bb = v[1];
-        if (!(sc->bb > 0.0))
-            sc->stop = 3;
-        else if (!isfinite(v[0]) || !isfinite(v[1]))
-            sc->stop = 2;
-        else
-            sc->stop = (v[1] <= sc->tol2 * sc->bb) ? 1 : 0;
-    }
-}
-
 __global__ __launch_bounds__(kBlock) void k_project_norm(int64_t n, double *__restrict__ r,
                                                          int singular, Scalars *__restrict__ sc,
                                                          double *__restrict__ partials)
 {
     const double mean = singular ? sc->sum_r / (double)n : 0.0;
     double rr = 0.0;
-    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * kBlock) {
+    GRID_STRIDE(i, n)
+    {
         double ri = r[i];
         if (singular) {
             ri -= mean;
@@ -426,8 +469,8 @@ __global__ __launch_bounds__(kBlock) void k_cast_scaled(int64_t n, const double 
                                                         const Scalars *__restrict__ outer)
 {
     const double inv = 1.0 / sqrt(outer->rr);
-    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * kBlock) {
+    GRID_STRIDE(i, n)
+    {
         r32[i] = (float)(r64[i] * inv);
         d32[i] = 0.0f;
     }
@@ -438,9 +481,37 @@ __global__ __launch_bounds__(kBlock) void k_correct(int64_t n, double *__restric
                                                     const Scalars *__restrict__ outer)
 {
     const double s = sqrt(outer->rr);
-    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * kBlock)
-        x[i] += s * (double)d32[i];
+    GRID_STRIDE(i, n) x[i] += s * (double)d32[i];
+}
+
+__global__ __launch_bounds__(kBlock) void k_cast(int64_t n, const double *__restrict__ r64,
+                                                 float *__restrict__ r32, float *__restrict__ x32)
+{
+    GRID_STRIDE(i, n)
+    {
+        r32[i] = (float)r64[i];
+        x32[i] = 0.0f;
+    }
+}
+
+// x64 += x32; x32 = 0 (the FP64 solution collects the FP32 corrections)
+__global__ __launch_bounds__(kBlock) void k_accumulate(int64_t n, double *__restrict__ x64,
+                                                       float *__restrict__ x32)
+{
+    GRID_STRIDE(i, n)
+    {
+        x64[i] += (double)x32[i];
+        x32[i] = 0.0f;
+    }
+}
+
+__global__ void k_set_threshold(Scalars *sc, double tol2, double bb)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        sc->tol2 = tol2;
+        sc->bb = bb;
+        sc->stop = 0;
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_wdot(int64_t n, const double *__restrict__ w,
@@ -449,9 +520,7 @@ __global__ __launch_bounds__(kBlock) void k_wdot(int64_t n, const double *__rest
                                                  double *__restrict__ partials)
 {
     double s = 0.0;
-    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * kBlock)
-        s += w[i] * x[i];
+    GRID_STRIDE(i, n) s += w[i] * x[i];
     double v[1] = {s};
     if (grid_sum<1>(v, partials, &sc->counter[2]) && threadIdx.x == 0) sc->wx = v[0];
 }
@@ -460,9 +529,7 @@ __global__ __launch_bounds__(kBlock) void k_shift(int64_t n, double *__restrict_
                                                   const Scalars *__restrict__ sc, double wsum)
 {
     const double c = sc->wx / wsum;
-    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * kBlock)
-        x[i] -= c;
+    GRID_STRIDE(i, n) x[i] -= c;
 }
 
 hns_status check_launch(const char *what)
@@ -473,6 +540,43 @@ hns_status check_launch(const char *what)
         return HNS_ERR_HIP;
     }
     return HNS_OK;
+}
+
+template <typename TV, typename TX, bool DOT>
+void spmv_dispatch(const DevMatrix &A, const void *p, void *q, const uint8_t *bc, int bit,
+                   const Scalars *sc, double *part, hipStream_t s)
+{
+    const int G = spmv_grid(A);
+    const bool f32 = std::is_same<TV, float>::value;
+    const TV *vs = f32 ? (const TV *)(const void *)A.sval32 : (const TV *)(const void *)A.sval;
+    const TV *vc = f32 ? (const TV *)(const void *)A.val32 : (const TV *)(const void *)A.val;
+    if (A.fmt == HNS_FMT_SELL)
+        k_spmv_sell<TV, TX, DOT><<<G, kBlock, 0, s>>>(A.n, A.nslices, A.slice_ptr, A.scol, vs,
+                                                      (const TX *)p, (TX *)q, bc, bit, sc, part);
+    else
+        k_spmv_csr<TV, TX, DOT><<<G, kBlock, 0, s>>>(A.n, A.rowptr, A.col, vc, (const TX *)p,
+                                                     (TX *)q, bc, bit, sc, part);
+}
+
+template <typename TV, typename TX, typename TD>
+hns_status iteration_impl(const IterArgs &a, int parity, hipStream_t s, hipEvent_t *ev)
+{
+    const uint8_t *bc = a.bit < 0 ? nullptr : a.bc;
+    const int Gs = spmv_grid(*a.A);
+    const int Gu = stream_grid(a.n);
+    double *P1 = a.partials + kPartSpmv;
+    double *P2 = a.partials + kPartUpdate;
+    if (ev) HNS_TRY_HIP(hipEventRecord(ev[0], s));
+    spmv_dispatch<TV, TX, true>(*a.A, a.p, a.q, bc, a.bit, a.sc, P1, s);
+    if (ev) HNS_TRY_HIP(hipEventRecord(ev[1], s));
+    k_update<TX, TD><<<Gu, kBlock, 0, s>>>(a.n, (TX *)a.x, (TX *)a.r, (const TX *)a.p,
+                                           (const TX *)a.q, (const TD *)a.dinv, a.sc, P1, Gs, P2,
+                                           parity);
+    if (ev) HNS_TRY_HIP(hipEventRecord(ev[2], s));
+    k_pupdate<TX, TD><<<Gu, kBlock, 0, s>>>(a.n, (TX *)a.p, (const TX *)a.r, (const TD *)a.dinv,
+                                            a.sc, P2, Gu, parity, 1);
+    if (ev) HNS_TRY_HIP(hipEventRecord(ev[3], s));
+    return check_launch("cg iteration");
 }
 
 }  // namespace
@@ -495,62 +599,26 @@ int spmv_grid(const DevMatrix &A)
     return (int)g;
 }
 
-template <typename T, bool DOT>
-static void spmv_dispatch(const DevMatrix &A, const T *vals_csr, const T *vals_sell,
-                          const void *p, void *q, const uint8_t *bc, int bit,
-                          const Scalars *sc, double *part, hipStream_t s)
-{
-    const int G = spmv_grid(A);
-    if (A.fmt == HNS_FMT_SELL)
-        k_spmv_sell<T, DOT><<<G, kBlock, 0, s>>>(A.n, A.nslices, A.slice_ptr, A.scol, vals_sell,
-                                                 (const T *)p, (T *)q, bc, bit, sc, part);
-    else
-        k_spmv_csr<T, DOT><<<G, kBlock, 0, s>>>(A.n, A.rowptr, A.col, vals_csr, (const T *)p,
-                                                (T *)q, bc, bit, sc, part);
-}
-
 hns_status launch_spmv_plain(const DevMatrix &A, bool fp32, const void *p, void *q,
                              const uint8_t *bc, int bit, hipStream_t s)
 {
     if (bit < 0) bc = nullptr;
     if (fp32)
-        spmv_dispatch<float, false>(A, A.val32, A.sval32, p, q, bc, bit, nullptr, nullptr, s);
+        spmv_dispatch<float, float, false>(A, p, q, bc, bit, nullptr, nullptr, s);
     else
-        spmv_dispatch<double, false>(A, A.val, A.sval, p, q, bc, bit, nullptr, nullptr, s);
+        spmv_dispatch<double, double, false>(A, p, q, bc, bit, nullptr, nullptr, s);
     return check_launch("spmv");
 }
 
 hns_status launch_iteration(const IterArgs &a, int parity, hipStream_t s, hipEvent_t *ev)
 {
-    const uint8_t *bc = a.bit < 0 ? nullptr : a.bc;
-    const int Gs = spmv_grid(*a.A);
-    const int Gu = stream_grid(a.n);
-    double *P1 = a.partials + kPartSpmv;
-    double *P2 = a.partials + kPartUpdate;
-    if (ev) HNS_TRY_HIP(hipEventRecord(ev[0], s));
-    if (a.fp32)
-        spmv_dispatch<float, true>(*a.A, a.A->val32, a.A->sval32, a.p, a.q, bc, a.bit, a.sc, P1,
-                                   s);
-    else
-        spmv_dispatch<double, true>(*a.A, a.A->val, a.A->sval, a.p, a.q, bc, a.bit, a.sc, P1, s);
-    if (ev) HNS_TRY_HIP(hipEventRecord(ev[1], s));
-    if (a.fp32)
-        k_update<float><<<Gu, kBlock, 0, s>>>(a.n, (float *)a.x, (float *)a.r, (const float *)a.p,
-                                              (const float *)a.q, (const float *)a.dinv, a.sc, P1,
-                                              Gs, P2, parity);
-    else
-        k_update<double><<<Gu, kBlock, 0, s>>>(a.n, (double *)a.x, (double *)a.r,
-                                               (const double *)a.p, (const double *)a.q,
-                                               (const double *)a.dinv, a.sc, P1, Gs, P2, parity);
-    if (ev) HNS_TRY_HIP(hipEventRecord(ev[2], s));
-    if (a.fp32)
-        k_pupdate<float><<<Gu, kBlock, 0, s>>>(a.n, (float *)a.p, (const float *)a.r,
-                                               (const float *)a.dinv, a.sc, P2, Gu, parity);
-    else
-        k_pupdate<double><<<Gu, kBlock, 0, s>>>(a.n, (double *)a.p, (const double *)a.r,
-                                                (const double *)a.dinv, a.sc, P2, Gu, parity);
-    if (ev) HNS_TRY_HIP(hipEventRecord(ev[3], s));
-    return check_launch("cg iteration");
+    switch (a.prec) {
+    case Prec::F64: return iteration_impl<double, double, double>(a, parity, s, ev);
+    case Prec::F32: return iteration_impl<float, float, float>(a, parity, s, ev);
+    case Prec::F32Store: return iteration_impl<float, double, float>(a, parity, s, ev);
+    }
+    set_error("unknown precision");
+    return HNS_ERR_INVALID;
 }
 
 hns_status launch_bstats(int64_t n, const double *b, const uint8_t *bc, int bit, Scalars *sc,
@@ -579,20 +647,57 @@ hns_status launch_residual(int64_t n, const double *b, const double *q, double *
     return check_launch("residual");
 }
 
-hns_status launch_init_dir(int64_t n, bool fp32, void *r, void *p, const void *dinv,
+hns_status launch_init_dir(int64_t n, Prec prec, void *r, void *p, const void *dinv,
                            bool singular, bool bb_from_rr, Scalars *sc, double *partials,
                            hipStream_t s)
 {
     const int G = stream_grid(n);
-    if (fp32)
-        k_init_dir<float><<<G, kBlock, 0, s>>>(n, (float *)r, (float *)p, (const float *)dinv,
-                                               singular ? 1 : 0, bb_from_rr ? 1 : 0, sc,
-                                               partials + kPartMisc);
-    else
-        k_init_dir<double><<<G, kBlock, 0, s>>>(n, (double *)r, (double *)p,
-                                                (const double *)dinv, singular ? 1 : 0,
-                                                bb_from_rr ? 1 : 0, sc, partials + kPartMisc);
+    const int sg = singular ? 1 : 0, bf = bb_from_rr ? 1 : 0;
+    double *P = partials + kPartMisc;
+    switch (prec) {
+    case Prec::F64:
+        k_init_dir<double, double><<<G, kBlock, 0, s>>>(n, (double *)r, (double *)p,
+                                                        (const double *)dinv, sg, bf, sc, P);
+        break;
+    case Prec::F32:
+        k_init_dir<float, float><<<G, kBlock, 0, s>>>(n, (float *)r, (float *)p,
+                                                      (const float *)dinv, sg, bf, sc, P);
+        break;
+    case Prec::F32Store:
+        k_init_dir<double, float><<<G, kBlock, 0, s>>>(n, (double *)r, (double *)p,
+                                                       (const float *)dinv, sg, bf, sc, P);
+        break;
+    }
     return check_launch("init_dir");
+}
+
+hns_status launch_replace_residual(int64_t n, Prec prec, const double *r64, void *r, void *p,
+                                   const void *dinv, Scalars *sc, double *partials, int parity,
+                                   hipStream_t s)
+{
+    const int Gu = stream_grid(n);
+    double *P2 = partials + kPartUpdate;
+    if (prec == Prec::F32) {
+        k_replace_rz<float, float><<<Gu, kBlock, 0, s>>>(n, r64, (float *)r, (const float *)dinv,
+                                                         P2);
+        HNS_TRY(check_launch("replace_rz"));
+        k_pupdate<float, float><<<Gu, kBlock, 0, s>>>(n, (float *)p, (const float *)r,
+                                                      (const float *)dinv, sc, P2, Gu, parity, 0);
+    } else if (prec == Prec::F32Store) {
+        k_replace_rz<double, float><<<Gu, kBlock, 0, s>>>(n, r64, nullptr, (const float *)dinv,
+                                                          P2);
+        HNS_TRY(check_launch("replace_rz"));
+        k_pupdate<double, float><<<Gu, kBlock, 0, s>>>(n, (double *)p, r64, (const float *)dinv,
+                                                       sc, P2, Gu, parity, 0);
+    } else {
+        k_replace_rz<double, double><<<Gu, kBlock, 0, s>>>(n, r64, nullptr,
+                                                           (const double *)dinv, P2);
+        HNS_TRY(check_launch("replace_rz"));
+        k_pupdate<double, double><<<Gu, kBlock, 0, s>>>(n, (double *)p, r64,
+                                                        (const double *)dinv, sc, P2, Gu, parity,
+                                                        0);
+    }
+    return check_launch("pupdate (replacement)");
 }
 
 hns_status launch_project_norm(int64_t n, double *r, bool singular, Scalars *sc,
@@ -615,6 +720,24 @@ hns_status launch_correct(int64_t n, double *x, const float *d32, const Scalars 
 {
     k_correct<<<stream_grid(n), kBlock, 0, s>>>(n, x, d32, outer);
     return check_launch("correct");
+}
+
+hns_status launch_cast(int64_t n, const double *r64, float *r32, float *x32, hipStream_t s)
+{
+    k_cast<<<stream_grid(n), kBlock, 0, s>>>(n, r64, r32, x32);
+    return check_launch("cast");
+}
+
+hns_status launch_accumulate(int64_t n, double *x64, float *x32, hipStream_t s)
+{
+    k_accumulate<<<stream_grid(n), kBlock, 0, s>>>(n, x64, x32);
+    return check_launch("accumulate");
+}
+
+hns_status launch_set_threshold(Scalars *sc, double tol2, double bb, hipStream_t s)
+{
+    k_set_threshold<<<1, 64, 0, s>>>(sc, tol2, bb);
+    return check_launch("set_threshold");
 }
 
 hns_status launch_normalise(int64_t n, double *x, const double *lumped, double lumped_sum,

@@ -144,7 +144,7 @@ static void reset_scalars(Scalars &h, double tol)
 }
 
 // ---------------------------------------------------------------------------
-// FP64 Jacobi-PCG
+// Solve drivers
 // ---------------------------------------------------------------------------
 struct SolveCtx {
     hns_operator *op;
@@ -158,35 +158,20 @@ struct SolveCtx {
     Workspace *w;
 };
 
-// r = b - A x (projected in the pure-Neumann case), then a fresh search
-// direction: z = D^-1 r, p = z, rho = r^T z.  Sets stop = 1 when already
-// converged, 3 when b = 0.
-static hns_status restart_fp64(const SolveCtx &c)
-{
-    hns_operator *op = c.op;
-    Workspace *w = c.w;
-    HNS_TRY(launch_spmv_plain(op->A, false, c.x, w->q, op->bc, c.bit, c.s));
-    HNS_TRY(launch_residual(op->n, c.b, w->q, w->r, op->bc, c.bit, c.singular, w->sc,
-                            w->partials, c.s));
-    HNS_TRY(launch_init_dir(op->n, false, w->r, w->p, op->dinv, c.singular, false, w->sc,
-                            w->partials, c.s));
-    return HNS_OK;
-}
-
-// Enqueue `count` CG iterations; `parity` is the iteration index since the
-// last restart (selects the rho slot) and is advanced.
-static hns_status enqueue_iterations(hns_operator *op, Workspace *w, const DevMatrix &A,
-                                     bool fp32, int bit, void *x, void *r, void *p, void *q,
-                                     const void *dinv, Scalars *sc, int count, int *parity,
-                                     hipStream_t s)
+// Enqueue `count` CG iterations of one recurrence.  parity0 is the number of
+// iterations executed since its last (re)start: it selects the rho slot of
+// each iteration.  Iterations enqueued after the stop flag was raised are
+// no-ops on the device, so the caller re-derives parity from the device's
+// iteration counter after each chunk.
+static hns_status enqueue_iterations(hns_operator *op, Workspace *w, Prec prec, int bit, void *x,
+                                     void *r, void *p, void *q, const void *dinv, Scalars *sc,
+                                     int count, int parity0, hipStream_t s)
 {
     const bool prof = op->profile != 0;
     if (prof) HNS_TRY(w->ensure_events(4 * (size_t)count));
-    IterArgs a{&A, fp32, op->n, x, r, p, q, dinv, op->bc, bit, sc, w->partials};
-    for (int it = 0; it < count; ++it) {
-        HNS_TRY(launch_iteration(a, *parity & 1, s, prof ? &w->ev[4 * it] : nullptr));
-        *parity += 1;
-    }
+    IterArgs a{&op->A, prec, op->n, x, r, p, q, dinv, op->bc, bit, sc, w->partials};
+    for (int it = 0; it < count; ++it)
+        HNS_TRY(launch_iteration(a, (parity0 + it) & 1, s, prof ? &w->ev[4 * it] : nullptr));
     return HNS_OK;
 }
 
@@ -206,11 +191,33 @@ static hns_status account_iterations(hns_operator *op, Workspace *w, bool fp32, 
     return HNS_OK;
 }
 
-static hns_status begin_solve(const SolveCtx &c, hns_solve_info *info, bool *done)
+// Run chunks of one recurrence (scalar block `which`) until its stop flag is
+// raised or the iteration budget is spent.  *since_start counts the
+// iterations executed since the recurrence's last (re)start.
+static hns_status run_chunks(const SolveCtx &c, int which, Prec prec, void *x, void *r, void *p,
+                             void *q, const void *dinv, int *since_start)
 {
     hns_operator *op = c.op;
     Workspace *w = c.w;
-    *done = false;
+    Scalars &h = w->host[which];
+    while (h.stop == 0) {
+        const int left = c.max_iter - h.iter;
+        if (left <= 0) break;
+        const int chunk = left < op->check_every ? left : op->check_every;
+        const int before = h.iter;
+        HNS_TRY(enqueue_iterations(op, w, prec, c.bit, x, r, p, q, dinv, w->sc + which, chunk,
+                                   *since_start, c.s));
+        HNS_TRY(pull_scalars(w, which, c.s));
+        *since_start += h.iter - before;
+        HNS_TRY(account_iterations(op, w, prec == Prec::F32, h.iter - before));
+    }
+    return HNS_OK;
+}
+
+static hns_status begin_solve(const SolveCtx &c, hns_solve_info *info)
+{
+    hns_operator *op = c.op;
+    Workspace *w = c.w;
     reset_scalars(w->host[0], c.tol);
     HNS_TRY(push_scalars(w, 0, c.s));
     HNS_TRY(launch_bstats(op->n, c.b, op->bc, c.bit, w->sc, w->partials, c.s));
@@ -218,87 +225,14 @@ static hns_status begin_solve(const SolveCtx &c, hns_solve_info *info, bool *don
     HNS_TRY(pull_scalars(w, 0, c.s));
     if (w->host[0].nonfinite > 0) {
         set_error("right-hand side has %.0f non-finite entries", w->host[0].nonfinite);
-        info->status = HNS_ERR_INVALID;
-        *done = true;
         return HNS_ERR_INVALID;
     }
     info->removed_mean = c.singular ? w->host[0].sumb / (double)op->n : 0.0;
     return HNS_OK;
 }
 
-static hns_status solve_fp64(const SolveCtx &c, hns_solve_info *info)
-{
-    hns_operator *op = c.op;
-    Workspace *w = c.w;
-    bool done;
-    HNS_TRY(begin_solve(c, info, &done));
-    HNS_TRY(restart_fp64(c));
-    HNS_TRY(pull_scalars(w, 0, c.s));
-    Scalars &h = w->host[0];
-    if (h.stop == 3) {  // b = 0
-        HNS_TRY(launch_prepare_x(op->n, c.x, nullptr, -1, true, c.s));
-        HNS_TRY_HIP(hipStreamSynchronize(c.s));
-        info->status = HNS_OK;
-        return HNS_OK;
-    }
-    hns_status status = HNS_NOT_CONVERGED;
-    int parity = 0;
-    if (h.stop == 1) {
-        status = HNS_OK;
-    } else if (h.stop == 2) {
-        status = HNS_ERR_BREAKDOWN;
-    } else {
-        for (;;) {
-            const int left = c.max_iter - h.iter;
-            if (left <= 0) break;
-            const int chunk = left < op->check_every ? left : op->check_every;
-            const int before = h.iter;
-            HNS_TRY(enqueue_iterations(op, w, op->A, false, c.bit, c.x, w->r, w->p, w->q,
-                                       op->dinv, w->sc, chunk, &parity, c.s));
-            HNS_TRY(pull_scalars(w, 0, c.s));
-            HNS_TRY(account_iterations(op, w, false, h.iter - before));
-            if (h.stop == 2) {
-                status = HNS_ERR_BREAKDOWN;
-                break;
-            }
-            if (h.stop == 1) {
-                // recursive residual below tolerance: verify with the true one
-                const int iters = h.iter;
-                HNS_TRY(restart_fp64(c));
-                HNS_TRY(pull_scalars(w, 0, c.s));
-                h.iter = iters;
-                parity = 0;
-                if (h.stop == 1) {
-                    status = HNS_OK;
-                    break;
-                }
-                // restarted from the true residual; the device counter was
-                // not touched by the restart kernels
-            }
-        }
-    }
-    info->iterations = h.iter;
-    info->outer_iterations = 1;
-    if (status == HNS_NOT_CONVERGED) {
-        const int iters = h.iter;
-        HNS_TRY(restart_fp64(c));
-        HNS_TRY(pull_scalars(w, 0, c.s));
-        h.iter = iters;
-    }
-    info->relres_true = h.bb > 0 ? std::sqrt(h.rr / h.bb) : 0.0;
-    if (status >= 0 && c.singular) {
-        HNS_TRY(launch_normalise(op->n, c.x, op->lumped, op->lumped_sum, w->sc, w->partials, c.s));
-        HNS_TRY_HIP(hipStreamSynchronize(c.s));
-    }
-    if (status == HNS_ERR_BREAKDOWN)
-        set_error("CG breakdown after %d iterations (p^T A p = %g)", h.iter, h.gamma);
-    info->status = status;
-    return status;
-}
-
-// ---------------------------------------------------------------------------
-// Mixed precision: FP32 inner PCG inside FP64 iterative refinement
-// ---------------------------------------------------------------------------
+// r = b - A x in FP64 (projected in the pure-Neumann case) into w->r; sum of
+// squares into sc[0].rr, |b|^2 into sc[0].bb.
 static hns_status true_residual_fp64(const SolveCtx &c)
 {
     hns_operator *op = c.op;
@@ -310,22 +244,128 @@ static hns_status true_residual_fp64(const SolveCtx &c)
     return HNS_OK;
 }
 
-static hns_status solve_mixed(const SolveCtx &c, hns_solve_info *info)
+static hns_status finish_solve(const SolveCtx &c, hns_solve_info *info, hns_status status)
 {
     hns_operator *op = c.op;
     Workspace *w = c.w;
-    bool done;
-    HNS_TRY(begin_solve(c, info, &done));
+    const Scalars &h = w->host[0];
+    info->relres_true = h.bb > 0 ? std::sqrt(h.rr / h.bb) : 0.0;
+    if (status >= 0 && c.singular) {
+        HNS_TRY(launch_normalise(op->n, c.x, op->lumped, op->lumped_sum, w->sc, w->partials,
+                                 c.s));
+    }
+    HNS_TRY_HIP(hipStreamSynchronize(c.s));
+    info->status = status;
+    return status;
+}
+
+// Jacobi-PCG of one recurrence with FP64 vectors on the device; `prec`
+// selects FP64 (plain solve) or FP32 matrix/diagonal storage.  Whenever the
+// recursive residual has fallen below `drop` times the last true residual
+// (or below the tolerance), the true residual b - A x is recomputed with the
+// FP64 matrix.  At the tolerance the solve ends if the true residual agrees;
+// otherwise the recurrence continues from the true residual: a full restart
+// (fresh direction) in the plain FP64 solve, a residual replacement that
+// keeps the direction in the FP32-storage variant.
+static hns_status solve_fp64_vectors(const SolveCtx &c, hns_solve_info *info, Prec prec)
+{
+    hns_operator *op = c.op;
+    Workspace *w = c.w;
+    HNS_TRY(begin_solve(c, info));
+    HNS_TRY(true_residual_fp64(c));
+    HNS_TRY(pull_scalars(w, 0, c.s));
+    Scalars &h = w->host[0];
+    info->outer_iterations = 0;
+    if (!(h.bb > 0.0)) {  // b = 0
+        HNS_TRY(launch_prepare_x(op->n, c.x, nullptr, -1, true, c.s));
+        return finish_solve(c, info, HNS_OK);
+    }
+    const bool storage = (prec == Prec::F32Store);
+    const void *dinv = storage ? (const void *)op->dinv32 : (const void *)op->dinv;
+    const double tol2 = c.tol * c.tol;
+    const double drop2 = storage ? op->replace_drop * op->replace_drop : 0.0;
+    hns_status status = HNS_NOT_CONVERGED;
+    int since = 0, replacements = 0, stalls = 0;
+    double rr_true = h.rr, bb = h.bb, rr_prev = h.rr;
+    bool fresh = true;
+    while (rr_true > tol2 * bb) {
+        if (fresh) {
+            // new direction from the true residual in w->r
+            if (storage) {  // next stop: residual down by `drop` (or at tol)
+                h.tol2 = std::max(tol2 * bb / rr_true, drop2);
+                h.bb = rr_true;
+            } else {
+                h.tol2 = tol2;
+                h.bb = bb;
+            }
+            h.stop = 0;
+            HNS_TRY(push_scalars(w, 0, c.s));
+            HNS_TRY(launch_init_dir(op->n, prec, w->r, w->p, dinv, false, false, w->sc,
+                                    w->partials, c.s));
+            HNS_TRY(pull_scalars(w, 0, c.s));
+            since = 0;
+            fresh = false;
+        }
+        if (h.stop == 0) HNS_TRY(run_chunks(c, 0, prec, c.x, w->r, w->p, w->q, dinv, &since));
+        info->iterations = h.iter;
+        if (h.stop == 2) {
+            status = HNS_ERR_BREAKDOWN;
+            set_error("CG breakdown after %d iterations (p^T A p = %g)", h.iter, h.gamma);
+            break;
+        }
+        const bool hit = (h.stop == 1);
+        // true residual, FP64 matrix
+        const int iters = h.iter;
+        HNS_TRY(true_residual_fp64(c));
+        HNS_TRY(pull_scalars(w, 0, c.s));
+        h.iter = iters;
+        rr_true = h.rr;
+        ++replacements;
+        if (rr_true <= tol2 * bb) {
+            status = HNS_OK;
+            break;
+        }
+        if (!hit || h.iter >= c.max_iter) break;  // budget spent
+        if (!storage) {
+            fresh = true;  // restart from the true residual
+            continue;
+        }
+        stalls = (rr_true > 0.81 * rr_prev) ? stalls + 1 : 0;
+        if (stalls >= 3) {
+            set_error("FP32-storage refinement stagnated at relative residual %g",
+                      std::sqrt(rr_true / bb));
+            break;
+        }
+        rr_prev = rr_true;
+        // residual replacement: keep the direction, continue from r_true
+        h.tol2 = std::max(tol2 * bb / rr_true, drop2);
+        HNS_TRY(launch_set_threshold(w->sc, h.tol2, rr_true, c.s));
+        HNS_TRY(launch_replace_residual(op->n, prec, w->r, nullptr, w->p, dinv, w->sc,
+                                        w->partials, (since - 1) & 1, c.s));
+        h.stop = 0;
+    }
+    // report the FP64 residual against |b|^2
+    h.bb = bb;
+    h.rr = rr_true;
+    info->outer_iterations = storage ? replacements : 1;
+    return finish_solve(c, info, status);
+}
+
+// Classic mixed-precision refinement: each FP64 correction step solves
+// A32 d = r / |r| by a fresh FP32 CG to `inner_tol`, then x += |r| d.
+static hns_status solve_mixed_restart(const SolveCtx &c, hns_solve_info *info)
+{
+    hns_operator *op = c.op;
+    Workspace *w = c.w;
+    HNS_TRY(begin_solve(c, info));
     HNS_TRY(true_residual_fp64(c));
     HNS_TRY(pull_scalars(w, 0, c.s));
     Scalars &h = w->host[0];
     Scalars &hi = w->host[1];
+    info->outer_iterations = 0;
     if (!(h.bb > 0.0)) {
         HNS_TRY(launch_prepare_x(op->n, c.x, nullptr, -1, true, c.s));
-        HNS_TRY_HIP(hipStreamSynchronize(c.s));
-        info->status = HNS_OK;
-        info->outer_iterations = 0;
-        return HNS_OK;
+        return finish_solve(c, info, HNS_OK);
     }
     const double tol2 = c.tol * c.tol;
     hns_status status = HNS_NOT_CONVERGED;
@@ -343,28 +383,18 @@ static hns_status solve_mixed(const SolveCtx &c, hns_solve_info *info)
         }
         rr_prev = h.rr;
         ++outer;
-        // inner problem A32 d = r / ||r||, solved to inner_tol
         HNS_TRY(launch_cast_scaled(op->n, w->r, w->r32, w->d32, w->sc, c.s));
         reset_scalars(hi, op->inner_tol);
         HNS_TRY(push_scalars(w, 1, c.s));
-        HNS_TRY(launch_init_dir(op->n, true, w->r32, w->p32, op->dinv32, false, true, w->sc + 1,
-                                w->partials, c.s));
+        HNS_TRY(launch_init_dir(op->n, Prec::F32, w->r32, w->p32, op->dinv32, false, true,
+                                w->sc + 1, w->partials, c.s));
         HNS_TRY(pull_scalars(w, 1, c.s));
-        bool inner_break = (hi.stop == 2);
-        int parity = 0;
-        while (hi.stop == 0) {
-            const int left = c.max_iter - total_inner - hi.iter;
-            if (left <= 0) break;
-            const int chunk = left < op->check_every ? left : op->check_every;
-            const int before = hi.iter;
-            HNS_TRY(enqueue_iterations(op, w, op->A, true, c.bit, w->d32, w->r32, w->p32, w->q32,
-                                       op->dinv32, w->sc + 1, chunk, &parity, c.s));
-            HNS_TRY(pull_scalars(w, 1, c.s));
-            HNS_TRY(account_iterations(op, w, true, hi.iter - before));
-            if (hi.stop == 2) inner_break = true;
-        }
+        int since = 0;
+        SolveCtx ci = c;
+        ci.max_iter = c.max_iter - total_inner;
+        HNS_TRY(run_chunks(ci, 1, Prec::F32, w->d32, w->r32, w->p32, w->q32, op->dinv32, &since));
         total_inner += hi.iter;
-        if (inner_break && hi.iter == 0) {
+        if (hi.stop == 2 && hi.iter == 0) {
             status = HNS_ERR_BREAKDOWN;
             set_error("FP32 inner CG broke down at its first iteration");
             break;
@@ -375,13 +405,99 @@ static hns_status solve_mixed(const SolveCtx &c, hns_solve_info *info)
     }
     info->iterations = total_inner;
     info->outer_iterations = outer;
-    info->relres_true = std::sqrt(h.rr / h.bb);
-    if (status >= 0 && c.singular) {
-        HNS_TRY(launch_normalise(op->n, c.x, op->lumped, op->lumped_sum, w->sc, w->partials, c.s));
-        HNS_TRY_HIP(hipStreamSynchronize(c.s));
+    return finish_solve(c, info, status);
+}
+
+// Mixed precision with residual replacement: one FP32 CG recurrence (matrix,
+// vectors and diagonal in FP32) keeps its search direction across refinement
+// steps.  Whenever its recursive residual has dropped by `replace_drop` since
+// the last FP64 residual, the FP32 iterate is added to the FP64 solution, the
+// true residual is recomputed in FP64, and the recurrence continues from it.
+static hns_status solve_mixed_replace(const SolveCtx &c, hns_solve_info *info)
+{
+    hns_operator *op = c.op;
+    Workspace *w = c.w;
+    HNS_TRY(begin_solve(c, info));
+    HNS_TRY(true_residual_fp64(c));
+    HNS_TRY(pull_scalars(w, 0, c.s));
+    Scalars &h = w->host[0];
+    Scalars &hi = w->host[1];
+    info->outer_iterations = 0;
+    if (!(h.bb > 0.0)) {
+        HNS_TRY(launch_prepare_x(op->n, c.x, nullptr, -1, true, c.s));
+        return finish_solve(c, info, HNS_OK);
     }
-    info->status = status;
-    return status;
+    const double tol2 = c.tol * c.tol;
+    const double drop2 = op->replace_drop * op->replace_drop;
+    hns_status status = HNS_NOT_CONVERGED;
+    int replacements = 0, since = 0, stalls = 0;
+    bool fresh = true;
+    double rr_prev = h.rr;
+    while (h.rr > tol2 * h.bb) {
+        const double thr2 = std::max(drop2, tol2 * h.bb / h.rr);
+        if (fresh) {
+            HNS_TRY(launch_cast(op->n, w->r, w->r32, w->d32, c.s));
+            reset_scalars(hi, 0.0);
+            hi.tol2 = thr2;
+            hi.bb = h.rr;
+            hi.iter = info->iterations;
+            HNS_TRY(push_scalars(w, 1, c.s));
+            HNS_TRY(launch_init_dir(op->n, Prec::F32, w->r32, w->p32, op->dinv32, false, false,
+                                    w->sc + 1, w->partials, c.s));
+            HNS_TRY(pull_scalars(w, 1, c.s));
+            since = 0;
+            fresh = false;
+        }
+        HNS_TRY(run_chunks(c, 1, Prec::F32, w->d32, w->r32, w->p32, w->q32, op->dinv32, &since));
+        info->iterations = hi.iter;
+        const bool broke = (hi.stop == 2);
+        // collect the FP32 correction and recompute the true residual in FP64
+        HNS_TRY(launch_accumulate(op->n, c.x, w->d32, c.s));
+        HNS_TRY(true_residual_fp64(c));
+        HNS_TRY(pull_scalars(w, 0, c.s));
+        ++replacements;
+        if (h.rr <= tol2 * h.bb) {
+            status = HNS_OK;
+            break;
+        }
+        if (hi.stop != 1 && !broke) break;  // iteration budget spent
+        stalls = (h.rr > 0.81 * rr_prev) ? stalls + 1 : 0;
+        if (stalls >= 3) {
+            set_error("mixed-precision refinement stagnated at relative residual %g",
+                      std::sqrt(h.rr / h.bb));
+            break;
+        }
+        rr_prev = h.rr;
+        if (broke) {
+            if (stalls > 0) {
+                status = HNS_ERR_BREAKDOWN;
+                set_error("FP32 CG broke down without progress after %d iterations", hi.iter);
+                break;
+            }
+            fresh = true;  // new direction from the new true residual
+            continue;
+        }
+        HNS_TRY(launch_set_threshold(w->sc + 1, std::max(drop2, tol2 * h.bb / h.rr), h.rr, c.s));
+        HNS_TRY(launch_replace_residual(op->n, Prec::F32, w->r, w->r32, w->p32, op->dinv32,
+                                        w->sc + 1, w->partials, (since - 1) & 1, c.s));
+        hi.stop = 0;
+    }
+    info->outer_iterations = replacements;
+    return finish_solve(c, info, status);
+}
+
+static hns_status solve_fp64(const SolveCtx &c, hns_solve_info *info)
+{
+    return solve_fp64_vectors(c, info, Prec::F64);
+}
+
+static hns_status solve_mixed(const SolveCtx &c, hns_solve_info *info)
+{
+    switch (c.op->mixed_variant) {
+    case 1: return solve_mixed_restart(c, info);
+    case 2: return solve_fp64_vectors(c, info, Prec::F32Store);
+    default: return solve_mixed_replace(c, info);
+    }
 }
 
 }  // namespace hns
@@ -451,6 +567,40 @@ static hns_status finish_operator(hns_operator *op, const HostCSR &A, uint32_t f
     return HNS_OK;
 }
 
+// Auxiliary forms of the step right-hand sides, all in CSR on the pattern of A
+static hns_status assemble_step_aux(hns_operator *op, const hns_mesh *mesh, const HostCSR &A)
+{
+    if (op->kind != HNS_HELMHOLTZ) {
+        set_error("HNS_STEP_AUX needs a HNS_HELMHOLTZ operator");
+        return HNS_ERR_INVALID;
+    }
+    {
+        HostCSR M;
+        HNS_TRY(assemble_host(mesh, 1.0, 0.0, 0.0, 0.0, M, nullptr));
+        HNS_TRY(upload_matrix(M, HNS_FMT_CSR, false, op->M));
+    }
+    for (int c = 0; c < 3; ++c) {
+        HostCSR B, Bt;
+        HNS_TRY(assemble_divergence_host(mesh, A, c, B));
+        transpose_values(B, Bt);
+        HNS_TRY(upload_matrix(B, HNS_FMT_CSR, false, op->B[c]));
+        HNS_TRY(upload_matrix(Bt, HNS_FMT_CSR, false, op->Bt[c]));
+    }
+    {
+        HostCSR Ms;
+        HNS_TRY(assemble_surface_mass_host(mesh, Ms));
+        HNS_TRY(upload_matrix(Ms, HNS_FMT_CSR, false, op->Ms));
+    }
+    hipError_t e = hipMalloc((void **)&op->step_tmp, 3 * (size_t)op->n * sizeof(double));
+    if (e != hipSuccess) {
+        op->step_tmp = nullptr;
+        set_error("step scratch allocation failed: %s", hipGetErrorString(e));
+        return HNS_ERR_OOM;
+    }
+    op->has_aux = true;
+    return HNS_OK;
+}
+
 hns_status hns_assemble(const hns_mesh *mesh, double nu_h, double nu_v, double dt, uint32_t flags,
                         hns_operator **out)
 {
@@ -490,6 +640,7 @@ hns_status hns_assemble(const hns_mesh *mesh, double nu_h, double nu_v, double d
         op->n = A.n;
         st = finish_operator(op, A, fmt, lumped, mesh->bc);
     }
+    if (st == HNS_OK && (flags & HNS_STEP_AUX)) st = assemble_step_aux(op, mesh, A);
     if (st != HNS_OK) {
         hns_operator_destroy(op);
         return st;
@@ -505,8 +656,9 @@ void hns_operator_destroy(hns_operator *op)
     op->A.release();
     op->M.release();
     for (auto &b : op->B) b.release();
+    for (auto &b : op->Bt) b.release();
     op->Ms.release();
-    void *ptrs[] = {op->dinv, op->dinv32, op->bc, op->lumped};
+    void *ptrs[] = {op->dinv, op->dinv32, op->bc, op->lumped, op->step_tmp};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (Workspace *w : op->ws_free) delete w;
@@ -557,6 +709,10 @@ hns_status hns_set_param(hns_operator *op, const char *name, double value)
         op->inner_tol = value;
     } else if (k == "max_outer" && value >= 1 && value <= 1000) {
         op->max_outer = (int)value;
+    } else if (k == "mixed_variant" && (value == 0 || value == 1 || value == 2)) {
+        op->mixed_variant = (int)value;
+    } else if (k == "replace_drop" && value > 0 && value < 1) {
+        op->replace_drop = value;
     } else if (k == "use_graph" && (value == 0 || value == 1)) {
         op->use_graph = (int)value;
     } else {
@@ -574,7 +730,8 @@ size_t hns_footprint_bytes(const hns_operator *op, int k, uint32_t mode, int inc
     if (include_operator) {
         b += op->A.bytes() + (size_t)op->n * (8 + 1 + 8);
         if (op->dinv32) b += (size_t)op->n * 4;
-        if (op->has_aux) b += op->M.bytes() + op->B[0].bytes() * 3 + op->Ms.bytes();
+        if (op->has_aux)
+            b += op->M.bytes() + op->B[0].bytes() * 6 + op->Ms.bytes() + 24 * (size_t)op->n;
     }
     return b;
 }

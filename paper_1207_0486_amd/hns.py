@@ -52,13 +52,18 @@ def _stream_handle(stream):
     return C.c_void_p(stream.cuda_stream)
 
 
-def _dev_f64(t: torch.Tensor, name: str, n: int | None = None, k: int | None = None):
+def _dev_f64(t: torch.Tensor, name: str, n: int | None = None, k: int | None = None,
+             rows: int | None = None):
+    """Device pointer of a contiguous float64 tensor of shape (n,), (n, k) or
+    (rows, n); None passes through as NULL."""
+    if t is None:
+        return None
     if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
         raise TypeError(f"{name} must be a CUDA (HIP) tensor")
     if t.dtype != torch.float64 or not t.is_contiguous():
         raise TypeError(f"{name} must be contiguous float64")
     if n is not None:
-        want = (n,) if k is None else (n, k)
+        want = (rows, n) if rows is not None else ((n,) if k is None else (n, k))
         if tuple(t.shape) != want:
             raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {want}")
     return C.c_void_p(t.data_ptr())
@@ -170,6 +175,47 @@ class Operator:
             st = L.lib().hns_apply(self._h, mask_bit, xp, yp, _stream_handle(stream))
         if st != L.HNS_OK:
             raise HNSError(st, "hns_apply")
+        return y
+
+    # -- projection-step right-hand sides (operators with step_aux=True) ----
+    def step_velocity_rhs(self, u, p=None, theta=None, f=None, out=None, stream=None):
+        """b_c = M u_c + dt (M_s theta_c + C_c + B_c^T p) for c = 1..3 (u: 3 x n)."""
+        b = torch.empty_like(u) if out is None else out
+        st = L.lib().hns_step_velocity_rhs(
+            self._h, _dev_f64(u, "u", self.n, rows=3), _dev_f64(p, "p", self.n),
+            _dev_f64(theta, "theta", self.n, rows=2), _dev_f64(f, "f", self.n),
+            _dev_f64(b, "out", self.n, rows=3), _stream_handle(stream))
+        if st != L.HNS_OK:
+            raise HNSError(st, "hns_step_velocity_rhs")
+        return b
+
+    def step_pressure_rhs(self, ut, out=None, stream=None):
+        """b = -(1/dt) sum_c B_c ut_c (ut: 3 x n)."""
+        b = torch.empty(self.n, dtype=torch.float64, device=ut.device) if out is None else out
+        st = L.lib().hns_step_pressure_rhs(self._h, _dev_f64(ut, "ut", self.n, rows=3),
+                                           _dev_f64(b, "out", self.n), _stream_handle(stream))
+        if st != L.HNS_OK:
+            raise HNSError(st, "hns_step_pressure_rhs")
+        return b
+
+    def step_correct(self, ut, q, p=None, out=None, stream=None):
+        """p += q; u_c = ut_c - dt (B_c q) / m_L (masked).  Returns u (3 x n)."""
+        u = torch.empty_like(ut) if out is None else out
+        st = L.lib().hns_step_correct(self._h, _dev_f64(ut, "ut", self.n, rows=3),
+                                      _dev_f64(q, "q", self.n), _dev_f64(p, "p", self.n),
+                                      _dev_f64(u, "out", self.n, rows=3), _stream_handle(stream))
+        if st != L.HNS_OK:
+            raise HNSError(st, "hns_step_correct")
+        return u
+
+    AUX = {"M": 0, "B1": 1, "B2": 2, "B3": 3, "B1T": 4, "B2T": 5, "B3T": 6, "Ms": 7}
+
+    def apply_aux(self, which: str, x, out=None, stream=None):
+        y = torch.empty_like(x) if out is None else out
+        st = L.lib().hns_apply_aux(self._h, self.AUX[which], _dev_f64(x, "x", self.n),
+                                   _dev_f64(y, "out", self.n), _stream_handle(stream))
+        if st != L.HNS_OK:
+            raise HNSError(st, "hns_apply_aux")
         return y
 
     def solve(self, b: torch.Tensor, x: torch.Tensor | None = None, tol: float = 1e-10,

@@ -112,11 +112,16 @@ def test_neumann_poisson_matches_oracle(dev, ragged_basin, fmt):
     assert abs(w @ xh) <= 1e-12 * np.abs(w).sum() * np.abs(xh).max()
 
 
-def test_mixed_error_against_tight_oracle(dev, ragged_basin):
+MIXED_VARIANTS = [0, 1, 2]  # FP32 + replacement, restarted refinement, FP32 storage
+
+
+@pytest.mark.parametrize("variant", MIXED_VARIANTS)
+def test_mixed_error_against_tight_oracle(dev, ragged_basin, variant):
     """FP32 inner / FP64 outer: error vs the oracle solved to 1e-13 within 1e-9."""
     from paper_1207_0486_amd.hns import Operator
     m = ragged_basin
     op = Operator(m, 1e3, 1e-2, 3600.0, kind="helmholtz", keep_fp32=True)
+    op.set_param("mixed_variant", variant)
     for bit in (0, 1, 2):
         d = (m.bc >> bit) & 1 == 1
         b = basin.normal_rhs(m.n, 40 + bit, dirichlet=d)
@@ -127,13 +132,15 @@ def test_mixed_error_against_tight_oracle(dev, ragged_basin):
         assert _relerr(x.cpu().numpy(), exact.x) <= 1e-9
 
 
-def test_mixed_neumann(dev, ragged_basin):
+@pytest.mark.parametrize("variant", MIXED_VARIANTS)
+def test_mixed_neumann(dev, ragged_basin, variant):
     from paper_1207_0486_amd.hns import Operator
     m = ragged_basin
     w = oracle.mass(m).matvec(np.ones(m.n))
     b = basin.normal_rhs(m.n, 50)
     exact = oracle.pcg(oracle.stiffness(m, 1e3, 1e-2), b, singular=True, weights=w, tol=1e-13)
     op = Operator(m, 1e3, 1e-2, kind="poisson", keep_fp32=True)
+    op.set_param("mixed_variant", variant)
     x, info = op.solve(_gpu(b, dev), tol=1e-10, mode="mixed")
     assert info.status == 0 and info.relres_true <= 1e-10
     assert _relerr(x.cpu().numpy(), exact.x) <= 1e-9
