@@ -34,30 +34,38 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def bytes_fp64_iter(n, nnz):
-    """Algorithmic bytes of one FP64 CG iteration: the CSR matrix (values,
-    column indices, row pointers) plus 13 vector passes of 8 bytes."""
-    return 12 * nnz + 4 * (n + 1) + 13 * 8 * n
+def matrix_bytes(fmt, n, nnz, value_bytes):
+    """Algorithmic bytes of one read of the operator in the storage format the
+    solve runs: symmetric diagonal storage reads the unique values of the
+    symmetric matrix ((nnz + n) / 2 of them) and no indices; CSR and sliced
+    ELL read every value, its column index and the row pointers."""
+    if fmt == "sdia":
+        return value_bytes * (nnz + n) // 2
+    return (value_bytes + 4) * nnz + 4 * (n + 1)
 
 
-def bytes_fp64_spmv(n, nnz):
-    """Algorithmic bytes of the SpMV kernel: matrix + read p + write q."""
-    return 12 * nnz + 4 * (n + 1) + 16 * n
+def bytes_iter(fmt, n, nnz, vb):
+    """One CG iteration: one operator read plus 13 vector passes (SpMV reads p
+    and writes q; the update reads x, p, r, q, D^-1 and writes x, r; the
+    direction update reads r, D^-1, p and writes p)."""
+    return matrix_bytes(fmt, n, nnz, vb) + 13 * vb * n
 
 
-def bytes_fp32_iter(n, nnz):
-    return 8 * nnz + 4 * (n + 1) + 13 * 4 * n
+def bytes_spmv(fmt, n, nnz, vb):
+    """The SpMV kernel alone: operator + read p + write q."""
+    return matrix_bytes(fmt, n, nnz, vb) + 2 * vb * n
 
 
-def bytes_fp64_residual(n, nnz):
-    return 12 * nnz + 4 * (n + 1) + 3 * 8 * n
+def bytes_residual(fmt, n, nnz):
+    """FP64 true residual b - A x: operator + read x, b + write r."""
+    return matrix_bytes(fmt, n, nnz, 8) + 3 * 8 * n
 
 
-def solve_bytes(info, n, nnz, mode):
+def solve_bytes(info, fmt, n, nnz, mode):
     if mode == "fp64":
-        return info.iterations * bytes_fp64_iter(n, nnz)
-    return (info.iterations * bytes_fp32_iter(n, nnz)
-            + (info.outer_iterations + 1) * bytes_fp64_residual(n, nnz))
+        return info.iterations * bytes_iter(fmt, n, nnz, 8)
+    return (info.iterations * bytes_iter(fmt, n, nnz, 4)
+            + (info.outer_iterations + 1) * (bytes_residual(fmt, n, nnz) + 8 * 3 * n))
 
 
 def make_forcing(m):
@@ -79,6 +87,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--fmt", default="auto")
+    ap.add_argument("--profile-period", type=int, default=16,
+                    help="time every N-th CG iteration with HIP events (0 = off)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the solver "
@@ -138,13 +148,15 @@ def main():
         total = time.perf_counter() - t
         prof = {"helm": helm.profile_read(), "pois": pois.profile_read()}
         for op in (helm, pois):
-            op.profile(False)
+            op.profile(0)
         return total, per, infos, prof
 
-    total64, per64, infos64, prof64 = timed("fp64", args.steps, args.warmup, True)
+    total64, per64, infos64, prof64 = timed("fp64", args.steps, args.warmup, args.profile_period)
     u64 = st.u.clone()
     ms64 = 1e3 * total64 / args.steps
-    bytes64 = sum(solve_bytes(i, n, nnz, "fp64") for i in infos64.values())
+    fmt = pois.format
+    bytes64 = sum(solve_bytes(i, fmt, n, nnz, "fp64") for i in infos64.values())
+    csr_equiv = sum(solve_bytes(i, "csr", n, nnz, "fp64") for i in infos64.values())
     gbs64 = bytes64 / (ms64 * 1e-3) / 1e9
     log(f"fp64: {ms64:.1f} ms/step, {gbs64:.0f} GB/s, iters "
         + ", ".join(f"{k}={i.iterations}" for k, i in infos64.items()))
@@ -152,7 +164,7 @@ def main():
     # dominant kernel: the SpMV of the pressure solve, timed live with HIP events
     spmv_ms, spmv_n = prof64["pois"]["spmv"]
     spmv_avg_us = 1e3 * spmv_ms / max(spmv_n, 1)
-    spmv_bytes = bytes_fp64_spmv(n, nnz)
+    spmv_bytes = bytes_spmv(fmt, n, nnz, 8)
     spmv_gbs = spmv_bytes / (spmv_avg_us * 1e-6) / 1e9
     kern = {}
     for name in ("spmv", "update", "pupdate"):
@@ -162,7 +174,7 @@ def main():
 
     mixed = None
     if not args.no_mixed:
-        totalm, perm, infosm, profm = timed("mixed", args.steps, args.warmup, True)
+        totalm, perm, infosm, profm = timed("mixed", args.steps, args.warmup, args.profile_period)
         msm = 1e3 * totalm / args.steps
         diff = float(torch.linalg.norm(st.u - u64) / torch.linalg.norm(u64))
         k32 = {}
@@ -193,7 +205,7 @@ def main():
         r = oracle.pcg(K, st.b_q.cpu().numpy(), singular=True, weights=w, tol=wl.tol,
                        maxit=args.cpu_iters)
         el = time.perf_counter() - t
-        cpu_gbs = r.iterations * bytes_fp64_iter(n, nnz) / el / 1e9
+        cpu_gbs = r.iterations * bytes_iter("csr", n, nnz, 8) / el / 1e9
         cpu = {"value": round(cpu_gbs, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
                "sample": f"first {r.iterations} Jacobi-PCG iterations of the {wl.name} "
                          f"pressure solve, FP64, 1 thread ({el:.1f} s)",
@@ -218,11 +230,14 @@ def main():
                    "rhs": "time step 1 after a step from rest (wind, Coriolis, pressure)",
                    "tol": wl.tol, "nu_h": wl.nu_h, "nu_v": wl.nu_v,
                    "dt": wl.dt},
+        "value_basis": "algorithmic bytes of the solves in the storage format used (operator "
+                       "read + 13 vector passes per CG iteration) / step time",
+        "csr_equivalent_GBs": round(csr_equiv / (ms64 * 1e-3) / 1e9, 1),
         "fp64": {k: {"iters": i.iterations, "relres": i.relres_true} for k, i in infos64.items()},
         "step_ms": [round(1e3 * v, 3) for v in per64],
         "roofline": {"bound": "hbm", "achieved": round(spmv_gbs, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(spmv_gbs / PEAK_HBM_GBS, 4), "traffic": None,
-                     "kernel": f"k_spmv_{pois.format}<double,true>",
+                     "kernel": f"k_spmv_{fmt}<double,double,true>",
                      "bytes_per_launch": spmv_bytes, "avg_us": round(spmv_avg_us, 2)},
         "pressure_kernels": kern,
         "mixed": mixed,

@@ -84,6 +84,12 @@ typedef struct {
 #define HNS_FMT_CSR   0x100u /* compressed sparse rows, 16 lanes per row            */
 #define HNS_FMT_SELL  0x200u /* sliced ELLPACK, slice height 64 (one wavefront),
                                 column-major inside a slice                          */
+#define HNS_FMT_SDIA  0x400u /* symmetric diagonal storage: main + at most 16 upper
+                                diagonals, no column indices, lower triangle read by
+                                symmetry; needs a bitwise-symmetric matrix whose
+                                pattern has few distinct offsets j - i (structured
+                                meshes).  HNS_FMT_AUTO picks it when it applies, else
+                                SELL when row lengths are even, else CSR            */
 
 /* Solve modes */
 #define HNS_FP64  0u         /* everything in FP64                                   */
@@ -222,15 +228,16 @@ hns_status hns_step_correct(hns_operator *helm, const double *ut_dev, const doub
 hns_status hns_apply_aux(hns_operator *helm, int which, const double *x_dev, double *y_dev,
                          void *stream);
 
-/* Kernel timing for measurement.  When enabled, every CG iteration a solve
- * runs on this operator records HIP events around its three kernels on the
- * solve's stream, and the durations of the iterations that did work (not the
- * no-op launches after convergence inside a chunk) are accumulated per kernel:
- *   kernel 0/1/2 = spmv / update / pupdate in FP64,
- *   kernel 3/4/5 = the same kernels in FP32 (inner solves of HNS_MIXED).
- * hns_profile_read returns the summed milliseconds and the launch count;
- * enabling (on = 1) also clears the counters. */
-hns_status hns_profile_enable(hns_operator *op, int on);
+/* Kernel timing for measurement.  With period P > 0, every P-th CG
+ * iteration of each chunk a solve runs on this operator records HIP events
+ * around its three kernels on the solve's stream, and the durations of the
+ * sampled iterations that did work (not the no-op launches after convergence
+ * inside a chunk) are accumulated per kernel:
+ *   kernel 0/1/2 = spmv / update / pupdate in FP64 vectors,
+ *   kernel 3/4/5 = the same kernels in FP32 (inner iterations of HNS_MIXED).
+ * hns_profile_read returns the summed milliseconds and the sampled launch
+ * count; hns_profile_enable(op, P > 0) also clears the counters, P = 0 stops. */
+hns_status hns_profile_enable(hns_operator *op, int period);
 hns_status hns_profile_read(const hns_operator *op, int kernel, double *total_ms,
                             int64_t *launches);
 

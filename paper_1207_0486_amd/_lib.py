@@ -22,6 +22,7 @@ HNS_STEP_AUX = 0x20
 HNS_FMT_AUTO = 0x000
 HNS_FMT_CSR = 0x100
 HNS_FMT_SELL = 0x200
+HNS_FMT_SDIA = 0x400
 
 HNS_FP64 = 0
 HNS_MIXED = 1

@@ -312,7 +312,10 @@ void transpose_values(const HostCSR &A, HostCSR &At)
 size_t DevMatrix::bytes() const
 {
     size_t b = 0;
-    if (fmt == HNS_FMT_CSR) {
+    if (fmt == HNS_FMT_SDIA) {
+        b += (size_t)(ndiag + 1) * n * 8;
+        if (dia32) b += (size_t)(ndiag + 1) * n * 4;
+    } else if (fmt == HNS_FMT_CSR) {
         b += (size_t)(n + 1) * 4 + (size_t)nnz * 12;
         if (val32) b += (size_t)nnz * 4;
     } else {
@@ -324,16 +327,44 @@ size_t DevMatrix::bytes() const
 
 void DevMatrix::release()
 {
-    void *ptrs[] = {rowptr, col, val, val32, slice_ptr, scol, sval, sval32};
+    void *ptrs[] = {rowptr, col, val, val32, slice_ptr, scol, sval, sval32, dia, dia32};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     rowptr = col = slice_ptr = scol = nullptr;
-    val = sval = nullptr;
-    val32 = sval32 = nullptr;
+    val = sval = dia = nullptr;
+    val32 = sval32 = dia32 = nullptr;
+}
+
+// Offsets j - i of the upper triangle when the matrix is bitwise symmetric
+// and uses at most kMaxDiag distinct upper offsets; empty otherwise.
+static std::vector<int32_t> symmetric_offsets(const HostCSR &h)
+{
+    std::vector<char> seen;
+    std::vector<int32_t> offs;
+    for (int64_t i = 0; i < h.n; ++i)
+        for (int32_t k = h.rowptr[i]; k < h.rowptr[i + 1]; ++k) {
+            const int64_t d = (int64_t)h.col[k] - i;
+            if (d <= 0) continue;
+            if (std::find(offs.begin(), offs.end(), (int32_t)d) == offs.end()) {
+                offs.push_back((int32_t)d);
+                if ((int)offs.size() > kMaxDiag) return {};
+            }
+        }
+    // bitwise symmetry of values and pattern
+    for (int64_t i = 0; i < h.n; ++i)
+        for (int32_t k = h.rowptr[i]; k < h.rowptr[i + 1]; ++k) {
+            const int64_t j = h.col[k];
+            if (j <= i) continue;
+            const int64_t t = find_col(h, j, (int32_t)i);
+            if (t < 0 || h.val[t] != h.val[k]) return {};
+        }
+    std::sort(offs.begin(), offs.end());
+    return offs;
 }
 
 uint32_t choose_format(const HostCSR &h)
 {
+    if (!symmetric_offsets(h).empty()) return HNS_FMT_SDIA;
     // Sliced ELL pays when rows inside a 64-row slice have similar lengths
     // (padding stays small); the structured basin meshes give < 5 % padding.
     int64_t n = h.n, padded = 0;
@@ -366,6 +397,37 @@ hns_status upload_matrix(const HostCSR &h, uint32_t fmt, bool keep32, DevMatrix 
     d.n = h.n;
     d.nnz = h.nnz();
     d.fmt = fmt;
+    if (fmt == HNS_FMT_SDIA) {
+        std::vector<int32_t> offs = symmetric_offsets(h);
+        if (offs.empty()) {
+            set_error("symmetric-diagonal storage needs a bitwise-symmetric matrix with at most "
+                      "%d upper diagonal offsets",
+                      kMaxDiag);
+            return HNS_ERR_INVALID;
+        }
+        const int64_t n = h.n;
+        d.ndiag = (int)offs.size();
+        for (int k = 0; k < d.ndiag; ++k) d.off[k] = offs[k];
+        std::vector<double> dia((size_t)(d.ndiag + 1) * n, 0.0);
+        parallel_for(n, [&](int64_t lo, int64_t hi) {
+            for (int64_t i = lo; i < hi; ++i)
+                for (int32_t k = h.rowptr[i]; k < h.rowptr[i + 1]; ++k) {
+                    const int64_t dj = (int64_t)h.col[k] - i;
+                    if (dj < 0) continue;
+                    int slot = 0;
+                    if (dj > 0)
+                        slot = 1 + (int)(std::lower_bound(offs.begin(), offs.end(), (int32_t)dj) -
+                                         offs.begin());
+                    dia[(size_t)slot * n + i] = h.val[k];
+                }
+        });
+        HNS_TRY(upload(dia, &d.dia));
+        if (keep32) {
+            std::vector<float> d32(dia.begin(), dia.end());
+            HNS_TRY(upload(d32, &d.dia32));
+        }
+        return HNS_OK;
+    }
     if (fmt == HNS_FMT_CSR) {
         HNS_TRY(upload(h.rowptr, &d.rowptr));
         HNS_TRY(upload(h.col, &d.col));

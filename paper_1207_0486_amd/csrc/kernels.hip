@@ -243,12 +243,107 @@ __global__ __launch_bounds__(kBlock) void k_spmv_csr(int64_t n, const int32_t *_
     }
 }
 
+// Offsets of the upper diagonals, passed by value (kernel-argument memory)
+struct DiaOffsets {
+    int32_t o[kMaxDiag];
+};
+
+// Symmetric diagonal storage, one row per lane: row i reads the main
+// diagonal, each upper diagonal at i (entry (i, i+o)) and at i-o (entry
+// (i-o, i) = (i, i-o) by symmetry).  All loads are unit-stride across the
+// wavefront (shifted copies of the same arrays), so there are no index
+// arrays and no gathers.  Each block owns a contiguous range of rows.
+template <typename TV, typename TX, bool DOT, int M>
+__global__ __launch_bounds__(kBlock) void k_spmv_sdia(int64_t n, DiaOffsets offs,
+                                                      const TV *__restrict__ dia,
+                                                      const TX *__restrict__ x, TX *__restrict__ y,
+                                                      const uint8_t *__restrict__ bc, int bit,
+                                                      const Scalars *__restrict__ sc,
+                                                      double *__restrict__ part)
+{
+    if constexpr (DOT) {
+        if (sc->stop) return;
+    }
+    const int G = gridDim.x;
+    const int lb = xcd_block(blockIdx.x, G);
+    const int64_t per = (((n + G - 1) / G) + kBlock - 1) / kBlock * kBlock;
+    const int64_t r0 = (int64_t)lb * per;
+    const int64_t r1 = r0 + per < n ? r0 + per : n;
+    double acc = 0.0;
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += kBlock) {
+        // every load is unconditional (indices clamped into range) so the
+        // 4 M + 2 loads of a row issue back to back; out-of-range terms are
+        // dropped by a select afterwards
+        const TX xi = x[i];
+        TX sum = (TX)dia[i] * xi;
+        TV up[M], lo[M];
+        TX xu[M], xl[M];
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            const int64_t o = offs.o[k];
+            const TV *u = dia + (int64_t)(k + 1) * n;
+            const int64_t iu = i + o < n ? i + o : n - 1;
+            const int64_t il = i >= o ? i - o : 0;
+            up[k] = u[i];
+            xu[k] = x[iu];
+            lo[k] = u[il];
+            xl[k] = x[il];
+        }
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            const int64_t o = offs.o[k];
+            sum += (i + o < n) ? (TX)up[k] * xu[k] : (TX)0;
+            sum += (i >= o) ? (TX)lo[k] * xl[k] : (TX)0;
+        }
+        if (is_dirichlet(bc, bit, i)) sum = 0;
+        y[i] = sum;
+        if constexpr (DOT) acc += (double)xi * (double)sum;
+    }
+    if constexpr (DOT) {
+        double v[1] = {acc};
+        store_block_partials<1>(v, part);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // CG vector updates
 // ---------------------------------------------------------------------------
 
+// V consecutive elements moved by one load/store instruction (16 bytes of TX)
+template <typename T, int V>
+struct alignas(sizeof(T) * V) Pack {
+    T v[V];
+};
+
+// Elementwise loop over [0, n): each thread handles packs of V consecutive
+// elements (V > 1 needs 16-byte aligned arrays), then the scalar tail.
+template <int V, typename F>
+__device__ __forceinline__ void for_packs(int64_t n, F &&body)
+{
+    const int64_t np = n / V;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t j = blockIdx.x * (int64_t)kBlock + threadIdx.x; j < np; j += stride)
+        body(j * V, std::integral_constant<int, V>());
+    if constexpr (V > 1) {
+        for (int64_t i = np * V + blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += stride)
+            body(i, std::integral_constant<int, 1>());
+    }
+}
+
+template <int W, typename T>
+__device__ __forceinline__ Pack<T, W> ld(const T *p, int64_t i)
+{
+    return *reinterpret_cast<const Pack<T, W> *>(p + i);
+}
+
+template <int W, typename T>
+__device__ __forceinline__ void st(T *p, int64_t i, const Pack<T, W> &v)
+{
+    *reinterpret_cast<Pack<T, W> *>(p + i) = v;
+}
+
 // x += alpha p; r -= alpha q; partials of r^T D^-1 r and r^T r.
-template <typename TX, typename TD>
+template <typename TX, typename TD, int V>
 __global__ __launch_bounds__(kBlock) void k_update(int64_t n, TX *__restrict__ x,
                                                    TX *__restrict__ r, const TX *__restrict__ p,
                                                    const TX *__restrict__ q,
@@ -275,15 +370,24 @@ __global__ __launch_bounds__(kBlock) void k_update(int64_t n, TX *__restrict__ x
     }
     const TX alpha = (TX)alpha_d;
     double rz = 0.0, rr = 0.0;
-    GRID_STRIDE(i, n)
-    {
-        x[i] = x[i] + alpha * p[i];
-        const TX ri = r[i] - alpha * q[i];
-        r[i] = ri;
-        const TX zi = (TX)dinv[i] * ri;
-        rz += (double)ri * (double)zi;
-        rr += (double)ri * (double)ri;
-    }
+    for_packs<V>(n, [&](int64_t i, auto w) {
+        constexpr int W = decltype(w)::value;
+        auto xv = ld<W>(x, i);
+        auto rv = ld<W>(r, i);
+        const auto pv = ld<W>(p, i);
+        const auto qv = ld<W>(q, i);
+        const auto dv = ld<W>(dinv, i);
+#pragma unroll
+        for (int e = 0; e < W; ++e) {
+            xv.v[e] = xv.v[e] + alpha * pv.v[e];
+            rv.v[e] = rv.v[e] - alpha * qv.v[e];
+            const TX zi = (TX)dv.v[e] * rv.v[e];
+            rz += (double)rv.v[e] * (double)zi;
+            rr += (double)rv.v[e] * (double)rv.v[e];
+        }
+        st<W>(x, i, xv);
+        st<W>(r, i, rv);
+    });
     double v[2] = {rz, rr};
     store_block_partials<2>(v, part_out);
 }
@@ -291,7 +395,7 @@ __global__ __launch_bounds__(kBlock) void k_update(int64_t n, TX *__restrict__ x
 // rho' = r^T z, rr = r^T r from the update partials; beta = rho' / rho;
 // p = D^-1 r + beta p unless converged.  `count` is added to the iteration
 // counter (0 when used after a residual replacement).
-template <typename TX, typename TD>
+template <typename TX, typename TD, int V = 1>
 __global__ __launch_bounds__(kBlock) void k_pupdate(int64_t n, TX *__restrict__ p,
                                                     const TX *__restrict__ r,
                                                     const TD *__restrict__ dinv,
@@ -318,7 +422,15 @@ __global__ __launch_bounds__(kBlock) void k_pupdate(int64_t n, TX *__restrict__ 
     }
     if (bad || conv) return;
     const TX beta = (TX)beta_d;
-    GRID_STRIDE(i, n) p[i] = (TX)dinv[i] * r[i] + beta * p[i];
+    for_packs<V>(n, [&](int64_t i, auto w) {
+        constexpr int W = decltype(w)::value;
+        auto pv = ld<W>(p, i);
+        const auto rv = ld<W>(r, i);
+        const auto dv = ld<W>(dinv, i);
+#pragma unroll
+        for (int e = 0; e < W; ++e) pv.v[e] = (TX)dv.v[e] * rv.v[e] + beta * pv.v[e];
+        st<W>(p, i, pv);
+    });
 }
 
 // (singular: r -= mean r) z = D^-1 r; p = z; rho[0] = r^T z; rr = r^T r.
@@ -542,12 +654,39 @@ hns_status check_launch(const char *what)
     return HNS_OK;
 }
 
+template <typename TV, typename TX, bool DOT, int M>
+void sdia_launch(const DevMatrix &A, const TV *vals, const void *p, void *q, const uint8_t *bc,
+                 int bit, const Scalars *sc, double *part, hipStream_t s)
+{
+    DiaOffsets offs;
+    for (int k = 0; k < kMaxDiag; ++k) offs.o[k] = k < A.ndiag ? A.off[k] : 0;
+    k_spmv_sdia<TV, TX, DOT, M><<<spmv_grid(A), kBlock, 0, s>>>(A.n, offs, vals, (const TX *)p,
+                                                                (TX *)q, bc, bit, sc, part);
+}
+
+template <typename TV, typename TX, bool DOT, int M = 1>
+void sdia_dispatch(const DevMatrix &A, const TV *vals, const void *p, void *q, const uint8_t *bc,
+                   int bit, const Scalars *sc, double *part, hipStream_t s)
+{
+    if constexpr (M <= kMaxDiag) {
+        if (A.ndiag == M)
+            sdia_launch<TV, TX, DOT, M>(A, vals, p, q, bc, bit, sc, part, s);
+        else
+            sdia_dispatch<TV, TX, DOT, M + 1>(A, vals, p, q, bc, bit, sc, part, s);
+    }
+}
+
 template <typename TV, typename TX, bool DOT>
 void spmv_dispatch(const DevMatrix &A, const void *p, void *q, const uint8_t *bc, int bit,
                    const Scalars *sc, double *part, hipStream_t s)
 {
     const int G = spmv_grid(A);
     const bool f32 = std::is_same<TV, float>::value;
+    if (A.fmt == HNS_FMT_SDIA) {
+        const TV *vd = f32 ? (const TV *)(const void *)A.dia32 : (const TV *)(const void *)A.dia;
+        sdia_dispatch<TV, TX, DOT>(A, vd, p, q, bc, bit, sc, part, s);
+        return;
+    }
     const TV *vs = f32 ? (const TV *)(const void *)A.sval32 : (const TV *)(const void *)A.sval;
     const TV *vc = f32 ? (const TV *)(const void *)A.val32 : (const TV *)(const void *)A.val;
     if (A.fmt == HNS_FMT_SELL)
@@ -558,23 +697,39 @@ void spmv_dispatch(const DevMatrix &A, const void *p, void *q, const uint8_t *bc
                                                      (TX *)q, bc, bit, sc, part);
 }
 
+inline bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
 template <typename TV, typename TX, typename TD>
 hns_status iteration_impl(const IterArgs &a, int parity, hipStream_t s, hipEvent_t *ev)
 {
+    constexpr int V = 16 / sizeof(TX);  // elements per 16-byte pack
     const uint8_t *bc = a.bit < 0 ? nullptr : a.bc;
     const int Gs = spmv_grid(*a.A);
-    const int Gu = stream_grid(a.n);
+    const int Gu = stream_grid((a.n + V - 1) / V);
     double *P1 = a.partials + kPartSpmv;
     double *P2 = a.partials + kPartUpdate;
+    // packs need every operand 16-byte aligned (a row of a 3 x n array with n
+    // odd is not): fall back to one element per thread then
+    const bool vec = aligned16(a.x) && aligned16(a.r) && aligned16(a.p) && aligned16(a.q) &&
+                     aligned16(a.dinv);
     if (ev) HNS_TRY_HIP(hipEventRecord(ev[0], s));
     spmv_dispatch<TV, TX, true>(*a.A, a.p, a.q, bc, a.bit, a.sc, P1, s);
     if (ev) HNS_TRY_HIP(hipEventRecord(ev[1], s));
-    k_update<TX, TD><<<Gu, kBlock, 0, s>>>(a.n, (TX *)a.x, (TX *)a.r, (const TX *)a.p,
-                                           (const TX *)a.q, (const TD *)a.dinv, a.sc, P1, Gs, P2,
-                                           parity);
+    if (vec)
+        k_update<TX, TD, V><<<Gu, kBlock, 0, s>>>(a.n, (TX *)a.x, (TX *)a.r, (const TX *)a.p,
+                                                  (const TX *)a.q, (const TD *)a.dinv, a.sc, P1,
+                                                  Gs, P2, parity);
+    else
+        k_update<TX, TD, 1><<<Gu, kBlock, 0, s>>>(a.n, (TX *)a.x, (TX *)a.r, (const TX *)a.p,
+                                                  (const TX *)a.q, (const TD *)a.dinv, a.sc, P1,
+                                                  Gs, P2, parity);
     if (ev) HNS_TRY_HIP(hipEventRecord(ev[2], s));
-    k_pupdate<TX, TD><<<Gu, kBlock, 0, s>>>(a.n, (TX *)a.p, (const TX *)a.r, (const TD *)a.dinv,
-                                            a.sc, P2, Gu, parity, 1);
+    if (vec)
+        k_pupdate<TX, TD, V><<<Gu, kBlock, 0, s>>>(a.n, (TX *)a.p, (const TX *)a.r,
+                                                   (const TD *)a.dinv, a.sc, P2, Gu, parity, 1);
+    else
+        k_pupdate<TX, TD, 1><<<Gu, kBlock, 0, s>>>(a.n, (TX *)a.p, (const TX *)a.r,
+                                                   (const TD *)a.dinv, a.sc, P2, Gu, parity, 1);
     if (ev) HNS_TRY_HIP(hipEventRecord(ev[3], s));
     return check_launch("cg iteration");
 }
@@ -592,7 +747,9 @@ int stream_grid(int64_t n)
 
 int spmv_grid(const DevMatrix &A)
 {
-    int64_t units = (A.fmt == HNS_FMT_SELL) ? (A.nslices + 3) / 4 : (A.n + 15) / 16;
+    int64_t units = (A.fmt == HNS_FMT_SELL)   ? (A.nslices + 3) / 4
+                    : (A.fmt == HNS_FMT_SDIA) ? (A.n + kBlock - 1) / kBlock
+                                              : (A.n + 15) / 16;
     int64_t g = units < kMaxGrid ? units : kMaxGrid;
     if (g < 1) g = 1;
     if (g >= 8) g &= ~int64_t(7);

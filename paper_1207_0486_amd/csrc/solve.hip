@@ -167,11 +167,13 @@ static hns_status enqueue_iterations(hns_operator *op, Workspace *w, Prec prec, 
                                      void *r, void *p, void *q, const void *dinv, Scalars *sc,
                                      int count, int parity0, hipStream_t s)
 {
-    const bool prof = op->profile != 0;
-    if (prof) HNS_TRY(w->ensure_events(4 * (size_t)count));
+    const int period = op->profile;
+    if (period > 0) HNS_TRY(w->ensure_events(4 * (size_t)count));
     IterArgs a{&op->A, prec, op->n, x, r, p, q, dinv, op->bc, bit, sc, w->partials};
-    for (int it = 0; it < count; ++it)
-        HNS_TRY(launch_iteration(a, (parity0 + it) & 1, s, prof ? &w->ev[4 * it] : nullptr));
+    for (int it = 0; it < count; ++it) {
+        const bool timed = period > 0 && (it % period) == 0;
+        HNS_TRY(launch_iteration(a, (parity0 + it) & 1, s, timed ? &w->ev[4 * it] : nullptr));
+    }
     return HNS_OK;
 }
 
@@ -179,9 +181,10 @@ static hns_status enqueue_iterations(hns_operator *op, Workspace *w, Prec prec, 
 // `done` iterations (those that did work) to the operator's counters.
 static hns_status account_iterations(hns_operator *op, Workspace *w, bool fp32, int done)
 {
-    if (!op->profile || done <= 0) return HNS_OK;
+    const int period = op->profile;
+    if (period <= 0 || done <= 0) return HNS_OK;
     const int base = fp32 ? 3 : 0;
-    for (int it = 0; it < done; ++it)
+    for (int it = 0; it < done; it += period)
         for (int k = 0; k < 3; ++k) {
             float ms = 0.0f;
             HNS_TRY_HIP(hipEventElapsedTime(&ms, w->ev[4 * it + k], w->ev[4 * it + k + 1]));
@@ -619,8 +622,8 @@ hns_status hns_assemble(const hns_mesh *mesh, double nu_h, double nu_v, double d
         set_error("viscosities must be finite and non-negative, dt finite");
         return HNS_ERR_INVALID;
     }
-    uint32_t fmt = flags & (HNS_FMT_CSR | HNS_FMT_SELL);
-    if (fmt == (HNS_FMT_CSR | HNS_FMT_SELL)) {
+    uint32_t fmt = flags & (HNS_FMT_CSR | HNS_FMT_SELL | HNS_FMT_SDIA);
+    if (fmt != 0 && fmt != HNS_FMT_CSR && fmt != HNS_FMT_SELL && fmt != HNS_FMT_SDIA) {
         set_error("choose one storage format");
         return HNS_ERR_INVALID;
     }
@@ -671,7 +674,11 @@ hns_status hns_profile_enable(hns_operator *op, int on)
         set_error("null operator");
         return HNS_ERR_INVALID;
     }
-    op->profile = on ? 1 : 0;
+    if (on < 0) {
+        set_error("profile period must be >= 0");
+        return HNS_ERR_INVALID;
+    }
+    op->profile = on;
     if (on)
         for (int k = 0; k < 6; ++k) {
             op->prof_ms[k] = 0.0;

@@ -15,8 +15,9 @@ import torch
 from . import _lib as L
 
 KINDS = {"poisson": L.HNS_POISSON, "helmholtz": L.HNS_HELMHOLTZ}
-FORMATS = {"auto": L.HNS_FMT_AUTO, "csr": L.HNS_FMT_CSR, "sell": L.HNS_FMT_SELL}
-FORMAT_NAMES = {L.HNS_FMT_CSR: "csr", L.HNS_FMT_SELL: "sell"}
+FORMATS = {"auto": L.HNS_FMT_AUTO, "csr": L.HNS_FMT_CSR, "sell": L.HNS_FMT_SELL,
+           "sdia": L.HNS_FMT_SDIA}
+FORMAT_NAMES = {L.HNS_FMT_CSR: "csr", L.HNS_FMT_SELL: "sell", L.HNS_FMT_SDIA: "sdia"}
 MODES = {"fp64": L.HNS_FP64, "mixed": L.HNS_MIXED}
 
 
@@ -147,8 +148,9 @@ class Operator:
         if st != L.HNS_OK:
             raise HNSError(st, "hns_set_param")
 
-    def profile(self, on: bool = True):
-        st = L.lib().hns_profile_enable(self._h, int(on))
+    def profile(self, period: int = 1):
+        """Time every `period`-th CG iteration with HIP events (0 = off)."""
+        st = L.lib().hns_profile_enable(self._h, int(period))
         if st != L.HNS_OK:
             raise HNSError(st, "hns_profile_enable")
 

@@ -55,9 +55,10 @@ def assert_parity(info, x_gpu, A, b, dirichlet=None, singular=False, weights=Non
 
 
 BOX = basin.configs.BOX_16x16x4
+FORMATS = ["csr", "sell", "sdia"]
 
 
-@pytest.mark.parametrize("fmt", ["csr", "sell"])
+@pytest.mark.parametrize("fmt", FORMATS)
 def test_box16_poisson_fp64_matches_oracle(dev, fmt):
     """Plain method, small: Dirichlet on Gamma_b, N(0,1) RHS projected to zero mean."""
     from paper_1207_0486_amd.hns import Operator
@@ -82,7 +83,7 @@ def ragged_basin():
     return basin.basin_mesh(24, 20, 6, seed=4)
 
 
-@pytest.mark.parametrize("fmt", ["csr", "sell"])
+@pytest.mark.parametrize("fmt", FORMATS)
 @pytest.mark.parametrize("bit", [0, 1, 2])
 def test_helmholtz_masks_match_oracle(dev, ragged_basin, fmt, bit):
     from paper_1207_0486_amd.hns import Operator
@@ -97,7 +98,7 @@ def test_helmholtz_masks_match_oracle(dev, ragged_basin, fmt, bit):
     assert_parity(info, xh, A, b, dirichlet=d)
 
 
-@pytest.mark.parametrize("fmt", ["csr", "sell"])
+@pytest.mark.parametrize("fmt", FORMATS)
 def test_neumann_poisson_matches_oracle(dev, ragged_basin, fmt):
     from paper_1207_0486_amd.hns import Operator
     m = ragged_basin
@@ -206,7 +207,7 @@ def test_apply_matches_oracle_product(dev, ragged_basin):
     m = ragged_basin
     x = np.random.default_rng(5).standard_normal(m.n)
     A = oracle.helmholtz(m, 1e3, 1e-2, 3600.0)
-    for fmt in ("csr", "sell"):
+    for fmt in FORMATS:
         op = Operator(m, 1e3, 1e-2, 3600.0, kind="helmholtz", fmt=fmt)
         y = op.apply(_gpu(x, dev)).cpu().numpy()
         ref = A.matvec(x)
@@ -237,4 +238,34 @@ def test_footprint(dev, ragged_basin):
     f4 = op.footprint(4, "fp64", include_operator=False)
     assert f1 >= 3 * 8 * op.n and f4 == 4 * f1
     assert op.footprint(1, "mixed", False) > f1
-    assert op.footprint(1, "fp64", True) > f1 + 12 * op.nnz
+    # at least the symmetric half of the values (8 bytes each)
+    assert op.footprint(1, "fp64", True) > f1 + 4 * op.nnz
+
+
+def test_unstructured_numbering_falls_back_from_diagonal_storage(dev, ragged_basin):
+    """A random node numbering scatters the offsets j - i: the automatic format
+    is then not the diagonal one, and the solve still matches the oracle."""
+    import copy
+    from paper_1207_0486_amd.hns import Operator
+    m = copy.deepcopy(ragged_basin)
+    perm = np.random.default_rng(9).permutation(m.n)
+    inv = np.empty_like(perm)
+    inv[perm] = np.arange(m.n)
+    m.xyz = m.xyz[perm]
+    m.bc = m.bc[perm]
+    m.tets = inv[m.tets].astype(np.int32)
+    m.surf_tris = inv[m.surf_tris].astype(np.int32)
+    op = Operator(m, 1e3, 1e-2, 3600.0, kind="helmholtz")
+    assert op.format in ("sell", "csr")
+    with pytest.raises(Exception):
+        Operator(m, 1e3, 1e-2, 3600.0, kind="helmholtz", fmt="sdia")
+    d = (m.bc & 1) == 1
+    b = basin.normal_rhs(m.n, 80, dirichlet=d)
+    x, info = op.solve(_gpu(b, dev), tol=1e-10, mask_bit=0)
+    assert_parity(info, x.cpu().numpy(), oracle.helmholtz(m, 1e3, 1e-2, 3600.0), b, dirichlet=d)
+
+
+def test_auto_format_is_diagonal_on_structured_mesh(dev, ragged_basin):
+    from paper_1207_0486_amd.hns import Operator
+    op = Operator(ragged_basin, 1e3, 1e-2, kind="poisson")
+    assert op.format == "sdia"
