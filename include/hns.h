@@ -136,18 +136,34 @@ hns_status hns_solve(hns_operator *op, int mask_bit, const double *b_dev, double
                      hns_solve_info *info);
 
 /* Solve k independent systems A x_j = b_j sharing one read of A per iteration
- * (multi-right-hand-side CG; each column keeps its own CG scalars and stops
- * on its own).  B_dev and X_dev are n x k row-major (the k values of one node
- * are contiguous).  mask_bits[j] is the Dirichlet bit of column j (-1 = none).
- * infos receives k entries.  HNS_MIXED runs FP32 inner iterations inside FP64
- * refinement.  The return value is the worst column status. */
+ * (multi-right-hand-side CG; each column keeps its own CG scalars, reduced
+ * deterministically, and stops on its own).  B_dev and X_dev are n x k
+ * row-major (the k values of one node are contiguous), 1 <= k <= 1024.
+ * mask_bits[j] is the Dirichlet bit of column j (-1 = none; with
+ * HNS_POISSON a pure-Neumann column, projected and normalised as in
+ * hns_solve).  X holds the initial guesses.  infos receives k entries
+ * (outer_iterations = FP64 residual evaluations of the whole batch).
+ * HNS_MIXED runs the FP32 recurrences with per-column FP64 residual
+ * replacement as in hns_solve.  With "use_graph" = 1 the chunks of
+ * "check_every" iterations are captured once into a HIP graph and replayed.
+ * The return value is the worst column status (negative first). */
 hns_status hns_solve_batched(hns_operator *op, int k, const int *mask_bits,
                              const double *B_dev, double *X_dev, double tol, int max_iter,
                              uint32_t mode, void *stream, hns_solve_info *infos);
 
+/* Time the multi-right-hand-side product kernel of `hns_solve_batched` for
+ * k columns in `mode` with 1, 2 and 4 consecutive columns per thread, on this
+ * operator; times_us[0..2] receive the microseconds per launch (-1 where k is
+ * not a multiple of the width) and *best_vec the fastest width, which later
+ * batched solves of k columns in that mode use.  hns_solve_batched runs this
+ * tuning itself the first time it meets (k, mode) unless "bspmm_vec" is set. */
+hns_status hns_tune_batched(hns_operator *op, int k, uint32_t mode, void *stream,
+                            double *times_us, int *best_vec);
+
 /* Device bytes a solve of k right-hand sides in `mode` needs beyond the
- * resident operator (workspace), plus the operator's own bytes when
- * include_operator != 0.  Used for admission by HBM footprint. */
+ * resident operator (workspace: k = 1 for hns_solve, k > 1 for
+ * hns_solve_batched), plus the operator's own bytes when include_operator
+ * != 0.  Used for admission by HBM footprint. */
 size_t hns_footprint_bytes(const hns_operator *op, int k, uint32_t mode, int include_operator);
 
 /* Basic operator facts. */
@@ -169,7 +185,10 @@ uint32_t hns_operator_format(const hns_operator *op);
  *                  2 FP32 matrix and diagonal with FP64 vectors, with the same
  *                    FP64 residual replacement as 0
  *   "replace_drop" residual drop between FP64 replacements (default 0.1)
- *   "use_graph"    1 = replay captured HIP graphs for iteration chunks */
+ *   "use_graph"    1 = replay captured HIP graphs for the iteration chunks of
+ *                  hns_solve_batched (default 0)
+ *   "bspmm_vec"    columns per thread of the batched kernels: 0 = autotune
+ *                  (default), or 1, 2, 4 */
 hns_status hns_set_param(hns_operator *op, const char *name, double value);
 
 /* y = A x on the device (FP64), with the rows of Dirichlet set mask_bit

@@ -50,6 +50,8 @@ _SIGNATURES = {
     "hns_solve_batched": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int), C.c_void_p,
                                     C.c_void_p, C.c_double, C.c_int, C.c_uint32, C.c_void_p,
                                     C.POINTER(hns_solve_info)]),
+    "hns_tune_batched": (C.c_int, [C.c_void_p, C.c_int, C.c_uint32, C.c_void_p,
+                                   C.POINTER(C.c_double), C.POINTER(C.c_int)]),
     "hns_footprint_bytes": (C.c_size_t, [C.c_void_p, C.c_int, C.c_uint32, C.c_int]),
     "hns_operator_n": (C.c_int64, [C.c_void_p]),
     "hns_operator_nnz": (C.c_int64, [C.c_void_p]),

@@ -1,0 +1,1108 @@
+// Multi-right-hand-side Jacobi-PCG: k independent CG recurrences that share
+// every read of the operator (the three velocity components of a step and
+// many wind scenarios solved at once).
+//
+// Vectors are n x k row-major (the k values of node i are contiguous).  A
+// thread owns V consecutive columns of one row (V is the autotuned pack
+// width) and, because the grid's thread count times V is a multiple of k,
+// always the same V columns: its per-column partial sums need no atomics and
+// are reduced deterministically (threads of a block in thread order, then
+// blocks in block order by one small reduction kernel per step).  One
+// iteration is five launches:
+//   spmm      Q = mask_j(A P) per column, per-block partials of p_j^T q_j
+//   reduce    gamma_j, alpha_j = rho_j / gamma_j (active columns)
+//   update    x_j += alpha_j p_j, r_j -= alpha_j q_j, partials of r^T z, r^T r
+//   reduce    rho_j', rr_j, beta_j, stop flags
+//   pupdate   p_j = z_j + beta_j p_j (columns still active)
+// Columns stop independently; a chunk of iterations is captured once into a
+// HIP graph and replayed.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+#include "kernels.h"
+
+namespace hns {
+
+// Per-column CG state (device)
+struct BCol {
+    double rho, alpha, beta, gamma;
+    double rr;        // recursive r^T r
+    double ref;       // reference r^T r of the current recurrence segment
+    double thr2;      // segment stops when rr <= thr2 * ref
+    double bb;        // |b|^2 (projected for pure-Neumann columns)
+    double tol2;      // tol^2
+    double rr_true;   // last FP64 true residual r^T r
+    double sumb;      // sum of the free entries of b
+    double mean_b;    // mean removed from b (pure-Neumann columns)
+    double mean_r;    // mean of the last FP64 residual (pure-Neumann projection)
+    double wx;        // sum lumped_i x_i
+    double nonfinite;
+    int32_t stop;     // 0 active, 1 segment threshold reached, 2 breakdown, 3 b = 0, 4 done
+    int32_t iter;     // iterations executed
+    int32_t bit;      // Dirichlet bit (-1 none)
+    int32_t singular; // pure-Neumann column
+    int32_t mark;     // selects the column for the next one-off kernel
+    int32_t fresh;    // next direction restarts from z (no beta)
+};
+
+namespace {
+
+enum : int32_t { ACTIVE = 0, THRESH = 1, BREAK = 2, ZERO = 3, DONE = 4, FAILED = 5 };
+
+#define PACK_LOOP(t, np)                                                       \
+    for (int64_t t = blockIdx.x * (int64_t)kBlock + threadIdx.x; t < (np); \
+         t += (int64_t)gridDim.x * kBlock)
+
+__device__ __forceinline__ bool masked(const uint8_t *bc, int bit, int64_t i)
+{
+    return bc != nullptr && bit >= 0 && ((bc[i] >> bit) & 1u);
+}
+
+// Reduce the per-thread values acc[NV][V] of a block to per-column partials
+// part[k][b * K + c] for the K columns; thread t owns columns j0(t) .. j0(t)+V-1
+// with j0(t) = ((b * kBlock + t) * V) mod K.
+template <int NV, int V>
+__device__ void block_column_partials(double (&acc)[NV][V], int K, double *part)
+{
+    __shared__ double s[NV][V][kBlock];
+#pragma unroll
+    for (int k = 0; k < NV; ++k)
+#pragma unroll
+        for (int v = 0; v < V; ++v) s[k][v][threadIdx.x] = acc[k][v];
+    __syncthreads();
+    const int P = K / V;  // column groups
+    const int64_t b = blockIdx.x;
+    for (int c = threadIdx.x; c < K; c += kBlock) {
+        const int g = c / V, v = c % V;
+        int t0 = (int)(((int64_t)g - b * kBlock) % P);
+        if (t0 < 0) t0 += P;
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            double sum = 0.0;
+            for (int t = t0; t < kBlock; t += P) sum += s[k][v][t];
+            part[(int64_t)k * gridDim.x * K + b * K + c] = sum;
+        }
+    }
+}
+
+// Sum of one column's partials over the G blocks (block order); result valid
+// in thread 0.
+__device__ double column_total(const double *part, int G, int K, int c)
+{
+    __shared__ double lds[kBlock / 64];
+    double t = 0.0;
+    for (int b = threadIdx.x; b < G; b += kBlock) t += part[(int64_t)b * K + c];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = t;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < kBlock / 64; ++w) s += lds[w];
+    __syncthreads();
+    return s;
+}
+
+template <typename T, int W>
+struct alignas(sizeof(T) * W) BPack {
+    T v[W];
+};
+
+template <int W, typename T>
+__device__ __forceinline__ BPack<T, W> bld(const T *p, int64_t e)
+{
+    return *reinterpret_cast<const BPack<T, W> *>(p + e);
+}
+
+template <int W, typename T>
+__device__ __forceinline__ void bst(T *p, int64_t e, const BPack<T, W> &v)
+{
+    *reinterpret_cast<BPack<T, W> *>(p + e) = v;
+}
+
+struct BOffsets {
+    int32_t o[kMaxDiag];
+};
+
+// ---------------------------------------------------------------------------
+// SpMM: Q = mask_j(A P), optional per-column partials of p_j^T q_j
+// ---------------------------------------------------------------------------
+template <typename TV, typename TX, int V, bool DOT, int M>
+__global__ __launch_bounds__(kBlock) void k_bspmm_sdia(int64_t n, int K, BOffsets offs,
+                                                       const TV *__restrict__ dia,
+                                                       const TX *__restrict__ P,
+                                                       TX *__restrict__ Q,
+                                                       const uint8_t *__restrict__ bc,
+                                                       const BCol *__restrict__ cols,
+                                                       double *__restrict__ part)
+{
+    double acc[1][V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) acc[0][v] = 0.0;
+    const int64_t np = n * K / V;
+    PACK_LOOP(t, np)
+    {
+        const int64_t e = t * V;
+        const int64_t i = e / K;
+        const auto pi = bld<V>(P, e);
+        const TX d = (TX)dia[i];
+        TX s[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) s[v] = d * pi.v[v];
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            const int64_t o = offs.o[k];
+            const TV *u = dia + (int64_t)(k + 1) * n;
+            const bool hu = i + o < n, hl = i >= o;
+            const int64_t iu = hu ? i + o : i, il = hl ? i - o : i;
+            const TX cu = hu ? (TX)u[i] : (TX)0;
+            const TX cl = hl ? (TX)u[il] : (TX)0;
+            const auto pu = bld<V>(P, iu * K + (e - i * K));
+            const auto pl = bld<V>(P, il * K + (e - i * K));
+#pragma unroll
+            for (int v = 0; v < V; ++v) s[v] += cu * pu.v[v] + cl * pl.v[v];
+        }
+        BPack<TX, V> out;
+        const int j0 = (int)(e - i * K);
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            out.v[v] = masked(bc, cols[j0 + v].bit, i) ? (TX)0 : s[v];
+            if constexpr (DOT) acc[0][v] += (double)pi.v[v] * (double)out.v[v];
+        }
+        bst<V>(Q, e, out);
+    }
+    if constexpr (DOT) block_column_partials<1, V>(acc, K, part);
+}
+
+template <typename TV, typename TX, int V, bool DOT>
+__global__ __launch_bounds__(kBlock) void k_bspmm_csr(int64_t n, int K,
+                                                      const int32_t *__restrict__ rowptr,
+                                                      const int32_t *__restrict__ col,
+                                                      const TV *__restrict__ val,
+                                                      const TX *__restrict__ P,
+                                                      TX *__restrict__ Q,
+                                                      const uint8_t *__restrict__ bc,
+                                                      const BCol *__restrict__ cols,
+                                                      double *__restrict__ part)
+{
+    double acc[1][V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) acc[0][v] = 0.0;
+    const int64_t np = n * K / V;
+    PACK_LOOP(t, np)
+    {
+        const int64_t e = t * V;
+        const int64_t i = e / K;
+        const int j0 = (int)(e - i * K);
+        TX s[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) s[v] = 0;
+        for (int32_t k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+            const TX a = (TX)val[k];
+            const auto pc = bld<V>(P, (int64_t)col[k] * K + j0);
+#pragma unroll
+            for (int v = 0; v < V; ++v) s[v] += a * pc.v[v];
+        }
+        const auto pi = bld<V>(P, e);
+        BPack<TX, V> out;
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            out.v[v] = masked(bc, cols[j0 + v].bit, i) ? (TX)0 : s[v];
+            if constexpr (DOT) acc[0][v] += (double)pi.v[v] * (double)out.v[v];
+        }
+        bst<V>(Q, e, out);
+    }
+    if constexpr (DOT) block_column_partials<1, V>(acc, K, part);
+}
+
+template <typename TV, typename TX, int V, bool DOT>
+__global__ __launch_bounds__(kBlock) void k_bspmm_sell(int64_t n, int K,
+                                                       const int32_t *__restrict__ sptr,
+                                                       const int32_t *__restrict__ col,
+                                                       const TV *__restrict__ val,
+                                                       const TX *__restrict__ P,
+                                                       TX *__restrict__ Q,
+                                                       const uint8_t *__restrict__ bc,
+                                                       const BCol *__restrict__ cols,
+                                                       double *__restrict__ part)
+{
+    double acc[1][V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) acc[0][v] = 0.0;
+    const int64_t np = n * K / V;
+    PACK_LOOP(t, np)
+    {
+        const int64_t e = t * V;
+        const int64_t i = e / K;
+        const int j0 = (int)(e - i * K);
+        const int64_t sl = i >> 6;
+        const int lane = (int)(i & 63);
+        const int32_t beg = sptr[sl];
+        const int32_t w = (sptr[sl + 1] - beg) >> 6;
+        TX s[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) s[v] = 0;
+        for (int jj = 0; jj < w; ++jj) {
+            const int32_t k = beg + jj * 64 + lane;
+            const TX a = (TX)val[k];
+            const auto pc = bld<V>(P, (int64_t)col[k] * K + j0);
+#pragma unroll
+            for (int v = 0; v < V; ++v) s[v] += a * pc.v[v];
+        }
+        const auto pi = bld<V>(P, e);
+        BPack<TX, V> out;
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            out.v[v] = masked(bc, cols[j0 + v].bit, i) ? (TX)0 : s[v];
+            if constexpr (DOT) acc[0][v] += (double)pi.v[v] * (double)out.v[v];
+        }
+        bst<V>(Q, e, out);
+    }
+    if constexpr (DOT) block_column_partials<1, V>(acc, K, part);
+}
+
+// ---------------------------------------------------------------------------
+// Per-column reductions (one block per column)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_bred_gamma(int K, const double *__restrict__ part,
+                                                       int G, BCol *__restrict__ cols)
+{
+    const int c = blockIdx.x;
+    const double g = column_total(part, G, K, c);
+    if (threadIdx.x == 0) {
+        BCol &s = cols[c];
+        if (s.stop != ACTIVE) return;
+        s.gamma = g;
+        if (!(g > 0.0) || !isfinite(g)) {
+            s.stop = BREAK;
+            s.alpha = 0.0;
+        } else {
+            s.alpha = s.rho / g;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_bred_rho(int K, const double *__restrict__ part,
+                                                     int G, BCol *__restrict__ cols)
+{
+    const int c = blockIdx.x;
+    const double rz = column_total(part, G, K, c);
+    const double rr = column_total(part + (int64_t)G * K, G, K, c);
+    if (threadIdx.x == 0) {
+        BCol &s = cols[c];
+        s.mark = 0;
+        s.fresh = 0;  // only the direction that opens a segment ignores beta
+        if (s.stop != ACTIVE) return;
+        s.iter += 1;
+        s.rr = rr;
+        if (!isfinite(rz) || !isfinite(rr)) {
+            s.stop = BREAK;
+            return;
+        }
+        s.beta = rz / s.rho;
+        s.rho = rz;
+        if (rr <= s.thr2 * s.ref)
+            s.stop = THRESH;
+        else
+            s.mark = 1;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Vector updates
+// ---------------------------------------------------------------------------
+template <typename TX, typename TD, int V>
+__global__ __launch_bounds__(kBlock) void k_bupdate(int64_t n, int K, TX *__restrict__ X,
+                                                    TX *__restrict__ R,
+                                                    const TX *__restrict__ P,
+                                                    const TX *__restrict__ Q,
+                                                    const TD *__restrict__ dinv,
+                                                    const BCol *__restrict__ cols,
+                                                    double *__restrict__ part)
+{
+    double acc[2][V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) acc[0][v] = acc[1][v] = 0.0;
+    const int64_t np = n * K / V;
+    PACK_LOOP(t, np)
+    {
+        const int64_t e = t * V;
+        const int64_t i = e / K;
+        const int j0 = (int)(e - i * K);
+        auto xv = bld<V>(X, e);
+        auto rv = bld<V>(R, e);
+        const auto pv = bld<V>(P, e);
+        const auto qv = bld<V>(Q, e);
+        const TX d = (TX)dinv[i];
+        bool any = false;
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const BCol &s = cols[j0 + v];
+            if (s.stop != ACTIVE) continue;
+            any = true;
+            const TX a = (TX)s.alpha;
+            xv.v[v] = xv.v[v] + a * pv.v[v];
+            rv.v[v] = rv.v[v] - a * qv.v[v];
+            const TX z = d * rv.v[v];
+            acc[0][v] += (double)rv.v[v] * (double)z;
+            acc[1][v] += (double)rv.v[v] * (double)rv.v[v];
+        }
+        if (any) {
+            bst<V>(X, e, xv);
+            bst<V>(R, e, rv);
+        }
+    }
+    block_column_partials<2, V>(acc, K, part);
+}
+
+// p = z + beta p for marked columns (fresh columns: p = z)
+template <typename TX, typename TD, int V>
+__global__ __launch_bounds__(kBlock) void k_bpupdate(int64_t n, int K, TX *__restrict__ P,
+                                                     const TX *__restrict__ R,
+                                                     const TD *__restrict__ dinv,
+                                                     const BCol *__restrict__ cols)
+{
+    const int64_t np = n * K / V;
+    PACK_LOOP(t, np)
+    {
+        const int64_t e = t * V;
+        const int64_t i = e / K;
+        const int j0 = (int)(e - i * K);
+        auto pv = bld<V>(P, e);
+        const auto rv = bld<V>(R, e);
+        const TX d = (TX)dinv[i];
+        bool any = false;
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const BCol &s = cols[j0 + v];
+            if (!s.mark) continue;
+            any = true;
+            pv.v[v] = s.fresh ? d * rv.v[v] : d * rv.v[v] + (TX)s.beta * pv.v[v];
+        }
+        if (any) bst<V>(P, e, pv);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// One-off kernels (elementwise over the n x K block, one element per thread)
+// ---------------------------------------------------------------------------
+#define ELEM_LOOP(e, ne)                                                       \
+    for (int64_t e = blockIdx.x * (int64_t)kBlock + threadIdx.x; e < (ne); \
+         e += (int64_t)gridDim.x * kBlock)
+
+// sum, sum of squares and non-finite count of the free entries of b
+__global__ __launch_bounds__(kBlock) void k_bbstats(int64_t n, int K, const double *__restrict__ B,
+                                                    const uint8_t *__restrict__ bc,
+                                                    const BCol *__restrict__ cols,
+                                                    double *__restrict__ part)
+{
+    double acc[3][1] = {{0.0}, {0.0}, {0.0}};
+    ELEM_LOOP(e, n * K)
+    {
+        const int64_t i = e / K;
+        const int j = (int)(e - i * K);
+        double b = masked(bc, cols[j].bit, i) ? 0.0 : B[e];
+        if (!isfinite(b)) {
+            acc[2][0] += 1.0;
+            b = 0.0;
+        }
+        acc[0][0] += b;
+        acc[1][0] += b * b;
+    }
+    block_column_partials<3, 1>(acc, K, part);
+}
+
+__global__ __launch_bounds__(kBlock) void k_bred_bstats(int64_t n, int K,
+                                                        const double *__restrict__ part, int G,
+                                                        BCol *__restrict__ cols)
+{
+    const int c = blockIdx.x;
+    const double s = column_total(part, G, K, c);
+    const double s2 = column_total(part + (int64_t)G * K, G, K, c);
+    const double bad = column_total(part + 2 * (int64_t)G * K, G, K, c);
+    if (threadIdx.x == 0) {
+        BCol &b = cols[c];
+        b.sumb = s;
+        b.nonfinite = bad;
+        b.mean_b = b.singular ? s / (double)n : 0.0;
+        (void)s2;
+    }
+}
+
+// R64 = mask(b - mean_b - Q64) for marked columns; partials of sum r, sum
+// (b - mean_b)^2, sum r^2
+__global__ __launch_bounds__(kBlock) void k_bresidual(int64_t n, int K,
+                                                      const double *__restrict__ B,
+                                                      const double *__restrict__ Q,
+                                                      double *__restrict__ R,
+                                                      const uint8_t *__restrict__ bc,
+                                                      const BCol *__restrict__ cols,
+                                                      double *__restrict__ part)
+{
+    double acc[3][1] = {{0.0}, {0.0}, {0.0}};
+    ELEM_LOOP(e, n * K)
+    {
+        const int64_t i = e / K;
+        const int j = (int)(e - i * K);
+        const BCol &s = cols[j];
+        if (!s.mark) continue;
+        double b = B[e] - s.mean_b;
+        double r = b - Q[e];
+        if (masked(bc, s.bit, i)) b = r = 0.0;
+        R[e] = r;
+        acc[0][0] += r;
+        acc[1][0] += b * b;
+        acc[2][0] += r * r;
+    }
+    block_column_partials<3, 1>(acc, K, part);
+}
+
+// true residual statistics; decide per marked column: done, or continue
+__global__ __launch_bounds__(kBlock) void k_bred_residual(int64_t n, int K,
+                                                          const double *__restrict__ part, int G,
+                                                          BCol *__restrict__ cols, double drop2,
+                                                          int first)
+{
+    const int c = blockIdx.x;
+    const double sr = column_total(part, G, K, c);
+    const double sbb = column_total(part + (int64_t)G * K, G, K, c);
+    const double srr = column_total(part + 2 * (int64_t)G * K, G, K, c);
+    if (threadIdx.x == 0) {
+        BCol &s = cols[c];
+        if (!s.mark) return;
+        const double mean = s.singular ? sr / (double)n : 0.0;
+        const double rr = fmax(srr - (double)n * mean * mean, 0.0);
+        s.mean_r = mean;
+        s.rr_true = rr;
+        if (first) {
+            s.bb = sbb;
+            if (!(sbb > 0.0)) {
+                s.stop = ZERO;
+                s.mark = 0;
+                return;
+            }
+        }
+        if (rr <= s.tol2 * s.bb) {
+            s.stop = DONE;
+            s.mark = 0;
+            return;
+        }
+        if (s.stop == FAILED) {
+            s.mark = 0;
+            return;
+        }
+        // next segment: stop once the recursive residual fell by drop (or at tol)
+        s.ref = rr;
+        s.thr2 = fmax(drop2, s.tol2 * s.bb / rr);
+        s.fresh = (first || s.stop == BREAK || drop2 == 0.0) ? 1 : 0;
+    }
+}
+
+// Working residual of marked columns from the FP64 one (projected for
+// pure-Neumann columns): r = (TX)(r64 - mean_r); partials of r^T z, r^T r.
+template <typename TX, typename TD>
+__global__ __launch_bounds__(kBlock) void k_bfrom64(int64_t n, int K,
+                                                    const double *__restrict__ R64,
+                                                    TX *__restrict__ R,
+                                                    const TD *__restrict__ dinv,
+                                                    const BCol *__restrict__ cols,
+                                                    double *__restrict__ part)
+{
+    double acc[2][1] = {{0.0}, {0.0}};
+    ELEM_LOOP(e, n * K)
+    {
+        const int64_t i = e / K;
+        const int j = (int)(e - i * K);
+        const BCol &s = cols[j];
+        if (!s.mark) continue;
+        const TX r = (TX)(R64[e] - s.mean_r);
+        R[e] = r;
+        const TX z = (TX)dinv[i] * r;
+        acc[0][0] += (double)r * (double)z;
+        acc[1][0] += (double)r * (double)r;
+    }
+    block_column_partials<2, 1>(acc, K, part);
+}
+
+// rho of the new segment; beta against the old rho unless fresh
+__global__ __launch_bounds__(kBlock) void k_bred_restart(int K, const double *__restrict__ part,
+                                                         int G, BCol *__restrict__ cols)
+{
+    const int c = blockIdx.x;
+    const double rz = column_total(part, G, K, c);
+    const double rr = column_total(part + (int64_t)G * K, G, K, c);
+    if (threadIdx.x == 0) {
+        BCol &s = cols[c];
+        if (!s.mark) return;
+        s.beta = s.fresh ? 0.0 : rz / s.rho;
+        s.rho = rz;
+        s.rr = rr;
+        s.stop = (isfinite(rz) && rz > 0.0) ? ACTIVE : BREAK;
+        if (s.stop != ACTIVE) s.mark = 0;
+    }
+}
+
+// x64 += x32, x32 = 0 for marked columns
+__global__ __launch_bounds__(kBlock) void k_baccumulate(int64_t n, int K, double *__restrict__ X,
+                                                        float *__restrict__ X32,
+                                                        const BCol *__restrict__ cols)
+{
+    ELEM_LOOP(e, n * K)
+    {
+        const int j = (int)(e % K);
+        if (!cols[j].mark) continue;
+        X[e] += (double)X32[e];
+        X32[e] = 0.0f;
+    }
+}
+
+// Mark columns: mode 0 those with stop in {THRESH, BREAK}; mode 1 all
+// columns; mode 2 the still active ones
+__global__ void k_bmark(int K, BCol *__restrict__ cols, int mode)
+{
+    for (int c = threadIdx.x; c < K; c += blockDim.x) {
+        BCol &s = cols[c];
+        s.mark = mode == 1   ? 1
+                 : mode == 2 ? (s.stop == ACTIVE ? 1 : 0)
+                             : ((s.stop == THRESH || s.stop == BREAK) ? 1 : 0);
+    }
+}
+
+// x = 0 on Dirichlet nodes (all entries of zero columns); x32 = 0
+__global__ __launch_bounds__(kBlock) void k_bprepare(int64_t n, int K, double *__restrict__ X,
+                                                     float *__restrict__ X32,
+                                                     const uint8_t *__restrict__ bc,
+                                                     const BCol *__restrict__ cols)
+{
+    ELEM_LOOP(e, n * K)
+    {
+        const int64_t i = e / K;
+        const BCol &s = cols[e - i * K];
+        if (s.stop == ZERO || masked(bc, s.bit, i)) X[e] = 0.0;
+        if (X32) X32[e] = 0.0f;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_bwdot(int64_t n, int K, const double *__restrict__ X,
+                                                  const double *__restrict__ w,
+                                                  double *__restrict__ part)
+{
+    double acc[1][1] = {{0.0}};
+    ELEM_LOOP(e, n * K) acc[0][0] += w[e / K] * X[e];
+    block_column_partials<1, 1>(acc, K, part);
+}
+
+__global__ __launch_bounds__(kBlock) void k_bred_wdot(int K, const double *__restrict__ part,
+                                                      int G, BCol *__restrict__ cols)
+{
+    const int c = blockIdx.x;
+    const double s = column_total(part, G, K, c);
+    if (threadIdx.x == 0) cols[c].wx = s;
+}
+
+__global__ __launch_bounds__(kBlock) void k_bshift(int64_t n, int K, double *__restrict__ X,
+                                                   const BCol *__restrict__ cols, double wsum)
+{
+    ELEM_LOOP(e, n * K)
+    {
+        const BCol &s = cols[e % K];
+        if (s.singular && (s.stop == DONE || s.stop == ACTIVE || s.stop == THRESH))
+            X[e] -= s.wx / wsum;
+    }
+}
+
+hns_status bcheck(const char *what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        set_error("launch of %s failed: %s", what, hipGetErrorString(e));
+        return HNS_ERR_HIP;
+    }
+    return HNS_OK;
+}
+
+// grid (multiple of K / gcd) so that every thread keeps the same columns
+int bgrid(int64_t packs, int K, int V)
+{
+    const int64_t tpg = (int64_t)kBlock * V;              // elements per block per sweep
+    const int64_t g0 = K / std::gcd((int64_t)K, tpg);     // blocks per period of columns
+    int64_t g = (packs + kBlock - 1) / kBlock;
+    const int64_t cap = std::max<int64_t>(g0, (kMaxGrid / g0) * g0);
+    g = std::min<int64_t>(g, cap);
+    g = std::max<int64_t>(((g + g0 - 1) / g0) * g0, g0);
+    return (int)g;
+}
+
+}  // namespace
+
+// ===========================================================================
+// Host side
+// ===========================================================================
+struct BWorkspace {
+    int64_t n = 0;
+    int K = 0;
+    bool mixed = false;
+    void *block = nullptr;
+    double *R64 = nullptr, *P64 = nullptr, *Q64 = nullptr;
+    float *X32 = nullptr, *R32 = nullptr, *P32 = nullptr, *Q32 = nullptr;
+    double *part = nullptr;  // 3 x kMaxGrid x K
+    BCol *cols = nullptr;
+    BCol *host = nullptr;    // pinned mirror
+    // captured iteration chunks: [mixed][V]
+    hipGraphExec_t graph = nullptr;
+    int graph_chunk = 0, graph_V = 0;
+    const void *graph_X = nullptr;
+    hipStream_t cap_stream = nullptr;  // private stream the chunks are captured on
+
+    static size_t bytes_for(int64_t n, int K, bool mixed)
+    {
+        auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+        const size_t nk = (size_t)n * K;
+        size_t b = 3 * al(nk * 8);
+        if (mixed) b += 4 * al(nk * 4);
+        b += al(3 * (size_t)kMaxGrid * K * 8) + al((size_t)K * sizeof(BCol));
+        return b;
+    }
+
+    hns_status allocate(int64_t n_, int K_, bool mixed_)
+    {
+        n = n_;
+        K = K_;
+        mixed = mixed_;
+        auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+        hipError_t e = hipMalloc(&block, bytes_for(n, K, mixed));
+        if (e != hipSuccess) {
+            block = nullptr;
+            set_error("batched workspace of %zu bytes: %s", bytes_for(n, K, mixed),
+                      hipGetErrorString(e));
+            return e == hipErrorOutOfMemory ? HNS_ERR_OOM : HNS_ERR_HIP;
+        }
+        const size_t nk = (size_t)n * K;
+        char *c = (char *)block;
+        R64 = (double *)c, c += al(nk * 8);
+        P64 = (double *)c, c += al(nk * 8);
+        Q64 = (double *)c, c += al(nk * 8);
+        if (mixed) {
+            X32 = (float *)c, c += al(nk * 4);
+            R32 = (float *)c, c += al(nk * 4);
+            P32 = (float *)c, c += al(nk * 4);
+            Q32 = (float *)c, c += al(nk * 4);
+        }
+        part = (double *)c, c += al(3 * (size_t)kMaxGrid * K * 8);
+        cols = (BCol *)c;
+        HNS_TRY_HIP(hipHostMalloc((void **)&host, K * sizeof(BCol), hipHostMallocDefault));
+        return HNS_OK;
+    }
+
+    void drop_graph()
+    {
+        if (graph) (void)hipGraphExecDestroy(graph);
+        graph = nullptr;
+        graph_chunk = 0;
+    }
+
+    ~BWorkspace()
+    {
+        drop_graph();
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
+        if (block) (void)hipFree(block);
+        if (host) (void)hipHostFree(host);
+    }
+};
+
+void destroy_bworkspace(BWorkspace *w) { delete w; }
+
+hns_status create_bworkspace(int64_t n, int K, bool mixed, BWorkspace **out)
+{
+    BWorkspace *w = new BWorkspace();
+    hns_status st = w->allocate(n, K, mixed);
+    if (st != HNS_OK) {
+        delete w;
+        *out = nullptr;
+        return st;
+    }
+    *out = w;
+    return HNS_OK;
+}
+
+size_t bworkspace_bytes(int64_t n, int K, bool mixed) { return BWorkspace::bytes_for(n, K, mixed); }
+
+int bworkspace_k(const BWorkspace *w) { return w->K; }
+bool bworkspace_mixed(const BWorkspace *w) { return w->mixed; }
+
+namespace {
+
+struct BCtx {
+    hns_operator *op;
+    BWorkspace *w;
+    int K;
+    int V;           // pack width of the iteration kernels
+    const double *B;
+    double *X;
+    hipStream_t s;
+    bool mixed;
+};
+
+hns_status pull(BCtx &c)
+{
+    HNS_TRY_HIP(hipMemcpyAsync(c.w->host, c.w->cols, c.K * sizeof(BCol), hipMemcpyDeviceToHost,
+                               c.s));
+    HNS_TRY_HIP(hipStreamSynchronize(c.s));
+    return HNS_OK;
+}
+
+template <typename TV, typename TX, int V, bool DOT>
+void bspmm_launch(const DevMatrix &A, int K, const TV *vals, const void *P, void *Q,
+                  const uint8_t *bc, const BCol *cols, double *part, hipStream_t s, int G)
+{
+    if (A.fmt == HNS_FMT_SDIA) {
+        BOffsets o;
+        for (int k = 0; k < kMaxDiag; ++k) o.o[k] = k < A.ndiag ? A.off[k] : 0;
+#define HNS_SDIA_CASE(M)                                                                     \
+    case M:                                                                                 \
+        k_bspmm_sdia<TV, TX, V, DOT, M><<<G, kBlock, 0, s>>>(A.n, K, o, vals, (const TX *)P, \
+                                                             (TX *)Q, bc, cols, part);       \
+        break;
+        switch (A.ndiag) {
+            HNS_SDIA_CASE(1) HNS_SDIA_CASE(2) HNS_SDIA_CASE(3) HNS_SDIA_CASE(4)
+            HNS_SDIA_CASE(5) HNS_SDIA_CASE(6) HNS_SDIA_CASE(7) HNS_SDIA_CASE(8)
+            HNS_SDIA_CASE(9) HNS_SDIA_CASE(10) HNS_SDIA_CASE(11) HNS_SDIA_CASE(12)
+            HNS_SDIA_CASE(13) HNS_SDIA_CASE(14) HNS_SDIA_CASE(15) HNS_SDIA_CASE(16)
+        }
+#undef HNS_SDIA_CASE
+    } else if (A.fmt == HNS_FMT_SELL) {
+        k_bspmm_sell<TV, TX, V, DOT><<<G, kBlock, 0, s>>>(A.n, K, A.slice_ptr, A.scol, vals,
+                                                          (const TX *)P, (TX *)Q, bc, cols, part);
+    } else {
+        k_bspmm_csr<TV, TX, V, DOT><<<G, kBlock, 0, s>>>(A.n, K, A.rowptr, A.col, vals,
+                                                         (const TX *)P, (TX *)Q, bc, cols, part);
+    }
+}
+
+template <typename T>
+const T *values_of(const DevMatrix &A)
+{
+    if (std::is_same<T, float>::value)
+        return (const T *)(const void *)(A.fmt == HNS_FMT_SDIA   ? (const void *)A.dia32
+                                         : A.fmt == HNS_FMT_SELL ? (const void *)A.sval32
+                                                                 : (const void *)A.val32);
+    return (const T *)(const void *)(A.fmt == HNS_FMT_SDIA   ? (const void *)A.dia
+                                     : A.fmt == HNS_FMT_SELL ? (const void *)A.sval
+                                                             : (const void *)A.val);
+}
+
+// plain FP64 product Q64 = mask_j(A X) (one element per thread)
+hns_status spmm64(BCtx &c, const double *X)
+{
+    const DevMatrix &A = c.op->A;
+    const int G = bgrid(A.n * (int64_t)c.K, c.K, 1);
+    bspmm_launch<double, double, 1, false>(A, c.K, values_of<double>(A), X, c.w->Q64, c.op->bc,
+                                           c.w->cols, nullptr, c.s, G);
+    return bcheck("batched spmm (fp64)");
+}
+
+template <typename TX, typename TD, int V>
+hns_status iteration_v(BCtx &c, TX *X, TX *R, TX *P, TX *Q, const TD *dinv)
+{
+    const DevMatrix &A = c.op->A;
+    const int64_t np = A.n * (int64_t)c.K / V;
+    const int G = bgrid(np, c.K, V);
+    double *part = c.w->part;
+    using TV = TX;
+    bspmm_launch<TV, TX, V, true>(A, c.K, values_of<TV>(A), P, Q, c.op->bc, c.w->cols, part, c.s,
+                                  G);
+    k_bred_gamma<<<c.K, kBlock, 0, c.s>>>(c.K, part, G, c.w->cols);
+    k_bupdate<TX, TD, V><<<G, kBlock, 0, c.s>>>(A.n, c.K, X, R, P, Q, dinv, c.w->cols, part);
+    k_bred_rho<<<c.K, kBlock, 0, c.s>>>(c.K, part, G, c.w->cols);
+    k_bpupdate<TX, TD, V><<<G, kBlock, 0, c.s>>>(A.n, c.K, P, R, dinv, c.w->cols);
+    return bcheck("batched iteration");
+}
+
+template <typename TX, typename TD>
+hns_status iteration(BCtx &c, TX *X, TX *R, TX *P, TX *Q, const TD *dinv)
+{
+    switch (c.V) {
+    case 4: return iteration_v<TX, TD, 4>(c, X, R, P, Q, dinv);
+    case 2: return iteration_v<TX, TD, 2>(c, X, R, P, Q, dinv);
+    default: return iteration_v<TX, TD, 1>(c, X, R, P, Q, dinv);
+    }
+}
+
+hns_status enqueue_chunk(BCtx &c, int count)
+{
+    for (int it = 0; it < count; ++it) {
+        hns_status st;
+        if (c.mixed)
+            st = iteration<float, float>(c, c.w->X32, c.w->R32, c.w->P32, c.w->Q32, c.op->dinv32);
+        else
+            st = iteration<double, double>(c, c.X, c.w->R64, c.w->P64, c.w->Q64, c.op->dinv);
+        if (st != HNS_OK) return st;
+    }
+    return HNS_OK;
+}
+
+// A chunk of iterations, from a captured graph when enabled.
+hns_status run_chunk(BCtx &c, int count)
+{
+    BWorkspace *w = c.w;
+    if (!c.op->use_graph || count != c.op->check_every) return enqueue_chunk(c, count);
+    if (!w->graph || w->graph_chunk != count || w->graph_V != c.V || w->graph_X != c.X) {
+        w->drop_graph();
+        // capture on a private stream (the caller's may be the null stream,
+        // which cannot be captured); the graph is then launched on the
+        // caller's stream
+        if (!w->cap_stream) HNS_TRY_HIP(hipStreamCreateWithFlags(&w->cap_stream, hipStreamNonBlocking));
+        BCtx cc = c;
+        cc.s = w->cap_stream;
+        hipGraph_t g = nullptr;
+        HNS_TRY_HIP(hipStreamBeginCapture(cc.s, hipStreamCaptureModeThreadLocal));
+        hns_status st = enqueue_chunk(cc, count);
+        hipError_t e = hipStreamEndCapture(cc.s, &g);
+        if (st != HNS_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return st;
+        }
+        if (e != hipSuccess) {
+            set_error("graph capture failed: %s", hipGetErrorString(e));
+            return HNS_ERR_HIP;
+        }
+        e = hipGraphInstantiate(&w->graph, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            w->graph = nullptr;
+            set_error("graph instantiation failed: %s", hipGetErrorString(e));
+            return HNS_ERR_HIP;
+        }
+        w->graph_chunk = count;
+        w->graph_V = c.V;
+        w->graph_X = c.X;
+    }
+    HNS_TRY_HIP(hipGraphLaunch(w->graph, c.s));
+    return HNS_OK;
+}
+
+// FP64 true residual of the marked columns, then the per-column decision
+hns_status true_residual(BCtx &c, double drop2, int first)
+{
+    const int64_t ne = c.op->n * (int64_t)c.K;
+    const int G = bgrid(ne, c.K, 1);
+    HNS_TRY(spmm64(c, c.X));
+    k_bresidual<<<G, kBlock, 0, c.s>>>(c.op->n, c.K, c.B, c.w->Q64, c.w->R64, c.op->bc, c.w->cols,
+                                       c.w->part);
+    k_bred_residual<<<c.K, kBlock, 0, c.s>>>(c.op->n, c.K, c.w->part, G, c.w->cols, drop2, first);
+    return bcheck("batched residual");
+}
+
+// New recurrence segment for the marked columns from R64
+hns_status new_segment(BCtx &c)
+{
+    const int64_t ne = c.op->n * (int64_t)c.K;
+    const int G = bgrid(ne, c.K, 1);
+    if (c.mixed)
+        k_bfrom64<float, float><<<G, kBlock, 0, c.s>>>(c.op->n, c.K, c.w->R64, c.w->R32,
+                                                       c.op->dinv32, c.w->cols, c.w->part);
+    else
+        k_bfrom64<double, double><<<G, kBlock, 0, c.s>>>(c.op->n, c.K, c.w->R64, c.w->R64,
+                                                         c.op->dinv, c.w->cols, c.w->part);
+    k_bred_restart<<<c.K, kBlock, 0, c.s>>>(c.K, c.w->part, G, c.w->cols);
+    const int Gp = bgrid(ne, c.K, 1);
+    if (c.mixed)
+        k_bpupdate<float, float, 1><<<Gp, kBlock, 0, c.s>>>(c.op->n, c.K, c.w->P32, c.w->R32,
+                                                            c.op->dinv32, c.w->cols);
+    else
+        k_bpupdate<double, double, 1><<<Gp, kBlock, 0, c.s>>>(c.op->n, c.K, c.w->P64, c.w->R64,
+                                                              c.op->dinv, c.w->cols);
+    return bcheck("batched segment");
+}
+
+}  // namespace
+
+hns_status solve_batched_impl(hns_operator *op, BWorkspace *w, int K, const int *bits,
+                              const double *B, double *X, double tol, int max_iter, bool mixed,
+                              int V, hipStream_t s, hns_solve_info *infos)
+{
+    BCtx c{op, w, K, V, B, X, s, mixed};
+    const int64_t n = op->n;
+    const int64_t ne = n * (int64_t)K;
+    const double drop2 = mixed ? op->replace_drop * op->replace_drop : 0.0;
+    // per-column set-up
+    for (int j = 0; j < K; ++j) {
+        BCol &h = w->host[j];
+        memset(&h, 0, sizeof(BCol));
+        h.bit = bits[j];
+        h.singular = (op->kind == HNS_POISSON && bits[j] < 0) ? 1 : 0;
+        h.tol2 = tol * tol;
+        h.mark = 1;
+        h.stop = ACTIVE;
+    }
+    HNS_TRY_HIP(hipMemcpyAsync(w->cols, w->host, K * sizeof(BCol), hipMemcpyHostToDevice, s));
+    const int G1 = bgrid(ne, K, 1);
+    k_bbstats<<<G1, kBlock, 0, s>>>(n, K, B, op->bc, w->cols, w->part);
+    k_bred_bstats<<<K, kBlock, 0, s>>>(n, K, w->part, G1, w->cols);
+    k_bprepare<<<G1, kBlock, 0, s>>>(n, K, X, mixed ? w->X32 : nullptr, op->bc, w->cols);
+    HNS_TRY(bcheck("batched set-up"));
+    HNS_TRY(pull(c));
+    for (int j = 0; j < K; ++j)
+        if (w->host[j].nonfinite > 0) {
+            set_error("right-hand side column %d has non-finite entries", j);
+            for (int q = 0; q < K; ++q) infos[q].status = HNS_ERR_INVALID;
+            return HNS_ERR_INVALID;
+        }
+    HNS_TRY(true_residual(c, drop2, 1));
+    HNS_TRY(new_segment(c));
+    HNS_TRY(pull(c));
+    int segments = 1;
+    std::vector<int> iter_at_break(K, -1);
+    for (;;) {
+        int active = 0, need = 0, maxit = 0;
+        bool stuck = false;
+        for (int j = 0; j < K; ++j) {
+            BCol &h = w->host[j];
+            maxit = std::max(maxit, h.iter);
+            if (h.stop == BREAK) {
+                // a breakdown right after a fresh restart, with no iteration
+                // done since the previous one, is final
+                if (iter_at_break[j] == h.iter) {
+                    h.stop = FAILED;
+                    stuck = true;
+                    continue;
+                }
+                iter_at_break[j] = h.iter;
+            }
+            if (h.stop == ACTIVE) ++active;
+            if (h.stop == THRESH || h.stop == BREAK) ++need;
+        }
+        if (stuck)  // host copy is current (nothing in flight): publish FAILED
+            HNS_TRY_HIP(hipMemcpyAsync(w->cols, w->host, K * sizeof(BCol), hipMemcpyHostToDevice,
+                                       s));
+        if (need > 0) {
+            // collect corrections, recompute the FP64 residual of those columns
+            k_bmark<<<1, kBlock, 0, s>>>(K, w->cols, 0);
+            if (mixed) k_baccumulate<<<G1, kBlock, 0, s>>>(n, K, X, w->X32, w->cols);
+            HNS_TRY(true_residual(c, drop2, 0));
+            HNS_TRY(new_segment(c));
+            HNS_TRY(pull(c));
+            ++segments;
+            continue;
+        }
+        if (active == 0 || maxit >= max_iter) break;
+        const int chunk = std::min(op->check_every, max_iter - maxit);
+        HNS_TRY(run_chunk(c, chunk));
+        HNS_TRY(pull(c));
+    }
+    // columns stopped by the iteration cap: collect their FP32 correction and
+    // report their true residual
+    int unfinished = 0;
+    for (int j = 0; j < K; ++j) unfinished += (w->host[j].stop == ACTIVE);
+    if (unfinished > 0) {
+        k_bmark<<<1, kBlock, 0, s>>>(K, w->cols, 2);
+        if (mixed) k_baccumulate<<<G1, kBlock, 0, s>>>(n, K, X, w->X32, w->cols);
+        HNS_TRY(true_residual(c, 0.0, 0));
+        HNS_TRY(bcheck("final residual"));
+    }
+    // zero right-hand sides give zero columns; Dirichlet entries are zero
+    k_bprepare<<<G1, kBlock, 0, s>>>(n, K, X, nullptr, op->bc, w->cols);
+    // pure-Neumann columns: zero mass-weighted mean
+    bool any_singular = false;
+    for (int j = 0; j < K; ++j) any_singular |= w->host[j].singular != 0;
+    if (any_singular) {
+        k_bwdot<<<G1, kBlock, 0, s>>>(n, K, X, op->lumped, w->part);
+        k_bred_wdot<<<K, kBlock, 0, s>>>(K, w->part, G1, w->cols);
+        k_bshift<<<G1, kBlock, 0, s>>>(n, K, X, w->cols, op->lumped_sum);
+        HNS_TRY(bcheck("batched normalisation"));
+    }
+    HNS_TRY(pull(c));
+    hns_status worst = HNS_OK;
+    for (int j = 0; j < K; ++j) {
+        const BCol &h = w->host[j];
+        hns_solve_info &inf = infos[j];
+        inf.iterations = h.iter;
+        inf.outer_iterations = segments;
+        inf.removed_mean = h.mean_b;
+        inf.relres_true = h.bb > 0 ? std::sqrt(h.rr_true / h.bb) : 0.0;
+        switch (h.stop) {
+        case DONE:
+        case ZERO: inf.status = HNS_OK; break;
+        case BREAK:
+        case FAILED: inf.status = HNS_ERR_BREAKDOWN; break;
+        default: inf.status = HNS_NOT_CONVERGED; break;
+        }
+        if (h.stop == ZERO) inf.relres_true = 0.0;
+        if (inf.status < 0 || (worst >= 0 && inf.status > worst)) worst = (hns_status)inf.status;
+    }
+    if (worst == HNS_ERR_BREAKDOWN) set_error("CG breakdown in at least one column");
+    return worst;
+}
+
+// Time one DOT SpMM of each pack width on this workspace; returns the best V
+hns_status tune_batched(hns_operator *op, BWorkspace *w, int K, bool mixed, hipStream_t s,
+                        double *times_us, int *best_V)
+{
+    BCtx c{op, w, K, 1, nullptr, nullptr, s, mixed};
+    const int widths[3] = {1, 2, 4};
+    hipEvent_t e0, e1;
+    HNS_TRY_HIP(hipEventCreate(&e0));
+    HNS_TRY_HIP(hipEventCreate(&e1));
+    // columns of the tuning run: all active, no Dirichlet bits
+    for (int j = 0; j < K; ++j) {
+        memset(&w->host[j], 0, sizeof(BCol));
+        w->host[j].bit = -1;
+    }
+    HNS_TRY_HIP(hipMemcpyAsync(w->cols, w->host, K * sizeof(BCol), hipMemcpyHostToDevice, s));
+    const DevMatrix &A = op->A;
+    const int64_t ne = A.n * (int64_t)K;
+    double best = 1e300;
+    *best_V = 1;
+    for (int q = 0; q < 3; ++q) {
+        const int V = widths[q];
+        times_us[q] = -1.0;
+        if (K % V) continue;
+        const int G = bgrid(ne / V, K, V);
+        auto launch = [&]() {
+            if (mixed) {
+                if (V == 1)
+                    bspmm_launch<float, float, 1, true>(A, K, values_of<float>(A), w->P32, w->Q32,
+                                                        nullptr, w->cols, w->part, s, G);
+                else if (V == 2)
+                    bspmm_launch<float, float, 2, true>(A, K, values_of<float>(A), w->P32, w->Q32,
+                                                        nullptr, w->cols, w->part, s, G);
+                else
+                    bspmm_launch<float, float, 4, true>(A, K, values_of<float>(A), w->P32, w->Q32,
+                                                        nullptr, w->cols, w->part, s, G);
+            } else {
+                if (V == 1)
+                    bspmm_launch<double, double, 1, true>(A, K, values_of<double>(A), w->P64,
+                                                          w->Q64, nullptr, w->cols, w->part, s, G);
+                else if (V == 2)
+                    bspmm_launch<double, double, 2, true>(A, K, values_of<double>(A), w->P64,
+                                                          w->Q64, nullptr, w->cols, w->part, s, G);
+                else
+                    bspmm_launch<double, double, 4, true>(A, K, values_of<double>(A), w->P64,
+                                                          w->Q64, nullptr, w->cols, w->part, s, G);
+            }
+        };
+        launch();
+        HNS_TRY(bcheck("tune"));
+        const int reps = 10;
+        HNS_TRY_HIP(hipEventRecord(e0, s));
+        for (int r = 0; r < reps; ++r) launch();
+        HNS_TRY_HIP(hipEventRecord(e1, s));
+        HNS_TRY_HIP(hipEventSynchronize(e1));
+        float ms = 0.0f;
+        HNS_TRY_HIP(hipEventElapsedTime(&ms, e0, e1));
+        times_us[q] = 1e3 * ms / reps;
+        if (times_us[q] < best) {
+            best = times_us[q];
+            *best_V = V;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)c;
+    return HNS_OK;
+}
+
+}  // namespace hns

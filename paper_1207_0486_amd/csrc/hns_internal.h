@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <cstdint>
 #include <mutex>
 #include <string>
@@ -81,6 +82,7 @@ struct DevMatrix {
 
 struct Scalars;           // device-side CG scalars (kernels.hip)
 struct Workspace;         // per-solve device buffers (solve.hip)
+struct BWorkspace;        // multi-right-hand-side buffers (batched.hip)
 
 }  // namespace hns
 
@@ -116,9 +118,24 @@ struct hns_operator {
     // workspaces, reused across solves
     std::mutex ws_mutex;
     std::vector<hns::Workspace *> ws_free;
+    std::vector<hns::BWorkspace *> bws_free;
+    int bspmm_vec = 0;                     // 0: autotune per (k, mode); else 1, 2 or 4
+    std::vector<std::array<int, 3>> tuned; // (k, mixed, V) chosen by the autotuner
 };
 
 namespace hns {
+
+// batched.hip
+hns_status create_bworkspace(int64_t n, int K, bool mixed, BWorkspace **out);
+void destroy_bworkspace(BWorkspace *w);
+size_t bworkspace_bytes(int64_t n, int K, bool mixed);
+int bworkspace_k(const BWorkspace *w);
+bool bworkspace_mixed(const BWorkspace *w);
+hns_status solve_batched_impl(hns_operator *op, BWorkspace *w, int K, const int *bits,
+                              const double *B, double *X, double tol, int max_iter, bool mixed,
+                              int V, hipStream_t s, hns_solve_info *infos);
+hns_status tune_batched(hns_operator *op, BWorkspace *w, int K, bool mixed, hipStream_t s,
+                        double *times_us, int *best_V);
 
 // assemble.cpp
 hns_status assemble_host(const hns_mesh *mesh, double c_mass, double c_stiff, double nu_h,

@@ -665,6 +665,7 @@ void hns_operator_destroy(hns_operator *op)
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (Workspace *w : op->ws_free) delete w;
+    for (BWorkspace *w : op->bws_free) destroy_bworkspace(w);
     delete op;
 }
 
@@ -720,6 +721,8 @@ hns_status hns_set_param(hns_operator *op, const char *name, double value)
         op->mixed_variant = (int)value;
     } else if (k == "replace_drop" && value > 0 && value < 1) {
         op->replace_drop = value;
+    } else if (k == "bspmm_vec" && (value == 0 || value == 1 || value == 2 || value == 4)) {
+        op->bspmm_vec = (int)value;
     } else if (k == "use_graph" && (value == 0 || value == 1)) {
         op->use_graph = (int)value;
     } else {
@@ -733,7 +736,7 @@ size_t hns_footprint_bytes(const hns_operator *op, int k, uint32_t mode, int inc
 {
     if (!op || k < 1) return 0;
     const bool mixed = (mode == HNS_MIXED);
-    size_t b = (size_t)k * Workspace::bytes_for(op->n, mixed);
+    size_t b = k == 1 ? Workspace::bytes_for(op->n, mixed) : bworkspace_bytes(op->n, k, mixed);
     if (include_operator) {
         b += op->A.bytes() + (size_t)op->n * (8 + 1 + 8);
         if (op->dinv32) b += (size_t)op->n * 4;
@@ -816,14 +819,114 @@ hns_status hns_apply(hns_operator *op, int mask_bit, const double *x_dev, double
     return HNS_OK;
 }
 
+static hns_status acquire_bws(hns_operator *op, int K, bool mixed, BWorkspace **out)
+{
+    {
+        std::lock_guard<std::mutex> g(op->ws_mutex);
+        for (size_t i = 0; i < op->bws_free.size(); ++i) {
+            BWorkspace *w = op->bws_free[i];
+            if (bworkspace_k(w) == K && (bworkspace_mixed(w) || !mixed)) {
+                op->bws_free.erase(op->bws_free.begin() + i);
+                *out = w;
+                return HNS_OK;
+            }
+        }
+    }
+    return create_bworkspace(op->n, K, mixed, out);
+}
+
+static void release_bws(hns_operator *op, BWorkspace *w)
+{
+    std::lock_guard<std::mutex> g(op->ws_mutex);
+    op->bws_free.push_back(w);
+}
+
+static hns_status check_batched_args(hns_operator *op, int k, const int *bits, const void *B,
+                                     const void *X, double tol, int max_iter, uint32_t mode)
+{
+    if (k < 1 || k > 1024 || !bits) {
+        set_error("k must be in [1, 1024] with k mask bits");
+        return HNS_ERR_INVALID;
+    }
+    for (int j = 0; j < k; ++j)
+        if (bits[j] < -1 || bits[j] > 7 || (bits[j] >= 0 && !op->bc)) {
+            set_error("bad mask bit %d for column %d", bits[j], j);
+            return HNS_ERR_INVALID;
+        }
+    return check_solve_args(op, -1, B, X, tol, max_iter, mode);
+}
+
+// pack width of the batched iteration kernels for (k, mode)
+static hns_status batched_vec(hns_operator *op, BWorkspace *w, int k, bool mixed, hipStream_t s,
+                              int *V)
+{
+    if (op->bspmm_vec > 0) {
+        *V = (k % op->bspmm_vec == 0) ? op->bspmm_vec : 1;
+        return HNS_OK;
+    }
+    for (const auto &t : op->tuned)
+        if (t[0] == k && t[1] == (int)mixed) {
+            *V = t[2];
+            return HNS_OK;
+        }
+    double times[3];
+    HNS_TRY(tune_batched(op, w, k, mixed, s, times, V));
+    op->tuned.push_back({k, (int)mixed, *V});
+    return HNS_OK;
+}
+
 hns_status hns_solve_batched(hns_operator *op, int k, const int *mask_bits, const double *B_dev,
                              double *X_dev, double tol, int max_iter, uint32_t mode, void *stream,
                              hns_solve_info *infos)
 {
-    (void)op; (void)k; (void)mask_bits; (void)B_dev; (void)X_dev; (void)tol; (void)max_iter;
-    (void)mode; (void)stream; (void)infos;
-    set_error("hns_solve_batched: not available in this build");
-    return HNS_ERR_INVALID;
+    if (!infos) {
+        set_error("infos must hold k entries");
+        return HNS_ERR_INVALID;
+    }
+    for (int j = 0; j < k && j < 1024; ++j) memset(&infos[j], 0, sizeof(hns_solve_info));
+    HNS_TRY(check_batched_args(op, k, mask_bits, B_dev, X_dev, tol, max_iter, mode));
+    if (op->bad_diag >= 0) {
+        set_error("diagonal entry %lld is not positive: Jacobi-PCG needs an SPD operator",
+                  (long long)op->bad_diag);
+        for (int j = 0; j < k; ++j) infos[j].status = HNS_ERR_BREAKDOWN;
+        return HNS_ERR_BREAKDOWN;
+    }
+    const bool mixed = (mode == HNS_MIXED);
+    hipStream_t s = (hipStream_t)stream;
+    BWorkspace *w = nullptr;
+    HNS_TRY(acquire_bws(op, k, mixed, &w));
+    int V = 1;
+    hns_status st = batched_vec(op, w, k, mixed, s, &V);
+    if (st == HNS_OK)
+        st = solve_batched_impl(op, w, k, mask_bits, B_dev, X_dev, tol, max_iter, mixed, V, s,
+                                infos);
+    release_bws(op, w);
+    return st;
+}
+
+hns_status hns_tune_batched(hns_operator *op, int k, uint32_t mode, void *stream,
+                            double *times_us, int *best_vec)
+{
+    if (!op || !times_us || !best_vec || k < 1 || k > 1024 ||
+        (mode != HNS_FP64 && mode != HNS_MIXED) || (mode == HNS_MIXED && !op->dinv32)) {
+        set_error("hns_tune_batched: bad arguments");
+        return HNS_ERR_INVALID;
+    }
+    const bool mixed = (mode == HNS_MIXED);
+    BWorkspace *w = nullptr;
+    HNS_TRY(acquire_bws(op, k, mixed, &w));
+    hns_status st = tune_batched(op, w, k, mixed, (hipStream_t)stream, times_us, best_vec);
+    release_bws(op, w);
+    if (st == HNS_OK) {
+        bool found = false;
+        for (auto &t : op->tuned)
+            if (t[0] == k && t[1] == (int)mixed) {
+                t[2] = *best_vec;
+                found = true;
+            }
+        if (!found) op->tuned.push_back({k, (int)mixed, *best_vec});
+    }
+    return st;
 }
 
 }  // extern "C"

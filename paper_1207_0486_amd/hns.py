@@ -237,6 +237,18 @@ class Operator:
             raise HNSError(st, "hns_solve")
         return x, SolveInfo._from(info)
 
+    def tune_batched(self, k: int, mode: str = "fp64", stream=None):
+        """Time the batched product for k columns at 1/2/4 columns per thread;
+        returns ({width: microseconds}, best width)."""
+        times = (C.c_double * 3)()
+        best = C.c_int()
+        with torch.cuda.device(self.device):
+            st = L.lib().hns_tune_batched(self._h, k, MODES[mode], _stream_handle(stream), times,
+                                          C.byref(best))
+        if st != L.HNS_OK:
+            raise HNSError(st, "hns_tune_batched")
+        return {w: times[i] for i, w in enumerate((1, 2, 4)) if times[i] >= 0}, best.value
+
     def solve_batched(self, B: torch.Tensor, X: torch.Tensor | None = None, mask_bits=None,
                       tol: float = 1e-10, max_iter: int = 100000, mode: str = "fp64",
                       stream=None, check: bool = True):

@@ -236,7 +236,8 @@ def test_footprint(dev, ragged_basin):
     op = Operator(ragged_basin, 1e3, 1e-2, 3600.0, kind="helmholtz", keep_fp32=True)
     f1 = op.footprint(1, "fp64", include_operator=False)
     f4 = op.footprint(4, "fp64", include_operator=False)
-    assert f1 >= 3 * 8 * op.n and f4 == 4 * f1
+    # single solve: r, p, q; batched (k = 4): R, P, Q blocks of n x 4
+    assert f1 >= 3 * 8 * op.n and f4 >= 4 * 3 * 8 * op.n
     assert op.footprint(1, "mixed", False) > f1
     # at least the symmetric half of the values (8 bytes each)
     assert op.footprint(1, "fp64", True) > f1 + 4 * op.nnz
