@@ -76,6 +76,171 @@ def make_forcing(m):
     return theta, f
 
 
+def bench_batched(torch, log, reps=3):
+    """Multi-RHS: 3 velocity components x 16 wind scenarios on the 128x128x20
+    basin, each scenario advanced one step from rest to get its time-step-1
+    right-hand sides; one batched solve against 48 single FP64 solves."""
+    import basin
+    from paper_1207_0486_amd.step import ProjectionStep
+    wl = basin.configs.BASIN_128x128x20_BATCH
+    dev = torch.device("cuda", 0)
+    t0 = time.time()
+    m = wl.mesh()
+    theta0, f = make_forcing(m)
+    st = ProjectionStep(m, wl.nu_h, wl.nu_v, wl.dt, theta0, f, device=dev)
+    st.pois.set_param("replace_drop", 0.1)
+    scen = basin.wind_scenarios(wl.extra["scenarios"], wl.extra["scenario_seed"])
+    cols, bits = [], []
+    zero3 = torch.zeros(3, m.n, dtype=torch.float64, device=dev)
+    zero = torch.zeros(m.n, dtype=torch.float64, device=dev)
+    for sc in scen:
+        theta = np.stack([basin.wind_tension(m.xyz[:, 1], m.Ly, sc.amplitude, sc.phase),
+                          np.zeros(m.n)])
+        st.theta.copy_(torch.as_tensor(theta, device=dev))
+        st.set_state(zero3, zero)
+        st.step(tol=wl.tol, mode="mixed")          # step 0 from rest
+        b = st.velocity_rhs()                       # time-step-1 right-hand sides
+        for c in range(3):
+            cols.append(b[c].clone())
+            bits.append(c)
+    B = torch.stack(cols, dim=1).contiguous()       # n x 48, row-major
+    k = B.shape[1]
+    helm = st.helm
+    log(f"batched set-up {wl.name}: n={m.n} k={k} ({time.time() - t0:.1f}s)")
+    times, best = helm.tune_batched(k, "mixed")
+    helm.set_param("use_graph", 1)
+    helm.set_param("replace_drop", 1e-3)
+
+    def run_batched(mode):
+        X = torch.zeros_like(B)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        X, infos = helm.solve_batched(B, X, mask_bits=bits, tol=wl.tol, mode=mode)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t, X, infos
+
+    def run_single():
+        X = torch.zeros_like(B)
+        Xc = torch.zeros(m.n, dtype=torch.float64, device=dev)
+        infos = []
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for j in range(k):
+            Xc.zero_()
+            _, info = helm.solve(B[:, j].contiguous(), Xc, tol=wl.tol, mask_bit=bits[j])
+            X[:, j] = Xc
+            infos.append(info)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t, X, infos
+
+    run_batched("mixed"), run_batched("fp64"), run_single()   # warm-up
+    tb = min(run_batched("mixed")[0] for _ in range(reps))
+    tb64 = min(run_batched("fp64")[0] for _ in range(reps))
+    ts = min(run_single()[0] for _ in range(reps))
+    _, Xb, ib = run_batched("mixed")
+    _, Xs, isg = run_single()
+    diff = float(((Xb - Xs).norm(dim=0) / Xs.norm(dim=0).clamp_min(1e-300)).max())
+    out = {
+        "workload": wl.name, "nodes": m.n, "rhs": k,
+        "rhs_recipe": "3 velocity components x 16 wind scenarios, time step 1 after a step "
+                      "from rest",
+        "batched_mixed_ms": round(1e3 * tb, 3),
+        "batched_fp64_ms": round(1e3 * tb64, 3),
+        "sequential_fp64_ms": round(1e3 * ts, 3),
+        "speedup_vs_sequential_fp64": round(ts / tb, 2),
+        "iterations_max": max(i.iterations for i in ib),
+        "relres_max": max(i.relres_true for i in ib),
+        "max_rel_diff_vs_sequential_fp64": diff,
+        "tile": {"columns_per_thread": best, "tuned_us": {str(w): round(t, 2)
+                                                          for w, t in times.items()}},
+        "graph": True,
+    }
+    log(f"batched: {out}")
+    helm.close()
+    st.pois.close()
+    return out
+
+
+def bench_serving(torch, log, budget_gb=16.0, mode="fp64", count=256):
+    """Serving: Poisson-process arrivals (50 req/s) of pressure / velocity solve
+    requests over five mesh sizes, tolerance 1e-8, continuous batching with
+    operators admitted by footprint and kept resident."""
+    import threading
+    import basin
+    from paper_1207_0486_amd.serve import GpuBackend, Request, Server
+    wl = basin.configs.SERVING
+    meshes = {}
+
+    def make(key):
+        idx, kind = key
+        if idx not in meshes:
+            meshes[idx] = basin.configs.serving_mesh(idx)
+        return meshes[idx], wl.nu_h, wl.nu_v, wl.dt, kind
+
+    reqs = basin.serving_requests(wl.extra["requests"] if count is None else count,
+                                  wl.extra["rate_hz"], wl.seed)
+    t0 = time.time()
+    be = GpuBackend(make, mode=mode, check_every=16)
+    srv = Server(be, budget_bytes=int(budget_gb * (1 << 30)), capacity=8, chunk=32)
+    # warm-up: one request per operator (assembly, tuning, graph capture)
+    keys = sorted({(r.mesh_index, r.kind) for r in reqs})
+    warm = []
+    for key in keys:
+        m = make(key)[0]
+        bit = -1 if key[1] == "poisson" else 0
+        d = None if bit < 0 else ((m.bc >> bit) & 1) == 1
+        warm.append(srv.submit(Request(key=key, b=basin.normal_rhs(m.n, 7, dirichlet=d),
+                                       mask_bit=bit, tol=wl.tol)))
+    try:
+        for f in warm:
+            f.result()
+    except BaseException:
+        srv.close()
+        raise
+    srv.results.clear()
+    log(f"serving warm-up: {len(keys)} operators resident ({time.time() - t0:.1f}s)")
+    # right-hand sides of the stream, generated before it starts
+    items = []
+    for r in reqs:
+        m = make((r.mesh_index, r.kind))[0]
+        bit = -1 if r.kind == "poisson" else 0
+        d = None if bit < 0 else ((m.bc >> bit) & 1) == 1
+        items.append((r, Request(key=(r.mesh_index, r.kind),
+                                 b=basin.normal_rhs(m.n, r.rhs_seed, dirichlet=d),
+                                 mask_bit=bit, tol=wl.tol)))
+    futs = []
+    start = time.perf_counter()
+
+    def feeder():
+        for r, q in items:
+            delay = start + r.arrival_s - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            q.arrival = time.perf_counter()
+            futs.append(srv.submit(q))
+
+    try:
+        th = threading.Thread(target=feeder)
+        th.start()
+        th.join()
+        results = [f.result() for f in futs]
+        end = time.perf_counter()
+        st = srv.stats(start, end)
+    finally:
+        srv.close()
+    nodes = sum(make((r.mesh_index, r.kind))[0].n for r, _ in items)
+    bad = sum(1 for x in results if x.info.status != 0)
+    out = {"requests": len(results), "rate_hz": wl.extra["rate_hz"], "tol": wl.tol,
+           "mode": mode, "budget_gb": budget_gb, "p50_ms": round(st["p50_ms"], 2),
+           "p99_ms": round(st["p99_ms"], 2), "mean_ms": round(st["mean_ms"], 2),
+           "solves_per_s": round(st["solves_per_s"], 2), "wall_s": round(end - start, 3),
+           "nodes_solved": int(nodes), "failed": bad, "operators_resident": len(keys),
+           "peak_gb": round(st["peak_bytes"] / (1 << 30), 3), "evictions": st["evictions"],
+           "meshes": [list(m) for m in basin.forcing.SERVING_MESHES]}
+    log(f"serving: {out}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -86,6 +251,10 @@ def main():
                     help="oracle PCG iterations in the CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serve-budget-gb", type=float, default=16.0)
+    ap.add_argument("--serve-mode", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--fmt", default="auto")
     ap.add_argument("--profile-period", type=int, default=16,
                     help="time every N-th CG iteration with HIP events (0 = off)")
@@ -194,6 +363,14 @@ def main():
         log(f"mixed: {msm:.1f} ms/step (x{ms64 / msm:.2f}), "
             + ", ".join(f"{k}={i.iterations}/{i.outer_iterations}" for k, i in infosm.items()))
 
+    batched = None
+    if not args.no_batched:
+        batched = bench_batched(torch, log)
+
+    serving = None
+    if not args.no_serving:
+        serving = bench_serving(torch, log, args.serve_budget_gb, args.serve_mode)
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -241,6 +418,8 @@ def main():
                      "bytes_per_launch": spmv_bytes, "avg_us": round(spmv_avg_us, 2)},
         "pressure_kernels": kern,
         "mixed": mixed,
+        "batched": batched,
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

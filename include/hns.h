@@ -151,6 +151,49 @@ hns_status hns_solve_batched(hns_operator *op, int k, const int *mask_bits,
                              const double *B_dev, double *X_dev, double tol, int max_iter,
                              uint32_t mode, void *stream, hns_solve_info *infos);
 
+/* ------------------------------------------------------------------------
+ * Batch sessions (continuous batching).  A session owns `capacity` slots =
+ * columns of a multi-right-hand-side recurrence on one operator.  Requests
+ * join free slots at any time (hns_batch_add), advance together with the
+ * requests already running (hns_batch_advance: all running slots share each
+ * operator read and each launch), and leave as soon as they finish
+ * (hns_batch_take), freeing the slot for the next request.  Per slot the
+ * arithmetic is that of hns_solve_batched (per-column scalars, tolerance and
+ * iteration cap; HNS_MIXED with FP64 residual replacement).  Calls on one
+ * session must not overlap; sessions of different operators may run on
+ * different streams concurrently.  Each call returns after its work on
+ * `stream` has completed.
+ * ------------------------------------------------------------------------ */
+typedef struct hns_batch hns_batch;
+
+/* Device bytes of a session (its workspace and right-hand-side block). */
+size_t hns_batch_footprint(const hns_operator *op, int capacity, uint32_t mode);
+
+/* Open a session of 1..1024 slots on `op` (mode HNS_FP64 or HNS_MIXED). */
+hns_status hns_batch_open(hns_operator *op, int capacity, uint32_t mode, hns_batch **out);
+void hns_batch_close(hns_batch *bt);
+
+/* Put `count` requests into free slots: slot slots[q] solves A x = b_devs[q]
+ * (device n-vector, copied) with Dirichlet bit mask_bits[q], relative
+ * tolerance tols[q] and at most max_iters[q] iterations.  A right-hand side
+ * with non-finite entries finishes at once with HNS_ERR_INVALID.
+ * HNS_ERR_INVALID (nothing added) for a busy or repeated slot. */
+hns_status hns_batch_add(hns_batch *bt, int count, const int *slots, const int *mask_bits,
+                         const double *const *b_devs, const double *tols,
+                         const int *max_iters, void *stream);
+
+/* Run up to `iterations` CG iterations of every running slot (fewer when all
+ * slots finish); *active_out (may be NULL) receives the slots still running. */
+hns_status hns_batch_advance(hns_batch *bt, int iterations, void *stream, int *active_out);
+
+/* states[slot] = 0 free, 1 running, 2 finished; infos (may be NULL) per slot. */
+hns_status hns_batch_poll(hns_batch *bt, int *states, hns_solve_info *infos, void *stream);
+
+/* Copy the result of a finished slot to x_dev (n doubles; pure-Neumann
+ * results shifted to zero mass-weighted mean) and free the slot. */
+hns_status hns_batch_take(hns_batch *bt, int slot, double *x_dev, hns_solve_info *info,
+                          void *stream);
+
 /* Time the multi-right-hand-side product kernel of `hns_solve_batched` for
  * k columns in `mode` with 1, 2 and 4 consecutive columns per thread, on this
  * operator; times_us[0..2] receive the microseconds per launch (-1 where k is

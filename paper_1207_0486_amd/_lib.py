@@ -52,6 +52,17 @@ _SIGNATURES = {
                                     C.POINTER(hns_solve_info)]),
     "hns_tune_batched": (C.c_int, [C.c_void_p, C.c_int, C.c_uint32, C.c_void_p,
                                    C.POINTER(C.c_double), C.POINTER(C.c_int)]),
+    "hns_batch_footprint": (C.c_size_t, [C.c_void_p, C.c_int, C.c_uint32]),
+    "hns_batch_open": (C.c_int, [C.c_void_p, C.c_int, C.c_uint32, C.POINTER(C.c_void_p)]),
+    "hns_batch_close": (None, [C.c_void_p]),
+    "hns_batch_add": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                C.POINTER(C.c_void_p), C.POINTER(C.c_double),
+                                C.POINTER(C.c_int), C.c_void_p]),
+    "hns_batch_advance": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.POINTER(C.c_int)]),
+    "hns_batch_poll": (C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.POINTER(hns_solve_info),
+                                 C.c_void_p]),
+    "hns_batch_take": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.POINTER(hns_solve_info),
+                                 C.c_void_p]),
     "hns_footprint_bytes": (C.c_size_t, [C.c_void_p, C.c_int, C.c_uint32, C.c_int]),
     "hns_operator_n": (C.c_int64, [C.c_void_p]),
     "hns_operator_nnz": (C.c_int64, [C.c_void_p]),

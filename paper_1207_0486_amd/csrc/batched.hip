@@ -20,6 +20,8 @@
 #include <cmath>
 #include <cstring>
 #include <numeric>
+#include <tuple>
+#include <utility>
 #include <vector>
 
 #include "kernels.h"
@@ -50,7 +52,10 @@ struct BCol {
 
 namespace {
 
-enum : int32_t { ACTIVE = 0, THRESH = 1, BREAK = 2, ZERO = 3, DONE = 4, FAILED = 5 };
+enum : int32_t {
+    ACTIVE = 0, THRESH = 1, BREAK = 2, ZERO = 3, DONE = 4, FAILED = 5, EMPTY = 6, CAPPED = 7,
+    BADRHS = 8
+};
 
 #define PACK_LOOP(t, np)                                                       \
     for (int64_t t = blockIdx.x * (int64_t)kBlock + threadIdx.x; t < (np); \
@@ -302,12 +307,15 @@ __global__ __launch_bounds__(kBlock) void k_bred_rho(int K, const double *__rest
             s.stop = BREAK;
             return;
         }
-        s.beta = rz / s.rho;
-        s.rho = rz;
-        if (rr <= s.thr2 * s.ref)
+        if (rr <= s.thr2 * s.ref) {
+            // segment ends: keep rho of this iteration's start, the next
+            // segment's direction is z_new + (rho_new / rho) p
             s.stop = THRESH;
-        else
+        } else {
+            s.beta = rz / s.rho;
+            s.rho = rz;
             s.mark = 1;
+        }
     }
 }
 
@@ -545,6 +553,46 @@ __global__ __launch_bounds__(kBlock) void k_bred_restart(int K, const double *__
     }
 }
 
+// Mark exactly the columns listed in slots[0..count)
+__global__ void k_bmark_list(int K, BCol *__restrict__ cols, const int32_t *__restrict__ slots,
+                             int count)
+{
+    for (int c = threadIdx.x; c < K; c += blockDim.x) cols[c].mark = 0;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int q = 0; q < count; ++q) cols[slots[q]].mark = 1;
+}
+
+// Column `slot` of B = b (contiguous n-vector); same column of X (and X32) = 0
+__global__ __launch_bounds__(kBlock) void k_bset_column(int64_t n, int K, double *__restrict__ B,
+                                                        double *__restrict__ X,
+                                                        float *__restrict__ X32,
+                                                        const double *__restrict__ b, int slot)
+{
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock) {
+        B[i * K + slot] = b[i];
+        X[i * K + slot] = 0.0;
+        if (X32) X32[i * K + slot] = 0.0f;
+    }
+}
+
+// x = column `slot` of X, shifted to zero mass-weighted mean when `shift`
+// (pure-Neumann columns; wx / wsum from cols[slot]), zeroed for b = 0
+__global__ __launch_bounds__(kBlock) void k_bget_column(int64_t n, int K,
+                                                        const double *__restrict__ X,
+                                                        double *__restrict__ x, int slot,
+                                                        const BCol *__restrict__ cols,
+                                                        double wsum, int shift)
+{
+    const BCol &s = cols[slot];
+    const double c = shift ? s.wx / wsum : 0.0;
+    const bool zero = s.stop == ZERO;
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock)
+        x[i] = zero ? 0.0 : X[i * K + slot] - c;
+}
+
 // x64 += x32, x32 = 0 for marked columns
 __global__ __launch_bounds__(kBlock) void k_baccumulate(int64_t n, int K, double *__restrict__ X,
                                                         float *__restrict__ X32,
@@ -654,8 +702,8 @@ struct BWorkspace {
     // captured iteration chunks: [mixed][V]
     hipGraphExec_t graph = nullptr;
     int graph_chunk = 0, graph_V = 0;
+    int graph_mixed = -1;              // precision the graph was captured for
     const void *graph_X = nullptr;
-    hipStream_t cap_stream = nullptr;  // private stream the chunks are captured on
 
     static size_t bytes_for(int64_t n, int K, bool mixed)
     {
@@ -702,12 +750,12 @@ struct BWorkspace {
         if (graph) (void)hipGraphExecDestroy(graph);
         graph = nullptr;
         graph_chunk = 0;
+        graph_mixed = -1;
     }
 
     ~BWorkspace()
     {
         drop_graph();
-        if (cap_stream) (void)hipStreamDestroy(cap_stream);
         if (block) (void)hipFree(block);
         if (host) (void)hipHostFree(host);
     }
@@ -754,17 +802,65 @@ hns_status pull(BCtx &c)
     return HNS_OK;
 }
 
+// Launches a kernel either on a stream or as the next node of a linear
+// graph (hipGraphAddKernelNode, so no stream capture is involved and other
+// threads' work on any stream cannot interfere with building the graph).
+struct Launcher {
+    hipStream_t s = nullptr;
+    hipGraph_t g = nullptr;
+    hipGraphNode_t last = nullptr;
+    hipError_t err = hipSuccess;
+
+    template <typename Tuple, size_t... I>
+    static void fill(void **params, Tuple &t, std::index_sequence<I...>)
+    {
+        ((params[I] = (void *)&std::get<I>(t)), ...);
+    }
+
+    template <typename... KArgs, typename... A>
+    void operator()(void (*k)(KArgs...), int grid, int block, A... a)
+    {
+        if (err != hipSuccess) return;
+        std::tuple<KArgs...> t(a...);
+        void *params[sizeof...(KArgs)];
+        fill(params, t, std::index_sequence_for<KArgs...>{});
+        if (g) {
+            hipKernelNodeParams p{};
+            p.func = (void *)k;
+            p.gridDim = dim3(grid);
+            p.blockDim = dim3(block);
+            p.sharedMemBytes = 0;
+            p.kernelParams = params;
+            p.extra = nullptr;
+            hipGraphNode_t node = nullptr;
+            err = hipGraphAddKernelNode(&node, g, last ? &last : nullptr, last ? 1 : 0, &p);
+            last = node;
+        } else {
+            err = hipLaunchKernel((const void *)k, dim3(grid), dim3(block), params, 0, s);
+        }
+    }
+
+    hns_status status(const char *what) const
+    {
+        if (err != hipSuccess) {
+            set_error("%s failed: %s", what, hipGetErrorString(err));
+            return HNS_ERR_HIP;
+        }
+        return HNS_OK;
+    }
+};
+
 template <typename TV, typename TX, int V, bool DOT>
-void bspmm_launch(const DevMatrix &A, int K, const TV *vals, const void *P, void *Q,
-                  const uint8_t *bc, const BCol *cols, double *part, hipStream_t s, int G)
+void bspmm_launch(Launcher &L, const DevMatrix &A, int K, const TV *vals, const void *P, void *Q,
+                  const uint8_t *bc, const BCol *cols, double *part, int G)
 {
     if (A.fmt == HNS_FMT_SDIA) {
         BOffsets o;
         for (int k = 0; k < kMaxDiag; ++k) o.o[k] = k < A.ndiag ? A.off[k] : 0;
-#define HNS_SDIA_CASE(M)                                                                     \
-    case M:                                                                                 \
-        k_bspmm_sdia<TV, TX, V, DOT, M><<<G, kBlock, 0, s>>>(A.n, K, o, vals, (const TX *)P, \
-                                                             (TX *)Q, bc, cols, part);       \
+#define HNS_SDIA_CASE(M)                                                              \
+    case M:                                                                          \
+        L(k_bspmm_sdia<TV, TX, V, DOT, M>, G, kBlock, A.n, K, o, vals, (const TX *)P, \
+          (TX *)Q, bc, cols, part);                                                  \
         break;
         switch (A.ndiag) {
             HNS_SDIA_CASE(1) HNS_SDIA_CASE(2) HNS_SDIA_CASE(3) HNS_SDIA_CASE(4)
@@ -774,11 +870,11 @@ void bspmm_launch(const DevMatrix &A, int K, const TV *vals, const void *P, void
         }
 #undef HNS_SDIA_CASE
     } else if (A.fmt == HNS_FMT_SELL) {
-        k_bspmm_sell<TV, TX, V, DOT><<<G, kBlock, 0, s>>>(A.n, K, A.slice_ptr, A.scol, vals,
-                                                          (const TX *)P, (TX *)Q, bc, cols, part);
+        L(k_bspmm_sell<TV, TX, V, DOT>, G, kBlock, A.n, K, (const int32_t *)A.slice_ptr,
+          (const int32_t *)A.scol, vals, (const TX *)P, (TX *)Q, bc, cols, part);
     } else {
-        k_bspmm_csr<TV, TX, V, DOT><<<G, kBlock, 0, s>>>(A.n, K, A.rowptr, A.col, vals,
-                                                         (const TX *)P, (TX *)Q, bc, cols, part);
+        L(k_bspmm_csr<TV, TX, V, DOT>, G, kBlock, A.n, K, (const int32_t *)A.rowptr,
+          (const int32_t *)A.col, vals, (const TX *)P, (TX *)Q, bc, cols, part);
     }
 }
 
@@ -799,77 +895,76 @@ hns_status spmm64(BCtx &c, const double *X)
 {
     const DevMatrix &A = c.op->A;
     const int G = bgrid(A.n * (int64_t)c.K, c.K, 1);
-    bspmm_launch<double, double, 1, false>(A, c.K, values_of<double>(A), X, c.w->Q64, c.op->bc,
-                                           c.w->cols, nullptr, c.s, G);
-    return bcheck("batched spmm (fp64)");
+    Launcher L{c.s};
+    bspmm_launch<double, double, 1, false>(L, A, c.K, values_of<double>(A), X, c.w->Q64, c.op->bc,
+                                           c.w->cols, nullptr, G);
+    return L.status("batched spmm (fp64)");
 }
 
 template <typename TX, typename TD, int V>
-hns_status iteration_v(BCtx &c, TX *X, TX *R, TX *P, TX *Q, const TD *dinv)
+void iteration_v(BCtx &c, Launcher &L, TX *X, TX *R, TX *P, TX *Q, const TD *dinv)
 {
     const DevMatrix &A = c.op->A;
     const int64_t np = A.n * (int64_t)c.K / V;
     const int G = bgrid(np, c.K, V);
     double *part = c.w->part;
+    BCol *cols = c.w->cols;
     using TV = TX;
-    bspmm_launch<TV, TX, V, true>(A, c.K, values_of<TV>(A), P, Q, c.op->bc, c.w->cols, part, c.s,
-                                  G);
-    k_bred_gamma<<<c.K, kBlock, 0, c.s>>>(c.K, part, G, c.w->cols);
-    k_bupdate<TX, TD, V><<<G, kBlock, 0, c.s>>>(A.n, c.K, X, R, P, Q, dinv, c.w->cols, part);
-    k_bred_rho<<<c.K, kBlock, 0, c.s>>>(c.K, part, G, c.w->cols);
-    k_bpupdate<TX, TD, V><<<G, kBlock, 0, c.s>>>(A.n, c.K, P, R, dinv, c.w->cols);
-    return bcheck("batched iteration");
+    bspmm_launch<TV, TX, V, true>(L, A, c.K, values_of<TV>(A), P, Q, c.op->bc, cols, part, G);
+    L(k_bred_gamma, c.K, kBlock, c.K, (const double *)part, G, cols);
+    L(k_bupdate<TX, TD, V>, G, kBlock, A.n, c.K, X, R, (const TX *)P, (const TX *)Q, dinv,
+      (const BCol *)cols, part);
+    L(k_bred_rho, c.K, kBlock, c.K, (const double *)part, G, cols);
+    L(k_bpupdate<TX, TD, V>, G, kBlock, A.n, c.K, P, (const TX *)R, dinv, (const BCol *)cols);
 }
 
 template <typename TX, typename TD>
-hns_status iteration(BCtx &c, TX *X, TX *R, TX *P, TX *Q, const TD *dinv)
+void iteration(BCtx &c, Launcher &L, TX *X, TX *R, TX *P, TX *Q, const TD *dinv)
 {
     switch (c.V) {
-    case 4: return iteration_v<TX, TD, 4>(c, X, R, P, Q, dinv);
-    case 2: return iteration_v<TX, TD, 2>(c, X, R, P, Q, dinv);
-    default: return iteration_v<TX, TD, 1>(c, X, R, P, Q, dinv);
+    case 4: iteration_v<TX, TD, 4>(c, L, X, R, P, Q, dinv); break;
+    case 2: iteration_v<TX, TD, 2>(c, L, X, R, P, Q, dinv); break;
+    default: iteration_v<TX, TD, 1>(c, L, X, R, P, Q, dinv); break;
     }
 }
 
-hns_status enqueue_chunk(BCtx &c, int count)
+hns_status enqueue_chunk(BCtx &c, Launcher &L, int count)
 {
     for (int it = 0; it < count; ++it) {
-        hns_status st;
         if (c.mixed)
-            st = iteration<float, float>(c, c.w->X32, c.w->R32, c.w->P32, c.w->Q32, c.op->dinv32);
+            iteration<float, float>(c, L, c.w->X32, c.w->R32, c.w->P32, c.w->Q32,
+                                    (const float *)c.op->dinv32);
         else
-            st = iteration<double, double>(c, c.X, c.w->R64, c.w->P64, c.w->Q64, c.op->dinv);
-        if (st != HNS_OK) return st;
+            iteration<double, double>(c, L, c.X, c.w->R64, c.w->P64, c.w->Q64,
+                                      (const double *)c.op->dinv);
     }
-    return HNS_OK;
+    return L.status("batched iteration");
 }
 
-// A chunk of iterations, from a captured graph when enabled.
+// A chunk of iterations, replayed from a graph when enabled.  The graph is
+// built node by node (no stream capture) and bakes in the kernels (precision,
+// pack width), the chunk length and every pointer; a workspace serves both
+// precisions, so all of them key the cached graph.
 hns_status run_chunk(BCtx &c, int count)
 {
     BWorkspace *w = c.w;
-    if (!c.op->use_graph || count != c.op->check_every) return enqueue_chunk(c, count);
-    if (!w->graph || w->graph_chunk != count || w->graph_V != c.V || w->graph_X != c.X) {
+    if (!c.op->use_graph || count != c.op->check_every) {
+        Launcher L{c.s};
+        return enqueue_chunk(c, L, count);
+    }
+    if (!w->graph || w->graph_chunk != count || w->graph_V != c.V || w->graph_X != c.X ||
+        w->graph_mixed != (int)c.mixed) {
         w->drop_graph();
-        // capture on a private stream (the caller's may be the null stream,
-        // which cannot be captured); the graph is then launched on the
-        // caller's stream
-        if (!w->cap_stream) HNS_TRY_HIP(hipStreamCreateWithFlags(&w->cap_stream, hipStreamNonBlocking));
-        BCtx cc = c;
-        cc.s = w->cap_stream;
         hipGraph_t g = nullptr;
-        HNS_TRY_HIP(hipStreamBeginCapture(cc.s, hipStreamCaptureModeThreadLocal));
-        hns_status st = enqueue_chunk(cc, count);
-        hipError_t e = hipStreamEndCapture(cc.s, &g);
+        HNS_TRY_HIP(hipGraphCreate(&g, 0));
+        Launcher L;
+        L.g = g;
+        hns_status st = enqueue_chunk(c, L, count);
         if (st != HNS_OK) {
-            if (g) (void)hipGraphDestroy(g);
+            (void)hipGraphDestroy(g);
             return st;
         }
-        if (e != hipSuccess) {
-            set_error("graph capture failed: %s", hipGetErrorString(e));
-            return HNS_ERR_HIP;
-        }
-        e = hipGraphInstantiate(&w->graph, g, nullptr, nullptr, 0);
+        hipError_t e = hipGraphInstantiate(&w->graph, g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
         if (e != hipSuccess) {
             w->graph = nullptr;
@@ -879,6 +974,7 @@ hns_status run_chunk(BCtx &c, int count)
         w->graph_chunk = count;
         w->graph_V = c.V;
         w->graph_X = c.X;
+        w->graph_mixed = (int)c.mixed;
     }
     HNS_TRY_HIP(hipGraphLaunch(w->graph, c.s));
     return HNS_OK;
@@ -1061,31 +1157,35 @@ hns_status tune_batched(hns_operator *op, BWorkspace *w, int K, bool mixed, hipS
         times_us[q] = -1.0;
         if (K % V) continue;
         const int G = bgrid(ne / V, K, V);
+        Launcher L{s};
         auto launch = [&]() {
             if (mixed) {
                 if (V == 1)
-                    bspmm_launch<float, float, 1, true>(A, K, values_of<float>(A), w->P32, w->Q32,
-                                                        nullptr, w->cols, w->part, s, G);
+                    bspmm_launch<float, float, 1, true>(L, A, K, values_of<float>(A), w->P32,
+                                                        w->Q32, nullptr, w->cols, w->part, G);
                 else if (V == 2)
-                    bspmm_launch<float, float, 2, true>(A, K, values_of<float>(A), w->P32, w->Q32,
-                                                        nullptr, w->cols, w->part, s, G);
+                    bspmm_launch<float, float, 2, true>(L, A, K, values_of<float>(A), w->P32,
+                                                        w->Q32, nullptr, w->cols, w->part, G);
                 else
-                    bspmm_launch<float, float, 4, true>(A, K, values_of<float>(A), w->P32, w->Q32,
-                                                        nullptr, w->cols, w->part, s, G);
+                    bspmm_launch<float, float, 4, true>(L, A, K, values_of<float>(A), w->P32,
+                                                        w->Q32, nullptr, w->cols, w->part, G);
             } else {
                 if (V == 1)
-                    bspmm_launch<double, double, 1, true>(A, K, values_of<double>(A), w->P64,
-                                                          w->Q64, nullptr, w->cols, w->part, s, G);
+                    bspmm_launch<double, double, 1, true>(L, A, K, values_of<double>(A),
+                                                          w->P64, w->Q64, nullptr, w->cols,
+                                                          w->part, G);
                 else if (V == 2)
-                    bspmm_launch<double, double, 2, true>(A, K, values_of<double>(A), w->P64,
-                                                          w->Q64, nullptr, w->cols, w->part, s, G);
+                    bspmm_launch<double, double, 2, true>(L, A, K, values_of<double>(A),
+                                                          w->P64, w->Q64, nullptr, w->cols,
+                                                          w->part, G);
                 else
-                    bspmm_launch<double, double, 4, true>(A, K, values_of<double>(A), w->P64,
-                                                          w->Q64, nullptr, w->cols, w->part, s, G);
+                    bspmm_launch<double, double, 4, true>(L, A, K, values_of<double>(A),
+                                                          w->P64, w->Q64, nullptr, w->cols,
+                                                          w->part, G);
             }
         };
         launch();
-        HNS_TRY(bcheck("tune"));
+        HNS_TRY(L.status("tune"));
         const int reps = 10;
         HNS_TRY_HIP(hipEventRecord(e0, s));
         for (int r = 0; r < reps; ++r) launch();
@@ -1106,3 +1206,354 @@ hns_status tune_batched(hns_operator *op, BWorkspace *w, int K, bool mixed, hipS
 }
 
 }  // namespace hns
+
+// ===========================================================================
+// Batch sessions: fixed-capacity slots that requests join and leave while the
+// shared recurrence keeps running (continuous batching).  Every slot is one
+// column of the n x K block; a free slot is an inactive column, so the
+// captured iteration graphs stay valid as requests come and go.
+// ===========================================================================
+struct hns_batch {
+    hns_operator *op = nullptr;
+    hns::BWorkspace *w = nullptr;
+    double *B = nullptr;
+    double *X = nullptr;
+    int32_t *slot_buf = nullptr;  // device list of slots for k_bmark_list
+    int K = 0;
+    bool mixed = false;
+    int V = 1;
+    int segments = 0;
+    std::vector<int> max_iter;
+    std::vector<int> iter_at_break;
+};
+
+namespace hns {
+namespace {
+
+hns_status session_pull(hns_batch *bt, hipStream_t s)
+{
+    HNS_TRY_HIP(hipMemcpyAsync(bt->w->host, bt->w->cols, bt->K * sizeof(BCol),
+                               hipMemcpyDeviceToHost, s));
+    HNS_TRY_HIP(hipStreamSynchronize(s));
+    return HNS_OK;
+}
+
+hns_status session_push(hns_batch *bt, hipStream_t s)
+{
+    HNS_TRY_HIP(hipMemcpyAsync(bt->w->cols, bt->w->host, bt->K * sizeof(BCol),
+                               hipMemcpyHostToDevice, s));
+    return HNS_OK;
+}
+
+// Replacement / restart pass for columns at their segment threshold or
+// broken down; caps columns at their iteration limit.  Host mirror current.
+hns_status session_service(hns_batch *bt, hipStream_t s)
+{
+    BWorkspace *w = bt->w;
+    const int K = bt->K;
+    const int64_t n = bt->op->n;
+    BCtx c{bt->op, w, K, bt->V, bt->B, bt->X, s, bt->mixed};
+    const double drop2 = bt->mixed ? bt->op->replace_drop * bt->op->replace_drop : 0.0;
+    const int G1 = bgrid(n * (int64_t)K, K, 1);
+    for (int round = 0; round < 4; ++round) {
+        bool changed = false;
+        int need = 0;
+        std::vector<int32_t> capped;
+        for (int j = 0; j < K; ++j) {
+            BCol &h = w->host[j];
+            if (h.stop == BREAK) {
+                if (bt->iter_at_break[j] == h.iter) {
+                    h.stop = FAILED;  // broke down again with no iteration in between
+                    changed = true;
+                    continue;
+                }
+                bt->iter_at_break[j] = h.iter;
+            }
+            if ((h.stop == ACTIVE || h.stop == THRESH) && h.iter >= bt->max_iter[j]) {
+                h.stop = CAPPED;
+                capped.push_back(j);
+                changed = true;
+            } else if (h.stop == THRESH || h.stop == BREAK) {
+                ++need;
+            }
+        }
+        if (changed) HNS_TRY(session_push(bt, s));
+        if (!capped.empty()) {
+            // collect the FP32 correction of capped columns, report their residual
+            HNS_TRY_HIP(hipMemcpyAsync(bt->slot_buf, capped.data(),
+                                       capped.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+            k_bmark_list<<<1, kBlock, 0, s>>>(K, w->cols, bt->slot_buf, (int)capped.size());
+            if (bt->mixed) k_baccumulate<<<G1, kBlock, 0, s>>>(n, K, bt->X, w->X32, w->cols);
+            HNS_TRY(true_residual(c, 0.0, 0));
+        }
+        if (need > 0) {
+            k_bmark<<<1, kBlock, 0, s>>>(K, w->cols, 0);
+            if (bt->mixed) k_baccumulate<<<G1, kBlock, 0, s>>>(n, K, bt->X, w->X32, w->cols);
+            HNS_TRY(true_residual(c, drop2, 0));
+            HNS_TRY(new_segment(c));
+            ++bt->segments;
+        }
+        HNS_TRY(bcheck("session service"));
+        if (capped.empty() && need == 0) return HNS_OK;
+        HNS_TRY(session_pull(bt, s));
+    }
+    return HNS_OK;
+}
+
+}  // namespace
+}  // namespace hns
+
+using namespace hns;
+
+extern "C" {
+
+size_t hns_batch_footprint(const hns_operator *op, int capacity, uint32_t mode)
+{
+    if (!op || capacity < 1) return 0;
+    return bworkspace_bytes(op->n, capacity, mode == HNS_MIXED) +
+           2 * (size_t)op->n * capacity * sizeof(double) + 256;
+}
+
+hns_status hns_batch_open(hns_operator *op, int capacity, uint32_t mode, hns_batch **out)
+{
+    if (!op || !out || capacity < 1 || capacity > 1024 || (mode != HNS_FP64 && mode != HNS_MIXED) ||
+        (mode == HNS_MIXED && !op->dinv32)) {
+        set_error("hns_batch_open: bad arguments");
+        return HNS_ERR_INVALID;
+    }
+    *out = nullptr;
+    hns_batch *bt = new hns_batch();
+    bt->op = op;
+    bt->K = capacity;
+    bt->mixed = (mode == HNS_MIXED);
+    bt->max_iter.assign(capacity, 0);
+    bt->iter_at_break.assign(capacity, -1);
+    hns_status st = create_bworkspace(op->n, capacity, bt->mixed, &bt->w);
+    const size_t nk = (size_t)op->n * capacity;
+    if (st == HNS_OK) {
+        hipError_t e = hipMalloc((void **)&bt->B, 2 * nk * sizeof(double) + 256);
+        if (e != hipSuccess) {
+            bt->B = nullptr;
+            set_error("batch session allocation failed: %s", hipGetErrorString(e));
+            st = e == hipErrorOutOfMemory ? HNS_ERR_OOM : HNS_ERR_HIP;
+        } else {
+            bt->X = bt->B + nk;
+            e = hipMalloc((void **)&bt->slot_buf, capacity * sizeof(int32_t));
+            if (e != hipSuccess) {
+                bt->slot_buf = nullptr;
+                set_error("batch session allocation failed: %s", hipGetErrorString(e));
+                st = HNS_ERR_OOM;
+            }
+        }
+    }
+    if (st == HNS_OK) {
+        if (op->bspmm_vec > 0) {
+            bt->V = (capacity % op->bspmm_vec == 0) ? op->bspmm_vec : 1;
+        } else {
+            double t[3];
+            st = tune_batched(op, bt->w, capacity, bt->mixed, nullptr, t, &bt->V);
+        }
+    }
+    if (st == HNS_OK) {
+        for (int j = 0; j < capacity; ++j) {
+            memset(&bt->w->host[j], 0, sizeof(BCol));
+            bt->w->host[j].stop = EMPTY;
+            bt->w->host[j].bit = -1;
+        }
+        hipError_t e1 = hipMemset(bt->B, 0, 2 * nk * sizeof(double));
+        hipError_t e2 = bt->mixed ? hipMemset(bt->w->X32, 0, nk * sizeof(float)) : hipSuccess;
+        hipError_t e3 = hipMemcpy(bt->w->cols, bt->w->host, capacity * sizeof(BCol),
+                                  hipMemcpyHostToDevice);
+        if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
+            set_error("batch session initialisation failed");
+            st = HNS_ERR_HIP;
+        }
+    }
+    if (st != HNS_OK) {
+        hns_batch_close(bt);
+        return st;
+    }
+    *out = bt;
+    return HNS_OK;
+}
+
+void hns_batch_close(hns_batch *bt)
+{
+    if (!bt) return;
+    (void)hipDeviceSynchronize();
+    if (bt->w) destroy_bworkspace(bt->w);
+    if (bt->B) (void)hipFree(bt->B);
+    if (bt->slot_buf) (void)hipFree(bt->slot_buf);
+    delete bt;
+}
+
+hns_status hns_batch_add(hns_batch *bt, int count, const int *slots, const int *mask_bits,
+                         const double *const *b_devs, const double *tols, const int *max_iters,
+                         void *stream)
+{
+    if (!bt || count < 1 || count > bt->K || !slots || !mask_bits || !b_devs || !tols ||
+        !max_iters) {
+        set_error("hns_batch_add: bad arguments");
+        return HNS_ERR_INVALID;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    hns_operator *op = bt->op;
+    BWorkspace *w = bt->w;
+    const int K = bt->K;
+    const int64_t n = op->n;
+    HNS_TRY(session_pull(bt, s));
+    for (int q = 0; q < count; ++q) {
+        const int j = slots[q];
+        if (j < 0 || j >= K || w->host[j].stop != EMPTY || !b_devs[q] || !(tols[q] > 0) ||
+            max_iters[q] < 0 || mask_bits[q] < -1 || mask_bits[q] > 7 ||
+            (mask_bits[q] >= 0 && !op->bc)) {
+            set_error("hns_batch_add: slot %d is not free or its arguments are invalid", j);
+            return HNS_ERR_INVALID;
+        }
+        for (int r = 0; r < q; ++r)
+            if (slots[r] == j) {
+                set_error("hns_batch_add: slot %d listed twice", j);
+                return HNS_ERR_INVALID;
+            }
+    }
+    for (int q = 0; q < count; ++q) {
+        const int j = slots[q];
+        k_bset_column<<<stream_grid(n), kBlock, 0, s>>>(n, K, bt->B, bt->X,
+                                                        bt->mixed ? w->X32 : nullptr, b_devs[q], j);
+        BCol &h = w->host[j];
+        memset(&h, 0, sizeof(BCol));
+        h.bit = mask_bits[q];
+        h.singular = (op->kind == HNS_POISSON && mask_bits[q] < 0) ? 1 : 0;
+        h.tol2 = tols[q] * tols[q];
+        h.stop = ACTIVE;
+        bt->max_iter[j] = max_iters[q];
+        bt->iter_at_break[j] = -1;
+    }
+    HNS_TRY(bcheck("batch add"));
+    HNS_TRY(session_push(bt, s));
+    const int G1 = bgrid(n * (int64_t)K, K, 1);
+    k_bbstats<<<G1, kBlock, 0, s>>>(n, K, bt->B, op->bc, w->cols, w->part);
+    k_bred_bstats<<<K, kBlock, 0, s>>>(n, K, w->part, G1, w->cols);
+    HNS_TRY(bcheck("batch add statistics"));
+    HNS_TRY(session_pull(bt, s));
+    std::vector<int32_t> ok;
+    for (int q = 0; q < count; ++q) {
+        const int j = slots[q];
+        if (w->host[j].nonfinite > 0)
+            w->host[j].stop = BADRHS;
+        else
+            ok.push_back(j);
+    }
+    HNS_TRY(session_push(bt, s));
+    if (!ok.empty()) {
+        HNS_TRY_HIP(hipMemcpyAsync(bt->slot_buf, ok.data(), ok.size() * sizeof(int32_t),
+                                   hipMemcpyHostToDevice, s));
+        k_bmark_list<<<1, kBlock, 0, s>>>(K, w->cols, bt->slot_buf, (int)ok.size());
+        BCtx c{op, w, K, bt->V, bt->B, bt->X, s, bt->mixed};
+        const double drop2 = bt->mixed ? op->replace_drop * op->replace_drop : 0.0;
+        HNS_TRY(true_residual(c, drop2, 1));
+        HNS_TRY(new_segment(c));
+    }
+    HNS_TRY(bcheck("batch add residual"));
+    HNS_TRY(session_pull(bt, s));
+    return HNS_OK;
+}
+
+hns_status hns_batch_advance(hns_batch *bt, int iterations, void *stream, int *active_out)
+{
+    if (!bt || iterations < 0) {
+        set_error("hns_batch_advance: bad arguments");
+        return HNS_ERR_INVALID;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    BCtx c{bt->op, bt->w, bt->K, bt->V, bt->B, bt->X, s, bt->mixed};
+    HNS_TRY(session_pull(bt, s));
+    int done = 0, active = 0;
+    for (;;) {
+        HNS_TRY(session_service(bt, s));
+        active = 0;
+        for (int j = 0; j < bt->K; ++j) active += (bt->w->host[j].stop == ACTIVE);
+        if (active == 0 || done >= iterations) break;
+        const int chunk = std::min(bt->op->check_every, iterations - done);
+        HNS_TRY(run_chunk(c, chunk));
+        HNS_TRY(session_pull(bt, s));
+        done += chunk;
+    }
+    if (active_out) *active_out = active;
+    return HNS_OK;
+}
+
+hns_status hns_batch_poll(hns_batch *bt, int *states, hns_solve_info *infos, void *stream)
+{
+    if (!bt || !states) {
+        set_error("hns_batch_poll: bad arguments");
+        return HNS_ERR_INVALID;
+    }
+    HNS_TRY(session_pull(bt, (hipStream_t)stream));
+    for (int j = 0; j < bt->K; ++j) {
+        const BCol &h = bt->w->host[j];
+        states[j] = h.stop == EMPTY                                          ? 0
+                    : (h.stop == ACTIVE || h.stop == THRESH || h.stop == BREAK) ? 1
+                                                                             : 2;
+        if (infos) {
+            hns_solve_info &inf = infos[j];
+            memset(&inf, 0, sizeof(inf));
+            inf.iterations = h.iter;
+            inf.outer_iterations = bt->segments;
+            inf.removed_mean = h.mean_b;
+            inf.relres_true = (h.bb > 0 && h.stop != ZERO) ? std::sqrt(h.rr_true / h.bb) : 0.0;
+            inf.status = (h.stop == DONE || h.stop == ZERO)      ? HNS_OK
+                         : (h.stop == FAILED || h.stop == BREAK) ? HNS_ERR_BREAKDOWN
+                         : h.stop == BADRHS                      ? HNS_ERR_INVALID
+                                                                 : HNS_NOT_CONVERGED;
+        }
+    }
+    return HNS_OK;
+}
+
+hns_status hns_batch_take(hns_batch *bt, int slot, double *x_dev, hns_solve_info *info,
+                          void *stream)
+{
+    if (!bt || slot < 0 || slot >= bt->K || !x_dev) {
+        set_error("hns_batch_take: bad arguments");
+        return HNS_ERR_INVALID;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    BWorkspace *w = bt->w;
+    HNS_TRY(session_pull(bt, s));
+    BCol &h = w->host[slot];
+    if (h.stop == EMPTY || h.stop == ACTIVE || h.stop == THRESH || h.stop == BREAK) {
+        set_error("hns_batch_take: slot %d has no finished solve", slot);
+        return HNS_ERR_INVALID;
+    }
+    int states[1];
+    (void)states;
+    hns_solve_info inf;
+    memset(&inf, 0, sizeof(inf));
+    {
+        std::vector<int> st(bt->K);
+        std::vector<hns_solve_info> all(bt->K);
+        HNS_TRY(hns_batch_poll(bt, st.data(), all.data(), stream));
+        inf = all[slot];
+    }
+    const int64_t n = bt->op->n;
+    const int K = bt->K;
+    const bool shift = h.singular && (h.stop == DONE || h.stop == CAPPED);
+    if (shift) {
+        const int G1 = bgrid(n * (int64_t)K, K, 1);
+        k_bwdot<<<G1, kBlock, 0, s>>>(n, K, bt->X, bt->op->lumped, w->part);
+        k_bred_wdot<<<K, kBlock, 0, s>>>(K, w->part, G1, w->cols);
+    }
+    k_bget_column<<<stream_grid(n), kBlock, 0, s>>>(n, K, bt->X, x_dev, slot, w->cols,
+                                                    bt->op->lumped_sum, shift ? 1 : 0);
+    HNS_TRY(bcheck("batch take"));
+    HNS_TRY(session_pull(bt, s));
+    w->host[slot].stop = EMPTY;
+    w->host[slot].mark = 0;
+    HNS_TRY(session_push(bt, s));
+    HNS_TRY_HIP(hipStreamSynchronize(s));
+    if (info) *info = inf;
+    return HNS_OK;
+}
+
+}  // extern "C"

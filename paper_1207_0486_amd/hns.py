@@ -270,3 +270,76 @@ class Operator:
         if st < 0 and check:
             raise HNSError(st, "hns_solve_batched")
         return X, [SolveInfo._from(infos[j]) for j in range(k)]
+
+
+class BatchSession:
+    """Fixed-capacity slots of a continuously batched multi-RHS recurrence on
+    one operator (hns_batch_*): requests join free slots at any time, advance
+    together, and leave when finished."""
+
+    def __init__(self, op: Operator, capacity: int, mode: str = "fp64"):
+        self.op = op
+        self.capacity = capacity
+        self.mode = mode
+        h = C.c_void_p()
+        with torch.cuda.device(op.device):
+            st = L.lib().hns_batch_open(op._h, capacity, MODES[mode], C.byref(h))
+        if st != L.HNS_OK:
+            raise HNSError(st, "hns_batch_open")
+        self._h = h
+
+    @staticmethod
+    def footprint(op: Operator, capacity: int, mode: str = "fp64") -> int:
+        return int(L.lib().hns_batch_footprint(op._h, capacity, MODES[mode]))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            L.lib().hns_batch_close(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def add(self, slots, mask_bits, bs, tols, max_iters, stream=None):
+        k = len(slots)
+        ptrs = (C.c_void_p * k)(*[_dev_f64(b, "b", self.op.n).value for b in bs])
+        with torch.cuda.device(self.op.device):
+            st = L.lib().hns_batch_add(
+                self._h, k, (C.c_int * k)(*slots), (C.c_int * k)(*mask_bits), ptrs,
+                (C.c_double * k)(*tols), (C.c_int * k)(*max_iters), _stream_handle(stream))
+        if st != L.HNS_OK:
+            raise HNSError(st, "hns_batch_add")
+
+    def advance(self, iterations: int, stream=None) -> int:
+        active = C.c_int()
+        with torch.cuda.device(self.op.device):
+            st = L.lib().hns_batch_advance(self._h, iterations, _stream_handle(stream),
+                                           C.byref(active))
+        if st != L.HNS_OK:
+            raise HNSError(st, "hns_batch_advance")
+        return active.value
+
+    def poll(self, stream=None):
+        """(states, infos): state 0 free, 1 running, 2 finished per slot."""
+        k = self.capacity
+        states = (C.c_int * k)()
+        infos = (L.hns_solve_info * k)()
+        with torch.cuda.device(self.op.device):
+            st = L.lib().hns_batch_poll(self._h, states, infos, _stream_handle(stream))
+        if st != L.HNS_OK:
+            raise HNSError(st, "hns_batch_poll")
+        return list(states), [SolveInfo._from(infos[j]) for j in range(k)]
+
+    def take(self, slot: int, out: torch.Tensor | None = None, stream=None):
+        x = torch.empty(self.op.n, dtype=torch.float64, device=self.op.device) if out is None \
+            else out
+        info = L.hns_solve_info()
+        with torch.cuda.device(self.op.device):
+            st = L.lib().hns_batch_take(self._h, slot, _dev_f64(x, "out", self.op.n),
+                                        C.byref(info), _stream_handle(stream))
+        if st != L.HNS_OK:
+            raise HNSError(st, "hns_batch_take")
+        return x, SolveInfo._from(info)
