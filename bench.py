@@ -17,6 +17,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import re
 import sys
 import time
 
@@ -74,6 +75,37 @@ def make_forcing(m):
     theta = np.stack([basin.wind_tension(m.xyz[:, 1], L), np.zeros(m.n)])
     f = basin.coriolis_parameter(m.xyz[:, 1], L)
     return theta, f
+
+
+COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "counters_spmv_sdia_fp64_basin256x256x20.md")
+KERNEL_SOURCES = ("kernels.hip", "kernels.h")
+
+
+def kernel_source_hash():
+    """SHA-256 over the sources of the CG kernels, to tell whether counter
+    figures taken earlier still describe the kernel that runs now."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1207_0486_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def counted_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed hardware-counter
+    summary (FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by what the
+    counter reads for a copy of known size), or None when there is none for
+    this kernel or the kernel sources changed since the counters were taken."""
+    try:
+        with open(COUNTER_SUMMARY) as f:
+            text = f.read()
+    except OSError:
+        return None
+    fields = dict(re.findall(r"^- (\w+): `([^`]*)`", text, flags=re.M))
+    if fields.get("kernel") != kernel or fields.get("source_sha256") != kernel_source_hash():
+        return None
+    return int(fields["traffic_bytes_per_launch"])
 
 
 def bench_batched(torch, log, reps=3):
@@ -241,6 +273,29 @@ def bench_serving(torch, log, budget_gb=16.0, mode="fp64", count=256):
     return out
 
 
+def traffic_probe(torch, log, iters=64):
+    """Short run for hardware-counter passes: a plain 1 GiB device copy (the
+    calibration kernel of known size) and 64 iterations of the 256x256x20
+    pressure solve (the dominant SpMV kernel)."""
+    import basin
+    from paper_1207_0486_amd.hns import Operator
+    dev = torch.device("cuda", 0)
+    a = torch.ones(1 << 27, dtype=torch.float64, device=dev)       # 1 GiB
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    wl = basin.configs.BASIN_256x256x20
+    m = wl.mesh()
+    pois = Operator(m, wl.nu_h, wl.nu_v, kind="poisson")
+    rhs = torch.as_tensor(basin.normal_rhs(m.n, 0, zero_mean=True), device=dev)
+    x, info = pois.solve(rhs, tol=1e-30, max_iter=iters, check=False)
+    torch.cuda.synchronize()
+    out = {"probe": "traffic", "copy_bytes": 2 * a.numel() * 8, "nodes": m.n, "nnz": pois.nnz,
+           "format": pois.format, "iterations": info.iterations,
+           "spmv_algorithmic_bytes": bytes_spmv(pois.format, m.n, pois.nnz, 8)}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -252,6 +307,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="only a 1 GiB copy and 64 pressure iterations (for counter passes)")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serve-budget-gb", type=float, default=16.0)
     ap.add_argument("--serve-mode", default="fp64", choices=["fp64", "mixed"])
@@ -259,6 +316,10 @@ def main():
     ap.add_argument("--profile-period", type=int, default=16,
                     help="time every N-th CG iteration with HIP events (0 = off)")
     args = ap.parse_args()
+    if args.traffic_probe:
+        import torch
+        traffic_probe(torch, log)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the solver "
               "does not shard across GPUs", file=sys.stderr)
@@ -335,6 +396,9 @@ def main():
     spmv_avg_us = 1e3 * spmv_ms / max(spmv_n, 1)
     spmv_bytes = bytes_spmv(fmt, n, nnz, 8)
     spmv_gbs = spmv_bytes / (spmv_avg_us * 1e-6) / 1e9
+    spmv_kernel = (f"k_spmv_sdia<double, double, true, {pois.ndiag}>" if fmt == "sdia"
+                   else f"k_spmv_{fmt}<double, double, true>")
+    traffic = counted_traffic(spmv_kernel)
     kern = {}
     for name in ("spmv", "update", "pupdate"):
         ms_, cnt = prof64["pois"][name]
@@ -413,8 +477,8 @@ def main():
         "fp64": {k: {"iters": i.iterations, "relres": i.relres_true} for k, i in infos64.items()},
         "step_ms": [round(1e3 * v, 3) for v in per64],
         "roofline": {"bound": "hbm", "achieved": round(spmv_gbs, 1), "peak": PEAK_HBM_GBS,
-                     "unit": "GB/s", "frac": round(spmv_gbs / PEAK_HBM_GBS, 4), "traffic": None,
-                     "kernel": f"k_spmv_{fmt}<double,double,true>",
+                     "unit": "GB/s", "frac": round(spmv_gbs / PEAK_HBM_GBS, 4), "traffic": traffic,
+                     "kernel": spmv_kernel,
                      "bytes_per_launch": spmv_bytes, "avg_us": round(spmv_avg_us, 2)},
         "pressure_kernels": kern,
         "mixed": mixed,

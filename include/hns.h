@@ -209,10 +209,14 @@ hns_status hns_tune_batched(hns_operator *op, int k, uint32_t mode, void *stream
  * != 0.  Used for admission by HBM footprint. */
 size_t hns_footprint_bytes(const hns_operator *op, int k, uint32_t mode, int include_operator);
 
-/* Basic operator facts. */
+/* Basic operator facts: rows, stored nonzeros of the full matrix, storage
+ * format (HNS_FMT_CSR, _SELL or _SDIA), and for symmetric diagonal storage
+ * the number of stored off-diagonals (upper ones; 0 for the other formats).
+ * -1 (0 for the format) for a null operator. */
 int64_t hns_operator_n(const hns_operator *op);
 int64_t hns_operator_nnz(const hns_operator *op);
 uint32_t hns_operator_format(const hns_operator *op);
+int hns_operator_ndiag(const hns_operator *op);
 
 /* Tunables (returns HNS_ERR_INVALID for an unknown name or a bad value):
  *   "check_every"  CG iterations between host convergence reads (default 32)

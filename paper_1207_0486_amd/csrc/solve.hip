@@ -703,6 +703,11 @@ hns_status hns_profile_read(const hns_operator *op, int kernel, double *total_ms
 int64_t hns_operator_n(const hns_operator *op) { return op ? op->n : -1; }
 int64_t hns_operator_nnz(const hns_operator *op) { return op ? op->A.nnz : -1; }
 uint32_t hns_operator_format(const hns_operator *op) { return op ? op->A.fmt : 0; }
+int hns_operator_ndiag(const hns_operator *op)
+{
+    if (!op) return -1;
+    return op->A.fmt == HNS_FMT_SDIA ? op->A.ndiag : 0;
+}
 
 hns_status hns_set_param(hns_operator *op, const char *name, double value)
 {

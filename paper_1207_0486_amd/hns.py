@@ -119,6 +119,7 @@ class Operator:
         self.n = int(L.lib().hns_operator_n(h))
         self.nnz = int(L.lib().hns_operator_nnz(h))
         self.format = FORMAT_NAMES.get(int(L.lib().hns_operator_format(h)), "?")
+        self.ndiag = int(L.lib().hns_operator_ndiag(h))
         self.keep_fp32 = keep_fp32
 
     # -- lifetime -------------------------------------------------------
