@@ -235,7 +235,14 @@ int hns_operator_ndiag(const hns_operator *op);
  *   "use_graph"    1 = replay captured HIP graphs for the iteration chunks of
  *                  hns_solve_batched (default 0)
  *   "bspmm_vec"    columns per thread of the batched kernels: 0 = autotune
- *                  (default), or 1, 2, 4 */
+ *                  (default), or 1, 2, 4
+ *   "spmv_it64"    launch shape of the single-vector diagonal-storage SpMV with
+ *   "spmv_it32"    FP64 / FP32 vectors: workgroup-sized row passes per block
+ *                  (defaults 1 and 2; integers 1..64)
+ *   "vec_it"       16-byte packs per thread of the single-vector CG updates
+ *                  (default 3; integers 1..64).  The three change the grid
+ *                  (and with it the summation order of the dot products),
+ *                  not the arithmetic of a row or a pack. */
 hns_status hns_set_param(hns_operator *op, const char *name, double value);
 
 /* y = A x on the device (FP64), with the rows of Dirichlet set mask_bit

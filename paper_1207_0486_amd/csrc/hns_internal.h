@@ -34,6 +34,7 @@ void set_error(const char *fmt, ...) __attribute__((format(printf, 1, 2)));
 constexpr int kBlock = 256;      // threads per workgroup (4 wavefronts)
 constexpr int kSlice = 64;       // sliced-ELL slice height = one wavefront
 constexpr int kMaxGrid = 2048;   // workgroups of the reducing kernels (multiple of 8 XCDs)
+constexpr int kMaxPart = 4096;   // workgroups of the single-vector CG kernels (partials slots)
 constexpr int kMaxDiag = 16;     // upper diagonals of the symmetric-diagonal format
 
 // ---------------------------------------------------------------------------
@@ -75,6 +76,12 @@ struct DevMatrix {
     int32_t off[kMaxDiag] = {0};
     double *dia = nullptr;
     float *dia32 = nullptr;
+    // launch shape of the single-vector CG kernels: workgroup-sized row
+    // passes per block of the FP64-vector and FP32-vector diagonal SpMV, and
+    // 16-byte packs per thread of the vector updates
+    int spmv_it64 = 1;
+    int spmv_it32 = 2;
+    int vec_it = 3;
 
     size_t bytes() const;
     void release();

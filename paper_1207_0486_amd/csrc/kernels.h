@@ -30,14 +30,23 @@ struct Scalars {
 
 // Layout of the per-workspace partial-sum buffer (doubles)
 constexpr int kPartSpmv = 0;                 // p^T q per SpMV block
-constexpr int kPartUpdate = kMaxGrid;        // r^T z, r^T r per update block
-constexpr int kPartMisc = 3 * kMaxGrid;      // one-off reductions (3 values)
-constexpr int kPartTotal = 6 * kMaxGrid;
+constexpr int kPartUpdate = kMaxPart;        // r^T z, r^T r per update block
+constexpr int kPartMisc = 3 * kMaxPart;      // one-off reductions (3 values)
+constexpr int kPartTotal = 6 * kMaxPart;
 
 // grid for a streaming kernel over n entries (multiple of 8 when >= 8)
 int stream_grid(int64_t n);
-// grid for the SpMV of a matrix
+// grid for the SpMV of a matrix in CSR or sliced ELL
 int spmv_grid(const DevMatrix &A);
+
+// Contiguous chunks: `grid` workgroups (a multiple of 8 when >= 8, at most
+// kMaxPart) of `per` consecutive units each (a multiple of `quantum`, at
+// least the requested per) cover `units` units.
+struct Chunks {
+    int grid;
+    int64_t per;
+};
+Chunks chunks(int64_t units, int64_t per, int64_t quantum);
 
 // Precision of one CG recurrence: matrix values / vectors / Jacobi diagonal
 enum class Prec {

@@ -118,12 +118,25 @@ __device__ __forceinline__ void load_reduced(const double *__restrict__ P, int G
 {
     __shared__ double lds[NV * (kBlock / 64)];
     __shared__ double bcast[NV];
+    // U independent loads per thread in flight at once (one L2 round trip
+    // per U * kBlock partials), then added in increasing block order
+    constexpr int U = NV == 1 ? 16 : 8;
     double t[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) t[k] = 0.0;
-    for (int b = threadIdx.x; b < G; b += kBlock) {
+    for (int b0 = threadIdx.x; b0 < G; b0 += U * kBlock) {
+        double u[NV][U];
 #pragma unroll
-        for (int k = 0; k < NV; ++k) t[k] += P[k * G + b];
+        for (int j = 0; j < U; ++j) {
+            const int b = b0 + j * kBlock;
+#pragma unroll
+            for (int k = 0; k < NV; ++k) u[k][j] = b < G ? P[k * G + b] : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+#pragma unroll
+            for (int k = 0; k < NV; ++k) t[k] += u[k][j];
+        }
     }
     block_sum<NV>(t, lds);
     if (threadIdx.x == 0) {
@@ -248,13 +261,36 @@ struct DiaOffsets {
     int32_t o[kMaxDiag];
 };
 
-// Symmetric diagonal storage, one row per lane: row i reads the main
-// diagonal, each upper diagonal at i (entry (i, i+o)) and at i-o (entry
-// (i-o, i) = (i, i-o) by symmetry).  All loads are unit-stride across the
-// wavefront (shifted copies of the same arrays), so there are no index
-// arrays and no gathers.  Each block owns a contiguous range of rows.
-template <typename TV, typename TX, bool DOT, int M>
-__global__ __launch_bounds__(kBlock) void k_spmv_sdia(int64_t n, DiaOffsets offs,
+// R consecutive values starting at p (8-byte aligned only: a shifted row may
+// start at an odd element; gfx950 global loads need no 16-byte alignment)
+template <int R, typename T>
+struct Run {
+    T v[R];
+};
+
+template <int R, typename T>
+__device__ __forceinline__ Run<R, T> ldrun(const T *p)
+{
+    Run<R, T> r;
+    __builtin_memcpy(&r, p, sizeof(r));
+    return r;
+}
+
+// Symmetric diagonal storage: row i reads the main diagonal, each upper
+// diagonal at i (entry (i, i+o)) and at i-o (entry (i-o, i) = (i, i-o) by
+// symmetry).  All loads are unit-stride across the wavefront (shifted copies
+// of the same arrays), so there are no index arrays and no gathers.  Block b
+// (after the XCD renumbering) owns rows [b rows, (b+1) rows).
+//
+// R = 1: one row per lane; every load is unconditional (indices clamped into
+// range) so the 4 M + 2 loads of a row issue back to back, and out-of-range
+// terms are dropped by a select afterwards.
+// R = 2: two consecutive rows per lane with 16-byte loads (half as many load
+// instructions); rows within the largest offset of either end take a
+// per-row path with explicit range tests.  Both forms add the terms of a row
+// in the same order: main, then (upper, lower) for each offset.
+template <typename TV, typename TX, bool DOT, int M, int R>
+__global__ __launch_bounds__(kBlock) void k_spmv_sdia(int64_t n, int64_t rows, DiaOffsets offs,
                                                       const TV *__restrict__ dia,
                                                       const TX *__restrict__ x, TX *__restrict__ y,
                                                       const uint8_t *__restrict__ bc, int bit,
@@ -264,40 +300,86 @@ __global__ __launch_bounds__(kBlock) void k_spmv_sdia(int64_t n, DiaOffsets offs
     if constexpr (DOT) {
         if (sc->stop) return;
     }
-    const int G = gridDim.x;
-    const int lb = xcd_block(blockIdx.x, G);
-    const int64_t per = (((n + G - 1) / G) + kBlock - 1) / kBlock * kBlock;
-    const int64_t r0 = (int64_t)lb * per;
-    const int64_t r1 = r0 + per < n ? r0 + per : n;
+    const int lb = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t r0 = (int64_t)lb * rows;
+    const int64_t r1 = r0 + rows < n ? r0 + rows : n;
     double acc = 0.0;
-    for (int64_t i = r0 + threadIdx.x; i < r1; i += kBlock) {
-        // every load is unconditional (indices clamped into range) so the
-        // 4 M + 2 loads of a row issue back to back; out-of-range terms are
-        // dropped by a select afterwards
-        const TX xi = x[i];
-        TX sum = (TX)dia[i] * xi;
-        TV up[M], lo[M];
-        TX xu[M], xl[M];
+    if constexpr (R == 1) {
+        for (int64_t i = r0 + threadIdx.x; i < r1; i += kBlock) {
+            const TX xi = x[i];
+            TX sum = (TX)dia[i] * xi;
+            TV up[M], lo[M];
+            TX xu[M], xl[M];
 #pragma unroll
-        for (int k = 0; k < M; ++k) {
-            const int64_t o = offs.o[k];
-            const TV *u = dia + (int64_t)(k + 1) * n;
-            const int64_t iu = i + o < n ? i + o : n - 1;
-            const int64_t il = i >= o ? i - o : 0;
-            up[k] = u[i];
-            xu[k] = x[iu];
-            lo[k] = u[il];
-            xl[k] = x[il];
-        }
+            for (int k = 0; k < M; ++k) {
+                const int64_t o = offs.o[k];
+                const TV *u = dia + (int64_t)(k + 1) * n;
+                const int64_t iu = i + o < n ? i + o : n - 1;
+                const int64_t il = i >= o ? i - o : 0;
+                up[k] = u[i];
+                xu[k] = x[iu];
+                lo[k] = u[il];
+                xl[k] = x[il];
+            }
 #pragma unroll
-        for (int k = 0; k < M; ++k) {
-            const int64_t o = offs.o[k];
-            sum += (i + o < n) ? (TX)up[k] * xu[k] : (TX)0;
-            sum += (i >= o) ? (TX)lo[k] * xl[k] : (TX)0;
+            for (int k = 0; k < M; ++k) {
+                const int64_t o = offs.o[k];
+                sum += (i + o < n) ? (TX)up[k] * xu[k] : (TX)0;
+                sum += (i >= o) ? (TX)lo[k] * xl[k] : (TX)0;
+            }
+            if (is_dirichlet(bc, bit, i)) sum = 0;
+            y[i] = sum;
+            if constexpr (DOT) acc += (double)xi * (double)sum;
         }
-        if (is_dirichlet(bc, bit, i)) sum = 0;
-        y[i] = sum;
-        if constexpr (DOT) acc += (double)xi * (double)sum;
+    } else {
+        const int64_t omax = offs.o[M - 1];
+        for (int64_t i = r0 + (int64_t)threadIdx.x * R; i < r1; i += (int64_t)kBlock * R) {
+            if (i >= omax && i + (R - 1) + omax < n) {
+                const Run<R, TX> xi = ldrun<R>(x + i);
+                const Run<R, TV> d0 = ldrun<R>(dia + i);
+                Run<R, TV> up[M], lo[M];
+                Run<R, TX> xu[M], xl[M];
+#pragma unroll
+                for (int k = 0; k < M; ++k) {
+                    const int64_t o = offs.o[k];
+                    const TV *u = dia + (int64_t)(k + 1) * n;
+                    up[k] = ldrun<R>(u + i);
+                    xu[k] = ldrun<R>(x + i + o);
+                    lo[k] = ldrun<R>(u + i - o);
+                    xl[k] = ldrun<R>(x + i - o);
+                }
+                Run<R, TX> out;
+#pragma unroll
+                for (int e = 0; e < R; ++e) {
+                    TX sum = (TX)d0.v[e] * xi.v[e];
+#pragma unroll
+                    for (int k = 0; k < M; ++k) {
+                        sum += (TX)up[k].v[e] * xu[k].v[e];
+                        sum += (TX)lo[k].v[e] * xl[k].v[e];
+                    }
+                    if (is_dirichlet(bc, bit, i + e)) sum = 0;
+                    out.v[e] = sum;
+                    if constexpr (DOT) acc += (double)xi.v[e] * (double)sum;
+                }
+                __builtin_memcpy(y + i, &out, sizeof(out));
+            } else {
+                for (int e = 0; e < R; ++e) {
+                    const int64_t j = i + e;
+                    if (j >= r1) break;
+                    const TX xj = x[j];
+                    TX sum = (TX)dia[j] * xj;
+                    for (int k = 0; k < M; ++k) {
+                        const int64_t o = offs.o[k];
+                        const TV *u = dia + (int64_t)(k + 1) * n;
+                        if (j + o < n) sum += (TX)u[j] * x[j + o];
+                        if (j >= o) sum += (TX)u[j - o] * x[j - o];
+                    }
+                    if (is_dirichlet(bc, bit, j)) sum = 0;
+                    y[j] = sum;
+                    if constexpr (DOT) acc += (double)xj * (double)sum;
+                }
+            }
+        }
     }
     if constexpr (DOT) {
         double v[1] = {acc};
@@ -315,12 +397,25 @@ struct alignas(sizeof(T) * V) Pack {
     T v[V];
 };
 
-// Elementwise loop over [0, n): each thread handles packs of V consecutive
-// elements (V > 1 needs 16-byte aligned arrays), then the scalar tail.
+// Elementwise loop over [0, n) in packs of V consecutive elements (V > 1
+// needs 16-byte aligned arrays).  With per > 0, block b (after the XCD
+// renumbering) owns packs [b per, (b+1) per) and block 0 also takes the
+// scalar tail; with per == 0 packs and tail are dealt grid-stride.
 template <int V, typename F>
-__device__ __forceinline__ void for_packs(int64_t n, F &&body)
+__device__ __forceinline__ void for_packs(int64_t n, int64_t per, F &&body)
 {
     const int64_t np = n / V;
+    if (per > 0) {
+        const int64_t j0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * per;
+        const int64_t j1 = j0 + per < np ? j0 + per : np;
+        for (int64_t j = j0 + threadIdx.x; j < j1; j += kBlock)
+            body(j * V, std::integral_constant<int, V>());
+        if constexpr (V > 1) {
+            if (blockIdx.x == 0 && threadIdx.x < n - np * V)
+                body(np * V + threadIdx.x, std::integral_constant<int, 1>());
+        }
+        return;
+    }
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     for (int64_t j = blockIdx.x * (int64_t)kBlock + threadIdx.x; j < np; j += stride)
         body(j * V, std::integral_constant<int, V>());
@@ -328,6 +423,55 @@ __device__ __forceinline__ void for_packs(int64_t n, F &&body)
         for (int64_t i = np * V + blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += stride)
             body(i, std::integral_constant<int, 1>());
     }
+}
+
+// for_packs for kernels that first need a block-wide prologue (the
+// re-reduction of the previous kernel's partials): each thread issues the
+// loads of its first pack before the prologue runs, so their memory latency
+// overlaps the prologue, and loads every further pack before it processes
+// the current one.  prologue() runs in every thread and returns the same
+// value in all threads of a block; false ends the loop (returns false).
+template <int V, typename Load, typename Pro, typename Body>
+__device__ __forceinline__ bool for_packs_ahead(int64_t n, int64_t per, Load &&load,
+                                                Pro &&prologue, Body &&body)
+{
+    using IV = std::integral_constant<int, V>;
+    using I1 = std::integral_constant<int, 1>;
+    const int64_t np = n / V;
+    int64_t j, j1, step;
+    if (per > 0) {
+        const int64_t j0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * per;
+        j = j0 + threadIdx.x;
+        j1 = j0 + per < np ? j0 + per : np;
+        step = kBlock;
+    } else {
+        j = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+        j1 = np;
+        step = (int64_t)gridDim.x * kBlock;
+    }
+    decltype(load(int64_t(0), IV())) cur{};
+    if (j < j1) cur = load(j * V, IV());
+    if (!prologue()) return false;
+    while (j < j1) {
+        const int64_t jn = j + step;
+        decltype(cur) nxt{};
+        if (jn < j1) nxt = load(jn * V, IV());
+        body(j * V, cur);
+        cur = nxt;
+        j = jn;
+    }
+    if constexpr (V > 1) {
+        if (per > 0) {
+            if (blockIdx.x == 0 && threadIdx.x < n - np * V) {
+                const int64_t i = np * V + threadIdx.x;
+                body(i, load(i, I1()));
+            }
+        } else {
+            for (int64_t i = np * V + blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += step)
+                body(i, load(i, I1()));
+        }
+    }
+    return true;
 }
 
 template <int W, typename T>
@@ -342,9 +486,21 @@ __device__ __forceinline__ void st(T *p, int64_t i, const Pack<T, W> &v)
     *reinterpret_cast<Pack<T, W> *>(p + i) = v;
 }
 
+template <typename TX, typename TD, int W>
+struct UpdatePacks {
+    Pack<TX, W> x, r, p, q;
+    Pack<TD, W> d;
+};
+
+template <typename TX, typename TD, int W>
+struct DirPacks {
+    Pack<TX, W> p, r;
+    Pack<TD, W> d;
+};
+
 // x += alpha p; r -= alpha q; partials of r^T D^-1 r and r^T r.
 template <typename TX, typename TD, int V>
-__global__ __launch_bounds__(kBlock) void k_update(int64_t n, TX *__restrict__ x,
+__global__ __launch_bounds__(kBlock) void k_update(int64_t n, int64_t per, TX *__restrict__ x,
                                                    TX *__restrict__ r, const TX *__restrict__ p,
                                                    const TX *__restrict__ q,
                                                    const TD *__restrict__ dinv,
@@ -353,41 +509,46 @@ __global__ __launch_bounds__(kBlock) void k_update(int64_t n, TX *__restrict__ x
                                                    double *__restrict__ part_out, int parity)
 {
     if (sc->stop) return;
-    double g[1];
-    load_reduced<1>(part_in, G_in, g);
-    const double gamma = g[0];
-    if (!(gamma > 0.0) || !isfinite(gamma)) {
+    TX alpha = 0;
+    auto load = [&](int64_t i, auto w) {
+        constexpr int W = decltype(w)::value;
+        return UpdatePacks<TX, TD, W>{ld<W>(x, i), ld<W>(r, i), ld<W>(p, i), ld<W>(q, i),
+                                      ld<W>(dinv, i)};
+    };
+    auto prologue = [&]() {
+        double g[1];
+        load_reduced<1>(part_in, G_in, g);
+        const double gamma = g[0];
+        if (!(gamma > 0.0) || !isfinite(gamma)) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) {
+                sc->gamma = gamma;
+                sc->stop = 2;
+            }
+            return false;
+        }
+        const double alpha_d = sc->rho[parity] / gamma;
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             sc->gamma = gamma;
-            sc->stop = 2;
+            sc->alpha = alpha_d;
         }
-        return;
-    }
-    const double alpha_d = sc->rho[parity] / gamma;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        sc->gamma = gamma;
-        sc->alpha = alpha_d;
-    }
-    const TX alpha = (TX)alpha_d;
+        alpha = (TX)alpha_d;
+        return true;
+    };
     double rz = 0.0, rr = 0.0;
-    for_packs<V>(n, [&](int64_t i, auto w) {
-        constexpr int W = decltype(w)::value;
-        auto xv = ld<W>(x, i);
-        auto rv = ld<W>(r, i);
-        const auto pv = ld<W>(p, i);
-        const auto qv = ld<W>(q, i);
-        const auto dv = ld<W>(dinv, i);
+    auto body = [&](int64_t i, auto in) {
+        constexpr int W = sizeof(in.x.v) / sizeof(TX);
 #pragma unroll
         for (int e = 0; e < W; ++e) {
-            xv.v[e] = xv.v[e] + alpha * pv.v[e];
-            rv.v[e] = rv.v[e] - alpha * qv.v[e];
-            const TX zi = (TX)dv.v[e] * rv.v[e];
-            rz += (double)rv.v[e] * (double)zi;
-            rr += (double)rv.v[e] * (double)rv.v[e];
+            in.x.v[e] = in.x.v[e] + alpha * in.p.v[e];
+            in.r.v[e] = in.r.v[e] - alpha * in.q.v[e];
+            const TX zi = (TX)in.d.v[e] * in.r.v[e];
+            rz += (double)in.r.v[e] * (double)zi;
+            rr += (double)in.r.v[e] * (double)in.r.v[e];
         }
-        st<W>(x, i, xv);
-        st<W>(r, i, rv);
-    });
+        st<W>(x, i, in.x);
+        st<W>(r, i, in.r);
+    };
+    if (!for_packs_ahead<V>(n, per, load, prologue, body)) return;
     double v[2] = {rz, rr};
     store_block_partials<2>(v, part_out);
 }
@@ -396,7 +557,7 @@ __global__ __launch_bounds__(kBlock) void k_update(int64_t n, TX *__restrict__ x
 // p = D^-1 r + beta p unless converged.  `count` is added to the iteration
 // counter (0 when used after a residual replacement).
 template <typename TX, typename TD, int V = 1>
-__global__ __launch_bounds__(kBlock) void k_pupdate(int64_t n, TX *__restrict__ p,
+__global__ __launch_bounds__(kBlock) void k_pupdate(int64_t n, int64_t per, TX *__restrict__ p,
                                                     const TX *__restrict__ r,
                                                     const TD *__restrict__ dinv,
                                                     Scalars *__restrict__ sc,
@@ -404,33 +565,38 @@ __global__ __launch_bounds__(kBlock) void k_pupdate(int64_t n, TX *__restrict__ 
                                                     int parity, int count)
 {
     if (sc->stop) return;
-    double v[2];
-    load_reduced<2>(part_in, G_in, v);
-    const double rho_new = v[0], rr = v[1];
-    const bool bad = !isfinite(rho_new) || !isfinite(rr);
-    const bool conv = !bad && rr <= sc->tol2 * sc->bb;
-    const double beta_d = rho_new / sc->rho[parity];
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        sc->rho[parity ^ 1] = rho_new;
-        sc->rr = rr;
-        sc->beta = beta_d;
-        sc->iter += count;
-        if (bad)
-            sc->stop = 2;
-        else if (conv)
-            sc->stop = 1;
-    }
-    if (bad || conv) return;
-    const TX beta = (TX)beta_d;
-    for_packs<V>(n, [&](int64_t i, auto w) {
+    TX beta = 0;
+    auto load = [&](int64_t i, auto w) {
         constexpr int W = decltype(w)::value;
-        auto pv = ld<W>(p, i);
-        const auto rv = ld<W>(r, i);
-        const auto dv = ld<W>(dinv, i);
+        return DirPacks<TX, TD, W>{ld<W>(p, i), ld<W>(r, i), ld<W>(dinv, i)};
+    };
+    auto prologue = [&]() {
+        double v[2];
+        load_reduced<2>(part_in, G_in, v);
+        const double rho_new = v[0], rr = v[1];
+        const bool bad = !isfinite(rho_new) || !isfinite(rr);
+        const bool conv = !bad && rr <= sc->tol2 * sc->bb;
+        const double beta_d = rho_new / sc->rho[parity];
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            sc->rho[parity ^ 1] = rho_new;
+            sc->rr = rr;
+            sc->beta = beta_d;
+            sc->iter += count;
+            if (bad)
+                sc->stop = 2;
+            else if (conv)
+                sc->stop = 1;
+        }
+        beta = (TX)beta_d;
+        return !(bad || conv);
+    };
+    auto body = [&](int64_t i, auto in) {
+        constexpr int W = sizeof(in.p.v) / sizeof(TX);
 #pragma unroll
-        for (int e = 0; e < W; ++e) pv.v[e] = (TX)dv.v[e] * rv.v[e] + beta * pv.v[e];
-        st<W>(p, i, pv);
-    });
+        for (int e = 0; e < W; ++e) in.p.v[e] = (TX)in.d.v[e] * in.r.v[e] + beta * in.p.v[e];
+        st<W>(p, i, in.p);
+    };
+    for_packs_ahead<V>(n, per, load, prologue, body);
 }
 
 // (singular: r -= mean r) z = D^-1 r; p = z; rho[0] = r^T z; rr = r^T r.
@@ -654,39 +820,54 @@ hns_status check_launch(const char *what)
     return HNS_OK;
 }
 
-template <typename TV, typename TX, bool DOT, int M>
-void sdia_launch(const DevMatrix &A, const TV *vals, const void *p, void *q, const uint8_t *bc,
-                 int bit, const Scalars *sc, double *part, hipStream_t s)
+// Rows per block of the diagonal SpMV: R rows per lane (two for FP64
+// vectors), `it` workgroup-sized passes per block, more passes when the grid
+// would exceed the partials slots.
+template <typename TX>
+Chunks sdia_chunks(const DevMatrix &A)
 {
+    constexpr int R = sizeof(TX) == 8 ? 2 : 1;
+    const int it = sizeof(TX) == 8 ? A.spmv_it64 : A.spmv_it32;
+    return chunks(A.n, (int64_t)kBlock * R * (it > 0 ? it : 1), (int64_t)kBlock * R);
+}
+
+template <typename TV, typename TX, bool DOT, int M>
+int sdia_launch(const DevMatrix &A, const TV *vals, const void *p, void *q, const uint8_t *bc,
+                int bit, const Scalars *sc, double *part, hipStream_t s)
+{
+    constexpr int R = sizeof(TX) == 8 ? 2 : 1;
     DiaOffsets offs;
     for (int k = 0; k < kMaxDiag; ++k) offs.o[k] = k < A.ndiag ? A.off[k] : 0;
-    k_spmv_sdia<TV, TX, DOT, M><<<spmv_grid(A), kBlock, 0, s>>>(A.n, offs, vals, (const TX *)p,
-                                                                (TX *)q, bc, bit, sc, part);
+    const Chunks c = sdia_chunks<TX>(A);
+    k_spmv_sdia<TV, TX, DOT, M, R><<<c.grid, kBlock, 0, s>>>(A.n, c.per, offs, vals,
+                                                             (const TX *)p, (TX *)q, bc, bit, sc,
+                                                             part);
+    return c.grid;
 }
 
 template <typename TV, typename TX, bool DOT, int M = 1>
-void sdia_dispatch(const DevMatrix &A, const TV *vals, const void *p, void *q, const uint8_t *bc,
-                   int bit, const Scalars *sc, double *part, hipStream_t s)
+int sdia_dispatch(const DevMatrix &A, const TV *vals, const void *p, void *q, const uint8_t *bc,
+                  int bit, const Scalars *sc, double *part, hipStream_t s)
 {
     if constexpr (M <= kMaxDiag) {
-        if (A.ndiag == M)
-            sdia_launch<TV, TX, DOT, M>(A, vals, p, q, bc, bit, sc, part, s);
-        else
-            sdia_dispatch<TV, TX, DOT, M + 1>(A, vals, p, q, bc, bit, sc, part, s);
+        if (A.ndiag == M) return sdia_launch<TV, TX, DOT, M>(A, vals, p, q, bc, bit, sc, part, s);
+        return sdia_dispatch<TV, TX, DOT, M + 1>(A, vals, p, q, bc, bit, sc, part, s);
     }
+    return 0;
 }
 
+// Launches q = A p (+ per-block partials of p^T q when DOT); returns the
+// grid, i.e. the number of partials written.
 template <typename TV, typename TX, bool DOT>
-void spmv_dispatch(const DevMatrix &A, const void *p, void *q, const uint8_t *bc, int bit,
-                   const Scalars *sc, double *part, hipStream_t s)
+int spmv_dispatch(const DevMatrix &A, const void *p, void *q, const uint8_t *bc, int bit,
+                  const Scalars *sc, double *part, hipStream_t s)
 {
-    const int G = spmv_grid(A);
     const bool f32 = std::is_same<TV, float>::value;
     if (A.fmt == HNS_FMT_SDIA) {
         const TV *vd = f32 ? (const TV *)(const void *)A.dia32 : (const TV *)(const void *)A.dia;
-        sdia_dispatch<TV, TX, DOT>(A, vd, p, q, bc, bit, sc, part, s);
-        return;
+        return sdia_dispatch<TV, TX, DOT>(A, vd, p, q, bc, bit, sc, part, s);
     }
+    const int G = spmv_grid(A);
     const TV *vs = f32 ? (const TV *)(const void *)A.sval32 : (const TV *)(const void *)A.sval;
     const TV *vc = f32 ? (const TV *)(const void *)A.val32 : (const TV *)(const void *)A.val;
     if (A.fmt == HNS_FMT_SELL)
@@ -695,6 +876,7 @@ void spmv_dispatch(const DevMatrix &A, const void *p, void *q, const uint8_t *bc
     else
         k_spmv_csr<TV, TX, DOT><<<G, kBlock, 0, s>>>(A.n, A.rowptr, A.col, vc, (const TX *)p,
                                                      (TX *)q, bc, bit, sc, part);
+    return G;
 }
 
 inline bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
@@ -704,32 +886,35 @@ hns_status iteration_impl(const IterArgs &a, int parity, hipStream_t s, hipEvent
 {
     constexpr int V = 16 / sizeof(TX);  // elements per 16-byte pack
     const uint8_t *bc = a.bit < 0 ? nullptr : a.bc;
-    const int Gs = spmv_grid(*a.A);
-    const int Gu = stream_grid((a.n + V - 1) / V);
     double *P1 = a.partials + kPartSpmv;
     double *P2 = a.partials + kPartUpdate;
     // packs need every operand 16-byte aligned (a row of a 3 x n array with n
     // odd is not): fall back to one element per thread then
     const bool vec = aligned16(a.x) && aligned16(a.r) && aligned16(a.p) && aligned16(a.q) &&
                      aligned16(a.dinv);
+    const Chunks cu = chunks(vec ? a.n / V : a.n, (int64_t)kBlock * a.A->vec_it, kBlock);
     if (ev) HNS_TRY_HIP(hipEventRecord(ev[0], s));
-    spmv_dispatch<TV, TX, true>(*a.A, a.p, a.q, bc, a.bit, a.sc, P1, s);
+    const int Gs = spmv_dispatch<TV, TX, true>(*a.A, a.p, a.q, bc, a.bit, a.sc, P1, s);
     if (ev) HNS_TRY_HIP(hipEventRecord(ev[1], s));
     if (vec)
-        k_update<TX, TD, V><<<Gu, kBlock, 0, s>>>(a.n, (TX *)a.x, (TX *)a.r, (const TX *)a.p,
-                                                  (const TX *)a.q, (const TD *)a.dinv, a.sc, P1,
-                                                  Gs, P2, parity);
+        k_update<TX, TD, V><<<cu.grid, kBlock, 0, s>>>(a.n, cu.per, (TX *)a.x, (TX *)a.r,
+                                                       (const TX *)a.p, (const TX *)a.q,
+                                                       (const TD *)a.dinv, a.sc, P1, Gs, P2,
+                                                       parity);
     else
-        k_update<TX, TD, 1><<<Gu, kBlock, 0, s>>>(a.n, (TX *)a.x, (TX *)a.r, (const TX *)a.p,
-                                                  (const TX *)a.q, (const TD *)a.dinv, a.sc, P1,
-                                                  Gs, P2, parity);
+        k_update<TX, TD, 1><<<cu.grid, kBlock, 0, s>>>(a.n, cu.per, (TX *)a.x, (TX *)a.r,
+                                                       (const TX *)a.p, (const TX *)a.q,
+                                                       (const TD *)a.dinv, a.sc, P1, Gs, P2,
+                                                       parity);
     if (ev) HNS_TRY_HIP(hipEventRecord(ev[2], s));
     if (vec)
-        k_pupdate<TX, TD, V><<<Gu, kBlock, 0, s>>>(a.n, (TX *)a.p, (const TX *)a.r,
-                                                   (const TD *)a.dinv, a.sc, P2, Gu, parity, 1);
+        k_pupdate<TX, TD, V><<<cu.grid, kBlock, 0, s>>>(a.n, cu.per, (TX *)a.p, (const TX *)a.r,
+                                                        (const TD *)a.dinv, a.sc, P2, cu.grid,
+                                                        parity, 1);
     else
-        k_pupdate<TX, TD, 1><<<Gu, kBlock, 0, s>>>(a.n, (TX *)a.p, (const TX *)a.r,
-                                                   (const TD *)a.dinv, a.sc, P2, Gu, parity, 1);
+        k_pupdate<TX, TD, 1><<<cu.grid, kBlock, 0, s>>>(a.n, cu.per, (TX *)a.p, (const TX *)a.r,
+                                                        (const TD *)a.dinv, a.sc, P2, cu.grid,
+                                                        parity, 1);
     if (ev) HNS_TRY_HIP(hipEventRecord(ev[3], s));
     return check_launch("cg iteration");
 }
@@ -754,6 +939,20 @@ int spmv_grid(const DevMatrix &A)
     if (g < 1) g = 1;
     if (g >= 8) g &= ~int64_t(7);
     return (int)g;
+}
+
+Chunks chunks(int64_t units, int64_t per, int64_t quantum)
+{
+    per = per < quantum ? quantum : (per + quantum - 1) / quantum * quantum;
+    int64_t g = (units + per - 1) / per;
+    if (g > kMaxPart) {
+        // more units per block (whole quanta) to stay within the slots
+        per = ((units + kMaxPart - 1) / kMaxPart + quantum - 1) / quantum * quantum;
+        g = (units + per - 1) / per;
+    }
+    if (g < 1) g = 1;
+    if (g >= 8) g = (g + 7) / 8 * 8;   // the few extra blocks find no units
+    return {(int)g, per};
 }
 
 hns_status launch_spmv_plain(const DevMatrix &A, bool fp32, const void *p, void *q,
@@ -838,19 +1037,19 @@ hns_status launch_replace_residual(int64_t n, Prec prec, const double *r64, void
         k_replace_rz<float, float><<<Gu, kBlock, 0, s>>>(n, r64, (float *)r, (const float *)dinv,
                                                          P2);
         HNS_TRY(check_launch("replace_rz"));
-        k_pupdate<float, float><<<Gu, kBlock, 0, s>>>(n, (float *)p, (const float *)r,
+        k_pupdate<float, float><<<Gu, kBlock, 0, s>>>(n, 0, (float *)p, (const float *)r,
                                                       (const float *)dinv, sc, P2, Gu, parity, 0);
     } else if (prec == Prec::F32Store) {
         k_replace_rz<double, float><<<Gu, kBlock, 0, s>>>(n, r64, nullptr, (const float *)dinv,
                                                           P2);
         HNS_TRY(check_launch("replace_rz"));
-        k_pupdate<double, float><<<Gu, kBlock, 0, s>>>(n, (double *)p, r64, (const float *)dinv,
+        k_pupdate<double, float><<<Gu, kBlock, 0, s>>>(n, 0, (double *)p, r64, (const float *)dinv,
                                                        sc, P2, Gu, parity, 0);
     } else {
         k_replace_rz<double, double><<<Gu, kBlock, 0, s>>>(n, r64, nullptr,
                                                            (const double *)dinv, P2);
         HNS_TRY(check_launch("replace_rz"));
-        k_pupdate<double, double><<<Gu, kBlock, 0, s>>>(n, (double *)p, r64,
+        k_pupdate<double, double><<<Gu, kBlock, 0, s>>>(n, 0, (double *)p, r64,
                                                         (const double *)dinv, sc, P2, Gu, parity,
                                                         0);
     }

@@ -730,6 +730,12 @@ hns_status hns_set_param(hns_operator *op, const char *name, double value)
         op->bspmm_vec = (int)value;
     } else if (k == "use_graph" && (value == 0 || value == 1)) {
         op->use_graph = (int)value;
+    } else if (k == "spmv_it64" && value >= 1 && value <= 64 && value == (int)value) {
+        op->A.spmv_it64 = (int)value;
+    } else if (k == "spmv_it32" && value >= 1 && value <= 64 && value == (int)value) {
+        op->A.spmv_it32 = (int)value;
+    } else if (k == "vec_it" && value >= 1 && value <= 64 && value == (int)value) {
+        op->A.vec_it = (int)value;
     } else {
         set_error("unknown parameter or bad value: %s = %g", name, value);
         return HNS_ERR_INVALID;
