@@ -78,7 +78,7 @@ def make_forcing(m):
 
 
 COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "counters_spmv_sdia_fp64_basin256x256x20.md")
-KERNEL_SOURCES = ("kernels.hip", "kernels.h")
+KERNEL_SOURCES = ("kernels.hip", "kernels.h", "hns_internal.h")
 
 
 def kernel_source_hash():
