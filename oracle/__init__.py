@@ -59,6 +59,11 @@ def lib():
         L.or_spmv.argtypes = [vp, dp, dp]
         L.or_spmv_t.argtypes = [vp, dp, dp, C.c_int64]
         L.or_pcg.restype = C.c_int
+        L.or_pcg_line.restype = C.c_int
+        L.or_pcg_line.argtypes = [vp, u8p, C.c_int, dp, dp, dp, C.c_double, C.c_int, C.c_int64,
+                                  C.POINTER(C.c_int), dp, dp, dp, dp, dp]
+        L.or_tridiag_solve.restype = C.c_int
+        L.or_tridiag_solve.argtypes = [C.c_int64, dp, dp, dp, dp, dp]
         L.or_pcg.argtypes = [vp, u8p, C.c_int, dp, dp, dp, C.c_double, C.c_int,
                              C.POINTER(C.c_int), dp, dp, dp, dp, dp]
         L.or_relres.restype = C.c_double
@@ -200,8 +205,10 @@ class PCGResult:
 
 
 def pcg(A: Matrix, b, dirichlet=None, singular=False, weights=None, x0=None,
-        tol=1e-10, maxit=100000, history=False, x_history=False) -> PCGResult:
-    """Jacobi-PCG on A after eliminating `dirichlet` nodes (boolean (n,) or None)."""
+        tol=1e-10, maxit=100000, history=False, x_history=False, line=0) -> PCGResult:
+    """Preconditioned CG on A after eliminating `dirichlet` nodes (boolean (n,)
+    or None).  line = 0: Jacobi (inverse diagonal); line = L >= 1: inverse of
+    the tridiagonal blocks on the consecutive columns of L nodes."""
     n = A.n
     b = _f64(b)
     x = np.zeros(n) if x0 is None else _f64(x0).copy()
@@ -213,14 +220,31 @@ def pcg(A: Matrix, b, dirichlet=None, singular=False, weights=None, x0=None,
     ah = np.zeros(maxit) if history else None
     bh = np.zeros(maxit) if history else None
     xh = np.zeros((maxit, n)) if x_history else None
-    st = lib().or_pcg(A._h, _u8(dmask), int(bool(singular)), None if w is None else _d(w),
-                      _d(b), _d(x), tol, maxit, C.byref(it), _d(rel), _d(rm),
-                      None if ah is None else _d(ah), None if bh is None else _d(bh),
-                      None if xh is None else _d(xh))
+    st = lib().or_pcg_line(A._h, _u8(dmask), int(bool(singular)), None if w is None else _d(w),
+                           _d(b), _d(x), tol, maxit, int(line), C.byref(it), _d(rel), _d(rm),
+                           None if ah is None else _d(ah), None if bh is None else _d(bh),
+                           None if xh is None else _d(xh))
     k = it.value
     return PCGResult(x=x, status=st, iterations=k, relres=float(rel[0]), removed_mean=float(rm[0]),
                      alphas=None if ah is None else ah[:k], betas=None if bh is None else bh[:k],
                      x_hist=None if xh is None else xh[:k])
+
+
+def tridiag_solve(d, e, r):
+    """z = T^-1 r for the symmetric tridiagonal T = tridiag(e, d, e) (Thomas)."""
+    d = _f64(d)
+    e = _f64(e)
+    r = _f64(r)
+    L = d.shape[0]
+    if e.shape[0] < max(L - 1, 0) or r.shape[0] != L:
+        raise ValueError("tridiag_solve: need len(e) >= len(d) - 1 and len(r) == len(d)")
+    e = np.concatenate([e[:max(L - 1, 0)], np.zeros(1)])
+    z = np.empty(L)
+    work = np.empty(L)
+    st = lib().or_tridiag_solve(L, _d(d), _d(e), _d(r), _d(z), _d(work))
+    if st != OK:
+        raise OracleError(st, "tridiag_solve")
+    return z
 
 
 def relres(A: Matrix, b, x, dirichlet=None) -> float:

@@ -18,7 +18,12 @@
  *   - assembly of those forms into compressed sparse rows;
  *   - the surface-tension load int_{Gamma_s} theta v ds (eq. fofa_velo_pred_h);
  *   - preconditioned conjugate gradients with a diagonal preconditioner
- *     (Remark 1 and the DIAG part of Remark 2 at the end of Sec. 5);
+ *     (Remark 1 and the DIAG part of Remark 2 at the end of Sec. 5), or with
+ *     the inverse of the vertical-line (water column) blocks of the matrix,
+ *     a block-diagonal preconditioner the paper does not use: it stands in
+ *     for its unavailable line-search preconditioner of Remark 2 and makes
+ *     the isotropic pressure operator of eq. fofa_q_cor_h tractable on thin
+ *     meshes;
  *   - a dense Cholesky factorisation for tiny systems.
  */
 #include <math.h>
@@ -399,6 +404,68 @@ or_csr *or_eliminate(const or_csr *A, const uint8_t *dirichlet)
 }
 
 /* ------------------------------------------------------------------------ */
+/* Tridiagonal solve of one water column                                     */
+/* ------------------------------------------------------------------------ */
+
+/* Solves T z = r for the symmetric tridiagonal T of order L with diagonal
+ * d[0..L-1] and off-diagonal e[0..L-2] (T[k][k+1] = T[k+1][k] = e[k]) by
+ * Gaussian elimination from the top of the column down, then substitution
+ * from the bottom up (the Thomas algorithm, no pivoting: T is symmetric
+ * positive definite here).  Every division is a product with the inverse
+ * pivot w[k] = 1 / u[k], so that L = 1 gives z = (1 / d) r exactly as the
+ * point Jacobi preconditioner does.  work holds L doubles.  Returns
+ * OR_ERR_BREAKDOWN on a non-positive pivot. */
+int or_tridiag_solve(int64_t L, const double *d, const double *e, const double *r, double *z,
+                     double *work)
+{
+    double *w = work;
+    double u = d[0];
+    if (!(u > 0.0)) return OR_ERR_BREAKDOWN;
+    w[0] = 1.0 / u;
+    z[0] = r[0] * w[0];
+    for (int64_t k = 1; k < L; ++k) {
+        double c = e[k - 1] * w[k - 1]; /* multiplier of row k-1 */
+        u = d[k] - e[k - 1] * c;
+        if (!(u > 0.0)) return OR_ERR_BREAKDOWN;
+        w[k] = 1.0 / u;
+        z[k] = (r[k] - e[k - 1] * z[k - 1]) * w[k];
+    }
+    for (int64_t k = L - 2; k >= 0; --k) z[k] = z[k] - (e[k] * w[k]) * z[k + 1];
+    return OR_OK;
+}
+
+/* Column blocks of A: for nodes i = c L + k (column c, level k), ld[i] =
+ * A[i][i] and le[i] = A[i][i+1] when i+1 is in the same column, else 0. */
+static void column_blocks(const or_csr *A, int64_t L, double *ld, double *le)
+{
+    for (int64_t i = 0; i < A->n; ++i) {
+        ld[i] = 0.0;
+        le[i] = 0.0;
+        int last = (i % L) == L - 1;
+        for (int64_t s = A->rowptr[i]; s < A->rowptr[i + 1]; ++s) {
+            if (A->col[s] == i) ld[i] = A->val[s];
+            if (!last && A->col[s] == i + 1) le[i] = A->val[s];
+        }
+    }
+}
+
+/* z = M^-1 r for the preconditioner of or_pcg_line: the inverse diagonal
+ * (line_len == 0) or the inverse of the column blocks (line_len >= 1). */
+static int apply_prec(int64_t n, int64_t line_len, const double *dinv, const double *ld,
+                      const double *le, const double *r, double *z, double *work)
+{
+    if (line_len == 0) {
+        for (int64_t i = 0; i < n; ++i) z[i] = dinv[i] * r[i];
+        return OR_OK;
+    }
+    for (int64_t c0 = 0; c0 < n; c0 += line_len) {
+        int st = or_tridiag_solve(line_len, ld + c0, le + c0, r + c0, z + c0, work);
+        if (st != OR_OK) return st;
+    }
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Jacobi-preconditioned conjugate gradient                                  */
 /* ------------------------------------------------------------------------ */
 
@@ -424,13 +491,21 @@ or_csr *or_eliminate(const or_csr *A, const uint8_t *dirichlet)
  * zero) and the last iterate on exit.  alpha_hist / beta_hist / x_hist may be
  * NULL; otherwise they receive the step lengths, the direction updates and the
  * iterates (maxit rows of n) of each iteration.
+ *
+ * line_len = 0 selects the inverse diagonal; line_len = L >= 1 selects the
+ * inverse of the tridiagonal blocks of the eliminated matrix on the columns
+ * {c L, ..., c L + L - 1} (the water columns of the vertical-first node
+ * numbering; n must be a multiple of L), applied by or_tridiag_solve.
+ * or_pcg is or_pcg_line with line_len = 0.
  */
-int or_pcg(const or_csr *A0, const uint8_t *dirichlet, int singular,
-           const double *weights, const double *b0, double *x, double tol,
-           int maxit, int *iters_out, double *relres_out, double *removed_mean,
-           double *alpha_hist, double *beta_hist, double *x_hist)
+int or_pcg_line(const or_csr *A0, const uint8_t *dirichlet, int singular,
+                const double *weights, const double *b0, double *x, double tol,
+                int maxit, int64_t line_len, int *iters_out, double *relres_out,
+                double *removed_mean, double *alpha_hist, double *beta_hist,
+                double *x_hist)
 {
     int64_t n = A0->n;
+    if (line_len < 0 || (line_len > 0 && n % line_len != 0)) return OR_ERR_INVALID;
     *iters_out = 0;
     *relres_out = 0.0;
     if (removed_mean) *removed_mean = 0.0;
@@ -444,8 +519,11 @@ int or_pcg(const or_csr *A0, const uint8_t *dirichlet, int singular,
     double *p = malloc(sizeof(double) * (size_t)n);
     double *q = malloc(sizeof(double) * (size_t)n);
     double *dinv = malloc(sizeof(double) * (size_t)n);
+    double *ld = line_len ? malloc(sizeof(double) * (size_t)n) : NULL;
+    double *le = line_len ? malloc(sizeof(double) * (size_t)n) : NULL;
+    double *work = line_len ? malloc(sizeof(double) * (size_t)line_len) : NULL;
     int status = OR_NOT_CONVERGED;
-    if (!A || !b || !r || !z || !p || !q || !dinv) {
+    if (!A || !b || !r || !z || !p || !q || !dinv || (line_len && (!ld || !le || !work))) {
         status = OR_ERR_NOMEM;
         goto done;
     }
@@ -468,6 +546,7 @@ int or_pcg(const or_csr *A0, const uint8_t *dirichlet, int singular,
         }
         dinv[i] = 1.0 / d;
     }
+    if (line_len) column_blocks(A, line_len, ld, le);
     double bnorm = sqrt(dot(n, b, b));
     if (bnorm == 0.0) {
         for (int64_t i = 0; i < n; ++i) x[i] = 0.0;
@@ -477,7 +556,8 @@ int or_pcg(const or_csr *A0, const uint8_t *dirichlet, int singular,
     or_spmv(A, x, q);
     for (int64_t i = 0; i < n; ++i) r[i] = b[i] - q[i];
     if (singular) remove_mean(n, r);
-    for (int64_t i = 0; i < n; ++i) z[i] = dinv[i] * r[i];
+    if ((status = apply_prec(n, line_len, dinv, ld, le, r, z, work)) != OR_OK) goto done;
+    status = OR_NOT_CONVERGED;
     for (int64_t i = 0; i < n; ++i) p[i] = z[i];
     double rho = dot(n, r, z);
     double relres = sqrt(dot(n, r, r)) / bnorm;
@@ -514,14 +594,16 @@ int or_pcg(const or_csr *A0, const uint8_t *dirichlet, int singular,
             }
             /* restart from the true residual */
             memcpy(r, q, sizeof(double) * (size_t)n);
-            for (int64_t i = 0; i < n; ++i) z[i] = dinv[i] * r[i];
+            if ((status = apply_prec(n, line_len, dinv, ld, le, r, z, work)) != OR_OK) break;
+            status = OR_NOT_CONVERGED;
             for (int64_t i = 0; i < n; ++i) p[i] = z[i];
             rho = dot(n, r, z);
             relres = true_rel;
             if (beta_hist) beta_hist[it - 1] = 0.0;
             continue;
         }
-        for (int64_t i = 0; i < n; ++i) z[i] = dinv[i] * r[i];
+        if ((status = apply_prec(n, line_len, dinv, ld, le, r, z, work)) != OR_OK) break;
+        status = OR_NOT_CONVERGED;
         double rho_new = dot(n, r, z);
         double beta = rho_new / rho;
         if (beta_hist) beta_hist[it - 1] = beta;
@@ -548,7 +630,19 @@ done:
     free(p);
     free(q);
     free(dinv);
+    free(ld);
+    free(le);
+    free(work);
     return status;
+}
+
+int or_pcg(const or_csr *A0, const uint8_t *dirichlet, int singular, const double *weights,
+           const double *b0, double *x, double tol, int maxit, int *iters_out,
+           double *relres_out, double *removed_mean, double *alpha_hist, double *beta_hist,
+           double *x_hist)
+{
+    return or_pcg_line(A0, dirichlet, singular, weights, b0, x, tol, maxit, 0, iters_out,
+                       relres_out, removed_mean, alpha_hist, beta_hist, x_hist);
 }
 
 /* True relative residual ||mask(b - A x)|| / ||mask(b)|| with Dirichlet rows
