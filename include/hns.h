@@ -218,6 +218,13 @@ int64_t hns_operator_nnz(const hns_operator *op);
 uint32_t hns_operator_format(const hns_operator *op);
 int hns_operator_ndiag(const hns_operator *op);
 
+/* Length of the water columns of the node numbering: nodes c L .. c L + L - 1
+ * share their horizontal position (x, y) for every column c, as in the
+ * vertical-first numbering of a terrain-following mesh; 0 when the numbering
+ * is not made of such columns (the line preconditioner is then unavailable),
+ * -1 for a null operator. */
+int hns_operator_line_len(const hns_operator *op);
+
 /* Tunables (returns HNS_ERR_INVALID for an unknown name or a bad value):
  *   "check_every"  CG iterations between host convergence reads (default 32)
  *   "inner_tol"    relative tolerance of each FP32 inner solve (default 1e-5)
@@ -242,7 +249,20 @@ int hns_operator_ndiag(const hns_operator *op);
  *   "vec_it"       16-byte packs per thread of the single-vector CG updates
  *                  (default 3; integers 1..64).  The three change the grid
  *                  (and with it the summation order of the dot products),
- *                  not the arithmetic of a row or a pack. */
+ *                  not the arithmetic of a row or a pack.
+ *   "precond"      0 = point Jacobi, the inverse diagonal (default; the
+ *                  diagonal preconditioner of the paper's Sec. 5 remarks);
+ *                  1 = vertical-line blocks: the inverse of the tridiagonal
+ *                  block of each water column (the diagonal plus the
+ *                  couplings between vertically adjacent nodes, Dirichlet
+ *                  rows replaced by the identity), solved by the Thomas
+ *                  recurrences with pivots factorised once per Dirichlet set
+ *                  on first use (2 n doubles of device memory per set).  It
+ *                  keeps CG's iteration count bounded on thin meshes whose
+ *                  vertical couplings dwarf the horizontal ones, e.g. the
+ *                  isotropic pressure operator of eq. fofa_q_cor_h.
+ *                  Needs hns_operator_line_len >= 2; HNS_FP64 single
+ *                  right-hand-side solves only (HNS_ERR_INVALID otherwise). */
 hns_status hns_set_param(hns_operator *op, const char *name, double value);
 
 /* y = A x on the device (FP64), with the rows of Dirichlet set mask_bit

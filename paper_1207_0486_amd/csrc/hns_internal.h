@@ -128,6 +128,19 @@ struct hns_operator {
     std::vector<hns::BWorkspace *> bws_free;
     int bspmm_vec = 0;                     // 0: autotune per (k, mode); else 1, 2 or 4
     std::vector<std::array<int, 3>> tuned; // (k, mixed, V) chosen by the autotuner
+    // vertical-line preconditioner: the rows form water columns of line_len
+    // consecutive nodes (0 when the numbering has none).  Host copies of the
+    // column blocks (diagonal; coupling to the next node of the column, 0 at
+    // the column top) and of the Dirichlet bits; device factors per mask
+    // (index mask_bit + 1: masked off-diagonal, then inverse pivots, 2 n
+    // doubles), built on first use.
+    int line_len = 0;
+    int precond = 0;                       // 0 point Jacobi, 1 vertical-line blocks
+    std::vector<double> line_d, line_e;
+    std::vector<uint8_t> bc_host;
+    std::mutex line_mutex;
+    double *line_fac[9] = {nullptr, nullptr, nullptr, nullptr, nullptr,
+                           nullptr, nullptr, nullptr, nullptr};
 };
 
 namespace hns {

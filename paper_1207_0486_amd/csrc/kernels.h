@@ -65,6 +65,12 @@ struct IterArgs {
     int bit;
     Scalars *sc;
     double *partials;   // kPartTotal doubles
+    // vertical-line preconditioner (FP64 only): when lfac is set, z = M^-1 r
+    // by the column blocks of `line_len` consecutive rows; lfac holds the
+    // masked off-diagonal (n) then the inverse pivots (n); z is an n-vector
+    const double *lfac = nullptr;
+    double *z = nullptr;
+    int line_len = 0;
 };
 
 // One CG iteration = three launches:
@@ -97,6 +103,17 @@ hns_status launch_init_dir(int64_t n, Prec prec, void *r, void *p, const void *d
                            bool singular, bool bb_from_rr, Scalars *sc, double *partials,
                            hipStream_t s);
 // (singular: r -= mean r) rr = r^T r, FP64 residual of the refinement loop
+// Columns per block of the line-preconditioned kernels (0 if the column is
+// too long for one block's LDS) and the grid that covers all columns.
+int line_cols_per_block(int line_len);
+int line_grid(int64_t n, int line_len);
+
+// Line-preconditioned first direction (FP64): (singular: r -= mean r);
+// z = M^-1 r; p = z; rho[0] = r^T z; rr = r^T r (and bb = rr if asked).
+hns_status launch_init_line(int64_t n, int line_len, double *r, double *p, const double *lfac,
+                            bool singular, bool bb_from_rr, Scalars *sc, double *partials,
+                            hipStream_t s);
+
 hns_status launch_project_norm(int64_t n, double *r, bool singular, Scalars *sc,
                                double *partials, hipStream_t s);
 // r32 = (float)(r64 / sqrt(rr)), d32 = 0

@@ -636,6 +636,191 @@ __global__ __launch_bounds__(kBlock) void k_init_dir(int64_t n, TX *__restrict__
     }
 }
 
+// ---------------------------------------------------------------------------
+// Vertical-line (water column) block preconditioner
+// ---------------------------------------------------------------------------
+// The rows of the vertical-first numbering form columns of L consecutive
+// nodes; z = M^-1 r solves each column's tridiagonal block (diagonal and the
+// couplings to the nodes above and below) by the Thomas recurrences with
+// precomputed inverse pivots w and masked off-diagonal e:
+//   y_0 = r_0 w_0,  y_k = (r_k - e_{k-1} y_{k-1}) w_k,
+//   z_{L-1} = y_{L-1},  z_k = y_k - (e_k w_k) z_{k+1}.
+// A block owns NC whole columns: its rows are staged through LDS with
+// coalesced loads, one lane per column runs the two recurrences, and the
+// result goes back to HBM coalesced.
+
+// Thomas recurrences of the columns staged in LDS: sr holds r (read), se, sw
+// the factors, sy receives z; returns this lane's share of r^T z.
+__device__ __forceinline__ double line_columns(int ncols, int L, const double *sr,
+                                               const double *se, const double *sw, double *sy)
+{
+    double rz = 0.0;
+    if ((int)threadIdx.x < ncols) {
+        const int b = threadIdx.x * L;
+        double y = sr[b] * sw[b];
+        sy[b] = y;
+        for (int k = 1; k < L; ++k) {
+            y = (sr[b + k] - se[b + k - 1] * y) * sw[b + k];
+            sy[b + k] = y;
+        }
+        double z = y;
+        rz += sr[b + L - 1] * z;
+        for (int k = L - 2; k >= 0; --k) {
+            z = sy[b + k] - (se[b + k] * sw[b + k]) * z;
+            sy[b + k] = z;
+            rz += sr[b + k] * z;
+        }
+    }
+    return rz;
+}
+
+template <int W>
+struct LinePacks {
+    Pack<double, W> p, z;
+};
+
+// x += alpha p; r -= alpha q; z = M^-1 r; partials of r^T z and r^T r.
+__global__ __launch_bounds__(kBlock) void k_update_line(
+    int64_t n, int L, int NC, double *__restrict__ x, double *__restrict__ r,
+    const double *__restrict__ p, const double *__restrict__ q, double *__restrict__ z,
+    const double *__restrict__ lfac, Scalars *__restrict__ sc,
+    const double *__restrict__ part_in, int G_in, double *__restrict__ part_out, int parity)
+{
+    if (sc->stop) return;
+    extern __shared__ double line_lds[];
+    double g[1];
+    load_reduced<1>(part_in, G_in, g);
+    const double gamma = g[0];
+    if (!(gamma > 0.0) || !isfinite(gamma)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            sc->gamma = gamma;
+            sc->stop = 2;
+        }
+        return;
+    }
+    const double alpha = sc->rho[parity] / gamma;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->gamma = gamma;
+        sc->alpha = alpha;
+    }
+    const int span = NC * L;
+    double *sr = line_lds, *se = sr + span, *sw = se + span, *sy = sw + span;
+    const int64_t row0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * span;
+    const int64_t left = n - row0;
+    const int rows = left <= 0 ? 0 : (left < span ? (int)left : span);
+    const double *le = lfac, *lw = lfac + n;
+    double rr = 0.0;
+    for (int t = threadIdx.x; t < rows; t += kBlock) {
+        const int64_t i = row0 + t;
+        const double xi = x[i] + alpha * p[i];
+        const double ri = r[i] - alpha * q[i];
+        x[i] = xi;
+        r[i] = ri;
+        sr[t] = ri;
+        se[t] = le[i];
+        sw[t] = lw[i];
+        rr += ri * ri;
+    }
+    __syncthreads();
+    const double rz = line_columns(rows / L, L, sr, se, sw, sy);
+    __syncthreads();
+    for (int t = threadIdx.x; t < rows; t += kBlock) z[row0 + t] = sy[t];
+    double v[2] = {rz, rr};
+    store_block_partials<2>(v, part_out);
+}
+
+// rho' = r^T z, rr = r^T r from the line update's partials; beta = rho'/rho;
+// p = z + beta p unless converged.
+__global__ __launch_bounds__(kBlock) void k_pupdate_line(int64_t n, int64_t per,
+                                                         double *__restrict__ p,
+                                                         const double *__restrict__ z,
+                                                         Scalars *__restrict__ sc,
+                                                         const double *__restrict__ part_in,
+                                                         int G_in, int parity)
+{
+    if (sc->stop) return;
+    double beta = 0.0;
+    auto load = [&](int64_t i, auto w) {
+        constexpr int W = decltype(w)::value;
+        return LinePacks<W>{ld<W>(p, i), ld<W>(z, i)};
+    };
+    auto prologue = [&]() {
+        double v[2];
+        load_reduced<2>(part_in, G_in, v);
+        const double rho_new = v[0], rr = v[1];
+        const bool bad = !isfinite(rho_new) || !isfinite(rr);
+        const bool conv = !bad && rr <= sc->tol2 * sc->bb;
+        beta = rho_new / sc->rho[parity];
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            sc->rho[parity ^ 1] = rho_new;
+            sc->rr = rr;
+            sc->beta = beta;
+            sc->iter += 1;
+            if (bad)
+                sc->stop = 2;
+            else if (conv)
+                sc->stop = 1;
+        }
+        return !(bad || conv);
+    };
+    auto body = [&](int64_t i, auto in) {
+        constexpr int W = sizeof(in.p.v) / sizeof(double);
+#pragma unroll
+        for (int e = 0; e < W; ++e) in.p.v[e] = in.z.v[e] + beta * in.p.v[e];
+        st<W>(p, i, in.p);
+    };
+    for_packs_ahead<2>(n, per, load, prologue, body);
+}
+
+// (singular: r -= mean r); z = M^-1 r; p = z; rho[0] = r^T z; rr = r^T r.
+__global__ __launch_bounds__(kBlock) void k_init_line(int64_t n, int L, int NC,
+                                                      double *__restrict__ r,
+                                                      double *__restrict__ p,
+                                                      const double *__restrict__ lfac,
+                                                      int singular, int bb_from_rr,
+                                                      Scalars *__restrict__ sc,
+                                                      double *__restrict__ partials)
+{
+    extern __shared__ double line_lds[];
+    const double mean = singular ? sc->sum_r / (double)n : 0.0;
+    const int span = NC * L;
+    double *sr = line_lds, *se = sr + span, *sw = se + span, *sy = sw + span;
+    const int64_t row0 = (int64_t)blockIdx.x * span;
+    const int64_t left = n - row0;
+    const int rows = left <= 0 ? 0 : (left < span ? (int)left : span);
+    const double *le = lfac, *lw = lfac + n;
+    double rr = 0.0;
+    for (int t = threadIdx.x; t < rows; t += kBlock) {
+        const int64_t i = row0 + t;
+        double ri = r[i];
+        if (singular) {
+            ri -= mean;
+            r[i] = ri;
+        }
+        sr[t] = ri;
+        se[t] = le[i];
+        sw[t] = lw[i];
+        rr += ri * ri;
+    }
+    __syncthreads();
+    const double rz = line_columns(rows / L, L, sr, se, sw, sy);
+    __syncthreads();
+    for (int t = threadIdx.x; t < rows; t += kBlock) p[row0 + t] = sy[t];
+    double v[2] = {rz, rr};
+    if (grid_sum<2>(v, partials, &sc->counter[2]) && threadIdx.x == 0) {
+        sc->rho[0] = v[0];
+        sc->rr = v[1];
+        sc->beta = 0.0;
+        if (bb_from_rr) sc->bb = v[1];
+        if (!(sc->bb > 0.0))
+            sc->stop = 3;
+        else if (!isfinite(v[0]) || !isfinite(v[1]))
+            sc->stop = 2;
+        else
+            sc->stop = (v[1] <= sc->tol2 * sc->bb) ? 1 : 0;
+    }
+}
+
 // Residual replacement: the working residual becomes the FP64 true residual
 // (converted to TX when dst is given, else src is the working residual), with
 // per-block partials of r^T D^-1 r and r^T r for the k_pupdate that follows.
@@ -881,6 +1066,30 @@ int spmv_dispatch(const DevMatrix &A, const void *p, void *q, const uint8_t *bc,
 
 inline bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 
+constexpr int kLineLds = 49152;   // bytes of LDS for the staged columns of one block
+
+hns_status line_iteration(const IterArgs &a, int parity, hipStream_t s, hipEvent_t *ev)
+{
+    const uint8_t *bc = a.bit < 0 ? nullptr : a.bc;
+    double *P1 = a.partials + kPartSpmv;
+    double *P2 = a.partials + kPartUpdate;
+    const int L = a.line_len;
+    const int NC = line_cols_per_block(L);
+    const int Gl = line_grid(a.n, L);
+    const Chunks cu = chunks(a.n / 2, (int64_t)kBlock * a.A->vec_it, kBlock);
+    if (ev) HNS_TRY_HIP(hipEventRecord(ev[0], s));
+    const int Gs = spmv_dispatch<double, double, true>(*a.A, a.p, a.q, bc, a.bit, a.sc, P1, s);
+    if (ev) HNS_TRY_HIP(hipEventRecord(ev[1], s));
+    k_update_line<<<Gl, kBlock, (size_t)4 * NC * L * sizeof(double), s>>>(
+        a.n, L, NC, (double *)a.x, (double *)a.r, (const double *)a.p, (const double *)a.q,
+        a.z, a.lfac, a.sc, P1, Gs, P2, parity);
+    if (ev) HNS_TRY_HIP(hipEventRecord(ev[2], s));
+    k_pupdate_line<<<cu.grid, kBlock, 0, s>>>(a.n, cu.per, (double *)a.p, a.z, a.sc, P2, Gl,
+                                              parity);
+    if (ev) HNS_TRY_HIP(hipEventRecord(ev[3], s));
+    return check_launch("line-preconditioned cg iteration");
+}
+
 template <typename TV, typename TX, typename TD>
 hns_status iteration_impl(const IterArgs &a, int parity, hipStream_t s, hipEvent_t *ev)
 {
@@ -966,8 +1175,44 @@ hns_status launch_spmv_plain(const DevMatrix &A, bool fp32, const void *p, void 
     return check_launch("spmv");
 }
 
+int line_cols_per_block(int line_len)
+{
+    if (line_len < 1) return 0;
+    int nc = kLineLds / (4 * (int)sizeof(double) * line_len);
+    return nc > 64 ? 64 : nc;   // one wavefront runs the recurrences
+}
+
+int line_grid(int64_t n, int line_len)
+{
+    const int nc = line_cols_per_block(line_len);
+    if (nc < 1) return 0;
+    const int64_t cols = n / line_len;
+    int64_t g = (cols + nc - 1) / nc;
+    if (g >= 8) g = (g + 7) / 8 * 8;
+    return (int)g;
+}
+
+hns_status launch_init_line(int64_t n, int line_len, double *r, double *p, const double *lfac,
+                            bool singular, bool bb_from_rr, Scalars *sc, double *partials,
+                            hipStream_t s)
+{
+    const int NC = line_cols_per_block(line_len);
+    const int G = line_grid(n, line_len);
+    k_init_line<<<G, kBlock, (size_t)4 * NC * line_len * sizeof(double), s>>>(
+        n, line_len, NC, r, p, lfac, singular ? 1 : 0, bb_from_rr ? 1 : 0, sc,
+        partials + kPartMisc);
+    return check_launch("init_line");
+}
+
 hns_status launch_iteration(const IterArgs &a, int parity, hipStream_t s, hipEvent_t *ev)
 {
+    if (a.lfac) {
+        if (a.prec != Prec::F64) {
+            set_error("the line preconditioner runs in FP64 only");
+            return HNS_ERR_INVALID;
+        }
+        return line_iteration(a, parity, s, ev);
+    }
     switch (a.prec) {
     case Prec::F64: return iteration_impl<double, double, double>(a, parity, s, ev);
     case Prec::F32: return iteration_impl<float, float, float>(a, parity, s, ev);

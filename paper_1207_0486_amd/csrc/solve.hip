@@ -31,6 +31,7 @@ struct Workspace {
     double *r = nullptr, *p = nullptr, *q = nullptr;
     float *r32 = nullptr, *p32 = nullptr, *q32 = nullptr, *d32 = nullptr;
     double *partials = nullptr;   // kPartTotal doubles
+    double *z = nullptr;          // M^-1 r of the line preconditioner (allocated on first use)
     Scalars *sc = nullptr;        // [0] FP64 / outer loop, [1] inner FP32 loop
     Scalars *host = nullptr;      // pinned mirror of sc[0..1]
     std::vector<hipEvent_t> ev;   // timing events, 4 per iteration of a chunk
@@ -84,9 +85,23 @@ struct Workspace {
         return HNS_OK;
     }
 
+    hns_status ensure_z()
+    {
+        if (z) return HNS_OK;
+        hipError_t e = hipMalloc(&z, n * sizeof(double));
+        if (e != hipSuccess) {
+            z = nullptr;
+            set_error("allocation of the preconditioned residual failed: %s",
+                      hipGetErrorString(e));
+            return e == hipErrorOutOfMemory ? HNS_ERR_OOM : HNS_ERR_HIP;
+        }
+        return HNS_OK;
+    }
+
     ~Workspace()
     {
         for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+        if (z) (void)hipFree(z);
         if (block) (void)hipFree(block);
         if (host) (void)hipHostFree(host);
     }
@@ -156,6 +171,7 @@ struct SolveCtx {
     int max_iter;
     hipStream_t s;
     Workspace *w;
+    const double *lfac = nullptr;   // line-preconditioner factors of this mask (FP64 solves)
 };
 
 // Enqueue `count` CG iterations of one recurrence.  parity0 is the number of
@@ -165,11 +181,17 @@ struct SolveCtx {
 // iteration counter after each chunk.
 static hns_status enqueue_iterations(hns_operator *op, Workspace *w, Prec prec, int bit, void *x,
                                      void *r, void *p, void *q, const void *dinv, Scalars *sc,
-                                     int count, int parity0, hipStream_t s)
+                                     int count, int parity0, hipStream_t s,
+                                     const double *lfac = nullptr)
 {
     const int period = op->profile;
     if (period > 0) HNS_TRY(w->ensure_events(4 * (size_t)count));
     IterArgs a{&op->A, prec, op->n, x, r, p, q, dinv, op->bc, bit, sc, w->partials};
+    if (lfac) {
+        a.lfac = lfac;
+        a.z = w->z;
+        a.line_len = op->line_len;
+    }
     for (int it = 0; it < count; ++it) {
         const bool timed = period > 0 && (it % period) == 0;
         HNS_TRY(launch_iteration(a, (parity0 + it) & 1, s, timed ? &w->ev[4 * it] : nullptr));
@@ -209,7 +231,7 @@ static hns_status run_chunks(const SolveCtx &c, int which, Prec prec, void *x, v
         const int chunk = left < op->check_every ? left : op->check_every;
         const int before = h.iter;
         HNS_TRY(enqueue_iterations(op, w, prec, c.bit, x, r, p, q, dinv, w->sc + which, chunk,
-                                   *since_start, c.s));
+                                   *since_start, c.s, prec == Prec::F64 ? c.lfac : nullptr));
         HNS_TRY(pull_scalars(w, which, c.s));
         *since_start += h.iter - before;
         HNS_TRY(account_iterations(op, w, prec == Prec::F32, h.iter - before));
@@ -303,8 +325,12 @@ static hns_status solve_fp64_vectors(const SolveCtx &c, hns_solve_info *info, Pr
             }
             h.stop = 0;
             HNS_TRY(push_scalars(w, 0, c.s));
-            HNS_TRY(launch_init_dir(op->n, prec, w->r, w->p, dinv, false, false, w->sc,
-                                    w->partials, c.s));
+            if (c.lfac && prec == Prec::F64)
+                HNS_TRY(launch_init_line(op->n, op->line_len, w->r, w->p, c.lfac, false, false,
+                                         w->sc, w->partials, c.s));
+            else
+                HNS_TRY(launch_init_dir(op->n, prec, w->r, w->p, dinv, false, false, w->sc,
+                                        w->partials, c.s));
             HNS_TRY(pull_scalars(w, 0, c.s));
             since = 0;
             fresh = false;
@@ -528,6 +554,44 @@ const char *hns_status_string(hns_status s)
     return "unknown status";
 }
 
+// Water columns of the node numbering: the first L nodes share (x, y), and
+// so does every later run of L nodes, each at its own (x, y).  Returns L, or 0
+// when the numbering is not made of such columns.
+static int detect_columns(const hns_mesh *mesh)
+{
+    const int64_t n = mesh->n_nodes;
+    const double *X = mesh->xyz;
+    if (n < 2 || !X) return 0;
+    auto same_xy = [X](int64_t a, int64_t b) {
+        return X[3 * a] == X[3 * b] && X[3 * a + 1] == X[3 * b + 1];
+    };
+    int64_t L = 1;
+    while (L < n && same_xy(0, L)) ++L;
+    if (L < 2 || n % L != 0 || L > (1 << 20)) return 0;
+    for (int64_t c = 0; c < n; c += L) {
+        for (int64_t k = 1; k < L; ++k)
+            if (!same_xy(c, c + k)) return 0;
+        if (c + L < n && same_xy(c, c + L)) return 0;
+    }
+    return (int)L;
+}
+
+// Column blocks of the assembled matrix for the line preconditioner.
+static void keep_column_blocks(hns_operator *op, const HostCSR &A, int L, const uint8_t *bc)
+{
+    op->line_len = L;
+    op->line_d.assign(A.n, 0.0);
+    op->line_e.assign(A.n, 0.0);
+    for (int64_t i = 0; i < A.n; ++i) {
+        const bool top = (i % L) == L - 1;
+        for (int32_t k = A.rowptr[i]; k < A.rowptr[i + 1]; ++k) {
+            if (A.col[k] == i) op->line_d[i] = A.val[k];
+            if (!top && A.col[k] == i + 1) op->line_e[i] = A.val[k];
+        }
+    }
+    if (bc) op->bc_host.assign(bc, bc + A.n);
+}
+
 static hns_status finish_operator(hns_operator *op, const HostCSR &A, uint32_t fmt_flag,
                                   const std::vector<double> &lumped, const uint8_t *bc_host)
 {
@@ -643,6 +707,10 @@ hns_status hns_assemble(const hns_mesh *mesh, double nu_h, double nu_v, double d
         op->n = A.n;
         st = finish_operator(op, A, fmt, lumped, mesh->bc);
     }
+    if (st == HNS_OK) {
+        const int L = detect_columns(mesh);
+        if (L >= 2) keep_column_blocks(op, A, L, mesh->bc);
+    }
     if (st == HNS_OK && (flags & HNS_STEP_AUX)) st = assemble_step_aux(op, mesh, A);
     if (st != HNS_OK) {
         hns_operator_destroy(op);
@@ -664,6 +732,8 @@ void hns_operator_destroy(hns_operator *op)
     void *ptrs[] = {op->dinv, op->dinv32, op->bc, op->lumped, op->step_tmp};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
+    for (double *f : op->line_fac)
+        if (f) (void)hipFree(f);
     for (Workspace *w : op->ws_free) delete w;
     for (BWorkspace *w : op->bws_free) destroy_bworkspace(w);
     delete op;
@@ -703,6 +773,8 @@ hns_status hns_profile_read(const hns_operator *op, int kernel, double *total_ms
 int64_t hns_operator_n(const hns_operator *op) { return op ? op->n : -1; }
 int64_t hns_operator_nnz(const hns_operator *op) { return op ? op->A.nnz : -1; }
 uint32_t hns_operator_format(const hns_operator *op) { return op ? op->A.fmt : 0; }
+int hns_operator_line_len(const hns_operator *op) { return op ? op->line_len : -1; }
+
 int hns_operator_ndiag(const hns_operator *op)
 {
     if (!op) return -1;
@@ -736,6 +808,20 @@ hns_status hns_set_param(hns_operator *op, const char *name, double value)
         op->A.spmv_it32 = (int)value;
     } else if (k == "vec_it" && value >= 1 && value <= 64 && value == (int)value) {
         op->A.vec_it = (int)value;
+    } else if (k == "precond" && (value == 0 || value == 1)) {
+        if (value == 1) {
+            if (op->line_len < 2) {
+                set_error("precond = 1 needs a node numbering made of water columns");
+                return HNS_ERR_INVALID;
+            }
+            const int G = line_grid(op->n, op->line_len);
+            if (G < 1 || G > kMaxPart) {
+                set_error("line preconditioner: %lld nodes in columns of %d do not fit the "
+                          "launch shape", (long long)op->n, op->line_len);
+                return HNS_ERR_INVALID;
+            }
+        }
+        op->precond = (int)value;
     } else {
         set_error("unknown parameter or bad value: %s = %g", name, value);
         return HNS_ERR_INVALID;
@@ -748,7 +834,10 @@ size_t hns_footprint_bytes(const hns_operator *op, int k, uint32_t mode, int inc
     if (!op || k < 1) return 0;
     const bool mixed = (mode == HNS_MIXED);
     size_t b = k == 1 ? Workspace::bytes_for(op->n, mixed) : bworkspace_bytes(op->n, k, mixed);
+    if (k == 1 && op->precond == 1) b += (size_t)op->n * sizeof(double);   // z
     if (include_operator) {
+        for (const double *f : op->line_fac)
+            if (f) b += 2 * (size_t)op->n * sizeof(double);
         b += op->A.bytes() + (size_t)op->n * (8 + 1 + 8);
         if (op->dinv32) b += (size_t)op->n * 4;
         if (op->has_aux)
@@ -787,6 +876,53 @@ static hns_status check_solve_args(hns_operator *op, int mask_bit, const void *b
     return HNS_OK;
 }
 
+// Device factors of the line preconditioner for Dirichlet set `bit` (-1 =
+// none): the column blocks with Dirichlet rows and columns replaced by the
+// identity, factorised top-down (u_0 = d_0, u_k = d_k - e_{k-1}^2 / u_{k-1});
+// stored as the masked couplings e followed by the inverse pivots 1 / u.
+static hns_status line_factors(hns_operator *op, int bit, const double **out)
+{
+    std::lock_guard<std::mutex> g(op->line_mutex);
+    double *&slot = op->line_fac[bit + 1];
+    if (!slot) {
+        const int64_t n = op->n;
+        const int L = op->line_len;
+        const bool masked = bit >= 0 && !op->bc_host.empty();
+        auto dir = [&](int64_t i) { return masked && ((op->bc_host[i] >> bit) & 1u); };
+        std::vector<double> host(2 * (size_t)n);
+        double *e = host.data(), *w = host.data() + n;
+        for (int64_t c0 = 0; c0 < n; c0 += L) {
+            for (int64_t i = c0; i < c0 + L; ++i) {
+                const bool top = (i == c0 + L - 1);
+                e[i] = (top || dir(i) || dir(i + 1)) ? 0.0 : op->line_e[i];
+                const double d = dir(i) ? 1.0 : op->line_d[i];
+                const double u = (i == c0) ? d : d - e[i - 1] * (e[i - 1] * w[i - 1]);
+                if (!(u > 0.0) || !std::isfinite(u)) {
+                    set_error("column block of node %lld is not positive definite",
+                              (long long)i);
+                    return HNS_ERR_BREAKDOWN;
+                }
+                w[i] = 1.0 / u;
+            }
+        }
+        double *dev = nullptr;
+        hipError_t err = hipMalloc(&dev, host.size() * sizeof(double));
+        if (err != hipSuccess) {
+            set_error("allocation of line factors failed: %s", hipGetErrorString(err));
+            return err == hipErrorOutOfMemory ? HNS_ERR_OOM : HNS_ERR_HIP;
+        }
+        err = hipMemcpy(dev, host.data(), host.size() * sizeof(double), hipMemcpyHostToDevice);
+        if (err != hipSuccess) {
+            (void)hipFree(dev);
+            set_error("upload of line factors failed: %s", hipGetErrorString(err));
+            return HNS_ERR_HIP;
+        }
+        slot = dev;
+    }
+    *out = slot;
+    return HNS_OK;
+}
+
 hns_status hns_solve(hns_operator *op, int mask_bit, const double *b_dev, double *x_dev,
                      double tol, int max_iter, uint32_t mode, void *stream, hns_solve_info *info)
 {
@@ -804,14 +940,31 @@ hns_status hns_solve(hns_operator *op, int mask_bit, const double *b_dev, double
         info->status = HNS_ERR_BREAKDOWN;
         return HNS_ERR_BREAKDOWN;
     }
+    const double *lfac = nullptr;
+    if (op->precond == 1) {
+        if (mode != HNS_FP64) {
+            set_error("the line preconditioner runs with HNS_FP64 only");
+            info->status = HNS_ERR_INVALID;
+            return HNS_ERR_INVALID;
+        }
+        st = line_factors(op, mask_bit, &lfac);
+        if (st != HNS_OK) {
+            info->status = st;
+            return st;
+        }
+    }
     Workspace *w = nullptr;
     st = acquire_ws(op, mode == HNS_MIXED, &w);
+    if (st == HNS_OK && lfac) {
+        st = w->ensure_z();
+        if (st != HNS_OK) release_ws(op, w);
+    }
     if (st != HNS_OK) {
         info->status = st;
         return st;
     }
     SolveCtx c{op, mask_bit, op->kind == HNS_POISSON && mask_bit < 0, b_dev, x_dev, tol,
-               max_iter, (hipStream_t)stream, w};
+               max_iter, (hipStream_t)stream, w, lfac};
     st = (mode == HNS_MIXED) ? solve_mixed(c, info) : solve_fp64(c, info);
     info->status = st;
     release_ws(op, w);
@@ -896,6 +1049,10 @@ hns_status hns_solve_batched(hns_operator *op, int k, const int *mask_bits, cons
     }
     for (int j = 0; j < k && j < 1024; ++j) memset(&infos[j], 0, sizeof(hns_solve_info));
     HNS_TRY(check_batched_args(op, k, mask_bits, B_dev, X_dev, tol, max_iter, mode));
+    if (op->precond != 0) {
+        set_error("multi-right-hand-side solves use the point Jacobi preconditioner only");
+        return HNS_ERR_INVALID;
+    }
     if (op->bad_diag >= 0) {
         set_error("diagonal entry %lld is not positive: Jacobi-PCG needs an SPD operator",
                   (long long)op->bad_diag);

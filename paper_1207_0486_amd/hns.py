@@ -120,6 +120,7 @@ class Operator:
         self.nnz = int(L.lib().hns_operator_nnz(h))
         self.format = FORMAT_NAMES.get(int(L.lib().hns_operator_format(h)), "?")
         self.ndiag = int(L.lib().hns_operator_ndiag(h))
+        self.line_len = int(L.lib().hns_operator_line_len(h))
         self.keep_fp32 = keep_fp32
 
     # -- lifetime -------------------------------------------------------
