@@ -193,6 +193,55 @@ def bench_batched(torch, log, reps=3):
     return out
 
 
+def bench_isotropic(torch, log, m, b_q, point_cap=3000):
+    """The paper's isotropic pressure Laplacian (nu = 1) on the 256x256x20 basin
+    with the projection step's pressure right-hand side: vertical-line block
+    preconditioner to 1e-9, against point Jacobi capped at `point_cap`
+    iterations."""
+    import basin
+    from paper_1207_0486_amd.hns import Operator
+    wl = basin.configs.BASIN_256x256x20_ISO
+    t0 = time.time()
+    op = Operator(m, wl.nu_h, wl.nu_v, kind="poisson")
+    op.set_param("check_every", 32)
+    log(f"isotropic pressure operator: line_len={op.line_len} ({time.time() - t0:.1f}s)")
+    n, nnz = op.n, op.nnz
+    fmt = op.format
+
+    def solve(precond, tol, max_iter, reps):
+        op.set_param("precond", precond)
+        best, info = None, None
+        for _ in range(reps):
+            x = torch.zeros_like(b_q)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            x, info = op.solve(b_q, x, tol=tol, max_iter=max_iter, check=False)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t
+            best = el if best is None else min(best, el)
+        return best, info
+
+    solve(1, wl.tol, 100000, 1)                       # warm-up (factors, workspace)
+    t_line, i_line = solve(1, wl.tol, 100000, 3)
+    # bytes per line-preconditioned iteration: operator + 2 (SpMV) + 9 (update
+    # reads x, r, p, q, couplings, pivots; writes x, r, z) + 3 (p-update) passes
+    line_bytes = i_line.iterations * (matrix_bytes(fmt, n, nnz, 8) + 14 * 8 * n)
+    t_pt, i_pt = solve(0, wl.tol, point_cap, 1)
+    out = {
+        "workload": wl.name, "nu": [wl.nu_h, wl.nu_h, wl.nu_v], "tol": wl.tol,
+        "rhs": "pressure right-hand side of time step 1 (the anisotropic step's -(1/dt) B u~)",
+        "line": {"ms": round(1e3 * t_line, 3), "iterations": i_line.iterations,
+                 "status": i_line.status, "relres": i_line.relres_true,
+                 "us_per_iter": round(1e6 * t_line / max(i_line.iterations, 1), 2),
+                 "GBs": round(line_bytes / t_line / 1e9, 1)},
+        "point_jacobi_capped": {"ms": round(1e3 * t_pt, 3), "iterations": i_pt.iterations,
+                                "status": i_pt.status, "relres": i_pt.relres_true},
+    }
+    op.close()
+    log(f"isotropic: {out}")
+    return out
+
+
 def bench_serving(torch, log, budget_gb=16.0, mode="fp64", count=256):
     """Serving: Poisson-process arrivals (50 req/s) of pressure / velocity solve
     requests over five mesh sizes, tolerance 1e-8, continuous batching with
@@ -307,6 +356,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-isotropic", action="store_true")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="only a 1 GiB copy and 64 pressure iterations (for counter passes)")
     ap.add_argument("--no-serving", action="store_true")
@@ -427,6 +477,10 @@ def main():
         log(f"mixed: {msm:.1f} ms/step (x{ms64 / msm:.2f}), "
             + ", ".join(f"{k}={i.iterations}/{i.outer_iterations}" for k, i in infosm.items()))
 
+    isotropic = None
+    if not args.no_isotropic:
+        isotropic = bench_isotropic(torch, log, m, st.b_q.clone())
+
     batched = None
     if not args.no_batched:
         batched = bench_batched(torch, log)
@@ -482,6 +536,7 @@ def main():
                      "bytes_per_launch": spmv_bytes, "avg_us": round(spmv_avg_us, 2)},
         "pressure_kernels": kern,
         "mixed": mixed,
+        "isotropic_pressure": isotropic,
         "batched": batched,
         "serving": serving,
         "cpu_baseline": cpu,
