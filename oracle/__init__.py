@@ -62,6 +62,8 @@ def lib():
         L.or_pcg_line.restype = C.c_int
         L.or_pcg_line.argtypes = [vp, u8p, C.c_int, dp, dp, dp, C.c_double, C.c_int, C.c_int64,
                                   C.POINTER(C.c_int), dp, dp, dp, dp, dp]
+        L.or_advection.restype = C.c_int
+        L.or_advection.argtypes = [C.c_int64, dp, C.c_int64, ip, dp, dp]
         L.or_tridiag_solve.restype = C.c_int
         L.or_tridiag_solve.argtypes = [C.c_int64, dp, dp, dp, dp, dp]
         L.or_pcg.argtypes = [vp, u8p, C.c_int, dp, dp, dp, C.c_double, C.c_int,
@@ -228,6 +230,19 @@ def pcg(A: Matrix, b, dirichlet=None, singular=False, weights=None, x0=None,
     return PCGResult(x=x, status=st, iterations=k, relres=float(rel[0]), removed_mean=float(rm[0]),
                      alphas=None if ah is None else ah[:k], betas=None if bh is None else bh[:k],
                      x_hist=None if xh is None else xh[:k])
+
+
+def advection(mesh, u):
+    """(3, n) array of int ((u . grad) u_c) phi_a dx for the P1 velocity u (3, n)."""
+    u = np.ascontiguousarray(u, dtype=np.float64).reshape(3, -1)
+    xyz = _f64(mesh.xyz)
+    tets = np.ascontiguousarray(mesh.tets, dtype=np.int32)
+    n = xyz.shape[0]
+    out = np.empty((3, n))
+    st = lib().or_advection(n, _d(xyz), tets.shape[0], _i(tets), _d(u), _d(out))
+    if st != OK:
+        raise OracleError(st, "advection")
+    return out
 
 
 def tridiag_solve(d, e, r):

@@ -17,6 +17,8 @@
  *     eq. fofa_velo_pred_h through its transpose);
  *   - assembly of those forms into compressed sparse rows;
  *   - the surface-tension load int_{Gamma_s} theta v ds (eq. fofa_velo_pred_h);
+ *   - the explicit advection term int ((u . grad) u_c) phi ds of the same
+ *     equation, evaluated at a given velocity;
  *   - preconditioned conjugate gradients with a diagonal preconditioner
  *     (Remark 1 and the DIAG part of Remark 2 at the end of Sec. 5), or with
  *     the inverse of the vertical-line (water column) blocks of the matrix,
@@ -278,6 +280,52 @@ int or_assemble(int64_t n, const double *xyz, int64_t ntet, const int32_t *tets,
     *out = trip_to_csr(&t);
     trip_free(&t);
     return *out ? OR_OK : OR_ERR_NOMEM;
+}
+
+/* Explicit advection term of the velocity prediction (Sec. 3 eq. pred_velo,
+ * Sec. 5 eq. fofa_velo_pred_h): for each component c and node a,
+ *   out[c][a] = int ((u . grad) u_c) phi_a dx
+ * for the P1 velocity u with nodal values u[c][i] (3 x n, component-major).
+ * On a tetrahedron grad u_c is constant, G_c = sum_b u_c(b) grad phi_b, and
+ * (u . grad) u_c = sum_b phi_b (u(b) . G_c) is linear, so the integral is the
+ * element mass matrix applied to the nodal values s_b = u(b) . G_c. */
+int or_advection(int64_t n, const double *xyz, int64_t ntet, const int32_t *tets,
+                 const double *u, double *out)
+{
+    if (n <= 0 || ntet < 0) return OR_ERR_INVALID;
+    if (check_conn(n, ntet, 4, tets) != OR_OK) return OR_ERR_MESH;
+    for (int64_t i = 0; i < 3 * n; ++i) out[i] = 0.0;
+    const double one[3] = {1.0, 1.0, 1.0};
+    for (int64_t e = 0; e < ntet; ++e) {
+        double X[12], M[16], B[48];
+        int64_t v[4];
+        for (int a = 0; a < 4; ++a) {
+            v[a] = tets[e * 4 + a];
+            for (int d = 0; d < 3; ++d) X[a * 3 + d] = xyz[v[a] * 3 + d];
+        }
+        double vol = or_element(X, one, NULL, M, B);
+        if (!(vol > 0.0)) return OR_ERR_MESH;
+        /* grad phi_b [d] = B[d][a][b] * 4 / vol for any a */
+        double g[4][3];
+        for (int b = 0; b < 4; ++b)
+            for (int d = 0; d < 3; ++d) g[b][d] = B[d * 16 + b] * 4.0 / vol;
+        for (int c = 0; c < 3; ++c) {
+            double G[3] = {0.0, 0.0, 0.0};
+            for (int b = 0; b < 4; ++b)
+                for (int d = 0; d < 3; ++d) G[d] += u[c * n + v[b]] * g[b][d];
+            double sv[4];
+            for (int b = 0; b < 4; ++b) {
+                sv[b] = 0.0;
+                for (int d = 0; d < 3; ++d) sv[b] += u[d * n + v[b]] * G[d];
+            }
+            for (int a = 0; a < 4; ++a) {
+                double r = 0.0;
+                for (int b = 0; b < 4; ++b) r += M[a * 4 + b] * sv[b];
+                out[c * n + v[a]] += r;
+            }
+        }
+    }
+    return OR_OK;
 }
 
 /* Mass matrix of the surface Gamma_s from its triangles: on a triangle of
