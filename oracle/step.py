@@ -104,18 +104,27 @@ class OracleLoop:
                   consistent mass matrix with the Dirichlet set of component c.
     The multiplication of the BDF2 equations by 2 dt / 3 turns the operator
     3/(2dt) M + K_nu into M + tau K_nu.
+
+    The pressure operator is the isotropic gradient form of eq. fofa_q_cor_h
+    (pressure_nu = (1, 1)) solved with the vertical-line block preconditioner
+    at tolerance pressure_tol (default: the step tolerance); with the
+    anisotropic K_nu in its place the loop is unstable on the basin meshes
+    (the vertical velocity grows about a hundredfold per step).
     """
     mesh: object
     nu_h: float
     nu_v: float
     dt: float
     advect: bool = True
+    pressure_nu: tuple = (1.0, 1.0)
+    pressure_line: bool = True
+    pressure_tol: float | None = None
 
     def __post_init__(self):
         m = self.mesh
         self.taus = (self.dt, 2.0 * self.dt / 3.0)
         self.A = [helmholtz(m, self.nu_h, self.nu_v, t) for t in self.taus]
-        self.K = stiffness(m, self.nu_h, self.nu_v)
+        self.K = stiffness(m, *self.pressure_nu)
         self.M = mass(m)
         self.B = [divergence(m, c) for c in range(3)]
         self.Ms = surface_mass(m)
@@ -160,7 +169,9 @@ class OracleLoop:
         if not project:
             return dict(b_vel=b, ut=ut, u=ut.copy(), p=p)
         bq = -(1.0 / tau) * sum(self.B[c].matvec(ut[c]) for c in range(3))
-        rq = pcg(self.K, bq, singular=True, weights=self.mL, tol=tol)
+        ptol = tol if self.pressure_tol is None else self.pressure_tol
+        rq = pcg(self.K, bq, singular=True, weights=self.mL, tol=ptol,
+                 line=(self.mesh.Nz + 1) if self.pressure_line else 0)
         assert rq.status == OK, rq.status
         p_new = (np.zeros(self.mesh.n) if p is None else p) + rq.x
         rhs = np.zeros_like(ut)
