@@ -77,7 +77,8 @@ typedef struct {
                                 first step, BDF2 uses dt' = 2 dt / 3)                */
 /* Options */
 #define HNS_KEEP_FP32 0x10u  /* also keep FP32 matrix/diagonal copies (HNS_MIXED)  */
-#define HNS_STEP_AUX  0x20u  /* also keep M, B_1..3, lumped mass and surface mass
+#define HNS_STEP_AUX  0x20u  /* also keep M, B_1..3, lumped mass, surface mass and
+                                the mesh (coordinates, tetrahedra, node incidence)
                                 for the step right-hand sides (hns_step_*)          */
 /* Storage format of A on the device (default: chosen from the pattern) */
 #define HNS_FMT_AUTO  0x000u
@@ -315,6 +316,47 @@ hns_status hns_step_pressure_rhs(hns_operator *helm, const double *ut_dev, doubl
  * (may be NULL). */
 hns_status hns_step_correct(hns_operator *helm, const double *ut_dev, const double *q_dev,
                             double *p_dev, double *u_dev, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Multi-step loop (Sec. 3 BDF2 scheme; Sec. 5 eqs. fofa_velo_pred_h,
+ * fofa_q_cor_h, fofa_pres_cor_h, fofa_velo_cor_h).  Multiplying the BDF2
+ * prediction by tau = 2 dt / 3 gives the operator M + tau K_nu (assemble a
+ * HNS_HELMHOLTZ operator with dt = tau); the first step is implicit Euler
+ * (tau = dt).  These calls use the auxiliary forms and the mesh kept by a
+ * HNS_STEP_AUX operator `aux` (any dt); all vectors are device arrays, 3 x n
+ * component-major for velocities; each call synchronises `stream`.
+ * ------------------------------------------------------------------------ */
+
+/* Explicit advection term: out_c[a] = int ((u . grad) u_c) phi_a dx for the P1
+ * velocity u_dev (3 x n), c = 1..3.  u_dev and out_dev must not alias. */
+hns_status hns_step_advection(hns_operator *aux, const double *u_dev, double *out_dev,
+                              void *stream);
+
+/* Prediction right-hand side of a BDF step:
+ *   b_c = a1 M u_c + a2 M u'_c + tau (M_s theta_c + C_c(u) - adv_c + B_c^T p),
+ * C_1 = M (f u_2), C_2 = -M (f u_1), C_3 = 0; zero on each component's
+ * Dirichlet set.  BDF2: a1 = 4/3, a2 = -1/3 with u' = u^{k-1}; implicit Euler:
+ * a1 = 1, a2 = 0 (uprev_dev may then be NULL).  p_dev, theta_dev (2 x n),
+ * f_dev and adv_dev (3 x n, from hns_step_advection) may be NULL (term
+ * absent). */
+hns_status hns_step_velocity_rhs_bdf(hns_operator *aux, double tau, double a1,
+                                     const double *u_dev, double a2, const double *uprev_dev,
+                                     const double *p_dev, const double *theta_dev,
+                                     const double *f_dev, const double *adv_dev, double *b_dev,
+                                     void *stream);
+
+/* Pressure-increment right-hand side b = -(1/tau) sum_c B_c u~_c. */
+hns_status hns_step_pressure_rhs_tau(hns_operator *aux, double tau, const double *ut_dev,
+                                     double *b_dev, void *stream);
+
+/* Consistent-mass velocity correction (eq. fofa_velo_cor_h with the sign of
+ * the correction equations): p += q when p_dev is not NULL, and
+ *   rhs_c = M u~_c - tau B_c q, zero on the Dirichlet set of component c,
+ * the right-hand side of M u_c = rhs_c, solved with hns_solve on a mass
+ * operator (HNS_HELMHOLTZ assembled with nu_h = nu_v = dt = 0) and mask c. */
+hns_status hns_step_correct_rhs(hns_operator *aux, double tau, const double *ut_dev,
+                                const double *q_dev, double *p_dev, double *rhs_dev,
+                                void *stream);
 
 /* y = F x for one auxiliary form F of a HNS_STEP_AUX operator:
  * which = 0 M, 1..3 B_c, 4..6 B_c^T, 7 M_s (testing and diagnostics). */

@@ -77,6 +77,14 @@ _SIGNATURES = {
     "hns_step_correct": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                    C.c_void_p]),
     "hns_apply_aux": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "hns_step_advection": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "hns_step_velocity_rhs_bdf": (C.c_int, [C.c_void_p, C.c_double, C.c_double, C.c_void_p,
+                                            C.c_double, C.c_void_p, C.c_void_p, C.c_void_p,
+                                            C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "hns_step_pressure_rhs_tau": (C.c_int, [C.c_void_p, C.c_double, C.c_void_p, C.c_void_p,
+                                            C.c_void_p]),
+    "hns_step_correct_rhs": (C.c_int, [C.c_void_p, C.c_double, C.c_void_p, C.c_void_p,
+                                       C.c_void_p, C.c_void_p, C.c_void_p]),
     "hns_profile_enable": (C.c_int, [C.c_void_p, C.c_int]),
     "hns_profile_read": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_double),
                                    C.POINTER(C.c_int64)]),

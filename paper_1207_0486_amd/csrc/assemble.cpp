@@ -486,4 +486,13 @@ hns_status upload_matrix(const HostCSR &h, uint32_t fmt, bool keep32, DevMatrix 
     return HNS_OK;
 }
 
+void tet_incidence(int64_t n, int64_t ntet, const int32_t *tets, std::vector<int64_t> &ptr,
+                   std::vector<int32_t> &tet, std::vector<int8_t> &loc)
+{
+    Incidence inc = build_incidence(n, ntet, 4, tets);
+    ptr = std::move(inc.ptr);
+    tet = std::move(inc.tet);
+    loc = std::move(inc.loc);
+}
+
 }  // namespace hns

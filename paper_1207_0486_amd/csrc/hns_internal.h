@@ -110,6 +110,14 @@ struct hns_operator {
     hns::DevMatrix M, B[3], Bt[3], Ms;
     bool has_aux = false;
     double *step_tmp = nullptr;   // 3 n doubles of scratch for the step kernels
+    // mesh on the device for the advection term (HNS_STEP_AUX): coordinates
+    // (n x 3), tetrahedra (ntet x 4) and the node -> tetrahedron incidence
+    int64_t ntet = 0;
+    double *mesh_xyz = nullptr;
+    int32_t *mesh_tets = nullptr;
+    int64_t *inc_ptr = nullptr;
+    int32_t *inc_tet = nullptr;
+    int8_t *inc_loc = nullptr;
     // tunables
     int check_every = 32;
     double inner_tol = 1e-5;
@@ -167,5 +175,9 @@ hns_status upload_matrix(const HostCSR &h, uint32_t fmt, bool keep32, DevMatrix 
 // same pattern, transposed values (the pattern must be structurally symmetric)
 void transpose_values(const HostCSR &A, HostCSR &At);
 uint32_t choose_format(const HostCSR &h);
+// node -> incident tetrahedra in ascending tetrahedron order (CSR), with the
+// node's local vertex number in each
+void tet_incidence(int64_t n, int64_t ntet, const int32_t *tets, std::vector<int64_t> &ptr,
+                   std::vector<int32_t> &tet, std::vector<int8_t> &loc);
 
 }  // namespace hns

@@ -664,6 +664,28 @@ static hns_status assemble_step_aux(hns_operator *op, const hns_mesh *mesh, cons
         set_error("step scratch allocation failed: %s", hipGetErrorString(e));
         return HNS_ERR_OOM;
     }
+    {   // the mesh itself, for the advection term
+        std::vector<int64_t> ptr;
+        std::vector<int32_t> tet;
+        std::vector<int8_t> loc;
+        tet_incidence(mesh->n_nodes, mesh->n_tets, mesh->tets, ptr, tet, loc);
+        auto up = [](const void *src, size_t bytes, void **dst) -> hns_status {
+            hipError_t err = hipMalloc(dst, bytes);
+            if (err != hipSuccess) {
+                *dst = nullptr;
+                set_error("hipMalloc of %zu bytes failed: %s", bytes, hipGetErrorString(err));
+                return err == hipErrorOutOfMemory ? HNS_ERR_OOM : HNS_ERR_HIP;
+            }
+            HNS_TRY_HIP(hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice));
+            return HNS_OK;
+        };
+        op->ntet = mesh->n_tets;
+        HNS_TRY(up(mesh->xyz, 3 * (size_t)op->n * sizeof(double), (void **)&op->mesh_xyz));
+        HNS_TRY(up(mesh->tets, 4 * (size_t)op->ntet * sizeof(int32_t), (void **)&op->mesh_tets));
+        HNS_TRY(up(ptr.data(), ptr.size() * sizeof(int64_t), (void **)&op->inc_ptr));
+        HNS_TRY(up(tet.data(), tet.size() * sizeof(int32_t), (void **)&op->inc_tet));
+        HNS_TRY(up(loc.data(), loc.size() * sizeof(int8_t), (void **)&op->inc_loc));
+    }
     op->has_aux = true;
     return HNS_OK;
 }
@@ -729,7 +751,8 @@ void hns_operator_destroy(hns_operator *op)
     for (auto &b : op->B) b.release();
     for (auto &b : op->Bt) b.release();
     op->Ms.release();
-    void *ptrs[] = {op->dinv, op->dinv32, op->bc, op->lumped, op->step_tmp};
+    void *ptrs[] = {op->dinv,     op->dinv32,    op->bc,      op->lumped,  op->step_tmp,
+                    op->mesh_xyz, op->mesh_tets, op->inc_ptr, op->inc_tet, op->inc_loc};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (double *f : op->line_fac)
@@ -841,7 +864,8 @@ size_t hns_footprint_bytes(const hns_operator *op, int k, uint32_t mode, int inc
         b += op->A.bytes() + (size_t)op->n * (8 + 1 + 8);
         if (op->dinv32) b += (size_t)op->n * 4;
         if (op->has_aux)
-            b += op->M.bytes() + op->B[0].bytes() * 6 + op->Ms.bytes() + 24 * (size_t)op->n;
+            b += op->M.bytes() + op->B[0].bytes() * 6 + op->Ms.bytes() + 24 * (size_t)op->n +
+                 (3 * 8 + 8) * (size_t)op->n + (4 * 4 + 4 * (4 + 1)) * (size_t)op->ntet;
     }
     return b;
 }

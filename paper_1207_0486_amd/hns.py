@@ -212,6 +212,51 @@ class Operator:
             raise HNSError(st, "hns_step_correct")
         return u
 
+    def step_advection(self, u, out=None, stream=None):
+        """out_c = int ((u . grad) u_c) phi (u: 3 x n).  Returns out (3 x n)."""
+        a = torch.empty_like(u) if out is None else out
+        st = L.lib().hns_step_advection(self._h, _dev_f64(u, "u", self.n, rows=3),
+                                        _dev_f64(a, "out", self.n, rows=3),
+                                        _stream_handle(stream))
+        if st != L.HNS_OK:
+            raise HNSError(st, "hns_step_advection")
+        return a
+
+    def step_velocity_rhs_bdf(self, tau, a1, u, a2=0.0, u_prev=None, p=None, theta=None,
+                              f=None, adv=None, out=None, stream=None):
+        """b_c = a1 M u_c + a2 M u'_c + tau (M_s theta_c + C_c - adv_c + B_c^T p)."""
+        b = torch.empty_like(u) if out is None else out
+        st = L.lib().hns_step_velocity_rhs_bdf(
+            self._h, float(tau), float(a1), _dev_f64(u, "u", self.n, rows=3), float(a2),
+            _dev_f64(u_prev, "u_prev", self.n, rows=3), _dev_f64(p, "p", self.n),
+            _dev_f64(theta, "theta", self.n, rows=2), _dev_f64(f, "f", self.n),
+            _dev_f64(adv, "adv", self.n, rows=3), _dev_f64(b, "out", self.n, rows=3),
+            _stream_handle(stream))
+        if st != L.HNS_OK:
+            raise HNSError(st, "hns_step_velocity_rhs_bdf")
+        return b
+
+    def step_pressure_rhs_tau(self, tau, ut, out=None, stream=None):
+        """b = -(1/tau) sum_c B_c ut_c."""
+        b = torch.empty(self.n, dtype=torch.float64, device=ut.device) if out is None else out
+        st = L.lib().hns_step_pressure_rhs_tau(self._h, float(tau),
+                                               _dev_f64(ut, "ut", self.n, rows=3),
+                                               _dev_f64(b, "out", self.n), _stream_handle(stream))
+        if st != L.HNS_OK:
+            raise HNSError(st, "hns_step_pressure_rhs_tau")
+        return b
+
+    def step_correct_rhs(self, tau, ut, q, p=None, out=None, stream=None):
+        """p += q; rhs_c = M ut_c - tau B_c q (masked).  Returns rhs (3 x n)."""
+        r = torch.empty_like(ut) if out is None else out
+        st = L.lib().hns_step_correct_rhs(self._h, float(tau), _dev_f64(ut, "ut", self.n, rows=3),
+                                          _dev_f64(q, "q", self.n), _dev_f64(p, "p", self.n),
+                                          _dev_f64(r, "out", self.n, rows=3),
+                                          _stream_handle(stream))
+        if st != L.HNS_OK:
+            raise HNSError(st, "hns_step_correct_rhs")
+        return r
+
     AUX = {"M": 0, "B1": 1, "B2": 2, "B3": 3, "B1T": 4, "B2T": 5, "B3T": 6, "Ms": 7}
 
     def apply_aux(self, which: str, x, out=None, stream=None):
