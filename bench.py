@@ -242,6 +242,60 @@ def bench_isotropic(torch, log, m, b_q, point_cap=3000):
     return out
 
 
+def bench_loop(torch, log, m, steps=4, stress_steps=2):
+    """Multi-step BDF2 projection loop on the 256x256x20 basin from rest:
+    implicit-Euler first step, then BDF2, explicit advection and Coriolis,
+    isotropic line-preconditioned pressure (tol 1e-8: the right-hand side of
+    the first step from rest has its rounding floor near 2e-9), consistent-mass
+    correction; velocity and mass solves to 1e-10.  Then the paper's run
+    constants (nu = (1e8, 1e8, 250) m^2/s, dt = one month) with point Jacobi
+    and with line blocks for the stiffness-dominated velocity solves (its
+    pressure right-hand side is small against the rounding of K q, so its
+    pressure tolerance is 1e-6)."""
+    import basin
+    from paper_1207_0486_amd.step import ProjectionLoop
+    theta, f = make_forcing(m)
+    zero3 = torch.zeros(3, m.n, dtype=torch.float64, device="cuda")
+    zero = torch.zeros(m.n, dtype=torch.float64, device="cuda")
+
+    def run(nu_h, nu_v, dt, nsteps, vprec, ptol):
+        t0 = time.time()
+        lp = ProjectionLoop(m, nu_h, nu_v, dt, theta, f, velocity_precond=vprec)
+        setup = time.time() - t0
+        lp.set_state(zero3, zero)
+        per, its = [], []
+        try:
+            for _ in range(nsteps):
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                r = lp.step(tol=1e-10, pressure_tol=ptol)
+                torch.cuda.synchronize()
+                per.append(round(1e3 * (time.perf_counter() - t), 2))
+                ok = all(i.status == 0 for i in r.velocity + r.correction) and r.pressure.status == 0
+                its.append({"velocity": [i.iterations for i in r.velocity],
+                            "pressure": r.pressure.iterations,
+                            "pressure_relres": float("%.3g" % r.pressure.relres_true),
+                            "mass": [i.iterations for i in r.correction], "ok": ok})
+            u = lp.u.abs().amax(dim=1).tolist()
+        finally:
+            lp.close()
+        return {"ms_per_step": per, "iterations": its, "setup_s": round(setup, 1),
+                "pressure_tol": ptol, "max_abs_u": [float("%.4g" % v) for v in u]}
+
+    wl = basin.configs.BASIN_256x256x20
+    out = {"workload": f"{wl.name} BDF2 loop from rest", "steps": steps,
+           "scheme": "implicit Euler first, BDF2 after; explicit advection + Coriolis; "
+                     "isotropic pressure with line blocks; consistent-mass correction",
+           "workload_constants": run(wl.nu_h, wl.nu_v, wl.dt, steps, 0, 1e-8)}
+    log(f"loop: {out['workload_constants']}")
+    stress = {}
+    for vprec, name in ((0, "velocity_point_jacobi"), (1, "velocity_line_blocks")):
+        stress[name] = run(1e8, 250.0, 2.592e6, stress_steps, vprec, 1e-6)
+        log(f"loop stress {name}: {stress[name]}")
+    out["paper_constants"] = {"nu": [1e8, 1e8, 250.0], "dt_s": 2.592e6, **stress}
+    return out
+
+
 def bench_serving(torch, log, budget_gb=16.0, mode="fp64", count=256):
     """Serving: Poisson-process arrivals (50 req/s) of pressure / velocity solve
     requests over five mesh sizes, tolerance 1e-8, continuous batching with
@@ -357,6 +411,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-isotropic", action="store_true")
+    ap.add_argument("--no-loop", action="store_true")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="only a 1 GiB copy and 64 pressure iterations (for counter passes)")
     ap.add_argument("--no-serving", action="store_true")
@@ -481,6 +536,10 @@ def main():
     if not args.no_isotropic:
         isotropic = bench_isotropic(torch, log, m, st.b_q.clone())
 
+    loop = None
+    if not args.no_loop:
+        loop = bench_loop(torch, log, m)
+
     batched = None
     if not args.no_batched:
         batched = bench_batched(torch, log)
@@ -537,6 +596,7 @@ def main():
         "pressure_kernels": kern,
         "mixed": mixed,
         "isotropic_pressure": isotropic,
+        "time_loop": loop,
         "batched": batched,
         "serving": serving,
         "cpu_baseline": cpu,

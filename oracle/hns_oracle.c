@@ -533,7 +533,10 @@ static int apply_prec(int64_t n, int64_t line_len, const double *dinv, const dou
  *
  * Stopping rule: ||b - A x||_2 <= tol * ||b||_2 for the true residual; the
  * recursively updated residual triggers the check and, if the true residual
- * is still too large, replaces the recursive one (restart).
+ * is still too large, replaces the recursive one (restart).  A tolerance
+ * below the rounding floor of the problem would restart forever: after three
+ * failed checks in a row none of which halved the smallest true residual
+ * seen at a check, the solve ends with OR_NOT_CONVERGED.
  *
  * x holds the initial guess on entry (Dirichlet entries are ignored and set to
  * zero) and the last iterate on exit.  alpha_hist / beta_hist / x_hist may be
@@ -614,7 +617,8 @@ int or_pcg_line(const or_csr *A0, const uint8_t *dirichlet, int singular,
         *relres_out = relres;
         goto normalize;
     }
-    int it = 0;
+    int it = 0, stalled = 0;
+    double best_true = INFINITY;
     while (it < maxit) {
         or_spmv(A, p, q);
         double gamma = dot(n, p, q);
@@ -637,6 +641,15 @@ int or_pcg_line(const or_csr *A0, const uint8_t *dirichlet, int singular,
             if (true_rel <= tol) {
                 relres = true_rel;
                 status = OR_OK;
+                if (beta_hist) beta_hist[it - 1] = 0.0;
+                break;
+            }
+            /* The rounding floor: three failed checks in a row that do not
+             * halve the best true residual so far end the solve. */
+            stalled = (true_rel > 0.5 * best_true) ? stalled + 1 : 0;
+            if (true_rel < best_true) best_true = true_rel;
+            if (stalled >= 3) {
+                relres = true_rel;
                 if (beta_hist) beta_hist[it - 1] = 0.0;
                 break;
             }

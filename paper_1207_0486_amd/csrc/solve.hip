@@ -310,8 +310,8 @@ static hns_status solve_fp64_vectors(const SolveCtx &c, hns_solve_info *info, Pr
     const double tol2 = c.tol * c.tol;
     const double drop2 = storage ? op->replace_drop * op->replace_drop : 0.0;
     hns_status status = HNS_NOT_CONVERGED;
-    int since = 0, replacements = 0, stalls = 0;
-    double rr_true = h.rr, bb = h.bb, rr_prev = h.rr;
+    int since = 0, replacements = 0, stalls = 0, floor_checks = 0;
+    double rr_true = h.rr, bb = h.bb, rr_prev = h.rr, rr_best = INFINITY;
     bool fresh = true;
     while (rr_true > tol2 * bb) {
         if (fresh) {
@@ -356,6 +356,15 @@ static hns_status solve_fp64_vectors(const SolveCtx &c, hns_solve_info *info, Pr
         }
         if (!hit || h.iter >= c.max_iter) break;  // budget spent
         if (!storage) {
+            // the rounding floor: three failed checks in a row that do not
+            // halve the smallest true residual seen at a check end the solve
+            floor_checks = (rr_true > 0.25 * rr_best) ? floor_checks + 1 : 0;
+            rr_best = std::min(rr_best, rr_true);
+            if (floor_checks >= 3) {
+                set_error("true residual stalled at %g, above the tolerance (rounding floor)",
+                          std::sqrt(rr_true / bb));
+                break;
+            }
             fresh = true;  // restart from the true residual
             continue;
         }

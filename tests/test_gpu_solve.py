@@ -270,3 +270,19 @@ def test_auto_format_is_diagonal_on_structured_mesh(dev, ragged_basin):
     from paper_1207_0486_amd.hns import Operator
     op = Operator(ragged_basin, 1e3, 1e-2, kind="poisson")
     assert op.format == "sdia"
+
+
+def test_tolerance_below_rounding_floor_stops_early(dev):
+    """Same rule as the oracle: restarts from the true residual stop after
+    three checks that do not halve the best true residual."""
+    from paper_1207_0486_amd.hns import Operator
+    m = basin.box_mesh(8, 8, 4)
+    d = (m.bc & 1) == 1
+    b = basin.normal_rhs(m.n, 2, dirichlet=d)
+    op = Operator(m, 1.0, 1e-4, 0.1, kind="helmholtz")
+    x, info = op.solve(_gpu(b, dev), tol=1e-19, max_iter=100000, mask_bit=0)
+    assert info.status == 1
+    assert info.iterations < 2000
+    assert info.relres_true < 1e-14
+    A = oracle.helmholtz(m, 1.0, 1e-4, 0.1)
+    assert oracle.relres(A, b, x.cpu().numpy(), d) < 1e-14

@@ -354,3 +354,19 @@ def test_manufactured_solution_rate(kind):
     errs = [_mms_error(N, kind) for N in (16, 32, 64)]
     rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
     assert np.all(rates >= 1.9), (errs, rates)
+
+
+def test_tolerance_below_rounding_floor_stops_early():
+    """A tolerance the rounding of A x cannot reach: CG restarts from the true
+    residual until three checks in a row fail to halve the best true residual,
+    then reports not-converged long before the iteration cap, with a true
+    residual near the floor."""
+    m = basin.box_mesh(8, 8, 4)
+    A = oracle.helmholtz(m, 1.0, 1e-4, 0.1)
+    d = (m.bc & 1) == 1
+    b = basin.normal_rhs(m.n, 2, dirichlet=d)
+    r = oracle.pcg(A, b, dirichlet=d, tol=1e-19, maxit=100000)
+    assert r.status == oracle.NOT_CONVERGED
+    assert r.iterations < 2000
+    assert r.relres < 1e-14
+    assert oracle.relres(A, b, r.x, d) == pytest.approx(r.relres, rel=1e-6)
