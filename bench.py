@@ -296,7 +296,7 @@ def bench_loop(torch, log, m, steps=4, stress_steps=2):
     return out
 
 
-def bench_serving(torch, log, budget_gb=16.0, mode="fp64", count=256):
+def bench_serving(torch, log, budget_gb=16.0, mode="fp64", count=256, capacity=8, chunk=32):
     """Serving: Poisson-process arrivals (50 req/s) of pressure / velocity solve
     requests over five mesh sizes, tolerance 1e-8, continuous batching with
     operators admitted by footprint and kept resident."""
@@ -316,7 +316,7 @@ def bench_serving(torch, log, budget_gb=16.0, mode="fp64", count=256):
                                   wl.extra["rate_hz"], wl.seed)
     t0 = time.time()
     be = GpuBackend(make, mode=mode, check_every=16)
-    srv = Server(be, budget_bytes=int(budget_gb * (1 << 30)), capacity=8, chunk=32)
+    srv = Server(be, budget_bytes=int(budget_gb * (1 << 30)), capacity=capacity, chunk=chunk)
     # warm-up: one request per operator (assembly, tuning, graph capture)
     keys = sorted({(r.mesh_index, r.kind) for r in reqs})
     warm = []
@@ -366,7 +366,7 @@ def bench_serving(torch, log, budget_gb=16.0, mode="fp64", count=256):
     nodes = sum(make((r.mesh_index, r.kind))[0].n for r, _ in items)
     bad = sum(1 for x in results if x.info.status != 0)
     out = {"requests": len(results), "rate_hz": wl.extra["rate_hz"], "tol": wl.tol,
-           "mode": mode, "budget_gb": budget_gb, "p50_ms": round(st["p50_ms"], 2),
+           "mode": mode, "capacity": capacity, "chunk": chunk, "budget_gb": budget_gb, "p50_ms": round(st["p50_ms"], 2),
            "p99_ms": round(st["p99_ms"], 2), "mean_ms": round(st["mean_ms"], 2),
            "solves_per_s": round(st["solves_per_s"], 2), "wall_s": round(end - start, 3),
            "nodes_solved": int(nodes), "failed": bad, "operators_resident": len(keys),
@@ -417,6 +417,9 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serve-budget-gb", type=float, default=16.0)
     ap.add_argument("--serve-mode", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--serve-capacity", type=int, default=2,
+                    help="slots per operator session")
+    ap.add_argument("--serve-chunk", type=int, default=32, help="iterations between admissions")
     ap.add_argument("--fmt", default="auto")
     ap.add_argument("--profile-period", type=int, default=16,
                     help="time every N-th CG iteration with HIP events (0 = off)")
@@ -546,7 +549,12 @@ def main():
 
     serving = None
     if not args.no_serving:
-        serving = bench_serving(torch, log, args.serve_budget_gb, args.serve_mode)
+        serving = bench_serving(torch, log, args.serve_budget_gb, args.serve_mode,
+                                capacity=args.serve_capacity, chunk=args.serve_chunk)
+        other = "mixed" if args.serve_mode == "fp64" else "fp64"
+        serving_other = bench_serving(torch, log, args.serve_budget_gb, other,
+                                      capacity=args.serve_capacity, chunk=args.serve_chunk)
+        serving = {args.serve_mode: serving, other: serving_other}
 
     cpu = None
     if not args.no_cpu_baseline:
