@@ -24,7 +24,11 @@
 // One-off reductions outside the iteration (right-hand-side statistics,
 // residual norms, normalisation) use a last-block-done pattern instead.
 #include <cmath>
+#include <tuple>
 #include <type_traits>
+#include <utility>
+
+#include <hip/hip_ext.h>
 
 #include "kernels.h"
 
@@ -260,6 +264,30 @@ __global__ __launch_bounds__(kBlock) void k_spmv_csr(int64_t n, const int32_t *_
 struct DiaOffsets {
     int32_t o[kMaxDiag];
 };
+
+// Launch of kernel k on stream s.  With an event pair ev2 the dispatch itself
+// records ev2[0] when the kernel starts and ev2[1] when it ends
+// (hipExtLaunchKernel), so their interval is the kernel's own duration.
+template <typename Tuple, size_t... I>
+void arg_pointers(Tuple &t, void **p, std::index_sequence<I...>)
+{
+    ((p[I] = (void *)&std::get<I>(t)), ...);
+}
+
+template <typename... KArgs, typename... A>
+hipError_t launch_k(void (*k)(KArgs...), int grid, int block, size_t shmem, hipStream_t s,
+                    hipEvent_t *ev2, A... a)
+{
+    if (!ev2) {
+        hipLaunchKernelGGL(k, dim3(grid), dim3(block), shmem, s, a...);
+        return hipGetLastError();
+    }
+    std::tuple<KArgs...> t(a...);
+    void *params[sizeof...(KArgs) > 0 ? sizeof...(KArgs) : 1];
+    arg_pointers(t, params, std::index_sequence_for<KArgs...>{});
+    return hipExtLaunchKernel((const void *)k, dim3(grid), dim3(block), params, shmem, s,
+                              ev2[0], ev2[1], 0);
+}
 
 // R consecutive values starting at p (8-byte aligned only: a shifted row may
 // start at an odd element; gfx950 global loads need no 16-byte alignment)
@@ -1018,56 +1046,61 @@ Chunks sdia_chunks(const DevMatrix &A)
 
 template <typename TV, typename TX, bool DOT, int M>
 int sdia_launch(const DevMatrix &A, const TV *vals, const void *p, void *q, const uint8_t *bc,
-                int bit, const Scalars *sc, double *part, hipStream_t s)
+                int bit, const Scalars *sc, double *part, hipStream_t s, hipEvent_t *ev2)
 {
     constexpr int R = sizeof(TX) == 8 ? 2 : 1;
     DiaOffsets offs;
     for (int k = 0; k < kMaxDiag; ++k) offs.o[k] = k < A.ndiag ? A.off[k] : 0;
     const Chunks c = sdia_chunks<TX>(A);
-    k_spmv_sdia<TV, TX, DOT, M, R><<<c.grid, kBlock, 0, s>>>(A.n, c.per, offs, vals,
-                                                             (const TX *)p, (TX *)q, bc, bit, sc,
-                                                             part);
+    if (launch_k(k_spmv_sdia<TV, TX, DOT, M, R>, c.grid, kBlock, 0, s, ev2, A.n, c.per, offs,
+                 vals, (const TX *)p, (TX *)q, bc, bit, sc, part) != hipSuccess)
+        return -1;
     return c.grid;
 }
 
 template <typename TV, typename TX, bool DOT, int M = 1>
 int sdia_dispatch(const DevMatrix &A, const TV *vals, const void *p, void *q, const uint8_t *bc,
-                  int bit, const Scalars *sc, double *part, hipStream_t s)
+                  int bit, const Scalars *sc, double *part, hipStream_t s, hipEvent_t *ev2)
 {
     if constexpr (M <= kMaxDiag) {
-        if (A.ndiag == M) return sdia_launch<TV, TX, DOT, M>(A, vals, p, q, bc, bit, sc, part, s);
-        return sdia_dispatch<TV, TX, DOT, M + 1>(A, vals, p, q, bc, bit, sc, part, s);
+        if (A.ndiag == M)
+            return sdia_launch<TV, TX, DOT, M>(A, vals, p, q, bc, bit, sc, part, s, ev2);
+        return sdia_dispatch<TV, TX, DOT, M + 1>(A, vals, p, q, bc, bit, sc, part, s, ev2);
     }
     return 0;
 }
 
 // Launches q = A p (+ per-block partials of p^T q when DOT); returns the
-// grid, i.e. the number of partials written.
+// grid, i.e. the number of partials written (-1 if the launch failed).
+// ev2: optional event pair recorded by the dispatch (kernel duration).
 template <typename TV, typename TX, bool DOT>
 int spmv_dispatch(const DevMatrix &A, const void *p, void *q, const uint8_t *bc, int bit,
-                  const Scalars *sc, double *part, hipStream_t s)
+                  const Scalars *sc, double *part, hipStream_t s, hipEvent_t *ev2 = nullptr)
 {
     const bool f32 = std::is_same<TV, float>::value;
     if (A.fmt == HNS_FMT_SDIA) {
         const TV *vd = f32 ? (const TV *)(const void *)A.dia32 : (const TV *)(const void *)A.dia;
-        return sdia_dispatch<TV, TX, DOT>(A, vd, p, q, bc, bit, sc, part, s);
+        return sdia_dispatch<TV, TX, DOT>(A, vd, p, q, bc, bit, sc, part, s, ev2);
     }
     const int G = spmv_grid(A);
     const TV *vs = f32 ? (const TV *)(const void *)A.sval32 : (const TV *)(const void *)A.sval;
     const TV *vc = f32 ? (const TV *)(const void *)A.val32 : (const TV *)(const void *)A.val;
+    hipError_t e;
     if (A.fmt == HNS_FMT_SELL)
-        k_spmv_sell<TV, TX, DOT><<<G, kBlock, 0, s>>>(A.n, A.nslices, A.slice_ptr, A.scol, vs,
-                                                      (const TX *)p, (TX *)q, bc, bit, sc, part);
+        e = launch_k(k_spmv_sell<TV, TX, DOT>, G, kBlock, 0, s, ev2, A.n, A.nslices,
+                     A.slice_ptr, A.scol, vs, (const TX *)p, (TX *)q, bc, bit, sc, part);
     else
-        k_spmv_csr<TV, TX, DOT><<<G, kBlock, 0, s>>>(A.n, A.rowptr, A.col, vc, (const TX *)p,
-                                                     (TX *)q, bc, bit, sc, part);
-    return G;
+        e = launch_k(k_spmv_csr<TV, TX, DOT>, G, kBlock, 0, s, ev2, A.n, A.rowptr, A.col, vc,
+                     (const TX *)p, (TX *)q, bc, bit, sc, part);
+    return e == hipSuccess ? G : -1;
 }
 
 inline bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 
 constexpr int kLineLds = 49152;   // bytes of LDS for the staged columns of one block
 
+// Event pairs of a timed iteration: ev[0..1] SpMV, ev[2..3] update,
+// ev[4..5] direction update (each recorded by its kernel's dispatch).
 hns_status line_iteration(const IterArgs &a, int parity, hipStream_t s, hipEvent_t *ev)
 {
     const uint8_t *bc = a.bit < 0 ? nullptr : a.bc;
@@ -1077,16 +1110,16 @@ hns_status line_iteration(const IterArgs &a, int parity, hipStream_t s, hipEvent
     const int NC = line_cols_per_block(L);
     const int Gl = line_grid(a.n, L);
     const Chunks cu = chunks(a.n / 2, (int64_t)kBlock * a.A->vec_it, kBlock);
-    if (ev) HNS_TRY_HIP(hipEventRecord(ev[0], s));
-    const int Gs = spmv_dispatch<double, double, true>(*a.A, a.p, a.q, bc, a.bit, a.sc, P1, s);
-    if (ev) HNS_TRY_HIP(hipEventRecord(ev[1], s));
-    k_update_line<<<Gl, kBlock, (size_t)4 * NC * L * sizeof(double), s>>>(
-        a.n, L, NC, (double *)a.x, (double *)a.r, (const double *)a.p, (const double *)a.q,
-        a.z, a.lfac, a.sc, P1, Gs, P2, parity);
-    if (ev) HNS_TRY_HIP(hipEventRecord(ev[2], s));
-    k_pupdate_line<<<cu.grid, kBlock, 0, s>>>(a.n, cu.per, (double *)a.p, a.z, a.sc, P2, Gl,
-                                              parity);
-    if (ev) HNS_TRY_HIP(hipEventRecord(ev[3], s));
+    const int Gs = spmv_dispatch<double, double, true>(*a.A, a.p, a.q, bc, a.bit, a.sc, P1, s,
+                                                       ev ? ev : nullptr);
+    if (Gs < 0) return check_launch("spmv");
+    HNS_TRY_HIP(launch_k(k_update_line, Gl, kBlock, (size_t)4 * NC * L * sizeof(double), s,
+                         ev ? ev + 2 : nullptr, a.n, L, NC, (double *)a.x, (double *)a.r,
+                         (const double *)a.p, (const double *)a.q, a.z, a.lfac, a.sc,
+                         (const double *)P1, Gs, P2, parity));
+    HNS_TRY_HIP(launch_k(k_pupdate_line, cu.grid, kBlock, 0, s, ev ? ev + 4 : nullptr, a.n,
+                         cu.per, (double *)a.p, (const double *)a.z, a.sc, (const double *)P2,
+                         Gl, parity));
     return check_launch("line-preconditioned cg iteration");
 }
 
@@ -1102,29 +1135,25 @@ hns_status iteration_impl(const IterArgs &a, int parity, hipStream_t s, hipEvent
     const bool vec = aligned16(a.x) && aligned16(a.r) && aligned16(a.p) && aligned16(a.q) &&
                      aligned16(a.dinv);
     const Chunks cu = chunks(vec ? a.n / V : a.n, (int64_t)kBlock * a.A->vec_it, kBlock);
-    if (ev) HNS_TRY_HIP(hipEventRecord(ev[0], s));
-    const int Gs = spmv_dispatch<TV, TX, true>(*a.A, a.p, a.q, bc, a.bit, a.sc, P1, s);
-    if (ev) HNS_TRY_HIP(hipEventRecord(ev[1], s));
-    if (vec)
-        k_update<TX, TD, V><<<cu.grid, kBlock, 0, s>>>(a.n, cu.per, (TX *)a.x, (TX *)a.r,
-                                                       (const TX *)a.p, (const TX *)a.q,
-                                                       (const TD *)a.dinv, a.sc, P1, Gs, P2,
-                                                       parity);
-    else
-        k_update<TX, TD, 1><<<cu.grid, kBlock, 0, s>>>(a.n, cu.per, (TX *)a.x, (TX *)a.r,
-                                                       (const TX *)a.p, (const TX *)a.q,
-                                                       (const TD *)a.dinv, a.sc, P1, Gs, P2,
-                                                       parity);
-    if (ev) HNS_TRY_HIP(hipEventRecord(ev[2], s));
-    if (vec)
-        k_pupdate<TX, TD, V><<<cu.grid, kBlock, 0, s>>>(a.n, cu.per, (TX *)a.p, (const TX *)a.r,
-                                                        (const TD *)a.dinv, a.sc, P2, cu.grid,
-                                                        parity, 1);
-    else
-        k_pupdate<TX, TD, 1><<<cu.grid, kBlock, 0, s>>>(a.n, cu.per, (TX *)a.p, (const TX *)a.r,
-                                                        (const TD *)a.dinv, a.sc, P2, cu.grid,
-                                                        parity, 1);
-    if (ev) HNS_TRY_HIP(hipEventRecord(ev[3], s));
+    const int Gs = spmv_dispatch<TV, TX, true>(*a.A, a.p, a.q, bc, a.bit, a.sc, P1, s,
+                                               ev ? ev : nullptr);
+    if (Gs < 0) return check_launch("spmv");
+    hipEvent_t *eu = ev ? ev + 2 : nullptr, *ep = ev ? ev + 4 : nullptr;
+    if (vec) {
+        HNS_TRY_HIP(launch_k(k_update<TX, TD, V>, cu.grid, kBlock, 0, s, eu, a.n, cu.per,
+                             (TX *)a.x, (TX *)a.r, (const TX *)a.p, (const TX *)a.q,
+                             (const TD *)a.dinv, a.sc, (const double *)P1, Gs, P2, parity));
+        HNS_TRY_HIP(launch_k(k_pupdate<TX, TD, V>, cu.grid, kBlock, 0, s, ep, a.n, cu.per,
+                             (TX *)a.p, (const TX *)a.r, (const TD *)a.dinv, a.sc,
+                             (const double *)P2, cu.grid, parity, 1));
+    } else {
+        HNS_TRY_HIP(launch_k(k_update<TX, TD, 1>, cu.grid, kBlock, 0, s, eu, a.n, cu.per,
+                             (TX *)a.x, (TX *)a.r, (const TX *)a.p, (const TX *)a.q,
+                             (const TD *)a.dinv, a.sc, (const double *)P1, Gs, P2, parity));
+        HNS_TRY_HIP(launch_k(k_pupdate<TX, TD, 1>, cu.grid, kBlock, 0, s, ep, a.n, cu.per,
+                             (TX *)a.p, (const TX *)a.r, (const TD *)a.dinv, a.sc,
+                             (const double *)P2, cu.grid, parity, 1));
+    }
     return check_launch("cg iteration");
 }
 

@@ -34,7 +34,7 @@ struct Workspace {
     double *z = nullptr;          // M^-1 r of the line preconditioner (allocated on first use)
     Scalars *sc = nullptr;        // [0] FP64 / outer loop, [1] inner FP32 loop
     Scalars *host = nullptr;      // pinned mirror of sc[0..1]
-    std::vector<hipEvent_t> ev;   // timing events, 4 per iteration of a chunk
+    std::vector<hipEvent_t> ev;   // timing events, a (start, end) pair per kernel of an iteration
 
     static size_t bytes_for(int64_t n, bool mixed)
     {
@@ -185,7 +185,7 @@ static hns_status enqueue_iterations(hns_operator *op, Workspace *w, Prec prec, 
                                      const double *lfac = nullptr)
 {
     const int period = op->profile;
-    if (period > 0) HNS_TRY(w->ensure_events(4 * (size_t)count));
+    if (period > 0) HNS_TRY(w->ensure_events(6 * (size_t)count));
     IterArgs a{&op->A, prec, op->n, x, r, p, q, dinv, op->bc, bit, sc, w->partials};
     if (lfac) {
         a.lfac = lfac;
@@ -194,7 +194,7 @@ static hns_status enqueue_iterations(hns_operator *op, Workspace *w, Prec prec, 
     }
     for (int it = 0; it < count; ++it) {
         const bool timed = period > 0 && (it % period) == 0;
-        HNS_TRY(launch_iteration(a, (parity0 + it) & 1, s, timed ? &w->ev[4 * it] : nullptr));
+        HNS_TRY(launch_iteration(a, (parity0 + it) & 1, s, timed ? &w->ev[6 * it] : nullptr));
     }
     return HNS_OK;
 }
@@ -209,7 +209,7 @@ static hns_status account_iterations(hns_operator *op, Workspace *w, bool fp32, 
     for (int it = 0; it < done; it += period)
         for (int k = 0; k < 3; ++k) {
             float ms = 0.0f;
-            HNS_TRY_HIP(hipEventElapsedTime(&ms, w->ev[4 * it + k], w->ev[4 * it + k + 1]));
+            HNS_TRY_HIP(hipEventElapsedTime(&ms, w->ev[6 * it + 2 * k], w->ev[6 * it + 2 * k + 1]));
             op->prof_ms[base + k] += ms;
             op->prof_count[base + k] += 1;
         }
