@@ -61,6 +61,13 @@ enum : int32_t {
     for (int64_t t = blockIdx.x * (int64_t)kBlock + threadIdx.x; t < (np); \
          t += (int64_t)gridDim.x * kBlock)
 
+// True in every thread of the block when at least one of the K columns is
+// running (stop == ACTIVE; mode 0) or is marked for a direction update
+// (mode 1).  The per-iteration kernels return at once otherwise, so the
+// iterations of a chunk that follow the last column's exit cost a launch
+// each instead of a pass over the n x K block.
+__device__ __forceinline__ bool any_column(const BCol *__restrict__ cols, int K, int mode);
+
 __device__ __forceinline__ bool masked(const uint8_t *bc, int bit, int64_t i)
 {
     return bc != nullptr && bit >= 0 && ((bc[i] >> bit) & 1u);
@@ -135,6 +142,14 @@ struct BOffsets {
 // ---------------------------------------------------------------------------
 // SpMM: Q = mask_j(A P), optional per-column partials of p_j^T q_j
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ bool any_column(const BCol *__restrict__ cols, int K, int mode)
+{
+    int mine = 0;
+    for (int c = threadIdx.x; c < K; c += blockDim.x)
+        mine |= mode == 0 ? (cols[c].stop == ACTIVE) : (cols[c].mark != 0);
+    return __syncthreads_or(mine) != 0;
+}
+
 template <typename TV, typename TX, int V, bool DOT, int M>
 __global__ __launch_bounds__(kBlock) void k_bspmm_sdia(int64_t n, int K, BOffsets offs,
                                                        const TV *__restrict__ dia,
@@ -144,6 +159,9 @@ __global__ __launch_bounds__(kBlock) void k_bspmm_sdia(int64_t n, int K, BOffset
                                                        const BCol *__restrict__ cols,
                                                        double *__restrict__ part)
 {
+    if constexpr (DOT) {
+        if (!any_column(cols, K, 0)) return;
+    }
     double acc[1][V];
 #pragma unroll
     for (int v = 0; v < V; ++v) acc[0][v] = 0.0;
@@ -193,6 +211,9 @@ __global__ __launch_bounds__(kBlock) void k_bspmm_csr(int64_t n, int K,
                                                       const BCol *__restrict__ cols,
                                                       double *__restrict__ part)
 {
+    if constexpr (DOT) {
+        if (!any_column(cols, K, 0)) return;
+    }
     double acc[1][V];
 #pragma unroll
     for (int v = 0; v < V; ++v) acc[0][v] = 0.0;
@@ -234,6 +255,9 @@ __global__ __launch_bounds__(kBlock) void k_bspmm_sell(int64_t n, int K,
                                                        const BCol *__restrict__ cols,
                                                        double *__restrict__ part)
 {
+    if constexpr (DOT) {
+        if (!any_column(cols, K, 0)) return;
+    }
     double acc[1][V];
 #pragma unroll
     for (int v = 0; v < V; ++v) acc[0][v] = 0.0;
@@ -331,6 +355,7 @@ __global__ __launch_bounds__(kBlock) void k_bupdate(int64_t n, int K, TX *__rest
                                                     const BCol *__restrict__ cols,
                                                     double *__restrict__ part)
 {
+    if (!any_column(cols, K, 0)) return;
     double acc[2][V];
 #pragma unroll
     for (int v = 0; v < V; ++v) acc[0][v] = acc[1][v] = 0.0;
@@ -373,6 +398,7 @@ __global__ __launch_bounds__(kBlock) void k_bpupdate(int64_t n, int K, TX *__res
                                                      const TD *__restrict__ dinv,
                                                      const BCol *__restrict__ cols)
 {
+    if (!any_column(cols, K, 1)) return;
     const int64_t np = n * K / V;
     PACK_LOOP(t, np)
     {
@@ -894,10 +920,18 @@ const T *values_of(const DevMatrix &A)
 hns_status spmm64(BCtx &c, const double *X)
 {
     const DevMatrix &A = c.op->A;
-    const int G = bgrid(A.n * (int64_t)c.K, c.K, 1);
+    const int V = (c.K % c.V == 0) ? c.V : 1;   // the tuned pack width
+    const int G = bgrid(A.n * (int64_t)c.K / V, c.K, V);
     Launcher L{c.s};
-    bspmm_launch<double, double, 1, false>(L, A, c.K, values_of<double>(A), X, c.w->Q64, c.op->bc,
-                                           c.w->cols, nullptr, G);
+    if (V == 4)
+        bspmm_launch<double, double, 4, false>(L, A, c.K, values_of<double>(A), X, c.w->Q64,
+                                               c.op->bc, c.w->cols, nullptr, G);
+    else if (V == 2)
+        bspmm_launch<double, double, 2, false>(L, A, c.K, values_of<double>(A), X, c.w->Q64,
+                                               c.op->bc, c.w->cols, nullptr, G);
+    else
+        bspmm_launch<double, double, 1, false>(L, A, c.K, values_of<double>(A), X, c.w->Q64,
+                                               c.op->bc, c.w->cols, nullptr, G);
     return L.status("batched spmm (fp64)");
 }
 
