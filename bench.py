@@ -435,6 +435,7 @@ def main():
 
     import torch
     import basin
+    from paper_1207_0486_amd.hns import Operator
     from paper_1207_0486_amd.step import ProjectionStep
 
     wl = basin.configs.BASIN_256x256x20
@@ -535,6 +536,18 @@ def main():
         log(f"mixed: {msm:.1f} ms/step (x{ms64 / msm:.2f}), "
             + ", ".join(f"{k}={i.iterations}/{i.outer_iterations}" for k, i in infosm.items()))
 
+    # operator set-up: host assembly against device-computed values (same
+    # pattern work on the host, bitwise the same matrix)
+    setup = {}
+    for gpu_asm in (False, True):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        op_a = Operator(m, wl.nu_h, wl.nu_v, kind="poisson", gpu_assembly=gpu_asm)
+        torch.cuda.synchronize()
+        setup["device_values_s" if gpu_asm else "host_s"] = round(time.perf_counter() - t, 3)
+        op_a.close()
+    log(f"pressure operator set-up: {setup}")
+
     isotropic = None
     if not args.no_isotropic:
         isotropic = bench_isotropic(torch, log, m, st.b_q.clone())
@@ -603,6 +616,7 @@ def main():
                      "bytes_per_launch": spmv_bytes, "avg_us": round(spmv_avg_us, 2)},
         "pressure_kernels": kern,
         "mixed": mixed,
+        "operator_setup": setup,
         "isotropic_pressure": isotropic,
         "time_loop": loop,
         "batched": batched,

@@ -77,6 +77,10 @@ typedef struct {
                                 first step, BDF2 uses dt' = 2 dt / 3)                */
 /* Options */
 #define HNS_KEEP_FP32 0x10u  /* also keep FP32 matrix/diagonal copies (HNS_MIXED)  */
+#define HNS_GPU_ASSEMBLY 0x40u /* compute the operator's values on the device (one
+                                lane per row gathers its tetrahedra in order, as the
+                                host loop does; bitwise the same values); the
+                                pattern and the auxiliary forms stay on the host    */
 #define HNS_STEP_AUX  0x20u  /* also keep M, B_1..3, lumped mass, surface mass and
                                 the mesh (coordinates, tetrahedra, node incidence)
                                 for the step right-hand sides (hns_step_*)          */

@@ -180,12 +180,24 @@ hns_status check_mesh(const hns_mesh *m)
 }  // namespace
 
 hns_status assemble_host(const hns_mesh *mesh, double c_mass, double c_stiff, double nu_h,
-                         double nu_v, HostCSR &A, std::vector<double> *lumped)
+                         double nu_v, HostCSR &A, std::vector<double> *lumped, bool values_on_device)
 {
     HNS_TRY(check_mesh(mesh));
     const int64_t n = mesh->n_nodes, ne = mesh->n_tets;
     const double *xyz = mesh->xyz;
     const int32_t *tets = mesh->tets;
+
+    if (values_on_device) {
+        // pattern here, values (and the volume check) by the device kernel
+        Incidence inc = build_incidence(n, ne, 4, tets);
+        build_pattern(n, 4, tets, inc, A);
+        if ((int64_t)A.col.size() >= (int64_t)INT32_MAX) {
+            set_error("operator has %zu nonzeros, beyond the int32 range", A.col.size());
+            return HNS_ERR_INVALID;
+        }
+        return assemble_values_device(mesh, inc.ptr, inc.tet, inc.loc, A, c_mass, c_stiff, nu_h,
+                                      nu_v, lumped);
+    }
 
     // element validity first (positive volume)
     std::atomic<int64_t> bad{-1};

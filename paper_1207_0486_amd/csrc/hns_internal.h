@@ -166,8 +166,17 @@ hns_status tune_batched(hns_operator *op, BWorkspace *w, int K, bool mixed, hipS
                         double *times_us, int *best_V);
 
 // assemble.cpp
+// values_on_device: the pattern is built here, the values (and the element
+// volume check) by a device kernel in the same order as the host loop
 hns_status assemble_host(const hns_mesh *mesh, double c_mass, double c_stiff, double nu_h,
-                         double nu_v, HostCSR &A, std::vector<double> *lumped);
+                         double nu_v, HostCSR &A, std::vector<double> *lumped,
+                         bool values_on_device = false);
+// assemble_gpu.hip
+hns_status assemble_values_device(const hns_mesh *mesh, const std::vector<int64_t> &inc_ptr,
+                                  const std::vector<int32_t> &inc_tet,
+                                  const std::vector<int8_t> &inc_loc, HostCSR &A, double c_mass,
+                                  double c_stiff, double nu_h, double nu_v,
+                                  std::vector<double> *lumped);
 hns_status assemble_divergence_host(const hns_mesh *mesh, const HostCSR &pattern, int comp,
                                     HostCSR &B);
 hns_status assemble_surface_mass_host(const hns_mesh *mesh, HostCSR &Ms);

@@ -733,7 +733,8 @@ hns_status hns_assemble(const hns_mesh *mesh, double nu_h, double nu_v, double d
     std::vector<double> lumped;
     const double c_mass = (kind == HNS_HELMHOLTZ) ? 1.0 : 0.0;
     const double c_stiff = (kind == HNS_HELMHOLTZ) ? dt : 1.0;
-    hns_status st = assemble_host(mesh, c_mass, c_stiff, nu_h, nu_v, A, &lumped);
+    hns_status st = assemble_host(mesh, c_mass, c_stiff, nu_h, nu_v, A, &lumped,
+                                  (flags & HNS_GPU_ASSEMBLY) != 0);
     if (st == HNS_OK) {
         op->n = A.n;
         st = finish_operator(op, A, fmt, lumped, mesh->bc);
