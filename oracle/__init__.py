@@ -62,6 +62,13 @@ def lib():
         L.or_pcg_line.restype = C.c_int
         L.or_pcg_line.argtypes = [vp, u8p, C.c_int, dp, dp, dp, C.c_double, C.c_int, C.c_int64,
                                   C.POINTER(C.c_int), dp, dp, dp, dp, dp]
+        L.or_pcg_ic0.restype = C.c_int
+        L.or_pcg_ic0.argtypes = [vp, u8p, C.c_int, dp, dp, dp, C.c_double, C.c_int,
+                                 C.POINTER(C.c_int), dp, dp, dp, dp, dp]
+        L.or_ic0_factor.restype = C.c_int
+        L.or_ic0_factor.argtypes = [vp, u8p, ip, C.POINTER(vp)]
+        L.or_greedy_colors.restype = C.c_int
+        L.or_greedy_colors.argtypes = [vp, ip]
         L.or_advection.restype = C.c_int
         L.or_advection.argtypes = [C.c_int64, dp, C.c_int64, ip, dp, dp]
         L.or_tridiag_solve.restype = C.c_int
@@ -207,10 +214,12 @@ class PCGResult:
 
 
 def pcg(A: Matrix, b, dirichlet=None, singular=False, weights=None, x0=None,
-        tol=1e-10, maxit=100000, history=False, x_history=False, line=0) -> PCGResult:
+        tol=1e-10, maxit=100000, history=False, x_history=False, line=0,
+        ic0=False) -> PCGResult:
     """Preconditioned CG on A after eliminating `dirichlet` nodes (boolean (n,)
     or None).  line = 0: Jacobi (inverse diagonal); line = L >= 1: inverse of
-    the tridiagonal blocks on the consecutive columns of L nodes."""
+    the tridiagonal blocks on the consecutive columns of L nodes; ic0: IC(0)
+    of the eliminated matrix in the greedy multicolour order."""
     n = A.n
     b = _f64(b)
     x = np.zeros(n) if x0 is None else _f64(x0).copy()
@@ -222,14 +231,42 @@ def pcg(A: Matrix, b, dirichlet=None, singular=False, weights=None, x0=None,
     ah = np.zeros(maxit) if history else None
     bh = np.zeros(maxit) if history else None
     xh = np.zeros((maxit, n)) if x_history else None
-    st = lib().or_pcg_line(A._h, _u8(dmask), int(bool(singular)), None if w is None else _d(w),
-                           _d(b), _d(x), tol, maxit, int(line), C.byref(it), _d(rel), _d(rm),
-                           None if ah is None else _d(ah), None if bh is None else _d(bh),
-                           None if xh is None else _d(xh))
+    hist = (None if ah is None else _d(ah), None if bh is None else _d(bh),
+            None if xh is None else _d(xh))
+    if ic0:
+        st = lib().or_pcg_ic0(A._h, _u8(dmask), int(bool(singular)),
+                              None if w is None else _d(w), _d(b), _d(x), tol, maxit,
+                              C.byref(it), _d(rel), _d(rm), *hist)
+    else:
+        st = lib().or_pcg_line(A._h, _u8(dmask), int(bool(singular)),
+                               None if w is None else _d(w), _d(b), _d(x), tol, maxit, int(line),
+                               C.byref(it), _d(rel), _d(rm), *hist)
     k = it.value
     return PCGResult(x=x, status=st, iterations=k, relres=float(rel[0]), removed_mean=float(rm[0]),
                      alphas=None if ah is None else ah[:k], betas=None if bh is None else bh[:k],
                      x_hist=None if xh is None else xh[:k])
+
+
+def greedy_colors(A: Matrix):
+    """Greedy colouring of A's graph in node order: (colours (n,), count)."""
+    color = np.empty(A.n, np.int32)
+    k = lib().or_greedy_colors(A._h, _i(color))
+    if k < 0:
+        raise OracleError(k, "greedy_colors")
+    return color, k
+
+
+def ic0_factor(A: Matrix, dirichlet=None):
+    """IC(0) of the eliminated A in the greedy multicolour order: (perm, L)
+    with perm[k] the node at position k and L a Matrix (lower triangular,
+    rows and columns in the permuted order)."""
+    dmask = None if dirichlet is None else np.ascontiguousarray(dirichlet, dtype=np.uint8)
+    perm = np.empty(A.n, np.int32)
+    h = C.c_void_p()
+    st = lib().or_ic0_factor(A._h, _u8(dmask), _i(perm), C.byref(h))
+    if st != OK:
+        raise OracleError(st, "ic0_factor")
+    return perm, Matrix(h.value)
 
 
 def advection(mesh, u):

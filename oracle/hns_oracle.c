@@ -497,10 +497,35 @@ static void column_blocks(const or_csr *A, int64_t L, double *ld, double *le)
     }
 }
 
-/* z = M^-1 r for the preconditioner of or_pcg_line: the inverse diagonal
- * (line_len == 0) or the inverse of the column blocks (line_len >= 1). */
-static int apply_prec(int64_t n, int64_t line_len, const double *dinv, const double *ld,
-                      const double *le, const double *r, double *z, double *work)
+/* The preconditioner of a PCG run: the inverse diagonal, the inverse of the
+ * column blocks (line_len >= 1), or IC(0) in the multicolour order (L set). */
+typedef struct {
+    int64_t line_len;
+    const double *dinv, *ld, *le;
+    double *work;
+    const or_csr *L;
+    const int32_t *perm;
+    double *y;
+} prec_t;
+
+static int apply_prec_line(int64_t n, int64_t line_len, const double *dinv, const double *ld,
+                           const double *le, const double *r, double *z, double *work);
+static void ic0_apply(const or_csr *L, const int32_t *perm, const double *r, double *z,
+                      double *y);
+
+static int apply_prec(int64_t n, const prec_t *P, const double *r, double *z)
+{
+    if (P->L) {
+        ic0_apply(P->L, P->perm, r, z, P->y);
+        return OR_OK;
+    }
+    return apply_prec_line(n, P->line_len, P->dinv, P->ld, P->le, r, z, P->work);
+}
+
+/* z = M^-1 r: the inverse diagonal (line_len == 0) or the inverse of the
+ * column blocks (line_len >= 1). */
+static int apply_prec_line(int64_t n, int64_t line_len, const double *dinv, const double *ld,
+                           const double *le, const double *r, double *z, double *work)
 {
     if (line_len == 0) {
         for (int64_t i = 0; i < n; ++i) z[i] = dinv[i] * r[i];
@@ -511,6 +536,162 @@ static int apply_prec(int64_t n, int64_t line_len, const double *dinv, const dou
         if (st != OR_OK) return st;
     }
     return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Incomplete Cholesky IC(0) in a multicolour ordering                       */
+/* ------------------------------------------------------------------------ */
+
+/* Greedy colouring of the matrix graph in node order: node i takes the
+ * smallest colour not taken by a neighbour j < i (j != i with A_ij stored).
+ * Returns the number of colours. */
+int or_greedy_colors(const or_csr *A, int32_t *color)
+{
+    int64_t n = A->n;
+    int32_t ncol = 0;
+    char *used = calloc(64, 1);
+    if (!used) return OR_ERR_NOMEM;
+    for (int64_t i = 0; i < n; ++i) {
+        memset(used, 0, 64);
+        for (int64_t s = A->rowptr[i]; s < A->rowptr[i + 1]; ++s) {
+            int32_t j = A->col[s];
+            if (j < i && color[j] < 64) used[color[j]] = 1;
+        }
+        int32_t c = 0;
+        while (c < 64 && used[c]) ++c;
+        if (c >= 64) {
+            free(used);
+            return OR_ERR_INVALID;
+        }
+        color[i] = c;
+        if (c + 1 > ncol) ncol = c + 1;
+    }
+    free(used);
+    return ncol;
+}
+
+/* The multicolour permutation: nodes sorted by (colour, node); perm[k] is
+ * the node at position k, iperm its inverse. */
+static void color_order(int64_t n, const int32_t *color, int32_t ncol, int32_t *perm,
+                        int32_t *iperm)
+{
+    int64_t k = 0;
+    for (int32_t c = 0; c < ncol; ++c)
+        for (int64_t i = 0; i < n; ++i)
+            if (color[i] == c) {
+                perm[k] = (int32_t)i;
+                iperm[i] = (int32_t)k;
+                ++k;
+            }
+}
+
+static int cmp_i32(const void *a, const void *b)
+{
+    int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+    return (x > y) - (x < y);
+}
+
+/* IC(0) of B = P A P^T (P the permutation above): lower triangular L with the
+ * pattern of the lower triangle of B such that (L L^T)_ij = B_ij on that
+ * pattern, computed row by row:
+ *   L_ij = (B_ij - sum_{k < j} L_ik L_jk) / L_jj     for j < i in the pattern,
+ *   L_ii = sqrt(B_ii - sum_{k < i} L_ik^2),
+ * the sums running over the stored entries of both rows.  Output: CSR of L
+ * (row i of B's order, ascending columns, the diagonal last).  Returns
+ * OR_ERR_BREAKDOWN when a pivot is not positive. */
+int or_ic0(const or_csr *A, const int32_t *perm, const int32_t *iperm, or_csr **Lout)
+{
+    *Lout = NULL;
+    int64_t n = A->n;
+    or_csr *L = calloc(1, sizeof(or_csr));
+    if (!L) return OR_ERR_NOMEM;
+    L->n = n;
+    L->rowptr = malloc(sizeof(int64_t) * (size_t)(n + 1));
+    /* lower pattern of B, rows of B in order */
+    int64_t cap = A->nnz + n;
+    L->col = malloc(sizeof(int32_t) * (size_t)cap);
+    L->val = malloc(sizeof(double) * (size_t)cap);
+    int32_t *tmpc = malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    if (!L->rowptr || !L->col || !L->val || !tmpc) {
+        free(tmpc);
+        or_csr_free(L);
+        return OR_ERR_NOMEM;
+    }
+    int64_t k = 0;
+    L->rowptr[0] = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t row = perm[i];
+        int64_t m = 0;
+        for (int64_t s = A->rowptr[row]; s < A->rowptr[row + 1]; ++s) {
+            int32_t j = iperm[A->col[s]];
+            if (j < i) tmpc[m++] = j;
+        }
+        qsort(tmpc, (size_t)m, sizeof(int32_t), cmp_i32);
+        for (int64_t t = 0; t < m; ++t) L->col[k + t] = tmpc[t];
+        L->col[k + m] = (int32_t)i;
+        k += m + 1;
+        L->rowptr[i + 1] = k;
+    }
+    L->nnz = k;
+    free(tmpc);
+    /* values row by row */
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t row = perm[i];
+        int64_t b0 = L->rowptr[i], b1 = L->rowptr[i + 1] - 1; /* strict lower [b0, b1) */
+        double diag = 0.0;
+        for (int64_t s = A->rowptr[row]; s < A->rowptr[row + 1]; ++s)
+            if (A->col[s] == row) diag = A->val[s];
+        for (int64_t t = b0; t < b1; ++t) {
+            int32_t j = L->col[t];
+            double bij = 0.0;
+            for (int64_t s = A->rowptr[row]; s < A->rowptr[row + 1]; ++s)
+                if (iperm[A->col[s]] == j) bij = A->val[s];
+            /* sum over k < j common to rows i (entries b0..t-1) and j */
+            double sum = 0.0;
+            int64_t u = b0, v = L->rowptr[j], vend = L->rowptr[j + 1] - 1;
+            while (u < t && v < vend) {
+                if (L->col[u] == L->col[v]) {
+                    sum += L->val[u] * L->val[v];
+                    ++u;
+                    ++v;
+                } else if (L->col[u] < L->col[v]) {
+                    ++u;
+                } else {
+                    ++v;
+                }
+            }
+            L->val[t] = (bij - sum) / L->val[L->rowptr[j + 1] - 1];
+        }
+        double d = diag;
+        for (int64_t t = b0; t < b1; ++t) d -= L->val[t] * L->val[t];
+        if (!(d > 0.0)) {
+            or_csr_free(L);
+            return OR_ERR_BREAKDOWN;
+        }
+        L->val[b1] = sqrt(d);
+    }
+    *Lout = L;
+    return OR_OK;
+}
+
+/* z = P^T (L L^T)^-1 P r: forward substitution with L, backward with L^T
+ * (column-oriented over the rows of L), in the permuted order. */
+static void ic0_apply(const or_csr *L, const int32_t *perm, const double *r, double *z,
+                      double *y)
+{
+    int64_t n = L->n;
+    for (int64_t i = 0; i < n; ++i) {
+        double s = r[perm[i]];
+        int64_t d = L->rowptr[i + 1] - 1;
+        for (int64_t t = L->rowptr[i]; t < d; ++t) s -= L->val[t] * y[L->col[t]];
+        y[i] = s / L->val[d];
+    }
+    for (int64_t i = n - 1; i >= 0; --i) {
+        int64_t d = L->rowptr[i + 1] - 1;
+        y[i] /= L->val[d];
+        for (int64_t t = L->rowptr[i]; t < d; ++t) y[L->col[t]] -= L->val[t] * y[i];
+    }
+    for (int64_t i = 0; i < n; ++i) z[perm[i]] = y[i];
 }
 
 /* ------------------------------------------------------------------------ */
@@ -549,11 +730,11 @@ static int apply_prec(int64_t n, int64_t line_len, const double *dinv, const dou
  * numbering; n must be a multiple of L), applied by or_tridiag_solve.
  * or_pcg is or_pcg_line with line_len = 0.
  */
-int or_pcg_line(const or_csr *A0, const uint8_t *dirichlet, int singular,
-                const double *weights, const double *b0, double *x, double tol,
-                int maxit, int64_t line_len, int *iters_out, double *relres_out,
-                double *removed_mean, double *alpha_hist, double *beta_hist,
-                double *x_hist)
+static int pcg_core(const or_csr *A0, const uint8_t *dirichlet, int singular,
+                    const double *weights, const double *b0, double *x, double tol, int maxit,
+                    int64_t line_len, int ic0, int *iters_out, double *relres_out,
+                    double *removed_mean, double *alpha_hist, double *beta_hist,
+                    double *x_hist)
 {
     int64_t n = A0->n;
     if (line_len < 0 || (line_len > 0 && n % line_len != 0)) return OR_ERR_INVALID;
@@ -573,8 +754,15 @@ int or_pcg_line(const or_csr *A0, const uint8_t *dirichlet, int singular,
     double *ld = line_len ? malloc(sizeof(double) * (size_t)n) : NULL;
     double *le = line_len ? malloc(sizeof(double) * (size_t)n) : NULL;
     double *work = line_len ? malloc(sizeof(double) * (size_t)line_len) : NULL;
+    int32_t *color = ic0 ? malloc(sizeof(int32_t) * (size_t)n) : NULL;
+    int32_t *perm = ic0 ? malloc(sizeof(int32_t) * (size_t)n) : NULL;
+    int32_t *iperm = ic0 ? malloc(sizeof(int32_t) * (size_t)n) : NULL;
+    double *ywork = ic0 ? malloc(sizeof(double) * (size_t)n) : NULL;
+    or_csr *L = NULL;
+    prec_t P;
     int status = OR_NOT_CONVERGED;
-    if (!A || !b || !r || !z || !p || !q || !dinv || (line_len && (!ld || !le || !work))) {
+    if (!A || !b || !r || !z || !p || !q || !dinv || (line_len && (!ld || !le || !work)) ||
+        (ic0 && (!color || !perm || !iperm || !ywork))) {
         status = OR_ERR_NOMEM;
         goto done;
     }
@@ -598,6 +786,24 @@ int or_pcg_line(const or_csr *A0, const uint8_t *dirichlet, int singular,
         dinv[i] = 1.0 / d;
     }
     if (line_len) column_blocks(A, line_len, ld, le);
+    if (ic0) {
+        int ncol = or_greedy_colors(A, color);
+        if (ncol < 0) {
+            status = ncol;
+            goto done;
+        }
+        color_order(n, color, ncol, perm, iperm);
+        if ((status = or_ic0(A, perm, iperm, &L)) != OR_OK) goto done;
+        status = OR_NOT_CONVERGED;
+    }
+    P.line_len = line_len;
+    P.dinv = dinv;
+    P.ld = ld;
+    P.le = le;
+    P.work = work;
+    P.L = L;
+    P.perm = perm;
+    P.y = ywork;
     double bnorm = sqrt(dot(n, b, b));
     if (bnorm == 0.0) {
         for (int64_t i = 0; i < n; ++i) x[i] = 0.0;
@@ -607,7 +813,7 @@ int or_pcg_line(const or_csr *A0, const uint8_t *dirichlet, int singular,
     or_spmv(A, x, q);
     for (int64_t i = 0; i < n; ++i) r[i] = b[i] - q[i];
     if (singular) remove_mean(n, r);
-    if ((status = apply_prec(n, line_len, dinv, ld, le, r, z, work)) != OR_OK) goto done;
+    if ((status = apply_prec(n, &P, r, z)) != OR_OK) goto done;
     status = OR_NOT_CONVERGED;
     for (int64_t i = 0; i < n; ++i) p[i] = z[i];
     double rho = dot(n, r, z);
@@ -655,7 +861,7 @@ int or_pcg_line(const or_csr *A0, const uint8_t *dirichlet, int singular,
             }
             /* restart from the true residual */
             memcpy(r, q, sizeof(double) * (size_t)n);
-            if ((status = apply_prec(n, line_len, dinv, ld, le, r, z, work)) != OR_OK) break;
+            if ((status = apply_prec(n, &P, r, z)) != OR_OK) break;
             status = OR_NOT_CONVERGED;
             for (int64_t i = 0; i < n; ++i) p[i] = z[i];
             rho = dot(n, r, z);
@@ -663,7 +869,7 @@ int or_pcg_line(const or_csr *A0, const uint8_t *dirichlet, int singular,
             if (beta_hist) beta_hist[it - 1] = 0.0;
             continue;
         }
-        if ((status = apply_prec(n, line_len, dinv, ld, le, r, z, work)) != OR_OK) break;
+        if ((status = apply_prec(n, &P, r, z)) != OR_OK) break;
         status = OR_NOT_CONVERGED;
         double rho_new = dot(n, r, z);
         double beta = rho_new / rho;
@@ -694,7 +900,60 @@ done:
     free(ld);
     free(le);
     free(work);
+    free(color);
+    free(perm);
+    free(iperm);
+    free(ywork);
+    or_csr_free(L);
     return status;
+}
+
+int or_pcg_line(const or_csr *A0, const uint8_t *dirichlet, int singular,
+                const double *weights, const double *b0, double *x, double tol,
+                int maxit, int64_t line_len, int *iters_out, double *relres_out,
+                double *removed_mean, double *alpha_hist, double *beta_hist,
+                double *x_hist)
+{
+    return pcg_core(A0, dirichlet, singular, weights, b0, x, tol, maxit, line_len, 0, iters_out,
+                    relres_out, removed_mean, alpha_hist, beta_hist, x_hist);
+}
+
+/* PCG with IC(0) of the eliminated matrix in the greedy multicolour order
+ * (or_greedy_colors, or_ic0): the preconditioner of Remark 3 at the end of
+ * Sec. 5 for the velocity systems, in an order whose triangular solves run
+ * colour by colour. */
+int or_pcg_ic0(const or_csr *A0, const uint8_t *dirichlet, int singular,
+               const double *weights, const double *b0, double *x, double tol, int maxit,
+               int *iters_out, double *relres_out, double *removed_mean, double *alpha_hist,
+               double *beta_hist, double *x_hist)
+{
+    return pcg_core(A0, dirichlet, singular, weights, b0, x, tol, maxit, 0, 1, iters_out,
+                    relres_out, removed_mean, alpha_hist, beta_hist, x_hist);
+}
+
+/* IC(0) factor of the eliminated matrix in the greedy multicolour order:
+ * perm (n) receives the order, L the factor (for tests). */
+int or_ic0_factor(const or_csr *A0, const uint8_t *dirichlet, int32_t *perm, or_csr **L)
+{
+    int64_t n = A0->n;
+    *L = NULL;
+    or_csr *A = or_eliminate(A0, dirichlet);
+    int32_t *color = malloc(sizeof(int32_t) * (size_t)n);
+    int32_t *iperm = malloc(sizeof(int32_t) * (size_t)n);
+    int st = OR_ERR_NOMEM;
+    if (A && color && iperm) {
+        int ncol = or_greedy_colors(A, color);
+        if (ncol < 0) {
+            st = ncol;
+        } else {
+            color_order(n, color, ncol, perm, iperm);
+            st = or_ic0(A, perm, iperm, L);
+        }
+    }
+    free(color);
+    free(iperm);
+    or_csr_free(A);
+    return st;
 }
 
 int or_pcg(const or_csr *A0, const uint8_t *dirichlet, int singular, const double *weights,
