@@ -77,6 +77,8 @@ typedef struct {
                                 first step, BDF2 uses dt' = 2 dt / 3)                */
 /* Options */
 #define HNS_KEEP_FP32 0x10u  /* also keep FP32 matrix/diagonal copies (HNS_MIXED)  */
+#define HNS_KEEP_HOST 0x80u  /* keep a host copy of the assembled matrix (needed by
+                                the IC(0) preconditioner, set_param "precond" = 2)   */
 #define HNS_GPU_ASSEMBLY 0x40u /* compute the operator's values on the device (one
                                 lane per row gathers its tetrahedra in order, as the
                                 host loop does; bitwise the same values); the
@@ -267,7 +269,19 @@ int hns_operator_line_len(const hns_operator *op);
  *                  vertical couplings dwarf the horizontal ones, e.g. the
  *                  isotropic pressure operator of eq. fofa_q_cor_h.
  *                  Needs hns_operator_line_len >= 2; HNS_FP64 single
- *                  right-hand-side solves only (HNS_ERR_INVALID otherwise). */
+ *                  right-hand-side solves only (HNS_ERR_INVALID otherwise).
+ *                  2 = incomplete Cholesky IC(0) (the velocity-system
+ *                  preconditioner of the paper's Sec. 5 remarks) in a greedy
+ *                  multicolour order: nodes coloured in node order with the
+ *                  smallest colour no lower-numbered neighbour of the matrix
+ *                  graph (Dirichlet rows and columns removed) has, then sorted
+ *                  by (colour, node); L has the pattern of the lower triangle
+ *                  of the reordered matrix and (L L^T)_ij matches it there.
+ *                  Each triangular solve runs one launch per colour.
+ *                  Factorised on the host per Dirichlet set on first use
+ *                  (needs HNS_KEEP_HOST); HNS_FP64 single right-hand sides
+ *                  with a Dirichlet set only; HNS_ERR_BREAKDOWN on a
+ *                  non-positive pivot. */
 hns_status hns_set_param(hns_operator *op, const char *name, double value);
 
 /* y = A x on the device (FP64), with the rows of Dirichlet set mask_bit

@@ -20,6 +20,7 @@ HNS_HELMHOLTZ = 0x2
 HNS_KEEP_FP32 = 0x10
 HNS_STEP_AUX = 0x20
 HNS_GPU_ASSEMBLY = 0x40
+HNS_KEEP_HOST = 0x80
 HNS_FMT_AUTO = 0x000
 HNS_FMT_CSR = 0x100
 HNS_FMT_SELL = 0x200

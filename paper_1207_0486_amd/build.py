@@ -19,8 +19,8 @@ LIB = os.path.join(HERE, "libhns.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["assemble.cpp", "assemble_gpu.hip", "kernels.hip", "solve.hip", "batched.hip",
-           "step.hip"]
+SOURCES = ["assemble.cpp", "assemble_gpu.hip", "ic0.cpp", "kernels.hip", "solve.hip",
+           "batched.hip", "step.hip"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", INCLUDE, "-I", CSRC,
           "-Wall", "-Wno-unused-result", "-Xclang", "-target-feature", "-Xclang",

@@ -87,6 +87,35 @@ struct DevMatrix {
     void release();
 };
 
+// IC(0) in the greedy multicolour order, host side (ic0.cpp)
+struct IC0Host {
+    int64_t n = 0;
+    int ncolors = 0;
+    std::vector<int32_t> perm;     // permuted position -> node
+    std::vector<int64_t> cstart;   // first position of each colour (ncolors + 1)
+    std::vector<int64_t> lptr;     // strict lower factor by permuted rows
+    std::vector<int32_t> lcol;
+    std::vector<double> lval;
+    std::vector<int64_t> uptr;     // its transpose (strict upper) by permuted rows
+    std::vector<int32_t> ucol;
+    std::vector<double> uval;
+    std::vector<double> diag;      // L_ii
+};
+hns_status ic0_factor_host(const HostCSR &A, const uint8_t *bc, int bit, IC0Host &F);
+
+// IC(0) factor on the device
+struct IC0Dev {
+    int64_t n = 0;
+    int ncolors = 0;
+    std::vector<int64_t> cstart;   // host copy of the colour starts
+    int32_t *perm = nullptr;
+    int64_t *lptr = nullptr, *uptr = nullptr;
+    int32_t *lcol = nullptr, *ucol = nullptr;
+    double *lval = nullptr, *uval = nullptr, *diag = nullptr;
+    size_t bytes = 0;
+    void release();
+};
+
 struct Scalars;           // device-side CG scalars (kernels.hip)
 struct Workspace;         // per-solve device buffers (solve.hip)
 struct BWorkspace;        // multi-right-hand-side buffers (batched.hip)
@@ -149,6 +178,11 @@ struct hns_operator {
     std::mutex line_mutex;
     double *line_fac[9] = {nullptr, nullptr, nullptr, nullptr, nullptr,
                            nullptr, nullptr, nullptr, nullptr};
+    // IC(0) preconditioner (precond = 2): host copy of the assembled matrix
+    // (kept with HNS_KEEP_HOST) and the device factors per mask (index bit + 1)
+    hns::HostCSR host_A;
+    hns::IC0Dev *ic0_fac[9] = {nullptr, nullptr, nullptr, nullptr, nullptr,
+                               nullptr, nullptr, nullptr, nullptr};
 };
 
 namespace hns {

@@ -71,6 +71,10 @@ struct IterArgs {
     const double *lfac = nullptr;
     double *z = nullptr;
     int line_len = 0;
+    // IC(0) preconditioner (FP64 only): when ic is set, z = M^-1 r by the
+    // colour-by-colour triangular solves; y is an n-vector of scratch
+    const IC0Dev *ic = nullptr;
+    double *y = nullptr;
 };
 
 // One CG iteration = three launches:
@@ -113,6 +117,10 @@ int line_grid(int64_t n, int line_len);
 hns_status launch_init_line(int64_t n, int line_len, double *r, double *p, const double *lfac,
                             bool singular, bool bb_from_rr, Scalars *sc, double *partials,
                             hipStream_t s);
+
+// IC(0) first direction (FP64): z = M^-1 r; p = z; rho[0] = r^T z; rr = r^T r.
+hns_status launch_init_ic0(int64_t n, const IC0Dev &F, const double *r, double *p, double *z,
+                           double *y, Scalars *sc, double *partials, hipStream_t s);
 
 hns_status launch_project_norm(int64_t n, double *r, bool singular, Scalars *sc,
                                double *partials, hipStream_t s);

@@ -849,6 +849,157 @@ __global__ __launch_bounds__(kBlock) void k_init_line(int64_t n, int L, int NC,
     }
 }
 
+// ---------------------------------------------------------------------------
+// IC(0) in the multicolour order
+// ---------------------------------------------------------------------------
+// Rows of one colour are not coupled, so each triangular solve is one launch
+// per colour, one lane per row (permuted positions [r0, r1)).
+
+// forward: y_r = (r[perm_r] - sum_t L_rt y_t) / L_rr
+__global__ __launch_bounds__(kBlock) void k_ic_forward(int64_t r0, int64_t r1,
+                                                       const int32_t *__restrict__ perm,
+                                                       const int64_t *__restrict__ lptr,
+                                                       const int32_t *__restrict__ lcol,
+                                                       const double *__restrict__ lval,
+                                                       const double *__restrict__ diag,
+                                                       const double *__restrict__ r,
+                                                       double *__restrict__ y)
+{
+    for (int64_t row = r0 + blockIdx.x * (int64_t)kBlock + threadIdx.x; row < r1;
+         row += (int64_t)gridDim.x * kBlock) {
+        double v = r[perm[row]];
+        for (int64_t t = lptr[row]; t < lptr[row + 1]; ++t) v -= lval[t] * y[lcol[t]];
+        y[row] = v / diag[row];
+    }
+}
+
+// backward: w_r = (y_r - sum_t U_rt w_t) / L_rr (U = L^T), in place in y;
+// z[perm_r] = w_r
+__global__ __launch_bounds__(kBlock) void k_ic_backward(int64_t r0, int64_t r1,
+                                                        const int32_t *__restrict__ perm,
+                                                        const int64_t *__restrict__ uptr,
+                                                        const int32_t *__restrict__ ucol,
+                                                        const double *__restrict__ uval,
+                                                        const double *__restrict__ diag,
+                                                        double *__restrict__ y,
+                                                        double *__restrict__ z)
+{
+    for (int64_t row = r0 + blockIdx.x * (int64_t)kBlock + threadIdx.x; row < r1;
+         row += (int64_t)gridDim.x * kBlock) {
+        double v = y[row];
+        for (int64_t t = uptr[row]; t < uptr[row + 1]; ++t) v -= uval[t] * y[ucol[t]];
+        v /= diag[row];
+        y[row] = v;
+        z[perm[row]] = v;
+    }
+}
+
+template <int W>
+struct XRPQPacks {
+    Pack<double, W> x, r, p, q;
+};
+
+// x += alpha p; r -= alpha q (no partials: r^T z and r^T r follow the solves)
+template <int V>
+__global__ __launch_bounds__(kBlock) void k_update_noz(int64_t n, int64_t per,
+                                                       double *__restrict__ x,
+                                                       double *__restrict__ r,
+                                                       const double *__restrict__ p,
+                                                       const double *__restrict__ q,
+                                                       Scalars *__restrict__ sc,
+                                                       const double *__restrict__ part_in,
+                                                       int G_in, int parity)
+{
+    if (sc->stop) return;
+    double alpha = 0.0;
+    auto load = [&](int64_t i, auto w) {
+        constexpr int W = decltype(w)::value;
+        return XRPQPacks<W>{ld<W>(x, i), ld<W>(r, i), ld<W>(p, i), ld<W>(q, i)};
+    };
+    auto prologue = [&]() {
+        double g[1];
+        load_reduced<1>(part_in, G_in, g);
+        const double gamma = g[0];
+        if (!(gamma > 0.0) || !isfinite(gamma)) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) {
+                sc->gamma = gamma;
+                sc->stop = 2;
+            }
+            return false;
+        }
+        alpha = sc->rho[parity] / gamma;
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            sc->gamma = gamma;
+            sc->alpha = alpha;
+        }
+        return true;
+    };
+    auto body = [&](int64_t i, auto in) {
+        constexpr int W = sizeof(in.x.v) / sizeof(double);
+#pragma unroll
+        for (int e = 0; e < W; ++e) {
+            in.x.v[e] = in.x.v[e] + alpha * in.p.v[e];
+            in.r.v[e] = in.r.v[e] - alpha * in.q.v[e];
+        }
+        st<W>(x, i, in.x);
+        st<W>(r, i, in.r);
+    };
+    for_packs_ahead<V>(n, per, load, prologue, body);
+}
+
+// per-block partials of r^T z and r^T r (consumed like the update's)
+template <int V>
+__global__ __launch_bounds__(kBlock) void k_dot_rz(int64_t n, int64_t per,
+                                                   const double *__restrict__ r,
+                                                   const double *__restrict__ z,
+                                                   const Scalars *__restrict__ sc,
+                                                   double *__restrict__ part_out)
+{
+    if (sc->stop) return;
+    double rz = 0.0, rr = 0.0;
+    for_packs<V>(n, per, [&](int64_t i, auto w) {
+        constexpr int W = decltype(w)::value;
+        const auto rv = ld<W>(r, i);
+        const auto zv = ld<W>(z, i);
+#pragma unroll
+        for (int e = 0; e < W; ++e) {
+            rz += rv.v[e] * zv.v[e];
+            rr += rv.v[e] * rv.v[e];
+        }
+    });
+    double v[2] = {rz, rr};
+    store_block_partials<2>(v, part_out);
+}
+
+// p = z; rho[0] = r^T z; rr = r^T r (first direction of an IC(0) recurrence)
+__global__ __launch_bounds__(kBlock) void k_init_from_z(int64_t n, const double *__restrict__ r,
+                                                        const double *__restrict__ z,
+                                                        double *__restrict__ p,
+                                                        Scalars *__restrict__ sc,
+                                                        double *__restrict__ partials)
+{
+    double rz = 0.0, rr = 0.0;
+    GRID_STRIDE(i, n)
+    {
+        const double ri = r[i], zi = z[i];
+        p[i] = zi;
+        rz += ri * zi;
+        rr += ri * ri;
+    }
+    double v[2] = {rz, rr};
+    if (grid_sum<2>(v, partials, &sc->counter[2]) && threadIdx.x == 0) {
+        sc->rho[0] = v[0];
+        sc->rr = v[1];
+        sc->beta = 0.0;
+        if (!(sc->bb > 0.0))
+            sc->stop = 3;
+        else if (!isfinite(v[0]) || !isfinite(v[1]))
+            sc->stop = 2;
+        else
+            sc->stop = (v[1] <= sc->tol2 * sc->bb) ? 1 : 0;
+    }
+}
+
 // Residual replacement: the working residual becomes the FP64 true residual
 // (converted to TX when dst is given, else src is the working residual), with
 // per-block partials of r^T D^-1 r and r^T r for the k_pupdate that follows.
@@ -1123,6 +1274,59 @@ hns_status line_iteration(const IterArgs &a, int parity, hipStream_t s, hipEvent
     return check_launch("line-preconditioned cg iteration");
 }
 
+// z = M^-1 r with the IC(0) factor: one launch per colour and direction
+hns_status ic0_apply(const IC0Dev &F, const double *r, double *y, double *z, hipStream_t s)
+{
+    for (int c = 0; c < F.ncolors; ++c) {
+        const int64_t r0 = F.cstart[c], r1 = F.cstart[c + 1];
+        if (r1 <= r0) continue;
+        k_ic_forward<<<stream_grid(r1 - r0), kBlock, 0, s>>>(r0, r1, F.perm, F.lptr, F.lcol,
+                                                              F.lval, F.diag, r, y);
+    }
+    for (int c = F.ncolors - 1; c >= 0; --c) {
+        const int64_t r0 = F.cstart[c], r1 = F.cstart[c + 1];
+        if (r1 <= r0) continue;
+        k_ic_backward<<<stream_grid(r1 - r0), kBlock, 0, s>>>(r0, r1, F.perm, F.uptr, F.ucol,
+                                                               F.uval, F.diag, y, z);
+    }
+    return check_launch("ic0 triangular solves");
+}
+
+// Event pairs as in line_iteration; the triangular solves are not timed.
+hns_status ic0_iteration(const IterArgs &a, int parity, hipStream_t s, hipEvent_t *ev)
+{
+    const uint8_t *bc = a.bit < 0 ? nullptr : a.bc;
+    double *P1 = a.partials + kPartSpmv;
+    double *P2 = a.partials + kPartUpdate;
+    const bool vec = aligned16(a.x) && aligned16(a.r) && aligned16(a.p) && aligned16(a.q) &&
+                     aligned16(a.z);
+    const Chunks cu = chunks(vec ? a.n / 2 : a.n, (int64_t)kBlock * a.A->vec_it, kBlock);
+    const int Gs = spmv_dispatch<double, double, true>(*a.A, a.p, a.q, bc, a.bit, a.sc, P1, s,
+                                                       ev ? ev : nullptr);
+    if (Gs < 0) return check_launch("spmv");
+    if (vec) {
+        HNS_TRY_HIP(launch_k(k_update_noz<2>, cu.grid, kBlock, 0, s, ev ? ev + 2 : nullptr, a.n,
+                             cu.per, (double *)a.x, (double *)a.r, (const double *)a.p,
+                             (const double *)a.q, a.sc, (const double *)P1, Gs, parity));
+    } else {
+        HNS_TRY_HIP(launch_k(k_update_noz<1>, cu.grid, kBlock, 0, s, ev ? ev + 2 : nullptr, a.n,
+                             cu.per, (double *)a.x, (double *)a.r, (const double *)a.p,
+                             (const double *)a.q, a.sc, (const double *)P1, Gs, parity));
+    }
+    HNS_TRY(ic0_apply(*a.ic, (const double *)a.r, a.y, a.z, s));
+    if (vec)
+        k_dot_rz<2><<<cu.grid, kBlock, 0, s>>>(a.n, cu.per, (const double *)a.r, a.z, a.sc, P2);
+    else
+        k_dot_rz<1><<<cu.grid, kBlock, 0, s>>>(a.n, cu.per, (const double *)a.r, a.z, a.sc, P2);
+    HNS_TRY(check_launch("dot r.z"));
+    // p and z are workspace vectors (16-byte aligned): packs of two always
+    const Chunks cp = chunks(a.n / 2, (int64_t)kBlock * a.A->vec_it, kBlock);
+    HNS_TRY_HIP(launch_k(k_pupdate_line, cp.grid, kBlock, 0, s, ev ? ev + 4 : nullptr, a.n,
+                         cp.per, (double *)a.p, (const double *)a.z, a.sc, (const double *)P2,
+                         cu.grid, parity));
+    return check_launch("ic0-preconditioned cg iteration");
+}
+
 template <typename TV, typename TX, typename TD>
 hns_status iteration_impl(const IterArgs &a, int parity, hipStream_t s, hipEvent_t *ev)
 {
@@ -1233,8 +1437,23 @@ hns_status launch_init_line(int64_t n, int line_len, double *r, double *p, const
     return check_launch("init_line");
 }
 
+hns_status launch_init_ic0(int64_t n, const IC0Dev &F, const double *r, double *p, double *z,
+                           double *y, Scalars *sc, double *partials, hipStream_t s)
+{
+    HNS_TRY(ic0_apply(F, r, y, z, s));
+    k_init_from_z<<<stream_grid(n), kBlock, 0, s>>>(n, r, z, p, sc, partials + kPartMisc);
+    return check_launch("init_ic0");
+}
+
 hns_status launch_iteration(const IterArgs &a, int parity, hipStream_t s, hipEvent_t *ev)
 {
+    if (a.ic) {
+        if (a.prec != Prec::F64) {
+            set_error("the IC(0) preconditioner runs in FP64 only");
+            return HNS_ERR_INVALID;
+        }
+        return ic0_iteration(a, parity, s, ev);
+    }
     if (a.lfac) {
         if (a.prec != Prec::F64) {
             set_error("the line preconditioner runs in FP64 only");

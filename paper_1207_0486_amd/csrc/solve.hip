@@ -31,7 +31,8 @@ struct Workspace {
     double *r = nullptr, *p = nullptr, *q = nullptr;
     float *r32 = nullptr, *p32 = nullptr, *q32 = nullptr, *d32 = nullptr;
     double *partials = nullptr;   // kPartTotal doubles
-    double *z = nullptr;          // M^-1 r of the line preconditioner (allocated on first use)
+    double *z = nullptr;          // M^-1 r of the line / IC(0) preconditioner (on first use)
+    double *y = nullptr;          // scratch of the IC(0) triangular solves (on first use)
     Scalars *sc = nullptr;        // [0] FP64 / outer loop, [1] inner FP32 loop
     Scalars *host = nullptr;      // pinned mirror of sc[0..1]
     std::vector<hipEvent_t> ev;   // timing events, a (start, end) pair per kernel of an iteration
@@ -98,10 +99,24 @@ struct Workspace {
         return HNS_OK;
     }
 
+    hns_status ensure_y()
+    {
+        if (y) return HNS_OK;
+        hipError_t e = hipMalloc(&y, n * sizeof(double));
+        if (e != hipSuccess) {
+            y = nullptr;
+            set_error("allocation of the triangular-solve scratch failed: %s",
+                      hipGetErrorString(e));
+            return e == hipErrorOutOfMemory ? HNS_ERR_OOM : HNS_ERR_HIP;
+        }
+        return HNS_OK;
+    }
+
     ~Workspace()
     {
         for (hipEvent_t e : ev) (void)hipEventDestroy(e);
         if (z) (void)hipFree(z);
+        if (y) (void)hipFree(y);
         if (block) (void)hipFree(block);
         if (host) (void)hipHostFree(host);
     }
@@ -172,6 +187,7 @@ struct SolveCtx {
     hipStream_t s;
     Workspace *w;
     const double *lfac = nullptr;   // line-preconditioner factors of this mask (FP64 solves)
+    const IC0Dev *ic = nullptr;     // IC(0) factor of this mask (FP64 solves)
 };
 
 // Enqueue `count` CG iterations of one recurrence.  parity0 is the number of
@@ -182,7 +198,7 @@ struct SolveCtx {
 static hns_status enqueue_iterations(hns_operator *op, Workspace *w, Prec prec, int bit, void *x,
                                      void *r, void *p, void *q, const void *dinv, Scalars *sc,
                                      int count, int parity0, hipStream_t s,
-                                     const double *lfac = nullptr)
+                                     const double *lfac = nullptr, const IC0Dev *ic = nullptr)
 {
     const int period = op->profile;
     if (period > 0) HNS_TRY(w->ensure_events(6 * (size_t)count));
@@ -191,6 +207,11 @@ static hns_status enqueue_iterations(hns_operator *op, Workspace *w, Prec prec, 
         a.lfac = lfac;
         a.z = w->z;
         a.line_len = op->line_len;
+    }
+    if (ic) {
+        a.ic = ic;
+        a.z = w->z;
+        a.y = w->y;
     }
     for (int it = 0; it < count; ++it) {
         const bool timed = period > 0 && (it % period) == 0;
@@ -231,7 +252,8 @@ static hns_status run_chunks(const SolveCtx &c, int which, Prec prec, void *x, v
         const int chunk = left < op->check_every ? left : op->check_every;
         const int before = h.iter;
         HNS_TRY(enqueue_iterations(op, w, prec, c.bit, x, r, p, q, dinv, w->sc + which, chunk,
-                                   *since_start, c.s, prec == Prec::F64 ? c.lfac : nullptr));
+                                   *since_start, c.s, prec == Prec::F64 ? c.lfac : nullptr,
+                                   prec == Prec::F64 ? c.ic : nullptr));
         HNS_TRY(pull_scalars(w, which, c.s));
         *since_start += h.iter - before;
         HNS_TRY(account_iterations(op, w, prec == Prec::F32, h.iter - before));
@@ -325,7 +347,10 @@ static hns_status solve_fp64_vectors(const SolveCtx &c, hns_solve_info *info, Pr
             }
             h.stop = 0;
             HNS_TRY(push_scalars(w, 0, c.s));
-            if (c.lfac && prec == Prec::F64)
+            if (c.ic && prec == Prec::F64)
+                HNS_TRY(launch_init_ic0(op->n, *c.ic, w->r, w->p, w->z, w->y, w->sc,
+                                        w->partials, c.s));
+            else if (c.lfac && prec == Prec::F64)
                 HNS_TRY(launch_init_line(op->n, op->line_len, w->r, w->p, c.lfac, false, false,
                                          w->sc, w->partials, c.s));
             else
@@ -742,6 +767,10 @@ hns_status hns_assemble(const hns_mesh *mesh, double nu_h, double nu_v, double d
     if (st == HNS_OK) {
         const int L = detect_columns(mesh);
         if (L >= 2) keep_column_blocks(op, A, L, mesh->bc);
+        if (flags & HNS_KEEP_HOST) {
+            op->host_A = A;
+            if (mesh->bc && op->bc_host.empty()) op->bc_host.assign(mesh->bc, mesh->bc + A.n);
+        }
     }
     if (st == HNS_OK && (flags & HNS_STEP_AUX)) st = assemble_step_aux(op, mesh, A);
     if (st != HNS_OK) {
@@ -767,6 +796,11 @@ void hns_operator_destroy(hns_operator *op)
         if (p) (void)hipFree(p);
     for (double *f : op->line_fac)
         if (f) (void)hipFree(f);
+    for (IC0Dev *f : op->ic0_fac)
+        if (f) {
+            f->release();
+            delete f;
+        }
     for (Workspace *w : op->ws_free) delete w;
     for (BWorkspace *w : op->bws_free) destroy_bworkspace(w);
     delete op;
@@ -841,7 +875,11 @@ hns_status hns_set_param(hns_operator *op, const char *name, double value)
         op->A.spmv_it32 = (int)value;
     } else if (k == "vec_it" && value >= 1 && value <= 64 && value == (int)value) {
         op->A.vec_it = (int)value;
-    } else if (k == "precond" && (value == 0 || value == 1)) {
+    } else if (k == "precond" && (value == 0 || value == 1 || value == 2)) {
+        if (value == 2 && op->host_A.col.empty()) {
+            set_error("precond = 2 (IC(0)) needs an operator assembled with HNS_KEEP_HOST");
+            return HNS_ERR_INVALID;
+        }
         if (value == 1) {
             if (op->line_len < 2) {
                 set_error("precond = 1 needs a node numbering made of water columns");
@@ -867,10 +905,13 @@ size_t hns_footprint_bytes(const hns_operator *op, int k, uint32_t mode, int inc
     if (!op || k < 1) return 0;
     const bool mixed = (mode == HNS_MIXED);
     size_t b = k == 1 ? Workspace::bytes_for(op->n, mixed) : bworkspace_bytes(op->n, k, mixed);
-    if (k == 1 && op->precond == 1) b += (size_t)op->n * sizeof(double);   // z
+    if (k == 1 && op->precond == 1) b += (size_t)op->n * sizeof(double);       // z
+    if (k == 1 && op->precond == 2) b += 2 * (size_t)op->n * sizeof(double);   // z, y
     if (include_operator) {
         for (const double *f : op->line_fac)
             if (f) b += 2 * (size_t)op->n * sizeof(double);
+        for (const IC0Dev *f : op->ic0_fac)
+            if (f) b += f->bytes;
         b += op->A.bytes() + (size_t)op->n * (8 + 1 + 8);
         if (op->dinv32) b += (size_t)op->n * 4;
         if (op->has_aux)
@@ -957,6 +998,65 @@ static hns_status line_factors(hns_operator *op, int bit, const double **out)
     return HNS_OK;
 }
 
+void IC0Dev::release()
+{
+    void *ptrs[] = {perm, lptr, uptr, lcol, ucol, lval, uval, diag};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    perm = nullptr;
+    lptr = uptr = nullptr;
+    lcol = ucol = nullptr;
+    lval = uval = diag = nullptr;
+}
+
+// Device IC(0) factor for Dirichlet set `bit`, factorised on first use.
+static hns_status ic0_factors(hns_operator *op, int bit, const IC0Dev **out)
+{
+    std::lock_guard<std::mutex> g(op->line_mutex);
+    IC0Dev *&slot = op->ic0_fac[bit + 1];
+    if (!slot) {
+        IC0Host H;
+        HNS_TRY(ic0_factor_host(op->host_A, op->bc_host.empty() ? nullptr : op->bc_host.data(),
+                                bit, H));
+        IC0Dev *D = new IC0Dev();
+        D->n = H.n;
+        D->ncolors = H.ncolors;
+        D->cstart = H.cstart;
+        auto up = [&](const void *src, size_t bytes, void **dst) -> hns_status {
+            hipError_t e = hipMalloc(dst, bytes > 0 ? bytes : 8);
+            if (e != hipSuccess) {
+                *dst = nullptr;
+                set_error("allocation of the IC(0) factor failed: %s", hipGetErrorString(e));
+                return e == hipErrorOutOfMemory ? HNS_ERR_OOM : HNS_ERR_HIP;
+            }
+            D->bytes += bytes;
+            if (bytes) HNS_TRY_HIP(hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice));
+            return HNS_OK;
+        };
+        hns_status st = HNS_OK;
+        auto run = [&]() -> hns_status {
+            HNS_TRY(up(H.perm.data(), H.perm.size() * 4, (void **)&D->perm));
+            HNS_TRY(up(H.lptr.data(), H.lptr.size() * 8, (void **)&D->lptr));
+            HNS_TRY(up(H.uptr.data(), H.uptr.size() * 8, (void **)&D->uptr));
+            HNS_TRY(up(H.lcol.data(), H.lcol.size() * 4, (void **)&D->lcol));
+            HNS_TRY(up(H.ucol.data(), H.ucol.size() * 4, (void **)&D->ucol));
+            HNS_TRY(up(H.lval.data(), H.lval.size() * 8, (void **)&D->lval));
+            HNS_TRY(up(H.uval.data(), H.uval.size() * 8, (void **)&D->uval));
+            HNS_TRY(up(H.diag.data(), H.diag.size() * 8, (void **)&D->diag));
+            return HNS_OK;
+        };
+        st = run();
+        if (st != HNS_OK) {
+            D->release();
+            delete D;
+            return st;
+        }
+        slot = D;
+    }
+    *out = slot;
+    return HNS_OK;
+}
+
 hns_status hns_solve(hns_operator *op, int mask_bit, const double *b_dev, double *x_dev,
                      double tol, int max_iter, uint32_t mode, void *stream, hns_solve_info *info)
 {
@@ -975,6 +1075,19 @@ hns_status hns_solve(hns_operator *op, int mask_bit, const double *b_dev, double
         return HNS_ERR_BREAKDOWN;
     }
     const double *lfac = nullptr;
+    const IC0Dev *ic = nullptr;
+    if (op->precond == 2) {
+        if (mode != HNS_FP64 || (op->kind == HNS_POISSON && mask_bit < 0)) {
+            set_error("the IC(0) preconditioner runs HNS_FP64 solves with a Dirichlet set only");
+            info->status = HNS_ERR_INVALID;
+            return HNS_ERR_INVALID;
+        }
+        st = ic0_factors(op, mask_bit, &ic);
+        if (st != HNS_OK) {
+            info->status = st;
+            return st;
+        }
+    }
     if (op->precond == 1) {
         if (mode != HNS_FP64) {
             set_error("the line preconditioner runs with HNS_FP64 only");
@@ -989,8 +1102,9 @@ hns_status hns_solve(hns_operator *op, int mask_bit, const double *b_dev, double
     }
     Workspace *w = nullptr;
     st = acquire_ws(op, mode == HNS_MIXED, &w);
-    if (st == HNS_OK && lfac) {
+    if (st == HNS_OK && (lfac || ic)) {
         st = w->ensure_z();
+        if (st == HNS_OK && ic) st = w->ensure_y();
         if (st != HNS_OK) release_ws(op, w);
     }
     if (st != HNS_OK) {
@@ -998,7 +1112,7 @@ hns_status hns_solve(hns_operator *op, int mask_bit, const double *b_dev, double
         return st;
     }
     SolveCtx c{op, mask_bit, op->kind == HNS_POISSON && mask_bit < 0, b_dev, x_dev, tol,
-               max_iter, (hipStream_t)stream, w, lfac};
+               max_iter, (hipStream_t)stream, w, lfac, ic};
     st = (mode == HNS_MIXED) ? solve_mixed(c, info) : solve_fp64(c, info);
     info->status = st;
     release_ws(op, w);

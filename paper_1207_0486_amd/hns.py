@@ -81,7 +81,8 @@ class Operator:
 
     def __init__(self, mesh, nu_h: float, nu_v: float, dt: float = 0.0, kind: str = "helmholtz",
                  keep_fp32: bool = False, step_aux: bool = False, fmt: str = "auto",
-                 device: int | torch.device | None = None, gpu_assembly: bool = False):
+                 device: int | torch.device | None = None, gpu_assembly: bool = False,
+                 keep_host: bool = False):
         self._h = None
         self.kind = kind
         flags = KINDS[kind] | FORMATS[fmt]
@@ -91,6 +92,8 @@ class Operator:
             flags |= L.HNS_STEP_AUX
         if gpu_assembly:
             flags |= L.HNS_GPU_ASSEMBLY
+        if keep_host:
+            flags |= L.HNS_KEEP_HOST
         xyz = np.ascontiguousarray(mesh.xyz, dtype=np.float64)
         tets = np.ascontiguousarray(mesh.tets, dtype=np.int32)
         bc = getattr(mesh, "bc", None)
