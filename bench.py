@@ -296,6 +296,47 @@ def bench_loop(torch, log, m, steps=4, stress_steps=2):
     return out
 
 
+def bench_preconditioners(torch, log, m, b_vel, reps=3):
+    """Velocity solve (component 1, its Dirichlet set) on the 256x256x20
+    basin with point Jacobi, vertical-line blocks and IC(0) in the greedy
+    multicolour order, to 1e-10: the workload operator M + dt K_nu and the
+    BDF2 operator of the paper's run constants (nu = (1e8, 1e8, 250), dt = one
+    month).  Time to tolerance with the operator resident; the first IC(0)
+    solve of a Dirichlet set includes its host factorisation and upload."""
+    import basin
+    from paper_1207_0486_amd.hns import Operator
+    wl = basin.configs.BASIN_256x256x20
+    cases = {"workload": (wl.nu_h, wl.nu_v, wl.dt),
+             "paper_constants_bdf2": (1e8, 250.0, 2.592e6 * 2.0 / 3.0)}
+    out = {"solve": "velocity component 1, Dirichlet set 0, tol 1e-10, FP64",
+           "rhs": "the projection step's velocity right-hand side"}
+    for name, (nu_h, nu_v, dt) in cases.items():
+        op = Operator(m, nu_h, nu_v, dt, kind="helmholtz", keep_host=True)
+        res = {}
+        for pre, label in ((0, "jacobi"), (1, "line"), (2, "ic0")):
+            op.set_param("precond", pre)
+            first = None
+            best, info = None, None
+            for rep in range(reps + 1):
+                x = torch.zeros_like(b_vel)
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                x, info = op.solve(b_vel, x, tol=1e-10, mask_bit=0, check=False)
+                torch.cuda.synchronize()
+                el = time.perf_counter() - t
+                if rep == 0:
+                    first = el
+                else:
+                    best = el if best is None else min(best, el)
+            res[label] = {"ms": round(1e3 * best, 3), "iterations": info.iterations,
+                          "status": info.status, "relres": float("%.3g" % info.relres_true),
+                          "first_solve_ms": round(1e3 * first, 1)}
+        op.close()
+        out[name] = res
+        log(f"preconditioners {name}: {res}")
+    return out
+
+
 def bench_serving(torch, log, budget_gb=16.0, mode="fp64", count=256, capacity=8, chunk=32):
     """Serving: Poisson-process arrivals (50 req/s) of pressure / velocity solve
     requests over five mesh sizes, tolerance 1e-8, continuous batching with
@@ -412,6 +453,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-isotropic", action="store_true")
     ap.add_argument("--no-loop", action="store_true")
+    ap.add_argument("--no-precond", action="store_true")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="only a 1 GiB copy and 64 pressure iterations (for counter passes)")
     ap.add_argument("--no-serving", action="store_true")
@@ -552,6 +594,10 @@ def main():
     if not args.no_isotropic:
         isotropic = bench_isotropic(torch, log, m, st.b_q.clone())
 
+    precond = None
+    if not args.no_precond:
+        precond = bench_preconditioners(torch, log, m, st.b_vel[0].clone())
+
     loop = None
     if not args.no_loop:
         loop = bench_loop(torch, log, m)
@@ -618,6 +664,7 @@ def main():
         "mixed": mixed,
         "operator_setup": setup,
         "isotropic_pressure": isotropic,
+        "velocity_preconditioners": precond,
         "time_loop": loop,
         "batched": batched,
         "serving": serving,
