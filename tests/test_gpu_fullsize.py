@@ -1,0 +1,66 @@
+"""Parity at the full 256x256x20 basin size (1,387,029 nodes), in the launch
+configuration the benchmark times: the operator against the oracle's own
+assembly, the first CG iterations against the oracle's iterates, and the
+converged pressure solve through the oracle's residual (a property that holds
+at any size)."""
+import numpy as np
+import pytest
+
+import basin
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def full():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1207_0486_amd.hns import Operator
+    wl = basin.configs.BASIN_256x256x20
+    m = wl.mesh()
+    op = Operator(m, wl.nu_h, wl.nu_v, kind="poisson")
+    K = oracle.stiffness(m, wl.nu_h, wl.nu_v)
+    w = oracle.mass(m).matvec(np.ones(m.n))
+    yield m, wl, op, K, w
+    op.close()
+
+
+def test_full_size_operator_matches_oracle(full):
+    m, wl, op, K, _ = full
+    assert op.n == 1387029 and op.nnz == 20192829 and op.format == "sdia"
+    x = np.random.default_rng(5).standard_normal(m.n)
+    got = op.apply(torch.as_tensor(x, device="cuda")).cpu().numpy()
+    want = K.matvec(x)
+    scale = np.abs(K.to_scipy()).sum(axis=1).max() * np.abs(x).max()
+    assert np.abs(got - want).max() <= 1e-13 * scale
+
+
+def test_full_size_first_iterations_match_oracle(full):
+    """Eight CG iterations of the pressure solve from x0 = 0: the GPU iterate
+    equals the oracle's to 1e-12 (rounding-order differences only)."""
+    m, wl, op, K, w = full
+    b = basin.normal_rhs(m.n, 11, zero_mean=True)
+    x, info = op.solve(torch.as_tensor(b, device="cuda"), tol=1e-300, max_iter=8, check=False)
+    assert info.iterations == 8
+    ref = oracle.pcg(K, b, singular=True, weights=w, tol=1e-300, maxit=8)
+    assert ref.iterations == 8
+    xh = x.cpu().numpy()
+    assert np.linalg.norm(xh - ref.x) <= 1e-12 * np.linalg.norm(ref.x)
+
+
+def test_full_size_pressure_solve_converges(full):
+    """The converged solve: the oracle's own residual of the GPU answer meets
+    the tolerance, and the answer has zero mass-weighted mean."""
+    m, wl, op, K, w = full
+    b = basin.normal_rhs(m.n, 12, zero_mean=True)
+    x, info = op.solve(torch.as_tensor(b, device="cuda"), tol=wl.tol)
+    assert info.status == 0 and info.relres_true <= wl.tol
+    xh = x.cpu().numpy()
+    bh = b - b.mean()
+    r = bh - K.matvec(xh)
+    r -= r.mean()
+    assert np.linalg.norm(r) <= 1.01 * wl.tol * np.linalg.norm(bh)
+    assert abs(w @ xh) <= 1e-12 * np.abs(w).sum() * np.abs(xh).max()

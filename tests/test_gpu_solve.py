@@ -286,3 +286,27 @@ def test_tolerance_below_rounding_floor_stops_early(dev):
     assert info.relres_true < 1e-14
     A = oracle.helmholtz(m, 1.0, 1e-4, 0.1)
     assert oracle.relres(A, b, x.cpu().numpy(), d) < 1e-14
+
+
+@pytest.mark.parametrize("case", ["box", "basin"])
+def test_error_against_exact_within_condition_bound(dev, case):
+    """P-exact: the FP64 GPU answer against the oracle solved to 1e-13 is within
+    kappa * tol, kappa estimated by Lanczos from the oracle's CG coefficients."""
+    from paper_1207_0486_amd.hns import Operator
+    if case == "box":
+        m = BOX.mesh()
+        d = ~m.free_mask(basin.BC_U1)
+        A = oracle.stiffness(m, BOX.nu_h, BOX.nu_v)
+        op = Operator(m, BOX.nu_h, BOX.nu_v, kind="poisson")
+    else:
+        m = basin.basin_mesh(24, 20, 6, seed=4)
+        d = (m.bc & 1) == 1
+        A = oracle.helmholtz(m, 1e3, 1e-2, 3600.0)
+        op = Operator(m, 1e3, 1e-2, 3600.0, kind="helmholtz")
+    b = basin.normal_rhs(m.n, 77, dirichlet=d)
+    x, info = op.solve(_gpu(b, dev), tol=1e-10, mask_bit=0)
+    exact = oracle.pcg(A, b, dirichlet=d, tol=1e-13, history=True)
+    kappa = oracle.lanczos_condition(exact.alphas, exact.betas)
+    err = _relerr(x.cpu().numpy(), exact.x)
+    assert info.status == 0 and kappa >= 1.0
+    assert err <= kappa * 1e-10
