@@ -7,8 +7,8 @@ Gamma_b, is the bottom plus the four lateral walls; Gamma_b splits into the
 Dirichlet part Gamma_0 and the artificial part Gamma_1 (Sec. 2 and the boundary
 conditions of the prediction step in Sec. 3).
 
-Mesh recipe (the paper meshes with hexahedra, Sec. 5; this build uses linear
-tetrahedra instead):
+Mesh recipe (the paper meshes with hexahedra, Sec. 5; the main path uses
+linear tetrahedra cut from the same cells, HexMesh below keeps the bricks):
   * nodes (i,j,k), 0<=i<=Nx, 0<=j<=Ny, 0<=k<=Nz, uniform sigma layers:
       x = i*Lx/Nx,  y = j*Ly/Ny,  z = -h(x,y)*(1 - k/Nz)
     so k = 0 is the bottom and k = Nz the surface z = 0;
@@ -217,3 +217,103 @@ def basin_mesh(Nx: int, Ny: int, Nz: int, L: float = 5.0e6, seed: int = 0,
     """
     return _build(Nx, Ny, Nz, L, L, lambda x, y: bathymetry(x, y, L, seed),
                   gamma0, gamma1)
+
+
+@dataclass
+class HexMesh:
+    """A structured terrain-following hexahedral mesh of order 1 (Q1) or 2 (Q2).
+
+    The elements are the Nx x Ny x Nz cells of the recipe above (the brick
+    elements of Sec. 5).  The nodes are the lattice of the refined grid
+    (order*Nx+1) x (order*Ny+1) x (order*Nz+1), numbered vertical-first like
+    the tetrahedral meshes, so water columns stay contiguous runs of
+    order*Nz+1 ids.  Each cell is the trilinear image of the reference cube
+    through its 8 corners; the other Q2 nodes sit at the images of the
+    reference nodes (mid-edge, mid-face and centre), so the refined lattice's
+    depth is the bilinear interpolant of the corner depths within each cell.
+
+    hexes     (n_hex, (order+1)**3) int32; local node (a, b, c), a along x,
+              b along y, c along z (each in 0..order), at column
+              a + (order+1)*b + (order+1)**2*c
+    bc        Dirichlet bits on the refined lattice (same split as the
+              tetrahedral meshes)
+    depth     ((order*Nx+1)*(order*Ny+1),) depth at the refined columns
+    """
+    Nx: int
+    Ny: int
+    Nz: int
+    order: int
+    Lx: float
+    Ly: float
+    xyz: np.ndarray
+    hexes: np.ndarray
+    bc: np.ndarray
+    depth: np.ndarray
+    gamma0: tuple = field(default=("bottom", "west", "east"))
+    gamma1: tuple = field(default=("south", "north"))
+
+    @property
+    def n(self) -> int:
+        return int(self.xyz.shape[0])
+
+    @property
+    def n_hex(self) -> int:
+        return int(self.hexes.shape[0])
+
+    @property
+    def line_len(self) -> int:
+        return self.order * self.Nz + 1
+
+
+def _build_hex(Nx, Ny, Nz, order, Lx, Ly, depth_fn, gamma0, gamma1) -> HexMesh:
+    if min(Nx, Ny, Nz) < 1:
+        raise ValueError("need at least one cell in each direction")
+    if order not in (1, 2):
+        raise ValueError("order must be 1 or 2")
+    p = order
+    Mx, My, Mz = p * Nx, p * Ny, p * Nz
+    # corner depths, then their bilinear interpolant on the refined columns
+    ci, cj = np.meshgrid(np.arange(Nx + 1), np.arange(Ny + 1), indexing="ij")
+    hc = np.asarray(depth_fn(ci.ravel() * (Lx / Nx), cj.ravel() * (Ly / Ny)),
+                    dtype=np.float64).reshape(Nx + 1, Ny + 1)
+    if np.any(hc <= 0):
+        raise ValueError("depth must be positive")
+    fi, fj = np.meshgrid(np.arange(Mx + 1), np.arange(My + 1), indexing="ij")
+    i0 = np.minimum(fi // p, Nx - 1)
+    j0 = np.minimum(fj // p, Ny - 1)
+    s = (fi - p * i0) / p
+    t = (fj - p * j0) / p
+    h = ((1 - s) * (1 - t) * hc[i0, j0] + s * (1 - t) * hc[i0 + 1, j0]
+         + (1 - s) * t * hc[i0, j0 + 1] + s * t * hc[i0 + 1, j0 + 1]).ravel()
+    i, j, k = _lattice(Mx, My, Mz)
+    x = i * (Lx / Mx)
+    y = j * (Ly / My)
+    z = -h[i * (My + 1) + j] * (1.0 - k / Mz)
+    xyz = np.stack([x, y, z], axis=1).astype(np.float64)
+    ei, ej, ek = np.meshgrid(np.arange(Nx), np.arange(Ny), np.arange(Nz), indexing="ij")
+    ei, ej, ek = ei.ravel(), ej.ravel(), ek.ravel()
+    q = p + 1
+    hexes = np.empty((ei.size, q ** 3), dtype=np.int64)
+    for c in range(q):
+        for b in range(q):
+            for a in range(q):
+                hexes[:, a + q * b + q * q * c] = node_index(p * ei + a, p * ej + b, p * ek + c,
+                                                             My, Mz)
+    return HexMesh(Nx=Nx, Ny=Ny, Nz=Nz, order=p, Lx=float(Lx), Ly=float(Ly), xyz=xyz,
+                   hexes=hexes.astype(np.int32), bc=dirichlet_bits(Mx, My, Mz, gamma0, gamma1),
+                   depth=h, gamma0=tuple(gamma0), gamma1=tuple(gamma1))
+
+
+def box_hex_mesh(Nx: int, Ny: int, Nz: int, order: int, Lx: float = 1.0, Ly: float = 1.0,
+                 H: float = 0.01, gamma0=WALLS, gamma1=()) -> HexMesh:
+    """Flat-bottomed box [0,Lx] x [0,Ly] x [-H, 0] in brick elements."""
+    return _build_hex(Nx, Ny, Nz, order, Lx, Ly,
+                      lambda x, y: np.full_like(x, H, dtype=np.float64), gamma0, gamma1)
+
+
+def basin_hex_mesh(Nx: int, Ny: int, Nz: int, order: int, L: float = 5.0e6, seed: int = 0,
+                   gamma0=("bottom", "west", "east"),
+                   gamma1=("south", "north")) -> HexMesh:
+    """Square basin over the seeded bathymetry, in brick elements of the given order."""
+    return _build_hex(Nx, Ny, Nz, order, L, L, lambda x, y: bathymetry(x, y, L, seed),
+                      gamma0, gamma1)

@@ -48,6 +48,11 @@ def lib():
         L.or_assemble.restype = C.c_int
         L.or_assemble.argtypes = [C.c_int64, dp, C.c_int64, ip, C.c_int, C.c_double,
                                   C.c_double, C.c_double, C.c_double, C.c_int, C.POINTER(vp)]
+        L.or_hex_element.restype = C.c_double
+        L.or_hex_element.argtypes = [C.c_int, dp, dp, dp, dp]
+        L.or_assemble_hex.restype = C.c_int
+        L.or_assemble_hex.argtypes = [C.c_int64, dp, C.c_int64, ip, C.c_int, C.c_double,
+                                      C.c_double, C.c_double, C.c_double, C.POINTER(vp)]
         L.or_assemble_surface_mass.restype = C.c_int
         L.or_assemble_surface_mass.argtypes = [C.c_int64, dp, C.c_int64, ip, C.POINTER(vp)]
         L.or_csr_free.argtypes = [vp]
@@ -188,6 +193,43 @@ def mass(mesh):
 def divergence(mesh, comp):
     """B_c with (B_c)_ij = int phi_i d phi_j / d x_c."""
     return _assemble(mesh.xyz, mesh.tets, 1, comp=comp)
+
+
+def hex_element(order, X8, nu=(1.0, 1.0, 1.0)):
+    """Element matrices (K_nu, M) of one brick of order 1 or 2 from its 8
+    corners (corner (c1,c2,c3) at row c1 + 2 c2 + 4 c3) and the smallest
+    Jacobian determinant at the quadrature points."""
+    X8 = _f64(X8).reshape(8, 3)
+    nloc = (order + 1) ** 3
+    K = np.empty((nloc, nloc))
+    M = np.empty((nloc, nloc))
+    det = lib().or_hex_element(order, _d(X8), _d(_f64(nu)), _d(K), _d(M))
+    return K, M, det
+
+
+def hex_operator(mesh, nu_h, nu_v, c_mass, c_stiff):
+    """c_mass * M + c_stiff * K_nu over a brick mesh (mesh.hexes, mesh.order)."""
+    xyz = _f64(mesh.xyz)
+    hexes = np.ascontiguousarray(mesh.hexes, dtype=np.int32)
+    h = C.c_void_p()
+    st = lib().or_assemble_hex(xyz.shape[0], _d(xyz), hexes.shape[0], _i(hexes), mesh.order,
+                               nu_h, nu_v, c_mass, c_stiff, C.byref(h))
+    if st != OK:
+        raise OracleError(st, "assemble_hex")
+    return Matrix(h.value)
+
+
+def hex_helmholtz(mesh, nu_h, nu_v, dt):
+    """Velocity-prediction operator M + dt*K_nu on a brick mesh."""
+    return hex_operator(mesh, nu_h, nu_v, 1.0, dt)
+
+
+def hex_stiffness(mesh, nu_h, nu_v):
+    return hex_operator(mesh, nu_h, nu_v, 0.0, 1.0)
+
+
+def hex_mass(mesh):
+    return hex_operator(mesh, 0.0, 0.0, 1.0, 0.0)
 
 
 def surface_mass(mesh):

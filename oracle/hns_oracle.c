@@ -16,6 +16,9 @@
  *     of eq. fofa_q_cor_h, and the pressure term int p div v of
  *     eq. fofa_velo_pred_h through its transpose);
  *   - assembly of those forms into compressed sparse rows;
+ *   - the same mass and anisotropic stiffness forms on the brick elements of
+ *     Sec. 5 (Q2 for the velocity, Q1 for the pressure), with a trilinear
+ *     geometry map and tensor Gauss quadrature;
  *   - the surface-tension load int_{Gamma_s} theta v ds (eq. fofa_velo_pred_h);
  *   - the explicit advection term int ((u . grad) u_c) phi ds of the same
  *     equation, evaluated at a given velocity;
@@ -1029,4 +1032,190 @@ int or_cholesky_solve(int64_t n, const double *A, const double *b, double *x)
     free(L);
     free(y);
     return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Brick elements: Q2 velocity / Q1 pressure spaces of Sec. 5               */
+/* ------------------------------------------------------------------------ */
+
+/* Value and derivative at s of the k-th Lagrange polynomial of degree p
+ * through the equispaced points t_m = -1 + 2m/p of [-1, 1]:
+ * l_k(s) = prod_{m != k} (s - t_m) / (t_k - t_m), differentiated factor by
+ * factor with the product rule. */
+static void lagrange_1d(int p, int k, double s, double *val, double *der)
+{
+    double tk = -1.0 + 2.0 * k / p;
+    double v = 1.0, d = 0.0;
+    for (int m = 0; m <= p; ++m) {
+        if (m == k) continue;
+        double tm = -1.0 + 2.0 * m / p;
+        double f = (s - tm) / (tk - tm);
+        d = d * f + v / (tk - tm);
+        v = v * f;
+    }
+    *val = v;
+    *der = d;
+}
+
+/* Gauss-Legendre rule with p + 1 points on [-1, 1]: 2 points (exact to
+ * degree 3) for p = 1, 3 points (exact to degree 5) for p = 2. */
+static void gauss_rule(int p, double *x, double *w)
+{
+    if (p == 1) {
+        x[0] = -1.0 / sqrt(3.0);
+        x[1] = 1.0 / sqrt(3.0);
+        w[0] = w[1] = 1.0;
+    } else {
+        x[0] = -sqrt(0.6);
+        x[1] = 0.0;
+        x[2] = sqrt(0.6);
+        w[0] = w[2] = 5.0 / 9.0;
+        w[1] = 8.0 / 9.0;
+    }
+}
+
+static double det3(const double A[3][3])
+{
+    return A[0][0] * (A[1][1] * A[2][2] - A[1][2] * A[2][1])
+         - A[0][1] * (A[1][0] * A[2][2] - A[1][2] * A[2][0])
+         + A[0][2] * (A[1][0] * A[2][1] - A[1][1] * A[2][0]);
+}
+
+/* Solves A g = r by Cramer's rule (det(A) given). */
+static void cramer3(const double A[3][3], double detA, const double *r, double *g)
+{
+    for (int k = 0; k < 3; ++k) {
+        double Ak[3][3];
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j)
+                Ak[i][j] = (j == k) ? r[i] : A[i][j];
+        g[k] = det3(Ak) / detA;
+    }
+}
+
+/* Element matrices of one brick of order p (1: Q1, 2: Q2), Sec. 5.
+ *   X8     the 8 corners, corner (c1, c2, c3) in {0,1}^3 at row c1 + 2 c2 + 4 c3
+ *   nu     (nu_1, nu_2, nu_3) of the anisotropic stiffness
+ *   K, M   nloc x nloc row-major, nloc = (p+1)^3, local node (a, b, c) (each
+ *          0..p, reference point (t_a, t_b, t_c)) at a + (p+1) b + (p+1)^2 c
+ * The element is the image of the reference cube [-1,1]^3 under the trilinear
+ * map through its corners; the basis functions are the products of the 1D
+ * Lagrange polynomials of degree p; the integrals use the tensor Gauss rule
+ * with p + 1 points per direction (exact for both forms on parallelepipeds).
+ *   M_ab = int phi_a phi_b,   K_ab = int sum_d nu_d (d_d phi_a)(d_d phi_b),
+ * with the physical gradient g of a basis function obtained from its
+ * reference gradient r through J^T g = r, J_rd = d x_r / d s_d.
+ * Returns the smallest Jacobian determinant over the quadrature points. */
+double or_hex_element(int p, const double *X8, const double *nu, double *K, double *M)
+{
+    const int q = p + 1, nloc = q * q * q;
+    double gx[3], gw[3];
+    gauss_rule(p, gx, gw);
+    for (int k = 0; k < nloc * nloc; ++k) {
+        K[k] = 0.0;
+        M[k] = 0.0;
+    }
+    double detmin = INFINITY;
+    double N[27], G[27][3];
+    for (int i3 = 0; i3 < q; ++i3)
+        for (int i2 = 0; i2 < q; ++i2)
+            for (int i1 = 0; i1 < q; ++i1) {
+                const double s[3] = {gx[i1], gx[i2], gx[i3]};
+                const double w = gw[i1] * gw[i2] * gw[i3];
+                double J[3][3] = {{0.0}};
+                for (int c = 0; c < 8; ++c) {
+                    int cc[3] = {c & 1, (c >> 1) & 1, (c >> 2) & 1};
+                    double lin[3], dlin[3];
+                    for (int d = 0; d < 3; ++d) {
+                        double sg = cc[d] ? 1.0 : -1.0;
+                        lin[d] = 0.5 * (1.0 + sg * s[d]);
+                        dlin[d] = 0.5 * sg;
+                    }
+                    double dG[3] = {dlin[0] * lin[1] * lin[2], lin[0] * dlin[1] * lin[2],
+                                    lin[0] * lin[1] * dlin[2]};
+                    for (int r = 0; r < 3; ++r)
+                        for (int d = 0; d < 3; ++d)
+                            J[r][d] += X8[3 * c + r] * dG[d];
+                }
+                double det = det3(J);
+                if (det < detmin) detmin = det;
+                double JT[3][3];
+                for (int r = 0; r < 3; ++r)
+                    for (int d = 0; d < 3; ++d)
+                        JT[d][r] = J[r][d];
+                for (int c = 0; c < q; ++c)
+                    for (int b = 0; b < q; ++b)
+                        for (int a = 0; a < q; ++a) {
+                            double va, da, vb, db, vc, dc;
+                            lagrange_1d(p, a, s[0], &va, &da);
+                            lagrange_1d(p, b, s[1], &vb, &db);
+                            lagrange_1d(p, c, s[2], &vc, &dc);
+                            int l = a + q * b + q * q * c;
+                            N[l] = va * vb * vc;
+                            double ref[3] = {da * vb * vc, va * db * vc, va * vb * dc};
+                            cramer3(JT, det, ref, G[l]);
+                        }
+                for (int a = 0; a < nloc; ++a)
+                    for (int b = 0; b < nloc; ++b) {
+                        M[a * nloc + b] += w * det * N[a] * N[b];
+                        double k = 0.0;
+                        for (int d = 0; d < 3; ++d)
+                            k += nu[d] * G[a][d] * G[b][d];
+                        K[a * nloc + b] += w * det * k;
+                    }
+            }
+    return detmin;
+}
+
+/* Assemble c_mass * M + c_stiff * K_nu (nu = (nu_h, nu_h, nu_v)) over a brick
+ * mesh of order p: hex holds (p+1)^3 node ids per element in the local order
+ * of or_hex_element.  An element whose Jacobian determinant is not positive
+ * at every quadrature point is a mesh error. */
+int or_assemble_hex(int64_t n, const double *xyz, int64_t nhex, const int32_t *hex, int p,
+                    double nu_h, double nu_v, double c_mass, double c_stiff, or_csr **out)
+{
+    *out = NULL;
+    if (n <= 0 || nhex < 0 || (p != 1 && p != 2)) return OR_ERR_INVALID;
+    const int q = p + 1, nloc = q * q * q;
+    if (check_conn(n, nhex, nloc, hex) != OR_OK) return OR_ERR_MESH;
+    triplets t;
+    memset(&t, 0, sizeof(t));
+    if (trip_init(&t, n, nhex, nloc, hex) != OR_OK) {
+        trip_free(&t);
+        return OR_ERR_NOMEM;
+    }
+    const double nu[3] = {nu_h, nu_h, nu_v};
+    double *K = malloc(sizeof(double) * nloc * nloc);
+    double *M = malloc(sizeof(double) * nloc * nloc);
+    if (!K || !M) {
+        free(K);
+        free(M);
+        trip_free(&t);
+        return OR_ERR_NOMEM;
+    }
+    int st = OR_OK;
+    for (int64_t e = 0; e < nhex && st == OR_OK; ++e) {
+        const int32_t *h = hex + e * nloc;
+        double X8[24];
+        for (int c = 0; c < 8; ++c) {
+            int l = (c & 1) * p + q * (((c >> 1) & 1) * p) + q * q * ((c >> 2) * p);
+            for (int d = 0; d < 3; ++d)
+                X8[3 * c + d] = xyz[(int64_t)h[l] * 3 + d];
+        }
+        if (!(or_hex_element(p, X8, nu, K, M) > 0.0)) {
+            st = OR_ERR_MESH;
+            break;
+        }
+        for (int a = 0; a < nloc; ++a)
+            for (int b = 0; b < nloc; ++b)
+                trip_add(&t, h[a], h[b], c_mass * M[a * nloc + b] + c_stiff * K[a * nloc + b]);
+    }
+    free(K);
+    free(M);
+    if (st == OR_OK) {
+        *out = trip_to_csr(&t);
+        if (!*out) st = OR_ERR_NOMEM;
+    }
+    trip_free(&t);
+    return st;
 }
