@@ -296,6 +296,66 @@ def bench_loop(torch, log, m, steps=4, stress_steps=2):
     return out
 
 
+def bench_bricks(torch, log, reps=3):
+    """The paper's own discretisation (Sec. 5) over the 256x256x20 basin's
+    bathymetry: Q2 velocity operator M + dt K_nu on 128x128x10 bricks
+    (1,387,029 nodes, the node lattice of the tetrahedral mesh), the Q1
+    pressure operator on the same bricks (the Q2/Q1 pair), and Q1 pressure on
+    256x256x20 bricks (1,387,029 nodes).  Jacobi-PCG to 1e-10 from x0 = 0;
+    the isotropic Q1 pressure also with the line blocks to 1e-8 (its rounding
+    floor is near 1e-9)."""
+    import basin
+    from paper_1207_0486_amd.hns import Operator
+    wl = basin.configs.BASIN_256x256x20
+    cases = (
+        ("q2_velocity_128x128x10", 2, (128, 128, 10), "helmholtz", (wl.nu_h, wl.nu_v), 0, 0,
+         1e-10),
+        ("q1_pressure_128x128x10", 1, (128, 128, 10), "poisson", (wl.nu_h, wl.nu_v), -1, 0,
+         1e-10),
+        ("q1_pressure_256x256x20", 1, (256, 256, 20), "poisson", (wl.nu_h, wl.nu_v), -1, 0,
+         1e-10),
+        ("q1_pressure_iso_line_128x128x10", 1, (128, 128, 10), "poisson", (1.0, 1.0), -1, 1,
+         1e-8),
+    )
+    out = {}
+    for name, order, (Nx, Ny, Nz), kind, nu, bit, precond, tol in cases:
+        m = basin.basin_hex_mesh(Nx, Ny, Nz, order, L=wl.L, seed=wl.seed)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        op = Operator(m, nu[0], nu[1], wl.dt if kind == "helmholtz" else 0.0, kind=kind)
+        torch.cuda.synchronize()
+        setup_s = time.perf_counter() - t0
+        op.set_param("precond", precond)
+        if bit >= 0:
+            d = ((m.bc >> bit) & 1) == 1
+            b = basin.normal_rhs(m.n, 31, dirichlet=d)
+        else:
+            b = basin.normal_rhs(m.n, 31, zero_mean=True)
+        b = torch.as_tensor(b, device="cuda")
+        best, info = None, None
+        for _ in range(reps):
+            x = torch.zeros_like(b)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            x, info = op.solve(b, x, tol=tol, mask_bit=bit, check=False)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t
+            best = el if best is None else min(best, el)
+        passes = 13 if precond == 0 else 14
+        by = info.iterations * (matrix_bytes(op.format, op.n, op.nnz, 8) + passes * 8 * op.n)
+        out[name] = {"order": order, "bricks": [Nx, Ny, Nz], "nodes": op.n, "nnz": op.nnz,
+                     "format": op.format, "nu": list(nu), "precond": ["jacobi", "line"][precond],
+                     "tol": tol, "setup_s": round(setup_s, 2), "iterations": info.iterations,
+                     "status": info.status, "relres": float("%.3g" % info.relres_true),
+                     "ms": round(1e3 * best, 3),
+                     "us_per_iter": round(1e6 * best / max(info.iterations, 1), 2),
+                     "GBs": round(by / best / 1e9, 1)}
+        log(f"bricks {name}: {out[name]}")
+        op.close()
+        del x, b
+    return out
+
+
 def bench_preconditioners(torch, log, m, b_vel, reps=3):
     """Velocity solve (component 1, its Dirichlet set) on the 256x256x20
     basin with point Jacobi, vertical-line blocks and IC(0) in the greedy
@@ -474,6 +534,7 @@ def main():
     ap.add_argument("--no-isotropic", action="store_true")
     ap.add_argument("--no-loop", action="store_true")
     ap.add_argument("--no-precond", action="store_true")
+    ap.add_argument("--no-bricks", action="store_true")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="only a 1 GiB copy and 64 pressure iterations (for counter passes)")
     ap.add_argument("--no-serving", action="store_true")
@@ -618,6 +679,10 @@ def main():
     if not args.no_precond:
         precond = bench_preconditioners(torch, log, m, st.b_vel[0].clone())
 
+    bricks = None
+    if not args.no_bricks:
+        bricks = bench_bricks(torch, log)
+
     loop = None
     if not args.no_loop:
         loop = bench_loop(torch, log, m)
@@ -685,6 +750,7 @@ def main():
         "operator_setup": setup,
         "isotropic_pressure": isotropic,
         "velocity_preconditioners": precond,
+        "bricks_q2_q1": bricks,
         "time_loop": loop,
         "batched": batched,
         "serving": serving,

@@ -121,6 +121,43 @@ typedef struct {
 hns_status hns_assemble(const hns_mesh *mesh, double nu_h, double nu_v, double dt,
                         uint32_t flags, hns_operator **out);
 
+/* Mesh of brick elements (the discretisation of Sec. 5: Q2 velocity, Q1
+ * pressure).  All arrays are host memory.
+ *   xyz       n_nodes x 3, row-major, float64
+ *   order     1 (Q1: 8 nodes per element) or 2 (Q2: 27 nodes per element)
+ *   hex       n_hex x (order+1)^3, int32, 0-based; local node (a, b, c), each
+ *             in 0..order and standing for the reference point
+ *             (-1 + 2a/order, -1 + 2b/order, -1 + 2c/order) of [-1,1]^3, at
+ *             column a + (order+1) b + (order+1)^2 c.  The element is the
+ *             trilinear image of the reference cube through its 8 corner
+ *             nodes (a, b, c in {0, order}); the coordinates of the other Q2
+ *             nodes are not used by the assembly.
+ *   bc        n_nodes, uint8, Dirichlet bits as in hns_mesh (may be NULL). */
+typedef struct {
+    int64_t n_nodes;
+    const double *xyz;
+    int64_t n_hex;
+    int32_t order;
+    int32_t reserved;
+    const int32_t *hex;
+    const uint8_t *bc;
+} hns_hex_mesh;
+
+/* Assemble the operator of `flags` on a brick mesh (Sec. 5): A = K_nu
+ * (HNS_POISSON) or M + dt*K_nu (HNS_HELMHOLTZ) for the Q1 or Q2 space of
+ * `mesh->order`, integrated with the tensor Gauss rule of order+1 points per
+ * direction.  The operator is used like one from hns_assemble (hns_solve,
+ * batched sessions, IC(0), mixed precision); the line preconditioner
+ * (set_param "precond" = 1) is offered for order 1 on a column-contiguous
+ * numbering.  Accepted options: HNS_KEEP_FP32, HNS_KEEP_HOST and a storage
+ * format; HNS_GPU_ASSEMBLY and HNS_STEP_AUX are HNS_ERR_INVALID here.
+ * Errors: HNS_ERR_INVALID (null/negative sizes, order not 1 or 2, non-finite
+ * coefficients, unsupported flags), HNS_ERR_MESH (node index out of range,
+ * non-finite coordinate, Jacobian determinant <= 0 at a quadrature point),
+ * HNS_ERR_OOM, HNS_ERR_HIP. */
+hns_status hns_assemble_hex(const hns_hex_mesh *mesh, double nu_h, double nu_v, double dt,
+                            uint32_t flags, hns_operator **out);
+
 /* Solve A x = b by Jacobi-preconditioned conjugate gradients (Remark 1 after
  * Sec. 5; the diagonal preconditioner is the DIAG part of Remark 2).
  *   mask_bit  Dirichlet set: nodes with bit mask_bit of mesh.bc are fixed to 0

@@ -37,6 +37,12 @@ class hns_mesh(C.Structure):
                 ("n_surf_tris", C.c_int64), ("surf_tris", C.POINTER(C.c_int32))]
 
 
+class hns_hex_mesh(C.Structure):
+    _fields_ = [("n_nodes", C.c_int64), ("xyz", C.POINTER(C.c_double)),
+                ("n_hex", C.c_int64), ("order", C.c_int32), ("reserved", C.c_int32),
+                ("hex", C.POINTER(C.c_int32)), ("bc", C.POINTER(C.c_uint8))]
+
+
 class hns_solve_info(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("outer_iterations", C.c_int32),
                 ("relres_true", C.c_double), ("removed_mean", C.c_double),
@@ -47,6 +53,8 @@ class hns_solve_info(C.Structure):
 _SIGNATURES = {
     "hns_assemble": (C.c_int, [C.POINTER(hns_mesh), C.c_double, C.c_double, C.c_double,
                                C.c_uint32, C.POINTER(C.c_void_p)]),
+    "hns_assemble_hex": (C.c_int, [C.POINTER(hns_hex_mesh), C.c_double, C.c_double,
+                                   C.c_double, C.c_uint32, C.POINTER(C.c_void_p)]),
     "hns_solve": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_double, C.c_int,
                             C.c_uint32, C.c_void_p, C.POINTER(hns_solve_info)]),
     "hns_solve_batched": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int), C.c_void_p,

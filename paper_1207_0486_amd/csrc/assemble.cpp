@@ -498,6 +498,230 @@ hns_status upload_matrix(const HostCSR &h, uint32_t fmt, bool keep32, DevMatrix 
     return HNS_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Brick elements (Sec. 5): Q2 velocity and Q1 pressure spaces
+// ---------------------------------------------------------------------------
+namespace {
+
+// Reference tables at the tensor Gauss points (p + 1 per direction, exact
+// for the mass and stiffness forms on parallelepipeds), reference cube
+// [-1, 1]^3, local node (a, b, c) at a + (p+1) b + (p+1)^2 c.
+struct BrickTables {
+    int p = 0, q = 0, nloc = 0, nq = 0;
+    std::vector<double> w;    // nq weights
+    std::vector<double> N;    // nq x nloc basis values
+    std::vector<double> dN;   // nq x nloc x 3 reference gradients
+    std::vector<double> dC;   // nq x 8 x 3 reference gradients of the corner (trilinear) functions
+};
+
+// 1D Lagrange basis of degree p on the equispaced nodes of [-1, 1]
+void basis_1d(int p, double s, double *v, double *d)
+{
+    if (p == 1) {
+        v[0] = 0.5 * (1.0 - s);
+        v[1] = 0.5 * (1.0 + s);
+        d[0] = -0.5;
+        d[1] = 0.5;
+    } else {
+        v[0] = 0.5 * s * (s - 1.0);
+        v[1] = (1.0 - s) * (1.0 + s);
+        v[2] = 0.5 * s * (s + 1.0);
+        d[0] = s - 0.5;
+        d[1] = -2.0 * s;
+        d[2] = s + 0.5;
+    }
+}
+
+BrickTables brick_tables(int p)
+{
+    BrickTables T;
+    T.p = p;
+    T.q = p + 1;
+    T.nloc = T.q * T.q * T.q;
+    T.nq = T.nloc;
+    double gp[3], gw[3];
+    if (p == 1) {
+        const double g = std::sqrt(1.0 / 3.0);
+        gp[0] = -g; gp[1] = g;
+        gw[0] = gw[1] = 1.0;
+    } else {
+        const double g = std::sqrt(3.0 / 5.0);
+        gp[0] = -g; gp[1] = 0.0; gp[2] = g;
+        gw[0] = gw[2] = 5.0 / 9.0;
+        gw[1] = 8.0 / 9.0;
+    }
+    T.w.resize(T.nq);
+    T.N.resize((size_t)T.nq * T.nloc);
+    T.dN.resize((size_t)T.nq * T.nloc * 3);
+    T.dC.resize((size_t)T.nq * 24);
+    const int q = T.q;
+    for (int k = 0; k < q; ++k)
+        for (int j = 0; j < q; ++j)
+            for (int i = 0; i < q; ++i) {
+                const int g = i + q * j + q * q * k;
+                const double s[3] = {gp[i], gp[j], gp[k]};
+                T.w[g] = gw[i] * gw[j] * gw[k];
+                double v[3][3], d[3][3], lv[3][2], ld[3][2];
+                for (int r = 0; r < 3; ++r) {
+                    basis_1d(p, s[r], v[r], d[r]);
+                    basis_1d(1, s[r], lv[r], ld[r]);
+                }
+                for (int c = 0; c < q; ++c)
+                    for (int b = 0; b < q; ++b)
+                        for (int a = 0; a < q; ++a) {
+                            const int l = a + q * b + q * q * c;
+                            T.N[(size_t)g * T.nloc + l] = v[0][a] * v[1][b] * v[2][c];
+                            double *g3 = &T.dN[((size_t)g * T.nloc + l) * 3];
+                            g3[0] = d[0][a] * v[1][b] * v[2][c];
+                            g3[1] = v[0][a] * d[1][b] * v[2][c];
+                            g3[2] = v[0][a] * v[1][b] * d[2][c];
+                        }
+                for (int c = 0; c < 8; ++c) {
+                    const int a = c & 1, b = (c >> 1) & 1, e = c >> 2;
+                    double *g3 = &T.dC[((size_t)g * 8 + c) * 3];
+                    g3[0] = ld[0][a] * lv[1][b] * lv[2][e];
+                    g3[1] = lv[0][a] * ld[1][b] * lv[2][e];
+                    g3[2] = lv[0][a] * lv[1][b] * ld[2][e];
+                }
+            }
+    return T;
+}
+
+// Element matrix c_mass M + c_stiff K_nu of one brick (nloc x nloc, row-major,
+// exactly symmetric: the upper triangle is computed and mirrored) and the
+// integrals of its basis functions.  Returns false if the Jacobian
+// determinant is not positive at a quadrature point.
+bool brick_matrix(const BrickTables &T, const double *xyz, const int32_t *h, double c_mass,
+                  double c_stiff, const double nu[3], double *E, double *ints,
+                  std::vector<double> &G)
+{
+    const int nloc = T.nloc, p = T.p, q = T.q;
+    double X[8][3];
+    for (int c = 0; c < 8; ++c) {
+        const int l = (c & 1) * p + q * (((c >> 1) & 1) * p) + q * q * ((c >> 2) * p);
+        for (int r = 0; r < 3; ++r) X[c][r] = xyz[3 * (int64_t)h[l] + r];
+    }
+    std::fill(E, E + (size_t)nloc * nloc, 0.0);
+    std::fill(ints, ints + nloc, 0.0);
+    G.resize((size_t)nloc * 3);
+    for (int g = 0; g < T.nq; ++g) {
+        // J[r][d] = d x_r / d s_d
+        double J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+        const double *dc = &T.dC[(size_t)g * 24];
+        for (int c = 0; c < 8; ++c)
+            for (int r = 0; r < 3; ++r)
+                for (int d = 0; d < 3; ++d) J[r][d] += X[c][r] * dc[3 * c + d];
+        // adjugate: inv(J) = adj(J) / det
+        double A[3][3];
+        A[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+        A[0][1] = J[0][2] * J[2][1] - J[0][1] * J[2][2];
+        A[0][2] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+        A[1][0] = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+        A[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+        A[1][2] = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+        A[2][0] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+        A[2][1] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
+        A[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+        const double det = J[0][0] * A[0][0] + J[0][1] * A[1][0] + J[0][2] * A[2][0];
+        if (!(det > 0.0) || !std::isfinite(det)) return false;
+        const double inv = 1.0 / det;
+        // physical gradient: grad phi_d = sum_s (d phi / d s_s) inv(J)[s][d]
+        const double *dn = &T.dN[(size_t)g * nloc * 3];
+        for (int a = 0; a < nloc; ++a)
+            for (int d = 0; d < 3; ++d)
+                G[3 * a + d] = (dn[3 * a] * A[0][d] + dn[3 * a + 1] * A[1][d] +
+                                dn[3 * a + 2] * A[2][d]) * inv;
+        const double wd = T.w[g] * det;
+        const double *n = &T.N[(size_t)g * nloc];
+        for (int a = 0; a < nloc; ++a) {
+            ints[a] += wd * n[a];
+            for (int b = a; b < nloc; ++b) {
+                const double k = nu[0] * (G[3 * a] * G[3 * b]) +
+                                 nu[1] * (G[3 * a + 1] * G[3 * b + 1]) +
+                                 nu[2] * (G[3 * a + 2] * G[3 * b + 2]);
+                E[(size_t)a * nloc + b] += wd * (c_mass * (n[a] * n[b]) + c_stiff * k);
+            }
+        }
+    }
+    for (int a = 0; a < nloc; ++a)
+        for (int b = 0; b < a; ++b) E[(size_t)a * nloc + b] = E[(size_t)b * nloc + a];
+    return true;
+}
+
+}  // namespace
+
+hns_status assemble_hex_host(const hns_hex_mesh *mesh, double c_mass, double c_stiff,
+                             double nu_h, double nu_v, HostCSR &A, std::vector<double> *lumped)
+{
+    if (!mesh || mesh->n_nodes <= 0 || mesh->n_hex < 0 || !mesh->xyz ||
+        (mesh->n_hex > 0 && !mesh->hex)) {
+        set_error("hex mesh: null arrays or non-positive sizes");
+        return HNS_ERR_INVALID;
+    }
+    if (mesh->order != 1 && mesh->order != 2) {
+        set_error("hex mesh: order must be 1 (Q1) or 2 (Q2), got %d", mesh->order);
+        return HNS_ERR_INVALID;
+    }
+    if (mesh->n_nodes >= (int64_t)INT32_MAX) {
+        set_error("hex mesh: %lld nodes exceed the int32 index range", (long long)mesh->n_nodes);
+        return HNS_ERR_INVALID;
+    }
+    const int q = mesh->order + 1, nloc = q * q * q;
+    const int64_t n = mesh->n_nodes, ne = mesh->n_hex;
+    for (int64_t e = 0; e < ne * nloc; ++e)
+        if (mesh->hex[e] < 0 || mesh->hex[e] >= n) {
+            set_error("hex mesh: element %lld references node %d outside [0,%lld)",
+                      (long long)(e / nloc), mesh->hex[e], (long long)n);
+            return HNS_ERR_MESH;
+        }
+    for (int64_t i = 0; i < 3 * n; ++i)
+        if (!std::isfinite(mesh->xyz[i])) {
+            set_error("hex mesh: non-finite coordinate at node %lld", (long long)(i / 3));
+            return HNS_ERR_MESH;
+        }
+    Incidence inc = build_incidence(n, ne, nloc, mesh->hex);
+    build_pattern(n, nloc, mesh->hex, inc, A);
+    if ((int64_t)A.col.size() >= (int64_t)INT32_MAX) {
+        set_error("operator has %zu nonzeros, beyond the int32 range", A.col.size());
+        return HNS_ERR_INVALID;
+    }
+    const BrickTables T = brick_tables(mesh->order);
+    const double nu[3] = {nu_h, nu_h, nu_v};
+    if (lumped) lumped->assign(n, 0.0);
+    std::atomic<int64_t> bad{-1};
+    // Each thread owns a range of rows and visits, in ascending order, every
+    // element touching them (elements on a range boundary are computed by
+    // both threads): a row sums its elements in ascending order whatever the
+    // thread count, so the values are deterministic and, the element
+    // matrices being exactly symmetric, bitwise symmetric.
+    parallel_for(n, [&](int64_t lo, int64_t hi) {
+        std::vector<int32_t> els(inc.tet.begin() + inc.ptr[lo], inc.tet.begin() + inc.ptr[hi]);
+        std::sort(els.begin(), els.end());
+        els.erase(std::unique(els.begin(), els.end()), els.end());
+        std::vector<double> E((size_t)nloc * nloc), ints(nloc), G;
+        for (int32_t e : els) {
+            const int32_t *h = mesh->hex + (int64_t)e * nloc;
+            if (!brick_matrix(T, mesh->xyz, h, c_mass, c_stiff, nu, E.data(), ints.data(), G)) {
+                bad.store(e);
+                return;
+            }
+            for (int a = 0; a < nloc; ++a) {
+                const int64_t i = h[a];
+                if (i < lo || i >= hi) continue;
+                for (int b = 0; b < nloc; ++b)
+                    A.val[find_col(A, i, h[b])] += E[(size_t)a * nloc + b];
+                if (lumped) (*lumped)[i] += ints[a];
+            }
+        }
+    });
+    if (bad.load() >= 0) {
+        set_error("hex mesh: element %lld has a non-positive Jacobian determinant",
+                  (long long)bad.load());
+        return HNS_ERR_MESH;
+    }
+    return HNS_OK;
+}
+
 void tet_incidence(int64_t n, int64_t ntet, const int32_t *tets, std::vector<int64_t> &ptr,
                    std::vector<int32_t> &tet, std::vector<int8_t> &loc)
 {

@@ -218,6 +218,10 @@ hns_status upload_matrix(const HostCSR &h, uint32_t fmt, bool keep32, DevMatrix 
 // same pattern, transposed values (the pattern must be structurally symmetric)
 void transpose_values(const HostCSR &A, HostCSR &At);
 uint32_t choose_format(const HostCSR &h);
+// brick elements of order 1 or 2: c_mass M + c_stiff K_nu and the integrals
+// of the basis functions (lumped)
+hns_status assemble_hex_host(const hns_hex_mesh *mesh, double c_mass, double c_stiff,
+                             double nu_h, double nu_v, HostCSR &A, std::vector<double> *lumped);
 // node -> incident tetrahedra in ascending tetrahedron order (CSR), with the
 // node's local vertex number in each
 void tet_incidence(int64_t n, int64_t ntet, const int32_t *tets, std::vector<int64_t> &ptr,

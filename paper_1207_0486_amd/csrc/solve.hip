@@ -781,6 +781,70 @@ hns_status hns_assemble(const hns_mesh *mesh, double nu_h, double nu_v, double d
     return HNS_OK;
 }
 
+hns_status hns_assemble_hex(const hns_hex_mesh *mesh, double nu_h, double nu_v, double dt,
+                            uint32_t flags, hns_operator **out)
+{
+    if (!out) {
+        set_error("out is null");
+        return HNS_ERR_INVALID;
+    }
+    *out = nullptr;
+    const uint32_t kind = flags & (HNS_POISSON | HNS_HELMHOLTZ);
+    if (kind != HNS_POISSON && kind != HNS_HELMHOLTZ) {
+        set_error("flags must select exactly one of HNS_POISSON / HNS_HELMHOLTZ");
+        return HNS_ERR_INVALID;
+    }
+    if (flags & (HNS_GPU_ASSEMBLY | HNS_STEP_AUX)) {
+        set_error("HNS_GPU_ASSEMBLY and HNS_STEP_AUX are not available for brick elements");
+        return HNS_ERR_INVALID;
+    }
+    if (!std::isfinite(nu_h) || !std::isfinite(nu_v) || !std::isfinite(dt) || nu_h < 0 ||
+        nu_v < 0) {
+        set_error("viscosities must be finite and non-negative, dt finite");
+        return HNS_ERR_INVALID;
+    }
+    const uint32_t fmt = flags & (HNS_FMT_CSR | HNS_FMT_SELL | HNS_FMT_SDIA);
+    if (fmt != 0 && fmt != HNS_FMT_CSR && fmt != HNS_FMT_SELL && fmt != HNS_FMT_SDIA) {
+        set_error("choose one storage format");
+        return HNS_ERR_INVALID;
+    }
+    hns_operator *op = new hns_operator();
+    (void)hipGetDevice(&op->device);
+    op->flags = flags;
+    op->kind = kind;
+    op->nu_h = nu_h;
+    op->nu_v = nu_v;
+    op->dt = dt;
+    HostCSR A;
+    std::vector<double> lumped;
+    const double c_mass = (kind == HNS_HELMHOLTZ) ? 1.0 : 0.0;
+    const double c_stiff = (kind == HNS_HELMHOLTZ) ? dt : 1.0;
+    hns_status st = assemble_hex_host(mesh, c_mass, c_stiff, nu_h, nu_v, A, &lumped);
+    if (st == HNS_OK) {
+        op->n = A.n;
+        st = finish_operator(op, A, fmt, lumped, mesh->bc);
+    }
+    if (st == HNS_OK) {
+        // Q1 column blocks are tridiagonal (vertical neighbours only); the Q2
+        // ones reach two levels, so the tridiagonal line factor does not apply
+        hns_mesh nodes = {};
+        nodes.n_nodes = mesh->n_nodes;
+        nodes.xyz = mesh->xyz;
+        const int L = mesh->order == 1 ? detect_columns(&nodes) : 0;
+        if (L >= 2) keep_column_blocks(op, A, L, mesh->bc);
+        if (flags & HNS_KEEP_HOST) {
+            op->host_A = A;
+            if (mesh->bc && op->bc_host.empty()) op->bc_host.assign(mesh->bc, mesh->bc + A.n);
+        }
+    }
+    if (st != HNS_OK) {
+        hns_operator_destroy(op);
+        return st;
+    }
+    *out = op;
+    return HNS_OK;
+}
+
 void hns_operator_destroy(hns_operator *op)
 {
     if (!op) return;

@@ -76,7 +76,9 @@ class Operator:
     kind="helmholtz": A = M + dt K_nu (velocity prediction);
     kind="poisson":   A = K_nu        (pressure increment).
     `mesh` is any object with xyz (n,3) float64, tets (T,4) int32, bc (n,)
-    uint8 (optional) and surf_tris (S,3) int32 (optional).
+    uint8 (optional) and surf_tris (S,3) int32 (optional); or a brick mesh
+    with xyz, hexes (E,(order+1)**3) int32, order (1: Q1, 2: Q2) and bc
+    (hns_assemble_hex).
     """
 
     def __init__(self, mesh, nu_h: float, nu_v: float, dt: float = 0.0, kind: str = "helmholtz",
@@ -95,19 +97,32 @@ class Operator:
         if keep_host:
             flags |= L.HNS_KEEP_HOST
         xyz = np.ascontiguousarray(mesh.xyz, dtype=np.float64)
-        tets = np.ascontiguousarray(mesh.tets, dtype=np.int32)
         bc = getattr(mesh, "bc", None)
         bc = None if bc is None else np.ascontiguousarray(bc, dtype=np.uint8)
-        tris = getattr(mesh, "surf_tris", None)
-        tris = None if tris is None else np.ascontiguousarray(tris, dtype=np.int32)
-        m = L.hns_mesh()
-        m.n_nodes = xyz.shape[0]
-        m.xyz = xyz.ctypes.data_as(C.POINTER(C.c_double))
-        m.n_tets = tets.shape[0]
-        m.tets = tets.ctypes.data_as(C.POINTER(C.c_int32))
-        m.bc = None if bc is None else bc.ctypes.data_as(C.POINTER(C.c_uint8))
-        m.n_surf_tris = 0 if tris is None else tris.shape[0]
-        m.surf_tris = None if tris is None else tris.ctypes.data_as(C.POINTER(C.c_int32))
+        hexes = getattr(mesh, "hexes", None)
+        if hexes is not None:
+            hexes = np.ascontiguousarray(hexes, dtype=np.int32)
+            m = L.hns_hex_mesh()
+            m.n_nodes = xyz.shape[0]
+            m.xyz = xyz.ctypes.data_as(C.POINTER(C.c_double))
+            m.n_hex = hexes.shape[0]
+            m.order = int(mesh.order)
+            m.hex = hexes.ctypes.data_as(C.POINTER(C.c_int32))
+            m.bc = None if bc is None else bc.ctypes.data_as(C.POINTER(C.c_uint8))
+            assemble = L.lib().hns_assemble_hex
+        else:
+            tets = np.ascontiguousarray(mesh.tets, dtype=np.int32)
+            tris = getattr(mesh, "surf_tris", None)
+            tris = None if tris is None else np.ascontiguousarray(tris, dtype=np.int32)
+            m = L.hns_mesh()
+            m.n_nodes = xyz.shape[0]
+            m.xyz = xyz.ctypes.data_as(C.POINTER(C.c_double))
+            m.n_tets = tets.shape[0]
+            m.tets = tets.ctypes.data_as(C.POINTER(C.c_int32))
+            m.bc = None if bc is None else bc.ctypes.data_as(C.POINTER(C.c_uint8))
+            m.n_surf_tris = 0 if tris is None else tris.shape[0]
+            m.surf_tris = None if tris is None else tris.ctypes.data_as(C.POINTER(C.c_int32))
+            assemble = L.lib().hns_assemble
         if device is None:
             idx = torch.cuda.current_device()
         elif isinstance(device, torch.device):
@@ -117,9 +132,9 @@ class Operator:
         self.device = torch.device("cuda", idx)
         h = C.c_void_p()
         with torch.cuda.device(self.device):
-            st = L.lib().hns_assemble(C.byref(m), nu_h, nu_v, dt, flags, C.byref(h))
+            st = assemble(C.byref(m), nu_h, nu_v, dt, flags, C.byref(h))
         if st != L.HNS_OK:
-            raise HNSError(st, "hns_assemble")
+            raise HNSError(st, "hns_assemble_hex" if hexes is not None else "hns_assemble")
         self._h = h
         self.n = int(L.lib().hns_operator_n(h))
         self.nnz = int(L.lib().hns_operator_nnz(h))
