@@ -46,10 +46,10 @@ def matrix_bytes(fmt, n, nnz, value_bytes):
 
 
 def bytes_iter(fmt, n, nnz, vb):
-    """One CG iteration: one operator read plus 13 vector passes (SpMV reads p
-    and writes q; the update reads x, p, r, q, D^-1 and writes x, r; the
-    direction update reads r, D^-1, p and writes p)."""
-    return matrix_bytes(fmt, n, nnz, vb) + 13 * vb * n
+    """One point-Jacobi CG iteration: one operator read plus 12 vector passes
+    (SpMV reads p and writes q; the update reads r, q, D^-1 and writes r; the
+    direction update reads x, p, r, D^-1 and writes x, p)."""
+    return matrix_bytes(fmt, n, nnz, vb) + 12 * vb * n
 
 
 def bytes_spmv(fmt, n, nnz, vb):
@@ -341,15 +341,21 @@ def bench_bricks(torch, log, reps=3):
             torch.cuda.synchronize()
             el = time.perf_counter() - t
             best = el if best is None else min(best, el)
-        passes = 13 if precond == 0 else 14
+        passes = 12 if precond == 0 else 14
         by = info.iterations * (matrix_bytes(op.format, op.n, op.nnz, 8) + passes * 8 * op.n)
+        # diagonal storage also reads the zeros it stores where a row lacks an offset
+        stored = ((op.ndiag + 1) * op.n * 8 if op.format == "sdia"
+                  else matrix_bytes(op.format, op.n, op.nnz, 8))
+        by_stored = info.iterations * (stored + passes * 8 * op.n)
         out[name] = {"order": order, "bricks": [Nx, Ny, Nz], "nodes": op.n, "nnz": op.nnz,
-                     "format": op.format, "nu": list(nu), "precond": ["jacobi", "line"][precond],
+                     "format": op.format, "ndiag": op.ndiag, "nu": list(nu),
+                     "precond": ["jacobi", "line"][precond],
                      "tol": tol, "setup_s": round(setup_s, 2), "iterations": info.iterations,
                      "status": info.status, "relres": float("%.3g" % info.relres_true),
                      "ms": round(1e3 * best, 3),
                      "us_per_iter": round(1e6 * best / max(info.iterations, 1), 2),
-                     "GBs": round(by / best / 1e9, 1)}
+                     "GBs": round(by / best / 1e9, 1),
+                     "GBs_stored": round(by_stored / best / 1e9, 1)}
         log(f"bricks {name}: {out[name]}")
         op.close()
         del x, b
@@ -737,7 +743,7 @@ def main():
                    "tol": wl.tol, "nu_h": wl.nu_h, "nu_v": wl.nu_v,
                    "dt": wl.dt},
         "value_basis": "algorithmic bytes of the solves in the storage format used (operator "
-                       "read + 13 vector passes per CG iteration) / step time",
+                       "read + 12 vector passes per CG iteration) / step time",
         "csr_equivalent_GBs": round(csr_equiv / (ms64 * 1e-3) / 1e9, 1),
         "fp64": {k: {"iters": i.iterations, "relres": i.relres_true} for k, i in infos64.items()},
         "step_ms": [round(1e3 * v, 3) for v in per64],

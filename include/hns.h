@@ -91,12 +91,14 @@ typedef struct {
 #define HNS_FMT_CSR   0x100u /* compressed sparse rows, 16 lanes per row            */
 #define HNS_FMT_SELL  0x200u /* sliced ELLPACK, slice height 64 (one wavefront),
                                 column-major inside a slice                          */
-#define HNS_FMT_SDIA  0x400u /* symmetric diagonal storage: main + at most 16 upper
-                                diagonals, no column indices, lower triangle read by
+#define HNS_FMT_SDIA  0x400u /* symmetric diagonal storage: main + at most 64 upper
+                                diagonals (zeros stored where a row lacks an
+                                offset), no column indices, lower triangle read by
                                 symmetry; needs a bitwise-symmetric matrix whose
                                 pattern has few distinct offsets j - i (structured
-                                meshes).  HNS_FMT_AUTO picks it when it applies, else
-                                SELL when row lengths are even, else CSR            */
+                                meshes).  HNS_FMT_AUTO picks it for up to 16 offsets,
+                                and for up to 64 when it stores fewer bytes than
+                                CSR; else SELL when row lengths are even, else CSR  */
 
 /* Solve modes */
 #define HNS_FP64  0u         /* everything in FP64                                   */

@@ -348,7 +348,7 @@ void DevMatrix::release()
 }
 
 // Offsets j - i of the upper triangle when the matrix is bitwise symmetric
-// and uses at most kMaxDiag distinct upper offsets; empty otherwise.
+// and uses at most kMaxDiagWide distinct upper offsets; empty otherwise.
 static std::vector<int32_t> symmetric_offsets(const HostCSR &h)
 {
     std::vector<char> seen;
@@ -359,7 +359,7 @@ static std::vector<int32_t> symmetric_offsets(const HostCSR &h)
             if (d <= 0) continue;
             if (std::find(offs.begin(), offs.end(), (int32_t)d) == offs.end()) {
                 offs.push_back((int32_t)d);
-                if ((int)offs.size() > kMaxDiag) return {};
+                if ((int)offs.size() > kMaxDiagWide) return {};
             }
         }
     // bitwise symmetry of values and pattern
@@ -376,7 +376,14 @@ static std::vector<int32_t> symmetric_offsets(const HostCSR &h)
 
 uint32_t choose_format(const HostCSR &h)
 {
-    if (!symmetric_offsets(h).empty()) return HNS_FMT_SDIA;
+    // Diagonal storage reads (ndiag + 1) n values and no indices, zeros
+    // included; beyond the unrolled kernels' limit it is taken only when that
+    // is fewer bytes than the values and column indices of CSR.
+    const std::vector<int32_t> offs = symmetric_offsets(h);
+    if (!offs.empty()) {
+        if ((int)offs.size() <= kMaxDiag) return HNS_FMT_SDIA;
+        if ((double)(offs.size() + 1) * h.n * 8.0 < 12.0 * (double)h.nnz()) return HNS_FMT_SDIA;
+    }
     // Sliced ELL pays when rows inside a 64-row slice have similar lengths
     // (padding stays small); the structured basin meshes give < 5 % padding.
     int64_t n = h.n, padded = 0;
@@ -414,7 +421,7 @@ hns_status upload_matrix(const HostCSR &h, uint32_t fmt, bool keep32, DevMatrix 
         if (offs.empty()) {
             set_error("symmetric-diagonal storage needs a bitwise-symmetric matrix with at most "
                       "%d upper diagonal offsets",
-                      kMaxDiag);
+                      kMaxDiagWide);
             return HNS_ERR_INVALID;
         }
         const int64_t n = h.n;

@@ -139,6 +139,10 @@ struct BOffsets {
     int32_t o[kMaxDiag];
 };
 
+struct BWideOffsets {
+    int32_t o[kMaxDiagWide];
+};
+
 // ---------------------------------------------------------------------------
 // SpMM: Q = mask_j(A P), optional per-column partials of p_j^T q_j
 // ---------------------------------------------------------------------------
@@ -176,6 +180,59 @@ __global__ __launch_bounds__(kBlock) void k_bspmm_sdia(int64_t n, int K, BOffset
 #pragma unroll
         for (int v = 0; v < V; ++v) s[v] = d * pi.v[v];
 #pragma unroll
+        for (int k = 0; k < M; ++k) {
+            const int64_t o = offs.o[k];
+            const TV *u = dia + (int64_t)(k + 1) * n;
+            const bool hu = i + o < n, hl = i >= o;
+            const int64_t iu = hu ? i + o : i, il = hl ? i - o : i;
+            const TX cu = hu ? (TX)u[i] : (TX)0;
+            const TX cl = hl ? (TX)u[il] : (TX)0;
+            const auto pu = bld<V>(P, iu * K + (e - i * K));
+            const auto pl = bld<V>(P, il * K + (e - i * K));
+#pragma unroll
+            for (int v = 0; v < V; ++v) s[v] += cu * pu.v[v] + cl * pl.v[v];
+        }
+        BPack<TX, V> out;
+        const int j0 = (int)(e - i * K);
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            out.v[v] = masked(bc, cols[j0 + v].bit, i) ? (TX)0 : s[v];
+            if constexpr (DOT) acc[0][v] += (double)pi.v[v] * (double)out.v[v];
+        }
+        bst<V>(Q, e, out);
+    }
+    if constexpr (DOT) block_column_partials<1, V>(acc, K, part);
+}
+
+// The same product for the wide symmetric-diagonal format: the offsets are a
+// run-time count (up to kMaxDiagWide), visited in ascending order as above.
+template <typename TV, typename TX, int V, bool DOT>
+__global__ __launch_bounds__(kBlock) void k_bspmm_sdia_wide(int64_t n, int K, int M,
+                                                            BWideOffsets offs,
+                                                            const TV *__restrict__ dia,
+                                                            const TX *__restrict__ P,
+                                                            TX *__restrict__ Q,
+                                                            const uint8_t *__restrict__ bc,
+                                                            const BCol *__restrict__ cols,
+                                                            double *__restrict__ part)
+{
+    if constexpr (DOT) {
+        if (!any_column(cols, K, 0)) return;
+    }
+    double acc[1][V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) acc[0][v] = 0.0;
+    const int64_t np = n * K / V;
+    PACK_LOOP(t, np)
+    {
+        const int64_t e = t * V;
+        const int64_t i = e / K;
+        const auto pi = bld<V>(P, e);
+        const TX d = (TX)dia[i];
+        TX s[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) s[v] = d * pi.v[v];
+#pragma unroll 4
         for (int k = 0; k < M; ++k) {
             const int64_t o = offs.o[k];
             const TV *u = dia + (int64_t)(k + 1) * n;
@@ -880,7 +937,12 @@ template <typename TV, typename TX, int V, bool DOT>
 void bspmm_launch(Launcher &L, const DevMatrix &A, int K, const TV *vals, const void *P, void *Q,
                   const uint8_t *bc, const BCol *cols, double *part, int G)
 {
-    if (A.fmt == HNS_FMT_SDIA) {
+    if (A.fmt == HNS_FMT_SDIA && A.ndiag > kMaxDiag) {
+        BWideOffsets o;
+        for (int k = 0; k < kMaxDiagWide; ++k) o.o[k] = k < A.ndiag ? A.off[k] : 0;
+        L(k_bspmm_sdia_wide<TV, TX, V, DOT>, G, kBlock, A.n, K, A.ndiag, o, vals, (const TX *)P,
+          (TX *)Q, bc, cols, part);
+    } else if (A.fmt == HNS_FMT_SDIA) {
         BOffsets o;
         for (int k = 0; k < kMaxDiag; ++k) o.o[k] = k < A.ndiag ? A.off[k] : 0;
 #define HNS_SDIA_CASE(M)                                                              \

@@ -35,7 +35,8 @@ constexpr int kBlock = 256;      // threads per workgroup (4 wavefronts)
 constexpr int kSlice = 64;       // sliced-ELL slice height = one wavefront
 constexpr int kMaxGrid = 2048;   // workgroups of the reducing kernels (multiple of 8 XCDs)
 constexpr int kMaxPart = 4096;   // workgroups of the single-vector CG kernels (partials slots)
-constexpr int kMaxDiag = 16;     // upper diagonals of the symmetric-diagonal format
+constexpr int kMaxDiag = 16;     // upper diagonals of the unrolled symmetric-diagonal kernels
+constexpr int kMaxDiagWide = 64; // upper diagonals of the grouped (wide) kernels
 
 // ---------------------------------------------------------------------------
 // Host-side compressed sparse rows (assembly output)
@@ -68,12 +69,13 @@ struct DevMatrix {
     int32_t *scol = nullptr;
     double *sval = nullptr;
     float *sval32 = nullptr;
-    // symmetric diagonal storage: the main diagonal and `ndiag` upper
+    // symmetric diagonal storage (ndiag <= kMaxDiag: unrolled kernels; up to
+    // kMaxDiagWide: offsets streamed in groups of 8): the main diagonal and `ndiag` upper
     // diagonals at offsets off[0] < ... < off[ndiag-1]; array k (k = 0 main,
     // k >= 1 upper) holds entry (i, i + off[k-1]) at dia[k * n + i] (zero
     // where the entry is absent); the lower triangle is read by symmetry
     int ndiag = 0;
-    int32_t off[kMaxDiag] = {0};
+    int32_t off[kMaxDiagWide] = {0};
     double *dia = nullptr;
     float *dia32 = nullptr;
     // launch shape of the single-vector CG kernels: workgroup-sized row

@@ -26,6 +26,7 @@ struct Scalars {
     int32_t stop;    // 0 running, 1 recursive residual below tolerance, 2 breakdown, 3 b = 0
     int32_t iter;    // CG iterations executed
     uint32_t counter[4];
+    uint32_t xtoken; // tag of the last iteration whose update ran (x += alpha p pending)
 };
 
 // Layout of the per-workspace partial-sum buffer (doubles)
@@ -75,16 +76,22 @@ struct IterArgs {
     // colour-by-colour triangular solves; y is an n-vector of scratch
     const IC0Dev *ic = nullptr;
     double *y = nullptr;
+    // tag of this iteration (unique within a workspace, never 0): links the
+    // point-Jacobi update to the direction update that completes it
+    uint32_t token = 0;
 };
 
 // One CG iteration = three launches:
 //   spmv    q = mask(A p), per-block partials of p^T q
 //   update  gamma = p^T q (every block sums the partials in the same order),
-//           alpha = rho / gamma, x += alpha p, r -= alpha q,
+//           alpha = rho / gamma, r -= alpha q,
 //           per-block partials of r^T D^-1 r and r^T r
 //   pupdate rho' and rr from the partials, beta = rho' / rho, stop flags,
-//           p = D^-1 r + beta p
-// ev (optional, 4 events) brackets the three kernels for timing.
+//           x += alpha p, then p = D^-1 r + beta p unless stopping
+// With point Jacobi the x update rides in the direction update, which reads
+// p anyway (one vector pass fewer); the line and IC(0) iterations keep it in
+// their update kernels.
+// ev (optional, 6 events) brackets the three kernels for timing.
 hns_status launch_iteration(const IterArgs &a, int parity, hipStream_t s, hipEvent_t *ev);
 
 // q = mask(A p) without reductions (residuals and hns_apply)

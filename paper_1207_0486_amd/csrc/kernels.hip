@@ -415,6 +415,107 @@ __global__ __launch_bounds__(kBlock) void k_spmv_sdia(int64_t n, int64_t rows, D
     }
 }
 
+// Offsets of the wide symmetric-diagonal format (kernel-argument memory)
+struct WideOffsets {
+    int32_t o[kMaxDiagWide];
+};
+
+// Symmetric diagonal storage with more upper diagonals than the unrolled
+// kernel takes (Q2 bricks: 62).  Same layout, same per-row order of the
+// terms (main, then (upper, lower) for each offset in ascending order), but
+// the offsets are streamed in groups of 8 so that a group's 32 loads are in
+// flight together without holding all 4 M of them in registers.  R rows per
+// lane as in k_spmv_sdia; interior rows take R-wide loads, rows within the
+// largest offset of either end the per-row path with range tests.
+template <typename TV, typename TX, bool DOT, int R>
+__global__ __launch_bounds__(kBlock) void k_spmv_sdia_wide(int64_t n, int64_t rows, int M,
+                                                           WideOffsets offs,
+                                                           const TV *__restrict__ dia,
+                                                           const TX *__restrict__ x,
+                                                           TX *__restrict__ y,
+                                                           const uint8_t *__restrict__ bc, int bit,
+                                                           const Scalars *__restrict__ sc,
+                                                           double *__restrict__ part)
+{
+    constexpr int GK = 8;
+    if constexpr (DOT) {
+        if (sc->stop) return;
+    }
+    const int lb = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t r0 = (int64_t)lb * rows;
+    const int64_t r1 = r0 + rows < n ? r0 + rows : n;
+    const int64_t omax = offs.o[M - 1];
+    const int Mfull = M - M % GK;
+    double acc = 0.0;
+    for (int64_t i = r0 + (int64_t)threadIdx.x * R; i < r1; i += (int64_t)kBlock * R) {
+        if (i >= omax && i + (R - 1) + omax < n) {
+            const Run<R, TX> xi = ldrun<R>(x + i);
+            const Run<R, TV> d0 = ldrun<R>(dia + i);
+            TX sum[R];
+#pragma unroll
+            for (int e = 0; e < R; ++e) sum[e] = (TX)d0.v[e] * xi.v[e];
+            for (int k0 = 0; k0 < Mfull; k0 += GK) {
+                Run<R, TV> up[GK], lo[GK];
+                Run<R, TX> xu[GK], xl[GK];
+#pragma unroll
+                for (int g = 0; g < GK; ++g) {
+                    const int64_t o = offs.o[k0 + g];
+                    const TV *u = dia + (int64_t)(k0 + g + 1) * n;
+                    up[g] = ldrun<R>(u + i);
+                    xu[g] = ldrun<R>(x + i + o);
+                    lo[g] = ldrun<R>(u + i - o);
+                    xl[g] = ldrun<R>(x + i - o);
+                }
+#pragma unroll
+                for (int g = 0; g < GK; ++g)
+#pragma unroll
+                    for (int e = 0; e < R; ++e) {
+                        sum[e] += (TX)up[g].v[e] * xu[g].v[e];
+                        sum[e] += (TX)lo[g].v[e] * xl[g].v[e];
+                    }
+            }
+            for (int k = Mfull; k < M; ++k) {
+                const int64_t o = offs.o[k];
+                const TV *u = dia + (int64_t)(k + 1) * n;
+                const Run<R, TV> up = ldrun<R>(u + i), lo = ldrun<R>(u + i - o);
+                const Run<R, TX> xu = ldrun<R>(x + i + o), xl = ldrun<R>(x + i - o);
+#pragma unroll
+                for (int e = 0; e < R; ++e) {
+                    sum[e] += (TX)up.v[e] * xu.v[e];
+                    sum[e] += (TX)lo.v[e] * xl.v[e];
+                }
+            }
+            Run<R, TX> out;
+#pragma unroll
+            for (int e = 0; e < R; ++e) {
+                out.v[e] = is_dirichlet(bc, bit, i + e) ? (TX)0 : sum[e];
+                if constexpr (DOT) acc += (double)xi.v[e] * (double)out.v[e];
+            }
+            __builtin_memcpy(y + i, &out, sizeof(out));
+        } else {
+            for (int e = 0; e < R; ++e) {
+                const int64_t j = i + e;
+                if (j >= r1) break;
+                const TX xj = x[j];
+                TX sum = (TX)dia[j] * xj;
+                for (int k = 0; k < M; ++k) {
+                    const int64_t o = offs.o[k];
+                    const TV *u = dia + (int64_t)(k + 1) * n;
+                    if (j + o < n) sum += (TX)u[j] * x[j + o];
+                    if (j >= o) sum += (TX)u[j - o] * x[j - o];
+                }
+                if (is_dirichlet(bc, bit, j)) sum = 0;
+                y[j] = sum;
+                if constexpr (DOT) acc += (double)xj * (double)sum;
+            }
+        }
+    }
+    if constexpr (DOT) {
+        double v[1] = {acc};
+        store_block_partials<1>(v, part);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // CG vector updates
 // ---------------------------------------------------------------------------
@@ -516,7 +617,7 @@ __device__ __forceinline__ void st(T *p, int64_t i, const Pack<T, W> &v)
 
 template <typename TX, typename TD, int W>
 struct UpdatePacks {
-    Pack<TX, W> x, r, p, q;
+    Pack<TX, W> r, q;
     Pack<TD, W> d;
 };
 
@@ -526,22 +627,28 @@ struct DirPacks {
     Pack<TD, W> d;
 };
 
-// x += alpha p; r -= alpha q; partials of r^T D^-1 r and r^T r.
+template <typename TX, typename TD, int W>
+struct XDirPacks {
+    Pack<TX, W> p, r, x;
+    Pack<TD, W> d;
+};
+
+// r -= alpha q; partials of r^T D^-1 r and r^T r.  Block 0 records alpha and
+// this iteration's tag, which the direction update needs to add alpha p to x.
 template <typename TX, typename TD, int V>
-__global__ __launch_bounds__(kBlock) void k_update(int64_t n, int64_t per, TX *__restrict__ x,
-                                                   TX *__restrict__ r, const TX *__restrict__ p,
+__global__ __launch_bounds__(kBlock) void k_update(int64_t n, int64_t per, TX *__restrict__ r,
                                                    const TX *__restrict__ q,
                                                    const TD *__restrict__ dinv,
                                                    Scalars *__restrict__ sc,
                                                    const double *__restrict__ part_in, int G_in,
-                                                   double *__restrict__ part_out, int parity)
+                                                   double *__restrict__ part_out, int parity,
+                                                   uint32_t token)
 {
     if (sc->stop) return;
     TX alpha = 0;
     auto load = [&](int64_t i, auto w) {
         constexpr int W = decltype(w)::value;
-        return UpdatePacks<TX, TD, W>{ld<W>(x, i), ld<W>(r, i), ld<W>(p, i), ld<W>(q, i),
-                                      ld<W>(dinv, i)};
+        return UpdatePacks<TX, TD, W>{ld<W>(r, i), ld<W>(q, i), ld<W>(dinv, i)};
     };
     auto prologue = [&]() {
         double g[1];
@@ -558,22 +665,21 @@ __global__ __launch_bounds__(kBlock) void k_update(int64_t n, int64_t per, TX *_
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             sc->gamma = gamma;
             sc->alpha = alpha_d;
+            sc->xtoken = token;
         }
         alpha = (TX)alpha_d;
         return true;
     };
     double rz = 0.0, rr = 0.0;
     auto body = [&](int64_t i, auto in) {
-        constexpr int W = sizeof(in.x.v) / sizeof(TX);
+        constexpr int W = sizeof(in.r.v) / sizeof(TX);
 #pragma unroll
         for (int e = 0; e < W; ++e) {
-            in.x.v[e] = in.x.v[e] + alpha * in.p.v[e];
             in.r.v[e] = in.r.v[e] - alpha * in.q.v[e];
             const TX zi = (TX)in.d.v[e] * in.r.v[e];
             rz += (double)in.r.v[e] * (double)zi;
             rr += (double)in.r.v[e] * (double)in.r.v[e];
         }
-        st<W>(x, i, in.x);
         st<W>(r, i, in.r);
     };
     if (!for_packs_ahead<V>(n, per, load, prologue, body)) return;
@@ -623,6 +729,65 @@ __global__ __launch_bounds__(kBlock) void k_pupdate(int64_t n, int64_t per, TX *
 #pragma unroll
         for (int e = 0; e < W; ++e) in.p.v[e] = (TX)in.d.v[e] * in.r.v[e] + beta * in.p.v[e];
         st<W>(p, i, in.p);
+    };
+    for_packs_ahead<V>(n, per, load, prologue, body);
+}
+
+// The direction update of a point-Jacobi iteration, completing it: when this
+// iteration's update ran (its tag is recorded; written by an earlier launch,
+// so every block reads it consistently), x += alpha p with the old p, then,
+// unless the iteration converged or broke down, p = D^-1 r + beta p.  The
+// entry test is the tag and not the stop flag: block 0 of this launch may
+// raise the flag while other blocks still have their x update to do.
+template <typename TX, typename TD, int V = 1>
+__global__ __launch_bounds__(kBlock) void k_pupdate_x(int64_t n, int64_t per,
+                                                      TX *__restrict__ x, TX *__restrict__ p,
+                                                      const TX *__restrict__ r,
+                                                      const TD *__restrict__ dinv,
+                                                      Scalars *__restrict__ sc,
+                                                      const double *__restrict__ part_in,
+                                                      int G_in, int parity, uint32_t token)
+{
+    if (sc->xtoken != token) return;
+    const TX alpha = (TX)sc->alpha;
+    TX beta = 0;
+    bool dir = true;
+    auto load = [&](int64_t i, auto w) {
+        constexpr int W = decltype(w)::value;
+        return XDirPacks<TX, TD, W>{ld<W>(p, i), ld<W>(r, i), ld<W>(x, i), ld<W>(dinv, i)};
+    };
+    auto prologue = [&]() {
+        double v[2];
+        load_reduced<2>(part_in, G_in, v);
+        const double rho_new = v[0], rr = v[1];
+        const bool bad = !isfinite(rho_new) || !isfinite(rr);
+        const bool conv = !bad && rr <= sc->tol2 * sc->bb;
+        const double beta_d = rho_new / sc->rho[parity];
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            sc->rho[parity ^ 1] = rho_new;
+            sc->rr = rr;
+            sc->beta = beta_d;
+            sc->iter += 1;
+            if (bad)
+                sc->stop = 2;
+            else if (conv)
+                sc->stop = 1;
+        }
+        beta = (TX)beta_d;
+        dir = !(bad || conv);
+        return true;
+    };
+    auto body = [&](int64_t i, auto in) {
+        constexpr int W = sizeof(in.p.v) / sizeof(TX);
+#pragma unroll
+        for (int e = 0; e < W; ++e) in.x.v[e] = in.x.v[e] + alpha * in.p.v[e];
+        st<W>(x, i, in.x);
+        if (dir) {
+#pragma unroll
+            for (int e = 0; e < W; ++e)
+                in.p.v[e] = (TX)in.d.v[e] * in.r.v[e] + beta * in.p.v[e];
+            st<W>(p, i, in.p);
+        }
     };
     for_packs_ahead<V>(n, per, load, prologue, body);
 }
@@ -1209,6 +1374,21 @@ int sdia_launch(const DevMatrix &A, const TV *vals, const void *p, void *q, cons
     return c.grid;
 }
 
+template <typename TV, typename TX, bool DOT>
+int sdia_wide_launch(const DevMatrix &A, const TV *vals, const void *p, void *q,
+                     const uint8_t *bc, int bit, const Scalars *sc, double *part, hipStream_t s,
+                     hipEvent_t *ev2)
+{
+    constexpr int R = sizeof(TX) == 8 ? 2 : 1;
+    WideOffsets offs;
+    for (int k = 0; k < kMaxDiagWide; ++k) offs.o[k] = k < A.ndiag ? A.off[k] : 0;
+    const Chunks c = sdia_chunks<TX>(A);
+    if (launch_k(k_spmv_sdia_wide<TV, TX, DOT, R>, c.grid, kBlock, 0, s, ev2, A.n, c.per,
+                 A.ndiag, offs, vals, (const TX *)p, (TX *)q, bc, bit, sc, part) != hipSuccess)
+        return -1;
+    return c.grid;
+}
+
 template <typename TV, typename TX, bool DOT, int M = 1>
 int sdia_dispatch(const DevMatrix &A, const TV *vals, const void *p, void *q, const uint8_t *bc,
                   int bit, const Scalars *sc, double *part, hipStream_t s, hipEvent_t *ev2)
@@ -1218,7 +1398,9 @@ int sdia_dispatch(const DevMatrix &A, const TV *vals, const void *p, void *q, co
             return sdia_launch<TV, TX, DOT, M>(A, vals, p, q, bc, bit, sc, part, s, ev2);
         return sdia_dispatch<TV, TX, DOT, M + 1>(A, vals, p, q, bc, bit, sc, part, s, ev2);
     }
-    return 0;
+    if (A.ndiag > kMaxDiag && A.ndiag <= kMaxDiagWide)
+        return sdia_wide_launch<TV, TX, DOT>(A, vals, p, q, bc, bit, sc, part, s, ev2);
+    return -1;
 }
 
 // Launches q = A p (+ per-block partials of p^T q when DOT); returns the
@@ -1345,18 +1527,18 @@ hns_status iteration_impl(const IterArgs &a, int parity, hipStream_t s, hipEvent
     hipEvent_t *eu = ev ? ev + 2 : nullptr, *ep = ev ? ev + 4 : nullptr;
     if (vec) {
         HNS_TRY_HIP(launch_k(k_update<TX, TD, V>, cu.grid, kBlock, 0, s, eu, a.n, cu.per,
-                             (TX *)a.x, (TX *)a.r, (const TX *)a.p, (const TX *)a.q,
-                             (const TD *)a.dinv, a.sc, (const double *)P1, Gs, P2, parity));
-        HNS_TRY_HIP(launch_k(k_pupdate<TX, TD, V>, cu.grid, kBlock, 0, s, ep, a.n, cu.per,
-                             (TX *)a.p, (const TX *)a.r, (const TD *)a.dinv, a.sc,
-                             (const double *)P2, cu.grid, parity, 1));
+                             (TX *)a.r, (const TX *)a.q, (const TD *)a.dinv, a.sc,
+                             (const double *)P1, Gs, P2, parity, a.token));
+        HNS_TRY_HIP(launch_k(k_pupdate_x<TX, TD, V>, cu.grid, kBlock, 0, s, ep, a.n, cu.per,
+                             (TX *)a.x, (TX *)a.p, (const TX *)a.r, (const TD *)a.dinv, a.sc,
+                             (const double *)P2, cu.grid, parity, a.token));
     } else {
         HNS_TRY_HIP(launch_k(k_update<TX, TD, 1>, cu.grid, kBlock, 0, s, eu, a.n, cu.per,
-                             (TX *)a.x, (TX *)a.r, (const TX *)a.p, (const TX *)a.q,
-                             (const TD *)a.dinv, a.sc, (const double *)P1, Gs, P2, parity));
-        HNS_TRY_HIP(launch_k(k_pupdate<TX, TD, 1>, cu.grid, kBlock, 0, s, ep, a.n, cu.per,
-                             (TX *)a.p, (const TX *)a.r, (const TD *)a.dinv, a.sc,
-                             (const double *)P2, cu.grid, parity, 1));
+                             (TX *)a.r, (const TX *)a.q, (const TD *)a.dinv, a.sc,
+                             (const double *)P1, Gs, P2, parity, a.token));
+        HNS_TRY_HIP(launch_k(k_pupdate_x<TX, TD, 1>, cu.grid, kBlock, 0, s, ep, a.n, cu.per,
+                             (TX *)a.x, (TX *)a.p, (const TX *)a.r, (const TD *)a.dinv, a.sc,
+                             (const double *)P2, cu.grid, parity, a.token));
     }
     return check_launch("cg iteration");
 }

@@ -36,6 +36,7 @@ struct Workspace {
     Scalars *sc = nullptr;        // [0] FP64 / outer loop, [1] inner FP32 loop
     Scalars *host = nullptr;      // pinned mirror of sc[0..1]
     std::vector<hipEvent_t> ev;   // timing events, a (start, end) pair per kernel of an iteration
+    uint32_t token = 0;           // last iteration tag handed out (IterArgs::token)
 
     static size_t bytes_for(int64_t n, bool mixed)
     {
@@ -215,6 +216,8 @@ static hns_status enqueue_iterations(hns_operator *op, Workspace *w, Prec prec, 
     }
     for (int it = 0; it < count; ++it) {
         const bool timed = period > 0 && (it % period) == 0;
+        if (++w->token == 0) w->token = 1;   // unique per workspace, never 0
+        a.token = w->token;
         HNS_TRY(launch_iteration(a, (parity0 + it) & 1, s, timed ? &w->ev[6 * it] : nullptr));
     }
     return HNS_OK;

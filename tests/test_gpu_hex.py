@@ -48,10 +48,13 @@ def _op(m, kind="helmholtz", fmt="auto", nu=(NU_H, NU_V), **kw):
 @pytest.mark.parametrize("order,fmt", [(1, "auto"), (1, "csr"), (1, "sell"),
                                        (2, "auto"), (2, "csr"), (2, "sell")])
 def test_hex_operator_product_matches_oracle(dev, order, fmt):
+    """Q1: the 27-point stencil in 13-diagonal storage; Q2: 125 lattice
+    offsets, 62 upper diagonals in the wide diagonal storage (fewer bytes than
+    CSR although about half the stored entries are zeros)."""
     m = _mesh(order)
     op = _op(m, fmt=fmt)
-    if fmt == "auto" and order == 1:
-        assert op.format == "sdia" and op.ndiag == 13     # the 27-point stencil
+    if fmt == "auto":
+        assert op.format == "sdia" and op.ndiag == (13 if order == 1 else 62)
     A = oracle.hex_helmholtz(m, NU_H, NU_V, DT)
     assert op.nnz == A.nnz
     x = np.random.default_rng(order).standard_normal(m.n)
@@ -190,6 +193,26 @@ def test_hex_mesh_errors(dev):
     with pytest.raises(HNSError) as e:
         Operator(m, 1.0, 1.0, 1.0, kind="helmholtz", gpu_assembly=True)
     assert e.value.status == -1
+
+
+@pytest.mark.parametrize("fmt", ["sdia", "csr"])
+def test_q2_velocity_solve_formats_agree(dev, fmt):
+    """The wide diagonal kernel (groups of 8 offsets, R rows per lane, the
+    edge rows on the per-row path) against CSR and the oracle on a mesh whose
+    rows span several blocks of every launch."""
+    m = basin.basin_hex_mesh(20, 16, 6, 2, seed=8)
+    op = _op(m, fmt=fmt, keep_fp32=True)
+    d = (m.bc & basin.BC_U2) != 0
+    b = basin.normal_rhs(m.n, 41, dirichlet=d)
+    x, info = op.solve(_gpu(b, dev), tol=1e-10, mask_bit=1)
+    A = oracle.hex_helmholtz(m, NU_H, NU_V, DT)
+    assert info.status == 0
+    assert oracle.relres(A, b, x.cpu().numpy(), d) <= 1.01e-10
+    same = oracle.pcg(A, b, dirichlet=d, tol=1e-300, maxit=info.iterations)
+    assert _rel(x.cpu().numpy(), same.x) <= 1e-10
+    xm, im = op.solve(_gpu(b, dev), tol=1e-10, mask_bit=1, mode="mixed")
+    assert im.status == 0
+    assert oracle.relres(A, b, xm.cpu().numpy(), d) <= 1.01e-10
 
 
 def test_q2_full_size_sampled_rows_and_solve(dev):
