@@ -225,7 +225,7 @@ def bench_isotropic(torch, log, m, b_q, point_cap=3000):
     t_line, i_line = solve(1, wl.tol, 100000, 3)
     # bytes per line-preconditioned iteration: operator + 2 (SpMV) + 9 (update
     # reads x, r, p, q, couplings, pivots; writes x, r, z) + 3 (p-update) passes
-    line_bytes = i_line.iterations * (matrix_bytes(fmt, n, nnz, 8) + 14 * 8 * n)
+    line_bytes = i_line.iterations * (matrix_bytes(fmt, n, nnz, 8) + 13 * 8 * n)
     t_pt, i_pt = solve(0, wl.tol, point_cap, 1)
     out = {
         "workload": wl.name, "nu": [wl.nu_h, wl.nu_h, wl.nu_v], "tol": wl.tol,
@@ -341,7 +341,7 @@ def bench_bricks(torch, log, reps=3):
             torch.cuda.synchronize()
             el = time.perf_counter() - t
             best = el if best is None else min(best, el)
-        passes = 12 if precond == 0 else 14
+        passes = 12 if precond == 0 else 13
         by = info.iterations * (matrix_bytes(op.format, op.n, op.nnz, 8) + passes * 8 * op.n)
         # diagonal storage also reads the zeros it stores where a row lacks an offset
         stored = ((op.ndiag + 1) * op.n * 8 if op.format == "sdia"

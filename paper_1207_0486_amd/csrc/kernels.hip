@@ -868,16 +868,17 @@ __device__ __forceinline__ double line_columns(int ncols, int L, const double *s
 }
 
 template <int W>
-struct LinePacks {
-    Pack<double, W> p, z;
+struct XLinePacks {
+    Pack<double, W> p, z, x;
 };
 
-// x += alpha p; r -= alpha q; z = M^-1 r; partials of r^T z and r^T r.
+// r -= alpha q; z = M^-1 r; partials of r^T z and r^T r.  Block 0 records
+// alpha and the iteration tag (x += alpha p is done by k_pupdate_line_x).
 __global__ __launch_bounds__(kBlock) void k_update_line(
-    int64_t n, int L, int NC, double *__restrict__ x, double *__restrict__ r,
-    const double *__restrict__ p, const double *__restrict__ q, double *__restrict__ z,
-    const double *__restrict__ lfac, Scalars *__restrict__ sc,
-    const double *__restrict__ part_in, int G_in, double *__restrict__ part_out, int parity)
+    int64_t n, int L, int NC, double *__restrict__ r, const double *__restrict__ q,
+    double *__restrict__ z, const double *__restrict__ lfac, Scalars *__restrict__ sc,
+    const double *__restrict__ part_in, int G_in, double *__restrict__ part_out, int parity,
+    uint32_t token)
 {
     if (sc->stop) return;
     extern __shared__ double line_lds[];
@@ -895,6 +896,7 @@ __global__ __launch_bounds__(kBlock) void k_update_line(
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         sc->gamma = gamma;
         sc->alpha = alpha;
+        sc->xtoken = token;
     }
     const int span = NC * L;
     double *sr = line_lds, *se = sr + span, *sw = se + span, *sy = sw + span;
@@ -905,9 +907,7 @@ __global__ __launch_bounds__(kBlock) void k_update_line(
     double rr = 0.0;
     for (int t = threadIdx.x; t < rows; t += kBlock) {
         const int64_t i = row0 + t;
-        const double xi = x[i] + alpha * p[i];
         const double ri = r[i] - alpha * q[i];
-        x[i] = xi;
         r[i] = ri;
         sr[t] = ri;
         se[t] = le[i];
@@ -922,20 +922,27 @@ __global__ __launch_bounds__(kBlock) void k_update_line(
     store_block_partials<2>(v, part_out);
 }
 
-// rho' = r^T z, rr = r^T r from the line update's partials; beta = rho'/rho;
-// p = z + beta p unless converged.
-__global__ __launch_bounds__(kBlock) void k_pupdate_line(int64_t n, int64_t per,
-                                                         double *__restrict__ p,
-                                                         const double *__restrict__ z,
-                                                         Scalars *__restrict__ sc,
-                                                         const double *__restrict__ part_in,
-                                                         int G_in, int parity)
+// Direction update of the line and IC(0) iterations, completing them as
+// k_pupdate_x does for point Jacobi: when this iteration's update ran (its
+// tag is recorded), x += alpha p with the old p; then rho' = r^T z, rr = r^T r
+// from the partials, beta = rho'/rho and, unless converged or broken down,
+// p = z + beta p.
+template <int V>
+__global__ __launch_bounds__(kBlock) void k_pupdate_line_x(int64_t n, int64_t per,
+                                                           double *__restrict__ x,
+                                                           double *__restrict__ p,
+                                                           const double *__restrict__ z,
+                                                           Scalars *__restrict__ sc,
+                                                           const double *__restrict__ part_in,
+                                                           int G_in, int parity, uint32_t token)
 {
-    if (sc->stop) return;
+    if (sc->xtoken != token) return;
+    const double alpha = sc->alpha;
     double beta = 0.0;
+    bool dir = true;
     auto load = [&](int64_t i, auto w) {
         constexpr int W = decltype(w)::value;
-        return LinePacks<W>{ld<W>(p, i), ld<W>(z, i)};
+        return XLinePacks<W>{ld<W>(p, i), ld<W>(z, i), ld<W>(x, i)};
     };
     auto prologue = [&]() {
         double v[2];
@@ -954,15 +961,21 @@ __global__ __launch_bounds__(kBlock) void k_pupdate_line(int64_t n, int64_t per,
             else if (conv)
                 sc->stop = 1;
         }
-        return !(bad || conv);
+        dir = !(bad || conv);
+        return true;
     };
     auto body = [&](int64_t i, auto in) {
         constexpr int W = sizeof(in.p.v) / sizeof(double);
 #pragma unroll
-        for (int e = 0; e < W; ++e) in.p.v[e] = in.z.v[e] + beta * in.p.v[e];
-        st<W>(p, i, in.p);
+        for (int e = 0; e < W; ++e) in.x.v[e] = in.x.v[e] + alpha * in.p.v[e];
+        st<W>(x, i, in.x);
+        if (dir) {
+#pragma unroll
+            for (int e = 0; e < W; ++e) in.p.v[e] = in.z.v[e] + beta * in.p.v[e];
+            st<W>(p, i, in.p);
+        }
     };
-    for_packs_ahead<2>(n, per, load, prologue, body);
+    for_packs_ahead<V>(n, per, load, prologue, body);
 }
 
 // (singular: r -= mean r); z = M^-1 r; p = z; rho[0] = r^T z; rr = r^T r.
@@ -1060,26 +1073,25 @@ __global__ __launch_bounds__(kBlock) void k_ic_backward(int64_t r0, int64_t r1,
 }
 
 template <int W>
-struct XRPQPacks {
-    Pack<double, W> x, r, p, q;
+struct RQPacks {
+    Pack<double, W> r, q;
 };
 
-// x += alpha p; r -= alpha q (no partials: r^T z and r^T r follow the solves)
+// r -= alpha q (no partials: r^T z and r^T r follow the solves); block 0
+// records alpha and the iteration tag for k_pupdate_line_x
 template <int V>
 __global__ __launch_bounds__(kBlock) void k_update_noz(int64_t n, int64_t per,
-                                                       double *__restrict__ x,
                                                        double *__restrict__ r,
-                                                       const double *__restrict__ p,
                                                        const double *__restrict__ q,
                                                        Scalars *__restrict__ sc,
                                                        const double *__restrict__ part_in,
-                                                       int G_in, int parity)
+                                                       int G_in, int parity, uint32_t token)
 {
     if (sc->stop) return;
     double alpha = 0.0;
     auto load = [&](int64_t i, auto w) {
         constexpr int W = decltype(w)::value;
-        return XRPQPacks<W>{ld<W>(x, i), ld<W>(r, i), ld<W>(p, i), ld<W>(q, i)};
+        return RQPacks<W>{ld<W>(r, i), ld<W>(q, i)};
     };
     auto prologue = [&]() {
         double g[1];
@@ -1096,17 +1108,14 @@ __global__ __launch_bounds__(kBlock) void k_update_noz(int64_t n, int64_t per,
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             sc->gamma = gamma;
             sc->alpha = alpha;
+            sc->xtoken = token;
         }
         return true;
     };
     auto body = [&](int64_t i, auto in) {
-        constexpr int W = sizeof(in.x.v) / sizeof(double);
+        constexpr int W = sizeof(in.r.v) / sizeof(double);
 #pragma unroll
-        for (int e = 0; e < W; ++e) {
-            in.x.v[e] = in.x.v[e] + alpha * in.p.v[e];
-            in.r.v[e] = in.r.v[e] - alpha * in.q.v[e];
-        }
-        st<W>(x, i, in.x);
+        for (int e = 0; e < W; ++e) in.r.v[e] = in.r.v[e] - alpha * in.q.v[e];
         st<W>(r, i, in.r);
     };
     for_packs_ahead<V>(n, per, load, prologue, body);
@@ -1434,6 +1443,27 @@ constexpr int kLineLds = 49152;   // bytes of LDS for the staged columns of one 
 
 // Event pairs of a timed iteration: ev[0..1] SpMV, ev[2..3] update,
 // ev[4..5] direction update (each recorded by its kernel's dispatch).
+// k_pupdate_line_x over the n rows: p and z are workspace vectors (16-byte
+// aligned), x may be a row of a caller's array at an 8-byte offset, in which
+// case one element per thread.  G_in: number of update partials.
+hns_status launch_pupdate_line_x(const IterArgs &a, int parity, int G_in, hipStream_t s,
+                                 hipEvent_t *ev2)
+{
+    double *P2 = a.partials + kPartUpdate;
+    if (aligned16(a.x)) {
+        const Chunks cp = chunks(a.n / 2, (int64_t)kBlock * a.A->vec_it, kBlock);
+        HNS_TRY_HIP(launch_k(k_pupdate_line_x<2>, cp.grid, kBlock, 0, s, ev2, a.n, cp.per,
+                             (double *)a.x, (double *)a.p, (const double *)a.z, a.sc,
+                             (const double *)P2, G_in, parity, a.token));
+    } else {
+        const Chunks cp = chunks(a.n, (int64_t)kBlock * a.A->vec_it, kBlock);
+        HNS_TRY_HIP(launch_k(k_pupdate_line_x<1>, cp.grid, kBlock, 0, s, ev2, a.n, cp.per,
+                             (double *)a.x, (double *)a.p, (const double *)a.z, a.sc,
+                             (const double *)P2, G_in, parity, a.token));
+    }
+    return HNS_OK;
+}
+
 hns_status line_iteration(const IterArgs &a, int parity, hipStream_t s, hipEvent_t *ev)
 {
     const uint8_t *bc = a.bit < 0 ? nullptr : a.bc;
@@ -1442,17 +1472,13 @@ hns_status line_iteration(const IterArgs &a, int parity, hipStream_t s, hipEvent
     const int L = a.line_len;
     const int NC = line_cols_per_block(L);
     const int Gl = line_grid(a.n, L);
-    const Chunks cu = chunks(a.n / 2, (int64_t)kBlock * a.A->vec_it, kBlock);
     const int Gs = spmv_dispatch<double, double, true>(*a.A, a.p, a.q, bc, a.bit, a.sc, P1, s,
                                                        ev ? ev : nullptr);
     if (Gs < 0) return check_launch("spmv");
     HNS_TRY_HIP(launch_k(k_update_line, Gl, kBlock, (size_t)4 * NC * L * sizeof(double), s,
-                         ev ? ev + 2 : nullptr, a.n, L, NC, (double *)a.x, (double *)a.r,
-                         (const double *)a.p, (const double *)a.q, a.z, a.lfac, a.sc,
-                         (const double *)P1, Gs, P2, parity));
-    HNS_TRY_HIP(launch_k(k_pupdate_line, cu.grid, kBlock, 0, s, ev ? ev + 4 : nullptr, a.n,
-                         cu.per, (double *)a.p, (const double *)a.z, a.sc, (const double *)P2,
-                         Gl, parity));
+                         ev ? ev + 2 : nullptr, a.n, L, NC, (double *)a.r, (const double *)a.q,
+                         a.z, a.lfac, a.sc, (const double *)P1, Gs, P2, parity, a.token));
+    HNS_TRY(launch_pupdate_line_x(a, parity, Gl, s, ev ? ev + 4 : nullptr));
     return check_launch("line-preconditioned cg iteration");
 }
 
@@ -1488,12 +1514,12 @@ hns_status ic0_iteration(const IterArgs &a, int parity, hipStream_t s, hipEvent_
     if (Gs < 0) return check_launch("spmv");
     if (vec) {
         HNS_TRY_HIP(launch_k(k_update_noz<2>, cu.grid, kBlock, 0, s, ev ? ev + 2 : nullptr, a.n,
-                             cu.per, (double *)a.x, (double *)a.r, (const double *)a.p,
-                             (const double *)a.q, a.sc, (const double *)P1, Gs, parity));
+                             cu.per, (double *)a.r, (const double *)a.q, a.sc,
+                             (const double *)P1, Gs, parity, a.token));
     } else {
         HNS_TRY_HIP(launch_k(k_update_noz<1>, cu.grid, kBlock, 0, s, ev ? ev + 2 : nullptr, a.n,
-                             cu.per, (double *)a.x, (double *)a.r, (const double *)a.p,
-                             (const double *)a.q, a.sc, (const double *)P1, Gs, parity));
+                             cu.per, (double *)a.r, (const double *)a.q, a.sc,
+                             (const double *)P1, Gs, parity, a.token));
     }
     HNS_TRY(ic0_apply(*a.ic, (const double *)a.r, a.y, a.z, s));
     if (vec)
@@ -1501,11 +1527,7 @@ hns_status ic0_iteration(const IterArgs &a, int parity, hipStream_t s, hipEvent_
     else
         k_dot_rz<1><<<cu.grid, kBlock, 0, s>>>(a.n, cu.per, (const double *)a.r, a.z, a.sc, P2);
     HNS_TRY(check_launch("dot r.z"));
-    // p and z are workspace vectors (16-byte aligned): packs of two always
-    const Chunks cp = chunks(a.n / 2, (int64_t)kBlock * a.A->vec_it, kBlock);
-    HNS_TRY_HIP(launch_k(k_pupdate_line, cp.grid, kBlock, 0, s, ev ? ev + 4 : nullptr, a.n,
-                         cp.per, (double *)a.p, (const double *)a.z, a.sc, (const double *)P2,
-                         cu.grid, parity));
+    HNS_TRY(launch_pupdate_line_x(a, parity, cu.grid, s, ev ? ev + 4 : nullptr));
     return check_launch("ic0-preconditioned cg iteration");
 }
 
