@@ -213,6 +213,43 @@ def test_q2_velocity_solve_formats_agree(dev, fmt):
     xm, im = op.solve(_gpu(b, dev), tol=1e-10, mask_bit=1, mode="mixed")
     assert im.status == 0
     assert oracle.relres(A, b, xm.cpu().numpy(), d) <= 1.01e-10
+    # four columns (pack widths 2 and 4 of the batched product), both modes
+    bits = [0, 1, 2, 1]
+    B = np.stack([basin.normal_rhs(m.n, 50 + j, dirichlet=((m.bc >> bits[j]) & 1) == 1)
+                  for j in range(4)], axis=1)
+    for mode in ("fp64", "mixed"):
+        X, infos = op.solve_batched(_gpu(B, dev), mask_bits=bits, tol=1e-10, mode=mode)
+        for j in range(4):
+            dj = ((m.bc >> bits[j]) & 1) == 1
+            assert infos[j].status == 0, (mode, j)
+            assert oracle.relres(A, B[:, j], X[:, j].cpu().numpy(), dj) <= 1.01e-10, (mode, j)
+
+
+@pytest.mark.parametrize("dims", [(1, 1, 1), (2, 1, 1), (1, 2, 3), (3, 2, 1), (5, 4, 2)])
+def test_q2_small_meshes_edge_rows(dev, dims):
+    """Meshes whose rows lie (mostly or all) within the largest diagonal
+    offset of an end, so the wide kernel's per-row path carries them: one
+    brick (27 nodes, every row on that path), one layer, one column of
+    bricks (26 to 62 distinct offsets on these lattices; the diagonal storage
+    is forced where the automatic choice would take CSR); product, masked
+    product and a Dirichlet solve against the oracle."""
+    m = basin.box_hex_mesh(*dims, 2, Lx=2.0, Ly=1.5, H=0.3)
+    op = _op(m, fmt="sdia")
+    assert op.format == "sdia" and 16 < op.ndiag <= 62     # the wide kernel
+    A = oracle.hex_helmholtz(m, NU_H, NU_V, DT)
+    x = np.random.default_rng(sum(dims)).standard_normal(m.n)
+    scale = np.abs(A.to_scipy()) @ np.abs(x)
+    got = op.apply(_gpu(x, dev)).cpu().numpy()
+    assert np.all(np.abs(got - A.matvec(x)) <= 1e-13 * scale)
+    d = (m.bc & basin.BC_U3) != 0
+    gm = op.apply(_gpu(x, dev), mask_bit=2).cpu().numpy()
+    assert np.all(gm[d] == 0.0)
+    b = basin.normal_rhs(m.n, 5, dirichlet=d)
+    if not np.any(b):
+        return
+    xs, info = op.solve(_gpu(b, dev), tol=1e-12, mask_bit=2)
+    assert info.status == 0
+    assert oracle.relres(A, b, xs.cpu().numpy(), d) <= 1.01e-12
 
 
 def test_q2_full_size_sampled_rows_and_solve(dev):
