@@ -503,10 +503,11 @@ def bench_serving(torch, log, budget_gb=16.0, mode="fp64", count=256, capacity=8
     return out
 
 
-def traffic_probe(torch, log, iters=64):
+def traffic_probe(torch, log, iters=64, q2_iters=16):
     """Short run for hardware-counter passes: a plain 1 GiB device copy (the
-    calibration kernel of known size) and 64 iterations of the 256x256x20
-    pressure solve (the dominant SpMV kernel)."""
+    calibration kernel of known size), 64 iterations of the 256x256x20
+    pressure solve (the dominant SpMV kernel), then 16 iterations of the Q2
+    velocity solve on 128x128x10 bricks (the wide diagonal SpMV)."""
     import basin
     from paper_1207_0486_amd.hns import Operator
     dev = torch.device("cuda", 0)
@@ -523,6 +524,17 @@ def traffic_probe(torch, log, iters=64):
     out = {"probe": "traffic", "copy_bytes": 2 * a.numel() * 8, "nodes": m.n, "nnz": pois.nnz,
            "format": pois.format, "iterations": info.iterations,
            "spmv_algorithmic_bytes": bytes_spmv(pois.format, m.n, pois.nnz, 8)}
+    pois.close()
+    del a, b
+    mq = basin.basin_hex_mesh(128, 128, 10, 2, L=wl.L, seed=wl.seed)
+    q2 = Operator(mq, wl.nu_h, wl.nu_v, wl.dt, kind="helmholtz")
+    d = (mq.bc & basin.BC_U1) != 0
+    rq = torch.as_tensor(basin.normal_rhs(mq.n, 31, dirichlet=d), device=dev)
+    xq, iq = q2.solve(rq, tol=1e-30, max_iter=q2_iters, mask_bit=0, check=False)
+    torch.cuda.synchronize()
+    out["q2"] = {"nodes": mq.n, "nnz": q2.nnz, "format": q2.format, "ndiag": q2.ndiag,
+                 "iterations": iq.iterations,
+                 "stored_bytes_per_spmv": (q2.ndiag + 1) * mq.n * 8 + 2 * 8 * mq.n}
     print(json.dumps(out), flush=True)
 
 
@@ -542,7 +554,8 @@ def main():
     ap.add_argument("--no-precond", action="store_true")
     ap.add_argument("--no-bricks", action="store_true")
     ap.add_argument("--traffic-probe", action="store_true",
-                    help="only a 1 GiB copy and 64 pressure iterations (for counter passes)")
+                    help="only a 1 GiB copy, 64 pressure iterations and 16 Q2 velocity "
+                         "iterations (for counter passes)")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serve-budget-gb", type=float, default=16.0)
     ap.add_argument("--serve-mode", default="fp64", choices=["fp64", "mixed"])
