@@ -252,6 +252,33 @@ def test_q2_small_meshes_edge_rows(dev, dims):
     assert oracle.relres(A, b, xs.cpu().numpy(), d) <= 1.01e-12
 
 
+def test_q2_mid_size_basin(dev):
+    """Q2 on 4 x 64 x 8 bricks (19,737 nodes, 2193 per x-plane: the
+    far lower-triangle reads cross many blocks of the launch); product, FP64
+    and mixed solves and the iterate at the same count against the oracle."""
+    m = basin.basin_hex_mesh(4, 64, 8, 2, seed=11)
+    assert m.n // (2 * 4 + 1) == 2193
+    op = _op(m, keep_fp32=True)
+    assert op.format == "sdia" and op.ndiag == 62
+    A = oracle.hex_helmholtz(m, NU_H, NU_V, DT)
+    x = np.random.default_rng(12).standard_normal(m.n)
+    scale = np.abs(A.to_scipy()) @ np.abs(x)
+    got = op.apply(_gpu(x, dev)).cpu().numpy()
+    assert np.all(np.abs(got - A.matvec(x)) <= 1e-13 * scale)
+    d = (m.bc & basin.BC_U1) != 0
+    b = basin.normal_rhs(m.n, 13, dirichlet=d)
+    xs, info = op.solve(_gpu(b, dev), tol=1e-10, mask_bit=0)
+    assert info.status == 0
+    assert oracle.relres(A, b, xs.cpu().numpy(), d) <= 1.01e-10
+    ref = oracle.pcg(A, b, dirichlet=d, tol=1e-10)
+    assert abs(info.iterations - ref.iterations) <= max(1, 0.02 * ref.iterations)
+    same = oracle.pcg(A, b, dirichlet=d, tol=1e-300, maxit=info.iterations)
+    assert _rel(xs.cpu().numpy(), same.x) <= 1e-10
+    xm, im = op.solve(_gpu(b, dev), tol=1e-10, mask_bit=0, mode="mixed")
+    assert im.status == 0
+    assert oracle.relres(A, b, xm.cpu().numpy(), d) <= 1.01e-10
+
+
 def test_q2_full_size_sampled_rows_and_solve(dev):
     """Q2 velocity operator on 128 x 128 x 10 bricks (1,387,029 nodes, the
     node lattice of the 256 x 256 x 20 tetrahedral mesh): sampled rows of the
