@@ -296,6 +296,38 @@ def bench_loop(torch, log, m, steps=4, stress_steps=2):
     return out
 
 
+def bench_small_box(torch, log, warm=2, reps=5):
+    """The small plain-method case (16x16x4 box, 1445 nodes, anisotropic
+    Laplacian, Dirichlet bottom and walls, FP64 Jacobi-PCG to 1e-10):
+    launch- and synchronisation-bound, so its figure is the latency of one
+    hns_solve call (median of `reps` after `warm` warm-ups), FP64 and mixed."""
+    import basin
+    from paper_1207_0486_amd.hns import Operator
+    cfg = basin.configs.BOX_16x16x4
+    m = cfg.mesh()
+    d = ~m.free_mask(basin.BC_U1)
+    b = torch.as_tensor(basin.normal_rhs(m.n, cfg.seed, zero_mean=True, dirichlet=d),
+                        device="cuda")
+    op = Operator(m, cfg.nu_h, cfg.nu_v, kind="poisson", keep_fp32=True)
+    out = {"workload": cfg.name, "nodes": m.n, "format": op.format, "tol": cfg.tol}
+    for mode in ("fp64", "mixed"):
+        ts, info = [], None
+        for k in range(warm + reps):
+            x = torch.zeros_like(b)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            x, info = op.solve(b, x, tol=cfg.tol, mask_bit=0, mode=mode)
+            torch.cuda.synchronize()
+            if k >= warm:
+                ts.append(time.perf_counter() - t)
+        out[mode] = {"latency_us_median": round(1e6 * float(np.median(ts)), 1),
+                     "latency_us_min": round(1e6 * min(ts), 1), "iterations": info.iterations,
+                     "relres": float("%.3g" % info.relres_true)}
+    op.close()
+    log(f"small box: {out}")
+    return out
+
+
 def bench_bricks(torch, log, reps=3):
     """The paper's own discretisation (Sec. 5) over the 256x256x20 basin's
     bathymetry: Q2 velocity operator M + dt K_nu on 128x128x10 bricks
@@ -698,6 +730,8 @@ def main():
     if not args.no_precond:
         precond = bench_preconditioners(torch, log, m, st.b_vel[0].clone())
 
+    small_box = bench_small_box(torch, log)
+
     bricks = None
     if not args.no_bricks:
         bricks = bench_bricks(torch, log)
@@ -763,12 +797,18 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(spmv_gbs, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(spmv_gbs / PEAK_HBM_GBS, 4), "traffic": traffic,
                      "kernel": spmv_kernel,
-                     "bytes_per_launch": spmv_bytes, "avg_us": round(spmv_avg_us, 2)},
+                     "bytes_per_launch": spmv_bytes, "avg_us": round(spmv_avg_us, 2),
+                     # the same launch priced at the canonical CSR bytes (values, column
+                     # indices, row pointers, p, q): what an index-carrying format moves
+                     "csr_canonical_bytes_per_launch": bytes_spmv("csr", n, nnz, 8),
+                     "frac_csr_canonical": round(bytes_spmv("csr", n, nnz, 8)
+                                                 / (spmv_avg_us * 1e-6) / 1e9 / PEAK_HBM_GBS, 4)},
         "pressure_kernels": kern,
         "mixed": mixed,
         "operator_setup": setup,
         "isotropic_pressure": isotropic,
         "velocity_preconditioners": precond,
+        "small_box": small_box,
         "bricks_q2_q1": bricks,
         "time_loop": loop,
         "batched": batched,

@@ -844,20 +844,27 @@ __global__ __launch_bounds__(kBlock) void k_init_dir(int64_t n, TX *__restrict__
 
 // Thomas recurrences of the columns staged in LDS: sr holds r (read), se, sw
 // the factors, sy receives z; returns this lane's share of r^T z.
-__device__ __forceinline__ double line_columns(int ncols, int L, const double *sr,
-                                               const double *se, const double *sw, double *sy)
+// The four arrays are disjoint regions of the block's LDS (restrict lets the
+// loads of later steps, which do not depend on the recurrence, issue ahead of
+// the earlier steps' stores; the unrolled loops give them room to).
+__device__ __forceinline__ double line_columns(int ncols, int L, const double *__restrict__ sr,
+                                               const double *__restrict__ se,
+                                               const double *__restrict__ sw,
+                                               double *__restrict__ sy)
 {
     double rz = 0.0;
     if ((int)threadIdx.x < ncols) {
         const int b = threadIdx.x * L;
         double y = sr[b] * sw[b];
         sy[b] = y;
+#pragma unroll 4
         for (int k = 1; k < L; ++k) {
             y = (sr[b + k] - se[b + k - 1] * y) * sw[b + k];
             sy[b + k] = y;
         }
         double z = y;
         rz += sr[b + L - 1] * z;
+#pragma unroll 4
         for (int k = L - 2; k >= 0; --k) {
             z = sy[b + k] - (se[b + k] * sw[b + k]) * z;
             sy[b + k] = z;
