@@ -296,6 +296,15 @@ int hns_operator_line_len(const hns_operator *op);
  *                  (default 3; integers 1..64).  The three change the grid
  *                  (and with it the summation order of the dot products),
  *                  not the arithmetic of a row or a pack.
+ *   "small_n"      point-Jacobi FP64 / FP32 single right-hand-side solves of
+ *                  operators with at most this many rows run each chunk of
+ *                  iterations in one workgroup (one launch per chunk instead
+ *                  of three per iteration; the same recurrence and stopping
+ *                  rule, dot products summed over 1024 threads instead of
+ *                  per-block partials); default 4096 (measured crossover:
+ *                  about 12 against 26 us per iteration at 1445 rows, 35
+ *                  against 19 at 6875), 0 = never, at most 1048576.  Not
+ *                  used while per-kernel timing is enabled.
  *   "precond"      0 = point Jacobi, the inverse diagonal (default; the
  *                  diagonal preconditioner of the paper's Sec. 5 remarks);
  *                  1 = vertical-line blocks: the inverse of the tridiagonal

@@ -151,6 +151,7 @@ struct hns_operator {
     int8_t *inc_loc = nullptr;
     // tunables
     int check_every = 32;
+    int64_t small_n = 4096;       // single-workgroup CG chunks up to this many rows (0: never)
     double inner_tol = 1e-5;
     int max_outer = 30;
     int mixed_variant = 0;        // 0 FP32 + replacement, 1 restarted refinement,

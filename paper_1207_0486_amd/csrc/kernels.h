@@ -94,6 +94,13 @@ struct IterArgs {
 // ev (optional, 6 events) brackets the three kernels for timing.
 hns_status launch_iteration(const IterArgs &a, int parity, hipStream_t s, hipEvent_t *ev);
 
+// `count` point-Jacobi CG iterations of a small system (n <= kSmallMaxN) in
+// one workgroup: the same recurrence, device scalars and stop rule as
+// `count` launch_iteration calls, with block barriers in place of the kernel
+// boundaries (latency-bound sizes).  FP64 or FP32 (prec F64 / F32) only.
+constexpr int64_t kSmallMaxN = 1 << 20;
+hns_status launch_cg_small(const IterArgs &a, int parity, int count, hipStream_t s);
+
 // q = mask(A p) without reductions (residuals and hns_apply)
 hns_status launch_spmv_plain(const DevMatrix &A, bool fp32, const void *p, void *q,
                              const uint8_t *bc, int bit, hipStream_t s);

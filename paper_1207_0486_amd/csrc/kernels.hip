@@ -1656,6 +1656,187 @@ hns_status launch_init_ic0(int64_t n, const IC0Dev &F, const double *r, double *
     return check_launch("init_ic0");
 }
 
+// ---------------------------------------------------------------------------
+// Small systems: a chunk of CG iterations in one workgroup
+// ---------------------------------------------------------------------------
+constexpr int kSmallBlock = 1024;
+
+// The operator as the small kernel reads it (passed by value)
+struct SmallMat {
+    int64_t n;
+    uint32_t fmt;
+    int ndiag;
+    int32_t off[kMaxDiagWide];
+    const int32_t *rowptr, *col;       // CSR
+    const int32_t *slice_ptr, *scol;   // sliced ELL
+};
+
+// Sum over the 16 wavefronts of the workgroup; every thread reads the 16
+// wave sums in the same order, so all obtain bit-identical totals.
+template <int NV>
+__device__ __forceinline__ void small_block_sum(double (&v)[NV], double *lds)
+{
+    constexpr int NW = kSmallBlock / 64;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = wave_sum(v[k]);
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) lds[k * NW + wid] = v[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        double t = 0.0;
+        for (int w = 0; w < NW; ++w) t += lds[k * NW + w];
+        v[k] = t;
+    }
+    __syncthreads();
+}
+
+// Row i of A p: diagonal storage in the order main, (upper, lower) per offset
+// (as the multi-block kernels); sliced ELL and CSR in storage order.
+template <typename TV, typename TX>
+__device__ __forceinline__ TX small_row(const SmallMat &A, const TV *__restrict__ vals,
+                                        const TX *__restrict__ p, int64_t i)
+{
+    const int64_t n = A.n;
+    if (A.fmt == HNS_FMT_SDIA) {
+        TX sum = (TX)vals[i] * p[i];
+        for (int k = 0; k < A.ndiag; ++k) {
+            const int64_t o = A.off[k];
+            const TV *u = vals + (int64_t)(k + 1) * n;
+            if (i + o < n) sum += (TX)u[i] * p[i + o];
+            if (i >= o) sum += (TX)u[i - o] * p[i - o];
+        }
+        return sum;
+    }
+    TX sum = 0;
+    if (A.fmt == HNS_FMT_SELL) {
+        const int64_t sl = i >> 6;
+        const int l = (int)(i & 63);
+        const int32_t beg = A.slice_ptr[sl];
+        const int32_t w = (A.slice_ptr[sl + 1] - beg) >> 6;
+        for (int j = 0; j < w; ++j) sum += (TX)vals[beg + 64 * j + l] * p[A.scol[beg + 64 * j + l]];
+        return sum;
+    }
+    for (int32_t k = A.rowptr[i]; k < A.rowptr[i + 1]; ++k) sum += (TX)vals[k] * p[A.col[k]];
+    return sum;
+}
+
+// `count` iterations; each thread keeps the rows i = t, t + 1024, ... in all
+// three phases, so only the product's reads of p at neighbouring rows need
+// the barrier at the end of an iteration.  Per element the arithmetic is
+// that of k_update and k_pupdate_x.
+template <typename TV, typename TX, typename TD>
+__global__ __launch_bounds__(kSmallBlock) void k_cg_small(SmallMat A, const TV *__restrict__ vals,
+                                                          TX *__restrict__ x, TX *__restrict__ r,
+                                                          TX *__restrict__ p, TX *__restrict__ q,
+                                                          const TD *__restrict__ dinv,
+                                                          const uint8_t *__restrict__ bc, int bit,
+                                                          Scalars *__restrict__ sc, int count,
+                                                          int parity)
+{
+    __shared__ double lds[2 * (kSmallBlock / 64)];
+    if (sc->stop) return;
+    const int64_t n = A.n;
+    double rho[2] = {sc->rho[0], sc->rho[1]};
+    double gamma = sc->gamma, alpha_d = sc->alpha, beta_d = sc->beta, rr = sc->rr;
+    const double limit = sc->tol2 * sc->bb;
+    int stop = 0, done = 0;
+    for (int it = 0; it < count; ++it) {
+        double v1[1] = {0.0};
+        for (int64_t i = threadIdx.x; i < n; i += kSmallBlock) {
+            TX sum = small_row<TV, TX>(A, vals, p, i);
+            if (is_dirichlet(bc, bit, i)) sum = 0;
+            q[i] = sum;
+            v1[0] += (double)p[i] * (double)sum;
+        }
+        small_block_sum<1>(v1, lds);
+        gamma = v1[0];
+        if (!(gamma > 0.0) || !isfinite(gamma)) {
+            stop = 2;
+            break;
+        }
+        alpha_d = rho[parity] / gamma;
+        const TX alpha = (TX)alpha_d;
+        double v2[2] = {0.0, 0.0};
+        for (int64_t i = threadIdx.x; i < n; i += kSmallBlock) {
+            const TX ri = r[i] - alpha * q[i];
+            r[i] = ri;
+            const TX zi = (TX)dinv[i] * ri;
+            v2[0] += (double)ri * (double)zi;
+            v2[1] += (double)ri * (double)ri;
+        }
+        small_block_sum<2>(v2, lds);
+        const double rho_new = v2[0];
+        rr = v2[1];
+        const bool bad = !isfinite(rho_new) || !isfinite(rr);
+        const bool conv = !bad && rr <= limit;
+        beta_d = rho_new / rho[parity];
+        const TX beta = (TX)beta_d;
+        const bool dir = !(bad || conv);
+        for (int64_t i = threadIdx.x; i < n; i += kSmallBlock) {
+            const TX pi = p[i];
+            x[i] = x[i] + alpha * pi;
+            if (dir) p[i] = (TX)dinv[i] * r[i] + beta * pi;
+        }
+        rho[parity ^ 1] = rho_new;
+        parity ^= 1;
+        ++done;
+        if (!dir) {
+            stop = bad ? 2 : 1;
+            break;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        sc->rho[0] = rho[0];
+        sc->rho[1] = rho[1];
+        sc->gamma = gamma;
+        sc->alpha = alpha_d;
+        sc->beta = beta_d;
+        sc->rr = rr;
+        sc->iter += done;
+        if (stop) sc->stop = stop;
+    }
+}
+
+hns_status launch_cg_small(const IterArgs &a, int parity, int count, hipStream_t s)
+{
+    const DevMatrix &M = *a.A;
+    if (a.n > kSmallMaxN || (a.prec != Prec::F64 && a.prec != Prec::F32) || a.lfac || a.ic) {
+        set_error("launch_cg_small: unsupported configuration");
+        return HNS_ERR_INVALID;
+    }
+    SmallMat A{};
+    A.n = M.n;
+    A.fmt = M.fmt;
+    A.ndiag = M.fmt == HNS_FMT_SDIA ? M.ndiag : 0;
+    for (int k = 0; k < kMaxDiagWide; ++k) A.off[k] = k < A.ndiag ? M.off[k] : 0;
+    A.rowptr = M.rowptr;
+    A.col = M.col;
+    A.slice_ptr = M.slice_ptr;
+    A.scol = M.scol;
+    const uint8_t *bc = a.bit < 0 ? nullptr : a.bc;
+    if (a.prec == Prec::F64) {
+        const double *v = M.fmt == HNS_FMT_SDIA ? M.dia : M.fmt == HNS_FMT_SELL ? M.sval : M.val;
+        k_cg_small<double, double, double><<<1, kSmallBlock, 0, s>>>(
+            A, v, (double *)a.x, (double *)a.r, (double *)a.p, (double *)a.q,
+            (const double *)a.dinv, bc, a.bit, a.sc, count, parity & 1);
+    } else {
+        const float *v = M.fmt == HNS_FMT_SDIA ? M.dia32 : M.fmt == HNS_FMT_SELL ? M.sval32 : M.val32;
+        if (!v) {
+            set_error("launch_cg_small: FP32 values not kept");
+            return HNS_ERR_INVALID;
+        }
+        k_cg_small<float, float, float><<<1, kSmallBlock, 0, s>>>(
+            A, v, (float *)a.x, (float *)a.r, (float *)a.p, (float *)a.q, (const float *)a.dinv,
+            bc, a.bit, a.sc, count, parity & 1);
+    }
+    return check_launch("small-system cg chunk");
+}
+
 hns_status launch_iteration(const IterArgs &a, int parity, hipStream_t s, hipEvent_t *ev)
 {
     if (a.ic) {

@@ -214,6 +214,11 @@ static hns_status enqueue_iterations(hns_operator *op, Workspace *w, Prec prec, 
         a.z = w->z;
         a.y = w->y;
     }
+    // latency-bound sizes: the whole chunk in one workgroup (point Jacobi,
+    // FP64 or FP32, not while per-kernel timing is on)
+    if (!lfac && !ic && period <= 0 && op->n <= op->small_n &&
+        (prec == Prec::F64 || prec == Prec::F32))
+        return launch_cg_small(a, parity0, count, s);
     for (int it = 0; it < count; ++it) {
         const bool timed = period > 0 && (it % period) == 0;
         if (++w->token == 0) w->token = 1;   // unique per workspace, never 0
@@ -942,6 +947,9 @@ hns_status hns_set_param(hns_operator *op, const char *name, double value)
         op->A.spmv_it32 = (int)value;
     } else if (k == "vec_it" && value >= 1 && value <= 64 && value == (int)value) {
         op->A.vec_it = (int)value;
+    } else if (k == "small_n" && value >= 0 && value <= (double)kSmallMaxN &&
+               value == (int64_t)value) {
+        op->small_n = (int64_t)value;
     } else if (k == "precond" && (value == 0 || value == 1 || value == 2)) {
         if (value == 2 && op->host_A.col.empty()) {
             set_error("precond = 2 (IC(0)) needs an operator assembled with HNS_KEEP_HOST");

@@ -1,0 +1,113 @@
+"""The single-workgroup CG chunk for latency-bound sizes against the
+multi-launch iteration (tunable small_n = 0) and the oracle: same recurrence,
+so the same iteration counts (within one) and answers to rounding."""
+import numpy as np
+import pytest
+
+import basin
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1207_0486_amd import hns  # noqa: F401
+    return torch.device("cuda", 0)
+
+
+def _gpu(a, dev):
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device=dev)
+
+
+def _rel(x, ref):
+    return float(np.linalg.norm(x - ref) / np.linalg.norm(ref))
+
+
+FORCE_SMALL, DEFAULT_SMALL = 1 << 20, 4096
+
+
+def _both(op, b, dev, **kw):
+    """(single-workgroup chunk, multi-launch) answers of the same solve."""
+    out = []
+    for small in (FORCE_SMALL, 0):
+        op.set_param("small_n", small)
+        x, info = op.solve(_gpu(b, dev), **kw)
+        out.append((x.cpu().numpy(), info))
+    op.set_param("small_n", DEFAULT_SMALL)
+    return out
+
+
+@pytest.mark.parametrize("fmt", ["auto", "csr", "sell"])
+@pytest.mark.parametrize("bit", [-1, 0, 2])
+def test_small_chunk_matches_multi_launch_and_oracle(dev, fmt, bit):
+    """Box 16x16x4 (the small plain-method case) and a 20x16x5 basin:
+    Dirichlet sets and the pure-Neumann pressure problem, in each storage."""
+    from paper_1207_0486_amd.hns import Operator
+    for m, nu in ((basin.box_mesh(16, 16, 4, gamma0=basin.mesh.WALLS), (1.0, 1e-4)),
+                  (basin.basin_mesh(20, 16, 5, seed=3), (1e3, 1e-2))):
+        kind = "poisson" if bit < 0 else "helmholtz"
+        op = Operator(m, nu[0], nu[1], 3600.0 if kind == "helmholtz" else 0.0, kind=kind, fmt=fmt)
+        d = None if bit < 0 else ((m.bc >> bit) & 1) == 1
+        b = basin.normal_rhs(m.n, 5 + bit, dirichlet=d, zero_mean=bit < 0)
+        (xs, i_s), (xm, i_m) = _both(op, b, dev, tol=1e-10, mask_bit=bit)
+        assert i_s.status == 0 and i_m.status == 0
+        assert abs(i_s.iterations - i_m.iterations) <= 1
+        assert _rel(xs, xm) <= 1e-9
+        A = (oracle.helmholtz(m, nu[0], nu[1], 3600.0) if kind == "helmholtz"
+             else oracle.stiffness(m, nu[0], nu[1]))
+        if bit >= 0:
+            assert oracle.relres(A, b, xs, d) <= 1.01e-10
+            same = oracle.pcg(A, b, dirichlet=d, tol=1e-300, maxit=i_s.iterations)
+            assert _rel(xs, same.x) <= 1e-10
+        else:
+            w = oracle.mass(m).matvec(np.ones(m.n))
+            ref = oracle.pcg(A, b, singular=True, weights=w, tol=1e-10)
+            assert abs(i_s.iterations - ref.iterations) <= max(1, 0.02 * ref.iterations)
+            assert _rel(xs, ref.x) <= 1e-8
+            assert abs(w @ xs) <= 1e-12 * np.abs(w).sum() * np.abs(xs).max()
+        op.close()
+
+
+def test_small_chunk_cap_zero_rhs_and_mixed(dev):
+    from paper_1207_0486_amd.hns import Operator
+    m = basin.basin_mesh(16, 12, 4, seed=2)
+    op = Operator(m, 1e3, 1e-2, 3600.0, keep_fp32=True)
+    d = (m.bc & 1) == 1
+    b = basin.normal_rhs(m.n, 9, dirichlet=d)
+    A = oracle.helmholtz(m, 1e3, 1e-2, 3600.0)
+    # iteration cap: the last iterate equals the oracle's iterate after 7 steps
+    (xs, i_s), (xm, i_m) = _both(op, b, dev, tol=1e-14, max_iter=7, mask_bit=0, check=False)
+    assert i_s.status == 1 and i_s.iterations == 7 and i_m.iterations == 7
+    same = oracle.pcg(A, b, dirichlet=d, tol=1e-300, maxit=7)
+    assert _rel(xs, same.x) <= 1e-12 and _rel(xm, same.x) <= 1e-12
+    # b = 0: x = 0 after no iteration
+    x, info = op.solve(_gpu(np.zeros(m.n), dev), x=_gpu(np.ones(m.n), dev), mask_bit=0)
+    assert info.status == 0 and info.iterations == 0 and float(x.abs().max()) == 0.0
+    # mixed precision through the FP32 chunk kernel
+    ref = oracle.pcg(A, b, dirichlet=d, tol=1e-13).x
+    for small in (FORCE_SMALL, 0):
+        op.set_param("small_n", small)
+        x, info = op.solve(_gpu(b, dev), tol=1e-10, mask_bit=0, mode="mixed")
+        assert info.status == 0
+        assert _rel(x.cpu().numpy(), ref) <= 1e-9
+
+
+@pytest.mark.parametrize("n_side", [(15, 15, 15), (31, 31, 15), (32, 32, 15)])
+def test_small_chunk_at_larger_sizes(dev, n_side):
+    """The chunk kernel forced on 4096, 16384 and 17424 rows (4 to 18 rows
+    per thread): the same answers as the multi-launch path."""
+    from paper_1207_0486_amd.hns import Operator
+    m = basin.box_mesh(*n_side, gamma0=basin.mesh.WALLS)
+    op = Operator(m, 1.0, 1e-4, kind="poisson")
+    d = (m.bc & 1) == 1
+    b = basin.normal_rhs(m.n, 4, dirichlet=d)
+    (xs, i_s), (xm, i_m) = _both(op, b, dev, tol=1e-10, mask_bit=0)
+    assert i_s.status == 0 and abs(i_s.iterations - i_m.iterations) <= 1
+    assert _rel(xs, xm) <= 1e-9
+    A = oracle.stiffness(m, 1.0, 1e-4)
+    assert oracle.relres(A, b, xs, d) <= 1.01e-10
