@@ -432,22 +432,26 @@ def bench_preconditioners(torch, log, m, b_vel, reps=3):
         op.close()
         out[name] = res
         log(f"preconditioners {name}: {res}")
-    # the workload's (anisotropic) pressure operator: point Jacobi against line blocks
-    op = Operator(m, wl.nu_h, wl.nu_v, kind="poisson")
+    # the workload's (anisotropic) pressure operator: point Jacobi against line
+    # blocks, FP64 and mixed (FP32 CG with FP64 residual replacement)
+    op = Operator(m, wl.nu_h, wl.nu_v, kind="poisson", keep_fp32=True)
+    op.set_param("replace_drop", 0.1)
     b_q = torch.as_tensor(basin.normal_rhs(m.n, 21, zero_mean=True), device=b_vel.device)
     res = {}
-    for pre, label in ((0, "jacobi"), (1, "line")):
+    for pre, mode, label in ((0, "fp64", "jacobi"), (1, "fp64", "line"),
+                             (0, "mixed", "jacobi_mixed"), (1, "mixed", "line_mixed")):
         op.set_param("precond", pre)
         best, info = None, None
         for rep in range(2):
             x = torch.zeros_like(b_q)
             torch.cuda.synchronize()
             t = time.perf_counter()
-            x, info = op.solve(b_q, x, tol=1e-10, check=False)
+            x, info = op.solve(b_q, x, tol=1e-10, mode=mode, check=False)
             torch.cuda.synchronize()
             el = time.perf_counter() - t
             best = el if best is None else min(best, el)
         res[label] = {"ms": round(1e3 * best, 3), "iterations": info.iterations,
+                      "replacements": info.outer_iterations,
                       "status": info.status, "relres": float("%.3g" % info.relres_true)}
     op.close()
     out["pressure_workload"] = {"rhs": "N(0,1), seed 21, zero mean", **res}

@@ -316,8 +316,10 @@ int hns_operator_line_len(const hns_operator *op);
  *                  keeps CG's iteration count bounded on thin meshes whose
  *                  vertical couplings dwarf the horizontal ones, e.g. the
  *                  isotropic pressure operator of eq. fofa_q_cor_h.
- *                  Needs hns_operator_line_len >= 2; HNS_FP64 single
- *                  right-hand-side solves only (HNS_ERR_INVALID otherwise).
+ *                  Needs hns_operator_line_len >= 2; single right-hand
+ *                  sides, HNS_FP64 or HNS_MIXED with mixed_variant 0 (FP32
+ *                  factors, 2 n floats per set, in the FP32 iterations);
+ *                  HNS_ERR_INVALID otherwise.
  *                  2 = incomplete Cholesky IC(0) (the velocity-system
  *                  preconditioner of the paper's Sec. 5 remarks) in a greedy
  *                  multicolour order: nodes coloured in node order with the

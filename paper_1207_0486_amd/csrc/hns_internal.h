@@ -181,6 +181,8 @@ struct hns_operator {
     std::mutex line_mutex;
     double *line_fac[9] = {nullptr, nullptr, nullptr, nullptr, nullptr,
                            nullptr, nullptr, nullptr, nullptr};
+    float *line_fac32[9] = {nullptr, nullptr, nullptr, nullptr, nullptr,
+                            nullptr, nullptr, nullptr, nullptr};   // FP32 copies (mixed)
     // IC(0) preconditioner (precond = 2): host copy of the assembled matrix
     // (kept with HNS_KEEP_HOST) and the device factors per mask (index bit + 1)
     hns::HostCSR host_A;

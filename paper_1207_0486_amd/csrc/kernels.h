@@ -69,8 +69,8 @@ struct IterArgs {
     // vertical-line preconditioner (FP64 only): when lfac is set, z = M^-1 r
     // by the column blocks of `line_len` consecutive rows; lfac holds the
     // masked off-diagonal (n) then the inverse pivots (n); z is an n-vector
-    const double *lfac = nullptr;
-    double *z = nullptr;
+    const void *lfac = nullptr;     // double (FP64) or float (F32) factors
+    void *z = nullptr;              // z in the precision of the iteration
     int line_len = 0;
     // IC(0) preconditioner (FP64 only): when ic is set, z = M^-1 r by the
     // colour-by-colour triangular solves; y is an n-vector of scratch
@@ -126,11 +126,20 @@ hns_status launch_init_dir(int64_t n, Prec prec, void *r, void *p, const void *d
 int line_cols_per_block(int line_len);
 int line_grid(int64_t n, int line_len);
 
-// Line-preconditioned first direction (FP64): (singular: r -= mean r);
-// z = M^-1 r; p = z; rho[0] = r^T z; rr = r^T r (and bb = rr if asked).
+// Line-preconditioned first direction (FP64, or FP32 for the inner
+// iterations of mixed precision): (singular: r -= mean r); z = M^-1 r; p = z;
+// rho[0] = r^T z; rr = r^T r (and bb = rr if asked).
 hns_status launch_init_line(int64_t n, int line_len, double *r, double *p, const double *lfac,
                             bool singular, bool bb_from_rr, Scalars *sc, double *partials,
                             hipStream_t s);
+hns_status launch_init_line(int64_t n, int line_len, float *r, float *p, const float *lfac,
+                            bool singular, bool bb_from_rr, Scalars *sc, double *partials,
+                            hipStream_t s);
+// Residual replacement of a line-preconditioned FP32 segment: r = (float) r64,
+// z = M^-1 r, then rho' = r^T z, beta = rho' / rho[parity], p = z + beta p.
+hns_status launch_replace_line(int64_t n, int line_len, const double *r64, float *r, float *z,
+                               float *p, const float *lfac, Scalars *sc, double *partials,
+                               int parity, int vec_it, hipStream_t s);
 
 // IC(0) first direction (FP64): z = M^-1 r; p = z; rho[0] = r^T z; rr = r^T r.
 hns_status launch_init_ic0(int64_t n, const IC0Dev &F, const double *r, double *p, double *z,

@@ -847,45 +847,52 @@ __global__ __launch_bounds__(kBlock) void k_init_dir(int64_t n, TX *__restrict__
 // The four arrays are disjoint regions of the block's LDS (restrict lets the
 // loads of later steps, which do not depend on the recurrence, issue ahead of
 // the earlier steps' stores; the unrolled loops give them room to).
-__device__ __forceinline__ double line_columns(int ncols, int L, const double *__restrict__ sr,
-                                               const double *__restrict__ se,
-                                               const double *__restrict__ sw,
-                                               double *__restrict__ sy)
+// T = double (FP64 solves) or float (the inner iterations of mixed precision;
+// r^T z is always summed in FP64).
+template <typename T>
+__device__ __forceinline__ double line_columns(int ncols, int L, const T *__restrict__ sr,
+                                               const T *__restrict__ se,
+                                               const T *__restrict__ sw, T *__restrict__ sy)
 {
     double rz = 0.0;
     if ((int)threadIdx.x < ncols) {
         const int b = threadIdx.x * L;
-        double y = sr[b] * sw[b];
+        T y = sr[b] * sw[b];
         sy[b] = y;
 #pragma unroll 4
         for (int k = 1; k < L; ++k) {
             y = (sr[b + k] - se[b + k - 1] * y) * sw[b + k];
             sy[b + k] = y;
         }
-        double z = y;
-        rz += sr[b + L - 1] * z;
+        T z = y;
+        rz += (double)sr[b + L - 1] * (double)z;
 #pragma unroll 4
         for (int k = L - 2; k >= 0; --k) {
             z = sy[b + k] - (se[b + k] * sw[b + k]) * z;
             sy[b + k] = z;
-            rz += sr[b + k] * z;
+            rz += (double)sr[b + k] * (double)z;
         }
     }
     return rz;
 }
 
-template <int W>
+template <typename T, int W>
 struct XLinePacks {
-    Pack<double, W> p, z, x;
+    Pack<T, W> p, z, x;
+};
+
+template <typename T, int W>
+struct LinePacks {
+    Pack<T, W> p, z;
 };
 
 // r -= alpha q; z = M^-1 r; partials of r^T z and r^T r.  Block 0 records
 // alpha and the iteration tag (x += alpha p is done by k_pupdate_line_x).
+template <typename T>
 __global__ __launch_bounds__(kBlock) void k_update_line(
-    int64_t n, int L, int NC, double *__restrict__ r, const double *__restrict__ q,
-    double *__restrict__ z, const double *__restrict__ lfac, Scalars *__restrict__ sc,
-    const double *__restrict__ part_in, int G_in, double *__restrict__ part_out, int parity,
-    uint32_t token)
+    int64_t n, int L, int NC, T *__restrict__ r, const T *__restrict__ q, T *__restrict__ z,
+    const T *__restrict__ lfac, Scalars *__restrict__ sc, const double *__restrict__ part_in,
+    int G_in, double *__restrict__ part_out, int parity, uint32_t token)
 {
     if (sc->stop) return;
     extern __shared__ double line_lds[];
@@ -899,30 +906,31 @@ __global__ __launch_bounds__(kBlock) void k_update_line(
         }
         return;
     }
-    const double alpha = sc->rho[parity] / gamma;
+    const double alpha_d = sc->rho[parity] / gamma;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         sc->gamma = gamma;
-        sc->alpha = alpha;
+        sc->alpha = alpha_d;
         sc->xtoken = token;
     }
+    const T alpha = (T)alpha_d;
     const int span = NC * L;
-    double *sr = line_lds, *se = sr + span, *sw = se + span, *sy = sw + span;
+    T *sr = reinterpret_cast<T *>(line_lds), *se = sr + span, *sw = se + span, *sy = sw + span;
     const int64_t row0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * span;
     const int64_t left = n - row0;
     const int rows = left <= 0 ? 0 : (left < span ? (int)left : span);
-    const double *le = lfac, *lw = lfac + n;
+    const T *le = lfac, *lw = lfac + n;
     double rr = 0.0;
     for (int t = threadIdx.x; t < rows; t += kBlock) {
         const int64_t i = row0 + t;
-        const double ri = r[i] - alpha * q[i];
+        const T ri = r[i] - alpha * q[i];
         r[i] = ri;
         sr[t] = ri;
         se[t] = le[i];
         sw[t] = lw[i];
-        rr += ri * ri;
+        rr += (double)ri * (double)ri;
     }
     __syncthreads();
-    const double rz = line_columns(rows / L, L, sr, se, sw, sy);
+    const double rz = line_columns<T>(rows / L, L, sr, se, sw, sy);
     __syncthreads();
     for (int t = threadIdx.x; t < rows; t += kBlock) z[row0 + t] = sy[t];
     double v[2] = {rz, rr};
@@ -934,22 +942,21 @@ __global__ __launch_bounds__(kBlock) void k_update_line(
 // tag is recorded), x += alpha p with the old p; then rho' = r^T z, rr = r^T r
 // from the partials, beta = rho'/rho and, unless converged or broken down,
 // p = z + beta p.
-template <int V>
+template <typename T, int V>
 __global__ __launch_bounds__(kBlock) void k_pupdate_line_x(int64_t n, int64_t per,
-                                                           double *__restrict__ x,
-                                                           double *__restrict__ p,
-                                                           const double *__restrict__ z,
+                                                           T *__restrict__ x, T *__restrict__ p,
+                                                           const T *__restrict__ z,
                                                            Scalars *__restrict__ sc,
                                                            const double *__restrict__ part_in,
                                                            int G_in, int parity, uint32_t token)
 {
     if (sc->xtoken != token) return;
-    const double alpha = sc->alpha;
-    double beta = 0.0;
+    const T alpha = (T)sc->alpha;
+    T beta = 0;
     bool dir = true;
     auto load = [&](int64_t i, auto w) {
         constexpr int W = decltype(w)::value;
-        return XLinePacks<W>{ld<W>(p, i), ld<W>(z, i), ld<W>(x, i)};
+        return XLinePacks<T, W>{ld<W>(p, i), ld<W>(z, i), ld<W>(x, i)};
     };
     auto prologue = [&]() {
         double v[2];
@@ -957,22 +964,23 @@ __global__ __launch_bounds__(kBlock) void k_pupdate_line_x(int64_t n, int64_t pe
         const double rho_new = v[0], rr = v[1];
         const bool bad = !isfinite(rho_new) || !isfinite(rr);
         const bool conv = !bad && rr <= sc->tol2 * sc->bb;
-        beta = rho_new / sc->rho[parity];
+        const double beta_d = rho_new / sc->rho[parity];
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             sc->rho[parity ^ 1] = rho_new;
             sc->rr = rr;
-            sc->beta = beta;
+            sc->beta = beta_d;
             sc->iter += 1;
             if (bad)
                 sc->stop = 2;
             else if (conv)
                 sc->stop = 1;
         }
+        beta = (T)beta_d;
         dir = !(bad || conv);
         return true;
     };
     auto body = [&](int64_t i, auto in) {
-        constexpr int W = sizeof(in.p.v) / sizeof(double);
+        constexpr int W = sizeof(in.p.v) / sizeof(T);
 #pragma unroll
         for (int e = 0; e < W; ++e) in.x.v[e] = in.x.v[e] + alpha * in.p.v[e];
         st<W>(x, i, in.x);
@@ -986,26 +994,25 @@ __global__ __launch_bounds__(kBlock) void k_pupdate_line_x(int64_t n, int64_t pe
 }
 
 // (singular: r -= mean r); z = M^-1 r; p = z; rho[0] = r^T z; rr = r^T r.
+template <typename T>
 __global__ __launch_bounds__(kBlock) void k_init_line(int64_t n, int L, int NC,
-                                                      double *__restrict__ r,
-                                                      double *__restrict__ p,
-                                                      const double *__restrict__ lfac,
-                                                      int singular, int bb_from_rr,
-                                                      Scalars *__restrict__ sc,
+                                                      T *__restrict__ r, T *__restrict__ p,
+                                                      const T *__restrict__ lfac, int singular,
+                                                      int bb_from_rr, Scalars *__restrict__ sc,
                                                       double *__restrict__ partials)
 {
     extern __shared__ double line_lds[];
-    const double mean = singular ? sc->sum_r / (double)n : 0.0;
+    const T mean = singular ? (T)(sc->sum_r / (double)n) : (T)0;
     const int span = NC * L;
-    double *sr = line_lds, *se = sr + span, *sw = se + span, *sy = sw + span;
+    T *sr = reinterpret_cast<T *>(line_lds), *se = sr + span, *sw = se + span, *sy = sw + span;
     const int64_t row0 = (int64_t)blockIdx.x * span;
     const int64_t left = n - row0;
     const int rows = left <= 0 ? 0 : (left < span ? (int)left : span);
-    const double *le = lfac, *lw = lfac + n;
+    const T *le = lfac, *lw = lfac + n;
     double rr = 0.0;
     for (int t = threadIdx.x; t < rows; t += kBlock) {
         const int64_t i = row0 + t;
-        double ri = r[i];
+        T ri = r[i];
         if (singular) {
             ri -= mean;
             r[i] = ri;
@@ -1013,10 +1020,10 @@ __global__ __launch_bounds__(kBlock) void k_init_line(int64_t n, int L, int NC,
         sr[t] = ri;
         se[t] = le[i];
         sw[t] = lw[i];
-        rr += ri * ri;
+        rr += (double)ri * (double)ri;
     }
     __syncthreads();
-    const double rz = line_columns(rows / L, L, sr, se, sw, sy);
+    const double rz = line_columns<T>(rows / L, L, sr, se, sw, sy);
     __syncthreads();
     for (int t = threadIdx.x; t < rows; t += kBlock) p[row0 + t] = sy[t];
     double v[2] = {rz, rr};
@@ -1032,6 +1039,86 @@ __global__ __launch_bounds__(kBlock) void k_init_line(int64_t n, int L, int NC,
         else
             sc->stop = (v[1] <= sc->tol2 * sc->bb) ? 1 : 0;
     }
+}
+
+// Residual replacement of a line-preconditioned mixed-precision segment: the
+// FP32 residual becomes the FP64 true residual r64 (cast), z = M^-1 r, and the
+// partials of r^T z and r^T r feed k_pdir_line (the counterpart of
+// k_replace_rz for point Jacobi).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_replace_line(int64_t n, int L, int NC,
+                                                         const double *__restrict__ r64,
+                                                         T *__restrict__ r, T *__restrict__ z,
+                                                         const T *__restrict__ lfac,
+                                                         double *__restrict__ part_out)
+{
+    extern __shared__ double line_lds[];
+    const int span = NC * L;
+    T *sr = reinterpret_cast<T *>(line_lds), *se = sr + span, *sw = se + span, *sy = sw + span;
+    const int64_t row0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * span;
+    const int64_t left = n - row0;
+    const int rows = left <= 0 ? 0 : (left < span ? (int)left : span);
+    const T *le = lfac, *lw = lfac + n;
+    double rr = 0.0;
+    for (int t = threadIdx.x; t < rows; t += kBlock) {
+        const int64_t i = row0 + t;
+        const T ri = (T)r64[i];
+        r[i] = ri;
+        sr[t] = ri;
+        se[t] = le[i];
+        sw[t] = lw[i];
+        rr += (double)ri * (double)ri;
+    }
+    __syncthreads();
+    const double rz = line_columns<T>(rows / L, L, sr, se, sw, sy);
+    __syncthreads();
+    for (int t = threadIdx.x; t < rows; t += kBlock) z[row0 + t] = sy[t];
+    double v[2] = {rz, rr};
+    store_block_partials<2>(v, part_out);
+}
+
+// rho' = r^T z, rr = r^T r from the partials, beta = rho' / rho, p = z + beta p
+// unless the recursive residual is already below the segment threshold (no
+// iteration is counted: the direction after a residual replacement)
+template <typename T, int V>
+__global__ __launch_bounds__(kBlock) void k_pdir_line(int64_t n, int64_t per, T *__restrict__ p,
+                                                      const T *__restrict__ z,
+                                                      Scalars *__restrict__ sc,
+                                                      const double *__restrict__ part_in,
+                                                      int G_in, int parity)
+{
+    if (sc->stop) return;
+    T beta = 0;
+    auto load = [&](int64_t i, auto w) {
+        constexpr int W = decltype(w)::value;
+        return LinePacks<T, W>{ld<W>(p, i), ld<W>(z, i)};
+    };
+    auto prologue = [&]() {
+        double v[2];
+        load_reduced<2>(part_in, G_in, v);
+        const double rho_new = v[0], rr = v[1];
+        const bool bad = !isfinite(rho_new) || !isfinite(rr);
+        const bool conv = !bad && rr <= sc->tol2 * sc->bb;
+        const double beta_d = rho_new / sc->rho[parity];
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            sc->rho[parity ^ 1] = rho_new;
+            sc->rr = rr;
+            sc->beta = beta_d;
+            if (bad)
+                sc->stop = 2;
+            else if (conv)
+                sc->stop = 1;
+        }
+        beta = (T)beta_d;
+        return !(bad || conv);
+    };
+    auto body = [&](int64_t i, auto in) {
+        constexpr int W = sizeof(in.p.v) / sizeof(T);
+#pragma unroll
+        for (int e = 0; e < W; ++e) in.p.v[e] = in.z.v[e] + beta * in.p.v[e];
+        st<W>(p, i, in.p);
+    };
+    for_packs_ahead<V>(n, per, load, prologue, body);
 }
 
 // ---------------------------------------------------------------------------
@@ -1453,24 +1540,29 @@ constexpr int kLineLds = 49152;   // bytes of LDS for the staged columns of one 
 // k_pupdate_line_x over the n rows: p and z are workspace vectors (16-byte
 // aligned), x may be a row of a caller's array at an 8-byte offset, in which
 // case one element per thread.  G_in: number of update partials.
+template <typename T>
 hns_status launch_pupdate_line_x(const IterArgs &a, int parity, int G_in, hipStream_t s,
                                  hipEvent_t *ev2)
 {
+    constexpr int V = 16 / sizeof(T);
     double *P2 = a.partials + kPartUpdate;
     if (aligned16(a.x)) {
-        const Chunks cp = chunks(a.n / 2, (int64_t)kBlock * a.A->vec_it, kBlock);
-        HNS_TRY_HIP(launch_k(k_pupdate_line_x<2>, cp.grid, kBlock, 0, s, ev2, a.n, cp.per,
-                             (double *)a.x, (double *)a.p, (const double *)a.z, a.sc,
-                             (const double *)P2, G_in, parity, a.token));
+        const Chunks cp = chunks(a.n / V, (int64_t)kBlock * a.A->vec_it, kBlock);
+        HNS_TRY_HIP(launch_k(k_pupdate_line_x<T, V>, cp.grid, kBlock, 0, s, ev2, a.n, cp.per,
+                             (T *)a.x, (T *)a.p, (const T *)a.z, a.sc, (const double *)P2, G_in,
+                             parity, a.token));
     } else {
         const Chunks cp = chunks(a.n, (int64_t)kBlock * a.A->vec_it, kBlock);
-        HNS_TRY_HIP(launch_k(k_pupdate_line_x<1>, cp.grid, kBlock, 0, s, ev2, a.n, cp.per,
-                             (double *)a.x, (double *)a.p, (const double *)a.z, a.sc,
-                             (const double *)P2, G_in, parity, a.token));
+        HNS_TRY_HIP(launch_k(k_pupdate_line_x<T, 1>, cp.grid, kBlock, 0, s, ev2, a.n, cp.per,
+                             (T *)a.x, (T *)a.p, (const T *)a.z, a.sc, (const double *)P2, G_in,
+                             parity, a.token));
     }
     return HNS_OK;
 }
 
+// T = double: FP64 iteration; T = float: FP32 matrix, vectors and factors
+// (inner iterations of mixed precision)
+template <typename T>
 hns_status line_iteration(const IterArgs &a, int parity, hipStream_t s, hipEvent_t *ev)
 {
     const uint8_t *bc = a.bit < 0 ? nullptr : a.bc;
@@ -1479,13 +1571,13 @@ hns_status line_iteration(const IterArgs &a, int parity, hipStream_t s, hipEvent
     const int L = a.line_len;
     const int NC = line_cols_per_block(L);
     const int Gl = line_grid(a.n, L);
-    const int Gs = spmv_dispatch<double, double, true>(*a.A, a.p, a.q, bc, a.bit, a.sc, P1, s,
-                                                       ev ? ev : nullptr);
+    const int Gs = spmv_dispatch<T, T, true>(*a.A, a.p, a.q, bc, a.bit, a.sc, P1, s,
+                                             ev ? ev : nullptr);
     if (Gs < 0) return check_launch("spmv");
-    HNS_TRY_HIP(launch_k(k_update_line, Gl, kBlock, (size_t)4 * NC * L * sizeof(double), s,
-                         ev ? ev + 2 : nullptr, a.n, L, NC, (double *)a.r, (const double *)a.q,
-                         a.z, a.lfac, a.sc, (const double *)P1, Gs, P2, parity, a.token));
-    HNS_TRY(launch_pupdate_line_x(a, parity, Gl, s, ev ? ev + 4 : nullptr));
+    HNS_TRY_HIP(launch_k(k_update_line<T>, Gl, kBlock, (size_t)4 * NC * L * sizeof(T), s,
+                         ev ? ev + 2 : nullptr, a.n, L, NC, (T *)a.r, (const T *)a.q, (T *)a.z,
+                         (const T *)a.lfac, a.sc, (const double *)P1, Gs, P2, parity, a.token));
+    HNS_TRY(launch_pupdate_line_x<T>(a, parity, Gl, s, ev ? ev + 4 : nullptr));
     return check_launch("line-preconditioned cg iteration");
 }
 
@@ -1528,13 +1620,14 @@ hns_status ic0_iteration(const IterArgs &a, int parity, hipStream_t s, hipEvent_
                              cu.per, (double *)a.r, (const double *)a.q, a.sc,
                              (const double *)P1, Gs, parity, a.token));
     }
-    HNS_TRY(ic0_apply(*a.ic, (const double *)a.r, a.y, a.z, s));
+    double *z = (double *)a.z;
+    HNS_TRY(ic0_apply(*a.ic, (const double *)a.r, a.y, z, s));
     if (vec)
-        k_dot_rz<2><<<cu.grid, kBlock, 0, s>>>(a.n, cu.per, (const double *)a.r, a.z, a.sc, P2);
+        k_dot_rz<2><<<cu.grid, kBlock, 0, s>>>(a.n, cu.per, (const double *)a.r, z, a.sc, P2);
     else
-        k_dot_rz<1><<<cu.grid, kBlock, 0, s>>>(a.n, cu.per, (const double *)a.r, a.z, a.sc, P2);
+        k_dot_rz<1><<<cu.grid, kBlock, 0, s>>>(a.n, cu.per, (const double *)a.r, z, a.sc, P2);
     HNS_TRY(check_launch("dot r.z"));
-    HNS_TRY(launch_pupdate_line_x(a, parity, cu.grid, s, ev ? ev + 4 : nullptr));
+    HNS_TRY(launch_pupdate_line_x<double>(a, parity, cu.grid, s, ev ? ev + 4 : nullptr));
     return check_launch("ic0-preconditioned cg iteration");
 }
 
@@ -1636,16 +1729,46 @@ int line_grid(int64_t n, int line_len)
     return (int)g;
 }
 
+template <typename T>
+static hns_status init_line_t(int64_t n, int line_len, T *r, T *p, const T *lfac, bool singular,
+                              bool bb_from_rr, Scalars *sc, double *partials, hipStream_t s)
+{
+    const int NC = line_cols_per_block(line_len);
+    const int G = line_grid(n, line_len);
+    k_init_line<T><<<G, kBlock, (size_t)4 * NC * line_len * sizeof(T), s>>>(
+        n, line_len, NC, r, p, lfac, singular ? 1 : 0, bb_from_rr ? 1 : 0, sc,
+        partials + kPartMisc);
+    return check_launch("init_line");
+}
+
 hns_status launch_init_line(int64_t n, int line_len, double *r, double *p, const double *lfac,
                             bool singular, bool bb_from_rr, Scalars *sc, double *partials,
                             hipStream_t s)
 {
+    return init_line_t<double>(n, line_len, r, p, lfac, singular, bb_from_rr, sc, partials, s);
+}
+
+hns_status launch_init_line(int64_t n, int line_len, float *r, float *p, const float *lfac,
+                            bool singular, bool bb_from_rr, Scalars *sc, double *partials,
+                            hipStream_t s)
+{
+    return init_line_t<float>(n, line_len, r, p, lfac, singular, bb_from_rr, sc, partials, s);
+}
+
+hns_status launch_replace_line(int64_t n, int line_len, const double *r64, float *r, float *z,
+                               float *p, const float *lfac, Scalars *sc, double *partials,
+                               int parity, int vec_it, hipStream_t s)
+{
     const int NC = line_cols_per_block(line_len);
     const int G = line_grid(n, line_len);
-    k_init_line<<<G, kBlock, (size_t)4 * NC * line_len * sizeof(double), s>>>(
-        n, line_len, NC, r, p, lfac, singular ? 1 : 0, bb_from_rr ? 1 : 0, sc,
-        partials + kPartMisc);
-    return check_launch("init_line");
+    double *P2 = partials + kPartUpdate;
+    k_replace_line<float><<<G, kBlock, (size_t)4 * NC * line_len * sizeof(float), s>>>(
+        n, line_len, NC, r64, r, z, lfac, P2);
+    HNS_TRY(check_launch("replace_line"));
+    // p and z are workspace vectors (16-byte aligned)
+    const Chunks cp = chunks(n / 4, (int64_t)kBlock * vec_it, kBlock);
+    k_pdir_line<float, 4><<<cp.grid, kBlock, 0, s>>>(n, cp.per, p, z, sc, P2, G, parity);
+    return check_launch("direction (line replacement)");
 }
 
 hns_status launch_init_ic0(int64_t n, const IC0Dev &F, const double *r, double *p, double *z,
@@ -1847,11 +1970,10 @@ hns_status launch_iteration(const IterArgs &a, int parity, hipStream_t s, hipEve
         return ic0_iteration(a, parity, s, ev);
     }
     if (a.lfac) {
-        if (a.prec != Prec::F64) {
-            set_error("the line preconditioner runs in FP64 only");
-            return HNS_ERR_INVALID;
-        }
-        return line_iteration(a, parity, s, ev);
+        if (a.prec == Prec::F64) return line_iteration<double>(a, parity, s, ev);
+        if (a.prec == Prec::F32) return line_iteration<float>(a, parity, s, ev);
+        set_error("the line preconditioner runs FP64 iterations or FP32 inner iterations");
+        return HNS_ERR_INVALID;
     }
     switch (a.prec) {
     case Prec::F64: return iteration_impl<double, double, double>(a, parity, s, ev);

@@ -189,6 +189,7 @@ struct SolveCtx {
     Workspace *w;
     const double *lfac = nullptr;   // line-preconditioner factors of this mask (FP64 solves)
     const IC0Dev *ic = nullptr;     // IC(0) factor of this mask (FP64 solves)
+    const float *lfac32 = nullptr;  // FP32 line factors (inner iterations of mixed solves)
 };
 
 // Enqueue `count` CG iterations of one recurrence.  parity0 is the number of
@@ -199,7 +200,7 @@ struct SolveCtx {
 static hns_status enqueue_iterations(hns_operator *op, Workspace *w, Prec prec, int bit, void *x,
                                      void *r, void *p, void *q, const void *dinv, Scalars *sc,
                                      int count, int parity0, hipStream_t s,
-                                     const double *lfac = nullptr, const IC0Dev *ic = nullptr)
+                                     const void *lfac = nullptr, const IC0Dev *ic = nullptr)
 {
     const int period = op->profile;
     if (period > 0) HNS_TRY(w->ensure_events(6 * (size_t)count));
@@ -259,9 +260,11 @@ static hns_status run_chunks(const SolveCtx &c, int which, Prec prec, void *x, v
         if (left <= 0) break;
         const int chunk = left < op->check_every ? left : op->check_every;
         const int before = h.iter;
+        const void *lf = prec == Prec::F64   ? (const void *)c.lfac
+                         : prec == Prec::F32 ? (const void *)c.lfac32
+                                             : nullptr;
         HNS_TRY(enqueue_iterations(op, w, prec, c.bit, x, r, p, q, dinv, w->sc + which, chunk,
-                                   *since_start, c.s, prec == Prec::F64 ? c.lfac : nullptr,
-                                   prec == Prec::F64 ? c.ic : nullptr));
+                                   *since_start, c.s, lf, prec == Prec::F64 ? c.ic : nullptr));
         HNS_TRY(pull_scalars(w, which, c.s));
         *since_start += h.iter - before;
         HNS_TRY(account_iterations(op, w, prec == Prec::F32, h.iter - before));
@@ -513,8 +516,12 @@ static hns_status solve_mixed_replace(const SolveCtx &c, hns_solve_info *info)
             hi.bb = h.rr;
             hi.iter = info->iterations;
             HNS_TRY(push_scalars(w, 1, c.s));
-            HNS_TRY(launch_init_dir(op->n, Prec::F32, w->r32, w->p32, op->dinv32, false, false,
-                                    w->sc + 1, w->partials, c.s));
+            if (c.lfac32)
+                HNS_TRY(launch_init_line(op->n, op->line_len, w->r32, w->p32, c.lfac32, false,
+                                         false, w->sc + 1, w->partials, c.s));
+            else
+                HNS_TRY(launch_init_dir(op->n, Prec::F32, w->r32, w->p32, op->dinv32, false,
+                                        false, w->sc + 1, w->partials, c.s));
             HNS_TRY(pull_scalars(w, 1, c.s));
             since = 0;
             fresh = false;
@@ -549,8 +556,13 @@ static hns_status solve_mixed_replace(const SolveCtx &c, hns_solve_info *info)
             continue;
         }
         HNS_TRY(launch_set_threshold(w->sc + 1, std::max(drop2, tol2 * h.bb / h.rr), h.rr, c.s));
-        HNS_TRY(launch_replace_residual(op->n, Prec::F32, w->r, w->r32, w->p32, op->dinv32,
-                                        w->sc + 1, w->partials, (since - 1) & 1, c.s));
+        if (c.lfac32)
+            HNS_TRY(launch_replace_line(op->n, op->line_len, w->r, w->r32, (float *)w->z, w->p32,
+                                        c.lfac32, w->sc + 1, w->partials, (since - 1) & 1,
+                                        op->A.vec_it, c.s));
+        else
+            HNS_TRY(launch_replace_residual(op->n, Prec::F32, w->r, w->r32, w->p32, op->dinv32,
+                                            w->sc + 1, w->partials, (since - 1) & 1, c.s));
         hi.stop = 0;
     }
     info->outer_iterations = replacements;
@@ -868,6 +880,8 @@ void hns_operator_destroy(hns_operator *op)
         if (p) (void)hipFree(p);
     for (double *f : op->line_fac)
         if (f) (void)hipFree(f);
+    for (float *f : op->line_fac32)
+        if (f) (void)hipFree(f);
     for (IC0Dev *f : op->ic0_fac)
         if (f) {
             f->release();
@@ -1030,44 +1044,78 @@ static hns_status check_solve_args(hns_operator *op, int mask_bit, const void *b
 // none): the column blocks with Dirichlet rows and columns replaced by the
 // identity, factorised top-down (u_0 = d_0, u_k = d_k - e_{k-1}^2 / u_{k-1});
 // stored as the masked couplings e followed by the inverse pivots 1 / u.
+// Column factors of Dirichlet set `bit` on the host: masked couplings e (n)
+// then inverse pivots w (n) of the top-down Thomas factorisation.
+static hns_status line_factors_host(const hns_operator *op, int bit, std::vector<double> &host)
+{
+    const int64_t n = op->n;
+    const int L = op->line_len;
+    const bool masked = bit >= 0 && !op->bc_host.empty();
+    auto dir = [&](int64_t i) { return masked && ((op->bc_host[i] >> bit) & 1u); };
+    host.assign(2 * (size_t)n, 0.0);
+    double *e = host.data(), *w = host.data() + n;
+    for (int64_t c0 = 0; c0 < n; c0 += L) {
+        for (int64_t i = c0; i < c0 + L; ++i) {
+            const bool top = (i == c0 + L - 1);
+            e[i] = (top || dir(i) || dir(i + 1)) ? 0.0 : op->line_e[i];
+            const double d = dir(i) ? 1.0 : op->line_d[i];
+            const double u = (i == c0) ? d : d - e[i - 1] * (e[i - 1] * w[i - 1]);
+            if (!(u > 0.0) || !std::isfinite(u)) {
+                set_error("column block of node %lld is not positive definite", (long long)i);
+                return HNS_ERR_BREAKDOWN;
+            }
+            w[i] = 1.0 / u;
+        }
+    }
+    return HNS_OK;
+}
+
+static hns_status upload_factors(const void *host, size_t bytes, void **dev)
+{
+    hipError_t err = hipMalloc(dev, bytes);
+    if (err != hipSuccess) {
+        *dev = nullptr;
+        set_error("allocation of line factors failed: %s", hipGetErrorString(err));
+        return err == hipErrorOutOfMemory ? HNS_ERR_OOM : HNS_ERR_HIP;
+    }
+    err = hipMemcpy(*dev, host, bytes, hipMemcpyHostToDevice);
+    if (err != hipSuccess) {
+        (void)hipFree(*dev);
+        *dev = nullptr;
+        set_error("upload of line factors failed: %s", hipGetErrorString(err));
+        return HNS_ERR_HIP;
+    }
+    return HNS_OK;
+}
+
+// Device factors of Dirichlet set `bit` (FP64), computed on first use.
 static hns_status line_factors(hns_operator *op, int bit, const double **out)
 {
     std::lock_guard<std::mutex> g(op->line_mutex);
     double *&slot = op->line_fac[bit + 1];
     if (!slot) {
-        const int64_t n = op->n;
-        const int L = op->line_len;
-        const bool masked = bit >= 0 && !op->bc_host.empty();
-        auto dir = [&](int64_t i) { return masked && ((op->bc_host[i] >> bit) & 1u); };
-        std::vector<double> host(2 * (size_t)n);
-        double *e = host.data(), *w = host.data() + n;
-        for (int64_t c0 = 0; c0 < n; c0 += L) {
-            for (int64_t i = c0; i < c0 + L; ++i) {
-                const bool top = (i == c0 + L - 1);
-                e[i] = (top || dir(i) || dir(i + 1)) ? 0.0 : op->line_e[i];
-                const double d = dir(i) ? 1.0 : op->line_d[i];
-                const double u = (i == c0) ? d : d - e[i - 1] * (e[i - 1] * w[i - 1]);
-                if (!(u > 0.0) || !std::isfinite(u)) {
-                    set_error("column block of node %lld is not positive definite",
-                              (long long)i);
-                    return HNS_ERR_BREAKDOWN;
-                }
-                w[i] = 1.0 / u;
-            }
-        }
-        double *dev = nullptr;
-        hipError_t err = hipMalloc(&dev, host.size() * sizeof(double));
-        if (err != hipSuccess) {
-            set_error("allocation of line factors failed: %s", hipGetErrorString(err));
-            return err == hipErrorOutOfMemory ? HNS_ERR_OOM : HNS_ERR_HIP;
-        }
-        err = hipMemcpy(dev, host.data(), host.size() * sizeof(double), hipMemcpyHostToDevice);
-        if (err != hipSuccess) {
-            (void)hipFree(dev);
-            set_error("upload of line factors failed: %s", hipGetErrorString(err));
-            return HNS_ERR_HIP;
-        }
-        slot = dev;
+        std::vector<double> host;
+        HNS_TRY(line_factors_host(op, bit, host));
+        void *dev = nullptr;
+        HNS_TRY(upload_factors(host.data(), host.size() * sizeof(double), &dev));
+        slot = (double *)dev;
+    }
+    *out = slot;
+    return HNS_OK;
+}
+
+// The same factors rounded to FP32, for the inner iterations of HNS_MIXED.
+static hns_status line_factors32(hns_operator *op, int bit, const float **out)
+{
+    std::lock_guard<std::mutex> g(op->line_mutex);
+    float *&slot = op->line_fac32[bit + 1];
+    if (!slot) {
+        std::vector<double> host;
+        HNS_TRY(line_factors_host(op, bit, host));
+        std::vector<float> h32(host.begin(), host.end());
+        void *dev = nullptr;
+        HNS_TRY(upload_factors(h32.data(), h32.size() * sizeof(float), &dev));
+        slot = (float *)dev;
     }
     *out = slot;
     return HNS_OK;
@@ -1150,6 +1198,7 @@ hns_status hns_solve(hns_operator *op, int mask_bit, const double *b_dev, double
         return HNS_ERR_BREAKDOWN;
     }
     const double *lfac = nullptr;
+    const float *lfac32 = nullptr;
     const IC0Dev *ic = nullptr;
     if (op->precond == 2) {
         if (mode != HNS_FP64 || (op->kind == HNS_POISSON && mask_bit < 0)) {
@@ -1164,12 +1213,14 @@ hns_status hns_solve(hns_operator *op, int mask_bit, const double *b_dev, double
         }
     }
     if (op->precond == 1) {
-        if (mode != HNS_FP64) {
-            set_error("the line preconditioner runs with HNS_FP64 only");
+        if (mode == HNS_MIXED && op->mixed_variant != 0) {
+            set_error("the line preconditioner runs HNS_MIXED solves with mixed_variant 0 "
+                      "(FP32 CG with FP64 residual replacement) only");
             info->status = HNS_ERR_INVALID;
             return HNS_ERR_INVALID;
         }
-        st = line_factors(op, mask_bit, &lfac);
+        st = mode == HNS_MIXED ? line_factors32(op, mask_bit, &lfac32)
+                               : line_factors(op, mask_bit, &lfac);
         if (st != HNS_OK) {
             info->status = st;
             return st;
@@ -1177,7 +1228,7 @@ hns_status hns_solve(hns_operator *op, int mask_bit, const double *b_dev, double
     }
     Workspace *w = nullptr;
     st = acquire_ws(op, mode == HNS_MIXED, &w);
-    if (st == HNS_OK && (lfac || ic)) {
+    if (st == HNS_OK && (lfac || lfac32 || ic)) {
         st = w->ensure_z();
         if (st == HNS_OK && ic) st = w->ensure_y();
         if (st != HNS_OK) release_ws(op, w);
@@ -1186,8 +1237,8 @@ hns_status hns_solve(hns_operator *op, int mask_bit, const double *b_dev, double
         info->status = st;
         return st;
     }
-    SolveCtx c{op, mask_bit, op->kind == HNS_POISSON && mask_bit < 0, b_dev, x_dev, tol,
-               max_iter, (hipStream_t)stream, w, lfac, ic};
+    SolveCtx c{op,   mask_bit, op->kind == HNS_POISSON && mask_bit < 0, b_dev, x_dev, tol,
+               max_iter, (hipStream_t)stream, w, lfac, ic, lfac32};
     st = (mode == HNS_MIXED) ? solve_mixed(c, info) : solve_fp64(c, info);
     info->status = st;
     release_ws(op, w);
