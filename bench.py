@@ -714,6 +714,22 @@ def main():
         log(f"mixed: {msm:.1f} ms/step (x{ms64 / msm:.2f}), "
             + ", ".join(f"{k}={i.iterations}/{i.outer_iterations}" for k, i in infosm.items()))
 
+    # the same step with the pressure solve preconditioned by the vertical-line
+    # blocks (the velocity solves keep point Jacobi): FP64 and mixed precision
+    line_step = None
+    if not args.no_precond:
+        pois.set_param("precond", 1)
+        line_step = {}
+        for mode in ("fp64",) + (() if args.no_mixed else ("mixed",)):
+            tot, per, inf, _ = timed(mode, args.steps, args.warmup, 0)
+            ms = 1e3 * tot / args.steps
+            line_step[mode] = {"ms_per_step": round(ms, 3),
+                               "speedup_vs_fp64_jacobi": round(ms64 / ms, 3),
+                               "pressure_iters": inf["q"].iterations,
+                               "pressure_relres": inf["q"].relres_true}
+        pois.set_param("precond", 0)
+        log(f"step with line-preconditioned pressure: {line_step}")
+
     # operator set-up: host assembly against device-computed values (same
     # pattern work on the host, bitwise the same matrix)
     setup = {}
@@ -809,6 +825,7 @@ def main():
                                                  / (spmv_avg_us * 1e-6) / 1e9 / PEAK_HBM_GBS, 4)},
         "pressure_kernels": kern,
         "mixed": mixed,
+        "line_pressure_step": line_step,
         "operator_setup": setup,
         "isotropic_pressure": isotropic,
         "velocity_preconditioners": precond,
