@@ -35,13 +35,15 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def matrix_bytes(fmt, n, nnz, value_bytes):
+def matrix_bytes(fmt, n, nnz, value_bytes, unit=False):
     """Algorithmic bytes of one read of the operator in the storage format the
     solve runs: symmetric diagonal storage reads the unique values of the
-    symmetric matrix ((nnz + n) / 2 of them) and no indices; CSR and sliced
-    ELL read every value, its column index and the row pointers."""
+    symmetric matrix ((nnz + n) / 2 of them; (nnz - n) / 2 for the
+    Jacobi-scaled operator, whose unit diagonal is not stored) and no indices;
+    CSR and sliced ELL read every value, its column index and the row
+    pointers."""
     if fmt == "sdia":
-        return value_bytes * (nnz + n) // 2
+        return value_bytes * ((nnz - n) if unit else (nnz + n)) // 2
     return (value_bytes + 4) * nnz + 4 * (n + 1)
 
 
@@ -52,9 +54,22 @@ def bytes_iter(fmt, n, nnz, vb):
     return matrix_bytes(fmt, n, nnz, vb) + 12 * vb * n
 
 
-def bytes_spmv(fmt, n, nnz, vb):
+def bytes_iter_scaled(n, nnz, vb):
+    """The same iteration as CG on the Jacobi-scaled operator: the operator
+    without its diagonal, 10 vector passes (no D^-1 reads) and the FP32
+    weights diag(A) of the residual norm read by the update."""
+    return matrix_bytes("sdia", n, nnz, vb, unit=True) + 10 * vb * n + 4 * n
+
+
+def bytes_spmv(fmt, n, nnz, vb, unit=False):
     """The SpMV kernel alone: operator + read p + write q."""
-    return matrix_bytes(fmt, n, nnz, vb) + 2 * vb * n
+    return matrix_bytes(fmt, n, nnz, vb, unit) + 2 * vb * n
+
+
+def jacobi_scaled(op):
+    """Whether point-Jacobi solves of `op` run as CG on the Jacobi-scaled
+    operator (tunable jacobi_scaling at its default 1, small_n at 4096)."""
+    return op.format == "sdia" and 1 <= op.ndiag <= 16 and op.n > 4096
 
 
 def bytes_residual(fmt, n, nnz):
@@ -62,10 +77,14 @@ def bytes_residual(fmt, n, nnz):
     return matrix_bytes(fmt, n, nnz, 8) + 3 * 8 * n
 
 
-def solve_bytes(info, fmt, n, nnz, mode):
+def solve_bytes(info, fmt, n, nnz, mode, scaled=False):
+    """Bytes of a solve: by default the plain Jacobi-PCG count (bytes_iter);
+    scaled=True: the bytes the Jacobi-scaled recurrence moves."""
+    it = (lambda vb: bytes_iter_scaled(n, nnz, vb)) if scaled else (
+        lambda vb: bytes_iter(fmt, n, nnz, vb))
     if mode == "fp64":
-        return info.iterations * bytes_iter(fmt, n, nnz, 8)
-    return (info.iterations * bytes_iter(fmt, n, nnz, 4)
+        return info.iterations * it(8)
+    return (info.iterations * it(4)
             + (info.outer_iterations + 1) * (bytes_residual(fmt, n, nnz) + 8 * 3 * n))
 
 
@@ -373,15 +392,20 @@ def bench_bricks(torch, log, reps=3):
             torch.cuda.synchronize()
             el = time.perf_counter() - t
             best = el if best is None else min(best, el)
-        passes = 12 if precond == 0 else 13
-        by = info.iterations * (matrix_bytes(op.format, op.n, op.nnz, 8) + passes * 8 * op.n)
+        scaled = precond == 0 and jacobi_scaled(op)
+        if scaled:   # bytes the Jacobi-scaled recurrence moves
+            by = info.iterations * bytes_iter_scaled(op.n, op.nnz, 8)
+            vec = 10 * 8 * op.n + 4 * op.n
+        else:
+            vec = (12 if precond == 0 else 13) * 8 * op.n
+            by = info.iterations * (matrix_bytes(op.format, op.n, op.nnz, 8) + vec)
         # diagonal storage also reads the zeros it stores where a row lacks an offset
-        stored = ((op.ndiag + 1) * op.n * 8 if op.format == "sdia"
+        stored = ((op.ndiag + (0 if scaled else 1)) * op.n * 8 if op.format == "sdia"
                   else matrix_bytes(op.format, op.n, op.nnz, 8))
-        by_stored = info.iterations * (stored + passes * 8 * op.n)
+        by_stored = info.iterations * (stored + vec)
         out[name] = {"order": order, "bricks": [Nx, Ny, Nz], "nodes": op.n, "nnz": op.nnz,
                      "format": op.format, "ndiag": op.ndiag, "nu": list(nu),
-                     "precond": ["jacobi", "line"][precond],
+                     "precond": ["jacobi", "line"][precond], "jacobi_scaled": scaled,
                      "tol": tol, "setup_s": round(setup_s, 2), "iterations": info.iterations,
                      "status": info.status, "relres": float("%.3g" % info.relres_true),
                      "ms": round(1e3 * best, 3),
@@ -559,7 +583,9 @@ def traffic_probe(torch, log, iters=64, q2_iters=16):
     torch.cuda.synchronize()
     out = {"probe": "traffic", "copy_bytes": 2 * a.numel() * 8, "nodes": m.n, "nnz": pois.nnz,
            "format": pois.format, "iterations": info.iterations,
-           "spmv_algorithmic_bytes": bytes_spmv(pois.format, m.n, pois.nnz, 8)}
+           "jacobi_scaled": jacobi_scaled(pois),
+           "spmv_algorithmic_bytes": bytes_spmv(pois.format, m.n, pois.nnz, 8,
+                                                unit=jacobi_scaled(pois))}
     pois.close()
     del a, b
     mq = basin.basin_hex_mesh(128, 128, 10, 2, L=wl.L, seed=wl.seed)
@@ -672,7 +698,9 @@ def main():
     u64 = st.u.clone()
     ms64 = 1e3 * total64 / args.steps
     fmt = pois.format
+    scaled = jacobi_scaled(pois)
     bytes64 = sum(solve_bytes(i, fmt, n, nnz, "fp64") for i in infos64.values())
+    moved64 = sum(solve_bytes(i, fmt, n, nnz, "fp64", scaled) for i in infos64.values())
     csr_equiv = sum(solve_bytes(i, "csr", n, nnz, "fp64") for i in infos64.values())
     gbs64 = bytes64 / (ms64 * 1e-3) / 1e9
     log(f"fp64: {ms64:.1f} ms/step, {gbs64:.0f} GB/s, iters "
@@ -681,9 +709,10 @@ def main():
     # dominant kernel: the SpMV of the pressure solve, timed live with HIP events
     spmv_ms, spmv_n = prof64["pois"]["spmv"]
     spmv_avg_us = 1e3 * spmv_ms / max(spmv_n, 1)
-    spmv_bytes = bytes_spmv(fmt, n, nnz, 8)
+    spmv_bytes = bytes_spmv(fmt, n, nnz, 8, unit=scaled)
     spmv_gbs = spmv_bytes / (spmv_avg_us * 1e-6) / 1e9
-    spmv_kernel = (f"k_spmv_sdia<double, double, true, {pois.ndiag}, 2>" if fmt == "sdia"
+    spmv_kernel = (f"k_spmv_sdia<double, double, true, {pois.ndiag}, 2, true>" if scaled
+                   else f"k_spmv_sdia<double, double, true, {pois.ndiag}, 2>" if fmt == "sdia"
                    else f"k_spmv_{fmt}<double, double, true>")
     traffic = counted_traffic(spmv_kernel)
     kern = {}
@@ -809,8 +838,13 @@ def main():
                    "rhs": "time step 1 after a step from rest (wind, Coriolis, pressure)",
                    "tol": wl.tol, "nu_h": wl.nu_h, "nu_v": wl.nu_v,
                    "dt": wl.dt},
-        "value_basis": "algorithmic bytes of the solves in the storage format used (operator "
-                       "read + 12 vector passes per CG iteration) / step time",
+        "value_basis": "Jacobi-PCG work of the step in bytes of the diagonal storage (operator "
+                       "read with its diagonal + 12 vector passes per CG iteration) / step time",
+        "jacobi_scaled": scaled,
+        "moved_GBs": round(moved64 / (ms64 * 1e-3) / 1e9, 1),
+        "moved_basis": "bytes the solves move as run: CG on the Jacobi-scaled operator (no "
+                       "stored diagonal, 10 vector passes + FP32 weights per iteration)"
+                       if scaled else "same as value",
         "csr_equivalent_GBs": round(csr_equiv / (ms64 * 1e-3) / 1e9, 1),
         "fp64": {k: {"iters": i.iterations, "relres": i.relres_true} for k, i in infos64.items()},
         "step_ms": [round(1e3 * v, 3) for v in per64],

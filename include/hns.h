@@ -305,6 +305,22 @@ int hns_operator_line_len(const hns_operator *op);
  *                  about 12 against 26 us per iteration at 1445 rows, 35
  *                  against 19 at 6875), 0 = never, at most 1048576.  Not
  *                  used while per-kernel timing is enabled.
+ *   "jacobi_scaling" 1 (default): point-Jacobi solves (precond 0) of an
+ *                  operator in symmetric diagonal storage with at most 16
+ *                  upper diagonals and more than "small_n" rows, HNS_FP64 or
+ *                  HNS_MIXED with mixed_variant 0, run the Jacobi-PCG
+ *                  recurrence of the paper's Sec. 5 remarks as plain CG on
+ *                  D^-1/2 A D^-1/2 (D = diag(A)) with the vectors
+ *                  D^1/2 x, D^-1/2 r, D^1/2 p: the same alpha, beta and
+ *                  iterates in exact arithmetic, with a unit diagonal that is
+ *                  not stored and no D^-1 reads per iteration.  Each segment
+ *                  between FP64 true-residual checks starts from the true
+ *                  residual, accumulates its correction in scaled form and
+ *                  adds D^-1/2 times it to x; the stopping test still uses
+ *                  |b - A x| (the recursive residual norm is weighted by
+ *                  diag(A)).  The scaled operator (FP64, and FP32 when the
+ *                  operator keeps FP32 values) is computed on the device on
+ *                  first use and stays resident.  0 = the unscaled recurrence.
  *   "precond"      0 = point Jacobi, the inverse diagonal (default; the
  *                  diagonal preconditioner of the paper's Sec. 5 remarks);
  *                  1 = vertical-line blocks: the inverse of the tridiagonal

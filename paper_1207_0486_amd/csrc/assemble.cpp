@@ -325,8 +325,9 @@ size_t DevMatrix::bytes() const
 {
     size_t b = 0;
     if (fmt == HNS_FMT_SDIA) {
-        b += (size_t)(ndiag + 1) * n * 8;
-        if (dia32) b += (size_t)(ndiag + 1) * n * 4;
+        const size_t arrays = (size_t)ndiag + (unit ? 0 : 1);
+        if (dia) b += arrays * n * 8;
+        if (dia32) b += arrays * n * 4;
     } else if (fmt == HNS_FMT_CSR) {
         b += (size_t)(n + 1) * 4 + (size_t)nnz * 12;
         if (val32) b += (size_t)nnz * 4;

@@ -78,6 +78,10 @@ struct DevMatrix {
     int32_t off[kMaxDiagWide] = {0};
     double *dia = nullptr;
     float *dia32 = nullptr;
+    // unit: a symmetrically Jacobi-scaled operator (main diagonal 1, not
+    // stored): array k = 0 .. ndiag-1 holds upper diagonal k (unrolled
+    // kernels only, products of the CG iteration only)
+    bool unit = false;
     // launch shape of the single-vector CG kernels: workgroup-sized row
     // passes per block of the FP64-vector and FP32-vector diagonal SpMV, and
     // 16-byte packs per thread of the vector updates
@@ -183,6 +187,15 @@ struct hns_operator {
                            nullptr, nullptr, nullptr, nullptr};
     float *line_fac32[9] = {nullptr, nullptr, nullptr, nullptr, nullptr,
                             nullptr, nullptr, nullptr, nullptr};   // FP32 copies (mixed)
+    // Jacobi scaling (jacobi_scaling = 1): point-Jacobi solves on an operator
+    // in the unrolled symmetric-diagonal format run plain CG on the
+    // unit-diagonal D^-1/2 A D^-1/2 (S, FP64 and, when A keeps FP32 values,
+    // FP32), with s = D^-1/2 and w = diag(A) in FP32; built on first use
+    // (under line_mutex).
+    int jacobi_scaling = 1;
+    hns::DevMatrix S;
+    double *jac_s = nullptr;
+    float *jac_w = nullptr;
     // IC(0) preconditioner (precond = 2): host copy of the assembled matrix
     // (kept with HNS_KEEP_HOST) and the device factors per mask (index bit + 1)
     hns::HostCSR host_A;

@@ -79,6 +79,11 @@ struct IterArgs {
     // tag of this iteration (unique within a workspace, never 0): links the
     // point-Jacobi update to the direction update that completes it
     uint32_t token = 0;
+    // Jacobi-scaled CG (point Jacobi on A as plain CG on D^-1/2 A D^-1/2):
+    // when set, A is the unit-diagonal scaled operator, x, r, p, q are the
+    // scaled vectors (x the correction D^1/2 dx of this segment, r = D^-1/2
+    // r_A), dinv is not read, and wjac = diag(A) in FP32 weighs |r_A|^2
+    const float *wjac = nullptr;
 };
 
 // One CG iteration = three launches:
@@ -166,6 +171,28 @@ hns_status launch_set_threshold(Scalars *sc, double tol2, double bb, hipStream_t
 hns_status launch_replace_residual(int64_t n, Prec prec, const double *r64, void *r, void *p,
                                    const void *dinv, Scalars *sc, double *partials, int parity,
                                    hipStream_t s);
+// Segment start of the Jacobi-scaled recurrence from the FP64 true residual
+// r64 (already projected when singular): r = (TX)(s r64) with s = diag(A)^-1/2,
+// p = r, dx = 0, rho[0] = r^T r, rr = r64^T r64, stop flag as launch_init_dir.
+// r may alias r64 (FP64 recurrence: the scaled residual replaces it in place).
+// prec F64 (TX = double) or F32 (TX = float).
+hns_status launch_scale_in(int64_t n, Prec prec, const double *r64, void *r, void *p, void *dx,
+                           const double *s_half, Scalars *sc, double *partials, hipStream_t s);
+// Segment end: x += s dx (FP64), dx = 0.
+hns_status launch_scale_out(int64_t n, Prec prec, double *x, void *dx, const double *s_half,
+                            hipStream_t s);
+// Residual replacement of the Jacobi-scaled FP32 recurrence: r = (float)(s r64),
+// rho' = r^T r, rr = r64^T r64, beta = rho' / rho[parity], p = r + beta p.
+hns_status launch_replace_scaled(int64_t n, const double *r64, float *r, float *p,
+                                 const double *s_half, Scalars *sc, double *partials, int parity,
+                                 hipStream_t s);
+// The scaled operator: from the main diagonal d (array 0 of `dia`) s = d^-1/2
+// and w = (float) d; out[k n + i] = dia[(k+1) n + i] s_i s_{i + off[k]} for the
+// ndiag upper diagonals (0 past the last row), and its FP32 rounding when out32.
+hns_status launch_jacobi_scale(int64_t n, int ndiag, const int32_t *off, const double *dia,
+                               double *s_half, float *w, double *out, float *out32,
+                               hipStream_t s);
+
 // wx = sum lumped_i x_i ; then x -= wx / lumped_sum
 hns_status launch_normalise(int64_t n, double *x, const double *lumped, double lumped_sum,
                             Scalars *sc, double *partials, hipStream_t s);

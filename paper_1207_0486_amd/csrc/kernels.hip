@@ -317,7 +317,9 @@ __device__ __forceinline__ Run<R, T> ldrun(const T *p)
 // instructions); rows within the largest offset of either end take a
 // per-row path with explicit range tests.  Both forms add the terms of a row
 // in the same order: main, then (upper, lower) for each offset.
-template <typename TV, typename TX, bool DOT, int M, int R>
+// UNIT: the symmetrically Jacobi-scaled operator D^-1/2 A D^-1/2, whose main
+// diagonal is 1 and not stored; dia then holds the M upper diagonals only.
+template <typename TV, typename TX, bool DOT, int M, int R, bool UNIT = false>
 __global__ __launch_bounds__(kBlock) void k_spmv_sdia(int64_t n, int64_t rows, DiaOffsets offs,
                                                       const TV *__restrict__ dia,
                                                       const TX *__restrict__ x, TX *__restrict__ y,
@@ -331,17 +333,18 @@ __global__ __launch_bounds__(kBlock) void k_spmv_sdia(int64_t n, int64_t rows, D
     const int lb = xcd_block(blockIdx.x, gridDim.x);
     const int64_t r0 = (int64_t)lb * rows;
     const int64_t r1 = r0 + rows < n ? r0 + rows : n;
+    constexpr int K0 = UNIT ? 0 : 1;   // array of the first upper diagonal
     double acc = 0.0;
     if constexpr (R == 1) {
         for (int64_t i = r0 + threadIdx.x; i < r1; i += kBlock) {
             const TX xi = x[i];
-            TX sum = (TX)dia[i] * xi;
+            TX sum = UNIT ? xi : (TX)dia[i] * xi;
             TV up[M], lo[M];
             TX xu[M], xl[M];
 #pragma unroll
             for (int k = 0; k < M; ++k) {
                 const int64_t o = offs.o[k];
-                const TV *u = dia + (int64_t)(k + 1) * n;
+                const TV *u = dia + (int64_t)(k + K0) * n;
                 const int64_t iu = i + o < n ? i + o : n - 1;
                 const int64_t il = i >= o ? i - o : 0;
                 up[k] = u[i];
@@ -364,13 +367,14 @@ __global__ __launch_bounds__(kBlock) void k_spmv_sdia(int64_t n, int64_t rows, D
         for (int64_t i = r0 + (int64_t)threadIdx.x * R; i < r1; i += (int64_t)kBlock * R) {
             if (i >= omax && i + (R - 1) + omax < n) {
                 const Run<R, TX> xi = ldrun<R>(x + i);
-                const Run<R, TV> d0 = ldrun<R>(dia + i);
+                Run<R, TV> d0;
+                if constexpr (!UNIT) d0 = ldrun<R>(dia + i);
                 Run<R, TV> up[M], lo[M];
                 Run<R, TX> xu[M], xl[M];
 #pragma unroll
                 for (int k = 0; k < M; ++k) {
                     const int64_t o = offs.o[k];
-                    const TV *u = dia + (int64_t)(k + 1) * n;
+                    const TV *u = dia + (int64_t)(k + K0) * n;
                     up[k] = ldrun<R>(u + i);
                     xu[k] = ldrun<R>(x + i + o);
                     lo[k] = ldrun<R>(u + i - o);
@@ -379,7 +383,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_sdia(int64_t n, int64_t rows, D
                 Run<R, TX> out;
 #pragma unroll
                 for (int e = 0; e < R; ++e) {
-                    TX sum = (TX)d0.v[e] * xi.v[e];
+                    TX sum = UNIT ? xi.v[e] : (TX)d0.v[e] * xi.v[e];
 #pragma unroll
                     for (int k = 0; k < M; ++k) {
                         sum += (TX)up[k].v[e] * xu[k].v[e];
@@ -395,10 +399,10 @@ __global__ __launch_bounds__(kBlock) void k_spmv_sdia(int64_t n, int64_t rows, D
                     const int64_t j = i + e;
                     if (j >= r1) break;
                     const TX xj = x[j];
-                    TX sum = (TX)dia[j] * xj;
+                    TX sum = UNIT ? xj : (TX)dia[j] * xj;
                     for (int k = 0; k < M; ++k) {
                         const int64_t o = offs.o[k];
-                        const TV *u = dia + (int64_t)(k + 1) * n;
+                        const TV *u = dia + (int64_t)(k + K0) * n;
                         if (j + o < n) sum += (TX)u[j] * x[j + o];
                         if (j >= o) sum += (TX)u[j - o] * x[j - o];
                     }
@@ -413,6 +417,114 @@ __global__ __launch_bounds__(kBlock) void k_spmv_sdia(int64_t n, int64_t rows, D
         double v[1] = {acc};
         store_block_partials<1>(v, part);
     }
+}
+
+// ---------------------------------------------------------------------------
+// Jacobi scaling: point-Jacobi PCG on A is plain CG on D^-1/2 A D^-1/2 with
+// the vectors x_S = D^1/2 x, r_S = D^-1/2 r, p_S = D^1/2 p (the same alpha,
+// beta and iterates in exact arithmetic); the scaled operator has a unit
+// diagonal, so neither the main diagonal nor D^-1 is read per iteration.
+// ---------------------------------------------------------------------------
+
+// s = d^-1/2 and w = (float) d from the main diagonal d of A
+__global__ __launch_bounds__(kBlock) void k_jacobi_diag(int64_t n, const double *__restrict__ d,
+                                                        double *__restrict__ sh,
+                                                        float *__restrict__ w)
+{
+    GRID_STRIDE(i, n)
+    {
+        const double di = d[i];
+        sh[i] = 1.0 / sqrt(di);
+        w[i] = (float)di;
+    }
+}
+
+// upper diagonal k of the scaled operator: a_{i, i+o} s_i s_{i+o}
+__global__ __launch_bounds__(kBlock) void k_jacobi_scale(int64_t n, int ndiag, DiaOffsets offs,
+                                                         const double *__restrict__ dia,
+                                                         const double *__restrict__ sh,
+                                                         double *__restrict__ out,
+                                                         float *__restrict__ out32)
+{
+    GRID_STRIDE(i, n)
+    {
+        const double si = sh[i];
+        for (int k = 0; k < ndiag; ++k) {
+            const int64_t j = i + offs.o[k];
+            const double v = j < n ? dia[(int64_t)(k + 1) * n + i] * si * sh[j] : 0.0;
+            out[(int64_t)k * n + i] = v;
+            if (out32) out32[(int64_t)k * n + i] = (float)v;
+        }
+    }
+}
+
+// Segment start from the FP64 true residual: r = (TX)(s r64), p = r, dx = 0;
+// rho[0] = r^T r, rr = r64^T r64.  r64 and r may be the same array (each
+// element is read before it is overwritten, by the same thread).
+template <typename TX>
+__global__ __launch_bounds__(kBlock) void k_scale_in(int64_t n, const double *r64, TX *r,
+                                                     TX *__restrict__ p, TX *__restrict__ dx,
+                                                     const double *__restrict__ sh,
+                                                     Scalars *__restrict__ sc,
+                                                     double *__restrict__ partials)
+{
+    double rho = 0.0, rr = 0.0;
+    GRID_STRIDE(i, n)
+    {
+        const double ra = r64[i];
+        const TX ri = (TX)(sh[i] * ra);
+        r[i] = ri;
+        p[i] = ri;
+        dx[i] = (TX)0;
+        rho += (double)ri * (double)ri;
+        rr += ra * ra;
+    }
+    double v[2] = {rho, rr};
+    if (grid_sum<2>(v, partials, &sc->counter[2]) && threadIdx.x == 0) {
+        sc->rho[0] = v[0];
+        sc->rr = v[1];
+        sc->beta = 0.0;
+        if (!(sc->bb > 0.0))
+            sc->stop = 3;
+        else if (!isfinite(v[0]) || !isfinite(v[1]))
+            sc->stop = 2;
+        else
+            sc->stop = (v[1] <= sc->tol2 * sc->bb) ? 1 : 0;
+    }
+}
+
+// Segment end: x += s dx in FP64, dx = 0
+template <typename TX>
+__global__ __launch_bounds__(kBlock) void k_scale_out(int64_t n, double *__restrict__ x,
+                                                      TX *__restrict__ dx,
+                                                      const double *__restrict__ sh)
+{
+    GRID_STRIDE(i, n)
+    {
+        x[i] += sh[i] * (double)dx[i];
+        dx[i] = (TX)0;
+    }
+}
+
+// Residual replacement of the scaled FP32 recurrence: r = (float)(s r64);
+// per-block partials of r^T r and r64^T r64 for the k_pupdate that follows.
+__global__ __launch_bounds__(kBlock) void k_replace_rz_scaled(int64_t n,
+                                                              const double *__restrict__ r64,
+                                                              float *__restrict__ r,
+                                                              const double *__restrict__ sh,
+                                                              double *__restrict__ part_out)
+{
+    double rz = 0.0, rr = 0.0;
+    GRID_STRIDE(i, n)
+    {
+        const double ra = r64[i];
+        const float ri = (float)(sh[i] * ra);
+        r[i] = ri;
+        rz += (double)ri * (double)ri;
+        rr += ra * ra;
+    }
+    double v[2] = {rz, rr};
+    store_block_partials<2>(v, part_out);
 }
 
 // Offsets of the wide symmetric-diagonal format (kernel-argument memory)
@@ -635,7 +747,10 @@ struct XDirPacks {
 
 // r -= alpha q; partials of r^T D^-1 r and r^T r.  Block 0 records alpha and
 // this iteration's tag, which the direction update needs to add alpha p to x.
-template <typename TX, typename TD, int V>
+// SC (CG on the Jacobi-scaled operator, r = D^-1/2 r_A): dinv holds the
+// weights diag(A) instead, and the partials are r^T r and r^T diag(A) r, the
+// latter being |r_A|^2 of the unscaled residual.
+template <typename TX, typename TD, int V, bool SC = false>
 __global__ __launch_bounds__(kBlock) void k_update(int64_t n, int64_t per, TX *__restrict__ r,
                                                    const TX *__restrict__ q,
                                                    const TD *__restrict__ dinv,
@@ -676,9 +791,15 @@ __global__ __launch_bounds__(kBlock) void k_update(int64_t n, int64_t per, TX *_
 #pragma unroll
         for (int e = 0; e < W; ++e) {
             in.r.v[e] = in.r.v[e] - alpha * in.q.v[e];
-            const TX zi = (TX)in.d.v[e] * in.r.v[e];
-            rz += (double)in.r.v[e] * (double)zi;
-            rr += (double)in.r.v[e] * (double)in.r.v[e];
+            const double ri = (double)in.r.v[e];
+            if constexpr (SC) {
+                rz += ri * ri;
+                rr += (double)in.d.v[e] * ri * ri;
+            } else {
+                const TX zi = (TX)in.d.v[e] * in.r.v[e];
+                rz += ri * (double)zi;
+                rr += ri * ri;
+            }
         }
         st<W>(r, i, in.r);
     };
@@ -690,7 +811,8 @@ __global__ __launch_bounds__(kBlock) void k_update(int64_t n, int64_t per, TX *_
 // rho' = r^T z, rr = r^T r from the update partials; beta = rho' / rho;
 // p = D^-1 r + beta p unless converged.  `count` is added to the iteration
 // counter (0 when used after a residual replacement).
-template <typename TX, typename TD, int V = 1>
+// SC: the Jacobi-scaled recurrence, z = r (dinv is not read).
+template <typename TX, typename TD, int V = 1, bool SC = false>
 __global__ __launch_bounds__(kBlock) void k_pupdate(int64_t n, int64_t per, TX *__restrict__ p,
                                                     const TX *__restrict__ r,
                                                     const TD *__restrict__ dinv,
@@ -702,7 +824,10 @@ __global__ __launch_bounds__(kBlock) void k_pupdate(int64_t n, int64_t per, TX *
     TX beta = 0;
     auto load = [&](int64_t i, auto w) {
         constexpr int W = decltype(w)::value;
-        return DirPacks<TX, TD, W>{ld<W>(p, i), ld<W>(r, i), ld<W>(dinv, i)};
+        if constexpr (SC)
+            return DirPacks<TX, TD, W>{ld<W>(p, i), ld<W>(r, i), {}};
+        else
+            return DirPacks<TX, TD, W>{ld<W>(p, i), ld<W>(r, i), ld<W>(dinv, i)};
     };
     auto prologue = [&]() {
         double v[2];
@@ -727,7 +852,8 @@ __global__ __launch_bounds__(kBlock) void k_pupdate(int64_t n, int64_t per, TX *
     auto body = [&](int64_t i, auto in) {
         constexpr int W = sizeof(in.p.v) / sizeof(TX);
 #pragma unroll
-        for (int e = 0; e < W; ++e) in.p.v[e] = (TX)in.d.v[e] * in.r.v[e] + beta * in.p.v[e];
+        for (int e = 0; e < W; ++e)
+            in.p.v[e] = (SC ? in.r.v[e] : (TX)in.d.v[e] * in.r.v[e]) + beta * in.p.v[e];
         st<W>(p, i, in.p);
     };
     for_packs_ahead<V>(n, per, load, prologue, body);
@@ -739,7 +865,8 @@ __global__ __launch_bounds__(kBlock) void k_pupdate(int64_t n, int64_t per, TX *
 // unless the iteration converged or broke down, p = D^-1 r + beta p.  The
 // entry test is the tag and not the stop flag: block 0 of this launch may
 // raise the flag while other blocks still have their x update to do.
-template <typename TX, typename TD, int V = 1>
+// SC: the Jacobi-scaled recurrence, z = r (dinv is not read).
+template <typename TX, typename TD, int V = 1, bool SC = false>
 __global__ __launch_bounds__(kBlock) void k_pupdate_x(int64_t n, int64_t per,
                                                       TX *__restrict__ x, TX *__restrict__ p,
                                                       const TX *__restrict__ r,
@@ -754,7 +881,10 @@ __global__ __launch_bounds__(kBlock) void k_pupdate_x(int64_t n, int64_t per,
     bool dir = true;
     auto load = [&](int64_t i, auto w) {
         constexpr int W = decltype(w)::value;
-        return XDirPacks<TX, TD, W>{ld<W>(p, i), ld<W>(r, i), ld<W>(x, i), ld<W>(dinv, i)};
+        if constexpr (SC)
+            return XDirPacks<TX, TD, W>{ld<W>(p, i), ld<W>(r, i), ld<W>(x, i), {}};
+        else
+            return XDirPacks<TX, TD, W>{ld<W>(p, i), ld<W>(r, i), ld<W>(x, i), ld<W>(dinv, i)};
     };
     auto prologue = [&]() {
         double v[2];
@@ -785,7 +915,7 @@ __global__ __launch_bounds__(kBlock) void k_pupdate_x(int64_t n, int64_t per,
         if (dir) {
 #pragma unroll
             for (int e = 0; e < W; ++e)
-                in.p.v[e] = (TX)in.d.v[e] * in.r.v[e] + beta * in.p.v[e];
+                in.p.v[e] = (SC ? in.r.v[e] : (TX)in.d.v[e] * in.r.v[e]) + beta * in.p.v[e];
             st<W>(p, i, in.p);
         }
     };
@@ -1471,6 +1601,16 @@ int sdia_launch(const DevMatrix &A, const TV *vals, const void *p, void *q, cons
     DiaOffsets offs;
     for (int k = 0; k < kMaxDiag; ++k) offs.o[k] = k < A.ndiag ? A.off[k] : 0;
     const Chunks c = sdia_chunks<TX>(A);
+    if constexpr (DOT && std::is_same<TV, TX>::value) {
+        if (A.unit) {
+            if (launch_k(k_spmv_sdia<TV, TX, DOT, M, R, true>, c.grid, kBlock, 0, s, ev2, A.n,
+                         c.per, offs, vals, (const TX *)p, (TX *)q, bc, bit, sc,
+                         part) != hipSuccess)
+                return -1;
+            return c.grid;
+        }
+    }
+    if (A.unit) return -1;   // the unit-diagonal form runs the CG products only
     if (launch_k(k_spmv_sdia<TV, TX, DOT, M, R>, c.grid, kBlock, 0, s, ev2, A.n, c.per, offs,
                  vals, (const TX *)p, (TX *)q, bc, bit, sc, part) != hipSuccess)
         return -1;
@@ -1501,7 +1641,7 @@ int sdia_dispatch(const DevMatrix &A, const TV *vals, const void *p, void *q, co
             return sdia_launch<TV, TX, DOT, M>(A, vals, p, q, bc, bit, sc, part, s, ev2);
         return sdia_dispatch<TV, TX, DOT, M + 1>(A, vals, p, q, bc, bit, sc, part, s, ev2);
     }
-    if (A.ndiag > kMaxDiag && A.ndiag <= kMaxDiagWide)
+    if (A.ndiag > kMaxDiag && A.ndiag <= kMaxDiagWide && !A.unit)
         return sdia_wide_launch<TV, TX, DOT>(A, vals, p, q, bc, bit, sc, part, s, ev2);
     return -1;
 }
@@ -1663,6 +1803,45 @@ hns_status iteration_impl(const IterArgs &a, int parity, hipStream_t s, hipEvent
                              (const double *)P2, cu.grid, parity, a.token));
     }
     return check_launch("cg iteration");
+}
+
+// Point-Jacobi iteration of CG on the Jacobi-scaled operator (a.A unit
+// diagonal, FP64 or FP32 values and vectors): the same three kernels without
+// the reads of D^-1; a.wjac (diag(A), FP32) weighs the unscaled residual norm.
+template <typename T>
+hns_status iteration_scaled(const IterArgs &a, int parity, hipStream_t s, hipEvent_t *ev)
+{
+    constexpr int V = 16 / sizeof(T);
+    const uint8_t *bc = a.bit < 0 ? nullptr : a.bc;
+    double *P1 = a.partials + kPartSpmv;
+    double *P2 = a.partials + kPartUpdate;
+    const bool vec = aligned16(a.x) && aligned16(a.r) && aligned16(a.p) && aligned16(a.q) &&
+                     aligned16(a.wjac);
+    if ((sizeof(T) == 4 ? (const void *)a.A->dia32 : (const void *)a.A->dia) == nullptr) {
+        set_error("the Jacobi-scaled operator has no values in this precision");
+        return HNS_ERR_INVALID;
+    }
+    const Chunks cu = chunks(vec ? a.n / V : a.n, (int64_t)kBlock * a.A->vec_it, kBlock);
+    const int Gs = spmv_dispatch<T, T, true>(*a.A, a.p, a.q, bc, a.bit, a.sc, P1, s,
+                                             ev ? ev : nullptr);
+    if (Gs < 0) return check_launch("spmv (Jacobi-scaled)");
+    hipEvent_t *eu = ev ? ev + 2 : nullptr, *ep = ev ? ev + 4 : nullptr;
+    if (vec) {
+        HNS_TRY_HIP(launch_k(k_update<T, float, V, true>, cu.grid, kBlock, 0, s, eu, a.n, cu.per,
+                             (T *)a.r, (const T *)a.q, a.wjac, a.sc, (const double *)P1, Gs, P2,
+                             parity, a.token));
+        HNS_TRY_HIP(launch_k(k_pupdate_x<T, float, V, true>, cu.grid, kBlock, 0, s, ep, a.n,
+                             cu.per, (T *)a.x, (T *)a.p, (const T *)a.r, (const float *)nullptr,
+                             a.sc, (const double *)P2, cu.grid, parity, a.token));
+    } else {
+        HNS_TRY_HIP(launch_k(k_update<T, float, 1, true>, cu.grid, kBlock, 0, s, eu, a.n, cu.per,
+                             (T *)a.r, (const T *)a.q, a.wjac, a.sc, (const double *)P1, Gs, P2,
+                             parity, a.token));
+        HNS_TRY_HIP(launch_k(k_pupdate_x<T, float, 1, true>, cu.grid, kBlock, 0, s, ep, a.n,
+                             cu.per, (T *)a.x, (T *)a.p, (const T *)a.r, (const float *)nullptr,
+                             a.sc, (const double *)P2, cu.grid, parity, a.token));
+    }
+    return check_launch("cg iteration (Jacobi-scaled)");
 }
 
 }  // namespace
@@ -1975,6 +2154,16 @@ hns_status launch_iteration(const IterArgs &a, int parity, hipStream_t s, hipEve
         set_error("the line preconditioner runs FP64 iterations or FP32 inner iterations");
         return HNS_ERR_INVALID;
     }
+    if (a.wjac) {
+        if (!a.A->unit || a.A->fmt != HNS_FMT_SDIA) {
+            set_error("the Jacobi-scaled iteration needs the unit-diagonal operator");
+            return HNS_ERR_INVALID;
+        }
+        if (a.prec == Prec::F64) return iteration_scaled<double>(a, parity, s, ev);
+        if (a.prec == Prec::F32) return iteration_scaled<float>(a, parity, s, ev);
+        set_error("the Jacobi-scaled iteration runs FP64 or FP32 recurrences");
+        return HNS_ERR_INVALID;
+    }
     switch (a.prec) {
     case Prec::F64: return iteration_impl<double, double, double>(a, parity, s, ev);
     case Prec::F32: return iteration_impl<float, float, float>(a, parity, s, ev);
@@ -2061,6 +2250,69 @@ hns_status launch_replace_residual(int64_t n, Prec prec, const double *r64, void
                                                         0);
     }
     return check_launch("pupdate (replacement)");
+}
+
+hns_status launch_scale_in(int64_t n, Prec prec, const double *r64, void *r, void *p, void *dx,
+                           const double *s_half, Scalars *sc, double *partials, hipStream_t s)
+{
+    const int G = stream_grid(n);
+    double *P = partials + kPartMisc;
+    if (prec == Prec::F64)
+        k_scale_in<double><<<G, kBlock, 0, s>>>(n, r64, (double *)r, (double *)p, (double *)dx,
+                                                s_half, sc, P);
+    else if (prec == Prec::F32)
+        k_scale_in<float><<<G, kBlock, 0, s>>>(n, r64, (float *)r, (float *)p, (float *)dx,
+                                               s_half, sc, P);
+    else {
+        set_error("the Jacobi-scaled recurrence runs in FP64 or FP32");
+        return HNS_ERR_INVALID;
+    }
+    return check_launch("scale_in");
+}
+
+hns_status launch_scale_out(int64_t n, Prec prec, double *x, void *dx, const double *s_half,
+                            hipStream_t s)
+{
+    const int G = stream_grid(n);
+    if (prec == Prec::F64)
+        k_scale_out<double><<<G, kBlock, 0, s>>>(n, x, (double *)dx, s_half);
+    else if (prec == Prec::F32)
+        k_scale_out<float><<<G, kBlock, 0, s>>>(n, x, (float *)dx, s_half);
+    else {
+        set_error("the Jacobi-scaled recurrence runs in FP64 or FP32");
+        return HNS_ERR_INVALID;
+    }
+    return check_launch("scale_out");
+}
+
+hns_status launch_replace_scaled(int64_t n, const double *r64, float *r, float *p,
+                                 const double *s_half, Scalars *sc, double *partials, int parity,
+                                 hipStream_t s)
+{
+    const int Gu = stream_grid(n);
+    double *P2 = partials + kPartUpdate;
+    k_replace_rz_scaled<<<Gu, kBlock, 0, s>>>(n, r64, r, s_half, P2);
+    HNS_TRY(check_launch("replace_rz (Jacobi-scaled)"));
+    k_pupdate<float, float, 1, true><<<Gu, kBlock, 0, s>>>(n, 0, p, (const float *)r, nullptr, sc,
+                                                           P2, Gu, parity, 0);
+    return check_launch("pupdate (Jacobi-scaled replacement)");
+}
+
+hns_status launch_jacobi_scale(int64_t n, int ndiag, const int32_t *off, const double *dia,
+                               double *s_half, float *w, double *out, float *out32,
+                               hipStream_t s)
+{
+    if (ndiag < 1 || ndiag > kMaxDiag) {
+        set_error("Jacobi scaling of %d upper diagonals (1 to %d supported)", ndiag, kMaxDiag);
+        return HNS_ERR_INVALID;
+    }
+    DiaOffsets offs;
+    for (int k = 0; k < kMaxDiag; ++k) offs.o[k] = k < ndiag ? off[k] : 0;
+    const int G = stream_grid(n);
+    k_jacobi_diag<<<G, kBlock, 0, s>>>(n, dia, s_half, w);
+    HNS_TRY(check_launch("jacobi_diag"));
+    k_jacobi_scale<<<G, kBlock, 0, s>>>(n, ndiag, offs, dia, s_half, out, out32);
+    return check_launch("jacobi_scale");
 }
 
 hns_status launch_project_norm(int64_t n, double *r, bool singular, Scalars *sc,

@@ -190,6 +190,7 @@ struct SolveCtx {
     const double *lfac = nullptr;   // line-preconditioner factors of this mask (FP64 solves)
     const IC0Dev *ic = nullptr;     // IC(0) factor of this mask (FP64 solves)
     const float *lfac32 = nullptr;  // FP32 line factors (inner iterations of mixed solves)
+    bool scaled = false;            // point Jacobi as CG on the Jacobi-scaled operator
 };
 
 // Enqueue `count` CG iterations of one recurrence.  parity0 is the number of
@@ -200,11 +201,17 @@ struct SolveCtx {
 static hns_status enqueue_iterations(hns_operator *op, Workspace *w, Prec prec, int bit, void *x,
                                      void *r, void *p, void *q, const void *dinv, Scalars *sc,
                                      int count, int parity0, hipStream_t s,
-                                     const void *lfac = nullptr, const IC0Dev *ic = nullptr)
+                                     const void *lfac = nullptr, const IC0Dev *ic = nullptr,
+                                     bool scaled = false)
 {
     const int period = op->profile;
     if (period > 0) HNS_TRY(w->ensure_events(6 * (size_t)count));
     IterArgs a{&op->A, prec, op->n, x, r, p, q, dinv, op->bc, bit, sc, w->partials};
+    if (scaled) {
+        a.A = &op->S;
+        a.dinv = nullptr;
+        a.wjac = op->jac_w;
+    }
     if (lfac) {
         a.lfac = lfac;
         a.z = w->z;
@@ -217,7 +224,7 @@ static hns_status enqueue_iterations(hns_operator *op, Workspace *w, Prec prec, 
     }
     // latency-bound sizes: the whole chunk in one workgroup (point Jacobi,
     // FP64 or FP32, not while per-kernel timing is on)
-    if (!lfac && !ic && period <= 0 && op->n <= op->small_n &&
+    if (!lfac && !ic && !scaled && period <= 0 && op->n <= op->small_n &&
         (prec == Prec::F64 || prec == Prec::F32))
         return launch_cg_small(a, parity0, count, s);
     for (int it = 0; it < count; ++it) {
@@ -264,7 +271,8 @@ static hns_status run_chunks(const SolveCtx &c, int which, Prec prec, void *x, v
                          : prec == Prec::F32 ? (const void *)c.lfac32
                                              : nullptr;
         HNS_TRY(enqueue_iterations(op, w, prec, c.bit, x, r, p, q, dinv, w->sc + which, chunk,
-                                   *since_start, c.s, lf, prec == Prec::F64 ? c.ic : nullptr));
+                                   *since_start, c.s, lf, prec == Prec::F64 ? c.ic : nullptr,
+                                   c.scaled));
         HNS_TRY(pull_scalars(w, which, c.s));
         *since_start += h.iter - before;
         HNS_TRY(account_iterations(op, w, prec == Prec::F32, h.iter - before));
@@ -358,7 +366,10 @@ static hns_status solve_fp64_vectors(const SolveCtx &c, hns_solve_info *info, Pr
             }
             h.stop = 0;
             HNS_TRY(push_scalars(w, 0, c.s));
-            if (c.ic && prec == Prec::F64)
+            if (c.scaled)   // r = D^-1/2 r_A in place, p = r, correction dx = 0
+                HNS_TRY(launch_scale_in(op->n, Prec::F64, w->r, w->r, w->p, w->z, op->jac_s,
+                                        w->sc, w->partials, c.s));
+            else if (c.ic && prec == Prec::F64)
                 HNS_TRY(launch_init_ic0(op->n, *c.ic, w->r, w->p, w->z, w->y, w->sc,
                                         w->partials, c.s));
             else if (c.lfac && prec == Prec::F64)
@@ -371,7 +382,13 @@ static hns_status solve_fp64_vectors(const SolveCtx &c, hns_solve_info *info, Pr
             since = 0;
             fresh = false;
         }
-        if (h.stop == 0) HNS_TRY(run_chunks(c, 0, prec, c.x, w->r, w->p, w->q, dinv, &since));
+        if (c.scaled) {
+            // the scaled recurrence accumulates its correction D^1/2 dx in w->z
+            if (h.stop == 0) HNS_TRY(run_chunks(c, 0, prec, w->z, w->r, w->p, w->q, nullptr, &since));
+            HNS_TRY(launch_scale_out(op->n, Prec::F64, c.x, w->z, op->jac_s, c.s));
+        } else if (h.stop == 0) {
+            HNS_TRY(run_chunks(c, 0, prec, c.x, w->r, w->p, w->q, dinv, &since));
+        }
         info->iterations = h.iter;
         if (h.stop == 2) {
             status = HNS_ERR_BREAKDOWN;
@@ -510,13 +527,16 @@ static hns_status solve_mixed_replace(const SolveCtx &c, hns_solve_info *info)
     while (h.rr > tol2 * h.bb) {
         const double thr2 = std::max(drop2, tol2 * h.bb / h.rr);
         if (fresh) {
-            HNS_TRY(launch_cast(op->n, w->r, w->r32, w->d32, c.s));
+            if (!c.scaled) HNS_TRY(launch_cast(op->n, w->r, w->r32, w->d32, c.s));
             reset_scalars(hi, 0.0);
             hi.tol2 = thr2;
             hi.bb = h.rr;
             hi.iter = info->iterations;
             HNS_TRY(push_scalars(w, 1, c.s));
-            if (c.lfac32)
+            if (c.scaled)   // r32 = (float)(D^-1/2 r_A), p = r32, correction d32 = 0
+                HNS_TRY(launch_scale_in(op->n, Prec::F32, w->r, w->r32, w->p32, w->d32,
+                                        op->jac_s, w->sc + 1, w->partials, c.s));
+            else if (c.lfac32)
                 HNS_TRY(launch_init_line(op->n, op->line_len, w->r32, w->p32, c.lfac32, false,
                                          false, w->sc + 1, w->partials, c.s));
             else
@@ -530,7 +550,10 @@ static hns_status solve_mixed_replace(const SolveCtx &c, hns_solve_info *info)
         info->iterations = hi.iter;
         const bool broke = (hi.stop == 2);
         // collect the FP32 correction and recompute the true residual in FP64
-        HNS_TRY(launch_accumulate(op->n, c.x, w->d32, c.s));
+        if (c.scaled)
+            HNS_TRY(launch_scale_out(op->n, Prec::F32, c.x, w->d32, op->jac_s, c.s));
+        else
+            HNS_TRY(launch_accumulate(op->n, c.x, w->d32, c.s));
         HNS_TRY(true_residual_fp64(c));
         HNS_TRY(pull_scalars(w, 0, c.s));
         ++replacements;
@@ -556,7 +579,10 @@ static hns_status solve_mixed_replace(const SolveCtx &c, hns_solve_info *info)
             continue;
         }
         HNS_TRY(launch_set_threshold(w->sc + 1, std::max(drop2, tol2 * h.bb / h.rr), h.rr, c.s));
-        if (c.lfac32)
+        if (c.scaled)
+            HNS_TRY(launch_replace_scaled(op->n, w->r, w->r32, w->p32, op->jac_s, w->sc + 1,
+                                          w->partials, (since - 1) & 1, c.s));
+        else if (c.lfac32)
             HNS_TRY(launch_replace_line(op->n, op->line_len, w->r, w->r32, (float *)w->z, w->p32,
                                         c.lfac32, w->sc + 1, w->partials, (since - 1) & 1,
                                         op->A.vec_it, c.s));
@@ -870,12 +896,14 @@ void hns_operator_destroy(hns_operator *op)
     if (!op) return;
     (void)hipDeviceSynchronize();
     op->A.release();
+    op->S.release();
     op->M.release();
     for (auto &b : op->B) b.release();
     for (auto &b : op->Bt) b.release();
     op->Ms.release();
     void *ptrs[] = {op->dinv,     op->dinv32,    op->bc,      op->lumped,  op->step_tmp,
-                    op->mesh_xyz, op->mesh_tets, op->inc_ptr, op->inc_tet, op->inc_loc};
+                    op->mesh_xyz, op->mesh_tets, op->inc_ptr, op->inc_tet, op->inc_loc,
+                    op->jac_s,    op->jac_w};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (double *f : op->line_fac)
@@ -956,11 +984,13 @@ hns_status hns_set_param(hns_operator *op, const char *name, double value)
     } else if (k == "use_graph" && (value == 0 || value == 1)) {
         op->use_graph = (int)value;
     } else if (k == "spmv_it64" && value >= 1 && value <= 64 && value == (int)value) {
-        op->A.spmv_it64 = (int)value;
+        op->A.spmv_it64 = op->S.spmv_it64 = (int)value;
     } else if (k == "spmv_it32" && value >= 1 && value <= 64 && value == (int)value) {
-        op->A.spmv_it32 = (int)value;
+        op->A.spmv_it32 = op->S.spmv_it32 = (int)value;
     } else if (k == "vec_it" && value >= 1 && value <= 64 && value == (int)value) {
-        op->A.vec_it = (int)value;
+        op->A.vec_it = op->S.vec_it = (int)value;
+    } else if (k == "jacobi_scaling" && (value == 0 || value == 1)) {
+        op->jacobi_scaling = (int)value;
     } else if (k == "small_n" && value >= 0 && value <= (double)kSmallMaxN &&
                value == (int64_t)value) {
         op->small_n = (int64_t)value;
@@ -1002,6 +1032,12 @@ size_t hns_footprint_bytes(const hns_operator *op, int k, uint32_t mode, int inc
         for (const IC0Dev *f : op->ic0_fac)
             if (f) b += f->bytes;
         b += op->A.bytes() + (size_t)op->n * (8 + 1 + 8);
+        // the Jacobi-scaled operator, resident once a point-Jacobi solve has used it
+        const bool scaled = op->S.dia || (op->jacobi_scaling && op->precond == 0 &&
+                                          op->A.fmt == HNS_FMT_SDIA && op->A.ndiag >= 1 &&
+                                          op->A.ndiag <= kMaxDiag && op->n > op->small_n);
+        if (scaled)
+            b += (size_t)op->A.ndiag * op->n * (op->A.dia32 ? 12 : 8) + (size_t)op->n * (8 + 4);
         if (op->dinv32) b += (size_t)op->n * 4;
         if (op->has_aux)
             b += op->M.bytes() + op->B[0].bytes() * 6 + op->Ms.bytes() + 24 * (size_t)op->n +
@@ -1180,6 +1216,61 @@ static hns_status ic0_factors(hns_operator *op, int bit, const IC0Dev **out)
     return HNS_OK;
 }
 
+// The Jacobi-scaled operator D^-1/2 A D^-1/2 (unit diagonal, upper diagonals
+// only; FP32 values too when A keeps them), s = D^-1/2 and w = diag(A) in
+// FP32, computed on the device on first use.
+static hns_status scaled_operator(hns_operator *op)
+{
+    std::lock_guard<std::mutex> g(op->line_mutex);
+    if (op->S.dia) return HNS_OK;
+    const DevMatrix &A = op->A;
+    const int64_t n = op->n;
+    DevMatrix S;
+    S.n = n;
+    S.nnz = A.nnz;
+    S.fmt = HNS_FMT_SDIA;
+    S.ndiag = A.ndiag;
+    for (int k = 0; k < kMaxDiagWide; ++k) S.off[k] = A.off[k];
+    S.unit = true;
+    S.spmv_it64 = A.spmv_it64;
+    S.spmv_it32 = A.spmv_it32;
+    S.vec_it = A.vec_it;
+    double *sh = nullptr;
+    float *w = nullptr;
+    auto fail = [&](hipError_t e, const char *what) {
+        S.release();
+        if (sh) (void)hipFree(sh);
+        if (w) (void)hipFree(w);
+        set_error("Jacobi scaling: %s failed: %s", what, hipGetErrorString(e));
+        return e == hipErrorOutOfMemory ? HNS_ERR_OOM : HNS_ERR_HIP;
+    };
+    const size_t vals = (size_t)A.ndiag * n;
+    hipError_t e = hipMalloc(&S.dia, vals * sizeof(double));
+    if (e != hipSuccess) return fail(e, "allocation");
+    if (A.dia32) {
+        e = hipMalloc(&S.dia32, vals * sizeof(float));
+        if (e != hipSuccess) return fail(e, "allocation");
+    }
+    e = hipMalloc(&sh, n * sizeof(double));
+    if (e != hipSuccess) return fail(e, "allocation");
+    e = hipMalloc(&w, n * sizeof(float));
+    if (e != hipSuccess) return fail(e, "allocation");
+    hns_status st = launch_jacobi_scale(n, A.ndiag, A.off, A.dia, sh, w, S.dia, S.dia32, nullptr);
+    if (st == HNS_OK) {
+        e = hipDeviceSynchronize();
+        if (e != hipSuccess) return fail(e, "scaling kernels");
+    } else {
+        S.release();
+        (void)hipFree(sh);
+        (void)hipFree(w);
+        return st;
+    }
+    op->S = S;
+    op->jac_s = sh;
+    op->jac_w = w;
+    return HNS_OK;
+}
+
 hns_status hns_solve(hns_operator *op, int mask_bit, const double *b_dev, double *x_dev,
                      double tol, int max_iter, uint32_t mode, void *stream, hns_solve_info *info)
 {
@@ -1226,9 +1317,22 @@ hns_status hns_solve(hns_operator *op, int mask_bit, const double *b_dev, double
             return st;
         }
     }
+    // point Jacobi on the unrolled diagonal format (above the single-workgroup
+    // size): plain CG on the Jacobi-scaled operator
+    bool scaled = op->jacobi_scaling && op->precond == 0 && op->A.fmt == HNS_FMT_SDIA &&
+                  op->A.ndiag >= 1 && op->A.ndiag <= kMaxDiag && op->n > op->small_n &&
+                  (mode == HNS_FP64 || (mode == HNS_MIXED && op->mixed_variant == 0));
+    if (scaled) {
+        st = scaled_operator(op);
+        if (st != HNS_OK) {
+            info->status = st;
+            return st;
+        }
+        if (mode == HNS_MIXED && !op->S.dia32) scaled = false;   // no FP32 values kept
+    }
     Workspace *w = nullptr;
     st = acquire_ws(op, mode == HNS_MIXED, &w);
-    if (st == HNS_OK && (lfac || lfac32 || ic)) {
+    if (st == HNS_OK && (lfac || lfac32 || ic || (scaled && mode == HNS_FP64))) {
         st = w->ensure_z();
         if (st == HNS_OK && ic) st = w->ensure_y();
         if (st != HNS_OK) release_ws(op, w);
@@ -1238,7 +1342,7 @@ hns_status hns_solve(hns_operator *op, int mask_bit, const double *b_dev, double
         return st;
     }
     SolveCtx c{op,   mask_bit, op->kind == HNS_POISSON && mask_bit < 0, b_dev, x_dev, tol,
-               max_iter, (hipStream_t)stream, w, lfac, ic, lfac32};
+               max_iter, (hipStream_t)stream, w, lfac, ic, lfac32, scaled};
     st = (mode == HNS_MIXED) ? solve_mixed(c, info) : solve_fp64(c, info);
     info->status = st;
     release_ws(op, w);
