@@ -711,9 +711,8 @@ def main():
     spmv_avg_us = 1e3 * spmv_ms / max(spmv_n, 1)
     spmv_bytes = bytes_spmv(fmt, n, nnz, 8, unit=scaled)
     spmv_gbs = spmv_bytes / (spmv_avg_us * 1e-6) / 1e9
-    spmv_kernel = (f"k_spmv_sdia<double, double, true, {pois.ndiag}, 2, true>" if scaled
-                   else f"k_spmv_sdia<double, double, true, {pois.ndiag}, 2>" if fmt == "sdia"
-                   else f"k_spmv_{fmt}<double, double, true>")
+    spmv_kernel = (f"k_spmv_sdia<double, double, true, {pois.ndiag}, 2, {str(scaled).lower()}>"
+                   if fmt == "sdia" else f"k_spmv_{fmt}<double, double, true>")
     traffic = counted_traffic(spmv_kernel)
     kern = {}
     for name in ("spmv", "update", "pupdate"):
