@@ -319,8 +319,20 @@ __device__ __forceinline__ Run<R, T> ldrun(const T *p)
 // in the same order: main, then (upper, lower) for each offset.
 // UNIT: the symmetrically Jacobi-scaled operator D^-1/2 A D^-1/2, whose main
 // diagonal is 1 and not stored; dia then holds the M upper diagonals only.
+// Waves per SIMD the two-row FP64 form is compiled for, as (min, max):
+// exactly 3 for the 15-point operator (M = 7: 162 VGPRs, every load of a lane
+// in flight; measured faster than 4 waves at 102 VGPRs), else the default.
+template <typename TV, typename TX, int M, int R>
+constexpr bool sdia_three_waves()
+{
+    return sizeof(TV) == 8 && sizeof(TX) == 8 && R == 2 && M == 7;
+}
+
 template <typename TV, typename TX, bool DOT, int M, int R, bool UNIT = false>
-__global__ __launch_bounds__(kBlock) void k_spmv_sdia(int64_t n, int64_t rows, DiaOffsets offs,
+__global__ __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu(sdia_three_waves<TV, TX, M, R>() ? 3 : 1,
+                                   sdia_three_waves<TV, TX, M, R>() ? 3 : 8)))
+void k_spmv_sdia(int64_t n, int64_t rows, DiaOffsets offs,
                                                       const TV *__restrict__ dia,
                                                       const TX *__restrict__ x, TX *__restrict__ y,
                                                       const uint8_t *__restrict__ bc, int bit,
@@ -366,6 +378,12 @@ __global__ __launch_bounds__(kBlock) void k_spmv_sdia(int64_t n, int64_t rows, D
         const int64_t omax = offs.o[M - 1];
         for (int64_t i = r0 + (int64_t)threadIdx.x * R; i < r1; i += (int64_t)kBlock * R) {
             if (i >= omax && i + (R - 1) + omax < n) {
+                // the Dirichlet bits first: tested between the products they
+                // make the compiler hold all 4 M + 2 loads at once (182
+                // VGPRs for M = 7 instead of 102)
+                bool dm[R];
+#pragma unroll
+                for (int e = 0; e < R; ++e) dm[e] = is_dirichlet(bc, bit, i + e);
                 const Run<R, TX> xi = ldrun<R>(x + i);
                 Run<R, TV> d0;
                 if constexpr (!UNIT) d0 = ldrun<R>(dia + i);
@@ -389,7 +407,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_sdia(int64_t n, int64_t rows, D
                         sum += (TX)up[k].v[e] * xu[k].v[e];
                         sum += (TX)lo[k].v[e] * xl[k].v[e];
                     }
-                    if (is_dirichlet(bc, bit, i + e)) sum = 0;
+                    if (dm[e]) sum = 0;
                     out.v[e] = sum;
                     if constexpr (DOT) acc += (double)xi.v[e] * (double)sum;
                 }
