@@ -3,10 +3,13 @@
 // One CG iteration (Remark 1 after Sec. 5 of the paper names PCG; the
 // diagonal preconditioner is the DIAG part of Remark 2) is three launches:
 //   spmv    q = A p (Dirichlet rows zeroed), per-block partials of p^T q
-//   update  gamma = p^T q, alpha = rho / gamma, x += alpha p, r -= alpha q,
+//   update  gamma = p^T q, alpha = rho / gamma, r -= alpha q,
 //           z = D^-1 r (not stored), per-block partials of r^T z and r^T r
 //   pupdate rho' = r^T z, rr = r^T r, beta = rho' / rho, stop flags,
-//           p = z + beta p
+//           x += alpha p, p = z + beta p
+// With Jacobi scaling the same three launches run plain CG on
+// D^-1/2 A D^-1/2 (unit diagonal, not stored; z = r; r^T r weighed by
+// diag(A) for the stopping test).
 // Each consumer kernel re-reduces the producer's per-block partials in every
 // block, in one fixed order, so all blocks hold bit-identical scalars without
 // a grid-wide fence, an atomic or an extra launch; block 0 records them.
