@@ -25,7 +25,6 @@ struct Scalars {
     double nonfinite;
     int32_t stop;    // 0 running, 1 recursive residual below tolerance, 2 breakdown, 3 b = 0
     int32_t iter;    // CG iterations executed
-    uint32_t counter[4];
     uint32_t xtoken; // tag of the last iteration whose update ran (x += alpha p pending)
 };
 

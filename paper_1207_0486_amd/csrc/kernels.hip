@@ -25,7 +25,8 @@
 // <float,double,float> (FP32 matrix and diagonal, FP64 vectors).
 //
 // One-off reductions outside the iteration (right-hand-side statistics,
-// residual norms, normalisation) use a last-block-done pattern instead.
+// residual norms, normalisation, recurrence starts) store per-block partials
+// the same way and a one-workgroup launch re-reduces them into the scalars.
 #include <cmath>
 #include <tuple>
 #include <type_traits>
@@ -66,42 +67,6 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double *lds)
         }
     }
     __syncthreads();
-}
-
-// Grid-wide sum of NV values for one-off reductions.  Returns true in all
-// threads of the last block to arrive; there thread 0 holds the totals in v.
-// partials holds NV x grid doubles; the counter is reset for the next launch.
-template <int NV>
-__device__ bool grid_sum(double (&v)[NV], double *partials, uint32_t *counter)
-{
-    __shared__ double lds[NV * (kBlock / 64)];
-    __shared__ int is_last;
-    block_sum<NV>(v, lds);
-    const int G = gridDim.x;
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int k = 0; k < NV; ++k) partials[k * G + blockIdx.x] = v[k];
-        __threadfence();
-        const uint32_t prev = atomicAdd(counter, 1u);
-        is_last = (prev == (uint32_t)(G - 1));
-    }
-    __syncthreads();
-    if (!is_last) return false;
-    __threadfence();
-    double t[NV];
-#pragma unroll
-    for (int k = 0; k < NV; ++k) t[k] = 0.0;
-    for (int b = threadIdx.x; b < G; b += kBlock) {
-#pragma unroll
-        for (int k = 0; k < NV; ++k) t[k] += partials[k * G + b];
-    }
-    block_sum<NV>(t, lds);
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int k = 0; k < NV; ++k) v[k] = t[k];
-        *counter = 0u;
-    }
-    return true;
 }
 
 // Sums NV per-thread values over the block and stores them as the block's
@@ -153,6 +118,68 @@ __device__ __forceinline__ void load_reduced(const double *__restrict__ P, int G
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < NV; ++k) out[k] = bcast[k];
+}
+
+// Finishing launches of the one-off reductions (one workgroup): the producer
+// kernel only stores its per-block partials, and this re-reduces them in the
+// same fixed order as every CG consumer and records the totals.  A
+// last-block-done pattern in the producer instead had every block take a
+// device-scope atomic on one counter, serialised beyond the per-XCD L2s.
+//
+// Start of a recurrence: rho[0] = r^T z, rr = r^T r (bb = rr when asked),
+// and the stop flag (3: b = 0, 2: non-finite, 1: already below tolerance).
+__global__ __launch_bounds__(kBlock) void k_fin_start(const double *__restrict__ P, int G,
+                                                      Scalars *__restrict__ sc, int bb_from_rr)
+{
+    double v[2];
+    load_reduced<2>(P, G, v);
+    if (threadIdx.x != 0) return;
+    sc->rho[0] = v[0];
+    sc->rr = v[1];
+    sc->beta = 0.0;
+    if (bb_from_rr) sc->bb = v[1];
+    if (!(sc->bb > 0.0))
+        sc->stop = 3;
+    else if (!isfinite(v[0]) || !isfinite(v[1]))
+        sc->stop = 2;
+    else
+        sc->stop = (v[1] <= sc->tol2 * sc->bb) ? 1 : 0;
+}
+
+// Statistics of b: sum, sum of squares, non-finite count
+__global__ __launch_bounds__(kBlock) void k_fin_bstats(const double *__restrict__ P, int G,
+                                                       Scalars *__restrict__ sc)
+{
+    double v[3];
+    load_reduced<3>(P, G, v);
+    if (threadIdx.x != 0) return;
+    sc->sumb = v[0];
+    sc->bb_raw = v[1];
+    sc->nonfinite = v[2];
+}
+
+// True residual: sum of r, |b - shift|^2
+__global__ __launch_bounds__(kBlock) void k_fin_residual(const double *__restrict__ P, int G,
+                                                         Scalars *__restrict__ sc)
+{
+    double v[2];
+    load_reduced<2>(P, G, v);
+    if (threadIdx.x != 0) return;
+    sc->sum_r = v[0];
+    sc->bb = v[1];
+}
+
+// One sum into sc->rr (which = 0) or sc->wx (which = 1)
+__global__ __launch_bounds__(kBlock) void k_fin_one(const double *__restrict__ P, int G,
+                                                    Scalars *__restrict__ sc, int which)
+{
+    double v[1];
+    load_reduced<1>(P, G, v);
+    if (threadIdx.x != 0) return;
+    if (which == 0)
+        sc->rr = v[0];
+    else
+        sc->wx = v[0];
 }
 
 // Workgroups are dealt to the 8 XCDs round-robin; renumber them so that each
@@ -501,17 +528,7 @@ __global__ __launch_bounds__(kBlock) void k_scale_in(int64_t n, const double *r6
         rr += ra * ra;
     }
     double v[2] = {rho, rr};
-    if (grid_sum<2>(v, partials, &sc->counter[2]) && threadIdx.x == 0) {
-        sc->rho[0] = v[0];
-        sc->rr = v[1];
-        sc->beta = 0.0;
-        if (!(sc->bb > 0.0))
-            sc->stop = 3;
-        else if (!isfinite(v[0]) || !isfinite(v[1]))
-            sc->stop = 2;
-        else
-            sc->stop = (v[1] <= sc->tol2 * sc->bb) ? 1 : 0;
-    }
+    store_block_partials<2>(v, partials);
 }
 
 // Segment end: x += s dx in FP64, dx = 0
@@ -693,6 +710,8 @@ __device__ __forceinline__ void for_packs(int64_t n, int64_t per, F &&body)
 // overlaps the prologue, and loads every further pack before it processes
 // the current one.  prologue() runs in every thread and returns the same
 // value in all threads of a block; false ends the loop (returns false).
+// (Loading all of a thread's packs before the prologue was measured slower:
+// the extra registers halve the occupancy.)
 template <int V, typename Load, typename Pro, typename Body>
 __device__ __forceinline__ bool for_packs_ahead(int64_t n, int64_t per, Load &&load,
                                                 Pro &&prologue, Body &&body)
@@ -948,7 +967,7 @@ template <typename TX, typename TD>
 __global__ __launch_bounds__(kBlock) void k_init_dir(int64_t n, TX *__restrict__ r,
                                                      TX *__restrict__ p,
                                                      const TD *__restrict__ dinv, int singular,
-                                                     int bb_from_rr, Scalars *__restrict__ sc,
+                                                     Scalars *__restrict__ sc,
                                                      double *__restrict__ partials)
 {
     const TX mean = singular ? (TX)(sc->sum_r / (double)n) : (TX)0;
@@ -966,18 +985,7 @@ __global__ __launch_bounds__(kBlock) void k_init_dir(int64_t n, TX *__restrict__
         rr += (double)ri * (double)ri;
     }
     double v[2] = {rz, rr};
-    if (grid_sum<2>(v, partials, &sc->counter[2]) && threadIdx.x == 0) {
-        sc->rho[0] = v[0];
-        sc->rr = v[1];
-        sc->beta = 0.0;
-        if (bb_from_rr) sc->bb = v[1];
-        if (!(sc->bb > 0.0))
-            sc->stop = 3;
-        else if (!isfinite(v[0]) || !isfinite(v[1]))
-            sc->stop = 2;
-        else
-            sc->stop = (v[1] <= sc->tol2 * sc->bb) ? 1 : 0;
-    }
+    store_block_partials<2>(v, partials);
 }
 
 // ---------------------------------------------------------------------------
@@ -1149,7 +1157,7 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_init_line(int64_t n, int L, int NC,
                                                       T *__restrict__ r, T *__restrict__ p,
                                                       const T *__restrict__ lfac, int singular,
-                                                      int bb_from_rr, Scalars *__restrict__ sc,
+                                                      Scalars *__restrict__ sc,
                                                       double *__restrict__ partials)
 {
     extern __shared__ double line_lds[];
@@ -1178,18 +1186,7 @@ __global__ __launch_bounds__(kBlock) void k_init_line(int64_t n, int L, int NC,
     __syncthreads();
     for (int t = threadIdx.x; t < rows; t += kBlock) p[row0 + t] = sy[t];
     double v[2] = {rz, rr};
-    if (grid_sum<2>(v, partials, &sc->counter[2]) && threadIdx.x == 0) {
-        sc->rho[0] = v[0];
-        sc->rr = v[1];
-        sc->beta = 0.0;
-        if (bb_from_rr) sc->bb = v[1];
-        if (!(sc->bb > 0.0))
-            sc->stop = 3;
-        else if (!isfinite(v[0]) || !isfinite(v[1]))
-            sc->stop = 2;
-        else
-            sc->stop = (v[1] <= sc->tol2 * sc->bb) ? 1 : 0;
-    }
+    store_block_partials<2>(v, partials);
 }
 
 // Residual replacement of a line-preconditioned mixed-precision segment: the
@@ -1406,17 +1403,7 @@ __global__ __launch_bounds__(kBlock) void k_init_from_z(int64_t n, const double 
         rr += ri * ri;
     }
     double v[2] = {rz, rr};
-    if (grid_sum<2>(v, partials, &sc->counter[2]) && threadIdx.x == 0) {
-        sc->rho[0] = v[0];
-        sc->rr = v[1];
-        sc->beta = 0.0;
-        if (!(sc->bb > 0.0))
-            sc->stop = 3;
-        else if (!isfinite(v[0]) || !isfinite(v[1]))
-            sc->stop = 2;
-        else
-            sc->stop = (v[1] <= sc->tol2 * sc->bb) ? 1 : 0;
-    }
+    store_block_partials<2>(v, partials);
 }
 
 // Residual replacement: the working residual becomes the FP64 true residual
@@ -1462,11 +1449,7 @@ __global__ __launch_bounds__(kBlock) void k_bstats(int64_t n, const double *__re
         s2 += bi * bi;
     }
     double v[3] = {s, s2, bad};
-    if (grid_sum<3>(v, partials, &sc->counter[2]) && threadIdx.x == 0) {
-        sc->sumb = v[0];
-        sc->bb_raw = v[1];
-        sc->nonfinite = v[2];
-    }
+    store_block_partials<3>(v, partials);
 }
 
 __global__ __launch_bounds__(kBlock) void k_prepare_x(int64_t n, double *__restrict__ x,
@@ -1499,10 +1482,7 @@ __global__ __launch_bounds__(kBlock) void k_residual(int64_t n, const double *__
         sbb += bi * bi;
     }
     double v[2] = {sr, sbb};
-    if (grid_sum<2>(v, partials, &sc->counter[2]) && threadIdx.x == 0) {
-        sc->sum_r = v[0];
-        sc->bb = v[1];
-    }
+    store_block_partials<2>(v, partials);
 }
 
 __global__ __launch_bounds__(kBlock) void k_project_norm(int64_t n, double *__restrict__ r,
@@ -1521,7 +1501,7 @@ __global__ __launch_bounds__(kBlock) void k_project_norm(int64_t n, double *__re
         rr += ri * ri;
     }
     double v[1] = {rr};
-    if (grid_sum<1>(v, partials, &sc->counter[2]) && threadIdx.x == 0) sc->rr = v[0];
+    store_block_partials<1>(v, partials);
 }
 
 __global__ __launch_bounds__(kBlock) void k_cast_scaled(int64_t n, const double *__restrict__ r64,
@@ -1583,7 +1563,7 @@ __global__ __launch_bounds__(kBlock) void k_wdot(int64_t n, const double *__rest
     double s = 0.0;
     GRID_STRIDE(i, n) s += w[i] * x[i];
     double v[1] = {s};
-    if (grid_sum<1>(v, partials, &sc->counter[2]) && threadIdx.x == 0) sc->wx = v[0];
+    store_block_partials<1>(v, partials);
 }
 
 __global__ __launch_bounds__(kBlock) void k_shift(int64_t n, double *__restrict__ x,
@@ -1936,9 +1916,10 @@ static hns_status init_line_t(int64_t n, int line_len, T *r, T *p, const T *lfac
     const int NC = line_cols_per_block(line_len);
     const int G = line_grid(n, line_len);
     k_init_line<T><<<G, kBlock, (size_t)4 * NC * line_len * sizeof(T), s>>>(
-        n, line_len, NC, r, p, lfac, singular ? 1 : 0, bb_from_rr ? 1 : 0, sc,
-        partials + kPartMisc);
-    return check_launch("init_line");
+        n, line_len, NC, r, p, lfac, singular ? 1 : 0, sc, partials + kPartMisc);
+    HNS_TRY(check_launch("init_line"));
+    k_fin_start<<<1, kBlock, 0, s>>>(partials + kPartMisc, G, sc, bb_from_rr ? 1 : 0);
+    return check_launch("fin_start");
 }
 
 hns_status launch_init_line(int64_t n, int line_len, double *r, double *p, const double *lfac,
@@ -1976,6 +1957,8 @@ hns_status launch_init_ic0(int64_t n, const IC0Dev &F, const double *r, double *
 {
     HNS_TRY(ic0_apply(F, r, y, z, s));
     k_init_from_z<<<stream_grid(n), kBlock, 0, s>>>(n, r, z, p, sc, partials + kPartMisc);
+    HNS_TRY(check_launch("init_from_z"));
+    k_fin_start<<<1, kBlock, 0, s>>>(partials + kPartMisc, stream_grid(n), sc, 0);
     return check_launch("init_ic0");
 }
 
@@ -2199,7 +2182,9 @@ hns_status launch_bstats(int64_t n, const double *b, const uint8_t *bc, int bit,
 {
     if (bit < 0) bc = nullptr;
     k_bstats<<<stream_grid(n), kBlock, 0, s>>>(n, b, bc, bit, sc, partials + kPartMisc);
-    return check_launch("bstats");
+    HNS_TRY(check_launch("bstats"));
+    k_fin_bstats<<<1, kBlock, 0, s>>>(partials + kPartMisc, stream_grid(n), sc);
+    return check_launch("fin_bstats");
 }
 
 hns_status launch_prepare_x(int64_t n, double *x, const uint8_t *bc, int bit, bool zero_all,
@@ -2217,7 +2202,9 @@ hns_status launch_residual(int64_t n, const double *b, const double *q, double *
     if (bit < 0) bc = nullptr;
     k_residual<<<stream_grid(n), kBlock, 0, s>>>(n, b, q, r, bc, bit, singular ? 1 : 0, sc,
                                                  partials + kPartMisc);
-    return check_launch("residual");
+    HNS_TRY(check_launch("residual"));
+    k_fin_residual<<<1, kBlock, 0, s>>>(partials + kPartMisc, stream_grid(n), sc);
+    return check_launch("fin_residual");
 }
 
 hns_status launch_init_dir(int64_t n, Prec prec, void *r, void *p, const void *dinv,
@@ -2230,18 +2217,20 @@ hns_status launch_init_dir(int64_t n, Prec prec, void *r, void *p, const void *d
     switch (prec) {
     case Prec::F64:
         k_init_dir<double, double><<<G, kBlock, 0, s>>>(n, (double *)r, (double *)p,
-                                                        (const double *)dinv, sg, bf, sc, P);
+                                                        (const double *)dinv, sg, sc, P);
         break;
     case Prec::F32:
         k_init_dir<float, float><<<G, kBlock, 0, s>>>(n, (float *)r, (float *)p,
-                                                      (const float *)dinv, sg, bf, sc, P);
+                                                      (const float *)dinv, sg, sc, P);
         break;
     case Prec::F32Store:
         k_init_dir<double, float><<<G, kBlock, 0, s>>>(n, (double *)r, (double *)p,
-                                                       (const float *)dinv, sg, bf, sc, P);
+                                                       (const float *)dinv, sg, sc, P);
         break;
     }
-    return check_launch("init_dir");
+    HNS_TRY(check_launch("init_dir"));
+    k_fin_start<<<1, kBlock, 0, s>>>(P, G, sc, bf);
+    return check_launch("fin_start");
 }
 
 hns_status launch_replace_residual(int64_t n, Prec prec, const double *r64, void *r, void *p,
@@ -2288,7 +2277,9 @@ hns_status launch_scale_in(int64_t n, Prec prec, const double *r64, void *r, voi
         set_error("the Jacobi-scaled recurrence runs in FP64 or FP32");
         return HNS_ERR_INVALID;
     }
-    return check_launch("scale_in");
+    HNS_TRY(check_launch("scale_in"));
+    k_fin_start<<<1, kBlock, 0, s>>>(P, G, sc, 0);
+    return check_launch("fin_start");
 }
 
 hns_status launch_scale_out(int64_t n, Prec prec, double *x, void *dx, const double *s_half,
@@ -2341,7 +2332,9 @@ hns_status launch_project_norm(int64_t n, double *r, bool singular, Scalars *sc,
 {
     k_project_norm<<<stream_grid(n), kBlock, 0, s>>>(n, r, singular ? 1 : 0, sc,
                                                      partials + kPartMisc);
-    return check_launch("project_norm");
+    HNS_TRY(check_launch("project_norm"));
+    k_fin_one<<<1, kBlock, 0, s>>>(partials + kPartMisc, stream_grid(n), sc, 0);
+    return check_launch("fin_norm");
 }
 
 hns_status launch_cast_scaled(int64_t n, const double *r64, float *r32, float *d32,
@@ -2381,6 +2374,8 @@ hns_status launch_normalise(int64_t n, double *x, const double *lumped, double l
 {
     k_wdot<<<stream_grid(n), kBlock, 0, s>>>(n, lumped, x, sc, partials + kPartMisc);
     HNS_TRY(check_launch("wdot"));
+    k_fin_one<<<1, kBlock, 0, s>>>(partials + kPartMisc, stream_grid(n), sc, 1);
+    HNS_TRY(check_launch("fin_wdot"));
     k_shift<<<stream_grid(n), kBlock, 0, s>>>(n, x, sc, lumped_sum);
     return check_launch("shift");
 }
