@@ -280,23 +280,6 @@ static hns_status run_chunks(const SolveCtx &c, int which, Prec prec, void *x, v
     return HNS_OK;
 }
 
-static hns_status begin_solve(const SolveCtx &c, hns_solve_info *info)
-{
-    hns_operator *op = c.op;
-    Workspace *w = c.w;
-    reset_scalars(w->host[0], c.tol);
-    HNS_TRY(push_scalars(w, 0, c.s));
-    HNS_TRY(launch_bstats(op->n, c.b, op->bc, c.bit, w->sc, w->partials, c.s));
-    HNS_TRY(launch_prepare_x(op->n, c.x, op->bc, c.bit, false, c.s));
-    HNS_TRY(pull_scalars(w, 0, c.s));
-    if (w->host[0].nonfinite > 0) {
-        set_error("right-hand side has %.0f non-finite entries", w->host[0].nonfinite);
-        return HNS_ERR_INVALID;
-    }
-    info->removed_mean = c.singular ? w->host[0].sumb / (double)op->n : 0.0;
-    return HNS_OK;
-}
-
 // r = b - A x in FP64 (projected in the pure-Neumann case) into w->r; sum of
 // squares into sc[0].rr, |b|^2 into sc[0].bb.
 static hns_status true_residual_fp64(const SolveCtx &c)
@@ -307,6 +290,26 @@ static hns_status true_residual_fp64(const SolveCtx &c)
     HNS_TRY(launch_residual(op->n, c.b, w->q, w->r, op->bc, c.bit, c.singular, w->sc,
                             w->partials, c.s));
     HNS_TRY(launch_project_norm(op->n, w->r, c.singular, w->sc, w->partials, c.s));
+    return HNS_OK;
+}
+
+// Start of a solve: statistics of b, Dirichlet entries of x zeroed, then the
+// FP64 true residual, and one read of the scalars for all of them.
+static hns_status begin_solve(const SolveCtx &c, hns_solve_info *info)
+{
+    hns_operator *op = c.op;
+    Workspace *w = c.w;
+    reset_scalars(w->host[0], c.tol);
+    HNS_TRY(push_scalars(w, 0, c.s));
+    HNS_TRY(launch_bstats(op->n, c.b, op->bc, c.bit, w->sc, w->partials, c.s));
+    HNS_TRY(launch_prepare_x(op->n, c.x, op->bc, c.bit, false, c.s));
+    HNS_TRY(true_residual_fp64(c));
+    HNS_TRY(pull_scalars(w, 0, c.s));
+    if (w->host[0].nonfinite > 0) {
+        set_error("right-hand side has %.0f non-finite entries", w->host[0].nonfinite);
+        return HNS_ERR_INVALID;
+    }
+    info->removed_mean = c.singular ? w->host[0].sumb / (double)op->n : 0.0;
     return HNS_OK;
 }
 
@@ -338,8 +341,6 @@ static hns_status solve_fp64_vectors(const SolveCtx &c, hns_solve_info *info, Pr
     hns_operator *op = c.op;
     Workspace *w = c.w;
     HNS_TRY(begin_solve(c, info));
-    HNS_TRY(true_residual_fp64(c));
-    HNS_TRY(pull_scalars(w, 0, c.s));
     Scalars &h = w->host[0];
     info->outer_iterations = 0;
     if (!(h.bb > 0.0)) {  // b = 0
@@ -378,7 +379,9 @@ static hns_status solve_fp64_vectors(const SolveCtx &c, hns_solve_info *info, Pr
             else
                 HNS_TRY(launch_init_dir(op->n, prec, w->r, w->p, dinv, false, false, w->sc,
                                         w->partials, c.s));
-            HNS_TRY(pull_scalars(w, 0, c.s));
+            // no read here: if the start already stopped the recurrence
+            // (converged, non-finite), the chunk's kernels exit at once and
+            // its read reports it
             since = 0;
             fresh = false;
         }
@@ -449,8 +452,6 @@ static hns_status solve_mixed_restart(const SolveCtx &c, hns_solve_info *info)
     hns_operator *op = c.op;
     Workspace *w = c.w;
     HNS_TRY(begin_solve(c, info));
-    HNS_TRY(true_residual_fp64(c));
-    HNS_TRY(pull_scalars(w, 0, c.s));
     Scalars &h = w->host[0];
     Scalars &hi = w->host[1];
     info->outer_iterations = 0;
@@ -479,7 +480,6 @@ static hns_status solve_mixed_restart(const SolveCtx &c, hns_solve_info *info)
         HNS_TRY(push_scalars(w, 1, c.s));
         HNS_TRY(launch_init_dir(op->n, Prec::F32, w->r32, w->p32, op->dinv32, false, true,
                                 w->sc + 1, w->partials, c.s));
-        HNS_TRY(pull_scalars(w, 1, c.s));
         int since = 0;
         SolveCtx ci = c;
         ci.max_iter = c.max_iter - total_inner;
@@ -509,8 +509,6 @@ static hns_status solve_mixed_replace(const SolveCtx &c, hns_solve_info *info)
     hns_operator *op = c.op;
     Workspace *w = c.w;
     HNS_TRY(begin_solve(c, info));
-    HNS_TRY(true_residual_fp64(c));
-    HNS_TRY(pull_scalars(w, 0, c.s));
     Scalars &h = w->host[0];
     Scalars &hi = w->host[1];
     info->outer_iterations = 0;
@@ -542,7 +540,6 @@ static hns_status solve_mixed_replace(const SolveCtx &c, hns_solve_info *info)
             else
                 HNS_TRY(launch_init_dir(op->n, Prec::F32, w->r32, w->p32, op->dinv32, false,
                                         false, w->sc + 1, w->partials, c.s));
-            HNS_TRY(pull_scalars(w, 1, c.s));
             since = 0;
             fresh = false;
         }

@@ -64,3 +64,39 @@ def test_full_size_pressure_solve_converges(full):
     r -= r.mean()
     assert np.linalg.norm(r) <= 1.01 * wl.tol * np.linalg.norm(bh)
     assert abs(w @ xh) <= 1e-12 * np.abs(w).sum() * np.abs(xh).max()
+
+
+@pytest.fixture(scope="module")
+def largest():
+    """The largest serving mesh, 384x384x24 (3,705,625 nodes): the SpMV and
+    update grids exceed the partials slots there, so the blocks take larger
+    chunks than the default launch shape."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1207_0486_amd.hns import Operator
+    wl = basin.configs.BASIN_256x256x20
+    m = basin.basin_mesh(384, 384, 24, seed=104)
+    yield m, wl, Operator, oracle.helmholtz(m, wl.nu_h, wl.nu_v, wl.dt)
+
+
+@pytest.mark.parametrize("mode", ["fp64", "mixed"])
+def test_largest_mesh_velocity_solve(largest, mode):
+    """Dirichlet set 0 on the largest mesh: eight iterations equal the
+    oracle's Jacobi-PCG iterate (FP64), and the converged solve meets the
+    tolerance in the oracle's residual (FP64 and mixed precision)."""
+    m, wl, Operator, A = largest
+    assert m.n == 3705625
+    op = Operator(m, wl.nu_h, wl.nu_v, wl.dt, kind="helmholtz", keep_fp32=True)
+    d = (m.bc & 1) == 1
+    b = basin.normal_rhs(m.n, 13, dirichlet=d)
+    bt = torch.as_tensor(b, device="cuda")
+    if mode == "fp64":
+        x, info = op.solve(bt, tol=1e-300, max_iter=8, mask_bit=0, check=False)
+        assert info.iterations == 8
+        ref = oracle.pcg(A, b, dirichlet=d, tol=1e-300, maxit=8)
+        xh = x.cpu().numpy()
+        assert np.linalg.norm(xh - ref.x) <= 1e-12 * np.linalg.norm(ref.x)
+    x, info = op.solve(bt, tol=wl.tol, mask_bit=0, mode=mode)
+    assert info.status == 0
+    assert oracle.relres(A, b, x.cpu().numpy(), d) <= 1.01 * wl.tol
+    op.close()
