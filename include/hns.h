@@ -198,16 +198,25 @@ hns_status hns_solve_batched(hns_operator *op, int k, const int *mask_bits,
                              uint32_t mode, void *stream, hns_solve_info *infos);
 
 /* ------------------------------------------------------------------------
- * Batch sessions (continuous batching).  A session owns `capacity` slots =
- * columns of a multi-right-hand-side recurrence on one operator.  Requests
- * join free slots at any time (hns_batch_add), advance together with the
- * requests already running (hns_batch_advance: all running slots share each
- * operator read and each launch), and leave as soon as they finish
- * (hns_batch_take), freeing the slot for the next request.  Per slot the
- * arithmetic is that of hns_solve_batched (per-column scalars, tolerance and
- * iteration cap; HNS_MIXED with FP64 residual replacement).  Calls on one
- * session must not overlap; sessions of different operators may run on
- * different streams concurrently.  Each call returns after its work on
+ * Batch sessions (continuous batching).  A session owns `capacity` slots on
+ * one operator.  Requests join free slots at any time (hns_batch_add),
+ * advance together with the requests already running (hns_batch_advance),
+ * and leave as soon as they finish (hns_batch_take), freeing the slot for
+ * the next request.  Two forms, chosen at hns_batch_open by the operator's
+ * "session_mode":
+ *  - shared block: the slots are the columns of one multi-right-hand-side
+ *    recurrence (all running slots share each operator read and each launch);
+ *    per slot the arithmetic is that of hns_solve_batched (per-column
+ *    scalars, tolerance and iteration cap; HNS_MIXED with FP64 residual
+ *    replacement);
+ *  - per slot: every slot runs hns_solve's own point-Jacobi recurrence
+ *    (HNS_MIXED as mixed_variant 0), its answer bitwise that of hns_solve
+ *    with x0 = 0; an advance enqueues one chunk of every running slot and
+ *    waits once.  With one or two slots sharing the operator read saves
+ *    nothing next to the vector traffic, and a half-empty block still moves
+ *    every column, so this is the default there.
+ * Calls on one session must not overlap; sessions of different operators may
+ * run on different streams concurrently.  Each call returns after its work on
  * `stream` has completed.
  * ------------------------------------------------------------------------ */
 typedef struct hns_batch hns_batch;
@@ -321,6 +330,9 @@ int hns_operator_line_len(const hns_operator *op);
  *                  diag(A)).  The scaled operator (FP64, and FP32 when the
  *                  operator keeps FP32 values) is computed on the device on
  *                  first use and stays resident.  0 = the unscaled recurrence.
+ *   "session_mode" form of the batch sessions opened afterwards: 0 (default)
+ *                  per-slot recurrences up to 2 slots, the shared block above;
+ *                  1 always the shared block; 2 always per slot
  *   "precond"      0 = point Jacobi, the inverse diagonal (default; the
  *                  diagonal preconditioner of the paper's Sec. 5 remarks);
  *                  1 = vertical-line blocks: the inverse of the tridiagonal

@@ -1311,6 +1311,7 @@ hns_status tune_batched(hns_operator *op, BWorkspace *w, int K, bool mixed, hipS
 // ===========================================================================
 struct hns_batch {
     hns_operator *op = nullptr;
+    hns::SlotSession *ss = nullptr;   // per-slot recurrences (then no block below)
     hns::BWorkspace *w = nullptr;
     double *B = nullptr;
     double *X = nullptr;
@@ -1406,6 +1407,8 @@ extern "C" {
 size_t hns_batch_footprint(const hns_operator *op, int capacity, uint32_t mode)
 {
     if (!op || capacity < 1) return 0;
+    if (slot_session_wanted(op, capacity))
+        return slot_session_bytes(op, capacity, mode == HNS_MIXED);
     return bworkspace_bytes(op->n, capacity, mode == HNS_MIXED) +
            2 * (size_t)op->n * capacity * sizeof(double) + 256;
 }
@@ -1422,6 +1425,15 @@ hns_status hns_batch_open(hns_operator *op, int capacity, uint32_t mode, hns_bat
     bt->op = op;
     bt->K = capacity;
     bt->mixed = (mode == HNS_MIXED);
+    if (slot_session_wanted(op, capacity)) {
+        const hns_status st = slot_session_open(op, capacity, bt->mixed, &bt->ss);
+        if (st != HNS_OK) {
+            delete bt;
+            return st;
+        }
+        *out = bt;
+        return HNS_OK;
+    }
     bt->max_iter.assign(capacity, 0);
     bt->iter_at_break.assign(capacity, -1);
     hns_status st = create_bworkspace(op->n, capacity, bt->mixed, &bt->w);
@@ -1476,6 +1488,11 @@ hns_status hns_batch_open(hns_operator *op, int capacity, uint32_t mode, hns_bat
 void hns_batch_close(hns_batch *bt)
 {
     if (!bt) return;
+    if (bt->ss) {
+        slot_session_close(bt->ss);
+        delete bt;
+        return;
+    }
     (void)hipDeviceSynchronize();
     if (bt->w) destroy_bworkspace(bt->w);
     if (bt->B) (void)hipFree(bt->B);
@@ -1493,6 +1510,8 @@ hns_status hns_batch_add(hns_batch *bt, int count, const int *slots, const int *
         return HNS_ERR_INVALID;
     }
     hipStream_t s = (hipStream_t)stream;
+    if (bt->ss)
+        return slot_session_add(bt->ss, count, slots, mask_bits, b_devs, tols, max_iters, s);
     hns_operator *op = bt->op;
     BWorkspace *w = bt->w;
     const int K = bt->K;
@@ -1562,6 +1581,7 @@ hns_status hns_batch_advance(hns_batch *bt, int iterations, void *stream, int *a
         return HNS_ERR_INVALID;
     }
     hipStream_t s = (hipStream_t)stream;
+    if (bt->ss) return slot_session_advance(bt->ss, iterations, s, active_out);
     BCtx c{bt->op, bt->w, bt->K, bt->V, bt->B, bt->X, s, bt->mixed};
     HNS_TRY(session_pull(bt, s));
     int done = 0, active = 0;
@@ -1585,6 +1605,7 @@ hns_status hns_batch_poll(hns_batch *bt, int *states, hns_solve_info *infos, voi
         set_error("hns_batch_poll: bad arguments");
         return HNS_ERR_INVALID;
     }
+    if (bt->ss) return slot_session_poll(bt->ss, states, infos);
     HNS_TRY(session_pull(bt, (hipStream_t)stream));
     for (int j = 0; j < bt->K; ++j) {
         const BCol &h = bt->w->host[j];
@@ -1615,6 +1636,7 @@ hns_status hns_batch_take(hns_batch *bt, int slot, double *x_dev, hns_solve_info
         return HNS_ERR_INVALID;
     }
     hipStream_t s = (hipStream_t)stream;
+    if (bt->ss) return slot_session_take(bt->ss, slot, x_dev, info, s);
     BWorkspace *w = bt->w;
     HNS_TRY(session_pull(bt, s));
     BCol &h = w->host[slot];

@@ -193,6 +193,9 @@ struct hns_operator {
     // FP32), with s = D^-1/2 and w = diag(A) in FP32; built on first use
     // (under line_mutex).
     int jacobi_scaling = 1;
+    // batch sessions: 0 per-slot recurrences up to 2 slots, the shared
+    // multi-right-hand-side block above; 1 always the block; 2 always per slot
+    int session_mode = 0;
     hns::DevMatrix S;
     double *jac_s = nullptr;
     float *jac_w = nullptr;
@@ -204,6 +207,20 @@ struct hns_operator {
 };
 
 namespace hns {
+
+// per-slot batch sessions (solve.hip)
+struct SlotSession;
+bool slot_session_wanted(const hns_operator *op, int capacity);
+size_t slot_session_bytes(const hns_operator *op, int capacity, bool mixed);
+hns_status slot_session_open(hns_operator *op, int capacity, bool mixed, SlotSession **out);
+void slot_session_close(SlotSession *ss);
+hns_status slot_session_add(SlotSession *ss, int count, const int *slots, const int *mask_bits,
+                            const double *const *b_devs, const double *tols,
+                            const int *max_iters, hipStream_t s);
+hns_status slot_session_advance(SlotSession *ss, int iterations, hipStream_t s, int *active_out);
+hns_status slot_session_poll(SlotSession *ss, int *states, hns_solve_info *infos);
+hns_status slot_session_take(SlotSession *ss, int slot, double *x_dev, hns_solve_info *info,
+                             hipStream_t s);
 
 // batched.hip
 hns_status create_bworkspace(int64_t n, int K, bool mixed, BWorkspace **out);

@@ -1,4 +1,6 @@
 // Host drivers of the CG solves and the C ABI of hns.h.
+#include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -328,37 +330,106 @@ static hns_status finish_solve(const SolveCtx &c, hns_solve_info *info, hns_stat
     return status;
 }
 
-// Jacobi-PCG of one recurrence with FP64 vectors on the device; `prec`
-// selects FP64 (plain solve) or FP32 matrix/diagonal storage.  Whenever the
-// recursive residual has fallen below `drop` times the last true residual
-// (or below the tolerance), the true residual b - A x is recomputed with the
-// FP64 matrix.  At the tolerance the solve ends if the true residual agrees;
-// otherwise the recurrence continues from the true residual: a full restart
-// (fresh direction) in the plain FP64 solve, a residual replacement that
-// keeps the direction in the FP32-storage variant.
-static hns_status solve_fp64_vectors(const SolveCtx &c, hns_solve_info *info, Prec prec)
-{
-    hns_operator *op = c.op;
-    Workspace *w = c.w;
-    HNS_TRY(begin_solve(c, info));
-    Scalars &h = w->host[0];
-    info->outer_iterations = 0;
-    if (!(h.bb > 0.0)) {  // b = 0
-        HNS_TRY(launch_prepare_x(op->n, c.x, nullptr, -1, true, c.s));
-        return finish_solve(c, info, HNS_OK);
-    }
-    const bool storage = (prec == Prec::F32Store);
-    const void *dinv = storage ? (const void *)op->dinv32 : (const void *)op->dinv;
-    const double tol2 = c.tol * c.tol;
-    const double drop2 = storage ? op->replace_drop * op->replace_drop : 0.0;
+// A single-right-hand-side solve advanced one chunk of iterations at a time:
+// hns_solve runs it to the end, a per-slot batch session interleaves several
+// on one stream.  begin() computes the statistics of b and the first FP64
+// true residual; enqueue() starts a recurrence segment when one is due and
+// enqueues one chunk of CG iterations and the read of its scalars; after()
+// runs once the stream has been waited for: when the recurrence stopped (or
+// the iteration cap was reached) it recomputes the FP64 true residual and
+// decides between the end of the solve, a restart and a residual
+// replacement; end() normalises and reports.
+//
+// Recurrences:
+//  - FP64 vectors (prec F64, or F32Store: FP32 matrix and diagonal): whenever
+//    the recursive residual has fallen below the tolerance (F64) or by
+//    `replace_drop` (F32Store), b - A x is recomputed with the FP64 matrix;
+//    at the tolerance the solve ends if it agrees, else the recurrence
+//    continues from it (a full restart in F64, a residual replacement that
+//    keeps the direction in F32Store).
+//  - mixed: one FP32 recurrence (matrix, vectors and diagonal in FP32) keeps
+//    its search direction across refinement steps; whenever its recursive
+//    residual has dropped by `replace_drop` since the last FP64 residual, the
+//    FP32 iterate is added to the FP64 solution, the true residual is
+//    recomputed in FP64, and the recurrence continues from it.
+struct ChunkedSolve {
+    SolveCtx c;
+    hns_solve_info *info = nullptr;
+    bool mixed = false;
+    Prec prec = Prec::F64;       // FP64-vector recurrence: F64 or F32Store
+    bool finished = false;
+    bool zero_b = false;
     hns_status status = HNS_NOT_CONVERGED;
-    int since = 0, replacements = 0, stalls = 0, floor_checks = 0;
-    double rr_true = h.rr, bb = h.bb, rr_prev = h.rr, rr_best = INFINITY;
     bool fresh = true;
-    while (rr_true > tol2 * bb) {
-        if (fresh) {
-            // new direction from the true residual in w->r
-            if (storage) {  // next stop: residual down by `drop` (or at tol)
+    int since = 0, replacements = 0, stalls = 0, floor_checks = 0, before = 0;
+    double tol2 = 0, drop2 = 0, rr_true = 0, bb = 0, rr_prev = 0, rr_best = INFINITY;
+    const void *dinv = nullptr;
+
+    int which() const { return mixed ? 1 : 0; }
+
+    hns_status begin()
+    {
+        hns_operator *op = c.op;
+        Workspace *w = c.w;
+        info->outer_iterations = 0;
+        HNS_TRY(begin_solve(c, info));
+        Scalars &h = w->host[0];
+        if (!(h.bb > 0.0)) {  // b = 0
+            HNS_TRY(launch_prepare_x(op->n, c.x, nullptr, -1, true, c.s));
+            zero_b = true;
+            status = HNS_OK;
+            finished = true;
+            return HNS_OK;
+        }
+        tol2 = c.tol * c.tol;
+        if (mixed) {
+            drop2 = op->replace_drop * op->replace_drop;
+            rr_prev = h.rr;
+            if (!(h.rr > tol2 * h.bb)) {
+                status = HNS_OK;
+                finished = true;
+            }
+        } else {
+            const bool storage = (prec == Prec::F32Store);
+            dinv = storage ? (const void *)op->dinv32 : (const void *)op->dinv;
+            drop2 = storage ? op->replace_drop * op->replace_drop : 0.0;
+            rr_true = h.rr;
+            bb = h.bb;
+            rr_prev = h.rr;
+            if (!(rr_true > tol2 * bb)) {
+                status = HNS_OK;
+                finished = true;
+            }
+        }
+        return HNS_OK;
+    }
+
+    // start of a recurrence segment from the FP64 true residual in w->r
+    hns_status start_segment()
+    {
+        hns_operator *op = c.op;
+        Workspace *w = c.w;
+        Scalars &h = w->host[0];
+        if (mixed) {
+            Scalars &hi = w->host[1];
+            const double thr2 = std::max(drop2, tol2 * h.bb / h.rr);
+            if (!c.scaled) HNS_TRY(launch_cast(op->n, w->r, w->r32, w->d32, c.s));
+            reset_scalars(hi, 0.0);
+            hi.tol2 = thr2;
+            hi.bb = h.rr;
+            hi.iter = info->iterations;
+            HNS_TRY(push_scalars(w, 1, c.s));
+            if (c.scaled)   // r32 = (float)(D^-1/2 r_A), p = r32, correction d32 = 0
+                HNS_TRY(launch_scale_in(op->n, Prec::F32, w->r, w->r32, w->p32, w->d32,
+                                        op->jac_s, w->sc + 1, w->partials, c.s));
+            else if (c.lfac32)
+                HNS_TRY(launch_init_line(op->n, op->line_len, w->r32, w->p32, c.lfac32, false,
+                                         false, w->sc + 1, w->partials, c.s));
+            else
+                HNS_TRY(launch_init_dir(op->n, Prec::F32, w->r32, w->p32, op->dinv32, false,
+                                        false, w->sc + 1, w->partials, c.s));
+        } else {
+            if (prec == Prec::F32Store) {  // next stop: residual down by `drop` (or at tol)
                 h.tol2 = std::max(tol2 * bb / rr_true, drop2);
                 h.bb = rr_true;
             } else {
@@ -379,24 +450,105 @@ static hns_status solve_fp64_vectors(const SolveCtx &c, hns_solve_info *info, Pr
             else
                 HNS_TRY(launch_init_dir(op->n, prec, w->r, w->p, dinv, false, false, w->sc,
                                         w->partials, c.s));
-            // no read here: if the start already stopped the recurrence
-            // (converged, non-finite), the chunk's kernels exit at once and
-            // its read reports it
-            since = 0;
-            fresh = false;
         }
-        if (c.scaled) {
-            // the scaled recurrence accumulates its correction D^1/2 dx in w->z
-            if (h.stop == 0) HNS_TRY(run_chunks(c, 0, prec, w->z, w->r, w->p, w->q, nullptr, &since));
-            HNS_TRY(launch_scale_out(op->n, Prec::F64, c.x, w->z, op->jac_s, c.s));
-        } else if (h.stop == 0) {
-            HNS_TRY(run_chunks(c, 0, prec, c.x, w->r, w->p, w->q, dinv, &since));
+        // no read here: if the start already stopped the recurrence
+        // (converged, non-finite), the chunk's kernels exit at once and its
+        // read reports it
+        since = 0;
+        fresh = false;
+        return HNS_OK;
+    }
+
+    // At most `budget` (and `check_every`) iterations, then the read of the
+    // recurrence's scalars into the pinned mirror; nothing is waited for.
+    hns_status enqueue(int budget)
+    {
+        hns_operator *op = c.op;
+        Workspace *w = c.w;
+        if (fresh) HNS_TRY(start_segment());
+        Scalars &hr = w->host[which()];
+        before = hr.iter;
+        const int chunk = std::min({c.max_iter - hr.iter, op->check_every, budget});
+        if (chunk > 0 && hr.stop == 0) {
+            const Prec p = mixed ? Prec::F32 : prec;
+            void *x = mixed ? (void *)w->d32 : c.scaled ? (void *)w->z : (void *)c.x;
+            void *r = mixed ? (void *)w->r32 : (void *)w->r;
+            void *pp = mixed ? (void *)w->p32 : (void *)w->p;
+            void *q = mixed ? (void *)w->q32 : (void *)w->q;
+            const void *di = c.scaled ? nullptr : mixed ? (const void *)op->dinv32 : dinv;
+            const void *lf = p == Prec::F64   ? (const void *)c.lfac
+                             : p == Prec::F32 ? (const void *)c.lfac32
+                                              : nullptr;
+            HNS_TRY(enqueue_iterations(op, w, p, c.bit, x, r, pp, q, di, w->sc + which(), chunk,
+                                       since, c.s, lf, p == Prec::F64 ? c.ic : nullptr,
+                                       c.scaled));
         }
+        HNS_TRY_HIP(hipMemcpyAsync(&w->host[which()], w->sc + which(), sizeof(Scalars),
+                                   hipMemcpyDeviceToHost, c.s));
+        return HNS_OK;
+    }
+
+    hns_status after()
+    {
+        hns_operator *op = c.op;
+        Workspace *w = c.w;
+        Scalars &h = w->host[0];
+        Scalars &hr = w->host[which()];
+        since += hr.iter - before;
+        HNS_TRY(account_iterations(op, w, mixed, hr.iter - before));
+        if (hr.stop == 0 && hr.iter < c.max_iter) return HNS_OK;   // still running
+        if (mixed) {
+            Scalars &hi = w->host[1];
+            info->iterations = hi.iter;
+            const bool broke = (hi.stop == 2);
+            // collect the FP32 correction and recompute the true residual in FP64
+            if (c.scaled)
+                HNS_TRY(launch_scale_out(op->n, Prec::F32, c.x, w->d32, op->jac_s, c.s));
+            else
+                HNS_TRY(launch_accumulate(op->n, c.x, w->d32, c.s));
+            HNS_TRY(true_residual_fp64(c));
+            HNS_TRY(pull_scalars(w, 0, c.s));
+            ++replacements;
+            if (h.rr <= tol2 * h.bb) return done(HNS_OK);
+            if (hi.stop != 1 && !broke) return done(HNS_NOT_CONVERGED);  // budget spent
+            stalls = (h.rr > 0.81 * rr_prev) ? stalls + 1 : 0;
+            if (stalls >= 3) {
+                set_error("mixed-precision refinement stagnated at relative residual %g",
+                          std::sqrt(h.rr / h.bb));
+                return done(HNS_NOT_CONVERGED);
+            }
+            rr_prev = h.rr;
+            if (broke) {
+                if (stalls > 0) {
+                    set_error("FP32 CG broke down without progress after %d iterations",
+                              hi.iter);
+                    return done(HNS_ERR_BREAKDOWN);
+                }
+                fresh = true;  // new direction from the new true residual
+                return HNS_OK;
+            }
+            HNS_TRY(launch_set_threshold(w->sc + 1, std::max(drop2, tol2 * h.bb / h.rr), h.rr,
+                                         c.s));
+            if (c.scaled)
+                HNS_TRY(launch_replace_scaled(op->n, w->r, w->r32, w->p32, op->jac_s, w->sc + 1,
+                                              w->partials, (since - 1) & 1, c.s));
+            else if (c.lfac32)
+                HNS_TRY(launch_replace_line(op->n, op->line_len, w->r, w->r32, (float *)w->z,
+                                            w->p32, c.lfac32, w->sc + 1, w->partials,
+                                            (since - 1) & 1, op->A.vec_it, c.s));
+            else
+                HNS_TRY(launch_replace_residual(op->n, Prec::F32, w->r, w->r32, w->p32,
+                                                op->dinv32, w->sc + 1, w->partials,
+                                                (since - 1) & 1, c.s));
+            hi.stop = 0;
+            return HNS_OK;
+        }
+        const bool storage = (prec == Prec::F32Store);
+        if (c.scaled) HNS_TRY(launch_scale_out(op->n, Prec::F64, c.x, w->z, op->jac_s, c.s));
         info->iterations = h.iter;
         if (h.stop == 2) {
-            status = HNS_ERR_BREAKDOWN;
             set_error("CG breakdown after %d iterations (p^T A p = %g)", h.iter, h.gamma);
-            break;
+            return done(HNS_ERR_BREAKDOWN);
         }
         const bool hit = (h.stop == 1);
         // true residual, FP64 matrix
@@ -406,11 +558,8 @@ static hns_status solve_fp64_vectors(const SolveCtx &c, hns_solve_info *info, Pr
         h.iter = iters;
         rr_true = h.rr;
         ++replacements;
-        if (rr_true <= tol2 * bb) {
-            status = HNS_OK;
-            break;
-        }
-        if (!hit || h.iter >= c.max_iter) break;  // budget spent
+        if (rr_true <= tol2 * bb) return done(HNS_OK);
+        if (!hit || h.iter >= c.max_iter) return done(HNS_NOT_CONVERGED);  // budget spent
         if (!storage) {
             // the rounding floor: three failed checks in a row that do not
             // halve the smallest true residual seen at a check end the solve
@@ -419,16 +568,16 @@ static hns_status solve_fp64_vectors(const SolveCtx &c, hns_solve_info *info, Pr
             if (floor_checks >= 3) {
                 set_error("true residual stalled at %g, above the tolerance (rounding floor)",
                           std::sqrt(rr_true / bb));
-                break;
+                return done(HNS_NOT_CONVERGED);
             }
             fresh = true;  // restart from the true residual
-            continue;
+            return HNS_OK;
         }
         stalls = (rr_true > 0.81 * rr_prev) ? stalls + 1 : 0;
         if (stalls >= 3) {
             set_error("FP32-storage refinement stagnated at relative residual %g",
                       std::sqrt(rr_true / bb));
-            break;
+            return done(HNS_NOT_CONVERGED);
         }
         rr_prev = rr_true;
         // residual replacement: keep the direction, continue from r_true
@@ -437,12 +586,42 @@ static hns_status solve_fp64_vectors(const SolveCtx &c, hns_solve_info *info, Pr
         HNS_TRY(launch_replace_residual(op->n, prec, w->r, nullptr, w->p, dinv, w->sc,
                                         w->partials, (since - 1) & 1, c.s));
         h.stop = 0;
+        return HNS_OK;
     }
-    // report the FP64 residual against |b|^2
-    h.bb = bb;
-    h.rr = rr_true;
-    info->outer_iterations = storage ? replacements : 1;
-    return finish_solve(c, info, status);
+
+    hns_status done(hns_status st)
+    {
+        status = st;
+        finished = true;
+        return HNS_OK;
+    }
+
+    hns_status end()
+    {
+        if (!zero_b) {
+            if (mixed) {
+                info->outer_iterations = replacements;
+            } else {
+                // report the FP64 residual against |b|^2
+                Scalars &h = c.w->host[0];
+                h.bb = bb;
+                h.rr = rr_true;
+                info->outer_iterations = (prec == Prec::F32Store) ? replacements : 1;
+            }
+        }
+        return finish_solve(c, info, status);
+    }
+};
+
+static hns_status run_to_end(ChunkedSolve &cs)
+{
+    HNS_TRY(cs.begin());
+    while (!cs.finished) {
+        HNS_TRY(cs.enqueue(INT_MAX));
+        HNS_TRY_HIP(hipStreamSynchronize(cs.c.s));
+        HNS_TRY(cs.after());
+    }
+    return cs.end();
 }
 
 // Classic mixed-precision refinement: each FP64 correction step solves
@@ -499,111 +678,285 @@ static hns_status solve_mixed_restart(const SolveCtx &c, hns_solve_info *info)
     return finish_solve(c, info, status);
 }
 
-// Mixed precision with residual replacement: one FP32 CG recurrence (matrix,
-// vectors and diagonal in FP32) keeps its search direction across refinement
-// steps.  Whenever its recursive residual has dropped by `replace_drop` since
-// the last FP64 residual, the FP32 iterate is added to the FP64 solution, the
-// true residual is recomputed in FP64, and the recurrence continues from it.
-static hns_status solve_mixed_replace(const SolveCtx &c, hns_solve_info *info)
+static hns_status solve_fp64(const SolveCtx &c, hns_solve_info *info, Prec prec = Prec::F64)
 {
-    hns_operator *op = c.op;
-    Workspace *w = c.w;
-    HNS_TRY(begin_solve(c, info));
-    Scalars &h = w->host[0];
-    Scalars &hi = w->host[1];
-    info->outer_iterations = 0;
-    if (!(h.bb > 0.0)) {
-        HNS_TRY(launch_prepare_x(op->n, c.x, nullptr, -1, true, c.s));
-        return finish_solve(c, info, HNS_OK);
-    }
-    const double tol2 = c.tol * c.tol;
-    const double drop2 = op->replace_drop * op->replace_drop;
-    hns_status status = HNS_NOT_CONVERGED;
-    int replacements = 0, since = 0, stalls = 0;
-    bool fresh = true;
-    double rr_prev = h.rr;
-    while (h.rr > tol2 * h.bb) {
-        const double thr2 = std::max(drop2, tol2 * h.bb / h.rr);
-        if (fresh) {
-            if (!c.scaled) HNS_TRY(launch_cast(op->n, w->r, w->r32, w->d32, c.s));
-            reset_scalars(hi, 0.0);
-            hi.tol2 = thr2;
-            hi.bb = h.rr;
-            hi.iter = info->iterations;
-            HNS_TRY(push_scalars(w, 1, c.s));
-            if (c.scaled)   // r32 = (float)(D^-1/2 r_A), p = r32, correction d32 = 0
-                HNS_TRY(launch_scale_in(op->n, Prec::F32, w->r, w->r32, w->p32, w->d32,
-                                        op->jac_s, w->sc + 1, w->partials, c.s));
-            else if (c.lfac32)
-                HNS_TRY(launch_init_line(op->n, op->line_len, w->r32, w->p32, c.lfac32, false,
-                                         false, w->sc + 1, w->partials, c.s));
-            else
-                HNS_TRY(launch_init_dir(op->n, Prec::F32, w->r32, w->p32, op->dinv32, false,
-                                        false, w->sc + 1, w->partials, c.s));
-            since = 0;
-            fresh = false;
-        }
-        HNS_TRY(run_chunks(c, 1, Prec::F32, w->d32, w->r32, w->p32, w->q32, op->dinv32, &since));
-        info->iterations = hi.iter;
-        const bool broke = (hi.stop == 2);
-        // collect the FP32 correction and recompute the true residual in FP64
-        if (c.scaled)
-            HNS_TRY(launch_scale_out(op->n, Prec::F32, c.x, w->d32, op->jac_s, c.s));
-        else
-            HNS_TRY(launch_accumulate(op->n, c.x, w->d32, c.s));
-        HNS_TRY(true_residual_fp64(c));
-        HNS_TRY(pull_scalars(w, 0, c.s));
-        ++replacements;
-        if (h.rr <= tol2 * h.bb) {
-            status = HNS_OK;
-            break;
-        }
-        if (hi.stop != 1 && !broke) break;  // iteration budget spent
-        stalls = (h.rr > 0.81 * rr_prev) ? stalls + 1 : 0;
-        if (stalls >= 3) {
-            set_error("mixed-precision refinement stagnated at relative residual %g",
-                      std::sqrt(h.rr / h.bb));
-            break;
-        }
-        rr_prev = h.rr;
-        if (broke) {
-            if (stalls > 0) {
-                status = HNS_ERR_BREAKDOWN;
-                set_error("FP32 CG broke down without progress after %d iterations", hi.iter);
-                break;
-            }
-            fresh = true;  // new direction from the new true residual
-            continue;
-        }
-        HNS_TRY(launch_set_threshold(w->sc + 1, std::max(drop2, tol2 * h.bb / h.rr), h.rr, c.s));
-        if (c.scaled)
-            HNS_TRY(launch_replace_scaled(op->n, w->r, w->r32, w->p32, op->jac_s, w->sc + 1,
-                                          w->partials, (since - 1) & 1, c.s));
-        else if (c.lfac32)
-            HNS_TRY(launch_replace_line(op->n, op->line_len, w->r, w->r32, (float *)w->z, w->p32,
-                                        c.lfac32, w->sc + 1, w->partials, (since - 1) & 1,
-                                        op->A.vec_it, c.s));
-        else
-            HNS_TRY(launch_replace_residual(op->n, Prec::F32, w->r, w->r32, w->p32, op->dinv32,
-                                            w->sc + 1, w->partials, (since - 1) & 1, c.s));
-        hi.stop = 0;
-    }
-    info->outer_iterations = replacements;
-    return finish_solve(c, info, status);
-}
-
-static hns_status solve_fp64(const SolveCtx &c, hns_solve_info *info)
-{
-    return solve_fp64_vectors(c, info, Prec::F64);
+    ChunkedSolve cs;
+    cs.c = c;
+    cs.info = info;
+    cs.prec = prec;
+    return run_to_end(cs);
 }
 
 static hns_status solve_mixed(const SolveCtx &c, hns_solve_info *info)
 {
     switch (c.op->mixed_variant) {
     case 1: return solve_mixed_restart(c, info);
-    case 2: return solve_fp64_vectors(c, info, Prec::F32Store);
-    default: return solve_mixed_replace(c, info);
+    case 2: return solve_fp64(c, info, Prec::F32Store);
+    default: {
+        ChunkedSolve cs;
+        cs.c = c;
+        cs.info = info;
+        cs.mixed = true;
+        return run_to_end(cs);
     }
+    }
+}
+
+// The Jacobi-scaled operator D^-1/2 A D^-1/2 (unit diagonal, upper diagonals
+// only; FP32 values too when A keeps them), s = D^-1/2 and w = diag(A) in
+// FP32, computed on the device on first use.
+static hns_status scaled_operator(hns_operator *op)
+{
+    std::lock_guard<std::mutex> g(op->line_mutex);
+    if (op->S.dia) return HNS_OK;
+    const DevMatrix &A = op->A;
+    const int64_t n = op->n;
+    DevMatrix S;
+    S.n = n;
+    S.nnz = A.nnz;
+    S.fmt = HNS_FMT_SDIA;
+    S.ndiag = A.ndiag;
+    for (int k = 0; k < kMaxDiagWide; ++k) S.off[k] = A.off[k];
+    S.unit = true;
+    S.spmv_it64 = A.spmv_it64;
+    S.spmv_it32 = A.spmv_it32;
+    S.vec_it = A.vec_it;
+    double *sh = nullptr;
+    float *w = nullptr;
+    auto fail = [&](hipError_t e, const char *what) {
+        S.release();
+        if (sh) (void)hipFree(sh);
+        if (w) (void)hipFree(w);
+        set_error("Jacobi scaling: %s failed: %s", what, hipGetErrorString(e));
+        return e == hipErrorOutOfMemory ? HNS_ERR_OOM : HNS_ERR_HIP;
+    };
+    const size_t vals = (size_t)A.ndiag * n;
+    hipError_t e = hipMalloc(&S.dia, vals * sizeof(double));
+    if (e != hipSuccess) return fail(e, "allocation");
+    if (A.dia32) {
+        e = hipMalloc(&S.dia32, vals * sizeof(float));
+        if (e != hipSuccess) return fail(e, "allocation");
+    }
+    e = hipMalloc(&sh, n * sizeof(double));
+    if (e != hipSuccess) return fail(e, "allocation");
+    e = hipMalloc(&w, n * sizeof(float));
+    if (e != hipSuccess) return fail(e, "allocation");
+    hns_status st = launch_jacobi_scale(n, A.ndiag, A.off, A.dia, sh, w, S.dia, S.dia32, nullptr);
+    if (st == HNS_OK) {
+        e = hipDeviceSynchronize();
+        if (e != hipSuccess) return fail(e, "scaling kernels");
+    } else {
+        S.release();
+        (void)hipFree(sh);
+        (void)hipFree(w);
+        return st;
+    }
+    op->S = S;
+    op->jac_s = sh;
+    op->jac_w = w;
+    return HNS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Per-slot batch sessions: every slot runs its own single-right-hand-side
+// recurrence (the chunked solve of hns_solve, point Jacobi, on the
+// Jacobi-scaled operator where hns_solve would use it), and an advance
+// enqueues one chunk of every running slot before it waits once.  For one or
+// two slots the shared operator read of the multi-right-hand-side block saves
+// nothing next to the vector traffic (two columns move as many bytes as two
+// single recurrences), while a half-empty block still moves both columns.
+// ---------------------------------------------------------------------------
+struct SlotSession {
+    hns_operator *op = nullptr;
+    int K = 0;
+    bool mixed = false;
+    bool scaled = false;
+    struct Slot {
+        int state = 0;   // 0 free, 1 running, 2 finished
+        double *b = nullptr, *x = nullptr;
+        Workspace *w = nullptr;
+        ChunkedSolve cs;
+        hns_solve_info info{};
+    };
+    std::vector<Slot> slots;
+};
+
+bool slot_session_wanted(const hns_operator *op, int capacity)
+{
+    return op->session_mode == 2 || (op->session_mode == 0 && capacity <= 2);
+}
+
+static bool session_scaled(const hns_operator *op, bool mixed)
+{
+    return op->jacobi_scaling && op->A.fmt == HNS_FMT_SDIA && op->A.ndiag >= 1 &&
+           op->A.ndiag <= kMaxDiag && op->n > op->small_n && (!mixed || op->A.dia32);
+}
+
+size_t slot_session_bytes(const hns_operator *op, int capacity, bool mixed)
+{
+    const size_t n = (size_t)op->n;
+    size_t per = Workspace::bytes_for(op->n, mixed) + 2 * ((n + 31) & ~size_t(31)) * sizeof(double);
+    if (session_scaled(op, mixed) && !mixed) per += n * sizeof(double);   // scaled correction
+    return per * (size_t)capacity + 256;
+}
+
+void slot_session_close(SlotSession *ss)
+{
+    if (!ss) return;
+    (void)hipDeviceSynchronize();
+    for (auto &sl : ss->slots) {
+        if (sl.b) (void)hipFree(sl.b);
+        delete sl.w;
+    }
+    delete ss;
+}
+
+hns_status slot_session_open(hns_operator *op, int capacity, bool mixed, SlotSession **out)
+{
+    *out = nullptr;
+    SlotSession *ss = new SlotSession();
+    ss->op = op;
+    ss->K = capacity;
+    ss->mixed = mixed;
+    ss->scaled = session_scaled(op, mixed);
+    ss->slots.resize(capacity);
+    auto fail = [&](hns_status st) {
+        slot_session_close(ss);
+        return st;
+    };
+    if (ss->scaled) {
+        const hns_status st = scaled_operator(op);
+        if (st != HNS_OK) return fail(st);
+        if (mixed && !op->S.dia32) ss->scaled = false;
+    }
+    const size_t n = (size_t)op->n;
+    const size_t n_al = (n + 31) & ~size_t(31);   // x 256-byte aligned, as a workspace vector
+    for (auto &sl : ss->slots) {
+        hipError_t e = hipMalloc((void **)&sl.b, 2 * n_al * sizeof(double));
+        if (e != hipSuccess) {
+            sl.b = nullptr;
+            set_error("batch session allocation failed: %s", hipGetErrorString(e));
+            return fail(e == hipErrorOutOfMemory ? HNS_ERR_OOM : HNS_ERR_HIP);
+        }
+        sl.x = sl.b + n_al;
+        sl.w = new Workspace();
+        hns_status st = sl.w->allocate(op->n, mixed);
+        if (st == HNS_OK && ss->scaled && !mixed) st = sl.w->ensure_z();
+        if (st != HNS_OK) return fail(st);
+    }
+    *out = ss;
+    return HNS_OK;
+}
+
+hns_status slot_session_add(SlotSession *ss, int count, const int *slots, const int *mask_bits,
+                            const double *const *b_devs, const double *tols,
+                            const int *max_iters, hipStream_t s)
+{
+    hns_operator *op = ss->op;
+    for (int q = 0; q < count; ++q) {
+        const int j = slots[q];
+        if (j < 0 || j >= ss->K || ss->slots[j].state != 0 || !b_devs[q] || !(tols[q] > 0) ||
+            !std::isfinite(tols[q]) || max_iters[q] < 0 || mask_bits[q] < -1 ||
+            mask_bits[q] > 7 || (mask_bits[q] >= 0 && !op->bc)) {
+            set_error("hns_batch_add: slot %d is not free or its arguments are invalid", j);
+            return HNS_ERR_INVALID;
+        }
+        for (int r = 0; r < q; ++r)
+            if (slots[r] == j) {
+                set_error("hns_batch_add: slot %d listed twice", j);
+                return HNS_ERR_INVALID;
+            }
+    }
+    for (int q = 0; q < count; ++q) {
+        SlotSession::Slot &sl = ss->slots[slots[q]];
+        HNS_TRY_HIP(hipMemcpyAsync(sl.b, b_devs[q], (size_t)op->n * sizeof(double),
+                                   hipMemcpyDeviceToDevice, s));
+        HNS_TRY(launch_prepare_x(op->n, sl.x, nullptr, -1, true, s));
+        memset(&sl.info, 0, sizeof(sl.info));
+        sl.cs = ChunkedSolve();
+        sl.cs.c = SolveCtx{op,       mask_bits[q], op->kind == HNS_POISSON && mask_bits[q] < 0,
+                           sl.b,     sl.x,         tols[q],
+                           max_iters[q], s,        sl.w,
+                           nullptr,  nullptr,      nullptr,
+                           ss->scaled};
+        sl.cs.info = &sl.info;
+        sl.cs.mixed = ss->mixed;
+        const hns_status st = sl.cs.begin();
+        if (st == HNS_ERR_INVALID) {   // non-finite right-hand side: finished at once
+            sl.info.status = HNS_ERR_INVALID;
+            sl.state = 2;
+            continue;
+        }
+        HNS_TRY(st);
+        if (sl.cs.finished) {
+            HNS_TRY(sl.cs.end());
+            sl.state = 2;
+        } else {
+            sl.state = 1;
+        }
+    }
+    return HNS_OK;
+}
+
+hns_status slot_session_advance(SlotSession *ss, int iterations, hipStream_t s, int *active_out)
+{
+    int done = 0;
+    for (;;) {
+        std::vector<SlotSession::Slot *> run;
+        for (auto &sl : ss->slots)
+            if (sl.state == 1) run.push_back(&sl);
+        if (run.empty() || done >= iterations) break;
+        const int budget = std::min(ss->op->check_every, iterations - done);
+        for (auto *sl : run) {
+            sl->cs.c.s = s;
+            HNS_TRY(sl->cs.enqueue(budget));
+        }
+        HNS_TRY_HIP(hipStreamSynchronize(s));
+        for (auto *sl : run) {
+            HNS_TRY(sl->cs.after());
+            if (sl->cs.finished) {
+                HNS_TRY(sl->cs.end());
+                sl->state = 2;
+            }
+        }
+        done += budget;
+    }
+    int active = 0;
+    for (auto &sl : ss->slots) active += (sl.state == 1);
+    if (active_out) *active_out = active;
+    return HNS_OK;
+}
+
+hns_status slot_session_poll(SlotSession *ss, int *states, hns_solve_info *infos)
+{
+    for (int j = 0; j < ss->K; ++j) {
+        const SlotSession::Slot &sl = ss->slots[j];
+        states[j] = sl.state;
+        if (infos) {
+            infos[j] = sl.info;
+            if (sl.state == 1) {
+                infos[j].iterations = sl.w->host[ss->mixed ? 1 : 0].iter;
+                infos[j].status = HNS_NOT_CONVERGED;
+            }
+        }
+    }
+    return HNS_OK;
+}
+
+hns_status slot_session_take(SlotSession *ss, int slot, double *x_dev, hns_solve_info *info,
+                             hipStream_t s)
+{
+    SlotSession::Slot &sl = ss->slots[slot];
+    if (sl.state != 2) {
+        set_error("hns_batch_take: slot %d has no finished solve", slot);
+        return HNS_ERR_INVALID;
+    }
+    HNS_TRY_HIP(hipMemcpyAsync(x_dev, sl.x, (size_t)ss->op->n * sizeof(double),
+                               hipMemcpyDeviceToDevice, s));
+    HNS_TRY_HIP(hipStreamSynchronize(s));
+    if (info) *info = sl.info;
+    sl.state = 0;
+    return HNS_OK;
 }
 
 }  // namespace hns
@@ -988,6 +1341,8 @@ hns_status hns_set_param(hns_operator *op, const char *name, double value)
         op->A.vec_it = op->S.vec_it = (int)value;
     } else if (k == "jacobi_scaling" && (value == 0 || value == 1)) {
         op->jacobi_scaling = (int)value;
+    } else if (k == "session_mode" && (value == 0 || value == 1 || value == 2)) {
+        op->session_mode = (int)value;
     } else if (k == "small_n" && value >= 0 && value <= (double)kSmallMaxN &&
                value == (int64_t)value) {
         op->small_n = (int64_t)value;
@@ -1210,61 +1565,6 @@ static hns_status ic0_factors(hns_operator *op, int bit, const IC0Dev **out)
         slot = D;
     }
     *out = slot;
-    return HNS_OK;
-}
-
-// The Jacobi-scaled operator D^-1/2 A D^-1/2 (unit diagonal, upper diagonals
-// only; FP32 values too when A keeps them), s = D^-1/2 and w = diag(A) in
-// FP32, computed on the device on first use.
-static hns_status scaled_operator(hns_operator *op)
-{
-    std::lock_guard<std::mutex> g(op->line_mutex);
-    if (op->S.dia) return HNS_OK;
-    const DevMatrix &A = op->A;
-    const int64_t n = op->n;
-    DevMatrix S;
-    S.n = n;
-    S.nnz = A.nnz;
-    S.fmt = HNS_FMT_SDIA;
-    S.ndiag = A.ndiag;
-    for (int k = 0; k < kMaxDiagWide; ++k) S.off[k] = A.off[k];
-    S.unit = true;
-    S.spmv_it64 = A.spmv_it64;
-    S.spmv_it32 = A.spmv_it32;
-    S.vec_it = A.vec_it;
-    double *sh = nullptr;
-    float *w = nullptr;
-    auto fail = [&](hipError_t e, const char *what) {
-        S.release();
-        if (sh) (void)hipFree(sh);
-        if (w) (void)hipFree(w);
-        set_error("Jacobi scaling: %s failed: %s", what, hipGetErrorString(e));
-        return e == hipErrorOutOfMemory ? HNS_ERR_OOM : HNS_ERR_HIP;
-    };
-    const size_t vals = (size_t)A.ndiag * n;
-    hipError_t e = hipMalloc(&S.dia, vals * sizeof(double));
-    if (e != hipSuccess) return fail(e, "allocation");
-    if (A.dia32) {
-        e = hipMalloc(&S.dia32, vals * sizeof(float));
-        if (e != hipSuccess) return fail(e, "allocation");
-    }
-    e = hipMalloc(&sh, n * sizeof(double));
-    if (e != hipSuccess) return fail(e, "allocation");
-    e = hipMalloc(&w, n * sizeof(float));
-    if (e != hipSuccess) return fail(e, "allocation");
-    hns_status st = launch_jacobi_scale(n, A.ndiag, A.off, A.dia, sh, w, S.dia, S.dia32, nullptr);
-    if (st == HNS_OK) {
-        e = hipDeviceSynchronize();
-        if (e != hipSuccess) return fail(e, "scaling kernels");
-    } else {
-        S.release();
-        (void)hipFree(sh);
-        (void)hipFree(w);
-        return st;
-    }
-    op->S = S;
-    op->jac_s = sh;
-    op->jac_w = w;
     return HNS_OK;
 }
 

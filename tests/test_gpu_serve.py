@@ -20,14 +20,15 @@ def _make(key):
     return m, 1e3, 1e-2, 3600.0, kind
 
 
+@pytest.mark.parametrize("capacity", [2, 4])   # per-slot sessions, shared block
 @pytest.mark.parametrize("mode", ["fp64", "mixed"])
-def test_served_equals_alone(mode):
+def test_served_equals_alone(mode, capacity):
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_1207_0486_amd.hns import Operator
     from paper_1207_0486_amd.serve import GpuBackend, Request, Server
     be = GpuBackend(_make, mode=mode, check_every=8)
-    srv = Server(be, budget_bytes=4 << 30, capacity=4, chunk=16)
+    srv = Server(be, budget_bytes=4 << 30, capacity=capacity, chunk=16)
     rng = np.random.default_rng(3)
     reqs = []
     for i in range(20):
