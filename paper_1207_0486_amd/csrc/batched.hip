@@ -154,6 +154,32 @@ __device__ __forceinline__ bool any_column(const BCol *__restrict__ cols, int K,
     return __syncthreads_or(mine) != 0;
 }
 
+// The Dirichlet bits of a thread's V columns.  A thread owns the same V
+// columns in every pass of PACK_LOOP (the grid's thread count times V is a
+// multiple of K), so the products read them once, before the loop, and only
+// the row's byte of bc inside it, issued with the other loads: testing
+// cols[j].bit and then bc[i] per column after the products serialised two
+// memory round trips per column and pack.
+template <int V>
+struct ColBits {
+    int bit[V];
+};
+
+template <int V>
+__device__ __forceinline__ ColBits<V> thread_col_bits(const BCol *__restrict__ cols, int K)
+{
+    ColBits<V> cb;
+    const int j0 = (int)((((int64_t)blockIdx.x * kBlock + threadIdx.x) * V) % K);
+#pragma unroll
+    for (int v = 0; v < V; ++v) cb.bit[v] = cols[j0 + v].bit;
+    return cb;
+}
+
+__device__ __forceinline__ bool masked_byte(uint8_t b, int bit)
+{
+    return bit >= 0 && ((b >> bit) & 1u);
+}
+
 template <typename TV, typename TX, int V, bool DOT, int M>
 __global__ __launch_bounds__(kBlock) void k_bspmm_sdia(int64_t n, int K, BOffsets offs,
                                                        const TV *__restrict__ dia,
@@ -170,10 +196,12 @@ __global__ __launch_bounds__(kBlock) void k_bspmm_sdia(int64_t n, int K, BOffset
 #pragma unroll
     for (int v = 0; v < V; ++v) acc[0][v] = 0.0;
     const int64_t np = n * K / V;
+    const ColBits<V> cbits = thread_col_bits<V>(cols, K);
     PACK_LOOP(t, np)
     {
         const int64_t e = t * V;
         const int64_t i = e / K;
+        const uint8_t bci = bc ? bc[i] : (uint8_t)0;
         const auto pi = bld<V>(P, e);
         const TX d = (TX)dia[i];
         TX s[V];
@@ -196,7 +224,7 @@ __global__ __launch_bounds__(kBlock) void k_bspmm_sdia(int64_t n, int K, BOffset
         const int j0 = (int)(e - i * K);
 #pragma unroll
         for (int v = 0; v < V; ++v) {
-            out.v[v] = masked(bc, cols[j0 + v].bit, i) ? (TX)0 : s[v];
+            out.v[v] = masked_byte(bci, cbits.bit[v]) ? (TX)0 : s[v];
             if constexpr (DOT) acc[0][v] += (double)pi.v[v] * (double)out.v[v];
         }
         bst<V>(Q, e, out);
@@ -223,10 +251,12 @@ __global__ __launch_bounds__(kBlock) void k_bspmm_sdia_wide(int64_t n, int K, in
 #pragma unroll
     for (int v = 0; v < V; ++v) acc[0][v] = 0.0;
     const int64_t np = n * K / V;
+    const ColBits<V> cbits = thread_col_bits<V>(cols, K);
     PACK_LOOP(t, np)
     {
         const int64_t e = t * V;
         const int64_t i = e / K;
+        const uint8_t bci = bc ? bc[i] : (uint8_t)0;
         const auto pi = bld<V>(P, e);
         const TX d = (TX)dia[i];
         TX s[V];
@@ -249,7 +279,7 @@ __global__ __launch_bounds__(kBlock) void k_bspmm_sdia_wide(int64_t n, int K, in
         const int j0 = (int)(e - i * K);
 #pragma unroll
         for (int v = 0; v < V; ++v) {
-            out.v[v] = masked(bc, cols[j0 + v].bit, i) ? (TX)0 : s[v];
+            out.v[v] = masked_byte(bci, cbits.bit[v]) ? (TX)0 : s[v];
             if constexpr (DOT) acc[0][v] += (double)pi.v[v] * (double)out.v[v];
         }
         bst<V>(Q, e, out);
@@ -275,10 +305,12 @@ __global__ __launch_bounds__(kBlock) void k_bspmm_csr(int64_t n, int K,
 #pragma unroll
     for (int v = 0; v < V; ++v) acc[0][v] = 0.0;
     const int64_t np = n * K / V;
+    const ColBits<V> cbits = thread_col_bits<V>(cols, K);
     PACK_LOOP(t, np)
     {
         const int64_t e = t * V;
         const int64_t i = e / K;
+        const uint8_t bci = bc ? bc[i] : (uint8_t)0;
         const int j0 = (int)(e - i * K);
         TX s[V];
 #pragma unroll
@@ -293,7 +325,7 @@ __global__ __launch_bounds__(kBlock) void k_bspmm_csr(int64_t n, int K,
         BPack<TX, V> out;
 #pragma unroll
         for (int v = 0; v < V; ++v) {
-            out.v[v] = masked(bc, cols[j0 + v].bit, i) ? (TX)0 : s[v];
+            out.v[v] = masked_byte(bci, cbits.bit[v]) ? (TX)0 : s[v];
             if constexpr (DOT) acc[0][v] += (double)pi.v[v] * (double)out.v[v];
         }
         bst<V>(Q, e, out);
@@ -319,10 +351,12 @@ __global__ __launch_bounds__(kBlock) void k_bspmm_sell(int64_t n, int K,
 #pragma unroll
     for (int v = 0; v < V; ++v) acc[0][v] = 0.0;
     const int64_t np = n * K / V;
+    const ColBits<V> cbits = thread_col_bits<V>(cols, K);
     PACK_LOOP(t, np)
     {
         const int64_t e = t * V;
         const int64_t i = e / K;
+        const uint8_t bci = bc ? bc[i] : (uint8_t)0;
         const int j0 = (int)(e - i * K);
         const int64_t sl = i >> 6;
         const int lane = (int)(i & 63);
@@ -342,7 +376,7 @@ __global__ __launch_bounds__(kBlock) void k_bspmm_sell(int64_t n, int K,
         BPack<TX, V> out;
 #pragma unroll
         for (int v = 0; v < V; ++v) {
-            out.v[v] = masked(bc, cols[j0 + v].bit, i) ? (TX)0 : s[v];
+            out.v[v] = masked_byte(bci, cbits.bit[v]) ? (TX)0 : s[v];
             if constexpr (DOT) acc[0][v] += (double)pi.v[v] * (double)out.v[v];
         }
         bst<V>(Q, e, out);
