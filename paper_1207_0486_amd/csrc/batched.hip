@@ -221,7 +221,6 @@ __global__ __launch_bounds__(kBlock) void k_bspmm_sdia(int64_t n, int K, BOffset
             for (int v = 0; v < V; ++v) s[v] += cu * pu.v[v] + cl * pl.v[v];
         }
         BPack<TX, V> out;
-        const int j0 = (int)(e - i * K);
 #pragma unroll
         for (int v = 0; v < V; ++v) {
             out.v[v] = masked_byte(bci, cbits.bit[v]) ? (TX)0 : s[v];
@@ -276,7 +275,6 @@ __global__ __launch_bounds__(kBlock) void k_bspmm_sdia_wide(int64_t n, int K, in
             for (int v = 0; v < V; ++v) s[v] += cu * pu.v[v] + cl * pl.v[v];
         }
         BPack<TX, V> out;
-        const int j0 = (int)(e - i * K);
 #pragma unroll
         for (int v = 0; v < V; ++v) {
             out.v[v] = masked_byte(bci, cbits.bit[v]) ? (TX)0 : s[v];
