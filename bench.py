@@ -625,8 +625,9 @@ def main():
                     help="slots per operator session")
     ap.add_argument("--serve-chunk", type=int, default=32, help="iterations between admissions")
     ap.add_argument("--fmt", default="auto")
-    ap.add_argument("--profile-period", type=int, default=16,
-                    help="time every N-th CG iteration with HIP events (0 = off)")
+    ap.add_argument("--profile-period", type=int, default=32,
+                    help="time every N-th CG iteration with HIP events (the middle one of each "
+                         "N-iteration window of a chunk; at most --check-every)")
     args = ap.parse_args()
     if args.traffic_probe:
         import torch
@@ -635,6 +636,10 @@ def main():
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the solver "
               "does not shard across GPUs", file=sys.stderr)
+        sys.exit(2)
+    if not 1 <= args.profile_period <= args.check_every:
+        print("--profile-period must be between 1 and --check-every: the roofline needs "
+              "timed SpMV launches", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -708,6 +713,8 @@ def main():
 
     # dominant kernel: the SpMV of the pressure solve, timed live with HIP events
     spmv_ms, spmv_n = prof64["pois"]["spmv"]
+    if spmv_n == 0:
+        raise RuntimeError("no pressure-solve SpMV launch was timed")
     spmv_avg_us = 1e3 * spmv_ms / max(spmv_n, 1)
     spmv_bytes = bytes_spmv(fmt, n, nnz, 8, unit=scaled)
     spmv_gbs = spmv_bytes / (spmv_avg_us * 1e-6) / 1e9

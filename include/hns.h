@@ -460,7 +460,10 @@ hns_status hns_apply_aux(hns_operator *helm, int which, const double *x_dev, dou
                          void *stream);
 
 /* Kernel timing for measurement.  With period P > 0, every P-th CG
- * iteration of each chunk a solve runs on this operator records HIP events
+ * iteration of each chunk a solve runs on this operator (iterations P/2,
+ * P/2 + P, ... of the chunk, counted from 0, so that with P > 1 a chunk's
+ * first iteration is not sampled; a chunk shorter than P/2 + 1 iterations
+ * samples none) records HIP events
  * around its three kernels on the solve's stream, and the durations of the
  * sampled iterations that did work (not the no-op launches after convergence
  * inside a chunk) are accumulated per kernel:

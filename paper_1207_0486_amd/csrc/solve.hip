@@ -229,8 +229,11 @@ static hns_status enqueue_iterations(hns_operator *op, Workspace *w, Prec prec, 
     if (!lfac && !ic && !scaled && period <= 0 && op->n <= op->small_n &&
         (prec == Prec::F64 || prec == Prec::F32))
         return launch_cg_small(a, parity0, count, s);
+    // sampled: the iteration in the middle of each period window, so a chunk's
+    // first iteration (launched after the host's read of the previous chunk,
+    // on an idle GPU) is never timed unless every iteration is
     for (int it = 0; it < count; ++it) {
-        const bool timed = period > 0 && (it % period) == 0;
+        const bool timed = period > 0 && (it % period) == period / 2;
         if (++w->token == 0) w->token = 1;   // unique per workspace, never 0
         a.token = w->token;
         HNS_TRY(launch_iteration(a, (parity0 + it) & 1, s, timed ? &w->ev[6 * it] : nullptr));
@@ -238,14 +241,15 @@ static hns_status enqueue_iterations(hns_operator *op, Workspace *w, Prec prec, 
     return HNS_OK;
 }
 
-// After the chunk has completed: add the kernel durations of the first
-// `done` iterations (those that did work) to the operator's counters.
+// After the chunk has completed: add the kernel durations of the sampled
+// iterations among the first `done` (those that did work) to the operator's
+// counters.
 static hns_status account_iterations(hns_operator *op, Workspace *w, bool fp32, int done)
 {
     const int period = op->profile;
     if (period <= 0 || done <= 0) return HNS_OK;
     const int base = fp32 ? 3 : 0;
-    for (int it = 0; it < done; it += period)
+    for (int it = period / 2; it < done; it += period)
         for (int k = 0; k < 3; ++k) {
             float ms = 0.0f;
             HNS_TRY_HIP(hipEventElapsedTime(&ms, w->ev[6 * it + 2 * k], w->ev[6 * it + 2 * k + 1]));

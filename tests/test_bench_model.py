@@ -88,3 +88,14 @@ def test_more_than_one_gpu_is_refused():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True, timeout=120)
     assert "one GPU only" in (r.stdout + r.stderr)
+
+
+@pytest.mark.parametrize("period", ["0", "64"])
+def test_untimed_sampling_is_refused(period):
+    """The roofline needs timed SpMV launches: a sampling period of 0, or one
+    longer than a chunk (no iteration of a chunk reaches its middle), is
+    refused before any GPU work."""
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--profile-period", period,
+                        "--check-every", "32"], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "--profile-period must be between 1 and --check-every" in r.stderr
