@@ -799,15 +799,19 @@ __global__ __launch_bounds__(kBlock) void k_update(int64_t n, int64_t per, TX *_
                                                    double *__restrict__ part_out, int parity,
                                                    uint32_t token)
 {
-    if (sc->stop) return;
     TX alpha = 0;
     auto load = [&](int64_t i, auto w) {
         constexpr int W = decltype(w)::value;
         return UpdatePacks<TX, TD, W>{ld<W>(r, i), ld<W>(q, i), ld<W>(dinv, i)};
     };
+    // the stop flag is read here, after the first pack's loads are issued and
+    // beside the partials, rather than at entry: a stopped launch still ends
+    // without a store, and a running one does not wait for the flag first
     auto prologue = [&]() {
+        const int stopped = sc->stop;
         double g[1];
         load_reduced<1>(part_in, G_in, g);
+        if (stopped) return false;
         const double gamma = g[0];
         if (!(gamma > 0.0) || !isfinite(gamma)) {
             if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -915,8 +919,7 @@ __global__ __launch_bounds__(kBlock) void k_pupdate_x(int64_t n, int64_t per,
                                                       const double *__restrict__ part_in,
                                                       int G_in, int parity, uint32_t token)
 {
-    if (sc->xtoken != token) return;
-    const TX alpha = (TX)sc->alpha;
+    TX alpha = 0;
     TX beta = 0;
     bool dir = true;
     auto load = [&](int64_t i, auto w) {
@@ -926,9 +929,15 @@ __global__ __launch_bounds__(kBlock) void k_pupdate_x(int64_t n, int64_t per,
         else
             return XDirPacks<TX, TD, W>{ld<W>(p, i), ld<W>(r, i), ld<W>(x, i), ld<W>(dinv, i)};
     };
+    // the tag and alpha are read in the prologue (as the update reads its stop
+    // flag), after the first pack's loads are issued
     auto prologue = [&]() {
+        const uint32_t tag = sc->xtoken;
+        const double alpha_d = sc->alpha;
         double v[2];
         load_reduced<2>(part_in, G_in, v);
+        if (tag != token) return false;
+        alpha = (TX)alpha_d;
         const double rho_new = v[0], rr = v[1];
         const bool bad = !isfinite(rho_new) || !isfinite(rr);
         const bool conv = !bad && rr <= sc->tol2 * sc->bb;
