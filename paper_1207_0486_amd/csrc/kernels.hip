@@ -1062,10 +1062,12 @@ __global__ __launch_bounds__(kBlock) void k_update_line(
     const T *__restrict__ lfac, Scalars *__restrict__ sc, const double *__restrict__ part_in,
     int G_in, double *__restrict__ part_out, int parity, uint32_t token)
 {
-    if (sc->stop) return;
     extern __shared__ double line_lds[];
+    // the stop flag is read beside the partials rather than before them
+    const int stopped = sc->stop;
     double g[1];
     load_reduced<1>(part_in, G_in, g);
+    if (stopped) return;
     const double gamma = g[0];
     if (!(gamma > 0.0) || !isfinite(gamma)) {
         if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -1118,17 +1120,22 @@ __global__ __launch_bounds__(kBlock) void k_pupdate_line_x(int64_t n, int64_t pe
                                                            const double *__restrict__ part_in,
                                                            int G_in, int parity, uint32_t token)
 {
-    if (sc->xtoken != token) return;
-    const T alpha = (T)sc->alpha;
+    T alpha = 0;
     T beta = 0;
     bool dir = true;
     auto load = [&](int64_t i, auto w) {
         constexpr int W = decltype(w)::value;
         return XLinePacks<T, W>{ld<W>(p, i), ld<W>(z, i), ld<W>(x, i)};
     };
+    // the tag and alpha are read in the prologue, after the first pack's
+    // loads are issued (as in k_pupdate_x)
     auto prologue = [&]() {
+        const uint32_t tag = sc->xtoken;
+        const double alpha_d = sc->alpha;
         double v[2];
         load_reduced<2>(part_in, G_in, v);
+        if (tag != token) return false;
+        alpha = (T)alpha_d;
         const double rho_new = v[0], rr = v[1];
         const bool bad = !isfinite(rho_new) || !isfinite(rr);
         const bool conv = !bad && rr <= sc->tol2 * sc->bb;
