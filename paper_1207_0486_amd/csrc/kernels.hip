@@ -89,7 +89,6 @@ __device__ __forceinline__ void load_reduced(const double *__restrict__ P, int G
                                              double (&out)[NV])
 {
     __shared__ double lds[NV * (kBlock / 64)];
-    __shared__ double bcast[NV];
     // U independent loads per thread in flight at once (one L2 round trip
     // per U * kBlock partials), then added in increasing block order
     constexpr int U = NV == 1 ? 16 : 8;
@@ -110,14 +109,23 @@ __device__ __forceinline__ void load_reduced(const double *__restrict__ P, int G
             for (int k = 0; k < NV; ++k) t[k] += u[k][j];
         }
     }
-    block_sum<NV>(t, lds);
-    if (threadIdx.x == 0) {
+    // wavefront sums, then every thread adds the kBlock/64 of them from LDS
+    // itself, in the order block_sum's thread 0 does (so the totals are
+    // bit-identical to it): one block barrier instead of three
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
-        for (int k = 0; k < NV; ++k) bcast[k] = t[k];
+    for (int k = 0; k < NV; ++k) t[k] = wave_sum(t[k]);
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) lds[k * (kBlock / 64) + wid] = t[k];
     }
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < NV; ++k) out[k] = bcast[k];
+    for (int k = 0; k < NV; ++k) {
+        double s = 0.0;
+        for (int w = 0; w < kBlock / 64; ++w) s += lds[k * (kBlock / 64) + w];
+        out[k] = s;
+    }
 }
 
 // Finishing launches of the one-off reductions (one workgroup): the producer
