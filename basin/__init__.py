@@ -12,7 +12,7 @@ arrays as inputs and derive everything else themselves.
 from .mesh import (BasinMesh, box_mesh, basin_mesh, bathymetry, node_index,
                    BC_U1, BC_U2, BC_U3, dirichlet_bits,
                    HexMesh, box_hex_mesh, basin_hex_mesh)
-from .forcing import (wind_tension, coriolis_parameter, normal_rhs,
+from .forcing import (wind_tension, coriolis_parameter, normal_rhs, random_state,
                       wind_scenarios, serving_requests, RHO0, OMEGA_EARTH)
 from . import configs
 
@@ -20,6 +20,6 @@ __all__ = [
     "BasinMesh", "box_mesh", "basin_mesh", "bathymetry", "node_index",
     "BC_U1", "BC_U2", "BC_U3", "dirichlet_bits",
     "HexMesh", "box_hex_mesh", "basin_hex_mesh",
-    "wind_tension", "coriolis_parameter", "normal_rhs", "wind_scenarios",
+    "wind_tension", "coriolis_parameter", "normal_rhs", "random_state", "wind_scenarios",
     "serving_requests", "RHO0", "OMEGA_EARTH", "configs",
 ]

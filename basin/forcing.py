@@ -44,6 +44,22 @@ def normal_rhs(n: int, seed: int, zero_mean: bool = False,
     return b
 
 
+def random_state(n: int, seed: int, bc: np.ndarray | None = None,
+                 velocity_scale: float = 0.1, pressure_scale: float = 1.0):
+    """Seeded stand-in for the state (u, p) a time step starts from: u (3, n)
+    and p (n,) iid normal from default_rng(seed), drawn in the order u_1, u_2,
+    u_3, p and scaled by velocity_scale (m/s) and pressure_scale; u_c is set
+    to zero where bit c - 1 of `bc` is set (the component's Dirichlet set)."""
+    rng = np.random.default_rng(seed)
+    u = velocity_scale * rng.standard_normal((3, n))
+    p = pressure_scale * rng.standard_normal(n)
+    if bc is not None:
+        bc = np.asarray(bc)
+        for c in range(3):
+            u[c][((bc >> c) & 1) == 1] = 0.0
+    return u, p
+
+
 @dataclass
 class WindScenario:
     amplitude: float

@@ -872,7 +872,6 @@ __global__ __launch_bounds__(kBlock) void k_pupdate(int64_t n, int64_t per, TX *
                                                     const double *__restrict__ part_in, int G_in,
                                                     int parity, int count)
 {
-    if (sc->stop) return;
     TX beta = 0;
     auto load = [&](int64_t i, auto w) {
         constexpr int W = decltype(w)::value;
@@ -881,9 +880,17 @@ __global__ __launch_bounds__(kBlock) void k_pupdate(int64_t n, int64_t per, TX *
         else
             return DirPacks<TX, TD, W>{ld<W>(p, i), ld<W>(r, i), ld<W>(dinv, i)};
     };
+    // the stop flag is read in the prologue, by every wave, and every wave
+    // then passes the block barrier of the re-reduction: block 0 of this very
+    // launch may raise the flag, and an entry test could let some waves of a
+    // later block leave while the others sum LDS slots the leavers never wrote
+    // (a block that sees the flag raised by block 0 here computes the same
+    // stopping decision from the same partials)
     auto prologue = [&]() {
+        const int stopped = sc->stop;
         double v[2];
         load_reduced<2>(part_in, G_in, v);
+        if (stopped) return false;
         const double rho_new = v[0], rr = v[1];
         const bool bad = !isfinite(rho_new) || !isfinite(rr);
         const bool conv = !bad && rr <= sc->tol2 * sc->bb;
@@ -1259,15 +1266,18 @@ __global__ __launch_bounds__(kBlock) void k_pdir_line(int64_t n, int64_t per, T 
                                                       const double *__restrict__ part_in,
                                                       int G_in, int parity)
 {
-    if (sc->stop) return;
     T beta = 0;
     auto load = [&](int64_t i, auto w) {
         constexpr int W = decltype(w)::value;
         return LinePacks<T, W>{ld<W>(p, i), ld<W>(z, i)};
     };
+    // stop flag read by every wave before the re-reduction's barrier (as in
+    // k_pupdate: block 0 of this launch may raise it)
     auto prologue = [&]() {
+        const int stopped = sc->stop;
         double v[2];
         load_reduced<2>(part_in, G_in, v);
+        if (stopped) return false;
         const double rho_new = v[0], rr = v[1];
         const bool bad = !isfinite(rho_new) || !isfinite(rr);
         const bool conv = !bad && rr <= sc->tol2 * sc->bb;
@@ -1353,15 +1363,18 @@ __global__ __launch_bounds__(kBlock) void k_update_noz(int64_t n, int64_t per,
                                                        const double *__restrict__ part_in,
                                                        int G_in, int parity, uint32_t token)
 {
-    if (sc->stop) return;
     double alpha = 0.0;
     auto load = [&](int64_t i, auto w) {
         constexpr int W = decltype(w)::value;
         return RQPacks<W>{ld<W>(r, i), ld<W>(q, i)};
     };
+    // stop flag read by every wave before the re-reduction's barrier (block 0
+    // of this launch may raise it on a breakdown)
     auto prologue = [&]() {
+        const int stopped = sc->stop;
         double g[1];
         load_reduced<1>(part_in, G_in, g);
+        if (stopped) return false;
         const double gamma = g[0];
         if (!(gamma > 0.0) || !isfinite(gamma)) {
             if (blockIdx.x == 0 && threadIdx.x == 0) {

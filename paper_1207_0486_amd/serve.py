@@ -132,20 +132,30 @@ class _GpuEntry:
 
 
 class _Resident:
-    """A resident operator with its session, pending queue and worker."""
+    """A resident operator with its session, pending queue and worker.
+
+    `pending` and `running` change only under the server's lock.  A request
+    moves from `pending` to `running` in the same critical section that
+    assigns its slot, so a resident is idle (and may be evicted) only while
+    its worker holds no request at all."""
 
     def __init__(self, key, entry, capacity):
         self.key = key
         self.entry = entry
         self.capacity = capacity
         self.pending = collections.deque()
-        self.running = {}            # slot -> Request
+        self.running = {}            # slot -> Request (being added or iterating)
         self.last_used = time.perf_counter()
         self.thread = None
+        self.evicted = False
 
     @property
     def idle(self):
         return not self.pending and not self.running
+
+
+class ServerClosed(RuntimeError):
+    """The server stopped before the request finished."""
 
 
 class Server:
@@ -154,6 +164,17 @@ class Server:
     budget_bytes: device memory the server may hold (operators + sessions);
     capacity: slots per operator session; chunk: iterations between
     admission points.
+
+    Threads: one worker per resident operator (adds, advances and takes its
+    session's requests) and one admission thread, which alone assembles
+    operators and evicts idle ones, so neither a submitting thread nor a
+    worker with running requests ever waits for an assembly.  An evicted
+    operator's worker closes its session and operator before the admission
+    thread opens the next one, so the device never holds more than the
+    budget.  A worker that ends for any reason (eviction, close, an error)
+    unregisters its operator and releases its bytes; requests it still held
+    fail with the error (or ServerClosed), and later requests for the same
+    operator get a fresh one.
     """
 
     def __init__(self, backend, budget_bytes, capacity=8, chunk=32):
@@ -170,142 +191,190 @@ class Server:
         self.stop_flag = False
         self.errors = []
         self.peak_used = 0
-        self.opening = set()                     # keys being assembled right now
+        self.workers = []                        # every worker thread started
+        self._admitter = threading.Thread(target=self._admit_loop, daemon=True)
+        self._admitter.start()
 
     # ------------------------------------------------------------------
     def submit(self, req: Request) -> Future:
         req.arrival = time.perf_counter() if not req.arrival else req.arrival
         with self.lock:
+            if self.stop_flag:
+                req.future.set_exception(ServerClosed("server is closed"))
+                return req.future
             res = self.resident.get(req.key)
             if res is not None:
                 res.pending.append(req)
             else:
                 self.waiting.append(req)
             self.lock.notify_all()
-        self._admit()
         return req.future
 
     def close(self):
         with self.lock:
             self.stop_flag = True
             self.lock.notify_all()
-        threads = [r.thread for r in self.resident.values() if r.thread is not None]
-        for t in threads:
+        self._admitter.join()
+        for t in list(self.workers):
             t.join()
-        for r in list(self.resident.values()):
-            r.entry.close()
-        self.resident.clear()
+        with self.lock:
+            left = list(self.waiting)
+            self.waiting.clear()
+        for req in left:
+            if not req.future.done():
+                req.future.set_exception(ServerClosed("server closed before admission"))
 
     # ------------------------------------------------------------------
-    def _admit(self):
-        """Admit waiting requests' operators in arrival order while memory allows."""
+    def _admit_loop(self):
         while True:
             with self.lock:
-                if not self.waiting or self.stop_flag:
+                if self.stop_flag:
                     return
-                req = self.waiting[0]
-                res = self.resident.get(req.key)
-                if res is not None:             # admitted meanwhile
-                    self.waiting.popleft()
-                    res.pending.append(req)
-                    self.lock.notify_all()
-                    continue
-                if req.key in self.opening:      # its operator is being assembled
-                    return
-                need = self.backend.estimate_bytes(req.key, self.capacity)
-                if need > self.budget:
-                    self.waiting.popleft()
-                    req.future.set_exception(MemoryError(
-                        f"operator {req.key} needs {need} bytes, budget is {self.budget}"))
-                    continue
+            progressed = self._admit()
+            if not progressed:
+                with self.lock:
+                    if self.stop_flag:
+                        return
+                    self.lock.wait(timeout=0.05)
+
+    def _admit(self):
+        """Admit the head of the waiting queue (first come, first served):
+        hand it to its resident operator, or open the operator when the
+        budget allows, evicting idle operators in least-recently-used order.
+        Returns whether anything changed."""
+        with self.lock:
+            if not self.waiting or self.stop_flag:
+                return False
+            req = self.waiting[0]
+            res = self.resident.get(req.key)
+            if res is not None:                  # admitted meanwhile
+                self.waiting.popleft()
+                res.pending.append(req)
+                self.lock.notify_all()
+                return True
+            need = self.backend.estimate_bytes(req.key, self.capacity)
+            if need > self.budget:
+                self.waiting.popleft()
+                req.future.set_exception(MemoryError(
+                    f"operator {req.key} needs {need} bytes, budget is {self.budget}"))
+                return True
+            if self.used + need > self.budget:
                 # evict idle operators (least recently used first) until it fits
-                while self.used + need > self.budget:
-                    idle = [r for r in self.resident.values() if r.idle]
-                    if not idle:
-                        return                   # wait for memory (first come, first served)
-                    victim = min(idle, key=lambda r: r.last_used)
-                    self._evict(victim)
+                victims, freed = [], 0
+                for r in sorted((r for r in self.resident.values() if r.idle),
+                                key=lambda r: r.last_used):
+                    if self.used - freed + need <= self.budget:
+                        break
+                    victims.append(r)
+                    freed += r.entry.nbytes
+                if self.used - freed + need > self.budget:
+                    return False                 # wait for memory
+                for r in victims:
+                    self._evict(r)
+            else:
+                victims = []
                 self.used += need                # reserve while assembling
                 self.waiting.popleft()
-                self.opening.add(req.key)
-            try:
-                entry = self.backend.open(req.key, self.capacity)
-            except Exception as e:  # noqa: BLE001 - reported through the future
-                with self.lock:
-                    self.used -= need
-                    self.opening.discard(req.key)
-                req.future.set_exception(e)
-                continue
+        if victims:
+            # the victims' workers close their sessions and release the bytes
+            for r in victims:
+                r.thread.join()
+            return True
+        try:
+            entry = self.backend.open(req.key, self.capacity)
+        except Exception as e:  # noqa: BLE001 - reported through the future
             with self.lock:
-                self.opening.discard(req.key)
-                self.used += entry.nbytes - need
-                self.peak_used = max(self.peak_used, self.used)
-                res = _Resident(req.key, entry, self.capacity)
-                res.pending.append(req)
-                # requests for the same key that queued behind it join too
-                for other in [w for w in self.waiting if w.key == req.key]:
-                    self.waiting.remove(other)
-                    res.pending.append(other)
-                self.resident[req.key] = res
-                self.events.append((time.perf_counter(), "admit", req.key))
-                res.thread = threading.Thread(target=self._worker, args=(res,), daemon=True)
-                res.thread.start()
+                self.used -= need
+            req.future.set_exception(e)
+            return True
+        with self.lock:
+            self.used += entry.nbytes - need
+            self.peak_used = max(self.peak_used, self.used)
+            res = _Resident(req.key, entry, self.capacity)
+            res.pending.append(req)
+            # requests for the same key that queued behind it join too
+            for other in [w for w in self.waiting if w.key == req.key]:
+                self.waiting.remove(other)
+                res.pending.append(other)
+            self.resident[req.key] = res
+            self.events.append((time.perf_counter(), "admit", req.key))
+            res.thread = threading.Thread(target=self._worker, args=(res,), daemon=True)
+            self.workers.append(res.thread)
+            res.thread.start()
+        return True
 
     def _evict(self, res):
-        # called with the lock held; the worker exits when it sees itself gone
+        # lock held; res is idle, so its worker holds no request and exits at
+        # its next look at the flag
         del self.resident[res.key]
-        self.used -= res.entry.nbytes
-        self.events.append((time.perf_counter(), "evict", res.key))
         res.evicted = True
+        self.events.append((time.perf_counter(), "evict", res.key))
         self.lock.notify_all()
+
+    def _retire(self, res, error):
+        """End of a worker: unregister the operator, release its bytes, fail
+        the requests it still held, close its session and operator."""
+        with self.lock:
+            if self.resident.get(res.key) is res:
+                del self.resident[res.key]
+            held = list(res.running.values()) + list(res.pending)
+            res.running.clear()
+            res.pending.clear()
+        for req in held:
+            if not req.future.done():
+                req.future.set_exception(
+                    error if error is not None else ServerClosed("server closed"))
+        try:
+            res.entry.close()
+        except Exception as e:  # noqa: BLE001
+            with self.lock:
+                self.errors.append(e)
+        with self.lock:
+            self.used -= res.entry.nbytes
+            self.lock.notify_all()
 
     def _worker(self, res: _Resident):
         entry = res.entry
         free = list(range(res.capacity))
+        error = None
         try:
             while True:
                 with self.lock:
                     while (not res.pending and not res.running and not self.stop_flag
-                           and not getattr(res, "evicted", False)):
+                           and not res.evicted):
                         self.lock.wait(timeout=0.05)
-                    if self.stop_flag or getattr(res, "evicted", False):
+                    if self.stop_flag or res.evicted:
                         break
                     batch = []
                     while res.pending and free:
-                        batch.append((free.pop(0), res.pending.popleft()))
+                        slot = free.pop(0)
+                        req = res.pending.popleft()
+                        res.running[slot] = req
+                        batch.append((slot, req))
                     res.last_used = time.perf_counter()
                 if batch:
                     entry.add(batch)
-                    for slot, req in batch:
-                        res.running[slot] = req
-                if res.running:
-                    entry.advance(self.chunk)
-                    states, infos = entry.poll()
-                    for slot in [s for s in list(res.running) if states[s] == 2]:
-                        req = res.running.pop(slot)
-                        x, info = entry.take(slot)
-                        free.append(slot)
-                        now = time.perf_counter()
-                        r = Result(x, info, now - req.arrival, req.key)
-                        with self.lock:
-                            self.results.append(r)
-                        req.future.set_result(r)
+                entry.advance(self.chunk)
+                states, infos = entry.poll()
+                for slot in [s for s in list(res.running) if states[s] == 2]:
+                    x, info = entry.take(slot)
+                    free.append(slot)
                     with self.lock:
-                        res.last_used = time.perf_counter()
-                        if res.idle:
-                            self.lock.notify_all()
-                    self._admit()
+                        req = res.running.pop(slot)
+                    r = Result(x, info, time.perf_counter() - req.arrival, req.key)
+                    with self.lock:
+                        self.results.append(r)
+                    req.future.set_result(r)
+                with self.lock:
+                    res.last_used = time.perf_counter()
+                    if res.idle:
+                        self.lock.notify_all()
         except Exception as e:  # noqa: BLE001 - surfaced to the waiting requests
+            error = e
             with self.lock:
                 self.errors.append(e)
-                for req in list(res.running.values()) + list(res.pending):
-                    if not req.future.done():
-                        req.future.set_exception(e)
-                res.running.clear()
-                res.pending.clear()
         finally:
-            if getattr(res, "evicted", False):
-                entry.close()
+            self._retire(res, error)
 
     # ------------------------------------------------------------------
     def stats(self, t0=None, t1=None):
@@ -318,6 +387,13 @@ class Server:
                         "max_ms": float(lat.max() * 1e3)})
         if t0 is not None and t1 is not None and t1 > t0:
             out["solves_per_s"] = float(lat.size / (t1 - t0))
+        by_key = {}
+        for r in self.results:
+            by_key.setdefault(r.key, []).append(r.latency_s)
+        out["by_key"] = {k: {"completed": len(v),
+                             "p50_ms": float(np.percentile(v, 50) * 1e3),
+                             "p99_ms": float(np.percentile(v, 99) * 1e3)}
+                         for k, v in by_key.items()}
         out["peak_bytes"] = int(self.peak_used)
         out["admissions"] = sum(1 for e in self.events if e[1] == "admit")
         out["evictions"] = sum(1 for e in self.events if e[1] == "evict")

@@ -148,3 +148,96 @@ def test_operator_larger_than_budget_fails_its_request():
     with pytest.raises(MemoryError):
         f.result(timeout=5)
     srv.close()
+
+
+class SlowAddBackend(FakeBackend):
+    """Adding a request to key 'slow' takes a while (a host-to-device copy
+    and the first residual on a real device)."""
+
+    def open(self, key, capacity):
+        entry = super().open(key, capacity)
+        if key == "slow":
+            plain_add = entry.add
+
+            def slow_add(items):
+                time.sleep(0.3)
+                plain_add(items)
+            entry.add = slow_add
+        return entry
+
+
+def test_operator_is_not_evicted_while_its_requests_are_being_added():
+    """While 'slow' adds its request, it holds that request and is not idle:
+    the admission of a third operator must evict the idle 'fast' one, and the
+    slow request still completes."""
+    be = SlowAddBackend({"slow": 400, "fast": 400, "third": 400}, cost=lambda r: 32)
+    srv = Server(be, budget_bytes=900, capacity=2, chunk=32)
+    f_slow = srv.submit(Request(key="slow", b=np.ones(2)))
+    f_fast = srv.submit(Request(key="fast", b=np.ones(2)))
+    f_fast.result(timeout=10)
+    assert not f_slow.done()                      # still inside its add
+    f_third = srv.submit(Request(key="third", b=np.ones(2)))
+    r_slow = f_slow.result(timeout=10)
+    f_third.result(timeout=10)
+    srv.close()
+    assert np.array_equal(r_slow.x, 2.0 * np.ones(2))
+    ev = [e[2] for e in srv.events if e[1] == "evict"]
+    assert ev == ["fast"]
+    assert srv.peak_used <= 900 and srv.used == 0 and not srv.errors
+
+
+class FailingBackend(FakeBackend):
+    """The first session opened for key 'bad' fails in its advance."""
+
+    def open(self, key, capacity):
+        entry = super().open(key, capacity)
+        if key == "bad" and self.opened.count("bad") == 1:
+            def broken(iterations):
+                raise RuntimeError("device error")
+            entry.advance = broken
+        return entry
+
+
+def test_worker_error_fails_its_requests_and_frees_the_operator():
+    be = FailingBackend({"bad": 300, "good": 300}, cost=lambda r: 32)
+    srv = Server(be, budget_bytes=1000, capacity=2, chunk=32)
+    f1 = srv.submit(Request(key="bad", b=np.ones(2)))
+    f2 = srv.submit(Request(key="good", b=np.ones(2)))
+    with pytest.raises(RuntimeError, match="device error"):
+        f1.result(timeout=10)
+    f2.result(timeout=10)
+    # the dead operator is unregistered: a later request gets a fresh one
+    r3 = srv.submit(Request(key="bad", b=np.full(2, 3.0))).result(timeout=10)
+    assert np.array_equal(r3.x, np.full(2, 6.0))
+    assert be.opened.count("bad") == 2
+    srv.close()
+    assert srv.used == 0 and len(srv.errors) == 1
+
+
+def test_close_resolves_every_future():
+    """Requests still running or waiting when the server closes fail with
+    ServerClosed instead of hanging."""
+    from paper_1207_0486_amd.serve import ServerClosed
+    be = FakeBackend({"a": 600, "b": 600}, cost=lambda r: 10 ** 9)   # never finishes
+    srv = Server(be, budget_bytes=1000, capacity=1, chunk=32)
+    fa = srv.submit(Request(key="a", b=np.ones(1)))
+    fb = srv.submit(Request(key="b", b=np.ones(1)))    # waits: a is busy
+    time.sleep(0.1)
+    srv.close()
+    for f in (fa, fb):
+        with pytest.raises(ServerClosed):
+            f.result(timeout=5)
+    assert srv.used == 0
+    with pytest.raises(ServerClosed):
+        srv.submit(Request(key="a", b=np.ones(1))).result(timeout=1)
+
+
+def test_latency_by_operator():
+    be = FakeBackend({"a": 100, "b": 100}, cost=lambda r: 32)
+    srv = Server(be, budget_bytes=1000, capacity=2, chunk=32)
+    futs = [srv.submit(Request(key=k, b=np.ones(1))) for k in "abab"]
+    _wait(futs)
+    srv.close()
+    st = srv.stats()
+    assert set(st["by_key"]) == {"a", "b"}
+    assert all(v["completed"] == 2 and v["p50_ms"] <= v["p99_ms"] for v in st["by_key"].values())
