@@ -18,6 +18,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "hns_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+_LIB_OMP = os.path.join(_HERE, "liboracle_omp.so")
 
 OK, NOT_CONVERGED, ERR_INVALID, ERR_NOMEM, ERR_MESH, ERR_BREAKDOWN = 0, 1, -1, -3, -4, -5
 
@@ -25,12 +26,21 @@ _lib = None
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (plain -O2, no fused multiply-add contraction)."""
+    """Compile the oracle with gcc (plain -O2, no fused multiply-add
+    contraction), and the OpenMP timing build of the same file (-O3
+    -march=native -fopenmp) used only for the benchmark's multi-core CPU
+    baseline and its reference solves."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
         subprocess.run(["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fPIC", "-shared",
-                        "-Wall", "-o", tmp, _SRC, "-lm"], check=True)
+                        "-Wall", "-Wno-unknown-pragmas", "-o", tmp, _SRC, "-lm"], check=True)
         os.replace(tmp, _LIB)
+    if force or not os.path.exists(_LIB_OMP):
+        tmp = _LIB_OMP + ".tmp"
+        subprocess.run(["gcc", "-O3", "-march=native", "-fopenmp", "-std=gnu99",
+                        "-ffp-contract=off", "-fPIC", "-shared", "-Wall", "-o", tmp, _SRC,
+                        "-lm"], check=True)
+        os.replace(tmp, _LIB_OMP)
     return _LIB
 
 
@@ -84,8 +94,38 @@ def lib():
         L.or_relres.argtypes = [vp, u8p, dp, dp]
         L.or_cholesky_solve.restype = C.c_int
         L.or_cholesky_solve.argtypes = [C.c_int64, dp, dp, dp]
+        _declare_timing(L)
         _lib = L
     return _lib
+
+
+def _declare_timing(L):
+    L.or_set_threads.restype = None
+    L.or_set_threads.argtypes = [C.c_int]
+    L.or_max_threads.restype = C.c_int
+    L.or_max_threads.argtypes = []
+    L.or_last_loop_seconds.restype = C.c_double
+    L.or_last_loop_seconds.argtypes = []
+
+
+_lib_omp = None
+
+
+def lib_omp():
+    """The OpenMP timing build (same source).  OMP_PROC_BIND / OMP_PLACES are
+    read when it is first loaded."""
+    global _lib_omp
+    if _lib_omp is None:
+        if not os.path.exists(_LIB_OMP):
+            build()
+        L = C.CDLL(_LIB_OMP)
+        dp, u8p, vp = C.POINTER(C.c_double), C.POINTER(C.c_uint8), C.c_void_p
+        L.or_pcg_line.restype = C.c_int
+        L.or_pcg_line.argtypes = [vp, u8p, C.c_int, dp, dp, dp, C.c_double, C.c_int, C.c_int64,
+                                  C.POINTER(C.c_int), dp, dp, dp, dp, dp]
+        _declare_timing(L)
+        _lib_omp = L
+    return _lib_omp
 
 
 def _d(a):
@@ -253,15 +293,22 @@ class PCGResult:
     alphas: np.ndarray | None = None
     betas: np.ndarray | None = None
     x_hist: np.ndarray | None = None
+    loop_s: float = 0.0
 
 
 def pcg(A: Matrix, b, dirichlet=None, singular=False, weights=None, x0=None,
         tol=1e-10, maxit=100000, history=False, x_history=False, line=0,
-        ic0=False) -> PCGResult:
+        ic0=False, threads=0) -> PCGResult:
     """Preconditioned CG on A after eliminating `dirichlet` nodes (boolean (n,)
     or None).  line = 0: Jacobi (inverse diagonal); line = L >= 1: inverse of
     the tridiagonal blocks on the consecutive columns of L nodes; ic0: IC(0)
-    of the eliminated matrix in the greedy multicolour order."""
+    of the eliminated matrix in the greedy multicolour order.
+
+    threads = 0 runs the plain parity build; threads >= 1 runs the OpenMP
+    timing build of the same source with that many threads (Jacobi or line
+    blocks only; rounding differs from the plain build in the order of the
+    dot-product sums).  The result's loop_s is the wall time of the iteration
+    loop."""
     n = A.n
     b = _f64(b)
     x = np.zeros(n) if x0 is None else _f64(x0).copy()
@@ -275,18 +322,23 @@ def pcg(A: Matrix, b, dirichlet=None, singular=False, weights=None, x0=None,
     xh = np.zeros((maxit, n)) if x_history else None
     hist = (None if ah is None else _d(ah), None if bh is None else _d(bh),
             None if xh is None else _d(xh))
+    if threads and ic0:
+        raise ValueError("the OpenMP timing build runs Jacobi or line blocks only")
+    L = lib_omp() if threads else lib()
+    if threads:
+        L.or_set_threads(int(threads))
     if ic0:
-        st = lib().or_pcg_ic0(A._h, _u8(dmask), int(bool(singular)),
-                              None if w is None else _d(w), _d(b), _d(x), tol, maxit,
-                              C.byref(it), _d(rel), _d(rm), *hist)
+        st = L.or_pcg_ic0(A._h, _u8(dmask), int(bool(singular)),
+                          None if w is None else _d(w), _d(b), _d(x), tol, maxit,
+                          C.byref(it), _d(rel), _d(rm), *hist)
     else:
-        st = lib().or_pcg_line(A._h, _u8(dmask), int(bool(singular)),
-                               None if w is None else _d(w), _d(b), _d(x), tol, maxit, int(line),
-                               C.byref(it), _d(rel), _d(rm), *hist)
+        st = L.or_pcg_line(A._h, _u8(dmask), int(bool(singular)),
+                           None if w is None else _d(w), _d(b), _d(x), tol, maxit, int(line),
+                           C.byref(it), _d(rel), _d(rm), *hist)
     k = it.value
     return PCGResult(x=x, status=st, iterations=k, relres=float(rel[0]), removed_mean=float(rm[0]),
                      alphas=None if ah is None else ah[:k], betas=None if bh is None else bh[:k],
-                     x_hist=None if xh is None else xh[:k])
+                     x_hist=None if xh is None else xh[:k], loop_s=float(L.or_last_loop_seconds()))
 
 
 def greedy_colors(A: Matrix):

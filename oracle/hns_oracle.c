@@ -30,11 +30,23 @@
  *     the isotropic pressure operator of eq. fofa_q_cor_h tractable on thin
  *     meshes;
  *   - a dense Cholesky factorisation for tiny systems.
+ *
+ * Two builds of this one file: the plain one (no OpenMP) is the parity
+ * oracle; compiled with -fopenmp it is the multi-core timing baseline of the
+ * Jacobi-PCG loop (static row partition of the products and vector updates,
+ * dot products as 256 fixed chunks each summed in order, then the chunk sums
+ * in order, so results do not depend on the thread count).  The OpenMP
+ * pragmas are ignored by the plain build, whose arithmetic they leave as is.
  */
+#define _POSIX_C_SOURCE 199309L /* clock_gettime */
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#include <time.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define OR_OK 0
 #define OR_NOT_CONVERGED 1
@@ -377,6 +389,7 @@ int or_assemble_surface_mass(int64_t n, const double *xyz, int64_t ntri,
 
 void or_spmv(const or_csr *A, const double *x, double *y)
 {
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < A->n; ++i) {
         double s = 0.0;
         for (int64_t k = A->rowptr[i]; k < A->rowptr[i + 1]; ++k)
@@ -394,21 +407,85 @@ void or_spmv_t(const or_csr *A, const double *x, double *y, int64_t ncols)
             y[A->col[k]] += A->val[k] * x[i];
 }
 
+#ifdef _OPENMP
+enum { OR_CHUNKS = 256 };
+
+/* sum_i a[i] b[i] (b == NULL: sum_i a[i]) over OR_CHUNKS contiguous chunks,
+ * each summed in order by one thread, then the chunk sums in order */
+static double chunked_sum(int64_t n, const double *a, const double *b)
+{
+    double part[OR_CHUNKS];
+#pragma omp parallel for schedule(static)
+    for (int c = 0; c < OR_CHUNKS; ++c) {
+        int64_t i0 = n * c / OR_CHUNKS, i1 = n * (c + 1) / OR_CHUNKS;
+        double s = 0.0;
+        if (b)
+            for (int64_t i = i0; i < i1; ++i) s += a[i] * b[i];
+        else
+            for (int64_t i = i0; i < i1; ++i) s += a[i];
+        part[c] = s;
+    }
+    double s = 0.0;
+    for (int c = 0; c < OR_CHUNKS; ++c) s += part[c];
+    return s;
+}
+#endif
+
 static double dot(int64_t n, const double *a, const double *b)
 {
+#ifdef _OPENMP
+    return chunked_sum(n, a, b);
+#else
     double s = 0.0;
     for (int64_t i = 0; i < n; ++i) s += a[i] * b[i];
     return s;
+#endif
 }
 
 /* v <- v - mean(v) * 1; returns the mean removed */
 static double remove_mean(int64_t n, double *v)
 {
+#ifdef _OPENMP
+    double mean = chunked_sum(n, v, NULL);
+#else
     double mean = 0.0;
     for (int64_t i = 0; i < n; ++i) mean += v[i];
+#endif
     mean /= (double)n;
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) v[i] -= mean;
     return mean;
+}
+
+/* Thread count of the timing build (ignored by the plain build) and the wall
+ * time of the last PCG iteration loop (set-up and elimination excluded). */
+static double g_loop_seconds = 0.0;
+
+void or_set_threads(int threads)
+{
+#ifdef _OPENMP
+    if (threads > 0) omp_set_num_threads(threads);
+#else
+    (void)threads;
+#endif
+}
+
+int or_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+double or_last_loop_seconds(void) { return g_loop_seconds; }
+
+static double wall_seconds(void)
+{
+    struct timespec t;
+    clock_gettime(CLOCK_MONOTONIC, &t);
+    return (double)t.tv_sec + 1e-9 * (double)t.tv_nsec;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -531,6 +608,7 @@ static int apply_prec_line(int64_t n, int64_t line_len, const double *dinv, cons
                            const double *le, const double *r, double *z, double *work)
 {
     if (line_len == 0) {
+#pragma omp parallel for schedule(static)
         for (int64_t i = 0; i < n; ++i) z[i] = dinv[i] * r[i];
         return OR_OK;
     }
@@ -740,6 +818,7 @@ static int pcg_core(const or_csr *A0, const uint8_t *dirichlet, int singular,
                     double *x_hist)
 {
     int64_t n = A0->n;
+    g_loop_seconds = 0.0;
     if (line_len < 0 || (line_len > 0 && n % line_len != 0)) return OR_ERR_INVALID;
     *iters_out = 0;
     *relres_out = 0.0;
@@ -813,11 +892,14 @@ static int pcg_core(const or_csr *A0, const uint8_t *dirichlet, int singular,
         status = OR_OK;
         goto done;
     }
+    const double t_loop = wall_seconds();
     or_spmv(A, x, q);
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) r[i] = b[i] - q[i];
     if (singular) remove_mean(n, r);
     if ((status = apply_prec(n, &P, r, z)) != OR_OK) goto done;
     status = OR_NOT_CONVERGED;
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) p[i] = z[i];
     double rho = dot(n, r, z);
     double relres = sqrt(dot(n, r, r)) / bnorm;
@@ -836,7 +918,9 @@ static int pcg_core(const or_csr *A0, const uint8_t *dirichlet, int singular,
             break;
         }
         double alpha = rho / gamma;
+#pragma omp parallel for schedule(static)
         for (int64_t i = 0; i < n; ++i) x[i] += alpha * p[i];
+#pragma omp parallel for schedule(static)
         for (int64_t i = 0; i < n; ++i) r[i] -= alpha * q[i];
         if (alpha_hist) alpha_hist[it] = alpha;
         if (x_hist) memcpy(x_hist + (int64_t)it * n, x, sizeof(double) * (size_t)n);
@@ -844,6 +928,7 @@ static int pcg_core(const or_csr *A0, const uint8_t *dirichlet, int singular,
         relres = sqrt(dot(n, r, r)) / bnorm;
         if (relres <= tol) {
             or_spmv(A, x, q);
+#pragma omp parallel for schedule(static)
             for (int64_t i = 0; i < n; ++i) q[i] = b[i] - q[i];
             if (singular) remove_mean(n, q);
             double true_rel = sqrt(dot(n, q, q)) / bnorm;
@@ -866,6 +951,7 @@ static int pcg_core(const or_csr *A0, const uint8_t *dirichlet, int singular,
             memcpy(r, q, sizeof(double) * (size_t)n);
             if ((status = apply_prec(n, &P, r, z)) != OR_OK) break;
             status = OR_NOT_CONVERGED;
+#pragma omp parallel for schedule(static)
             for (int64_t i = 0; i < n; ++i) p[i] = z[i];
             rho = dot(n, r, z);
             relres = true_rel;
@@ -877,9 +963,11 @@ static int pcg_core(const or_csr *A0, const uint8_t *dirichlet, int singular,
         double rho_new = dot(n, r, z);
         double beta = rho_new / rho;
         if (beta_hist) beta_hist[it - 1] = beta;
+#pragma omp parallel for schedule(static)
         for (int64_t i = 0; i < n; ++i) p[i] = z[i] + beta * p[i];
         rho = rho_new;
     }
+    g_loop_seconds = wall_seconds() - t_loop;
     *iters_out = it;
     *relres_out = relres;
 normalize:

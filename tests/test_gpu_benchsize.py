@@ -140,19 +140,36 @@ def c2_pressure(c2):
 
 
 def test_full_size_pressure_solve_p_same(c2, c2_pressure):
-    """The pure-Neumann pressure solve, FP64 to 1e-10 (about 2,400
+    """The pure-Neumann pressure solve, FP64 to 1e-10 (about 2,000
     iterations): the GPU answer against the oracle's iterate after as many
-    iterations, both projected and shifted to zero mass-weighted mean."""
+    iterations, both projected and shifted to zero mass-weighted mean.
+
+    Over 2,000 iterations at this conditioning CG amplifies rounding: the
+    oracle's own iterate moves by about 1e-9 when b is perturbed by one unit
+    in the last place, an order above 1e-10 (and 50x below the error of
+    either answer against the exact solution, which is bounded by
+    kappa * tol, not by tol).  The GPU iterate must lie within twice that
+    self-sensitivity (and within 1e-10 if the sensitivity is smaller), and
+    the iteration counts within max(1, 2 %)."""
     gpu, ref = c2["gpu"], c2["ref"]
     b = c2_pressure
     x, info = gpu.pois.solve(_t(b), tol=TOL, mask_bit=-1)
     assert info.status == 0 and info.relres_true <= TOL
     xh = x.cpu().numpy()
-    same = p_same(ref.K, b, None, True, ref.mL, info.iterations, TOL)
+    its = info.iterations
+    same = p_same(ref.K, b, None, True, ref.mL, its, TOL)
     err = _rel(xh, same.x)
-    print(f"q: {info.iterations} iterations (oracle stopped at {same.iterations}, "
-          f"status {same.status}), P-same difference {err:.2e}", flush=True)
-    assert err <= 1e-10, err
+    # one unit in the last place on every entry, signs from a seeded draw
+    sign = np.where(np.random.default_rng(23).standard_normal(b.size) < 0, -1.0, 1.0)
+    bp = b + sign * np.spacing(np.abs(b))
+    pert = p_same(ref.K, bp, None, True, ref.mL, its, TOL)
+    sens = _rel(pert.x, same.x)
+    margin = max(1, int(0.02 * its))
+    full = oracle.pcg(ref.K, b, singular=True, weights=ref.mL, tol=TOL, maxit=its + margin)
+    print(f"q: {its} iterations (oracle converged at {full.iterations}, status {full.status}); "
+          f"P-same difference {err:.2e}, oracle self-sensitivity {sens:.2e}", flush=True)
+    assert full.status == 0 and abs(full.iterations - its) <= margin
+    assert err <= max(1e-10, 2.0 * sens), (err, sens)
     bh = b - b.mean()
     r = bh - ref.K.matvec(xh)
     r -= r.mean()
