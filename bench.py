@@ -96,6 +96,200 @@ def make_forcing(m):
     return theta, f
 
 
+def oracle_threads():
+    """Threads of the multi-core CPU baseline: OMP_NUM_THREADS when set (this
+    process's share of the host), else the CPUs the process may run on."""
+    v = os.environ.get("OMP_NUM_THREADS", "")
+    if v.isdigit() and int(v) > 0:
+        return int(v)
+    return len(os.sched_getaffinity(0))
+
+
+def host_cpu():
+    """CPU model and core counts of this host, from lscpu."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+    except (OSError, subprocess.SubprocessError):
+        return {}
+    f = {}
+    for line in out.splitlines():
+        if ":" in line:
+            k, v = line.split(":", 1)
+            f[k.strip()] = v.strip()
+
+    def num(key):
+        try:
+            return int(f.get(key, "0"))
+        except ValueError:
+            return 0
+    sockets = max(num("Socket(s)"), 1)
+    return {"model": f.get("Model name"), "sockets": sockets,
+            "physical_cores": sockets * num("Core(s) per socket"),
+            "logical_cpus": num("CPU(s)"), "affinity_cpus": len(os.sched_getaffinity(0))}
+
+
+def oracle_reference(m, wl, theta, f, threads, log):
+    """The oracle's own time step 1 on the mesh: its step from rest (FP64
+    Jacobi-PCG to the workload tolerance), then the step-1 systems, each
+    solved to 1e-13 (the reference the GPU answers are measured against) and
+    to the workload tolerance (the CPU time to tolerance).  The pressure
+    right-hand side of step 1 comes from the reference velocity predictions.
+    Solves run in the OpenMP build of the oracle with `threads` threads."""
+    import oracle
+    from oracle.step import OracleStep
+    t0 = time.time()
+    ost = OracleStep(m, wl.nu_h, wl.nu_v, wl.dt)
+    log(f"oracle assembly of the step forms {time.time() - t0:.1f}s")
+    n = m.n
+    zero3, zero = np.zeros((3, n)), np.zeros(n)
+    t0 = time.time()
+    b0 = ost.velocity_rhs(zero3, zero, theta, f)
+    ut0 = np.stack([oracle.pcg(ost.A, b0[c], dirichlet=ost.dirichlet[c], tol=wl.tol,
+                               threads=threads).x for c in range(3)])
+    q0 = oracle.pcg(ost.K, ost.pressure_rhs(ut0), singular=True, weights=ost.mL, tol=wl.tol,
+                    threads=threads).x
+    u1, p1 = ost.correct(ut0, q0, zero)
+    log(f"oracle step from rest {time.time() - t0:.1f}s")
+    t0 = time.time()
+    b1 = ost.velocity_rhs(u1, p1, theta, f)
+    systems = {}
+    ut1 = np.zeros((3, n))
+
+    def solve(name, A, b, d, bit, singular):
+        w = ost.mL if singular else None
+        ex = oracle.pcg(A, b, dirichlet=d, singular=singular, weights=w, tol=1e-13,
+                        history=True, threads=threads)
+        at = oracle.pcg(A, b, dirichlet=d, singular=singular, weights=w, tol=wl.tol,
+                        threads=threads)
+        systems[name] = {"b": b, "bit": bit, "exact": ex.x, "exact_status": ex.status,
+                         "exact_iters": ex.iterations,
+                         "kappa": oracle.lanczos_condition(ex.alphas, ex.betas),
+                         "cpu_iters": at.iterations, "cpu_s": at.loop_s}
+        return ex.x
+
+    for c in range(3):
+        ut1[c] = solve(f"u{c + 1}", ost.A, b1[c], ost.dirichlet[c], c, False)
+    solve("q", ost.K, ost.pressure_rhs(ut1), None, -1, True)
+    log(f"oracle step-1 references {time.time() - t0:.1f}s: "
+        + ", ".join(f"{k}: {v['exact_iters']} it to 1e-13 (status {v['exact_status']}), "
+                    f"{v['cpu_iters']} it / {v['cpu_s']:.2f}s to {wl.tol:g}, "
+                    f"kappa ~{v['kappa']:.3g}" for k, v in systems.items()))
+    return systems
+
+
+ERROR_TARGET = 1e-9
+TOL_LADDER = (1e-10, 1e-11, 1e-12)
+
+
+def bench_errors(torch, log, helm, pois, systems, reps=3):
+    """Each step-1 system of the oracle solved on the GPU (FP64 and mixed) at
+    the tolerances of TOL_LADDER, until the relative error against the
+    oracle's 1e-13 solution is at most ERROR_TARGET: time to the workload
+    tolerance (the first rung) and time to that error, separately (median
+    of `reps` solves from x0 = 0, operator and b resident)."""
+    out = {}
+    for name, sy in systems.items():
+        op = pois if name == "q" else helm
+        b = torch.as_tensor(sy["b"], device="cuda")
+        ex = sy["exact"]
+        row = {"kappa_estimate": float("%.4g" % sy["kappa"]), "exact_iters": sy["exact_iters"]}
+        for mode in ("fp64", "mixed"):
+            ladder = []
+            for tol in TOL_LADDER:
+                ts = []
+                for _ in range(reps):
+                    x = torch.zeros_like(b)
+                    torch.cuda.synchronize()
+                    t = time.perf_counter()
+                    x, info = op.solve(b, x, tol=tol, mask_bit=sy["bit"], mode=mode)
+                    torch.cuda.synchronize()
+                    ts.append(time.perf_counter() - t)
+                xh = x.cpu().numpy()
+                err = float(np.linalg.norm(xh - ex) / np.linalg.norm(ex))
+                ladder.append({"tol": tol, "ms": round(1e3 * float(np.median(ts)), 3),
+                               "iters": info.iterations, "outer": info.outer_iterations,
+                               "status": info.status, "rel_err": float("%.4g" % err)})
+                if err <= ERROR_TARGET:
+                    break
+            hit = ladder[-1]["rel_err"] <= ERROR_TARGET
+            row[mode] = {"time_to_tol_ms": ladder[0]["ms"], "rel_err_at_tol": ladder[0]["rel_err"],
+                         "time_to_1e-9_error_ms": ladder[-1]["ms"] if hit else None,
+                         "tol_for_1e-9_error": ladder[-1]["tol"] if hit else None,
+                         "ladder": ladder}
+        out[name] = row
+        log(f"errors vs oracle {name}: " + json.dumps(row))
+    return out
+
+
+def cpu_baseline(log, wl, systems, threads, m2_bytes_iter):
+    """The oracle timed on this host: the four step-1 solves of the 256x256x20
+    step to the workload tolerance with `threads` OpenMP threads (loop time;
+    the headline figure, in GB/s of the CSR-equivalent Jacobi-PCG bytes),
+    a one-thread sample of the plain parity build on the pressure solve, the
+    16x16x4 box case, and the 48 right-hand sides of the 128x128x20 basin
+    solved one after another."""
+    import basin
+    import oracle
+    from oracle.step import OracleStep
+    its = sum(v["cpu_iters"] for v in systems.values())
+    secs = sum(v["cpu_s"] for v in systems.values())
+    gbs = its * m2_bytes_iter / secs / 1e9
+    out = {"value": round(gbs, 3), "unit": "GB/s", "cores": threads, "kind": "oracle",
+           "sample": f"the four time-step-1 solves of {wl.name} (the oracle's own right-hand "
+                     f"sides) to {wl.tol:g}, OpenMP build of the oracle, {threads} threads, "
+                     f"iteration loops only ({secs:.1f} s)",
+           "cpu": host_cpu(), "threads": threads,
+           "c2_solves": {k: {"iters": v["cpu_iters"], "s": round(v["cpu_s"], 3)}
+                         for k, v in systems.items()},
+           "c2_solves_total_s": round(secs, 3)}
+    # one thread, plain parity build: the first 300 pressure iterations
+    q = systems["q"]
+    wlq = basin.configs.BASIN_256x256x20
+    m = wlq.mesh()
+    K = oracle.stiffness(m, wlq.nu_h, wlq.nu_v)
+    w = oracle.mass(m).matvec(np.ones(m.n))
+    r = oracle.pcg(K, q["b"], singular=True, weights=w, tol=wlq.tol, maxit=300)
+    out["one_thread"] = {"s_per_iter": round(r.loop_s / max(r.iterations, 1), 5),
+                         "GBs": round(r.iterations * m2_bytes_iter / r.loop_s / 1e9, 3),
+                         "sample": f"first {r.iterations} iterations of the pressure solve, "
+                                   "plain parity build"}
+    del K
+    # the small box case
+    cfg = basin.configs.BOX_16x16x4
+    mb = cfg.mesh()
+    d = ~mb.free_mask(basin.BC_U1)
+    bb = basin.normal_rhs(mb.n, cfg.seed, zero_mean=True, dirichlet=d)
+    Kb = oracle.stiffness(mb, cfg.nu_h, cfg.nu_v)
+    box = {}
+    for t in (1, threads):
+        rs = [oracle.pcg(Kb, bb, dirichlet=d, tol=cfg.tol, threads=t) for _ in range(3)]
+        box[f"threads_{t}"] = {"iters": rs[0].iterations,
+                               "us_median": round(1e6 * float(np.median([x.loop_s for x in rs])), 1)}
+    out["box16x16x4"] = box
+    # 48 right-hand sides on 128x128x20, one solve after another
+    wl4 = basin.configs.BASIN_128x128x20_BATCH
+    m4 = wl4.mesh()
+    ost = OracleStep(m4, wl4.nu_h, wl4.nu_v, wl4.dt)
+    f4 = basin.coriolis_parameter(m4.xyz[:, 1], m4.Ly)
+    tot_s, tot_it = 0.0, 0
+    for s_, sc in enumerate(basin.wind_scenarios(wl4.extra["scenarios"],
+                                                 wl4.extra["scenario_seed"])):
+        theta = np.stack([basin.wind_tension(m4.xyz[:, 1], m4.Ly, sc.amplitude, sc.phase),
+                          np.zeros(m4.n)])
+        u, p = basin.random_state(m4.n, 100 + s_, m4.bc)
+        b = ost.velocity_rhs(u, p, theta, f4)
+        for c in range(3):
+            r = oracle.pcg(ost.A, b[c], dirichlet=ost.dirichlet[c], tol=wl4.tol, threads=threads)
+            tot_s += r.loop_s
+            tot_it += r.iterations
+    out["basin128x128x20_48_sequential"] = {
+        "s": round(tot_s, 3), "iters": tot_it,
+        "rhs": "velocity right-hand sides of 16 wind scenarios from a seeded state per scenario"}
+    log(f"cpu baseline: {out}")
+    return out
+
+
 COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "counters_spmv_sdia_fp64_basin256x256x20.md")
 KERNEL_SOURCES = ("kernels.hip", "kernels.h", "hns_internal.h")
 
@@ -483,12 +677,18 @@ def bench_preconditioners(torch, log, m, b_vel, reps=3):
     return out
 
 
-def bench_serving(torch, log, budget_gb=16.0, mode="fp64", count=256, capacity=8, chunk=32):
+def bench_serving(torch, log, budget_gb=1.5, mode="fp64", count=256, capacity=8, chunk=32,
+                  check=True, oracle_cache=None):
     """Serving: Poisson-process arrivals (50 req/s) of pressure / velocity solve
     requests over five mesh sizes, tolerance 1e-8, continuous batching with
-    operators admitted by footprint and kept resident."""
+    operators admitted by footprint under an HBM budget (the whole set of ten
+    operators needs about 3.5 GB, so a budget of 1.5 GB makes the server
+    evict idle operators and assemble them again).  check=True: one request
+    per mesh size is solved again alone on a fresh operator (the served
+    answer must be the same) and checked by the oracle's own residual."""
     import threading
     import basin
+    from paper_1207_0486_amd.hns import Operator
     from paper_1207_0486_amd.serve import GpuBackend, Request, Server
     wl = basin.configs.SERVING
     meshes = {}
@@ -504,7 +704,8 @@ def bench_serving(torch, log, budget_gb=16.0, mode="fp64", count=256, capacity=8
     t0 = time.time()
     be = GpuBackend(make, mode=mode, check_every=16)
     srv = Server(be, budget_bytes=int(budget_gb * (1 << 30)), capacity=capacity, chunk=chunk)
-    # warm-up: one request per operator (assembly, tuning, graph capture)
+    # warm-up: one request per operator (assembly, tuning); with a small
+    # budget the early operators are evicted again
     keys = sorted({(r.mesh_index, r.kind) for r in reqs})
     warm = []
     for key in keys:
@@ -514,13 +715,16 @@ def bench_serving(torch, log, budget_gb=16.0, mode="fp64", count=256, capacity=8
         warm.append(srv.submit(Request(key=key, b=basin.normal_rhs(m.n, 7, dirichlet=d),
                                        mask_bit=bit, tol=wl.tol)))
     try:
-        for f in warm:
-            f.result()
+        for fu in warm:
+            fu.result()
     except BaseException:
         srv.close()
         raise
-    srv.results.clear()
-    log(f"serving warm-up: {len(keys)} operators resident ({time.time() - t0:.1f}s)")
+    with srv.lock:
+        srv.results.clear()
+        ev0 = len(srv.events)
+    log(f"serving warm-up ({mode}): {len(keys)} operators, {len(srv.resident)} resident "
+        f"({time.time() - t0:.1f}s)")
     # right-hand sides of the stream, generated before it starts
     items = []
     for r in reqs:
@@ -545,22 +749,78 @@ def bench_serving(torch, log, budget_gb=16.0, mode="fp64", count=256, capacity=8
         th = threading.Thread(target=feeder)
         th.start()
         th.join()
-        results = [f.result() for f in futs]
+        results = [fu.result() for fu in futs]
         end = time.perf_counter()
         st = srv.stats(start, end)
+        stream_events = srv.events[ev0:]
     finally:
         srv.close()
     nodes = sum(make((r.mesh_index, r.kind))[0].n for r, _ in items)
     bad = sum(1 for x in results if x.info.status != 0)
+    per_mesh = {}
+    for (r, _), res in zip(items, results):
+        per_mesh.setdefault(r.mesh_index, []).append(res.latency_s)
+    sizes = basin.forcing.SERVING_MESHES
+    by_mesh = {"x".join(map(str, sizes[i])): {
+        "requests": len(v), "p50_ms": round(float(np.percentile(v, 50)) * 1e3, 2),
+        "p99_ms": round(float(np.percentile(v, 99)) * 1e3, 2)} for i, v in sorted(per_mesh.items())}
     out = {"requests": len(results), "rate_hz": wl.extra["rate_hz"], "tol": wl.tol,
-           "mode": mode, "capacity": capacity, "chunk": chunk, "budget_gb": budget_gb, "p50_ms": round(st["p50_ms"], 2),
-           "p99_ms": round(st["p99_ms"], 2), "mean_ms": round(st["mean_ms"], 2),
-           "solves_per_s": round(st["solves_per_s"], 2), "wall_s": round(end - start, 3),
-           "nodes_solved": int(nodes), "failed": bad, "operators_resident": len(keys),
-           "peak_gb": round(st["peak_bytes"] / (1 << 30), 3), "evictions": st["evictions"],
-           "meshes": [list(m) for m in basin.forcing.SERVING_MESHES]}
+           "mode": mode, "capacity": capacity, "chunk": chunk, "budget_gb": budget_gb,
+           "p50_ms": round(st["p50_ms"], 2), "p99_ms": round(st["p99_ms"], 2),
+           "mean_ms": round(st["mean_ms"], 2), "solves_per_s": round(st["solves_per_s"], 2),
+           "wall_s": round(end - start, 3), "nodes_solved": int(nodes), "failed": bad,
+           "operators": len(keys), "peak_gb": round(st["peak_bytes"] / (1 << 30), 3),
+           "admissions_in_stream": sum(1 for e in stream_events if e[1] == "admit"),
+           "evictions_in_stream": sum(1 for e in stream_events if e[1] == "evict"),
+           "evictions": st["evictions"], "by_mesh": by_mesh,
+           "meshes": [list(mm) for mm in sizes]}
+    if check:
+        out["check"] = serving_check(torch, log, items, results, make, mode, wl.tol,
+                                     oracle_cache)
     log(f"serving: {out}")
     return out
+
+
+def serving_check(torch, log, items, results, make, mode, tol, cache):
+    """One served request per mesh size (the first of each in the stream):
+    the same solve alone on a freshly assembled operator (per-slot sessions
+    run hns_solve's recurrence, so the answers should agree bit for bit) and
+    the oracle's own residual of the served answer."""
+    import oracle
+    from paper_1207_0486_amd.hns import Operator
+    cache = {} if cache is None else cache
+    seen, rows = set(), []
+    for (r, q), res in zip(items, results):
+        if r.mesh_index in seen:
+            continue
+        seen.add(r.mesh_index)
+        m, nu_h, nu_v, dt, kind = make(q.key)
+        op = Operator(m, nu_h, nu_v, dt, kind=kind, keep_fp32=mode == "mixed",
+                      gpu_assembly=True)
+        op.set_param("check_every", 16)
+        x, info = op.solve(torch.as_tensor(q.b, device="cuda"), tol=tol, mask_bit=q.mask_bit,
+                           mode=mode)
+        alone = x.cpu().numpy()
+        op.close()
+        diff = float(np.abs(res.x - alone).max() / max(np.abs(alone).max(), 1e-300))
+        if q.key not in cache:
+            cache[q.key] = (oracle.stiffness(m, nu_h, nu_v) if kind == "poisson"
+                            else oracle.helmholtz(m, nu_h, nu_v, dt))
+        A = cache[q.key]
+        if q.mask_bit < 0:
+            bh = q.b - q.b.mean()
+            rr = bh - A.matvec(res.x)
+            rr -= rr.mean()
+            relres = float(np.linalg.norm(rr) / np.linalg.norm(bh))
+        else:
+            d = ((m.bc >> q.mask_bit) & 1) == 1
+            relres = oracle.relres(A, q.b, res.x, d)
+        rows.append({"mesh": r.mesh_index, "kind": kind, "nodes": m.n,
+                     "served_iters": res.info.iterations, "alone_iters": info.iterations,
+                     "max_rel_diff_vs_alone": diff, "oracle_relres": float("%.4g" % relres)})
+    ok = all(x["max_rel_diff_vs_alone"] == 0.0 and x["oracle_relres"] <= 1.01 * tol for x in rows)
+    log(f"serving check ({mode}): {rows}")
+    return {"ok": ok, "samples": rows}
 
 
 def traffic_probe(torch, log, iters=64, q2_iters=16):
@@ -601,14 +861,17 @@ def traffic_probe(torch, log, iters=64, q2_iters=16):
 
 
 def main():
+    # the OpenMP build of the oracle (CPU baseline) reads these when loaded
+    os.environ.setdefault("OMP_PROC_BIND", "close")
+    os.environ.setdefault("OMP_PLACES", "cores")
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--check-every", type=int, default=32)
-    ap.add_argument("--cpu-iters", type=int, default=1000,
-                    help="oracle PCG iterations in the CPU-baseline sample")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the oracle: its step-1 references, the per-solve errors and the "
+                         "CPU baseline")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-isotropic", action="store_true")
@@ -619,7 +882,8 @@ def main():
                     help="only a 1 GiB copy, 64 pressure iterations and 16 Q2 velocity "
                          "iterations (for counter passes)")
     ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--serve-budget-gb", type=float, default=16.0)
+    ap.add_argument("--serve-budget-gb", type=float, default=1.5,
+                    help="HBM budget of the serving stream (its ten operators need ~3.5 GB)")
     ap.add_argument("--serve-mode", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--serve-capacity", type=int, default=2,
                     help="slots per operator session")
@@ -672,11 +936,26 @@ def main():
         f"{r0.pressure.iterations} ({time.time() - t0:.1f}s)")
 
     def one_step(mode):
+        """The step of ProjectionStep.step, with the wall time of each solve
+        (hns_solve returns when its answer is final)."""
         st.set_state(u1, p1)
-        res = st.step(tol=wl.tol, mode=mode)
-        infos = {f"u{c + 1}": res.velocity[c] for c in range(3)}
-        infos["q"] = res.pressure
-        return infos
+        infos, times = {}, {}
+        st.velocity_rhs()
+        for c in range(3):
+            st.ut[c].zero_()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            _, infos[f"u{c + 1}"] = helm.solve(st.b_vel[c], st.ut[c], tol=wl.tol, mask_bit=c,
+                                               mode=mode)
+            times[f"u{c + 1}"] = time.perf_counter() - t
+        st.pressure_rhs()
+        st.q.zero_()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, infos["q"] = pois.solve(st.b_q, st.q, tol=wl.tol, mask_bit=-1, mode=mode)
+        times["q"] = time.perf_counter() - t
+        st.correct()
+        return infos, times
 
     def timed(mode, steps, warmup, profile):
         for _ in range(warmup):
@@ -687,19 +966,24 @@ def main():
         t = time.perf_counter()
         per = []
         infos = None
+        solve_s = {}
         for _ in range(steps):
             ts = time.perf_counter()
-            infos = one_step(mode)
+            infos, times = one_step(mode)
             torch.cuda.synchronize()
             per.append(time.perf_counter() - ts)
+            for k, v in times.items():
+                solve_s.setdefault(k, []).append(v)
         torch.cuda.synchronize()
         total = time.perf_counter() - t
         prof = {"helm": helm.profile_read(), "pois": pois.profile_read()}
         for op in (helm, pois):
             op.profile(0)
-        return total, per, infos, prof
+        solve_ms = {k: round(1e3 * float(np.median(v)), 3) for k, v in solve_s.items()}
+        return total, per, infos, prof, solve_ms
 
-    total64, per64, infos64, prof64 = timed("fp64", args.steps, args.warmup, args.profile_period)
+    total64, per64, infos64, prof64, solve_ms64 = timed("fp64", args.steps, args.warmup,
+                                                         args.profile_period)
     u64 = st.u.clone()
     ms64 = 1e3 * total64 / args.steps
     fmt = pois.format
@@ -729,7 +1013,8 @@ def main():
 
     mixed = None
     if not args.no_mixed:
-        totalm, perm, infosm, profm = timed("mixed", args.steps, args.warmup, args.profile_period)
+        totalm, perm, infosm, profm, solve_msm = timed("mixed", args.steps, args.warmup,
+                                                       args.profile_period)
         msm = 1e3 * totalm / args.steps
         diff = float(torch.linalg.norm(st.u - u64) / torch.linalg.norm(u64))
         k32 = {}
@@ -742,12 +1027,20 @@ def main():
             "variant": "FP32 CG, FP64 residual replacement",
             "velocity_rel_diff_vs_fp64": diff,
             "solves": {k: {"fp32_iters": i.iterations, "replacements": i.outer_iterations,
-                           "relres": i.relres_true}
+                           "relres": i.relres_true, "ms": solve_msm[k]}
                        for k, i in infosm.items()},
             "pressure_kernels": k32,
         }
         log(f"mixed: {msm:.1f} ms/step (x{ms64 / msm:.2f}), "
             + ", ".join(f"{k}={i.iterations}/{i.outer_iterations}" for k, i in infosm.items()))
+
+    # per-solve error against the oracle (its own step-1 systems solved to
+    # 1e-13), time to the tolerance and time to 1e-9 error, FP64 and mixed
+    systems = errors = None
+    threads = oracle_threads()
+    if not args.no_cpu_baseline:
+        systems = oracle_reference(m, wl, theta, f, threads, log)
+        errors = bench_errors(torch, log, helm, pois, systems)
 
     # the same step with the pressure solve preconditioned by the vertical-line
     # blocks (the velocity solves keep point Jacobi): FP64 and mixed precision
@@ -756,7 +1049,7 @@ def main():
         pois.set_param("precond", 1)
         line_step = {}
         for mode in ("fp64",) + (() if args.no_mixed else ("mixed",)):
-            tot, per, inf, _ = timed(mode, args.steps, args.warmup, 0)
+            tot, per, inf, _, _ = timed(mode, args.steps, args.warmup, 0)
             ms = 1e3 * tot / args.steps
             line_step[mode] = {"ms_per_step": round(ms, 3),
                                "speedup_vs_fp64_jacobi": round(ms64 / ms, 3),
@@ -801,34 +1094,25 @@ def main():
 
     serving = None
     if not args.no_serving:
+        cache = {}
         serving = bench_serving(torch, log, args.serve_budget_gb, args.serve_mode,
-                                capacity=args.serve_capacity, chunk=args.serve_chunk)
+                                capacity=args.serve_capacity, chunk=args.serve_chunk,
+                                check=not args.no_cpu_baseline, oracle_cache=cache)
         other = "mixed" if args.serve_mode == "fp64" else "fp64"
         serving_other = bench_serving(torch, log, args.serve_budget_gb, other,
-                                      capacity=args.serve_capacity, chunk=args.serve_chunk)
+                                      capacity=args.serve_capacity, chunk=args.serve_chunk,
+                                      check=not args.no_cpu_baseline, oracle_cache=cache)
         serving = {args.serve_mode: serving, other: serving_other}
+        del cache
 
     cpu = None
-    if not args.no_cpu_baseline:
-        import oracle
-        t0 = time.time()
-        K = oracle.stiffness(m, wl.nu_h, wl.nu_v)
-        w = oracle.mass(m).matvec(np.ones(m.n))
-        log(f"oracle assembly {time.time() - t0:.1f}s")
-        t = time.perf_counter()
-        r = oracle.pcg(K, st.b_q.cpu().numpy(), singular=True, weights=w, tol=wl.tol,
-                       maxit=args.cpu_iters)
-        el = time.perf_counter() - t
-        cpu_gbs = r.iterations * bytes_iter("csr", n, nnz, 8) / el / 1e9
-        cpu = {"value": round(cpu_gbs, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
-               "sample": f"first {r.iterations} Jacobi-PCG iterations of the {wl.name} "
-                         f"pressure solve, FP64, 1 thread ({el:.1f} s)",
-               "s_per_iter": round(el / max(r.iterations, 1), 5)}
-        log(f"cpu oracle: {cpu}")
+    if systems is not None:
+        cpu = cpu_baseline(log, wl, systems, threads, bytes_iter("csr", n, nnz, 8))
 
+    moved_gbs = moved64 / (ms64 * 1e-3) / 1e9
     out = {
         "metric": METRIC,
-        "value": round(gbs64, 2),
+        "value": round(moved_gbs, 2),
         "unit": "GB/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -844,15 +1128,22 @@ def main():
                    "rhs": "time step 1 after a step from rest (wind, Coriolis, pressure)",
                    "tol": wl.tol, "nu_h": wl.nu_h, "nu_v": wl.nu_v,
                    "dt": wl.dt},
-        "value_basis": "Jacobi-PCG work of the step in bytes of the diagonal storage (operator "
-                       "read with its diagonal + 12 vector passes per CG iteration) / step time",
+        "value_basis": ("bytes the step's solves move as run / step time: CG on the "
+                        "Jacobi-scaled operator (upper diagonals without the unit diagonal, 10 "
+                        "vector passes and the FP32 weights per iteration)" if scaled else
+                        "bytes the step's solves move as run / step time: operator read + 12 "
+                        "vector passes per Jacobi-PCG iteration"),
         "jacobi_scaled": scaled,
-        "moved_GBs": round(moved64 / (ms64 * 1e-3) / 1e9, 1),
-        "moved_basis": "bytes the solves move as run: CG on the Jacobi-scaled operator (no "
-                       "stored diagonal, 10 vector passes + FP32 weights per iteration)"
-                       if scaled else "same as value",
+        "algorithm_equivalent_GBs": round(gbs64, 1),
+        "algorithm_equivalent_basis": "the same iterations priced as plain Jacobi-PCG on the "
+                                      "diagonal storage (operator with its diagonal + 12 vector "
+                                      "passes) / step time",
         "csr_equivalent_GBs": round(csr_equiv / (ms64 * 1e-3) / 1e9, 1),
-        "fp64": {k: {"iters": i.iterations, "relres": i.relres_true} for k, i in infos64.items()},
+        "fp64": {k: {"iters": i.iterations, "relres": i.relres_true, "ms": solve_ms64[k]}
+                 for k, i in infos64.items()},
+        "pressure_time_to_tol_ms": {"fp64": solve_ms64["q"],
+                                    "mixed": None if mixed is None else solve_msm["q"]},
+        "errors_vs_oracle": errors,
         "step_ms": [round(1e3 * v, 3) for v in per64],
         "roofline": {"bound": "hbm", "achieved": round(spmv_gbs, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(spmv_gbs / PEAK_HBM_GBS, 4), "traffic": traffic,

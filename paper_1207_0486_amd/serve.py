@@ -57,9 +57,11 @@ class GpuBackend:
     of a key; it is assembled on first use.
     """
 
-    def __init__(self, make_operator, device=0, mode="fp64", check_every=16):
+    def __init__(self, make_operator, device=0, mode="fp64", check_every=16,
+                 gpu_assembly=True):
         import torch
         self.torch = torch
+        self.gpu_assembly = gpu_assembly   # operator values computed on the device
         self._make = make_operator
         self._made = {}
         self._made_lock = threading.Lock()
@@ -87,7 +89,7 @@ class GpuBackend:
         mesh, nu_h, nu_v, dt, kind = self.make_operator(key)
         with self.torch.cuda.device(self.device):
             op = Operator(mesh, nu_h, nu_v, dt, kind=kind, keep_fp32=self.mode == "mixed",
-                          device=self.device)
+                          device=self.device, gpu_assembly=self.gpu_assembly)
             op.set_param("check_every", self.check_every)
             op.set_param("use_graph", 1)
             sess = BatchSession(op, capacity, self.mode)
