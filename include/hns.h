@@ -181,6 +181,35 @@ hns_status hns_solve(hns_operator *op, int mask_bit, const double *b_dev, double
                      double tol, int max_iter, uint32_t mode, void *stream,
                      hns_solve_info *info);
 
+/* Allocation-free variant of hns_solve, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Same arguments, results and errors as hns_solve,
+ * but the solve's workspace (CG vectors, partial sums, device scalars) lives
+ * in a static device array of the library (hns_noalloc_scratch_bytes() =
+ * 96 MiB; each GPU the library runs on holds its own copy until the process
+ * ends), and the call allocates nothing: no hipMalloc, hipFree or pinned host
+ * memory.  Every call on one GPU shares that array, which keeps the last
+ * call's contents (each call initialises what it reads), so calls that
+ * overlap on one GPU race: the caller serialises them.
+ *   - point Jacobi only: an operator with set_param "precond" != 0 is
+ *     HNS_ERR_INVALID;
+ *   - where hns_solve would run the Jacobi-scaled recurrence, that recurrence
+ *     runs if the operator already holds its scaled copy (built by a
+ *     previous hns_solve), else the unscaled point-Jacobi recurrence (the
+ *     same iterates in exact arithmetic, another rounding);
+ *   - an operator whose workspace exceeds the scratch (hns_noalloc_bytes(op,
+ *     mode) > hns_noalloc_scratch_bytes(): beyond about 3.1M rows in HNS_FP64
+ *     and 2.5M in HNS_MIXED) is HNS_ERR_INVALID, with nothing run;
+ *   - per-kernel timing (hns_profile_enable) is not recorded by these calls. */
+hns_status hns_solve_noalloc(hns_operator *op, int mask_bit, const double *b_dev,
+                             double *x_dev, double tol, int max_iter, uint32_t mode,
+                             void *stream, hns_solve_info *info);
+
+/* Scratch bytes hns_solve_noalloc needs for `op` in `mode`, and the size of
+ * the static scratch (0 for a null operator). */
+size_t hns_noalloc_bytes(const hns_operator *op, uint32_t mode);
+size_t hns_noalloc_scratch_bytes(void);
+
 /* Solve k independent systems A x_j = b_j sharing one read of A per iteration
  * (multi-right-hand-side CG; each column keeps its own CG scalars, reduced
  * deterministically, and stops on its own).  B_dev and X_dev are n x k

@@ -57,6 +57,11 @@ _SIGNATURES = {
                                    C.c_double, C.c_uint32, C.POINTER(C.c_void_p)]),
     "hns_solve": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_double, C.c_int,
                             C.c_uint32, C.c_void_p, C.POINTER(hns_solve_info)]),
+    "hns_solve_noalloc": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_double,
+                                    C.c_int, C.c_uint32, C.c_void_p,
+                                    C.POINTER(hns_solve_info)]),
+    "hns_noalloc_bytes": (C.c_size_t, [C.c_void_p, C.c_uint32]),
+    "hns_noalloc_scratch_bytes": (C.c_size_t, []),
     "hns_solve_batched": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int), C.c_void_p,
                                     C.c_void_p, C.c_double, C.c_int, C.c_uint32, C.c_void_p,
                                     C.POINTER(hns_solve_info)]),

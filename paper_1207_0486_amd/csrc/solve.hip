@@ -39,29 +39,22 @@ struct Workspace {
     Scalars *host = nullptr;      // pinned mirror of sc[0..1]
     std::vector<hipEvent_t> ev;   // timing events, a (start, end) pair per kernel of an iteration
     uint32_t token = 0;           // last iteration tag handed out (IterArgs::token)
+    bool borrowed = false;        // buffers lent by the caller (nothing freed, no timing events)
+
+    static size_t al(size_t b) { return (b + 255) & ~size_t(255); }
 
     static size_t bytes_for(int64_t n, bool mixed)
     {
-        auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
         size_t b = 3 * al(n * sizeof(double));
         if (mixed) b += 4 * al(n * sizeof(float));
         b += al(kPartTotal * sizeof(double)) + al(2 * sizeof(Scalars));
         return b;
     }
 
-    hns_status allocate(int64_t n_, bool mixed_)
+    // points the buffers into `base` (bytes_for(n, mixed) bytes, 256-byte
+    // aligned, plus al(8 n) more for z when with_z)
+    void carve(char *c, bool with_z)
     {
-        n = n_;
-        mixed = mixed_;
-        auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
-        hipError_t e = hipMalloc(&block, bytes_for(n, mixed));
-        if (e != hipSuccess) {
-            block = nullptr;
-            set_error("workspace allocation of %zu bytes failed: %s", bytes_for(n, mixed),
-                      hipGetErrorString(e));
-            return e == hipErrorOutOfMemory ? HNS_ERR_OOM : HNS_ERR_HIP;
-        }
-        char *c = (char *)block;
         r = (double *)c, c += al(n * sizeof(double));
         p = (double *)c, c += al(n * sizeof(double));
         q = (double *)c, c += al(n * sizeof(double));
@@ -72,11 +65,40 @@ struct Workspace {
             d32 = (float *)c, c += al(n * sizeof(float));
         }
         partials = (double *)c, c += al(kPartTotal * sizeof(double));
-        sc = (Scalars *)c;
+        sc = (Scalars *)c, c += al(2 * sizeof(Scalars));
+        if (with_z) z = (double *)c;
+    }
+
+    hns_status allocate(int64_t n_, bool mixed_)
+    {
+        n = n_;
+        mixed = mixed_;
+        hipError_t e = hipMalloc(&block, bytes_for(n, mixed));
+        if (e != hipSuccess) {
+            block = nullptr;
+            set_error("workspace allocation of %zu bytes failed: %s", bytes_for(n, mixed),
+                      hipGetErrorString(e));
+            return e == hipErrorOutOfMemory ? HNS_ERR_OOM : HNS_ERR_HIP;
+        }
+        carve((char *)block, false);
         HNS_TRY_HIP(hipMemset(sc, 0, 2 * sizeof(Scalars)));
         HNS_TRY_HIP(hipHostMalloc((void **)&host, 2 * sizeof(Scalars), hipHostMallocDefault));
         memset(host, 0, 2 * sizeof(Scalars));
         return HNS_OK;
+    }
+
+    // buffers lent by the caller: device memory `base` as carve() lays it
+    // out, and a host mirror of the two scalar blocks
+    void borrow(int64_t n_, bool mixed_, void *base, bool with_z, Scalars *host_mirror,
+                uint32_t token0)
+    {
+        n = n_;
+        mixed = mixed_;
+        borrowed = true;
+        carve((char *)base, with_z);
+        host = host_mirror;
+        memset(host, 0, 2 * sizeof(Scalars));
+        token = token0;
     }
 
     hns_status ensure_events(size_t count)
@@ -118,6 +140,7 @@ struct Workspace {
     ~Workspace()
     {
         for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+        if (borrowed) return;
         if (z) (void)hipFree(z);
         if (y) (void)hipFree(y);
         if (block) (void)hipFree(block);
@@ -206,7 +229,7 @@ static hns_status enqueue_iterations(hns_operator *op, Workspace *w, Prec prec, 
                                      const void *lfac = nullptr, const IC0Dev *ic = nullptr,
                                      bool scaled = false)
 {
-    const int period = op->profile;
+    const int period = w->borrowed ? 0 : op->profile;
     if (period > 0) HNS_TRY(w->ensure_events(6 * (size_t)count));
     IterArgs a{&op->A, prec, op->n, x, r, p, q, dinv, op->bc, bit, sc, w->partials};
     if (scaled) {
@@ -246,7 +269,7 @@ static hns_status enqueue_iterations(hns_operator *op, Workspace *w, Prec prec, 
 // counters.
 static hns_status account_iterations(hns_operator *op, Workspace *w, bool fp32, int done)
 {
-    const int period = op->profile;
+    const int period = w->borrowed ? 0 : op->profile;
     if (period <= 0 || done <= 0) return HNS_OK;
     const int base = fp32 ? 3 : 0;
     for (int it = period / 2; it < done; it += period)
@@ -1570,6 +1593,125 @@ static hns_status ic0_factors(hns_operator *op, int bit, const IC0Dev **out)
     }
     *out = slot;
     return HNS_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free solves (hns_solve_noalloc): the workspace of a solve lives
+// in `scratch`, a file-scope device array of which every GPU the library
+// runs on holds its own copy until the process ends.  Host code never uses
+// the array's name as an address: the device address of each GPU's copy is
+// looked up once per device (with that device current) and kept here.  The
+// host mirror of the CG scalars is a file-scope host array per device.  Calls
+// on one GPU share all of it, so calls that overlap on one GPU race.
+// ---------------------------------------------------------------------------
+namespace hns {
+
+constexpr size_t kScratchBytes = size_t(96) << 20;   // 96 MiB per GPU
+constexpr int kScratchDevices = 64;
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+static std::mutex g_scratch_mutex;
+static void *g_scratch_dev[kScratchDevices];          // scratch's address on each GPU
+static Scalars g_scratch_host[kScratchDevices][2];    // host mirror of the scalars
+static uint32_t g_scratch_token[kScratchDevices];     // iteration tags handed out so far
+
+// Device address of `scratch` on the current device (looked up on the
+// device's first call) and the device's index.
+static hns_status scratch_address(void **out, int *dev_out)
+{
+    int dev = -1;
+    HNS_TRY_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kScratchDevices) {
+        set_error("hns_solve_noalloc: device %d is beyond the %d devices it supports", dev,
+                  kScratchDevices);
+        return HNS_ERR_INVALID;
+    }
+    std::lock_guard<std::mutex> g(g_scratch_mutex);
+    if (!g_scratch_dev[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            set_error("hns_solve_noalloc: address of the static scratch on device %d: %s", dev,
+                      e != hipSuccess ? hipGetErrorString(e) : "null address");
+            return HNS_ERR_HIP;
+        }
+        g_scratch_dev[dev] = ptr;
+    }
+    *out = g_scratch_dev[dev];
+    *dev_out = dev;
+    return HNS_OK;
+}
+
+}  // namespace hns
+
+extern "C" {
+
+size_t hns_noalloc_scratch_bytes(void) { return kScratchBytes; }
+
+size_t hns_noalloc_bytes(const hns_operator *op, uint32_t mode)
+{
+    if (!op) return 0;
+    const bool mixed = (mode == HNS_MIXED);
+    // the correction vector of the Jacobi-scaled FP64 recurrence is counted
+    // whether or not that recurrence runs
+    return Workspace::bytes_for(op->n, mixed) + (mixed ? 0 : Workspace::al(op->n * sizeof(double)));
+}
+
+hns_status hns_solve_noalloc(hns_operator *op, int mask_bit, const double *b_dev, double *x_dev,
+                             double tol, int max_iter, uint32_t mode, void *stream,
+                             hns_solve_info *info)
+{
+    hns_solve_info local;
+    if (!info) info = &local;
+    memset(info, 0, sizeof(*info));
+    hns_status st = check_solve_args(op, mask_bit, b_dev, x_dev, tol, max_iter, mode);
+    if (st == HNS_OK && op->precond != 0) {
+        set_error("hns_solve_noalloc runs point Jacobi only (set_param \"precond\" = 0): the "
+                  "other preconditioners build factors on first use");
+        st = HNS_ERR_INVALID;
+    }
+    if (st == HNS_OK && op->bad_diag >= 0) {
+        set_error("diagonal entry %lld is not positive: Jacobi-PCG needs an SPD operator",
+                  (long long)op->bad_diag);
+        st = HNS_ERR_BREAKDOWN;
+    }
+    const bool mixed = (mode == HNS_MIXED);
+    const size_t need = (st == HNS_OK) ? hns_noalloc_bytes(op, mode) : 0;
+    if (st == HNS_OK && need > kScratchBytes) {
+        set_error("hns_solve_noalloc: %lld rows need %zu bytes of scratch, more than the %zu "
+                  "bytes of the static scratch",
+                  (long long)op->n, need, kScratchBytes);
+        st = HNS_ERR_INVALID;
+    }
+    void *base = nullptr;
+    int dev = 0;
+    if (st == HNS_OK) st = scratch_address(&base, &dev);
+    if (st != HNS_OK) {
+        info->status = st;
+        return st;
+    }
+    // hns_solve's recurrence where the operator already holds what it needs:
+    // the Jacobi-scaled copy is built (and allocated) by hns_solve on its
+    // first use, so without it the unscaled point-Jacobi recurrence runs (the
+    // same iterates in exact arithmetic)
+    bool scaled = op->jacobi_scaling && op->A.fmt == HNS_FMT_SDIA && op->A.ndiag >= 1 &&
+                  op->A.ndiag <= kMaxDiag && op->n > op->small_n &&
+                  (!mixed || op->mixed_variant == 0);
+    if (scaled) {
+        std::lock_guard<std::mutex> g(op->line_mutex);
+        scaled = op->S.dia && (!mixed || op->S.dia32);
+    }
+    Workspace w;
+    w.borrow(op->n, mixed, base, !mixed, g_scratch_host[dev], g_scratch_token[dev]);
+    SolveCtx c{op,       mask_bit, op->kind == HNS_POISSON && mask_bit < 0, b_dev, x_dev, tol,
+               max_iter, (hipStream_t)stream, &w, nullptr, nullptr, nullptr, scaled};
+    st = mixed ? solve_mixed(c, info) : solve_fp64(c, info);
+    g_scratch_token[dev] = w.token;
+    info->status = st;
+    return st;
 }
 
 hns_status hns_solve(hns_operator *op, int mask_bit, const double *b_dev, double *x_dev,

@@ -304,6 +304,31 @@ class Operator:
             raise HNSError(st, "hns_solve")
         return x, SolveInfo._from(info)
 
+    def solve_noalloc(self, b: torch.Tensor, x: torch.Tensor, tol: float = 1e-10,
+                      max_iter: int = 100000, mode: str = "fp64", mask_bit: int = -1,
+                      stream=None, check: bool = True):
+        """hns_solve_noalloc: the solve of `solve` with its workspace in the
+        library's static device scratch (no device allocation; x, the initial
+        guess, is required and overwritten).  Returns (x, SolveInfo)."""
+        bp = _dev_f64(b, "b", self.n)
+        xp = _dev_f64(x, "x", self.n)
+        info = L.hns_solve_info()
+        with torch.cuda.device(self.device):
+            st = L.lib().hns_solve_noalloc(self._h, mask_bit, bp, xp, tol, max_iter, MODES[mode],
+                                           _stream_handle(stream), C.byref(info))
+        if st < 0 and check:
+            raise HNSError(st, "hns_solve_noalloc")
+        return x, SolveInfo._from(info)
+
+    def noalloc_bytes(self, mode: str = "fp64") -> int:
+        """Scratch bytes hns_solve_noalloc needs for this operator in `mode`."""
+        return int(L.lib().hns_noalloc_bytes(self._h, MODES[mode]))
+
+    @staticmethod
+    def noalloc_scratch_bytes() -> int:
+        """Size of the static scratch of hns_solve_noalloc (per GPU)."""
+        return int(L.lib().hns_noalloc_scratch_bytes())
+
     def tune_batched(self, k: int, mode: str = "fp64", stream=None):
         """Time the batched product for k columns at 1/2/4 columns per thread;
         returns ({width: microseconds}, best width)."""
