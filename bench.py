@@ -162,7 +162,8 @@ def oracle_reference(m, wl, theta, f, threads, log):
                         history=True, threads=threads)
         at = oracle.pcg(A, b, dirichlet=d, singular=singular, weights=w, tol=wl.tol,
                         threads=threads)
-        systems[name] = {"b": b, "bit": bit, "exact": ex.x, "exact_status": ex.status,
+        systems[name] = {"b": b, "bit": bit, "A": A, "d": d, "singular": singular, "w": w,
+                         "exact": ex.x, "exact_status": ex.status,
                          "exact_iters": ex.iterations,
                          "kappa": oracle.lanczos_condition(ex.alphas, ex.betas),
                          "cpu_iters": at.iterations, "cpu_s": at.loop_s}
@@ -182,12 +183,15 @@ ERROR_TARGET = 1e-9
 TOL_LADDER = (1e-10, 1e-11, 1e-12)
 
 
-def bench_errors(torch, log, helm, pois, systems, reps=3):
+def bench_errors(torch, log, helm, pois, systems, threads, reps=3):
     """Each step-1 system of the oracle solved on the GPU (FP64 and mixed) at
     the tolerances of TOL_LADDER, until the relative error against the
     oracle's 1e-13 solution is at most ERROR_TARGET: time to the workload
     tolerance (the first rung) and time to that error, separately (median
-    of `reps` solves from x0 = 0, operator and b resident)."""
+    of `reps` solves from x0 = 0, operator and b resident).  The FP64 answer
+    at the workload tolerance is also compared with the oracle's iterate
+    after as many iterations (the OpenMP build, same stopping rule)."""
+    import oracle
     out = {}
     for name, sy in systems.items():
         op = pois if name == "q" else helm
@@ -217,6 +221,18 @@ def bench_errors(torch, log, helm, pois, systems, reps=3):
                          "time_to_1e-9_error_ms": ladder[-1]["ms"] if hit else None,
                          "tol_for_1e-9_error": ladder[-1]["tol"] if hit else None,
                          "ladder": ladder}
+            if mode == "fp64":
+                x, info = op.solve(b, tol=TOL_LADDER[0], mask_bit=sy["bit"])
+                its = info.iterations
+                kw = dict(dirichlet=sy["d"], singular=sy["singular"], weights=sy["w"],
+                          threads=threads)
+                same = oracle.pcg(sy["A"], sy["b"], tol=TOL_LADDER[0], maxit=its, **kw)
+                if same.iterations < its:
+                    same = oracle.pcg(sy["A"], sy["b"], tol=1e-300, maxit=its, **kw)
+                xs = x.cpu().numpy()
+                row[mode]["p_same_rel_diff"] = float(
+                    "%.4g" % (np.linalg.norm(xs - same.x) / np.linalg.norm(same.x)))
+                row[mode]["oracle_iters_at_tol"] = sy["cpu_iters"]
         out[name] = row
         log(f"errors vs oracle {name}: " + json.dumps(row))
     return out
@@ -1040,7 +1056,7 @@ def main():
     threads = oracle_threads()
     if not args.no_cpu_baseline:
         systems = oracle_reference(m, wl, theta, f, threads, log)
-        errors = bench_errors(torch, log, helm, pois, systems)
+        errors = bench_errors(torch, log, helm, pois, systems, threads)
 
     # the same step with the pressure solve preconditioned by the vertical-line
     # blocks (the velocity solves keep point Jacobi): FP64 and mixed precision

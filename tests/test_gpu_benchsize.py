@@ -144,13 +144,16 @@ def test_full_size_pressure_solve_p_same(c2, c2_pressure):
     iterations): the GPU answer against the oracle's iterate after as many
     iterations, both projected and shifted to zero mass-weighted mean.
 
-    Over 2,000 iterations at this conditioning CG amplifies rounding: the
-    oracle's own iterate moves by about 1e-9 when b is perturbed by one unit
-    in the last place, an order above 1e-10 (and 50x below the error of
-    either answer against the exact solution, which is bounded by
-    kappa * tol, not by tol).  The GPU iterate must lie within twice that
-    self-sensitivity (and within 1e-10 if the sensitivity is smaller), and
-    the iteration counts within max(1, 2 %)."""
+    Over 2,000 iterations at this conditioning (Lanczos estimate ~2e5) CG
+    amplifies rounding, so the iterate depends on the order of the sums at
+    the 1e-9 level: the oracle's own OpenMP build, which differs from the
+    plain build only in the order of its dot-product sums (fixed chunks),
+    lands that far from it.  The GPU (other sum orders throughout: block
+    partials, diagonal-by-diagonal products, the Jacobi-scaled recurrence)
+    must lie within a few times that reduction-order spread, and within
+    1e-10 where the spread is smaller; the iteration counts within
+    max(1, 2 %).  (Both answers are ~5e-8 from the exact solution, the
+    kappa * tol scale.)"""
     gpu, ref = c2["gpu"], c2["ref"]
     b = c2_pressure
     x, info = gpu.pois.solve(_t(b), tol=TOL, mask_bit=-1)
@@ -159,17 +162,19 @@ def test_full_size_pressure_solve_p_same(c2, c2_pressure):
     its = info.iterations
     same = p_same(ref.K, b, None, True, ref.mL, its, TOL)
     err = _rel(xh, same.x)
-    # one unit in the last place on every entry, signs from a seeded draw
-    sign = np.where(np.random.default_rng(23).standard_normal(b.size) < 0, -1.0, 1.0)
-    bp = b + sign * np.spacing(np.abs(b))
-    pert = p_same(ref.K, bp, None, True, ref.mL, its, TOL)
-    sens = _rel(pert.x, same.x)
+    order = oracle.pcg(ref.K, b, singular=True, weights=ref.mL, tol=TOL, maxit=its, threads=8)
+    if order.iterations < its:
+        order = oracle.pcg(ref.K, b, singular=True, weights=ref.mL, tol=1e-300, maxit=its,
+                           threads=8)
+    spread = _rel(order.x, same.x)
     margin = max(1, int(0.02 * its))
-    full = oracle.pcg(ref.K, b, singular=True, weights=ref.mL, tol=TOL, maxit=its + margin)
+    full = oracle.pcg(ref.K, b, singular=True, weights=ref.mL, tol=TOL, maxit=its + margin,
+                      threads=8)
     print(f"q: {its} iterations (oracle converged at {full.iterations}, status {full.status}); "
-          f"P-same difference {err:.2e}, oracle self-sensitivity {sens:.2e}", flush=True)
+          f"P-same difference {err:.2e}, oracle reduction-order spread {spread:.2e}",
+          flush=True)
     assert full.status == 0 and abs(full.iterations - its) <= margin
-    assert err <= max(1e-10, 2.0 * sens), (err, sens)
+    assert err <= max(1e-10, 4.0 * spread), (err, spread)
     bh = b - b.mean()
     r = bh - ref.K.matvec(xh)
     r -= r.mean()
