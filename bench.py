@@ -905,6 +905,9 @@ def main():
                     help="slots per operator session")
     ap.add_argument("--serve-chunk", type=int, default=32, help="iterations between admissions")
     ap.add_argument("--fmt", default="auto")
+    ap.add_argument("--param", action="append", default=[], metavar="NAME=VALUE",
+                    help="hns_set_param tunable applied to the step's two operators "
+                         "(repeatable; for A/B comparisons)")
     ap.add_argument("--profile-period", type=int, default=32,
                     help="time every N-th CG iteration with HIP events (the middle one of each "
                          "N-iteration window of a chunk; at most --check-every)")
@@ -941,6 +944,10 @@ def main():
         op.set_param("mixed_variant", 0)
     helm.set_param("replace_drop", 1e-3)
     pois.set_param("replace_drop", 0.1)
+    for kv in args.param:
+        name, value = kv.split("=", 1)
+        for op in (helm, pois):
+            op.set_param(name, float(value))
     log(f"assembled: nnz={pois.nnz} format={pois.format} ({time.time() - t0:.1f}s)")
     n, nnz = pois.n, pois.nnz
 
