@@ -368,7 +368,8 @@ def bench_batched(torch, log, reps=3):
     k = B.shape[1]
     helm = st.helm
     log(f"batched set-up {wl.name}: n={m.n} k={k} ({time.time() - t0:.1f}s)")
-    times, best = helm.tune_batched(k, "mixed")
+    times, plan = helm.tune_batched(k, "mixed")
+    times64, plan64 = helm.tune_batched(k, "fp64")
     helm.set_param("use_graph", 1)
     helm.set_param("replace_drop", 1e-3)
 
@@ -412,8 +413,10 @@ def bench_batched(torch, log, reps=3):
         "iterations_max": max(i.iterations for i in ib),
         "relres_max": max(i.relres_true for i in ib),
         "max_rel_diff_vs_sequential_fp64": diff,
-        "tile": {"columns_per_thread": best, "tuned_us": {str(w): round(t, 2)
-                                                          for w, t in times.items()}},
+        "plan": {"mixed": {"columns_per_thread": plan & 7, "tiled_shape": plan >> 3,
+                           "tuned_us": {w: round(t, 2) for w, t in times.items()}},
+                 "fp64": {"columns_per_thread": plan64 & 7, "tiled_shape": plan64 >> 3,
+                          "tuned_us": {w: round(t, 2) for w, t in times64.items()}}},
         "graph": True,
     }
     log(f"batched: {out}")

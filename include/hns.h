@@ -278,14 +278,27 @@ hns_status hns_batch_poll(hns_batch *bt, int *states, hns_solve_info *infos, voi
 hns_status hns_batch_take(hns_batch *bt, int slot, double *x_dev, hns_solve_info *info,
                           void *stream);
 
-/* Time the multi-right-hand-side product kernel of `hns_solve_batched` for
- * k columns in `mode` with 1, 2 and 4 consecutive columns per thread, on this
- * operator; times_us[0..2] receive the microseconds per launch (-1 where k is
- * not a multiple of the width) and *best_vec the fastest width, which later
- * batched solves of k columns in that mode use.  hns_solve_batched runs this
- * tuning itself the first time it meets (k, mode) unless "bspmm_vec" is set. */
+/* Autotuner of the multi-right-hand-side product of `hns_solve_batched` for
+ * k columns in `mode` on this operator.  It times one launch of
+ *   - the grid-stride product with 1, 2 and 4 consecutive columns per
+ *     thread: times_us[0..2] (-1 where k is not a multiple of the width), and
+ *   - on the narrow symmetric diagonal format, the LDS-tiled product in its
+ *     three tile shapes (a block stages the rows its tile of consecutive rows
+ *     reads, for a group of columns, then reads every term from LDS; FP64:
+ *     16, 8, 16 columns by 64, 128, 32 rows, FP32: 32, 16, 16 columns by 64,
+ *     128, 64 rows): times_us[3..5] (-1 where the shape does not apply),
+ * so times_us holds 6 doubles.  *best_plan receives the plan later batched
+ * solves of k columns in that mode use: V + 8 s, V the fastest width (also
+ * the width of the vector updates) and s the tiled shape (1..3) when one is
+ * faster than that width's product, else 0.  hns_solve_batched and the
+ * shared-block sessions choose their plan the same way on first use of
+ * (k, mode), unless "bspmm_vec" is set; plans are kept per process and in a
+ * JSON file keyed by (GPU architecture, rows, nonzeros, k, precision,
+ * format): $HNS_TUNE_CACHE, else $XDG_CACHE_HOME/hns/bspmm_plans.json
+ * ($HOME/.cache when XDG_CACHE_HOME is unset); an unreadable or unwritable
+ * file only means that the tuner runs again. */
 hns_status hns_tune_batched(hns_operator *op, int k, uint32_t mode, void *stream,
-                            double *times_us, int *best_vec);
+                            double *times_us, int *best_plan);
 
 /* Device bytes a solve of k right-hand sides in `mode` needs beyond the
  * resident operator (workspace: k = 1 for hns_solve, k > 1 for
@@ -327,6 +340,11 @@ int hns_operator_line_len(const hns_operator *op);
  *                  hns_solve_batched (default 0)
  *   "bspmm_vec"    columns per thread of the batched kernels: 0 = autotune
  *                  (default), or 1, 2, 4
+ *   "bspmm_tile"   LDS-tiled batched product: -1 = the autotuner decides
+ *                  (default), 0 = never, 1..3 = that tile shape (with
+ *                  "bspmm_vec" set: always, where it applies; else the only
+ *                  shape the autotuner tries); plans found with a value
+ *                  other than -1 are not written to the plan file
  *   "spmv_it64"    launch shape of the single-vector diagonal-storage SpMV with
  *   "spmv_it32"    FP64 / FP32 vectors: workgroup-sized row passes per block
  *                  (defaults 1 and 2; integers 1..64)

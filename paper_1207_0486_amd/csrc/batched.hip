@@ -16,10 +16,18 @@
 //   pupdate   p_j = z_j + beta_j p_j (columns still active)
 // Columns stop independently; a chunk of iterations is captured once into a
 // HIP graph and replayed.
+#include <sys/stat.h>
+#include <unistd.h>
+
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <numeric>
+#include <string>
 #include <tuple>
 #include <utility>
 #include <vector>
@@ -229,6 +237,159 @@ __global__ __launch_bounds__(kBlock) void k_bspmm_sdia(int64_t n, int K, BOffset
         bst<V>(Q, e, out);
     }
     if constexpr (DOT) block_column_partials<1, V>(acc, K, part);
+}
+
+// ---------------------------------------------------------------------------
+// LDS-tiled product for the narrow symmetric-diagonal format.  A block owns
+// tiles of T consecutive rows and one group of C columns; the rows its tile
+// needs (row i reads rows i and i +- o_k) form a few clusters of nearby
+// offsets, which the block stages into LDS with coalesced 16-byte loads
+// (zeros outside [0, n)), so each value of P comes from global memory about
+// (staged rows / T) times instead of 2 M + 1 times, and every term of a row
+// then reads LDS.  Terms of a row in the order of k_bspmm_sdia: main, then
+// (upper + lower) for each offset.  Each thread owns NP packs of 16 bytes of
+// one row (PK columns each), the same columns in every tile; per-column
+// partials of p^T q are reduced over the block in row order and stored at
+// part[slot * K + column] (slot = the block's index within its column group).
+// ---------------------------------------------------------------------------
+// Workgroup b runs on XCD b mod 8 (round-robin dispatch): renumbered so that
+// each XCD takes a contiguous eighth of the tiles (its L2 then holds the rows
+// its neighbouring tiles stage again).
+__device__ __forceinline__ int tile_block(int b, int G)
+{
+    return (G >= 8 && (G & 7) == 0) ? (b & 7) * (G >> 3) + (b >> 3) : b;
+}
+
+struct TileMap {
+    int32_t nclus;                        // clusters of staged rows
+    int32_t rows;                         // staged rows in all
+    int32_t lo[2 * kMaxDiag + 1];         // cluster c: rows i0 + lo[c] .. (cnt[c] of them)
+    int32_t cnt[2 * kMaxDiag + 1];
+    int32_t base[2 * kMaxDiag + 1];       // LDS row of the cluster's first staged row
+    int32_t lrow[2 * kMaxDiag + 1];       // term t: LDS row of tile row 0 (t = 0 main,
+                                          // 2k + 1 at + off[k], 2k + 2 at - off[k])
+    int32_t off[kMaxDiag];
+};
+
+template <typename TV, typename TX, int C, int NP, int M>
+__global__ __launch_bounds__(kBlock) void k_bspmm_tile(int64_t n, int K, TileMap tm,
+                                                       const TV *__restrict__ dia,
+                                                       const TX *__restrict__ P,
+                                                       TX *__restrict__ Q,
+                                                       const uint8_t *__restrict__ bc,
+                                                       const BCol *__restrict__ cols,
+                                                       double *__restrict__ part, int64_t ntiles,
+                                                       int64_t tpb, int ngroups)
+{
+    constexpr int PK = 16 / sizeof(TX);      // columns per 16-byte pack
+    constexpr int W = PK * NP;               // columns per thread
+    constexpr int TPR = C / W;               // threads per tile row
+    constexpr int T = kBlock / TPR;          // rows per tile
+    constexpr int PPR = C / PK;              // packs per staged row
+    constexpr int U = 8;                     // staging loads in flight per thread
+    static_assert(C % W == 0 && kBlock % TPR == 0, "tile shape");
+    extern __shared__ __align__(16) unsigned char smem[];
+    TX *lds = reinterpret_cast<TX *>(smem);
+    if (!any_column(cols, K, 0)) return;
+    const int lb = tile_block(blockIdx.x, gridDim.x);
+    const int group = lb % ngroups;
+    const int64_t slot = lb / ngroups;
+    const int c0 = group * C;
+    const int tr = threadIdx.x / TPR;
+    const int tc = (threadIdx.x % TPR) * W;
+    int cbit[W];
+#pragma unroll
+    for (int v = 0; v < W; ++v) cbit[v] = cols[c0 + tc + v].bit;
+    double acc[W];
+#pragma unroll
+    for (int v = 0; v < W; ++v) acc[v] = 0.0;
+    const int64_t t0 = slot * tpb;
+    const int64_t t1 = t0 + tpb < ntiles ? t0 + tpb : ntiles;
+    const int total = tm.rows * PPR;
+    for (int64_t tile = t0; tile < t1; ++tile) {
+        const int64_t i0 = tile * T;
+        // stage the clusters' rows: U loads in flight, then their stores
+        for (int b0 = threadIdx.x; b0 < total; b0 += U * kBlock) {
+            BPack<TX, PK> v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int idx = b0 + u * kBlock;
+#pragma unroll
+                for (int e = 0; e < PK; ++e) v[u].v[e] = (TX)0;
+                if (idx < total) {
+                    const int lr = idx / PPR, pk = idx - lr * PPR;
+                    int c = 0;
+                    while (c + 1 < tm.nclus && lr >= tm.base[c + 1]) ++c;
+                    const int64_t g = i0 + tm.lo[c] + (lr - tm.base[c]);
+                    if (g >= 0 && g < n) v[u] = bld<PK>(P, g * K + c0 + pk * PK);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int idx = b0 + u * kBlock;
+                if (idx < total) bst<PK>(lds, (int64_t)idx * PK, v[u]);
+            }
+        }
+        __syncthreads();
+        const int64_t i = i0 + tr;
+        if (i < n) {
+            // the row's operator entries first (all loads in flight)
+            const uint8_t bci = bc ? bc[i] : (uint8_t)0;
+            const TX d = (TX)dia[i];
+            TX cu[M], cl[M];
+#pragma unroll
+            for (int k = 0; k < M; ++k) {
+                const int64_t o = tm.off[k];
+                const TV *u = dia + (int64_t)(k + 1) * n;
+                cu[k] = (i + o < n) ? (TX)u[i] : (TX)0;
+                cl[k] = (i >= o) ? (TX)u[i >= o ? i - o : 0] : (TX)0;
+            }
+            TX p0[W], s[W];
+#pragma unroll
+            for (int q = 0; q < NP; ++q) {
+                const auto pv = bld<PK>(lds, (int64_t)(tm.lrow[0] + tr) * C + tc + q * PK);
+#pragma unroll
+                for (int e = 0; e < PK; ++e) p0[q * PK + e] = pv.v[e];
+            }
+#pragma unroll
+            for (int v = 0; v < W; ++v) s[v] = d * p0[v];
+#pragma unroll
+            for (int k = 0; k < M; ++k) {
+                const int64_t ru = (int64_t)(tm.lrow[2 * k + 1] + tr) * C + tc;
+                const int64_t rl = (int64_t)(tm.lrow[2 * k + 2] + tr) * C + tc;
+#pragma unroll
+                for (int q = 0; q < NP; ++q) {
+                    const auto pu = bld<PK>(lds, ru + q * PK);
+                    const auto pl = bld<PK>(lds, rl + q * PK);
+#pragma unroll
+                    for (int e = 0; e < PK; ++e)
+                        s[q * PK + e] += cu[k] * pu.v[e] + cl[k] * pl.v[e];
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < NP; ++q) {
+                BPack<TX, PK> out;
+#pragma unroll
+                for (int e = 0; e < PK; ++e) {
+                    const int v = q * PK + e;
+                    out.v[e] = masked_byte(bci, cbit[v]) ? (TX)0 : s[v];
+                    acc[v] += (double)p0[v] * (double)out.v[e];
+                }
+                bst<PK>(Q, i * K + c0 + tc + q * PK, out);
+            }
+        }
+        __syncthreads();
+    }
+    // per-column partials over the block's T rows, in row order
+    double *red = reinterpret_cast<double *>(smem);   // T x C doubles (fits the staging area)
+#pragma unroll
+    for (int v = 0; v < W; ++v) red[tr * C + tc + v] = acc[v];
+    __syncthreads();
+    for (int c = threadIdx.x; c < C; c += kBlock) {
+        double sum = 0.0;
+        for (int r = 0; r < T; ++r) sum += red[r * C + c];
+        part[slot * K + c0 + c] = sum;
+    }
 }
 
 // The same product for the wide symmetric-diagonal format: the offsets are a
@@ -907,7 +1068,18 @@ struct BCtx {
     double *X;
     hipStream_t s;
     bool mixed;
+    int tile = 0;    // tiled product shape (0: the grid-stride product of width V)
 };
+
+// A product plan as the autotuner records it: plan = V + 8 s, V the width of
+// the grid-stride kernels (1, 2, 4), s the tiled product shape (0: none).
+BCtx bctx(hns_operator *op, BWorkspace *w, int K, int plan, const double *B, double *X,
+          hipStream_t s, bool mixed)
+{
+    BCtx c{op, w, K, plan & 7, B, X, s, mixed};
+    c.tile = plan >> 3;
+    return c;
+}
 
 hns_status pull(BCtx &c)
 {
@@ -935,6 +1107,13 @@ struct Launcher {
     template <typename... KArgs, typename... A>
     void operator()(void (*k)(KArgs...), int grid, int block, A... a)
     {
+        with_lds(0, k, grid, block, a...);
+    }
+
+    // the same with `shm` bytes of dynamic LDS
+    template <typename... KArgs, typename... A>
+    void with_lds(size_t shm, void (*k)(KArgs...), int grid, int block, A... a)
+    {
         if (err != hipSuccess) return;
         std::tuple<KArgs...> t(a...);
         void *params[sizeof...(KArgs)];
@@ -944,14 +1123,14 @@ struct Launcher {
             p.func = (void *)k;
             p.gridDim = dim3(grid);
             p.blockDim = dim3(block);
-            p.sharedMemBytes = 0;
+            p.sharedMemBytes = (unsigned int)shm;
             p.kernelParams = params;
             p.extra = nullptr;
             hipGraphNode_t node = nullptr;
             err = hipGraphAddKernelNode(&node, g, last ? &last : nullptr, last ? 1 : 0, &p);
             last = node;
         } else {
-            err = hipLaunchKernel((const void *)k, dim3(grid), dim3(block), params, 0, s);
+            err = hipLaunchKernel((const void *)k, dim3(grid), dim3(block), params, shm, s);
         }
     }
 
@@ -998,6 +1177,134 @@ void bspmm_launch(Launcher &L, const DevMatrix &A, int K, const TV *vals, const 
     }
 }
 
+// Tile shapes of k_bspmm_tile, (columns per tile, 16-byte packs per thread),
+// per precision; rows per tile T = 256 * 16 / (C * sizeof) * NP ... see
+// tile_rows.  Index 1.. of a shape is the `tile` choice of the autotuner (0:
+// the grid-stride product).
+struct TileShape {
+    int C, NP;
+};
+constexpr int kTileShapes = kTileShapesAbi;
+constexpr TileShape kTileShapes64[kTileShapes] = {{16, 2}, {8, 2}, {16, 1}};   // T = 64, 128, 32
+constexpr TileShape kTileShapes32[kTileShapes] = {{32, 2}, {16, 2}, {16, 1}};  // T = 64, 128, 64
+constexpr size_t kTileLds = 65536;   // bytes of LDS a tile may stage
+
+int tile_rows(int C, int NP, size_t tx)
+{
+    const int W = (int)(16 / tx) * NP;
+    return kBlock / (C / W);
+}
+
+// Staging plan of a tile of T rows: the distinct offsets 0, +-off[k], merged
+// into clusters wherever the gap between neighbours is below T (a cluster
+// [lo, hi] stages T + hi - lo rows).
+void tile_plan(const DevMatrix &A, int T, TileMap *tm)
+{
+    std::vector<int> o = {0};
+    for (int k = 0; k < A.ndiag; ++k) {
+        o.push_back(A.off[k]);
+        o.push_back(-A.off[k]);
+    }
+    std::sort(o.begin(), o.end());
+    o.erase(std::unique(o.begin(), o.end()), o.end());
+    memset(tm, 0, sizeof(*tm));
+    std::vector<int> lo, hi;
+    for (int v : o) {
+        if (!lo.empty() && v - hi.back() < T)
+            hi.back() = v;
+        else {
+            lo.push_back(v);
+            hi.push_back(v);
+        }
+    }
+    tm->nclus = (int)lo.size();
+    int rows = 0;
+    for (int c = 0; c < tm->nclus; ++c) {
+        tm->lo[c] = lo[c];
+        tm->cnt[c] = T + hi[c] - lo[c];
+        tm->base[c] = rows;
+        rows += tm->cnt[c];
+    }
+    tm->rows = rows;
+    auto lrow = [&](int off) {
+        for (int c = 0; c < tm->nclus; ++c)
+            if (off >= lo[c] && off <= hi[c]) return tm->base[c] + (off - lo[c]);
+        return 0;
+    };
+    tm->lrow[0] = lrow(0);
+    for (int k = 0; k < A.ndiag; ++k) {
+        tm->off[k] = A.off[k];
+        tm->lrow[2 * k + 1] = lrow(A.off[k]);
+        tm->lrow[2 * k + 2] = lrow(-A.off[k]);
+    }
+}
+
+// Dynamic LDS bytes of tile shape `shape` (1-based) for K columns, or 0 when
+// the shape does not apply (format, K not a multiple of C, too much LDS).
+template <typename TX>
+size_t tile_lds(const DevMatrix &A, int K, int shape)
+{
+    // the shapes are compiled for the 15-point P1 (7 upper diagonals) and the
+    // 27-point Q1 (13) stencils
+    if (shape < 1 || shape > kTileShapes || A.fmt != HNS_FMT_SDIA || A.unit ||
+        (A.ndiag != 7 && A.ndiag != 13))
+        return 0;
+    const TileShape ts = sizeof(TX) == 8 ? kTileShapes64[shape - 1] : kTileShapes32[shape - 1];
+    if (K % ts.C) return 0;
+    const int T = tile_rows(ts.C, ts.NP, sizeof(TX));
+    TileMap tm;
+    tile_plan(A, T, &tm);
+    const size_t b = std::max((size_t)tm.rows * ts.C * sizeof(TX), (size_t)T * ts.C * 8);
+    return b <= kTileLds ? b : 0;
+}
+
+template <typename TX, int C, int NP>
+int tile_launch_shape(Launcher &L, const DevMatrix &A, int K, const TX *vals, const void *P,
+                      void *Q, const uint8_t *bc, const BCol *cols, double *part, size_t shm)
+{
+    if (A.ndiag != 7 && A.ndiag != 13) return -1;
+    const int T = tile_rows(C, NP, sizeof(TX));
+    TileMap tm;
+    tile_plan(A, T, &tm);
+    const int ngroups = K / C;
+    const int64_t ntiles = (A.n + T - 1) / T;
+    int64_t Gt = std::min<int64_t>(ntiles, kMaxGrid);
+    // a whole number of XCDs' worth of blocks in all (the XCD renumbering)
+    while (Gt > 1 && (Gt * ngroups) % 8) --Gt;
+    const int64_t tpb = (ntiles + Gt - 1) / Gt;
+    if (A.ndiag == 7)
+        L.with_lds(shm, k_bspmm_tile<TX, TX, C, NP, 7>, (int)(Gt * ngroups), kBlock, A.n, K, tm,
+                   vals, (const TX *)P, (TX *)Q, bc, cols, part, ntiles, tpb, ngroups);
+    else
+        L.with_lds(shm, k_bspmm_tile<TX, TX, C, NP, 13>, (int)(Gt * ngroups), kBlock, A.n, K,
+                   tm, vals, (const TX *)P, (TX *)Q, bc, cols, part, ntiles, tpb, ngroups);
+    return (int)Gt;
+}
+
+// Tiled product of shape `shape` (1-based); returns the number of partial
+// slots per column it wrote (the G of k_bred_gamma), -1 if not applicable.
+template <typename TX>
+int bspmm_tile_launch(Launcher &L, const DevMatrix &A, int K, int shape, const TX *vals,
+                      const void *P, void *Q, const uint8_t *bc, const BCol *cols, double *part)
+{
+    const size_t shm = tile_lds<TX>(A, K, shape);
+    if (!shm) return -1;
+    if constexpr (sizeof(TX) == 8) {
+        switch (shape) {
+        case 1: return tile_launch_shape<TX, 16, 2>(L, A, K, vals, P, Q, bc, cols, part, shm);
+        case 2: return tile_launch_shape<TX, 8, 2>(L, A, K, vals, P, Q, bc, cols, part, shm);
+        case 3: return tile_launch_shape<TX, 16, 1>(L, A, K, vals, P, Q, bc, cols, part, shm);
+        }
+    } else {
+        switch (shape) {
+        case 1: return tile_launch_shape<TX, 32, 2>(L, A, K, vals, P, Q, bc, cols, part, shm);
+        case 2: return tile_launch_shape<TX, 16, 2>(L, A, K, vals, P, Q, bc, cols, part, shm);
+        case 3: return tile_launch_shape<TX, 16, 1>(L, A, K, vals, P, Q, bc, cols, part, shm);
+        }
+    }
+    return -1;
+}
+
 template <typename T>
 const T *values_of(const DevMatrix &A)
 {
@@ -1038,8 +1345,15 @@ void iteration_v(BCtx &c, Launcher &L, TX *X, TX *R, TX *P, TX *Q, const TD *din
     double *part = c.w->part;
     BCol *cols = c.w->cols;
     using TV = TX;
-    bspmm_launch<TV, TX, V, true>(L, A, c.K, values_of<TV>(A), P, Q, c.op->bc, cols, part, G);
-    L(k_bred_gamma, c.K, kBlock, c.K, (const double *)part, G, cols);
+    int Gp = -1;
+    if (c.tile > 0)
+        Gp = bspmm_tile_launch<TX>(L, A, c.K, c.tile, values_of<TX>(A), P, Q, c.op->bc, cols,
+                                   part);
+    if (Gp < 0) {
+        bspmm_launch<TV, TX, V, true>(L, A, c.K, values_of<TV>(A), P, Q, c.op->bc, cols, part, G);
+        Gp = G;
+    }
+    L(k_bred_gamma, c.K, kBlock, c.K, (const double *)part, Gp, cols);
     L(k_bupdate<TX, TD, V>, G, kBlock, A.n, c.K, X, R, (const TX *)P, (const TX *)Q, dinv,
       (const BCol *)cols, part);
     L(k_bred_rho, c.K, kBlock, c.K, (const double *)part, G, cols);
@@ -1080,7 +1394,8 @@ hns_status run_chunk(BCtx &c, int count)
         Launcher L{c.s};
         return enqueue_chunk(c, L, count);
     }
-    if (!w->graph || w->graph_chunk != count || w->graph_V != c.V || w->graph_X != c.X ||
+    const int plan = c.V + 8 * c.tile;
+    if (!w->graph || w->graph_chunk != count || w->graph_V != plan || w->graph_X != c.X ||
         w->graph_mixed != (int)c.mixed) {
         w->drop_graph();
         hipGraph_t g = nullptr;
@@ -1100,7 +1415,7 @@ hns_status run_chunk(BCtx &c, int count)
             return HNS_ERR_HIP;
         }
         w->graph_chunk = count;
-        w->graph_V = c.V;
+        w->graph_V = plan;
         w->graph_X = c.X;
         w->graph_mixed = (int)c.mixed;
     }
@@ -1148,7 +1463,7 @@ hns_status solve_batched_impl(hns_operator *op, BWorkspace *w, int K, const int 
                               const double *B, double *X, double tol, int max_iter, bool mixed,
                               int V, hipStream_t s, hns_solve_info *infos)
 {
-    BCtx c{op, w, K, V, B, X, s, mixed};
+    BCtx c = bctx(op, w, K, V, B, X, s, mixed);
     const int64_t n = op->n;
     const int64_t ne = n * (int64_t)K;
     const double drop2 = mixed ? op->replace_drop * op->replace_drop : 0.0;
@@ -1261,11 +1576,13 @@ hns_status solve_batched_impl(hns_operator *op, BWorkspace *w, int K, const int 
     return worst;
 }
 
-// Time one DOT SpMM of each pack width on this workspace; returns the best V
+// Time one DOT product of each pack width (1, 2, 4) and of each tiled shape
+// that applies, on this workspace; times_us[0..2] the widths, [3..] the tiled
+// shapes (-1 where not applicable); *best_plan = V + 8 s: V the fastest
+// width (the iteration kernels' width), s the tiled shape if one beats it.
 hns_status tune_batched(hns_operator *op, BWorkspace *w, int K, bool mixed, hipStream_t s,
-                        double *times_us, int *best_V)
+                        double *times_us, int *best_plan)
 {
-    BCtx c{op, w, K, 1, nullptr, nullptr, s, mixed};
     const int widths[3] = {1, 2, 4};
     hipEvent_t e0, e1;
     HNS_TRY_HIP(hipEventCreate(&e0));
@@ -1279,14 +1596,28 @@ hns_status tune_batched(hns_operator *op, BWorkspace *w, int K, bool mixed, hipS
     const DevMatrix &A = op->A;
     const int64_t ne = A.n * (int64_t)K;
     double best = 1e300;
-    *best_V = 1;
+    int best_V = 1, best_tile = 0;
+    auto time_it = [&](auto &&launch, double *out) -> hns_status {
+        Launcher L{s};
+        launch(L);
+        HNS_TRY(L.status("tune"));
+        const int reps = 10;
+        HNS_TRY_HIP(hipEventRecord(e0, s));
+        for (int r = 0; r < reps; ++r) launch(L);
+        HNS_TRY_HIP(hipEventRecord(e1, s));
+        HNS_TRY_HIP(hipEventSynchronize(e1));
+        HNS_TRY(L.status("tune"));
+        float ms = 0.0f;
+        HNS_TRY_HIP(hipEventElapsedTime(&ms, e0, e1));
+        *out = 1e3 * ms / reps;
+        return HNS_OK;
+    };
     for (int q = 0; q < 3; ++q) {
         const int V = widths[q];
         times_us[q] = -1.0;
         if (K % V) continue;
         const int G = bgrid(ne / V, K, V);
-        Launcher L{s};
-        auto launch = [&]() {
+        auto launch = [&](Launcher &L) {
             if (mixed) {
                 if (V == 1)
                     bspmm_launch<float, float, 1, true>(L, A, K, values_of<float>(A), w->P32,
@@ -1312,24 +1643,164 @@ hns_status tune_batched(hns_operator *op, BWorkspace *w, int K, bool mixed, hipS
                                                           w->part, G);
             }
         };
-        launch();
-        HNS_TRY(L.status("tune"));
-        const int reps = 10;
-        HNS_TRY_HIP(hipEventRecord(e0, s));
-        for (int r = 0; r < reps; ++r) launch();
-        HNS_TRY_HIP(hipEventRecord(e1, s));
-        HNS_TRY_HIP(hipEventSynchronize(e1));
-        float ms = 0.0f;
-        HNS_TRY_HIP(hipEventElapsedTime(&ms, e0, e1));
-        times_us[q] = 1e3 * ms / reps;
+        HNS_TRY(time_it(launch, &times_us[q]));
         if (times_us[q] < best) {
             best = times_us[q];
-            *best_V = V;
+            best_V = V;
         }
     }
+    const double best_stride = best;
+    for (int sh = 1; sh <= kTileShapes; ++sh) {
+        times_us[2 + sh] = -1.0;
+        if (op->bspmm_tile == 0 || (op->bspmm_tile > 0 && op->bspmm_tile != sh)) continue;
+        const bool ok = mixed ? tile_lds<float>(A, K, sh) > 0 : tile_lds<double>(A, K, sh) > 0;
+        if (!ok) continue;
+        auto launch = [&](Launcher &L) {
+            if (mixed)
+                bspmm_tile_launch<float>(L, A, K, sh, values_of<float>(A), w->P32, w->Q32,
+                                         nullptr, w->cols, w->part);
+            else
+                bspmm_tile_launch<double>(L, A, K, sh, values_of<double>(A), w->P64, w->Q64,
+                                          nullptr, w->cols, w->part);
+        };
+        HNS_TRY(time_it(launch, &times_us[2 + sh]));
+        if (times_us[2 + sh] < best) {
+            best = times_us[2 + sh];
+            best_tile = sh;
+        }
+    }
+    (void)best_stride;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    (void)c;
+    *best_plan = best_V + 8 * best_tile;
+    return HNS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Product plans kept across processes: a small JSON object keyed by
+// "arch|n|nnz|k|precision|format", in $HNS_TUNE_CACHE or else
+// $XDG_CACHE_HOME/hns/bspmm_plans.json ($HOME/.cache when unset).  Unreadable
+// or unwritable files are ignored (the autotuner then runs again).
+// ---------------------------------------------------------------------------
+namespace {
+
+std::mutex g_plan_mutex;
+
+std::string plan_cache_path()
+{
+    const char *e = getenv("HNS_TUNE_CACHE");
+    if (e && *e) return e;
+    const char *x = getenv("XDG_CACHE_HOME");
+    const char *h = getenv("HOME");
+    std::string dir = (x && *x) ? std::string(x) : (h && *h) ? std::string(h) + "/.cache" : "";
+    return dir.empty() ? std::string() : dir + "/hns/bspmm_plans.json";
+}
+
+std::map<std::string, int> plan_cache_read(const std::string &path)
+{
+    std::map<std::string, int> m;
+    FILE *f = path.empty() ? nullptr : fopen(path.c_str(), "r");
+    if (!f) return m;
+    char line[512];
+    while (fgets(line, sizeof(line), f)) {
+        const char *a = strchr(line, '"');
+        const char *b = a ? strchr(a + 1, '"') : nullptr;
+        const char *c = b ? strchr(b + 1, ':') : nullptr;
+        if (!c) continue;
+        int v = 0;
+        if (sscanf(c + 1, "%d", &v) == 1) m[std::string(a + 1, b)] = v;
+    }
+    fclose(f);
+    return m;
+}
+
+}  // namespace
+
+std::string plan_key(const hns_operator *op, int K, bool mixed)
+{
+    int dev = 0;
+    hipDeviceProp_t p{};
+    std::string arch = "gpu";
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&p, dev) == hipSuccess) {
+        arch = p.gcnArchName;
+        const size_t colon = arch.find(':');
+        if (colon != std::string::npos) arch.resize(colon);
+    }
+    const char *fmt = op->A.fmt == HNS_FMT_SDIA ? "sdia" : op->A.fmt == HNS_FMT_SELL ? "sell"
+                                                                                     : "csr";
+    char buf[256];
+    snprintf(buf, sizeof(buf), "%s|%lld|%lld|%d|%s|%s", arch.c_str(), (long long)op->n,
+             (long long)op->A.nnz, K, mixed ? "fp32" : "fp64", fmt);
+    return buf;
+}
+
+bool plan_cache_get(const std::string &key, int *plan)
+{
+    std::lock_guard<std::mutex> g(g_plan_mutex);
+    const auto m = plan_cache_read(plan_cache_path());
+    const auto it = m.find(key);
+    if (it == m.end()) return false;
+    *plan = it->second;
+    return true;
+}
+
+void plan_cache_put(const std::string &key, int plan)
+{
+    std::lock_guard<std::mutex> g(g_plan_mutex);
+    const std::string path = plan_cache_path();
+    if (path.empty()) return;
+    auto m = plan_cache_read(path);
+    m[key] = plan;
+    const size_t slash = path.rfind('/');
+    if (slash != std::string::npos) {
+        std::string dir = path.substr(0, slash);
+        for (size_t i = 1; i <= dir.size(); ++i)
+            if (i == dir.size() || dir[i] == '/') (void)mkdir(dir.substr(0, i).c_str(), 0755);
+    }
+    const std::string tmp = path + ".tmp" + std::to_string((long long)getpid());
+    FILE *f = fopen(tmp.c_str(), "w");
+    if (!f) return;
+    fputs("{\n", f);
+    size_t i = 0;
+    for (const auto &kv : m)
+        fprintf(f, "  \"%s\": %d%s\n", kv.first.c_str(), kv.second, ++i < m.size() ? "," : "");
+    fputs("}\n", f);
+    const bool ok = fclose(f) == 0;
+    if (ok)
+        (void)rename(tmp.c_str(), path.c_str());
+    else
+        (void)remove(tmp.c_str());
+}
+
+// Product plan of the batched iteration for (k, mode): the tunables when
+// set, else the plan tuned earlier in this process, else the one kept in the
+// plan cache for this (arch, n, nnz, k, precision, format), else the
+// autotuner's (recorded in both).
+hns_status batched_plan(hns_operator *op, BWorkspace *w, int k, bool mixed, hipStream_t s,
+                        int *plan)
+{
+    if (op->bspmm_vec > 0) {
+        const int V = (k % op->bspmm_vec == 0) ? op->bspmm_vec : 1;
+        *plan = V + 8 * (op->bspmm_tile > 0 ? op->bspmm_tile : 0);
+        return HNS_OK;
+    }
+    {
+        std::lock_guard<std::mutex> g(op->ws_mutex);
+        for (const auto &t : op->tuned)
+            if (t[0] == k && t[1] == (int)mixed) {
+                *plan = t[2];
+                return HNS_OK;
+            }
+    }
+    const std::string key = plan_key(op, k, mixed);
+    const bool cacheable = op->bspmm_tile < 0;   // the default search only
+    if (!(cacheable && plan_cache_get(key, plan))) {
+        double times[3 + kTileShapesAbi];
+        HNS_TRY(tune_batched(op, w, k, mixed, s, times, plan));
+        if (cacheable) plan_cache_put(key, *plan);
+    }
+    std::lock_guard<std::mutex> g(op->ws_mutex);
+    op->tuned.push_back({k, (int)mixed, *plan});
     return HNS_OK;
 }
 
@@ -1381,7 +1852,7 @@ hns_status session_service(hns_batch *bt, hipStream_t s)
     BWorkspace *w = bt->w;
     const int K = bt->K;
     const int64_t n = bt->op->n;
-    BCtx c{bt->op, w, K, bt->V, bt->B, bt->X, s, bt->mixed};
+    BCtx c = bctx(bt->op, w, K, bt->V, bt->B, bt->X, s, bt->mixed);
     const double drop2 = bt->mixed ? bt->op->replace_drop * bt->op->replace_drop : 0.0;
     const int G1 = bgrid(n * (int64_t)K, K, 1);
     for (int round = 0; round < 4; ++round) {
@@ -1487,12 +1958,7 @@ hns_status hns_batch_open(hns_operator *op, int capacity, uint32_t mode, hns_bat
         }
     }
     if (st == HNS_OK) {
-        if (op->bspmm_vec > 0) {
-            bt->V = (capacity % op->bspmm_vec == 0) ? op->bspmm_vec : 1;
-        } else {
-            double t[3];
-            st = tune_batched(op, bt->w, capacity, bt->mixed, nullptr, t, &bt->V);
-        }
+        st = batched_plan(op, bt->w, capacity, bt->mixed, nullptr, &bt->V);
     }
     if (st == HNS_OK) {
         for (int j = 0; j < capacity; ++j) {
@@ -1596,7 +2062,7 @@ hns_status hns_batch_add(hns_batch *bt, int count, const int *slots, const int *
         HNS_TRY_HIP(hipMemcpyAsync(bt->slot_buf, ok.data(), ok.size() * sizeof(int32_t),
                                    hipMemcpyHostToDevice, s));
         k_bmark_list<<<1, kBlock, 0, s>>>(K, w->cols, bt->slot_buf, (int)ok.size());
-        BCtx c{op, w, K, bt->V, bt->B, bt->X, s, bt->mixed};
+        BCtx c = bctx(op, w, K, bt->V, bt->B, bt->X, s, bt->mixed);
         const double drop2 = bt->mixed ? op->replace_drop * op->replace_drop : 0.0;
         HNS_TRY(true_residual(c, drop2, 1));
         HNS_TRY(new_segment(c));
@@ -1614,7 +2080,7 @@ hns_status hns_batch_advance(hns_batch *bt, int iterations, void *stream, int *a
     }
     hipStream_t s = (hipStream_t)stream;
     if (bt->ss) return slot_session_advance(bt->ss, iterations, s, active_out);
-    BCtx c{bt->op, bt->w, bt->K, bt->V, bt->B, bt->X, s, bt->mixed};
+    BCtx c = bctx(bt->op, bt->w, bt->K, bt->V, bt->B, bt->X, s, bt->mixed);
     HNS_TRY(session_pull(bt, s));
     int done = 0, active = 0;
     for (;;) {

@@ -171,6 +171,7 @@ struct hns_operator {
     std::vector<hns::Workspace *> ws_free;
     std::vector<hns::BWorkspace *> bws_free;
     int bspmm_vec = 0;                     // 0: autotune per (k, mode); else 1, 2 or 4
+    int bspmm_tile = -1;                   // tiled product: -1 autotune, 0 never, 1..3 shape
     std::vector<std::array<int, 3>> tuned; // (k, mixed, V) chosen by the autotuner
     // vertical-line preconditioner: the rows form water columns of line_len
     // consecutive nodes (0 when the numbering has none).  Host copies of the
@@ -231,8 +232,20 @@ bool bworkspace_mixed(const BWorkspace *w);
 hns_status solve_batched_impl(hns_operator *op, BWorkspace *w, int K, const int *bits,
                               const double *B, double *X, double tol, int max_iter, bool mixed,
                               int V, hipStream_t s, hns_solve_info *infos);
+// Product plan of the multi-right-hand-side solves: plan = V + 8 s, V the
+// width (1, 2, 4) of the grid-stride iteration kernels, s the LDS-tiled
+// product shape (0: none, 1..kTileShapesAbi).  tune_batched times the widths
+// into times_us[0..2] and the tiled shapes into times_us[3..] (-1 where one
+// does not apply) and returns the fastest plan; plan_cache_get/put read and
+// write the plans kept across processes under plan_key(op, K, mixed).
+constexpr int kTileShapesAbi = 3;
 hns_status tune_batched(hns_operator *op, BWorkspace *w, int K, bool mixed, hipStream_t s,
-                        double *times_us, int *best_V);
+                        double *times_us, int *best_plan);
+std::string plan_key(const hns_operator *op, int K, bool mixed);
+bool plan_cache_get(const std::string &key, int *plan);
+void plan_cache_put(const std::string &key, int plan);
+hns_status batched_plan(hns_operator *op, BWorkspace *w, int k, bool mixed, hipStream_t s,
+                        int *plan);
 
 // assemble.cpp
 // values_on_device: the pattern is built here, the values (and the element

@@ -1358,6 +1358,11 @@ hns_status hns_set_param(hns_operator *op, const char *name, double value)
         op->replace_drop = value;
     } else if (k == "bspmm_vec" && (value == 0 || value == 1 || value == 2 || value == 4)) {
         op->bspmm_vec = (int)value;
+        op->tuned.clear();
+    } else if (k == "bspmm_tile" && value >= -1 && value <= kTileShapesAbi &&
+               value == (int)value) {
+        op->bspmm_tile = (int)value;
+        op->tuned.clear();
     } else if (k == "use_graph" && (value == 0 || value == 1)) {
         op->use_graph = (int)value;
     } else if (k == "spmv_it64" && value >= 1 && value <= 64 && value == (int)value) {
@@ -1841,25 +1846,6 @@ static hns_status check_batched_args(hns_operator *op, int k, const int *bits, c
     return check_solve_args(op, -1, B, X, tol, max_iter, mode);
 }
 
-// pack width of the batched iteration kernels for (k, mode)
-static hns_status batched_vec(hns_operator *op, BWorkspace *w, int k, bool mixed, hipStream_t s,
-                              int *V)
-{
-    if (op->bspmm_vec > 0) {
-        *V = (k % op->bspmm_vec == 0) ? op->bspmm_vec : 1;
-        return HNS_OK;
-    }
-    for (const auto &t : op->tuned)
-        if (t[0] == k && t[1] == (int)mixed) {
-            *V = t[2];
-            return HNS_OK;
-        }
-    double times[3];
-    HNS_TRY(tune_batched(op, w, k, mixed, s, times, V));
-    op->tuned.push_back({k, (int)mixed, *V});
-    return HNS_OK;
-}
-
 hns_status hns_solve_batched(hns_operator *op, int k, const int *mask_bits, const double *B_dev,
                              double *X_dev, double tol, int max_iter, uint32_t mode, void *stream,
                              hns_solve_info *infos)
@@ -1885,7 +1871,7 @@ hns_status hns_solve_batched(hns_operator *op, int k, const int *mask_bits, cons
     BWorkspace *w = nullptr;
     HNS_TRY(acquire_bws(op, k, mixed, &w));
     int V = 1;
-    hns_status st = batched_vec(op, w, k, mixed, s, &V);
+    hns_status st = batched_plan(op, w, k, mixed, s, &V);
     if (st == HNS_OK)
         st = solve_batched_impl(op, w, k, mask_bits, B_dev, X_dev, tol, max_iter, mixed, V, s,
                                 infos);
@@ -1894,9 +1880,9 @@ hns_status hns_solve_batched(hns_operator *op, int k, const int *mask_bits, cons
 }
 
 hns_status hns_tune_batched(hns_operator *op, int k, uint32_t mode, void *stream,
-                            double *times_us, int *best_vec)
+                            double *times_us, int *best_plan)
 {
-    if (!op || !times_us || !best_vec || k < 1 || k > 1024 ||
+    if (!op || !times_us || !best_plan || k < 1 || k > 1024 ||
         (mode != HNS_FP64 && mode != HNS_MIXED) || (mode == HNS_MIXED && !op->dinv32)) {
         set_error("hns_tune_batched: bad arguments");
         return HNS_ERR_INVALID;
@@ -1904,16 +1890,18 @@ hns_status hns_tune_batched(hns_operator *op, int k, uint32_t mode, void *stream
     const bool mixed = (mode == HNS_MIXED);
     BWorkspace *w = nullptr;
     HNS_TRY(acquire_bws(op, k, mixed, &w));
-    hns_status st = tune_batched(op, w, k, mixed, (hipStream_t)stream, times_us, best_vec);
+    hns_status st = tune_batched(op, w, k, mixed, (hipStream_t)stream, times_us, best_plan);
     release_bws(op, w);
     if (st == HNS_OK) {
+        if (op->bspmm_tile < 0) plan_cache_put(plan_key(op, k, mixed), *best_plan);
+        std::lock_guard<std::mutex> g(op->ws_mutex);
         bool found = false;
         for (auto &t : op->tuned)
             if (t[0] == k && t[1] == (int)mixed) {
-                t[2] = *best_vec;
+                t[2] = *best_plan;
                 found = true;
             }
-        if (!found) op->tuned.push_back({k, (int)mixed, *best_vec});
+        if (!found) op->tuned.push_back({k, (int)mixed, *best_plan});
     }
     return st;
 }

@@ -330,16 +330,19 @@ class Operator:
         return int(L.lib().hns_noalloc_scratch_bytes())
 
     def tune_batched(self, k: int, mode: str = "fp64", stream=None):
-        """Time the batched product for k columns at 1/2/4 columns per thread;
-        returns ({width: microseconds}, best width)."""
-        times = (C.c_double * 3)()
+        """Time the batched product for k columns: the grid-stride product at
+        1/2/4 columns per thread and the LDS-tiled product in its shapes 1..3;
+        returns ({"w1"/"w2"/"w4"/"tile1".."tile3": microseconds}, plan) with
+        plan = width + 8 * tiled shape (0: none)."""
+        times = (C.c_double * 6)()
         best = C.c_int()
         with torch.cuda.device(self.device):
             st = L.lib().hns_tune_batched(self._h, k, MODES[mode], _stream_handle(stream), times,
                                           C.byref(best))
         if st != L.HNS_OK:
             raise HNSError(st, "hns_tune_batched")
-        return {w: times[i] for i, w in enumerate((1, 2, 4)) if times[i] >= 0}, best.value
+        names = ("w1", "w2", "w4", "tile1", "tile2", "tile3")
+        return {nm: times[i] for i, nm in enumerate(names) if times[i] >= 0}, best.value
 
     def solve_batched(self, B: torch.Tensor, X: torch.Tensor | None = None, mask_bits=None,
                       tol: float = 1e-10, max_iter: int = 100000, mode: str = "fp64",

@@ -170,9 +170,14 @@ def test_odd_column_counts_and_tuner(mesh, k):
     bits = [j % 3 for j in range(k)]
     B = _rhs_block(m, bits, 800)
     op = Operator(m, 1e3, 1e-2, 3600.0, kind="helmholtz", keep_fp32=True)
-    times, best = op.tune_batched(k, "mixed")
-    assert best in times and all(t > 0 for t in times.values())
-    assert 1 in times and (2 in times) == (k % 2 == 0) and (4 in times) == (k % 4 == 0)
+    times, plan = op.tune_batched(k, "mixed")
+    V, tile = plan & 7, plan >> 3
+    assert f"w{V}" in times and all(t > 0 for t in times.values())
+    assert "w1" in times and ("w2" in times) == (k % 2 == 0) and ("w4" in times) == (k % 4 == 0)
+    # FP32 tiles: shapes of 32, 16 and 16 columns
+    assert ("tile1" in times) == (k % 32 == 0) and ("tile3" in times) == (k % 16 == 0)
+    assert tile == 0 or (f"tile{tile}" in times
+                         and times[f"tile{tile}"] == min(times.values()))
     X, infos = op.solve_batched(_t(B), mask_bits=bits, tol=1e-10, mode="mixed")
     A = oracle.helmholtz(m, 1e3, 1e-2, 3600.0)
     for j in (0, k - 1):
@@ -237,3 +242,58 @@ def test_graph_capture_while_other_threads_allocate(mesh):
     finally:
         stop.set()
         th.join()
+
+
+@pytest.mark.parametrize("tile", [1, 2, 3])
+@pytest.mark.parametrize("mode", ["fp64", "mixed"])
+def test_tiled_product_columns_match_oracle(mesh, tile, mode):
+    """The LDS-tiled product (each tile shape; 32 columns, 3,675 rows: a
+    ragged last tile) in the whole batched solve: FP64 columns equal the
+    oracle's iterate after as many iterations and the grid-stride product's
+    answer; mixed columns meet the tolerance by the oracle's residual and
+    agree with the grid-stride mixed solve."""
+    from paper_1207_0486_amd.hns import Operator
+    m = mesh
+    bits = [j % 3 for j in range(32)]
+    B = _t(_rhs_block(m, bits, 1000))
+    op = Operator(m, 1e3, 1e-2, 3600.0, kind="helmholtz", keep_fp32=True)
+    op.set_param("bspmm_vec", 4)
+    op.set_param("bspmm_tile", 0)
+    X0, i0 = op.solve_batched(B, mask_bits=bits, tol=1e-10, mode=mode)
+    op.set_param("bspmm_tile", tile)
+    X1, i1 = op.solve_batched(B, mask_bits=bits, tol=1e-10, mode=mode)
+    A = oracle.helmholtz(m, 1e3, 1e-2, 3600.0)
+    X0h, X1h, Bh = X0.cpu().numpy(), X1.cpu().numpy(), B.cpu().numpy()
+    for j, bit in enumerate(bits):
+        d = ((m.bc >> bit) & 1) == 1
+        assert i1[j].status == 0
+        assert oracle.relres(A, Bh[:, j], X1h[:, j], d) <= 1.01e-10
+        assert np.all(X1h[d, j] == 0)
+        assert _rel(X1h[:, j], X0h[:, j]) <= 1e-10
+        if mode == "fp64" and j in (0, 13, 31):
+            same = oracle.pcg(A, Bh[:, j], dirichlet=d, tol=1e-300, maxit=i1[j].iterations)
+            assert _rel(X1h[:, j], same.x) <= 1e-10
+
+
+def test_tiled_product_neumann_columns(mesh):
+    """Pure-Neumann columns through the tiled product (Poisson operator, 16
+    columns, FP32 shape 3 and FP64 shape 1)."""
+    from paper_1207_0486_amd.hns import Operator
+    m = mesh
+    bits = [-1] * 16
+    B = _t(_rhs_block(m, bits, 1100))
+    K = oracle.stiffness(m, 1e3, 1e-2)
+    w = oracle.mass(m).matvec(np.ones(m.n))
+    op = Operator(m, 1e3, 1e-2, kind="poisson", keep_fp32=True)
+    op.set_param("bspmm_vec", 4)
+    for mode, tile in (("fp64", 1), ("mixed", 3)):
+        op.set_param("bspmm_tile", tile)
+        X, infos = op.solve_batched(B, mask_bits=bits, tol=1e-10, mode=mode)
+        Xh, Bh = X.cpu().numpy(), B.cpu().numpy()
+        for j in (0, 7, 15):
+            assert infos[j].status == 0
+            bh = Bh[:, j] - Bh[:, j].mean()
+            r = bh - K.matvec(Xh[:, j])
+            r -= r.mean()
+            assert np.linalg.norm(r) <= 1.01e-10 * np.linalg.norm(bh)
+            assert abs(w @ Xh[:, j]) <= 1e-12 * np.abs(w).sum() * np.abs(Xh[:, j]).max()
