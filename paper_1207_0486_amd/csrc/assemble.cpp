@@ -19,6 +19,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <thread>
 
 #include "hns_internal.h"
@@ -94,21 +95,51 @@ struct Incidence {
     std::vector<int8_t> loc;   // local vertex number of the node in that tetrahedron
 };
 
+// Counts and fills run in parallel (atomic per-node cursors); each node's
+// list is then sorted by element index, so the result is the serial one.
 Incidence build_incidence(int64_t n, int64_t ne, int nloc, const int32_t *conn)
 {
     Incidence inc;
+    std::vector<std::atomic<int64_t>> cnt(n);
+    parallel_for(n, [&](int64_t lo, int64_t hi) {
+        for (int64_t i = lo; i < hi; ++i) cnt[i].store(0, std::memory_order_relaxed);
+    });
+    parallel_for(ne, [&](int64_t lo, int64_t hi) {
+        for (int64_t e = lo * nloc; e < hi * nloc; ++e)
+            cnt[conn[e]].fetch_add(1, std::memory_order_relaxed);
+    });
     inc.ptr.assign(n + 1, 0);
-    for (int64_t e = 0; e < ne * nloc; ++e) inc.ptr[conn[e] + 1]++;
-    for (int64_t i = 0; i < n; ++i) inc.ptr[i + 1] += inc.ptr[i];
+    for (int64_t i = 0; i < n; ++i) inc.ptr[i + 1] = inc.ptr[i] + cnt[i].load();
     inc.tet.resize(inc.ptr[n]);
     inc.loc.resize(inc.ptr[n]);
-    std::vector<int64_t> fill(inc.ptr.begin(), inc.ptr.end() - 1);
-    for (int64_t e = 0; e < ne; ++e)
-        for (int a = 0; a < nloc; ++a) {
-            int64_t s = fill[conn[e * nloc + a]]++;
-            inc.tet[s] = (int32_t)e;
-            inc.loc[s] = (int8_t)a;
+    parallel_for(n, [&](int64_t lo, int64_t hi) {
+        for (int64_t i = lo; i < hi; ++i) cnt[i].store(inc.ptr[i], std::memory_order_relaxed);
+    });
+    parallel_for(ne, [&](int64_t lo, int64_t hi) {
+        for (int64_t e = lo; e < hi; ++e)
+            for (int a = 0; a < nloc; ++a) {
+                const int64_t s = cnt[conn[e * nloc + a]].fetch_add(1, std::memory_order_relaxed);
+                inc.tet[s] = (int32_t)e;
+                inc.loc[s] = (int8_t)a;
+            }
+    });
+    parallel_for(n, [&](int64_t lo, int64_t hi) {
+        for (int64_t i = lo; i < hi; ++i) {
+            // insertion sort of the (element, local vertex) pairs by element
+            for (int64_t s = inc.ptr[i] + 1; s < inc.ptr[i + 1]; ++s) {
+                const int32_t t = inc.tet[s];
+                const int8_t l = inc.loc[s];
+                int64_t r = s;
+                while (r > inc.ptr[i] && inc.tet[r - 1] > t) {
+                    inc.tet[r] = inc.tet[r - 1];
+                    inc.loc[r] = inc.loc[r - 1];
+                    --r;
+                }
+                inc.tet[r] = t;
+                inc.loc[r] = l;
+            }
         }
+    });
     return inc;
 }
 
@@ -126,23 +157,24 @@ void build_pattern(int64_t n, int nloc, const int32_t *conn, const Incidence &in
         std::sort(buf.begin(), buf.end());
         buf.erase(std::unique(buf.begin(), buf.end()), buf.end());
     };
+    // one pass: every range of rows keeps its columns, then they are placed
+    std::vector<std::pair<int64_t, std::vector<int32_t>>> parts;
+    std::mutex pm;
     parallel_for(n, [&](int64_t lo, int64_t hi) {
-        std::vector<int32_t> buf;
+        std::vector<int32_t> buf, all;
         for (int64_t i = lo; i < hi; ++i) {
             row_cols(i, buf);
             len[i] = (int32_t)buf.size();
+            all.insert(all.end(), buf.begin(), buf.end());
         }
+        std::lock_guard<std::mutex> g(pm);
+        parts.emplace_back(lo, std::move(all));
     });
     for (int64_t i = 0; i < n; ++i) A.rowptr[i + 1] = A.rowptr[i] + len[i];
     A.col.resize(A.rowptr[n]);
     A.val.assign(A.rowptr[n], 0.0);
-    parallel_for(n, [&](int64_t lo, int64_t hi) {
-        std::vector<int32_t> buf;
-        for (int64_t i = lo; i < hi; ++i) {
-            row_cols(i, buf);
-            std::copy(buf.begin(), buf.end(), A.col.begin() + A.rowptr[i]);
-        }
-    });
+    for (const auto &pt : parts)
+        std::copy(pt.second.begin(), pt.second.end(), A.col.begin() + A.rowptr[pt.first]);
 }
 
 inline int64_t find_col(const HostCSR &A, int64_t row, int32_t c)
@@ -352,25 +384,43 @@ void DevMatrix::release()
 // and uses at most kMaxDiagWide distinct upper offsets; empty otherwise.
 static std::vector<int32_t> symmetric_offsets(const HostCSR &h)
 {
-    std::vector<char> seen;
+    // distinct upper offsets per range of rows, merged; then the bitwise
+    // symmetry of values and pattern, in parallel
     std::vector<int32_t> offs;
-    for (int64_t i = 0; i < h.n; ++i)
-        for (int32_t k = h.rowptr[i]; k < h.rowptr[i + 1]; ++k) {
-            const int64_t d = (int64_t)h.col[k] - i;
-            if (d <= 0) continue;
-            if (std::find(offs.begin(), offs.end(), (int32_t)d) == offs.end()) {
-                offs.push_back((int32_t)d);
-                if ((int)offs.size() > kMaxDiagWide) return {};
+    std::mutex om;
+    std::atomic<bool> too_many{false}, asym{false};
+    parallel_for(h.n, [&](int64_t lo, int64_t hi) {
+        std::vector<int32_t> mine;
+        for (int64_t i = lo; i < hi && !too_many.load(std::memory_order_relaxed); ++i)
+            for (int32_t k = h.rowptr[i]; k < h.rowptr[i + 1]; ++k) {
+                const int64_t d = (int64_t)h.col[k] - i;
+                if (d <= 0) continue;
+                if (std::find(mine.begin(), mine.end(), (int32_t)d) == mine.end()) {
+                    mine.push_back((int32_t)d);
+                    if ((int)mine.size() > kMaxDiagWide) {
+                        too_many.store(true);
+                        break;
+                    }
+                }
             }
-        }
-    // bitwise symmetry of values and pattern
-    for (int64_t i = 0; i < h.n; ++i)
-        for (int32_t k = h.rowptr[i]; k < h.rowptr[i + 1]; ++k) {
-            const int64_t j = h.col[k];
-            if (j <= i) continue;
-            const int64_t t = find_col(h, j, (int32_t)i);
-            if (t < 0 || h.val[t] != h.val[k]) return {};
-        }
+        std::lock_guard<std::mutex> g(om);
+        for (int32_t d : mine)
+            if (std::find(offs.begin(), offs.end(), d) == offs.end()) offs.push_back(d);
+    });
+    if (too_many.load() || (int)offs.size() > kMaxDiagWide) return {};
+    parallel_for(h.n, [&](int64_t lo, int64_t hi) {
+        for (int64_t i = lo; i < hi && !asym.load(std::memory_order_relaxed); ++i)
+            for (int32_t k = h.rowptr[i]; k < h.rowptr[i + 1]; ++k) {
+                const int64_t j = h.col[k];
+                if (j <= i) continue;
+                const int64_t t = find_col(h, j, (int32_t)i);
+                if (t < 0 || h.val[t] != h.val[k]) {
+                    asym.store(true);
+                    break;
+                }
+            }
+    });
+    if (asym.load()) return {};
     std::sort(offs.begin(), offs.end());
     return offs;
 }
