@@ -25,7 +25,7 @@ def _make(key):
 def test_served_equals_alone(mode, capacity):
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
-    from paper_1207_0486_amd.hns import Operator
+    from paper_1207_0486_amd.hns import BatchSession, Operator
     from paper_1207_0486_amd.serve import GpuBackend, Request, Server
     be = GpuBackend(_make, mode=mode, check_every=8)
     srv = Server(be, budget_bytes=4 << 30, capacity=capacity, chunk=16)
@@ -69,6 +69,25 @@ def test_served_equals_alone(mode, capacity):
             assert oracle.relres(A, r.b, out.x, d) <= 1.01e-8
         # ... and agree with each other
         diff = np.linalg.norm(out.x - x_alone) / np.linalg.norm(x_alone)
-        assert diff <= 1e-6, (r.key, diff)
+        if capacity <= 2:
+            # per-slot sessions run hns_solve's own recurrence: bit for bit
+            assert np.array_equal(out.x, x_alone), (r.key, diff)
+        else:
+            # the shared block runs the block recurrence: against the same
+            # request alone in a block session of the same capacity, within
+            # the parity tolerance (the per-column sums of a slot may run in
+            # another order than those of the slot it was served in); against
+            # hns_solve, both answers meet the tolerance
+            assert diff <= 1e-6, (r.key, diff)
+            sess = BatchSession(op, capacity, mode)
+            bt = torch.as_tensor(r.b, device="cuda")
+            sess.add([0], [r.mask_bit], [bt], [1e-8], [r.max_iter])
+            while sess.advance(16):
+                pass
+            x_blk, _ = sess.take(0)
+            sess.close()
+            xb = x_blk.cpu().numpy()
+            d_blk = np.linalg.norm(out.x - xb) / np.linalg.norm(xb)
+            assert d_blk <= (1e-10 if mode == "fp64" else 1e-9), (r.key, d_blk)
     st = srv.stats()
     assert st["completed"] == 20 and st["p50_ms"] <= st["p99_ms"]
