@@ -79,10 +79,19 @@ typedef struct {
 #define HNS_KEEP_FP32 0x10u  /* also keep FP32 matrix/diagonal copies (HNS_MIXED)  */
 #define HNS_KEEP_HOST 0x80u  /* keep a host copy of the assembled matrix (needed by
                                 the IC(0) preconditioner, set_param "precond" = 2)   */
-#define HNS_GPU_ASSEMBLY 0x40u /* compute the operator's values on the device (one
-                                lane per row gathers its tetrahedra in order, as the
-                                host loop does; bitwise the same values); the
-                                pattern and the auxiliary forms stay on the host    */
+#define HNS_GPU_ASSEMBLY 0x40u /* build the operator on the device, bitwise the host
+                                path's operator: without HNS_KEEP_HOST and
+                                HNS_STEP_AUX, with the automatic or the diagonal
+                                format, and when the element offsets fit the
+                                unrolled diagonal storage (at most 16 upper
+                                diagonals), everything (node incidence by counting
+                                sort, offsets, values in diagonal storage, D^-1,
+                                lumped mass); otherwise the values only (one lane
+                                per row gathers its tetrahedra in order, as the host
+                                loop does) on a pattern built on the host.  The
+                                mesh is copied to the device for it; the transient
+                                device memory is about twice the mesh arrays
+                                (coordinates, tetrahedra, incidence lists)        */
 #define HNS_STEP_AUX  0x20u  /* also keep M, B_1..3, lumped mass, surface mass and
                                 the mesh (coordinates, tetrahedra, node incidence)
                                 for the step right-hand sides (hns_step_*)          */
@@ -238,8 +247,9 @@ hns_status hns_solve_batched(hns_operator *op, int k, const int *mask_bits,
  *    per slot the arithmetic is that of hns_solve_batched (per-column
  *    scalars, tolerance and iteration cap; HNS_MIXED with FP64 residual
  *    replacement);
- *  - per slot: every slot runs hns_solve's own point-Jacobi recurrence
- *    (HNS_MIXED as mixed_variant 0), its answer bitwise that of hns_solve
+ *  - per slot: every slot runs hns_solve's own recurrence (HNS_MIXED as
+ *    mixed_variant 0; the line preconditioner when "precond" is 1, point
+ *    Jacobi otherwise, IC(0) included), its answer bitwise that of hns_solve
  *    with x0 = 0; an advance enqueues one chunk of every running slot and
  *    waits once.  With one or two slots sharing the operator read saves
  *    nothing next to the vector traffic, and a half-empty block still moves
@@ -321,6 +331,11 @@ int hns_operator_ndiag(const hns_operator *op);
  * is not made of such columns (the line preconditioner is then unavailable),
  * -1 for a null operator. */
 int hns_operator_line_len(const hns_operator *op);
+
+/* Where the operator was built: 0 on the host, 1 values on the device on a
+ * host pattern, 2 entirely on the device (HNS_GPU_ASSEMBLY); -1 for a null
+ * operator. */
+int hns_operator_assembly(const hns_operator *op);
 
 /* Tunables (returns HNS_ERR_INVALID for an unknown name or a bad value):
  *   "check_every"  CG iterations between host convergence reads (default 32)

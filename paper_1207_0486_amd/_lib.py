@@ -84,6 +84,7 @@ _SIGNATURES = {
     "hns_operator_format": (C.c_uint32, [C.c_void_p]),
     "hns_operator_ndiag": (C.c_int, [C.c_void_p]),
     "hns_operator_line_len": (C.c_int, [C.c_void_p]),
+    "hns_operator_assembly": (C.c_int, [C.c_void_p]),
     "hns_set_param": (C.c_int, [C.c_void_p, C.c_char_p, C.c_double]),
     "hns_apply": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]),
     "hns_step_velocity_rhs": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,

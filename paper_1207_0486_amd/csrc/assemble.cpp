@@ -187,14 +187,7 @@ inline int64_t find_col(const HostCSR &A, int64_t row, int32_t c)
 
 hns_status check_mesh(const hns_mesh *m)
 {
-    if (!m || m->n_nodes <= 0 || m->n_tets < 0 || !m->xyz || (m->n_tets > 0 && !m->tets)) {
-        set_error("mesh: null arrays or non-positive sizes");
-        return HNS_ERR_INVALID;
-    }
-    if (m->n_nodes >= (int64_t)INT32_MAX) {
-        set_error("mesh: %lld nodes exceed the int32 index range", (long long)m->n_nodes);
-        return HNS_ERR_INVALID;
-    }
+    HNS_TRY(check_mesh_arrays(m));
     for (int64_t e = 0; e < 4 * m->n_tets; ++e)
         if (m->tets[e] < 0 || m->tets[e] >= m->n_nodes) {
             set_error("mesh: tetrahedron %lld references node %d outside [0,%lld)",
@@ -210,6 +203,19 @@ hns_status check_mesh(const hns_mesh *m)
 }
 
 }  // namespace
+
+hns_status check_mesh_arrays(const hns_mesh *m)
+{
+    if (!m || m->n_nodes <= 0 || m->n_tets < 0 || !m->xyz || (m->n_tets > 0 && !m->tets)) {
+        set_error("mesh: null arrays or non-positive sizes");
+        return HNS_ERR_INVALID;
+    }
+    if (m->n_nodes >= (int64_t)INT32_MAX) {
+        set_error("mesh: %lld nodes exceed the int32 index range", (long long)m->n_nodes);
+        return HNS_ERR_INVALID;
+    }
+    return HNS_OK;
+}
 
 hns_status assemble_host(const hns_mesh *mesh, double c_mass, double c_stiff, double nu_h,
                          double nu_v, HostCSR &A, std::vector<double> *lumped, bool values_on_device)

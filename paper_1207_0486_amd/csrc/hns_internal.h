@@ -141,6 +141,7 @@ struct hns_operator {
     double *lumped = nullptr;   // M 1 (mass-weighted mean of the Neumann answer)
     double lumped_sum = 0.0;
     int64_t bad_diag = -1;      // first non-positive diagonal entry, -1 if none
+    int assembly = 0;           // 0 host, 1 values on the device, 2 the whole operator there
     // auxiliary forms for the step right-hand sides
     hns::DevMatrix M, B[3], Bt[3], Ms;
     bool has_aux = false;
@@ -248,6 +249,8 @@ hns_status batched_plan(hns_operator *op, BWorkspace *w, int k, bool mixed, hipS
                         int *plan);
 
 // assemble.cpp
+// null arrays, sizes and the int32 node range of a tetrahedral mesh
+hns_status check_mesh_arrays(const hns_mesh *m);
 // values_on_device: the pattern is built here, the values (and the element
 // volume check) by a device kernel in the same order as the host loop
 hns_status assemble_host(const hns_mesh *mesh, double c_mass, double c_stiff, double nu_h,
@@ -259,6 +262,15 @@ hns_status assemble_values_device(const hns_mesh *mesh, const std::vector<int64_
                                   const std::vector<int8_t> &inc_loc, HostCSR &A, double c_mass,
                                   double c_stiff, double nu_h, double nu_v,
                                   std::vector<double> *lumped);
+// The whole operator on the device in symmetric diagonal storage (A, D^-1,
+// FP32 copies with keep32, lumped mass and its total, first non-positive
+// diagonal, structural nonzeros): bitwise the host path's operator.  Checks
+// the vertex indices and coordinates itself (check_mesh_arrays first).
+// *applicable = false, with op untouched, where the element offsets do not
+// fit the unrolled diagonal storage (then the host path builds it).
+hns_status assemble_operator_device(const hns_mesh *mesh, double c_mass, double c_stiff,
+                                    double nu_h, double nu_v, bool keep32, hns_operator *op,
+                                    bool *applicable);
 hns_status assemble_divergence_host(const hns_mesh *mesh, const HostCSR &pattern, int comp,
                                     HostCSR &B);
 hns_status assemble_surface_mass_host(const hns_mesh *mesh, HostCSR &Ms);

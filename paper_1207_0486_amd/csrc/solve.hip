@@ -9,6 +9,12 @@
 
 #include "kernels.h"
 
+// the line factors of a Dirichlet set (defined with the entry points below)
+extern "C" {
+static hns_status line_factors(hns_operator *op, int bit, const double **out);
+static hns_status line_factors32(hns_operator *op, int bit, const float **out);
+}
+
 namespace hns {
 
 static thread_local std::string g_last_error;
@@ -798,6 +804,7 @@ struct SlotSession {
     int K = 0;
     bool mixed = false;
     bool scaled = false;
+    bool line = false;   // the vertical-line block preconditioner (set_param "precond" = 1)
     struct Slot {
         int state = 0;   // 0 free, 1 running, 2 finished
         double *b = nullptr, *x = nullptr;
@@ -819,11 +826,22 @@ static bool session_scaled(const hns_operator *op, bool mixed)
            op->A.ndiag <= kMaxDiag && op->n > op->small_n && (!mixed || op->A.dia32);
 }
 
+// line blocks in a per-slot session: "precond" = 1 (a per-slot HNS_MIXED
+// solve is always mixed_variant 0, which runs them); IC(0) sessions keep point
+// Jacobi
+static bool session_line(const hns_operator *op)
+{
+    return op->precond == 1;
+}
+
 size_t slot_session_bytes(const hns_operator *op, int capacity, bool mixed)
 {
     const size_t n = (size_t)op->n;
     size_t per = Workspace::bytes_for(op->n, mixed) + 2 * ((n + 31) & ~size_t(31)) * sizeof(double);
-    if (session_scaled(op, mixed) && !mixed) per += n * sizeof(double);   // scaled correction
+    if (session_line(op))
+        per += n * sizeof(double);                                          // z
+    else if (session_scaled(op, mixed) && !mixed)
+        per += n * sizeof(double);                                          // scaled correction
     return per * (size_t)capacity + 256;
 }
 
@@ -845,7 +863,8 @@ hns_status slot_session_open(hns_operator *op, int capacity, bool mixed, SlotSes
     ss->op = op;
     ss->K = capacity;
     ss->mixed = mixed;
-    ss->scaled = session_scaled(op, mixed);
+    ss->line = session_line(op);
+    ss->scaled = !ss->line && session_scaled(op, mixed);
     ss->slots.resize(capacity);
     auto fail = [&](hns_status st) {
         slot_session_close(ss);
@@ -868,7 +887,7 @@ hns_status slot_session_open(hns_operator *op, int capacity, bool mixed, SlotSes
         sl.x = sl.b + n_al;
         sl.w = new Workspace();
         hns_status st = sl.w->allocate(op->n, mixed);
-        if (st == HNS_OK && ss->scaled && !mixed) st = sl.w->ensure_z();
+        if (st == HNS_OK && (ss->line || (ss->scaled && !mixed))) st = sl.w->ensure_z();
         if (st != HNS_OK) return fail(st);
     }
     *out = ss;
@@ -900,11 +919,19 @@ hns_status slot_session_add(SlotSession *ss, int count, const int *slots, const 
                                    hipMemcpyDeviceToDevice, s));
         HNS_TRY(launch_prepare_x(op->n, sl.x, nullptr, -1, true, s));
         memset(&sl.info, 0, sizeof(sl.info));
+        const double *lfac = nullptr;
+        const float *lfac32 = nullptr;
+        if (ss->line) {   // factors of this Dirichlet set (built on its first use)
+            if (ss->mixed)
+                HNS_TRY(line_factors32(op, mask_bits[q], &lfac32));
+            else
+                HNS_TRY(line_factors(op, mask_bits[q], &lfac));
+        }
         sl.cs = ChunkedSolve();
         sl.cs.c = SolveCtx{op,       mask_bits[q], op->kind == HNS_POISSON && mask_bits[q] < 0,
                            sl.b,     sl.x,         tols[q],
                            max_iters[q], s,        sl.w,
-                           nullptr,  nullptr,      nullptr,
+                           lfac,     nullptr,      lfac32,
                            ss->scaled};
         sl.cs.info = &sl.info;
         sl.cs.mixed = ss->mixed;
@@ -1049,6 +1076,38 @@ static void keep_column_blocks(hns_operator *op, const HostCSR &A, int L, const 
     if (bc) op->bc_host.assign(bc, bc + A.n);
 }
 
+// Dirichlet bits and column blocks of an operator assembled on the device
+// (the diagonal and the coupling to the next node of a column, read back
+// from the diagonal storage).
+static hns_status finish_device_operator(hns_operator *op, const hns_mesh *mesh)
+{
+    const int64_t n = op->n;
+    if (mesh->bc) {
+        hipError_t e = hipMalloc((void **)&op->bc, (size_t)n);
+        if (e != hipSuccess) {
+            op->bc = nullptr;
+            set_error("hipMalloc of %lld bytes failed: %s", (long long)n, hipGetErrorString(e));
+            return e == hipErrorOutOfMemory ? HNS_ERR_OOM : HNS_ERR_HIP;
+        }
+        HNS_TRY_HIP(hipMemcpy(op->bc, mesh->bc, (size_t)n, hipMemcpyHostToDevice));
+    }
+    const int L = detect_columns(mesh);
+    if (L < 2) return HNS_OK;
+    op->line_len = L;
+    op->line_d.assign(n, 0.0);
+    op->line_e.assign(n, 0.0);
+    HNS_TRY_HIP(hipMemcpy(op->line_d.data(), op->A.dia, n * sizeof(double),
+                          hipMemcpyDeviceToHost));
+    for (int k = 0; k < op->A.ndiag; ++k)
+        if (op->A.off[k] == 1) {
+            HNS_TRY_HIP(hipMemcpy(op->line_e.data(), op->A.dia + (size_t)(k + 1) * n,
+                                  n * sizeof(double), hipMemcpyDeviceToHost));
+            for (int64_t i = L - 1; i < n; i += L) op->line_e[i] = 0.0;   // column tops
+        }
+    if (mesh->bc) op->bc_host.assign(mesh->bc, mesh->bc + n);
+    return HNS_OK;
+}
+
 static hns_status finish_operator(hns_operator *op, const HostCSR &A, uint32_t fmt_flag,
                                   const std::vector<double> &lumped, const uint8_t *bc_host)
 {
@@ -1181,8 +1240,29 @@ hns_status hns_assemble(const hns_mesh *mesh, double nu_h, double nu_v, double d
     std::vector<double> lumped;
     const double c_mass = (kind == HNS_HELMHOLTZ) ? 1.0 : 0.0;
     const double c_stiff = (kind == HNS_HELMHOLTZ) ? dt : 1.0;
+    if ((flags & HNS_GPU_ASSEMBLY) && !(flags & (HNS_KEEP_HOST | HNS_STEP_AUX)) &&
+        (fmt == 0 || fmt == HNS_FMT_SDIA)) {
+        // pattern, offsets and values on the device where the operator fits
+        // the unrolled diagonal storage
+        bool done = false;
+        hns_status st = check_mesh_arrays(mesh);
+        if (st == HNS_OK)
+            st = assemble_operator_device(mesh, c_mass, c_stiff, nu_h, nu_v,
+                                          (flags & HNS_KEEP_FP32) != 0, op, &done);
+        if (st == HNS_OK && done) st = finish_device_operator(op, mesh);
+        if (st != HNS_OK) {
+            hns_operator_destroy(op);
+            return st;
+        }
+        if (done) {
+            op->assembly = 2;
+            *out = op;
+            return HNS_OK;
+        }
+    }
     hns_status st = assemble_host(mesh, c_mass, c_stiff, nu_h, nu_v, A, &lumped,
                                   (flags & HNS_GPU_ASSEMBLY) != 0);
+    if (flags & HNS_GPU_ASSEMBLY) op->assembly = 1;
     if (st == HNS_OK) {
         op->n = A.n;
         st = finish_operator(op, A, fmt, lumped, mesh->bc);
@@ -1332,6 +1412,8 @@ int64_t hns_operator_n(const hns_operator *op) { return op ? op->n : -1; }
 int64_t hns_operator_nnz(const hns_operator *op) { return op ? op->A.nnz : -1; }
 uint32_t hns_operator_format(const hns_operator *op) { return op ? op->A.fmt : 0; }
 int hns_operator_line_len(const hns_operator *op) { return op ? op->line_len : -1; }
+
+int hns_operator_assembly(const hns_operator *op) { return op ? op->assembly : -1; }
 
 int hns_operator_ndiag(const hns_operator *op)
 {

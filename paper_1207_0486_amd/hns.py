@@ -141,6 +141,8 @@ class Operator:
         self.format = FORMAT_NAMES.get(int(L.lib().hns_operator_format(h)), "?")
         self.ndiag = int(L.lib().hns_operator_ndiag(h))
         self.line_len = int(L.lib().hns_operator_line_len(h))
+        # 0 host, 1 values on the device (host pattern), 2 built on the device
+        self.assembly = int(L.lib().hns_operator_assembly(h))
         self.keep_fp32 = keep_fp32
 
     # -- lifetime -------------------------------------------------------

@@ -1,4 +1,6 @@
-"""Device assembly of the operator values: bitwise the host assembly, equal to
+"""Device assembly: the whole operator built on the device (incidence,
+offsets, diagonal storage) where it fits the unrolled diagonal storage, else
+the values on a host pattern; bitwise the host assembly either way, equal to
 the oracle's independent assembly, and the same mesh errors."""
 import dataclasses
 
@@ -37,25 +39,39 @@ MESHES = {
 }
 
 
+# where the build runs: whole operator on the device (diagonal storage fits),
+# or the values only (a random numbering spreads the offsets over the range)
+WHERE = {"box16": 2, "basin": 2, "permuted": 1}
+
+
 @pytest.mark.parametrize("name", list(MESHES))
 @pytest.mark.parametrize("kind", ["poisson", "helmholtz"])
 def test_device_values_are_the_host_values(dev, name, kind):
     from paper_1207_0486_amd.hns import Operator
     m = MESHES[name]()
     nu_h, nu_v, dt = 1e3, 1e-2, 3600.0
-    host = Operator(m, nu_h, nu_v, dt, kind=kind)
-    gpu = Operator(m, nu_h, nu_v, dt, kind=kind, gpu_assembly=True)
-    assert (gpu.n, gpu.nnz, gpu.format, gpu.ndiag) == (host.n, host.nnz, host.format, host.ndiag)
+    host = Operator(m, nu_h, nu_v, dt, kind=kind, keep_fp32=True)
+    gpu = Operator(m, nu_h, nu_v, dt, kind=kind, gpu_assembly=True, keep_fp32=True)
+    assert host.assembly == 0 and gpu.assembly == WHERE[name]
+    assert (gpu.n, gpu.nnz, gpu.format, gpu.ndiag, gpu.line_len) == \
+        (host.n, host.nnz, host.format, host.ndiag, host.line_len)
     rng = np.random.default_rng(3)
     for _ in range(3):
         x = torch.as_tensor(rng.standard_normal(m.n), device=dev)
         assert torch.equal(gpu.apply(x), host.apply(x))
-    # diagonal and lumped mass too: identical solves
+    # diagonal, FP32 copies, lumped mass and column blocks too: identical solves
     b = torch.as_tensor(basin.normal_rhs(m.n, 9, zero_mean=kind == "poisson"), device=dev)
     bit = -1 if kind == "poisson" else 0
-    xh, ih = host.solve(b, tol=1e-10, mask_bit=bit)
-    xg, ig = gpu.solve(b, tol=1e-10, mask_bit=bit)
-    assert ih.iterations == ig.iterations and torch.equal(xh, xg)
+    for mode in ("fp64", "mixed"):
+        xh, ih = host.solve(b, tol=1e-10, mask_bit=bit, mode=mode)
+        xg, ig = gpu.solve(b, tol=1e-10, mask_bit=bit, mode=mode)
+        assert ih.iterations == ig.iterations and torch.equal(xh, xg), mode
+    if host.line_len >= 2:
+        for op in (host, gpu):
+            op.set_param("precond", 1)
+        xh, ih = host.solve(b, tol=1e-10, mask_bit=bit)
+        xg, ig = gpu.solve(b, tol=1e-10, mask_bit=bit)
+        assert ih.iterations == ig.iterations and torch.equal(xh, xg)
     # against the oracle's own assembly
     A = oracle.helmholtz(m, nu_h, nu_v, dt) if kind == "helmholtz" else \
         oracle.stiffness(m, nu_h, nu_v)
@@ -66,13 +82,28 @@ def test_device_values_are_the_host_values(dev, name, kind):
         np.abs(xr).max()
 
 
-def test_device_assembly_reports_inverted_tetrahedra(dev):
-    from paper_1207_0486_amd.hns import HNSError, Operator
+def _bad_meshes():
     m = basin.box_mesh(4, 4, 2)
-    tets = m.tets.copy()
-    tets[17, [1, 2]] = tets[17, [2, 1]]       # negative volume
-    bad = dataclasses.replace(m, tets=tets)
+    inverted = m.tets.copy()
+    inverted[17, [1, 2]] = inverted[17, [2, 1]]       # negative volume
+    outside = m.tets.copy()
+    outside[9, 3] = m.n                               # vertex index out of range
+    xyz = m.xyz.copy()
+    xyz[11, 2] = np.nan                               # non-finite coordinate
+    return {"inverted": dataclasses.replace(m, tets=inverted),
+            "outside": dataclasses.replace(m, tets=outside),
+            "nan": dataclasses.replace(m, xyz=xyz)}
+
+
+@pytest.mark.parametrize("case", ["inverted", "outside", "nan"])
+def test_device_assembly_reports_mesh_errors(dev, case):
+    from paper_1207_0486_amd import _lib as L
+    from paper_1207_0486_amd.hns import HNSError, Operator
+    bad = _bad_meshes()[case]
+    msgs = []
     for gpu_assembly in (False, True):
         with pytest.raises(HNSError) as e:
             Operator(bad, 1.0, 1.0, 0.1, kind="helmholtz", gpu_assembly=gpu_assembly)
         assert e.value.status == -4
+        msgs.append(L.lib().hns_last_error())
+    assert msgs[0] == msgs[1], msgs

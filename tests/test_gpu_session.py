@@ -49,15 +49,18 @@ def _run(sess, adds, advance=13, limit=100000):
         assert rnd < limit
 
 
+@pytest.mark.parametrize("precond", [0, 1])
 @pytest.mark.parametrize("mode", ["fp64", "mixed"])
 @pytest.mark.parametrize("kind", ["poisson", "helmholtz"])
-def test_per_slot_session_equals_solve_bitwise(dev, mode, kind):
-    """Two slots on the 40x36x6 basin (10,619 rows, Jacobi-scaled): the second
-    request joins while the first runs; each answer equals hns_solve's."""
+def test_per_slot_session_equals_solve_bitwise(dev, mode, kind, precond):
+    """Two slots on the 40x36x6 basin (10,619 rows, Jacobi-scaled point
+    Jacobi, or the water-column line blocks): the second request joins while
+    the first runs; each answer equals hns_solve's."""
     from paper_1207_0486_amd.hns import BatchSession, Operator
     m = basin.basin_mesh(40, 36, 6, seed=5)
     op = Operator(m, *NU, DT if kind == "helmholtz" else 0.0, kind=kind, keep_fp32=True)
     op.set_param("session_mode", 2)
+    op.set_param("precond", precond)
     bits = [-1, -1] if kind == "poisson" else [0, 2]
     bs = [torch.as_tensor(_rhs(m, bits[q], 50 + q), device=dev) for q in range(2)]
     sess = BatchSession(op, 2, mode)
