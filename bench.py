@@ -697,12 +697,13 @@ def bench_preconditioners(torch, log, m, b_vel, reps=3):
 
 
 def bench_serving(torch, log, budget_gb=1.5, mode="fp64", count=256, capacity=8, chunk=32,
-                  check=True, oracle_cache=None):
+                  check=True, oracle_cache=None, line_pressure=False):
     """Serving: Poisson-process arrivals (50 req/s) of pressure / velocity solve
     requests over five mesh sizes, tolerance 1e-8, continuous batching with
-    operators admitted by footprint under an HBM budget (the whole set of ten
-    operators needs about 3.5 GB, so a budget of 1.5 GB makes the server
-    evict idle operators and assemble them again).  check=True: one request
+    operators admitted by footprint under an HBM budget (the ten operators
+    with two-slot sessions hold about 2.7 GB in FP64 and 3.7 GB in mixed
+    precision, so a budget of 1.5 GB makes the server evict idle operators and
+    build them again on the device).  check=True: one request
     per mesh size is solved again alone on a fresh operator (the served
     answer must be the same) and checked by the oracle's own residual."""
     import threading
@@ -721,7 +722,7 @@ def bench_serving(torch, log, budget_gb=1.5, mode="fp64", count=256, capacity=8,
     reqs = basin.serving_requests(wl.extra["requests"] if count is None else count,
                                   wl.extra["rate_hz"], wl.seed)
     t0 = time.time()
-    be = GpuBackend(make, mode=mode, check_every=16)
+    be = GpuBackend(make, mode=mode, check_every=16, line_pressure=line_pressure)
     srv = Server(be, budget_bytes=int(budget_gb * (1 << 30)), capacity=capacity, chunk=chunk)
     # warm-up: one request per operator (assembly, tuning); with a small
     # budget the early operators are evicted again
@@ -785,6 +786,7 @@ def bench_serving(torch, log, budget_gb=1.5, mode="fp64", count=256, capacity=8,
         "p99_ms": round(float(np.percentile(v, 99)) * 1e3, 2)} for i, v in sorted(per_mesh.items())}
     out = {"requests": len(results), "rate_hz": wl.extra["rate_hz"], "tol": wl.tol,
            "mode": mode, "capacity": capacity, "chunk": chunk, "budget_gb": budget_gb,
+           "pressure_precond": "line" if line_pressure else "jacobi",
            "p50_ms": round(st["p50_ms"], 2), "p99_ms": round(st["p99_ms"], 2),
            "mean_ms": round(st["mean_ms"], 2), "solves_per_s": round(st["solves_per_s"], 2),
            "wall_s": round(end - start, 3), "nodes_solved": int(nodes), "failed": bad,
@@ -795,12 +797,12 @@ def bench_serving(torch, log, budget_gb=1.5, mode="fp64", count=256, capacity=8,
            "meshes": [list(mm) for mm in sizes]}
     if check:
         out["check"] = serving_check(torch, log, items, results, make, mode, wl.tol,
-                                     oracle_cache)
+                                     oracle_cache, line_pressure)
     log(f"serving: {out}")
     return out
 
 
-def serving_check(torch, log, items, results, make, mode, tol, cache):
+def serving_check(torch, log, items, results, make, mode, tol, cache, line_pressure=False):
     """One served request per mesh size (the first of each in the stream):
     the same solve alone on a freshly assembled operator (per-slot sessions
     run hns_solve's recurrence, so the answers should agree bit for bit) and
@@ -817,6 +819,8 @@ def serving_check(torch, log, items, results, make, mode, tol, cache):
         op = Operator(m, nu_h, nu_v, dt, kind=kind, keep_fp32=mode == "mixed",
                       gpu_assembly=True)
         op.set_param("check_every", 16)
+        if line_pressure and kind == "poisson" and op.line_len >= 2:
+            op.set_param("precond", 1)
         x, info = op.solve(torch.as_tensor(q.b, device="cuda"), tol=tol, mask_bit=q.mask_bit,
                            mode=mode)
         alone = x.cpu().numpy()
@@ -902,11 +906,15 @@ def main():
                          "iterations (for counter passes)")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serve-budget-gb", type=float, default=1.5,
-                    help="HBM budget of the serving stream (its ten operators need ~3.5 GB)")
+                    help="HBM budget of the serving stream (its ten operators hold 2.7-3.7 GB)")
     ap.add_argument("--serve-mode", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--serve-capacity", type=int, default=2,
                     help="slots per operator session")
     ap.add_argument("--serve-chunk", type=int, default=32, help="iterations between admissions")
+    ap.add_argument("--serve-resident-gb", type=float, default=8.0,
+                    help="second serving run with a budget that holds every operator (0: skip)")
+    ap.add_argument("--serve-line-pressure", action="store_true",
+                    help="serve Poisson requests with the water-column line preconditioner")
     ap.add_argument("--fmt", default="auto")
     ap.add_argument("--param", action="append", default=[], metavar="NAME=VALUE",
                     help="hns_set_param tunable applied to the step's two operators "
@@ -1123,13 +1131,22 @@ def main():
         cache = {}
         serving = bench_serving(torch, log, args.serve_budget_gb, args.serve_mode,
                                 capacity=args.serve_capacity, chunk=args.serve_chunk,
-                                check=not args.no_cpu_baseline, oracle_cache=cache)
+                                check=not args.no_cpu_baseline, oracle_cache=cache,
+                                line_pressure=args.serve_line_pressure)
         other = "mixed" if args.serve_mode == "fp64" else "fp64"
         serving_other = bench_serving(torch, log, args.serve_budget_gb, other,
                                       capacity=args.serve_capacity, chunk=args.serve_chunk,
-                                      check=not args.no_cpu_baseline, oracle_cache=cache)
+                                      check=not args.no_cpu_baseline, oracle_cache=cache,
+                                      line_pressure=args.serve_line_pressure)
         serving = {args.serve_mode: serving, other: serving_other}
         del cache
+        if args.serve_resident_gb > 0:
+            # every operator resident: no admission or eviction in the stream
+            serving["all_resident"] = {
+                md: bench_serving(torch, log, args.serve_resident_gb, md,
+                                  capacity=args.serve_capacity, chunk=args.serve_chunk,
+                                  check=False, line_pressure=args.serve_line_pressure)
+                for md in (args.serve_mode, other)}
 
     cpu = None
     if systems is not None:

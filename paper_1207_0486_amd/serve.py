@@ -58,10 +58,13 @@ class GpuBackend:
     """
 
     def __init__(self, make_operator, device=0, mode="fp64", check_every=16,
-                 gpu_assembly=True):
+                 gpu_assembly=True, line_pressure=False):
         import torch
         self.torch = torch
-        self.gpu_assembly = gpu_assembly   # operator values computed on the device
+        self.gpu_assembly = gpu_assembly   # operators built on the device
+        # Poisson requests on water-column numberings with the line
+        # preconditioner (per-slot sessions run it; see hns_batch_open)
+        self.line_pressure = line_pressure
         self._make = make_operator
         self._made = {}
         self._made_lock = threading.Lock()
@@ -92,6 +95,8 @@ class GpuBackend:
                           device=self.device, gpu_assembly=self.gpu_assembly)
             op.set_param("check_every", self.check_every)
             op.set_param("use_graph", 1)
+            if self.line_pressure and kind == "poisson" and op.line_len >= 2:
+                op.set_param("precond", 1)
             sess = BatchSession(op, capacity, self.mode)
             stream = self.torch.cuda.Stream(device=self.device)
         nbytes = op.footprint(1, self.mode, True) + BatchSession.footprint(op, capacity, self.mode)
