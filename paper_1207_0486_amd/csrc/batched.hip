@@ -69,6 +69,22 @@ enum : int32_t {
     for (int64_t t = blockIdx.x * (int64_t)kBlock + threadIdx.x; t < (np); \
          t += (int64_t)gridDim.x * kBlock)
 
+// The same walk by element e = t V and row i = e / K: the grid's thread count
+// times V is a multiple of K (bgrid), so a thread keeps the columns of its
+// first pack in every pass and its row advances by a constant (no 64-bit
+// division per pack).
+#define ROW_LOOP(e, i, n, K, V)                                                             \
+    for (int64_t e = (blockIdx.x * (int64_t)kBlock + threadIdx.x) * (V), i = e / (K),       \
+                 de_ = (int64_t)gridDim.x * kBlock * (V), di_ = de_ / (K);                  \
+         e < (int64_t)(n) * (K); e += de_, i += di_)
+
+// First column of the thread's packs in ROW_LOOP.
+template <int V>
+__device__ __forceinline__ int thread_col0(int K)
+{
+    return (int)((((int64_t)blockIdx.x * kBlock + threadIdx.x) * V) % K);
+}
+
 // True in every thread of the block when at least one of the K columns is
 // running (stop == ACTIVE; mode 0) or is marked for a direction update
 // (mode 1).  The per-iteration kernels return at once otherwise, so the
@@ -177,7 +193,7 @@ template <int V>
 __device__ __forceinline__ ColBits<V> thread_col_bits(const BCol *__restrict__ cols, int K)
 {
     ColBits<V> cb;
-    const int j0 = (int)((((int64_t)blockIdx.x * kBlock + threadIdx.x) * V) % K);
+    const int j0 = thread_col0<V>(K);
 #pragma unroll
     for (int v = 0; v < V; ++v) cb.bit[v] = cols[j0 + v].bit;
     return cb;
@@ -203,12 +219,17 @@ __global__ __launch_bounds__(kBlock) void k_bspmm_sdia(int64_t n, int K, BOffset
     double acc[1][V];
 #pragma unroll
     for (int v = 0; v < V; ++v) acc[0][v] = 0.0;
-    const int64_t np = n * K / V;
     const ColBits<V> cbits = thread_col_bits<V>(cols, K);
-    PACK_LOOP(t, np)
+    const int j0 = thread_col0<V>(K);
+    // the iteration's product: a thread whose columns have all stopped
+    // skips its rows (their q is not read again)
+    bool mine = !DOT;
+    if constexpr (DOT) {
+#pragma unroll
+        for (int v = 0; v < V; ++v) mine |= cols[j0 + v].stop == ACTIVE;
+    }
+    if (mine) ROW_LOOP(e, i, n, K, V)
     {
-        const int64_t e = t * V;
-        const int64_t i = e / K;
         const uint8_t bci = bc ? bc[i] : (uint8_t)0;
         const auto pi = bld<V>(P, e);
         const TX d = (TX)dia[i];
@@ -223,8 +244,8 @@ __global__ __launch_bounds__(kBlock) void k_bspmm_sdia(int64_t n, int K, BOffset
             const int64_t iu = hu ? i + o : i, il = hl ? i - o : i;
             const TX cu = hu ? (TX)u[i] : (TX)0;
             const TX cl = hl ? (TX)u[il] : (TX)0;
-            const auto pu = bld<V>(P, iu * K + (e - i * K));
-            const auto pl = bld<V>(P, il * K + (e - i * K));
+            const auto pu = bld<V>(P, iu * K + j0);
+            const auto pl = bld<V>(P, il * K + j0);
 #pragma unroll
             for (int v = 0; v < V; ++v) s[v] += cu * pu.v[v] + cl * pl.v[v];
         }
@@ -609,34 +630,36 @@ __global__ __launch_bounds__(kBlock) void k_bupdate(int64_t n, int K, TX *__rest
     double acc[2][V];
 #pragma unroll
     for (int v = 0; v < V; ++v) acc[0][v] = acc[1][v] = 0.0;
-    const int64_t np = n * K / V;
-    PACK_LOOP(t, np)
+    // the thread's columns are the same in every pass: their state once
+    const int j0 = thread_col0<V>(K);
+    bool act[V];
+    TX a[V];
+    bool any = false;
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        const BCol &s = cols[j0 + v];
+        act[v] = s.stop == ACTIVE;
+        a[v] = (TX)s.alpha;
+        any |= act[v];
+    }
+    if (any) ROW_LOOP(e, i, n, K, V)
     {
-        const int64_t e = t * V;
-        const int64_t i = e / K;
-        const int j0 = (int)(e - i * K);
         auto xv = bld<V>(X, e);
         auto rv = bld<V>(R, e);
         const auto pv = bld<V>(P, e);
         const auto qv = bld<V>(Q, e);
         const TX d = (TX)dinv[i];
-        bool any = false;
 #pragma unroll
         for (int v = 0; v < V; ++v) {
-            const BCol &s = cols[j0 + v];
-            if (s.stop != ACTIVE) continue;
-            any = true;
-            const TX a = (TX)s.alpha;
-            xv.v[v] = xv.v[v] + a * pv.v[v];
-            rv.v[v] = rv.v[v] - a * qv.v[v];
+            if (!act[v]) continue;
+            xv.v[v] = xv.v[v] + a[v] * pv.v[v];
+            rv.v[v] = rv.v[v] - a[v] * qv.v[v];
             const TX z = d * rv.v[v];
             acc[0][v] += (double)rv.v[v] * (double)z;
             acc[1][v] += (double)rv.v[v] * (double)rv.v[v];
         }
-        if (any) {
-            bst<V>(X, e, xv);
-            bst<V>(R, e, rv);
-        }
+        bst<V>(X, e, xv);
+        bst<V>(R, e, rv);
     }
     block_column_partials<2, V>(acc, K, part);
 }
@@ -649,24 +672,29 @@ __global__ __launch_bounds__(kBlock) void k_bpupdate(int64_t n, int K, TX *__res
                                                      const BCol *__restrict__ cols)
 {
     if (!any_column(cols, K, 1)) return;
-    const int64_t np = n * K / V;
-    PACK_LOOP(t, np)
+    const int j0 = thread_col0<V>(K);
+    bool mark[V], fresh[V];
+    TX beta[V];
+    bool any = false;
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        const BCol &s = cols[j0 + v];
+        mark[v] = s.mark != 0;
+        fresh[v] = s.fresh != 0;
+        beta[v] = (TX)s.beta;
+        any |= mark[v];
+    }
+    if (any) ROW_LOOP(e, i, n, K, V)
     {
-        const int64_t e = t * V;
-        const int64_t i = e / K;
-        const int j0 = (int)(e - i * K);
         auto pv = bld<V>(P, e);
         const auto rv = bld<V>(R, e);
         const TX d = (TX)dinv[i];
-        bool any = false;
 #pragma unroll
         for (int v = 0; v < V; ++v) {
-            const BCol &s = cols[j0 + v];
-            if (!s.mark) continue;
-            any = true;
-            pv.v[v] = s.fresh ? d * rv.v[v] : d * rv.v[v] + (TX)s.beta * pv.v[v];
+            if (!mark[v]) continue;
+            pv.v[v] = fresh[v] ? d * rv.v[v] : d * rv.v[v] + beta[v] * pv.v[v];
         }
-        if (any) bst<V>(P, e, pv);
+        bst<V>(P, e, pv);
     }
 }
 
