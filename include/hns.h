@@ -228,8 +228,15 @@ size_t hns_noalloc_scratch_bytes(void);
  * hns_solve).  X holds the initial guesses.  infos receives k entries
  * (outer_iterations = FP64 residual evaluations of the whole batch).
  * HNS_MIXED runs the FP32 recurrences with per-column FP64 residual
- * replacement as in hns_solve.  With "use_graph" = 1 the chunks of
- * "check_every" iterations are captured once into a HIP graph and replayed.
+ * replacement as in hns_solve.  The host reads the columns' state after
+ * chunks of at most "check_every" iterations: the first recurrence segment
+ * runs whole chunks (HNS_MIXED: 8, 16, ... iterations), later ones the
+ * longest segment so far plus 2
+ * (so a residual replacement follows soon after the columns reach their
+ * threshold), and a replacement waits up to 2 iterations for columns still
+ * running; the chunking does not change any column's arithmetic.  With
+ * "use_graph" = 1 each chunk length is captured once into a HIP graph (a few
+ * kept per workspace) and replayed.
  * The return value is the worst column status (negative first). */
 hns_status hns_solve_batched(hns_operator *op, int k, const int *mask_bits,
                              const double *B_dev, double *X_dev, double tol, int max_iter,

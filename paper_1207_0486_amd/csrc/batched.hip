@@ -1003,11 +1003,15 @@ struct BWorkspace {
     double *part = nullptr;  // 3 x kMaxGrid x K
     BCol *cols = nullptr;
     BCol *host = nullptr;    // pinned mirror
-    // captured iteration chunks: [mixed][V]
-    hipGraphExec_t graph = nullptr;
-    int graph_chunk = 0, graph_V = 0;
-    int graph_mixed = -1;              // precision the graph was captured for
-    const void *graph_X = nullptr;
+    // captured iteration chunks, keyed by chunk length, plan, precision and
+    // the solution block they update (a few kept, oldest dropped first)
+    struct ChunkGraph {
+        hipGraphExec_t exec = nullptr;
+        int chunk = 0, plan = 0, mixed = 0;
+        const void *X = nullptr;
+    };
+    static constexpr size_t kGraphs = 16;
+    std::vector<ChunkGraph> graphs;
 
     static size_t bytes_for(int64_t n, int K, bool mixed)
     {
@@ -1051,10 +1055,9 @@ struct BWorkspace {
 
     void drop_graph()
     {
-        if (graph) (void)hipGraphExecDestroy(graph);
-        graph = nullptr;
-        graph_chunk = 0;
-        graph_mixed = -1;
+        for (auto &g : graphs)
+            if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        graphs.clear();
     }
 
     ~BWorkspace()
@@ -1418,14 +1421,16 @@ hns_status enqueue_chunk(BCtx &c, Launcher &L, int count)
 hns_status run_chunk(BCtx &c, int count)
 {
     BWorkspace *w = c.w;
-    if (!c.op->use_graph || count != c.op->check_every) {
+    if (!c.op->use_graph) {
         Launcher L{c.s};
         return enqueue_chunk(c, L, count);
     }
     const int plan = c.V + 8 * c.tile;
-    if (!w->graph || w->graph_chunk != count || w->graph_V != plan || w->graph_X != c.X ||
-        w->graph_mixed != (int)c.mixed) {
-        w->drop_graph();
+    hipGraphExec_t exec = nullptr;
+    for (const auto &g : w->graphs)
+        if (g.chunk == count && g.plan == plan && g.X == c.X && g.mixed == (int)c.mixed)
+            exec = g.exec;
+    if (!exec) {
         hipGraph_t g = nullptr;
         HNS_TRY_HIP(hipGraphCreate(&g, 0));
         Launcher L;
@@ -1435,19 +1440,21 @@ hns_status run_chunk(BCtx &c, int count)
             (void)hipGraphDestroy(g);
             return st;
         }
-        hipError_t e = hipGraphInstantiate(&w->graph, g, nullptr, nullptr, 0);
+        hipError_t e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
         if (e != hipSuccess) {
-            w->graph = nullptr;
             set_error("graph instantiation failed: %s", hipGetErrorString(e));
             return HNS_ERR_HIP;
         }
-        w->graph_chunk = count;
-        w->graph_V = plan;
-        w->graph_X = c.X;
-        w->graph_mixed = (int)c.mixed;
+        if (w->graphs.size() >= BWorkspace::kGraphs) {
+            // drop the oldest once its replays have finished
+            HNS_TRY_HIP(hipStreamSynchronize(c.s));
+            (void)hipGraphExecDestroy(w->graphs.front().exec);
+            w->graphs.erase(w->graphs.begin());
+        }
+        w->graphs.push_back({exec, count, plan, (int)c.mixed, c.X});
     }
-    HNS_TRY_HIP(hipGraphLaunch(w->graph, c.s));
+    HNS_TRY_HIP(hipGraphLaunch(exec, c.s));
     return HNS_OK;
 }
 
@@ -1523,6 +1530,20 @@ hns_status solve_batched_impl(hns_operator *op, BWorkspace *w, int K, const int 
     HNS_TRY(pull(c));
     int segments = 1;
     std::vector<int> iter_at_break(K, -1);
+    // chunk length: check_every in the first segment (8, 16, ... up to it in
+    // mixed precision, whose segments end at a fixed FP32 residual drop, a
+    // few iterations), then the longest segment seen so far plus 2, so that
+    // a replacement follows soon after the columns reach their threshold (the
+    // launches of a chunk after every column has stopped return at once, but
+    // still cost a launch each); the columns' arithmetic does not depend on it
+    std::vector<int> seg_begin(K, 0);
+    int seg_longest = 0;
+    int grow = mixed ? std::min(8, op->check_every) : op->check_every;
+    // a replacement serves every column that is waiting for one and costs a
+    // product over the whole block (about two iterations): while other
+    // columns are still running it waits up to kGrace iterations for them
+    constexpr int kGrace = 2;
+    int waited = -1;   // iterations run since a column first waited, -1: none waits
     for (;;) {
         int active = 0, need = 0, maxit = 0;
         bool stuck = false;
@@ -1545,18 +1566,35 @@ hns_status solve_batched_impl(hns_operator *op, BWorkspace *w, int K, const int 
         if (stuck)  // host copy is current (nothing in flight): publish FAILED
             HNS_TRY_HIP(hipMemcpyAsync(w->cols, w->host, K * sizeof(BCol), hipMemcpyHostToDevice,
                                        s));
+        if (need > 0 && active > 0 && waited < kGrace && maxit < max_iter) {
+            const int extra = std::min(kGrace - std::max(waited, 0), max_iter - maxit);
+            HNS_TRY(run_chunk(c, extra));
+            HNS_TRY(pull(c));
+            waited = std::max(waited, 0) + extra;
+            continue;
+        }
         if (need > 0) {
+            waited = -1;
+            std::vector<int> restart;
+            for (int j = 0; j < K; ++j) {
+                const BCol &h = w->host[j];
+                if (h.stop == THRESH) seg_longest = std::max(seg_longest, h.iter - seg_begin[j]);
+                if (h.stop == THRESH || h.stop == BREAK) restart.push_back(j);
+            }
             // collect corrections, recompute the FP64 residual of those columns
             k_bmark<<<1, kBlock, 0, s>>>(K, w->cols, 0);
             if (mixed) k_baccumulate<<<G1, kBlock, 0, s>>>(n, K, X, w->X32, w->cols);
             HNS_TRY(true_residual(c, drop2, 0));
             HNS_TRY(new_segment(c));
             HNS_TRY(pull(c));
+            for (int j : restart) seg_begin[j] = w->host[j].iter;
             ++segments;
             continue;
         }
         if (active == 0 || maxit >= max_iter) break;
-        const int chunk = std::min(op->check_every, max_iter - maxit);
+        int per = seg_longest > 0 ? std::max(4, seg_longest + 2) : grow;
+        if (seg_longest == 0) grow = std::min(2 * grow, op->check_every);
+        const int chunk = std::min(std::min(op->check_every, per), max_iter - maxit);
         HNS_TRY(run_chunk(c, chunk));
         HNS_TRY(pull(c));
     }
