@@ -92,6 +92,19 @@ typedef struct {
                                 mesh is copied to the device for it; the transient
                                 device memory is about twice the mesh arrays
                                 (coordinates, tetrahedra, incidence lists)        */
+#define HNS_MATRIX_FREE 0x800u /* bricks only (hns_assemble_hex): no stored matrix;
+                                every product is computed element by element from
+                                the mesh (sum factorisation over the tensor Gauss
+                                points, trilinear geometry recomputed at each
+                                point), element results summed into each node in
+                                ascending element order (deterministic).  Only
+                                the diagonal (Jacobi), the lumped mass and the
+                                mesh are kept.  HNS_FP64 solves (point Jacobi or,
+                                for order 1, the line preconditioner), per-slot
+                                batch sessions and hns_apply; HNS_MIXED, block
+                                multi-right-hand-side solves, IC(0) and the
+                                allocation-free solve return HNS_ERR_INVALID.
+                                hns_operator_format reports HNS_MATRIX_FREE       */
 #define HNS_STEP_AUX  0x20u  /* also keep M, B_1..3, lumped mass, surface mass and
                                 the mesh (coordinates, tetrahedra, node incidence)
                                 for the step right-hand sides (hns_step_*)          */
@@ -161,7 +174,8 @@ typedef struct {
  * batched sessions, IC(0), mixed precision); the line preconditioner
  * (set_param "precond" = 1) is offered for order 1 on a column-contiguous
  * numbering.  Accepted options: HNS_KEEP_FP32, HNS_KEEP_HOST and a storage
- * format; HNS_GPU_ASSEMBLY and HNS_STEP_AUX are HNS_ERR_INVALID here.
+ * format, or HNS_MATRIX_FREE alone; HNS_GPU_ASSEMBLY and HNS_STEP_AUX are
+ * HNS_ERR_INVALID here.
  * Errors: HNS_ERR_INVALID (null/negative sizes, order not 1 or 2, non-finite
  * coefficients, unsupported flags), HNS_ERR_MESH (node index out of range,
  * non-finite coordinate, Jacobian determinant <= 0 at a quadrature point),

@@ -25,6 +25,7 @@ HNS_FMT_AUTO = 0x000
 HNS_FMT_CSR = 0x100
 HNS_FMT_SELL = 0x200
 HNS_FMT_SDIA = 0x400
+HNS_MATRIX_FREE = 0x800
 
 HNS_FP64 = 0
 HNS_MIXED = 1

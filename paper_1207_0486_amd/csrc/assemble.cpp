@@ -369,6 +369,9 @@ size_t DevMatrix::bytes() const
     } else if (fmt == HNS_FMT_CSR) {
         b += (size_t)(n + 1) * 4 + (size_t)nnz * 12;
         if (val32) b += (size_t)nnz * 4;
+    } else if (fmt == HNS_MATRIX_FREE) {
+        b += (size_t)mf_ne * (nloc() * 4 + 24 * 8) + (size_t)(n + 1) * 8 +
+             (size_t)mf_ne * nloc() * 4;
     } else {
         b += (size_t)(nslices + 1) * 4 + (size_t)sell_len * 12;
         if (sval32) b += (size_t)sell_len * 4;
@@ -378,12 +381,16 @@ size_t DevMatrix::bytes() const
 
 void DevMatrix::release()
 {
-    void *ptrs[] = {rowptr, col, val, val32, slice_ptr, scol, sval, sval32, dia, dia32};
+    void *ptrs[] = {rowptr, col,    val,     val32,     slice_ptr, scol,  sval,
+                    sval32, dia,    dia32,   mf_nodes,  mf_corner, mf_ptr, mf_ent};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     rowptr = col = slice_ptr = scol = nullptr;
     val = sval = dia = nullptr;
     val32 = sval32 = dia32 = nullptr;
+    mf_nodes = mf_ent = nullptr;
+    mf_corner = nullptr;
+    mf_ptr = nullptr;
 }
 
 // Offsets j - i of the upper triangle when the matrix is bitwise symmetric
@@ -783,6 +790,78 @@ hns_status assemble_hex_host(const hns_hex_mesh *mesh, double c_mass, double c_s
                   (long long)bad.load());
         return HNS_ERR_MESH;
     }
+    return HNS_OK;
+}
+
+hns_status upload_matrix_free(const hns_hex_mesh *mesh, double c_mass, double c_stiff,
+                              double nu_h, double nu_v, int64_t nnz, DevMatrix &d)
+{
+    const int p = mesh->order, q = p + 1, nloc = q * q * q;
+    const int64_t n = mesh->n_nodes, ne = mesh->n_hex;
+    if (ne * nloc >= (int64_t)INT32_MAX) {
+        set_error("matrix-free bricks: %lld element nodes exceed the int32 range",
+                  (long long)(ne * nloc));
+        return HNS_ERR_INVALID;
+    }
+    d.n = n;
+    d.nnz = nnz;
+    d.fmt = HNS_MATRIX_FREE;
+    d.mf_order = p;
+    d.mf_ne = ne;
+    d.mf_coef[0] = c_mass;
+    d.mf_coef[1] = c_stiff;
+    d.mf_coef[2] = nu_h;
+    d.mf_coef[3] = nu_h;
+    d.mf_coef[4] = nu_v;
+    // 1D tables at the Gauss points (the points and weights of brick_tables)
+    double gp[3] = {0, 0, 0};
+    if (p == 1) {
+        const double g = std::sqrt(1.0 / 3.0);
+        gp[0] = -g;
+        gp[1] = g;
+        d.mf_gw[0] = d.mf_gw[1] = 1.0;
+    } else {
+        const double g = std::sqrt(3.0 / 5.0);
+        gp[0] = -g;
+        gp[1] = 0.0;
+        gp[2] = g;
+        d.mf_gw[0] = d.mf_gw[2] = 5.0 / 9.0;
+        d.mf_gw[1] = 8.0 / 9.0;
+    }
+    for (int g = 0; g < q; ++g) {
+        double v[3], dv[3], lv[2], ld[2];
+        basis_1d(p, gp[g], v, dv);
+        basis_1d(1, gp[g], lv, ld);
+        for (int a = 0; a < q; ++a) {
+            d.mf_V[a][g] = v[a];
+            d.mf_D[a][g] = dv[a];
+        }
+        for (int a = 0; a < 2; ++a) {
+            d.mf_LV[a][g] = lv[a];
+            d.mf_LD[a][g] = ld[a];
+        }
+    }
+    // corners: local node (a, b, c) with a, b, c in {0, p}, corner index
+    // a' + 2 b' + 4 c' (a' = a / p)
+    std::vector<double> corner((size_t)ne * 24);
+    parallel_for(ne, [&](int64_t lo, int64_t hi) {
+        for (int64_t e = lo; e < hi; ++e) {
+            const int32_t *h = mesh->hex + e * nloc;
+            for (int c = 0; c < 8; ++c) {
+                const int l = (c & 1) * p + q * (((c >> 1) & 1) * p) + q * q * ((c >> 2) * p);
+                for (int r = 0; r < 3; ++r) corner[(size_t)e * 24 + 3 * c + r] =
+                    mesh->xyz[3 * (int64_t)h[l] + r];
+            }
+        }
+    });
+    Incidence inc = build_incidence(n, ne, nloc, mesh->hex);
+    std::vector<int32_t> ent(inc.tet.size());
+    for (size_t s2 = 0; s2 < ent.size(); ++s2) ent[s2] = inc.tet[s2] * nloc + inc.loc[s2];
+    std::vector<int32_t> nodes(mesh->hex, mesh->hex + ne * nloc);
+    HNS_TRY(upload(nodes, &d.mf_nodes));
+    HNS_TRY(upload(corner, &d.mf_corner));
+    HNS_TRY(upload(inc.ptr, &d.mf_ptr));
+    HNS_TRY(upload(ent, &d.mf_ent));
     return HNS_OK;
 }
 

@@ -1989,6 +1989,10 @@ hns_status hns_batch_open(hns_operator *op, int capacity, uint32_t mode, hns_bat
         set_error("hns_batch_open: bad arguments");
         return HNS_ERR_INVALID;
     }
+    if (op->A.fmt == HNS_MATRIX_FREE && (mode != HNS_FP64 || !slot_session_wanted(op, capacity))) {
+        set_error("hns_batch_open: a matrix-free operator serves HNS_FP64 per-slot sessions only");
+        return HNS_ERR_INVALID;
+    }
     *out = nullptr;
     hns_batch *bt = new hns_batch();
     bt->op = op;

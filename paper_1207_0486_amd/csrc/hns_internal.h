@@ -88,6 +88,26 @@ struct DevMatrix {
     int spmv_it64 = 1;
     int spmv_it32 = 2;
     int vec_it = 3;
+    // matrix-free bricks (fmt == HNS_MATRIX_FREE): the product is computed
+    // element by element; per element its (order+1)^3 nodes (mf_nodes) and
+    // its 8 corner coordinates (mf_corner, 24 doubles); per node the
+    // (element, local node) pairs that touch it, as element * nloc + local,
+    // in ascending element order (mf_ptr, n + 1; mf_ent); the coefficients
+    // of c_mass M + c_stiff K_nu and the 1D Gauss tables (host copies, kernel
+    // arguments)
+    int mf_order = 0;
+    int64_t mf_ne = 0;
+    int32_t *mf_nodes = nullptr;
+    double *mf_corner = nullptr;
+    int64_t *mf_ptr = nullptr;
+    int32_t *mf_ent = nullptr;
+    double mf_coef[5] = {0, 0, 0, 0, 0};   // c_mass, c_stiff, nu_x, nu_y, nu_z
+    double mf_gw[3] = {0, 0, 0};           // Gauss weights
+    double mf_V[3][3] = {}, mf_D[3][3] = {};   // basis a at point g: value, derivative
+    double mf_LV[2][3] = {}, mf_LD[2][3] = {}; // trilinear corner basis at point g
+    // doubles of per-product scratch (element outputs) a solve needs
+    size_t mf_scratch() const { return fmt == HNS_MATRIX_FREE ? (size_t)mf_ne * nloc() : 0; }
+    int nloc() const { return (mf_order + 1) * (mf_order + 1) * (mf_order + 1); }
 
     size_t bytes() const;
     void release();
@@ -282,6 +302,10 @@ uint32_t choose_format(const HostCSR &h);
 // of the basis functions (lumped)
 hns_status assemble_hex_host(const hns_hex_mesh *mesh, double c_mass, double c_stiff,
                              double nu_h, double nu_v, HostCSR &A, std::vector<double> *lumped);
+// The matrix-free form of the same operator on the device (fmt, order,
+// element nodes and corners, node -> element lists, coefficients, 1D tables)
+hns_status upload_matrix_free(const hns_hex_mesh *mesh, double c_mass, double c_stiff,
+                              double nu_h, double nu_v, int64_t nnz, DevMatrix &d);
 // node -> incident tetrahedra in ascending tetrahedron order (CSR), with the
 // node's local vertex number in each
 void tet_incidence(int64_t n, int64_t ntet, const int32_t *tets, std::vector<int64_t> &ptr,

@@ -83,6 +83,9 @@ struct IterArgs {
     // scaled vectors (x the correction D^1/2 dx of this segment, r = D^-1/2
     // r_A), dinv is not read, and wjac = diag(A) in FP32 weighs |r_A|^2
     const float *wjac = nullptr;
+    // matrix-free operators: the element results of one product
+    // (A->mf_scratch() doubles)
+    double *mf = nullptr;
 };
 
 // One CG iteration = three launches:
@@ -107,7 +110,8 @@ hns_status launch_cg_small(const IterArgs &a, int parity, int count, hipStream_t
 
 // q = mask(A p) without reductions (residuals and hns_apply)
 hns_status launch_spmv_plain(const DevMatrix &A, bool fp32, const void *p, void *q,
-                             const uint8_t *bc, int bit, hipStream_t s);
+                             const uint8_t *bc, int bit, hipStream_t s,
+                             double *mf_scratch = nullptr);
 // statistics of the free entries of b (sum, sum of squares, non-finite count)
 hns_status launch_bstats(int64_t n, const double *b, const uint8_t *bc, int bit, Scalars *sc,
                          double *partials, hipStream_t s);

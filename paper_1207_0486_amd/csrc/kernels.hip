@@ -1620,6 +1620,14 @@ hns_status check_launch(const char *what)
     return HNS_OK;
 }
 
+// A product that could not be launched: the HIP error if there is one, else
+// HNS_ERR_INVALID (the dispatcher has set the reason)
+static hns_status spmv_failed(const char *what)
+{
+    const hns_status st = check_launch(what);
+    return st != HNS_OK ? st : HNS_ERR_INVALID;
+}
+
 // Rows per block of the diagonal SpMV: R rows per lane (two for FP64
 // vectors), `it` workgroup-sized passes per block, more passes when the grid
 // would exceed the partials slots.
@@ -1687,11 +1695,283 @@ int sdia_dispatch(const DevMatrix &A, const TV *vals, const void *p, void *q, co
 // Launches q = A p (+ per-block partials of p^T q when DOT); returns the
 // grid, i.e. the number of partials written (-1 if the launch failed).
 // ev2: optional event pair recorded by the dispatch (kernel duration).
+// ---------------------------------------------------------------------------
+// Matrix-free bricks: y = (c_mass M + c_stiff K_nu) x element by element
+// (the forms of Sec. 5 on Q1 / Q2 bricks with the tensor Gauss rule of
+// order + 1 points per direction, the element the trilinear image of the
+// reference cube through its corners).  With u = sum_b N_b x_b,
+//   y_a = sum_g [ N_a(g) w det c_mass u(g)
+//                 + sum_s dN_a/ds_s(g) w c_stiff sum_d adj(J)_sd nu_d (grad u)_d ],
+// (grad u)_d = sum_s du/ds_s adj(J)_sd / det: the element matrix of the
+// assembled operator applied to x_e, evaluated by sum factorisation (the
+// tensor-product basis contracted one direction at a time, forward to the
+// Gauss points and back).  One thread per Gauss point / local node, an
+// element per (order+1)^3 lanes of a wavefront, the contractions through
+// LDS.  Element results go to a scratch array; a second kernel sums each
+// node's contributions in ascending element order (deterministic), zeroes
+// Dirichlet rows and forms the p^T q partials.
+// ---------------------------------------------------------------------------
+struct MfTables {
+    double V[3][3], D[3][3];     // basis a at point g: value, derivative
+    double LV[2][3], LD[2][3];   // trilinear corner basis
+    double gw[3];                // Gauss weights
+    double coef[5];              // c_mass, c_stiff, nu_x, nu_y, nu_z
+};
+
+template <int P>
+__global__ __launch_bounds__(kBlock) void k_mf_element(int64_t ne,
+                                                       const int32_t *__restrict__ nodes,
+                                                       const double *__restrict__ corner,
+                                                       const double *__restrict__ x, MfTables T,
+                                                       double *__restrict__ Y,
+                                                       const Scalars *__restrict__ sc)
+{
+    constexpr int Q = P + 1, NL = Q * Q * Q, EW = 64 / NL, EB = (kBlock / 64) * EW;
+    if (sc && sc->stop) return;
+    __shared__ double sV[3][3], sD[3][3], sLV[2][3], sLD[2][3], sW[3];
+    __shared__ double a0[EB][NL], a1[EB][NL], a2[EB][NL], a3[EB][NL];
+    __shared__ double b0[EB][NL], b1[EB][NL], b2[EB][NL];
+    __shared__ double sX[EB][24];
+    if (threadIdx.x < 9) {
+        sV[threadIdx.x / 3][threadIdx.x % 3] = T.V[threadIdx.x / 3][threadIdx.x % 3];
+        sD[threadIdx.x / 3][threadIdx.x % 3] = T.D[threadIdx.x / 3][threadIdx.x % 3];
+    } else if (threadIdx.x < 15) {
+        const int k = threadIdx.x - 9;
+        sLV[k / 3][k % 3] = T.LV[k / 3][k % 3];
+        sLD[k / 3][k % 3] = T.LD[k / 3][k % 3];
+    } else if (threadIdx.x < 18) {
+        sW[threadIdx.x - 15] = T.gw[threadIdx.x - 15];
+    }
+    const int lane = threadIdx.x & 63;
+    const int slot = lane / NL, t = lane - slot * NL;
+    const int es = (threadIdx.x >> 6) * EW + slot;   // element slot of the block
+    const bool on = slot < EW;
+    const int t0 = t % Q, t1 = (t / Q) % Q, t2 = t / (Q * Q);
+    const double cm = T.coef[0], cs = T.coef[1];
+    const double nu[3] = {T.coef[2], T.coef[3], T.coef[4]};
+    for (int64_t e0 = (int64_t)blockIdx.x * EB; e0 < ne; e0 += (int64_t)gridDim.x * EB) {
+        const int64_t e = e0 + es;
+        const bool act = on && e < ne;
+        // x at the element's nodes; its corners
+        if (act) {
+            a0[es][t] = x[nodes[e * NL + t]];
+            for (int k = t; k < 24; k += NL) sX[es][k] = corner[e * 24 + k];
+        }
+        __syncthreads();
+        // forward, direction 0: thread (g0 = t0, a1 = t1, a2 = t2)
+        if (act) {
+            double v = 0.0, d = 0.0;
+#pragma unroll
+            for (int a = 0; a < Q; ++a) {
+                const double xa = a0[es][a + Q * t1 + Q * Q * t2];
+                v += sV[a][t0] * xa;
+                d += sD[a][t0] * xa;
+            }
+            b0[es][t] = v;
+            b1[es][t] = d;
+        }
+        __syncthreads();
+        // direction 1: thread (g0, g1 = t1, a2)
+        if (act) {
+            double vv = 0.0, vd = 0.0, dv = 0.0;
+#pragma unroll
+            for (int a = 0; a < Q; ++a) {
+                const int k = t0 + Q * a + Q * Q * t2;
+                vv += sV[a][t1] * b0[es][k];
+                vd += sD[a][t1] * b0[es][k];
+                dv += sV[a][t1] * b1[es][k];
+            }
+            a1[es][t] = vv;
+            a2[es][t] = vd;
+            a3[es][t] = dv;
+        }
+        __syncthreads();
+        // direction 2, then the point's geometry and fluxes: thread g = t
+        if (act) {
+            double u = 0.0, us[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+            for (int a = 0; a < Q; ++a) {
+                const int k = t0 + Q * t1 + Q * Q * a;
+                u += sV[a][t2] * a1[es][k];
+                us[2] += sD[a][t2] * a1[es][k];
+                us[1] += sV[a][t2] * a2[es][k];
+                us[0] += sV[a][t2] * a3[es][k];
+            }
+            // J[r][d] = d x_r / d s_d from the 8 corners
+            double J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                const int c0 = c & 1, c1 = (c >> 1) & 1, c2 = c >> 2;
+                const double g0 = sLD[c0][t0] * sLV[c1][t1] * sLV[c2][t2];
+                const double g1 = sLV[c0][t0] * sLD[c1][t1] * sLV[c2][t2];
+                const double g2 = sLV[c0][t0] * sLV[c1][t1] * sLD[c2][t2];
+#pragma unroll
+                for (int r = 0; r < 3; ++r) {
+                    const double X = sX[es][3 * c + r];
+                    J[r][0] += X * g0;
+                    J[r][1] += X * g1;
+                    J[r][2] += X * g2;
+                }
+            }
+            double A[3][3];
+            A[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+            A[0][1] = J[0][2] * J[2][1] - J[0][1] * J[2][2];
+            A[0][2] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+            A[1][0] = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+            A[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+            A[1][2] = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+            A[2][0] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+            A[2][1] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
+            A[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+            const double det = J[0][0] * A[0][0] + J[0][1] * A[1][0] + J[0][2] * A[2][0];
+            const double w = sW[t0] * sW[t1] * sW[t2];
+            const double inv = 1.0 / det;
+            double f[3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+                f[d] = nu[d] * ((us[0] * A[0][d] + us[1] * A[1][d] + us[2] * A[2][d]) * inv);
+            // mass and reference fluxes at the point (arrays free since the
+            // forward pass of direction 1): M -> b0, F_0 -> b1, F_1 -> b2, F_2 -> a0
+            b0[es][t] = w * det * cm * u;
+            b1[es][t] = w * cs * (A[0][0] * f[0] + A[0][1] * f[1] + A[0][2] * f[2]);
+            b2[es][t] = w * cs * (A[1][0] * f[0] + A[1][1] * f[1] + A[1][2] * f[2]);
+            a0[es][t] = w * cs * (A[2][0] * f[0] + A[2][1] * f[1] + A[2][2] * f[2]);
+        }
+        __syncthreads();
+        // back, direction 2: thread (g0, g1, a2 = t2)
+        if (act) {
+            double ra = 0.0, rb = 0.0, rc = 0.0;
+#pragma unroll
+            for (int g = 0; g < Q; ++g) {
+                const int k = t0 + Q * t1 + Q * Q * g;
+                ra += sV[t2][g] * b0[es][k] + sD[t2][g] * a0[es][k];
+                rb += sV[t2][g] * b2[es][k];
+                rc += sV[t2][g] * b1[es][k];
+            }
+            a1[es][t] = ra;
+            a2[es][t] = rb;
+            a3[es][t] = rc;
+        }
+        __syncthreads();
+        // direction 1: thread (g0, a1 = t1, a2)
+        if (act) {
+            double sa = 0.0, sc2 = 0.0;
+#pragma unroll
+            for (int g = 0; g < Q; ++g) {
+                const int k = t0 + Q * g + Q * Q * t2;
+                sa += sV[t1][g] * a1[es][k] + sD[t1][g] * a2[es][k];
+                sc2 += sV[t1][g] * a3[es][k];
+            }
+            b0[es][t] = sa;
+            b1[es][t] = sc2;
+        }
+        __syncthreads();
+        // direction 0: thread (a0 = t0, a1, a2): the element's y at node t
+        if (act) {
+            double y = 0.0;
+#pragma unroll
+            for (int g = 0; g < Q; ++g) {
+                const int k = g + Q * t1 + Q * Q * t2;
+                y += sV[t0][g] * b0[es][k] + sD[t0][g] * b1[es][k];
+            }
+            Y[e * NL + t] = y;
+        }
+        __syncthreads();
+    }
+}
+
+// y_i = sum of node i's element results in ascending element order; zero on
+// Dirichlet rows; per-block partials of x^T y
+template <bool DOT>
+__global__ __launch_bounds__(kBlock) void k_mf_gather(int64_t n, const int64_t *__restrict__ ptr,
+                                                      const int32_t *__restrict__ ent,
+                                                      const double *__restrict__ Y,
+                                                      const double *__restrict__ x,
+                                                      double *__restrict__ y,
+                                                      const uint8_t *__restrict__ bc, int bit,
+                                                      const Scalars *__restrict__ sc,
+                                                      double *__restrict__ part)
+{
+    if constexpr (DOT) {
+        if (sc->stop) return;
+    }
+    double acc = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock) {
+        double s = 0.0;
+        for (int64_t k = ptr[i]; k < ptr[i + 1]; ++k) s += Y[ent[k]];
+        if (is_dirichlet(bc, bit, i)) s = 0.0;
+        y[i] = s;
+        if constexpr (DOT) acc += x[i] * s;
+    }
+    if constexpr (DOT) {
+        double v[1] = {acc};
+        store_block_partials<1>(v, part);
+    }
+}
+
+template <int P, bool DOT>
+int mf_launch_p(const DevMatrix &A, const double *x, double *y, const uint8_t *bc, int bit,
+                const Scalars *sc, double *part, double *scratch, hipStream_t s,
+                hipEvent_t *ev2)
+{
+    constexpr int NL = (P + 1) * (P + 1) * (P + 1), EB = (kBlock / 64) * (64 / NL);
+    MfTables T;
+    for (int a = 0; a < 3; ++a)
+        for (int g = 0; g < 3; ++g) {
+            T.V[a][g] = A.mf_V[a][g];
+            T.D[a][g] = A.mf_D[a][g];
+        }
+    for (int a = 0; a < 2; ++a)
+        for (int g = 0; g < 3; ++g) {
+            T.LV[a][g] = A.mf_LV[a][g];
+            T.LD[a][g] = A.mf_LD[a][g];
+        }
+    for (int g = 0; g < 3; ++g) T.gw[g] = A.mf_gw[g];
+    for (int k = 0; k < 5; ++k) T.coef[k] = A.mf_coef[k];
+    const int64_t blocks = (A.mf_ne + EB - 1) / EB;
+    const int Ge = (int)std::max<int64_t>(1, std::min<int64_t>(blocks, 65536));
+    const int Gg = stream_grid(A.n);
+    hipEvent_t e1[2] = {ev2 ? ev2[0] : nullptr, nullptr};
+    hipEvent_t e2[2] = {nullptr, ev2 ? ev2[1] : nullptr};
+    if (launch_k(k_mf_element<P>, Ge, kBlock, 0, s, ev2 ? e1 : nullptr, A.mf_ne,
+                 (const int32_t *)A.mf_nodes, (const double *)A.mf_corner, x, T, scratch,
+                 DOT ? sc : (const Scalars *)nullptr) != hipSuccess)
+        return -1;
+    if (launch_k(k_mf_gather<DOT>, Gg, kBlock, 0, s, ev2 ? e2 : nullptr, A.n,
+                 (const int64_t *)A.mf_ptr, (const int32_t *)A.mf_ent, (const double *)scratch,
+                 x, y, bc, bit, sc, part) != hipSuccess)
+        return -1;
+    return Gg;
+}
+
+// Matrix-free product (FP64 only); returns the number of partials, -1 on a
+// failed launch or without scratch.
+template <bool DOT>
+int mf_launch(const DevMatrix &A, const double *x, double *y, const uint8_t *bc, int bit,
+              const Scalars *sc, double *part, double *scratch, hipStream_t s, hipEvent_t *ev2)
+{
+    if (!scratch) {
+        set_error("matrix-free product without its element scratch");
+        return -1;
+    }
+    if (A.mf_order == 1) return mf_launch_p<1, DOT>(A, x, y, bc, bit, sc, part, scratch, s, ev2);
+    return mf_launch_p<2, DOT>(A, x, y, bc, bit, sc, part, scratch, s, ev2);
+}
+
 template <typename TV, typename TX, bool DOT>
 int spmv_dispatch(const DevMatrix &A, const void *p, void *q, const uint8_t *bc, int bit,
-                  const Scalars *sc, double *part, hipStream_t s, hipEvent_t *ev2 = nullptr)
+                  const Scalars *sc, double *part, hipStream_t s, hipEvent_t *ev2 = nullptr,
+                  double *mf_scratch = nullptr)
 {
     const bool f32 = std::is_same<TV, float>::value;
+    if (A.fmt == HNS_MATRIX_FREE) {
+        if constexpr (std::is_same<TV, double>::value && std::is_same<TX, double>::value)
+            return mf_launch<DOT>(A, (const double *)p, (double *)q, bc, bit, sc, part,
+                                  mf_scratch, s, ev2);
+        set_error("matrix-free operators compute FP64 products only");
+        return -1;
+    }
     if (A.fmt == HNS_FMT_SDIA) {
         const TV *vd = f32 ? (const TV *)(const void *)A.dia32 : (const TV *)(const void *)A.dia;
         return sdia_dispatch<TV, TX, DOT>(A, vd, p, q, bc, bit, sc, part, s, ev2);
@@ -1750,8 +2030,8 @@ hns_status line_iteration(const IterArgs &a, int parity, hipStream_t s, hipEvent
     const int NC = line_cols_per_block(L);
     const int Gl = line_grid(a.n, L);
     const int Gs = spmv_dispatch<T, T, true>(*a.A, a.p, a.q, bc, a.bit, a.sc, P1, s,
-                                             ev ? ev : nullptr);
-    if (Gs < 0) return check_launch("spmv");
+                                             ev ? ev : nullptr, a.mf);
+    if (Gs < 0) return spmv_failed("spmv");
     HNS_TRY_HIP(launch_k(k_update_line<T>, Gl, kBlock, (size_t)4 * NC * L * sizeof(T), s,
                          ev ? ev + 2 : nullptr, a.n, L, NC, (T *)a.r, (const T *)a.q, (T *)a.z,
                          (const T *)a.lfac, a.sc, (const double *)P1, Gs, P2, parity, a.token));
@@ -1787,8 +2067,8 @@ hns_status ic0_iteration(const IterArgs &a, int parity, hipStream_t s, hipEvent_
                      aligned16(a.z);
     const Chunks cu = chunks(vec ? a.n / 2 : a.n, (int64_t)kBlock * a.A->vec_it, kBlock);
     const int Gs = spmv_dispatch<double, double, true>(*a.A, a.p, a.q, bc, a.bit, a.sc, P1, s,
-                                                       ev ? ev : nullptr);
-    if (Gs < 0) return check_launch("spmv");
+                                                       ev ? ev : nullptr, a.mf);
+    if (Gs < 0) return spmv_failed("spmv");
     if (vec) {
         HNS_TRY_HIP(launch_k(k_update_noz<2>, cu.grid, kBlock, 0, s, ev ? ev + 2 : nullptr, a.n,
                              cu.per, (double *)a.r, (const double *)a.q, a.sc,
@@ -1822,8 +2102,8 @@ hns_status iteration_impl(const IterArgs &a, int parity, hipStream_t s, hipEvent
                      aligned16(a.dinv);
     const Chunks cu = chunks(vec ? a.n / V : a.n, (int64_t)kBlock * a.A->vec_it, kBlock);
     const int Gs = spmv_dispatch<TV, TX, true>(*a.A, a.p, a.q, bc, a.bit, a.sc, P1, s,
-                                               ev ? ev : nullptr);
-    if (Gs < 0) return check_launch("spmv");
+                                               ev ? ev : nullptr, a.mf);
+    if (Gs < 0) return spmv_failed("spmv");
     hipEvent_t *eu = ev ? ev + 2 : nullptr, *ep = ev ? ev + 4 : nullptr;
     if (vec) {
         HNS_TRY_HIP(launch_k(k_update<TX, TD, V>, cu.grid, kBlock, 0, s, eu, a.n, cu.per,
@@ -1861,8 +2141,8 @@ hns_status iteration_scaled(const IterArgs &a, int parity, hipStream_t s, hipEve
     }
     const Chunks cu = chunks(vec ? a.n / V : a.n, (int64_t)kBlock * a.A->vec_it, kBlock);
     const int Gs = spmv_dispatch<T, T, true>(*a.A, a.p, a.q, bc, a.bit, a.sc, P1, s,
-                                             ev ? ev : nullptr);
-    if (Gs < 0) return check_launch("spmv (Jacobi-scaled)");
+                                             ev ? ev : nullptr, a.mf);
+    if (Gs < 0) return spmv_failed("spmv (Jacobi-scaled)");
     hipEvent_t *eu = ev ? ev + 2 : nullptr, *ep = ev ? ev + 4 : nullptr;
     if (vec) {
         HNS_TRY_HIP(launch_k(k_update<T, float, V, true>, cu.grid, kBlock, 0, s, eu, a.n, cu.per,
@@ -1919,13 +2199,16 @@ Chunks chunks(int64_t units, int64_t per, int64_t quantum)
 }
 
 hns_status launch_spmv_plain(const DevMatrix &A, bool fp32, const void *p, void *q,
-                             const uint8_t *bc, int bit, hipStream_t s)
+                             const uint8_t *bc, int bit, hipStream_t s, double *mf_scratch)
 {
     if (bit < 0) bc = nullptr;
+    int G;
     if (fp32)
-        spmv_dispatch<float, float, false>(A, p, q, bc, bit, nullptr, nullptr, s);
+        G = spmv_dispatch<float, float, false>(A, p, q, bc, bit, nullptr, nullptr, s);
     else
-        spmv_dispatch<double, double, false>(A, p, q, bc, bit, nullptr, nullptr, s);
+        G = spmv_dispatch<double, double, false>(A, p, q, bc, bit, nullptr, nullptr, s, nullptr,
+                                                 mf_scratch);
+    if (G < 0 && A.fmt == HNS_MATRIX_FREE) return HNS_ERR_INVALID;   // the reason is set
     return check_launch("spmv");
 }
 

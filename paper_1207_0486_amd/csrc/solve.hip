@@ -41,6 +41,7 @@ struct Workspace {
     double *partials = nullptr;   // kPartTotal doubles
     double *z = nullptr;          // M^-1 r of the line / IC(0) preconditioner (on first use)
     double *y = nullptr;          // scratch of the IC(0) triangular solves (on first use)
+    double *mf = nullptr;         // element results of a matrix-free product (on first use)
     Scalars *sc = nullptr;        // [0] FP64 / outer loop, [1] inner FP32 loop
     Scalars *host = nullptr;      // pinned mirror of sc[0..1]
     std::vector<hipEvent_t> ev;   // timing events, a (start, end) pair per kernel of an iteration
@@ -143,12 +144,26 @@ struct Workspace {
         return HNS_OK;
     }
 
+    hns_status ensure_mf(size_t count)
+    {
+        if (mf || count == 0) return HNS_OK;
+        hipError_t e = hipMalloc(&mf, count * sizeof(double));
+        if (e != hipSuccess) {
+            mf = nullptr;
+            set_error("allocation of the matrix-free element results failed: %s",
+                      hipGetErrorString(e));
+            return e == hipErrorOutOfMemory ? HNS_ERR_OOM : HNS_ERR_HIP;
+        }
+        return HNS_OK;
+    }
+
     ~Workspace()
     {
         for (hipEvent_t e : ev) (void)hipEventDestroy(e);
         if (borrowed) return;
         if (z) (void)hipFree(z);
         if (y) (void)hipFree(y);
+        if (mf) (void)hipFree(mf);
         if (block) (void)hipFree(block);
         if (host) (void)hipHostFree(host);
     }
@@ -156,21 +171,30 @@ struct Workspace {
 
 static hns_status acquire_ws(hns_operator *op, bool mixed, Workspace **out)
 {
+    Workspace *w = nullptr;
     {
         std::lock_guard<std::mutex> g(op->ws_mutex);
         for (size_t i = 0; i < op->ws_free.size(); ++i) {
-            Workspace *w = op->ws_free[i];
-            if (w->mixed || !mixed) {
+            if (op->ws_free[i]->mixed || !mixed) {
+                w = op->ws_free[i];
                 op->ws_free.erase(op->ws_free.begin() + i);
-                *out = w;
-                return HNS_OK;
+                break;
             }
         }
     }
-    Workspace *w = new Workspace();
-    hns_status st = w->allocate(op->n, mixed);
+    if (!w) {
+        w = new Workspace();
+        hns_status st = w->allocate(op->n, mixed);
+        if (st != HNS_OK) {
+            delete w;
+            return st;
+        }
+    }
+    // a matrix-free operator's products need their element scratch
+    hns_status st = w->ensure_mf(op->A.mf_scratch());
     if (st != HNS_OK) {
-        delete w;
+        std::lock_guard<std::mutex> g(op->ws_mutex);
+        op->ws_free.push_back(w);
         return st;
     }
     *out = w;
@@ -238,6 +262,7 @@ static hns_status enqueue_iterations(hns_operator *op, Workspace *w, Prec prec, 
     const int period = w->borrowed ? 0 : op->profile;
     if (period > 0) HNS_TRY(w->ensure_events(6 * (size_t)count));
     IterArgs a{&op->A, prec, op->n, x, r, p, q, dinv, op->bc, bit, sc, w->partials};
+    a.mf = w->mf;
     if (scaled) {
         a.A = &op->S;
         a.dinv = nullptr;
@@ -256,7 +281,7 @@ static hns_status enqueue_iterations(hns_operator *op, Workspace *w, Prec prec, 
     // latency-bound sizes: the whole chunk in one workgroup (point Jacobi,
     // FP64 or FP32, not while per-kernel timing is on)
     if (!lfac && !ic && !scaled && period <= 0 && op->n <= op->small_n &&
-        (prec == Prec::F64 || prec == Prec::F32))
+        op->A.fmt != HNS_MATRIX_FREE && (prec == Prec::F64 || prec == Prec::F32))
         return launch_cg_small(a, parity0, count, s);
     // sampled: the iteration in the middle of each period window, so a chunk's
     // first iteration (launched after the host's read of the previous chunk,
@@ -321,7 +346,7 @@ static hns_status true_residual_fp64(const SolveCtx &c)
 {
     hns_operator *op = c.op;
     Workspace *w = c.w;
-    HNS_TRY(launch_spmv_plain(op->A, false, c.x, w->q, op->bc, c.bit, c.s));
+    HNS_TRY(launch_spmv_plain(op->A, false, c.x, w->q, op->bc, c.bit, c.s, w->mf));
     HNS_TRY(launch_residual(op->n, c.b, w->q, w->r, op->bc, c.bit, c.singular, w->sc,
                             w->partials, c.s));
     HNS_TRY(launch_project_norm(op->n, w->r, c.singular, w->sc, w->partials, c.s));
@@ -837,7 +862,8 @@ static bool session_line(const hns_operator *op)
 size_t slot_session_bytes(const hns_operator *op, int capacity, bool mixed)
 {
     const size_t n = (size_t)op->n;
-    size_t per = Workspace::bytes_for(op->n, mixed) + 2 * ((n + 31) & ~size_t(31)) * sizeof(double);
+    size_t per = Workspace::bytes_for(op->n, mixed) + 2 * ((n + 31) & ~size_t(31)) * sizeof(double) +
+                 op->A.mf_scratch() * sizeof(double);
     if (session_line(op))
         per += n * sizeof(double);                                          // z
     else if (session_scaled(op, mixed) && !mixed)
@@ -888,6 +914,7 @@ hns_status slot_session_open(hns_operator *op, int capacity, bool mixed, SlotSes
         sl.w = new Workspace();
         hns_status st = sl.w->allocate(op->n, mixed);
         if (st == HNS_OK && (ss->line || (ss->scaled && !mixed))) st = sl.w->ensure_z();
+        if (st == HNS_OK) st = sl.w->ensure_mf(op->A.mf_scratch());
         if (st != HNS_OK) return fail(st);
     }
     *out = ss;
@@ -1108,12 +1135,34 @@ static hns_status finish_device_operator(hns_operator *op, const hns_mesh *mesh)
     return HNS_OK;
 }
 
+static hns_status finish_diagonal(hns_operator *op, const HostCSR &A,
+                                  const std::vector<double> &lumped, const uint8_t *bc_host);
+
 static hns_status finish_operator(hns_operator *op, const HostCSR &A, uint32_t fmt_flag,
                                   const std::vector<double> &lumped, const uint8_t *bc_host)
 {
     const bool keep32 = (op->flags & HNS_KEEP_FP32) != 0;
     uint32_t fmt = fmt_flag ? fmt_flag : choose_format(A);
     HNS_TRY(upload_matrix(A, fmt, keep32, op->A));
+    return finish_diagonal(op, A, lumped, bc_host);
+}
+
+// A brick operator without a stored matrix: the element data of the
+// matrix-free product, and the diagonal and lumped mass of the assembled one
+static hns_status finish_matrix_free(hns_operator *op, const hns_hex_mesh *mesh, const HostCSR &A,
+                                     double c_mass, double c_stiff,
+                                     const std::vector<double> &lumped)
+{
+    HNS_TRY(upload_matrix_free(mesh, c_mass, c_stiff, op->nu_h, op->nu_v, A.nnz(), op->A));
+    return finish_diagonal(op, A, lumped, mesh->bc);
+}
+
+// D^-1 (and its FP32 copy with HNS_KEEP_FP32), the Dirichlet bits and the
+// lumped mass of an assembled matrix, uploaded
+static hns_status finish_diagonal(hns_operator *op, const HostCSR &A,
+                                  const std::vector<double> &lumped, const uint8_t *bc_host)
+{
+    const bool keep32 = (op->flags & HNS_KEEP_FP32) != 0;
     // Jacobi: inverse diagonal
     std::vector<double> dinv(A.n, 0.0);
     for (int64_t i = 0; i < A.n; ++i) {
@@ -1229,6 +1278,10 @@ hns_status hns_assemble(const hns_mesh *mesh, double nu_h, double nu_v, double d
         set_error("choose one storage format");
         return HNS_ERR_INVALID;
     }
+    if (flags & HNS_MATRIX_FREE) {
+        set_error("HNS_MATRIX_FREE is offered for brick elements (hns_assemble_hex) only");
+        return HNS_ERR_INVALID;
+    }
     hns_operator *op = new hns_operator();
     (void)hipGetDevice(&op->device);
     op->flags = flags;
@@ -1301,6 +1354,12 @@ hns_status hns_assemble_hex(const hns_hex_mesh *mesh, double nu_h, double nu_v, 
         set_error("HNS_GPU_ASSEMBLY and HNS_STEP_AUX are not available for brick elements");
         return HNS_ERR_INVALID;
     }
+    const bool mfree = (flags & HNS_MATRIX_FREE) != 0;
+    if (mfree && (flags & (HNS_KEEP_FP32 | HNS_KEEP_HOST | HNS_FMT_CSR | HNS_FMT_SELL |
+                           HNS_FMT_SDIA))) {
+        set_error("HNS_MATRIX_FREE takes no storage format, HNS_KEEP_FP32 or HNS_KEEP_HOST");
+        return HNS_ERR_INVALID;
+    }
     if (!std::isfinite(nu_h) || !std::isfinite(nu_v) || !std::isfinite(dt) || nu_h < 0 ||
         nu_v < 0) {
         set_error("viscosities must be finite and non-negative, dt finite");
@@ -1325,7 +1384,8 @@ hns_status hns_assemble_hex(const hns_hex_mesh *mesh, double nu_h, double nu_v, 
     hns_status st = assemble_hex_host(mesh, c_mass, c_stiff, nu_h, nu_v, A, &lumped);
     if (st == HNS_OK) {
         op->n = A.n;
-        st = finish_operator(op, A, fmt, lumped, mesh->bc);
+        st = mfree ? finish_matrix_free(op, mesh, A, c_mass, c_stiff, lumped)
+                   : finish_operator(op, A, fmt, lumped, mesh->bc);
     }
     if (st == HNS_OK) {
         // Q1 column blocks are tridiagonal (vertical neighbours only); the Q2
@@ -1492,6 +1552,7 @@ size_t hns_footprint_bytes(const hns_operator *op, int k, uint32_t mode, int inc
     size_t b = k == 1 ? Workspace::bytes_for(op->n, mixed) : bworkspace_bytes(op->n, k, mixed);
     if (k == 1 && op->precond == 1) b += (size_t)op->n * sizeof(double);       // z
     if (k == 1 && op->precond == 2) b += 2 * (size_t)op->n * sizeof(double);   // z, y
+    if (k == 1) b += op->A.mf_scratch() * sizeof(double);   // matrix-free element results
     if (include_operator) {
         for (const double *f : op->line_fac)
             if (f) b += 2 * (size_t)op->n * sizeof(double);
@@ -1533,6 +1594,10 @@ static hns_status check_solve_args(hns_operator *op, int mask_bit, const void *b
     }
     if (mode != HNS_FP64 && mode != HNS_MIXED) {
         set_error("unknown mode %u", mode);
+        return HNS_ERR_INVALID;
+    }
+    if (mode == HNS_MIXED && op->A.fmt == HNS_MATRIX_FREE) {
+        set_error("matrix-free operators run HNS_FP64 solves only");
         return HNS_ERR_INVALID;
     }
     if (mode == HNS_MIXED && !op->dinv32) {
@@ -1760,6 +1825,10 @@ hns_status hns_solve_noalloc(hns_operator *op, int mask_bit, const double *b_dev
                   "other preconditioners build factors on first use");
         st = HNS_ERR_INVALID;
     }
+    if (st == HNS_OK && op->A.fmt == HNS_MATRIX_FREE) {
+        set_error("hns_solve_noalloc: matrix-free operators need their element scratch");
+        st = HNS_ERR_INVALID;
+    }
     if (st == HNS_OK && op->bad_diag >= 0) {
         set_error("diagonal entry %lld is not positive: Jacobi-PCG needs an SPD operator",
                   (long long)op->bad_diag);
@@ -1886,6 +1955,18 @@ hns_status hns_apply(hns_operator *op, int mask_bit, const double *x_dev, double
         set_error("hns_apply: bad arguments");
         return HNS_ERR_INVALID;
     }
+    if (op->A.fmt == HNS_MATRIX_FREE) {   // element scratch from the workspace pool
+        Workspace *w = nullptr;
+        HNS_TRY(acquire_ws(op, false, &w));
+        hns_status st = launch_spmv_plain(op->A, false, x_dev, y_dev, op->bc, mask_bit,
+                                          (hipStream_t)stream, w->mf);
+        if (st == HNS_OK && hipStreamSynchronize((hipStream_t)stream) != hipSuccess) {
+            set_error("hns_apply: the product failed on the device");
+            st = HNS_ERR_HIP;
+        }
+        release_ws(op, w);
+        return st;
+    }
     HNS_TRY(launch_spmv_plain(op->A, false, x_dev, y_dev, op->bc, mask_bit, (hipStream_t)stream));
     HNS_TRY_HIP(hipStreamSynchronize((hipStream_t)stream));
     return HNS_OK;
@@ -1942,6 +2023,10 @@ hns_status hns_solve_batched(hns_operator *op, int k, const int *mask_bits, cons
         set_error("multi-right-hand-side solves use the point Jacobi preconditioner only");
         return HNS_ERR_INVALID;
     }
+    if (op->A.fmt == HNS_MATRIX_FREE) {
+        set_error("multi-right-hand-side solves need a stored matrix (not HNS_MATRIX_FREE)");
+        return HNS_ERR_INVALID;
+    }
     if (op->bad_diag >= 0) {
         set_error("diagonal entry %lld is not positive: Jacobi-PCG needs an SPD operator",
                   (long long)op->bad_diag);
@@ -1967,6 +2052,10 @@ hns_status hns_tune_batched(hns_operator *op, int k, uint32_t mode, void *stream
     if (!op || !times_us || !best_plan || k < 1 || k > 1024 ||
         (mode != HNS_FP64 && mode != HNS_MIXED) || (mode == HNS_MIXED && !op->dinv32)) {
         set_error("hns_tune_batched: bad arguments");
+        return HNS_ERR_INVALID;
+    }
+    if (op->A.fmt == HNS_MATRIX_FREE) {
+        set_error("hns_tune_batched: matrix-free operators have no batched product");
         return HNS_ERR_INVALID;
     }
     const bool mixed = (mode == HNS_MIXED);

@@ -17,7 +17,8 @@ from . import _lib as L
 KINDS = {"poisson": L.HNS_POISSON, "helmholtz": L.HNS_HELMHOLTZ}
 FORMATS = {"auto": L.HNS_FMT_AUTO, "csr": L.HNS_FMT_CSR, "sell": L.HNS_FMT_SELL,
            "sdia": L.HNS_FMT_SDIA}
-FORMAT_NAMES = {L.HNS_FMT_CSR: "csr", L.HNS_FMT_SELL: "sell", L.HNS_FMT_SDIA: "sdia"}
+FORMAT_NAMES = {L.HNS_FMT_CSR: "csr", L.HNS_FMT_SELL: "sell", L.HNS_FMT_SDIA: "sdia",
+                L.HNS_MATRIX_FREE: "matrix-free"}
 MODES = {"fp64": L.HNS_FP64, "mixed": L.HNS_MIXED}
 
 
@@ -78,16 +79,19 @@ class Operator:
     `mesh` is any object with xyz (n,3) float64, tets (T,4) int32, bc (n,)
     uint8 (optional) and surf_tris (S,3) int32 (optional); or a brick mesh
     with xyz, hexes (E,(order+1)**3) int32, order (1: Q1, 2: Q2) and bc
-    (hns_assemble_hex).
+    (hns_assemble_hex; matrix_free=True: no stored matrix, element-by-element
+    products, FP64 solves only).
     """
 
     def __init__(self, mesh, nu_h: float, nu_v: float, dt: float = 0.0, kind: str = "helmholtz",
                  keep_fp32: bool = False, step_aux: bool = False, fmt: str = "auto",
                  device: int | torch.device | None = None, gpu_assembly: bool = False,
-                 keep_host: bool = False):
+                 keep_host: bool = False, matrix_free: bool = False):
         self._h = None
         self.kind = kind
         flags = KINDS[kind] | FORMATS[fmt]
+        if matrix_free:
+            flags |= L.HNS_MATRIX_FREE
         if keep_fp32:
             flags |= L.HNS_KEEP_FP32
         if step_aux:
