@@ -47,6 +47,14 @@ def matrix_bytes(fmt, n, nnz, value_bytes, unit=False):
     return (value_bytes + 4) * nnz + 4 * (n + 1)
 
 
+def mf_product_bytes(n, ne, nloc):
+    """One matrix-free brick product: per element its node indices and 8
+    corners (24 doubles), its nloc results written to the scratch and read
+    back by the node gather with their (element, local) indices; per node the
+    list start, p read and q written."""
+    return ne * (4 * nloc + 8 * 24) + ne * nloc * (8 + 8 + 4) + 8 * (n + 1) + 16 * n
+
+
 def bytes_iter(fmt, n, nnz, vb):
     """One point-Jacobi CG iteration: one operator read plus 12 vector passes
     (SpMV reads p and writes q; the update reads r, q, D^-1 and writes r; the
@@ -574,6 +582,8 @@ def bench_bricks(torch, log, reps=3):
     cases = (
         ("q2_velocity_128x128x10", 2, (128, 128, 10), "helmholtz", (wl.nu_h, wl.nu_v), 0, 0,
          1e-10),
+        ("q2_velocity_matrix_free_128x128x10", 2, (128, 128, 10), "helmholtz",
+         (wl.nu_h, wl.nu_v), 0, 0, 1e-10),
         ("q1_pressure_128x128x10", 1, (128, 128, 10), "poisson", (wl.nu_h, wl.nu_v), -1, 0,
          1e-10),
         ("q1_pressure_256x256x20", 1, (256, 256, 20), "poisson", (wl.nu_h, wl.nu_v), -1, 0,
@@ -586,7 +596,9 @@ def bench_bricks(torch, log, reps=3):
         m = basin.basin_hex_mesh(Nx, Ny, Nz, order, L=wl.L, seed=wl.seed)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        op = Operator(m, nu[0], nu[1], wl.dt if kind == "helmholtz" else 0.0, kind=kind)
+        mfree = "matrix_free" in name
+        op = Operator(m, nu[0], nu[1], wl.dt if kind == "helmholtz" else 0.0, kind=kind,
+                      matrix_free=mfree)
         torch.cuda.synchronize()
         setup_s = time.perf_counter() - t0
         op.set_param("precond", precond)
@@ -605,17 +617,29 @@ def bench_bricks(torch, log, reps=3):
             torch.cuda.synchronize()
             el = time.perf_counter() - t
             best = el if best is None else min(best, el)
+        # the product's own time (kernel events on every iteration of one solve)
+        op.profile(1)
+        op.solve(b, torch.zeros_like(b), tol=tol, mask_bit=bit, check=False)
+        prof = op.profile_read()
+        op.profile(0)
+        product_us = 1e3 * prof["spmv"][0] / max(prof["spmv"][1], 1)
         scaled = precond == 0 and jacobi_scaled(op)
-        if scaled:   # bytes the Jacobi-scaled recurrence moves
+        if mfree:   # element data, the element results written and gathered, p and q
+            ne = m.hexes.shape[0]
+            prod = mf_product_bytes(op.n, ne, m.hexes.shape[1])
+            vec = 10 * 8 * op.n
+            by = by_stored = info.iterations * (prod + vec)
+        elif scaled:   # bytes the Jacobi-scaled recurrence moves
             by = info.iterations * bytes_iter_scaled(op.n, op.nnz, 8)
             vec = 10 * 8 * op.n + 4 * op.n
         else:
             vec = (12 if precond == 0 else 13) * 8 * op.n
             by = info.iterations * (matrix_bytes(op.format, op.n, op.nnz, 8) + vec)
-        # diagonal storage also reads the zeros it stores where a row lacks an offset
-        stored = ((op.ndiag + (0 if scaled else 1)) * op.n * 8 if op.format == "sdia"
-                  else matrix_bytes(op.format, op.n, op.nnz, 8))
-        by_stored = info.iterations * (stored + vec)
+        if not mfree:
+            # diagonal storage also reads the zeros it stores where a row lacks an offset
+            stored = ((op.ndiag + (0 if scaled else 1)) * op.n * 8 if op.format == "sdia"
+                      else matrix_bytes(op.format, op.n, op.nnz, 8))
+            by_stored = info.iterations * (stored + vec)
         out[name] = {"order": order, "bricks": [Nx, Ny, Nz], "nodes": op.n, "nnz": op.nnz,
                      "format": op.format, "ndiag": op.ndiag, "nu": list(nu),
                      "precond": ["jacobi", "line"][precond], "jacobi_scaled": scaled,
@@ -623,6 +647,7 @@ def bench_bricks(torch, log, reps=3):
                      "status": info.status, "relres": float("%.3g" % info.relres_true),
                      "ms": round(1e3 * best, 3),
                      "us_per_iter": round(1e6 * best / max(info.iterations, 1), 2),
+                     "product_us": round(product_us, 2),
                      "GBs": round(by / best / 1e9, 1),
                      "GBs_stored": round(by_stored / best / 1e9, 1)}
         log(f"bricks {name}: {out[name]}")

@@ -382,13 +382,13 @@ size_t DevMatrix::bytes() const
 void DevMatrix::release()
 {
     void *ptrs[] = {rowptr, col,    val,     val32,     slice_ptr, scol,  sval,
-                    sval32, dia,    dia32,   mf_nodes,  mf_corner, mf_ptr, mf_ent};
+                    sval32, dia,    dia32,   mf_nodes,  mf_corner, mf_ptr, mf_pos};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     rowptr = col = slice_ptr = scol = nullptr;
     val = sval = dia = nullptr;
     val32 = sval32 = dia32 = nullptr;
-    mf_nodes = mf_ent = nullptr;
+    mf_nodes = mf_pos = nullptr;
     mf_corner = nullptr;
     mf_ptr = nullptr;
 }
@@ -854,14 +854,16 @@ hns_status upload_matrix_free(const hns_hex_mesh *mesh, double c_mass, double c_
             }
         }
     });
+    // node i's (element, local node) pairs in ascending element order at
+    // positions ptr[i] .. ptr[i+1]; pos[e nloc + a] = the position of (e, a)
     Incidence inc = build_incidence(n, ne, nloc, mesh->hex);
-    std::vector<int32_t> ent(inc.tet.size());
-    for (size_t s2 = 0; s2 < ent.size(); ++s2) ent[s2] = inc.tet[s2] * nloc + inc.loc[s2];
+    std::vector<int32_t> pos(inc.tet.size());
+    for (size_t k = 0; k < pos.size(); ++k) pos[(size_t)inc.tet[k] * nloc + inc.loc[k]] = (int32_t)k;
     std::vector<int32_t> nodes(mesh->hex, mesh->hex + ne * nloc);
     HNS_TRY(upload(nodes, &d.mf_nodes));
     HNS_TRY(upload(corner, &d.mf_corner));
     HNS_TRY(upload(inc.ptr, &d.mf_ptr));
-    HNS_TRY(upload(ent, &d.mf_ent));
+    HNS_TRY(upload(pos, &d.mf_pos));
     return HNS_OK;
 }
 

@@ -90,17 +90,17 @@ struct DevMatrix {
     int vec_it = 3;
     // matrix-free bricks (fmt == HNS_MATRIX_FREE): the product is computed
     // element by element; per element its (order+1)^3 nodes (mf_nodes) and
-    // its 8 corner coordinates (mf_corner, 24 doubles); per node the
-    // (element, local node) pairs that touch it, as element * nloc + local,
-    // in ascending element order (mf_ptr, n + 1; mf_ent); the coefficients
-    // of c_mass M + c_stiff K_nu and the 1D Gauss tables (host copies, kernel
-    // arguments)
+    // its 8 corner coordinates (mf_corner, 24 doubles); the (element, local
+    // node) pairs that touch node i take positions mf_ptr[i] .. mf_ptr[i+1]
+    // of the scratch, in ascending element order, and mf_pos[e nloc + a] is
+    // the position of pair (e, a); the coefficients of c_mass M + c_stiff
+    // K_nu and the 1D Gauss tables (host copies, kernel arguments)
     int mf_order = 0;
     int64_t mf_ne = 0;
     int32_t *mf_nodes = nullptr;
     double *mf_corner = nullptr;
     int64_t *mf_ptr = nullptr;
-    int32_t *mf_ent = nullptr;
+    int32_t *mf_pos = nullptr;
     double mf_coef[5] = {0, 0, 0, 0, 0};   // c_mass, c_stiff, nu_x, nu_y, nu_z
     double mf_gw[3] = {0, 0, 0};           // Gauss weights
     double mf_V[3][3] = {}, mf_D[3][3] = {};   // basis a at point g: value, derivative

@@ -1707,9 +1707,10 @@ int sdia_dispatch(const DevMatrix &A, const TV *vals, const void *p, void *q, co
 // tensor-product basis contracted one direction at a time, forward to the
 // Gauss points and back).  One thread per Gauss point / local node, an
 // element per (order+1)^3 lanes of a wavefront, the contractions through
-// LDS.  Element results go to a scratch array; a second kernel sums each
-// node's contributions in ascending element order (deterministic), zeroes
-// Dirichlet rows and forms the p^T q partials.
+// LDS.  Element results go to a scratch array at node-ordered positions (a
+// node's contributions contiguous, in ascending element order); a second
+// kernel sums each node's run (deterministic), zeroes Dirichlet rows and
+// forms the p^T q partials.
 // ---------------------------------------------------------------------------
 struct MfTables {
     double V[3][3], D[3][3];     // basis a at point g: value, derivative
@@ -1718,10 +1719,21 @@ struct MfTables {
     double coef[5];              // c_mass, c_stiff, nu_x, nu_y, nu_z
 };
 
+// Exchange through LDS between the lanes of one wavefront: its LDS
+// operations complete in program order, so only the compiler must keep the
+// reads after the writes (no workgroup barrier).
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <int P>
 __global__ __launch_bounds__(kBlock) void k_mf_element(int64_t ne,
                                                        const int32_t *__restrict__ nodes,
                                                        const double *__restrict__ corner,
+                                                       const int32_t *__restrict__ pos,
                                                        const double *__restrict__ x, MfTables T,
                                                        double *__restrict__ Y,
                                                        const Scalars *__restrict__ sc)
@@ -1749,6 +1761,7 @@ __global__ __launch_bounds__(kBlock) void k_mf_element(int64_t ne,
     const int t0 = t % Q, t1 = (t / Q) % Q, t2 = t / (Q * Q);
     const double cm = T.coef[0], cs = T.coef[1];
     const double nu[3] = {T.coef[2], T.coef[3], T.coef[4]};
+    __syncthreads();   // the tables; below, every element lives in one wavefront
     for (int64_t e0 = (int64_t)blockIdx.x * EB; e0 < ne; e0 += (int64_t)gridDim.x * EB) {
         const int64_t e = e0 + es;
         const bool act = on && e < ne;
@@ -1757,7 +1770,7 @@ __global__ __launch_bounds__(kBlock) void k_mf_element(int64_t ne,
             a0[es][t] = x[nodes[e * NL + t]];
             for (int k = t; k < 24; k += NL) sX[es][k] = corner[e * 24 + k];
         }
-        __syncthreads();
+        wave_lds_sync();
         // forward, direction 0: thread (g0 = t0, a1 = t1, a2 = t2)
         if (act) {
             double v = 0.0, d = 0.0;
@@ -1770,7 +1783,7 @@ __global__ __launch_bounds__(kBlock) void k_mf_element(int64_t ne,
             b0[es][t] = v;
             b1[es][t] = d;
         }
-        __syncthreads();
+        wave_lds_sync();
         // direction 1: thread (g0, g1 = t1, a2)
         if (act) {
             double vv = 0.0, vd = 0.0, dv = 0.0;
@@ -1785,7 +1798,7 @@ __global__ __launch_bounds__(kBlock) void k_mf_element(int64_t ne,
             a2[es][t] = vd;
             a3[es][t] = dv;
         }
-        __syncthreads();
+        wave_lds_sync();
         // direction 2, then the point's geometry and fluxes: thread g = t
         if (act) {
             double u = 0.0, us[3] = {0.0, 0.0, 0.0};
@@ -1837,7 +1850,7 @@ __global__ __launch_bounds__(kBlock) void k_mf_element(int64_t ne,
             b2[es][t] = w * cs * (A[1][0] * f[0] + A[1][1] * f[1] + A[1][2] * f[2]);
             a0[es][t] = w * cs * (A[2][0] * f[0] + A[2][1] * f[1] + A[2][2] * f[2]);
         }
-        __syncthreads();
+        wave_lds_sync();
         // back, direction 2: thread (g0, g1, a2 = t2)
         if (act) {
             double ra = 0.0, rb = 0.0, rc = 0.0;
@@ -1852,7 +1865,7 @@ __global__ __launch_bounds__(kBlock) void k_mf_element(int64_t ne,
             a2[es][t] = rb;
             a3[es][t] = rc;
         }
-        __syncthreads();
+        wave_lds_sync();
         // direction 1: thread (g0, a1 = t1, a2)
         if (act) {
             double sa = 0.0, sc2 = 0.0;
@@ -1865,7 +1878,7 @@ __global__ __launch_bounds__(kBlock) void k_mf_element(int64_t ne,
             b0[es][t] = sa;
             b1[es][t] = sc2;
         }
-        __syncthreads();
+        wave_lds_sync();
         // direction 0: thread (a0 = t0, a1, a2): the element's y at node t
         if (act) {
             double y = 0.0;
@@ -1874,17 +1887,16 @@ __global__ __launch_bounds__(kBlock) void k_mf_element(int64_t ne,
                 const int k = g + Q * t1 + Q * Q * t2;
                 y += sV[t0][g] * b0[es][k] + sD[t0][g] * b1[es][k];
             }
-            Y[e * NL + t] = y;
+            Y[pos[e * NL + t]] = y;
         }
-        __syncthreads();
+        wave_lds_sync();
     }
 }
 
-// y_i = sum of node i's element results in ascending element order; zero on
-// Dirichlet rows; per-block partials of x^T y
+// y_i = sum of node i's element results (its run of the scratch, ascending
+// element order); zero on Dirichlet rows; per-block partials of x^T y
 template <bool DOT>
 __global__ __launch_bounds__(kBlock) void k_mf_gather(int64_t n, const int64_t *__restrict__ ptr,
-                                                      const int32_t *__restrict__ ent,
                                                       const double *__restrict__ Y,
                                                       const double *__restrict__ x,
                                                       double *__restrict__ y,
@@ -1899,7 +1911,7 @@ __global__ __launch_bounds__(kBlock) void k_mf_gather(int64_t n, const int64_t *
     for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * kBlock) {
         double s = 0.0;
-        for (int64_t k = ptr[i]; k < ptr[i + 1]; ++k) s += Y[ent[k]];
+        for (int64_t k = ptr[i]; k < ptr[i + 1]; ++k) s += Y[k];
         if (is_dirichlet(bc, bit, i)) s = 0.0;
         y[i] = s;
         if constexpr (DOT) acc += x[i] * s;
@@ -1935,12 +1947,13 @@ int mf_launch_p(const DevMatrix &A, const double *x, double *y, const uint8_t *b
     hipEvent_t e1[2] = {ev2 ? ev2[0] : nullptr, nullptr};
     hipEvent_t e2[2] = {nullptr, ev2 ? ev2[1] : nullptr};
     if (launch_k(k_mf_element<P>, Ge, kBlock, 0, s, ev2 ? e1 : nullptr, A.mf_ne,
-                 (const int32_t *)A.mf_nodes, (const double *)A.mf_corner, x, T, scratch,
+                 (const int32_t *)A.mf_nodes, (const double *)A.mf_corner,
+                 (const int32_t *)A.mf_pos, x, T, scratch,
                  DOT ? sc : (const Scalars *)nullptr) != hipSuccess)
         return -1;
     if (launch_k(k_mf_gather<DOT>, Gg, kBlock, 0, s, ev2 ? e2 : nullptr, A.n,
-                 (const int64_t *)A.mf_ptr, (const int32_t *)A.mf_ent, (const double *)scratch,
-                 x, y, bc, bit, sc, part) != hipSuccess)
+                 (const int64_t *)A.mf_ptr, (const double *)scratch, x, y, bc, bit, sc,
+                 part) != hipSuccess)
         return -1;
     return Gg;
 }
