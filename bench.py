@@ -875,7 +875,8 @@ def traffic_probe(torch, log, iters=64, q2_iters=16):
     """Short run for hardware-counter passes: a plain 1 GiB device copy (the
     calibration kernel of known size), 64 iterations of the 256x256x20
     pressure solve (the dominant SpMV kernel), then 16 iterations of the Q2
-    velocity solve on 128x128x10 bricks (the wide diagonal SpMV)."""
+    velocity solve on 128x128x10 bricks (the wide diagonal SpMV), then the
+    same 16 iterations on the matrix-free Q2 operator."""
     import basin
     from paper_1207_0486_amd.hns import Operator
     dev = torch.device("cuda", 0)
@@ -905,6 +906,14 @@ def traffic_probe(torch, log, iters=64, q2_iters=16):
     out["q2"] = {"nodes": mq.n, "nnz": q2.nnz, "format": q2.format, "ndiag": q2.ndiag,
                  "iterations": iq.iterations,
                  "stored_bytes_per_spmv": (q2.ndiag + 1) * mq.n * 8 + 2 * 8 * mq.n}
+    q2.close()
+    qf = Operator(mq, wl.nu_h, wl.nu_v, wl.dt, kind="helmholtz", matrix_free=True)
+    xf, iff = qf.solve(rq, tol=1e-30, max_iter=q2_iters, mask_bit=0, check=False)
+    torch.cuda.synchronize()
+    out["q2_matrix_free"] = {"iterations": iff.iterations,
+                             "algorithmic_bytes_per_product":
+                                 mf_product_bytes(mq.n, mq.hexes.shape[0], mq.hexes.shape[1])}
+    qf.close()
     print(json.dumps(out), flush=True)
 
 
