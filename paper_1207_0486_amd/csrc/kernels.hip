@@ -1762,14 +1762,34 @@ __global__ __launch_bounds__(kBlock) void k_mf_element(int64_t ne,
     const double cm = T.coef[0], cs = T.coef[1];
     const double nu[3] = {T.coef[2], T.coef[3], T.coef[4]};
     __syncthreads();   // the tables; below, every element lives in one wavefront
-    for (int64_t e0 = (int64_t)blockIdx.x * EB; e0 < ne; e0 += (int64_t)gridDim.x * EB) {
+    // the next group's x values and corners are loaded into registers while
+    // the current group computes (a workgroup takes several groups in turn)
+    constexpr int NC = (24 + NL - 1) / NL;   // corner values per lane
+    const int64_t stride = (int64_t)gridDim.x * EB;
+    double px = 0.0, pc[NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) pc[k] = 0.0;
+    auto fetch = [&](int64_t e) {
+        if (on && e < ne) {
+            px = x[nodes[e * NL + t]];
+#pragma unroll
+            for (int k = 0; k < NC; ++k)
+                if (t + k * NL < 24) pc[k] = corner[e * 24 + t + k * NL];
+        }
+    };
+    fetch((int64_t)blockIdx.x * EB + es);
+    for (int64_t e0 = (int64_t)blockIdx.x * EB; e0 < ne; e0 += stride) {
         const int64_t e = e0 + es;
         const bool act = on && e < ne;
-        // x at the element's nodes; its corners
+        int32_t out = 0;
         if (act) {
-            a0[es][t] = x[nodes[e * NL + t]];
-            for (int k = t; k < 24; k += NL) sX[es][k] = corner[e * 24 + k];
+            a0[es][t] = px;
+#pragma unroll
+            for (int k = 0; k < NC; ++k)
+                if (t + k * NL < 24) sX[es][t + k * NL] = pc[k];
+            out = pos[e * NL + t];
         }
+        fetch(e + stride);
         wave_lds_sync();
         // forward, direction 0: thread (g0 = t0, a1 = t1, a2 = t2)
         if (act) {
@@ -1887,7 +1907,7 @@ __global__ __launch_bounds__(kBlock) void k_mf_element(int64_t ne,
                 const int k = g + Q * t1 + Q * Q * t2;
                 y += sV[t0][g] * b0[es][k] + sD[t0][g] * b1[es][k];
             }
-            Y[pos[e * NL + t]] = y;
+            Y[out] = y;
         }
         wave_lds_sync();
     }
@@ -1941,8 +1961,10 @@ int mf_launch_p(const DevMatrix &A, const double *x, double *y, const uint8_t *b
         }
     for (int g = 0; g < 3; ++g) T.gw[g] = A.mf_gw[g];
     for (int k = 0; k < 5; ++k) T.coef[k] = A.mf_coef[k];
+    // about two workgroups per SIMD's share of the chip at a time, each taking
+    // several groups of elements in turn (the loads of the next overlap)
     const int64_t blocks = (A.mf_ne + EB - 1) / EB;
-    const int Ge = (int)std::max<int64_t>(1, std::min<int64_t>(blocks, 65536));
+    const int Ge = (int)std::max<int64_t>(1, std::min<int64_t>(blocks, 2048));
     const int Gg = stream_grid(A.n);
     hipEvent_t e1[2] = {ev2 ? ev2[0] : nullptr, nullptr};
     hipEvent_t e2[2] = {nullptr, ev2 ? ev2[1] : nullptr};

@@ -107,3 +107,53 @@ def test_device_assembly_reports_mesh_errors(dev, case):
         assert e.value.status == -4
         msgs.append(L.lib().hns_last_error())
     assert msgs[0] == msgs[1], msgs
+
+
+def _mesh_of(xyz, tets, bc=None):
+    import types
+    return types.SimpleNamespace(xyz=np.asarray(xyz, dtype=np.float64),
+                                 tets=np.asarray(tets, dtype=np.int32).reshape(-1, 4),
+                                 bc=None if bc is None else np.asarray(bc, dtype=np.uint8))
+
+
+def _pair(m, kind="helmholtz"):
+    from paper_1207_0486_amd.hns import Operator
+    host = Operator(m, 1.0, 0.5, 0.1, kind=kind)
+    gpu = Operator(m, 1.0, 0.5, 0.1, kind=kind, gpu_assembly=True)
+    return host, gpu
+
+
+def test_device_build_edge_meshes(dev):
+    """One tetrahedron (every row at the ends of the diagonal storage); a
+    mesh with a node no tetrahedron touches (its diagonal is zero: both
+    builds report it as a breakdown of the solve); a mesh with no
+    tetrahedron at all (no offsets: the host path); each bitwise the host
+    build."""
+    from paper_1207_0486_amd.hns import HNSError
+    rng = np.random.default_rng(4)
+    one = _mesh_of([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]], [[0, 1, 2, 3]])
+    box = basin.box_mesh(2, 2, 1)
+    extra = _mesh_of(np.vstack([box.xyz, [[5.0, 5.0, 5.0]]]), box.tets)
+    empty = _mesh_of([[0, 0, 0], [1, 0, 0]], np.zeros((0, 4)))
+    for m, where in ((one, 2), (extra, 2), (empty, 1)):
+        host, gpu = _pair(m)
+        assert gpu.assembly == where
+        assert (gpu.n, gpu.nnz, gpu.format, gpu.ndiag) == (host.n, host.nnz, host.format,
+                                                           host.ndiag)
+        x = torch.as_tensor(rng.standard_normal(gpu.n), device=dev)
+        assert torch.equal(gpu.apply(x), host.apply(x))
+        b = torch.as_tensor(rng.standard_normal(gpu.n), device=dev)
+        outs = []
+        for op in (host, gpu):
+            try:
+                xs, info = op.solve(b, tol=1e-10)
+                outs.append(("ok", xs))
+            except HNSError as e:
+                outs.append(("err", e.status))
+        assert outs[0][0] == outs[1][0]
+        if outs[0][0] == "ok":
+            assert torch.equal(outs[0][1], outs[1][1])
+        else:
+            assert outs[0][1] == outs[1][1] == -5   # breakdown: a zero diagonal
+        if m is one:
+            assert outs[0][0] == "ok"
