@@ -359,7 +359,8 @@ int hns_operator_line_len(const hns_operator *op);
 int hns_operator_assembly(const hns_operator *op);
 
 /* Tunables (returns HNS_ERR_INVALID for an unknown name or a bad value):
- *   "check_every"  CG iterations between host convergence reads (default 32)
+ *   "check_every"  CG iterations between host convergence reads (default 32;
+ *                  see "small_n" for the single-workgroup path)
  *   "inner_tol"    relative tolerance of each FP32 inner solve (default 1e-5)
  *   "max_outer"    cap on refinement steps of the restarted variant (default 30)
  *   "mixed_variant" HNS_MIXED algorithm:
@@ -393,10 +394,13 @@ int hns_operator_assembly(const hns_operator *op);
  *                  iterations in one workgroup (one launch per chunk instead
  *                  of three per iteration; the same recurrence and stopping
  *                  rule, dot products summed over 1024 threads instead of
- *                  per-block partials); default 4096 (measured crossover:
- *                  about 12 against 26 us per iteration at 1445 rows, 35
- *                  against 19 at 6875), 0 = never, at most 1048576.  Not
- *                  used while per-kernel timing is enabled.
+ *                  per-block partials; up to 4096 rows the vectors stay in
+ *                  registers and LDS for the whole chunk).  The workgroup
+ *                  stops by itself at the tolerance, so its chunks take up
+ *                  to max(check_every, 1024) iterations (per-slot sessions:
+ *                  the iterations of an advance).  Default 4096, 0 = never,
+ *                  at most 1048576.  Not used while per-kernel timing is
+ *                  enabled.
  *   "jacobi_scaling" 1 (default): point-Jacobi solves (precond 0) of an
  *                  operator in symmetric diagonal storage with at most 16
  *                  upper diagonals and more than "small_n" rows, HNS_FP64 or

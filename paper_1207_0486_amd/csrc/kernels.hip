@@ -2463,6 +2463,149 @@ __global__ __launch_bounds__(kSmallBlock) void k_cg_small(SmallMat A, const TV *
     }
 }
 
+// The same chunk for up to 4 kSmallBlock rows: a thread keeps its rows' x,
+// r, q and D^-1 in registers and the direction p lives in LDS (the product
+// reads it at neighbouring rows), so an iteration touches global memory only
+// for the matrix values; x, r and p are loaded at the start of the chunk and
+// stored at its end.  Per element and per sum the arithmetic and order are
+// those of k_cg_small.
+template <typename TV, typename TX, typename TD, int ROWS>
+__global__ __launch_bounds__(kSmallBlock) void k_cg_small_lds(
+    SmallMat A, const TV *__restrict__ vals, TX *__restrict__ x, TX *__restrict__ r,
+    TX *__restrict__ p, const TD *__restrict__ dinv, const uint8_t *__restrict__ bc, int bit,
+    Scalars *__restrict__ sc, int count, int parity)
+{
+    extern __shared__ __align__(16) unsigned char small_dyn[];
+    TX *sp = reinterpret_cast<TX *>(small_dyn);
+    __shared__ double lds[2 * (kSmallBlock / 64)];
+    if (sc->stop) return;
+    const int64_t n = A.n;
+    TX xr[ROWS], rv[ROWS], qv[ROWS], dv[ROWS];
+    bool dm[ROWS];
+#pragma unroll
+    for (int k = 0; k < ROWS; ++k) {
+        const int64_t i = threadIdx.x + (int64_t)k * kSmallBlock;
+        xr[k] = rv[k] = qv[k] = dv[k] = (TX)0;
+        dm[k] = false;
+        if (i < n) {
+            xr[k] = x[i];
+            rv[k] = r[i];
+            dv[k] = (TX)dinv[i];
+            dm[k] = is_dirichlet(bc, bit, i);
+            sp[i] = p[i];
+        }
+    }
+    __syncthreads();
+    double rho[2] = {sc->rho[0], sc->rho[1]};
+    double gamma = sc->gamma, alpha_d = sc->alpha, beta_d = sc->beta, rr = sc->rr;
+    const double limit = sc->tol2 * sc->bb;
+    int stop = 0, done = 0;
+    for (int it = 0; it < count; ++it) {
+        double v1[1] = {0.0};
+#pragma unroll
+        for (int k = 0; k < ROWS; ++k) {
+            const int64_t i = threadIdx.x + (int64_t)k * kSmallBlock;
+            if (i < n) {
+                TX sum = small_row<TV, TX>(A, vals, sp, i);
+                if (dm[k]) sum = 0;
+                qv[k] = sum;
+                v1[0] += (double)sp[i] * (double)sum;
+            }
+        }
+        small_block_sum<1>(v1, lds);
+        gamma = v1[0];
+        if (!(gamma > 0.0) || !isfinite(gamma)) {
+            stop = 2;
+            break;
+        }
+        alpha_d = rho[parity] / gamma;
+        const TX alpha = (TX)alpha_d;
+        double v2[2] = {0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k < ROWS; ++k) {
+            const int64_t i = threadIdx.x + (int64_t)k * kSmallBlock;
+            if (i < n) {
+                const TX ri = rv[k] - alpha * qv[k];
+                rv[k] = ri;
+                const TX zi = dv[k] * ri;
+                v2[0] += (double)ri * (double)zi;
+                v2[1] += (double)ri * (double)ri;
+            }
+        }
+        small_block_sum<2>(v2, lds);
+        const double rho_new = v2[0];
+        rr = v2[1];
+        const bool bad = !isfinite(rho_new) || !isfinite(rr);
+        const bool conv = !bad && rr <= limit;
+        beta_d = rho_new / rho[parity];
+        const TX beta = (TX)beta_d;
+        const bool dir = !(bad || conv);
+#pragma unroll
+        for (int k = 0; k < ROWS; ++k) {
+            const int64_t i = threadIdx.x + (int64_t)k * kSmallBlock;
+            if (i < n) {
+                const TX pi = sp[i];
+                xr[k] = xr[k] + alpha * pi;
+                if (dir) sp[i] = dv[k] * rv[k] + beta * pi;
+            }
+        }
+        rho[parity ^ 1] = rho_new;
+        parity ^= 1;
+        ++done;
+        if (!dir) {
+            stop = bad ? 2 : 1;
+            break;
+        }
+        __syncthreads();
+    }
+    // a thread stores only its own rows, whose p it alone wrote
+#pragma unroll
+    for (int k = 0; k < ROWS; ++k) {
+        const int64_t i = threadIdx.x + (int64_t)k * kSmallBlock;
+        if (i < n) {
+            x[i] = xr[k];
+            r[i] = rv[k];
+            p[i] = sp[i];
+        }
+    }
+    if (threadIdx.x == 0) {
+        sc->rho[0] = rho[0];
+        sc->rho[1] = rho[1];
+        sc->gamma = gamma;
+        sc->alpha = alpha_d;
+        sc->beta = beta_d;
+        sc->rr = rr;
+        sc->iter += done;
+        if (stop) sc->stop = stop;
+    }
+}
+
+template <typename TV, typename TX, typename TD>
+void launch_small_lds(const SmallMat &A, const TV *v, TX *x, TX *r, TX *p, const TD *dinv,
+                      const uint8_t *bc, int bit, Scalars *sc, int count, int parity,
+                      hipStream_t s)
+{
+    const size_t shm = (size_t)A.n * sizeof(TX);
+    switch ((A.n + kSmallBlock - 1) / kSmallBlock) {
+    case 1:
+        k_cg_small_lds<TV, TX, TD, 1><<<1, kSmallBlock, shm, s>>>(A, v, x, r, p, dinv, bc, bit,
+                                                                  sc, count, parity);
+        break;
+    case 2:
+        k_cg_small_lds<TV, TX, TD, 2><<<1, kSmallBlock, shm, s>>>(A, v, x, r, p, dinv, bc, bit,
+                                                                  sc, count, parity);
+        break;
+    case 3:
+        k_cg_small_lds<TV, TX, TD, 3><<<1, kSmallBlock, shm, s>>>(A, v, x, r, p, dinv, bc, bit,
+                                                                  sc, count, parity);
+        break;
+    default:
+        k_cg_small_lds<TV, TX, TD, 4><<<1, kSmallBlock, shm, s>>>(A, v, x, r, p, dinv, bc, bit,
+                                                                  sc, count, parity);
+        break;
+    }
+}
+
 hns_status launch_cg_small(const IterArgs &a, int parity, int count, hipStream_t s)
 {
     const DevMatrix &M = *a.A;
@@ -2480,20 +2623,32 @@ hns_status launch_cg_small(const IterArgs &a, int parity, int count, hipStream_t
     A.slice_ptr = M.slice_ptr;
     A.scol = M.scol;
     const uint8_t *bc = a.bit < 0 ? nullptr : a.bc;
+    // up to 4 rows per thread the vectors stay on chip for the whole chunk
+    const bool on_chip = a.n <= 4 * (int64_t)kSmallBlock;
     if (a.prec == Prec::F64) {
         const double *v = M.fmt == HNS_FMT_SDIA ? M.dia : M.fmt == HNS_FMT_SELL ? M.sval : M.val;
-        k_cg_small<double, double, double><<<1, kSmallBlock, 0, s>>>(
-            A, v, (double *)a.x, (double *)a.r, (double *)a.p, (double *)a.q,
-            (const double *)a.dinv, bc, a.bit, a.sc, count, parity & 1);
+        if (on_chip)
+            launch_small_lds<double, double, double>(A, v, (double *)a.x, (double *)a.r,
+                                                     (double *)a.p, (const double *)a.dinv, bc,
+                                                     a.bit, a.sc, count, parity & 1, s);
+        else
+            k_cg_small<double, double, double><<<1, kSmallBlock, 0, s>>>(
+                A, v, (double *)a.x, (double *)a.r, (double *)a.p, (double *)a.q,
+                (const double *)a.dinv, bc, a.bit, a.sc, count, parity & 1);
     } else {
         const float *v = M.fmt == HNS_FMT_SDIA ? M.dia32 : M.fmt == HNS_FMT_SELL ? M.sval32 : M.val32;
         if (!v) {
             set_error("launch_cg_small: FP32 values not kept");
             return HNS_ERR_INVALID;
         }
-        k_cg_small<float, float, float><<<1, kSmallBlock, 0, s>>>(
-            A, v, (float *)a.x, (float *)a.r, (float *)a.p, (float *)a.q, (const float *)a.dinv,
-            bc, a.bit, a.sc, count, parity & 1);
+        if (on_chip)
+            launch_small_lds<float, float, float>(A, v, (float *)a.x, (float *)a.r,
+                                                  (float *)a.p, (const float *)a.dinv, bc, a.bit,
+                                                  a.sc, count, parity & 1, s);
+        else
+            k_cg_small<float, float, float><<<1, kSmallBlock, 0, s>>>(
+                A, v, (float *)a.x, (float *)a.r, (float *)a.p, (float *)a.q,
+                (const float *)a.dinv, bc, a.bit, a.sc, count, parity & 1);
     }
     return check_launch("small-system cg chunk");
 }

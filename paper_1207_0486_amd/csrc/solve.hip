@@ -253,6 +253,20 @@ struct SolveCtx {
 // each iteration.  Iterations enqueued after the stop flag was raised are
 // no-ops on the device, so the caller re-derives parity from the device's
 // iteration counter after each chunk.
+// Chunks of a recurrence that the single-workgroup kernel runs (latency-bound
+// sizes: point Jacobi, FP64 or FP32, not while per-kernel timing is on).  It
+// stops by itself at the tolerance, so its chunks may be long: one launch and
+// one host read instead of one per check_every iterations.
+constexpr int kSmallChunk = 1024;
+
+static bool small_chunks(const hns_operator *op, const Workspace *w, Prec prec, const void *lfac,
+                         const IC0Dev *ic, bool scaled)
+{
+    const int period = w->borrowed ? 0 : op->profile;
+    return !lfac && !ic && !scaled && period <= 0 && op->n <= op->small_n &&
+           op->A.fmt != HNS_MATRIX_FREE && (prec == Prec::F64 || prec == Prec::F32);
+}
+
 static hns_status enqueue_iterations(hns_operator *op, Workspace *w, Prec prec, int bit, void *x,
                                      void *r, void *p, void *q, const void *dinv, Scalars *sc,
                                      int count, int parity0, hipStream_t s,
@@ -278,11 +292,8 @@ static hns_status enqueue_iterations(hns_operator *op, Workspace *w, Prec prec, 
         a.z = w->z;
         a.y = w->y;
     }
-    // latency-bound sizes: the whole chunk in one workgroup (point Jacobi,
-    // FP64 or FP32, not while per-kernel timing is on)
-    if (!lfac && !ic && !scaled && period <= 0 && op->n <= op->small_n &&
-        op->A.fmt != HNS_MATRIX_FREE && (prec == Prec::F64 || prec == Prec::F32))
-        return launch_cg_small(a, parity0, count, s);
+    // latency-bound sizes: the whole chunk in one workgroup
+    if (small_chunks(op, w, prec, lfac, ic, scaled)) return launch_cg_small(a, parity0, count, s);
     // sampled: the iteration in the middle of each period window, so a chunk's
     // first iteration (launched after the host's read of the previous chunk,
     // on an idle GPU) is never timed unless every iteration is
@@ -325,11 +336,14 @@ static hns_status run_chunks(const SolveCtx &c, int which, Prec prec, void *x, v
     while (h.stop == 0) {
         const int left = c.max_iter - h.iter;
         if (left <= 0) break;
-        const int chunk = left < op->check_every ? left : op->check_every;
-        const int before = h.iter;
         const void *lf = prec == Prec::F64   ? (const void *)c.lfac
                          : prec == Prec::F32 ? (const void *)c.lfac32
                                              : nullptr;
+        const int per = small_chunks(op, w, prec, lf, prec == Prec::F64 ? c.ic : nullptr, c.scaled)
+                            ? std::max(op->check_every, kSmallChunk)
+                            : op->check_every;
+        const int chunk = left < per ? left : per;
+        const int before = h.iter;
         HNS_TRY(enqueue_iterations(op, w, prec, c.bit, x, r, p, q, dinv, w->sc + which, chunk,
                                    *since_start, c.s, lf, prec == Prec::F64 ? c.ic : nullptr,
                                    c.scaled));
@@ -526,17 +540,20 @@ struct ChunkedSolve {
         if (fresh) HNS_TRY(start_segment());
         Scalars &hr = w->host[which()];
         before = hr.iter;
-        const int chunk = std::min({c.max_iter - hr.iter, op->check_every, budget});
+        const Prec p = mixed ? Prec::F32 : prec;
+        const void *lf = p == Prec::F64   ? (const void *)c.lfac
+                         : p == Prec::F32 ? (const void *)c.lfac32
+                                          : nullptr;
+        const int per = small_chunks(op, w, p, lf, p == Prec::F64 ? c.ic : nullptr, c.scaled)
+                            ? std::max(op->check_every, kSmallChunk)
+                            : op->check_every;
+        const int chunk = std::min({c.max_iter - hr.iter, per, budget});
         if (chunk > 0 && hr.stop == 0) {
-            const Prec p = mixed ? Prec::F32 : prec;
             void *x = mixed ? (void *)w->d32 : c.scaled ? (void *)w->z : (void *)c.x;
             void *r = mixed ? (void *)w->r32 : (void *)w->r;
             void *pp = mixed ? (void *)w->p32 : (void *)w->p;
             void *q = mixed ? (void *)w->q32 : (void *)w->q;
             const void *di = c.scaled ? nullptr : mixed ? (const void *)op->dinv32 : dinv;
-            const void *lf = p == Prec::F64   ? (const void *)c.lfac
-                             : p == Prec::F32 ? (const void *)c.lfac32
-                                              : nullptr;
             HNS_TRY(enqueue_iterations(op, w, p, c.bit, x, r, pp, q, di, w->sc + which(), chunk,
                                        since, c.s, lf, p == Prec::F64 ? c.ic : nullptr,
                                        c.scaled));
