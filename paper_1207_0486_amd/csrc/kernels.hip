@@ -27,6 +27,7 @@
 // One-off reductions outside the iteration (right-hand-side statistics,
 // residual norms, normalisation, recurrence starts) store per-block partials
 // the same way and a one-workgroup launch re-reduces them into the scalars.
+#include <atomic>
 #include <cmath>
 #include <tuple>
 #include <type_traits>
@@ -2469,17 +2470,25 @@ __global__ __launch_bounds__(kSmallBlock) void k_cg_small(SmallMat A, const TV *
 // for the matrix values; x, r and p are loaded at the start of the chunk and
 // stored at its end.  Per element and per sum the arithmetic and order are
 // those of k_cg_small.
-template <typename TV, typename TX, typename TD, int ROWS>
+// With VL the matrix values (diagonal storage, (ndiag + 1) n of them) are
+// copied into LDS too, ahead of p, and every product reads them there.
+template <typename TV, typename TX, typename TD, int ROWS, bool VL>
 __global__ __launch_bounds__(kSmallBlock) void k_cg_small_lds(
-    SmallMat A, const TV *__restrict__ vals, TX *__restrict__ x, TX *__restrict__ r,
+    SmallMat A, const TV *__restrict__ gvals, TX *__restrict__ x, TX *__restrict__ r,
     TX *__restrict__ p, const TD *__restrict__ dinv, const uint8_t *__restrict__ bc, int bit,
     Scalars *__restrict__ sc, int count, int parity)
 {
     extern __shared__ __align__(16) unsigned char small_dyn[];
-    TX *sp = reinterpret_cast<TX *>(small_dyn);
+    const int64_t nv = VL ? (int64_t)(A.ndiag + 1) * A.n : 0;
+    const size_t vbytes = ((size_t)nv * sizeof(TV) + 15) & ~size_t(15);
+    TV *svals = reinterpret_cast<TV *>(small_dyn);
+    TX *sp = reinterpret_cast<TX *>(small_dyn + vbytes);
     __shared__ double lds[2 * (kSmallBlock / 64)];
     if (sc->stop) return;
     const int64_t n = A.n;
+    if constexpr (VL)
+        for (int64_t k = threadIdx.x; k < nv; k += kSmallBlock) svals[k] = gvals[k];
+    const TV *vals = VL ? (const TV *)svals : gvals;
     TX xr[ROWS], rv[ROWS], qv[ROWS], dv[ROWS];
     bool dm[ROWS];
 #pragma unroll
@@ -2580,30 +2589,65 @@ __global__ __launch_bounds__(kSmallBlock) void k_cg_small_lds(
     }
 }
 
+// LDS a single workgroup may take on gfx950 (160 KB), less the static arrays
+constexpr size_t kSmallLdsBytes = 160 * 1024 - 1024;
+
+template <typename TV, typename TX, typename TD, int ROWS, bool VL>
+hipError_t launch_small_rows(const SmallMat &A, const TV *v, TX *x, TX *r, TX *p,
+                             const TD *dinv, const uint8_t *bc, int bit, Scalars *sc, int count,
+                             int parity, size_t shm, hipStream_t s)
+{
+    auto k = k_cg_small_lds<TV, TX, TD, ROWS, VL>;
+    // raised once per instantiation to the largest size it may take
+    static std::atomic<bool> raised{false};
+    if (shm > 64 * 1024 && !raised.load(std::memory_order_acquire)) {
+        const hipError_t e = hipFuncSetAttribute((const void *)k,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                 (int)kSmallLdsBytes);
+        if (e != hipSuccess) return e;
+        raised.store(true, std::memory_order_release);
+    }
+    hipLaunchKernelGGL(k, dim3(1), dim3(kSmallBlock), shm, s, A, v, x, r, p, dinv, bc, bit, sc,
+                       count, parity);
+    return hipGetLastError();
+}
+
+template <typename TV, typename TX, typename TD, bool VL>
+hipError_t launch_small_vl(const SmallMat &A, const TV *v, TX *x, TX *r, TX *p, const TD *dinv,
+                           const uint8_t *bc, int bit, Scalars *sc, int count, int parity,
+                           size_t shm, hipStream_t s)
+{
+    switch ((A.n + kSmallBlock - 1) / kSmallBlock) {
+    case 1:
+        return launch_small_rows<TV, TX, TD, 1, VL>(A, v, x, r, p, dinv, bc, bit, sc, count,
+                                                    parity, shm, s);
+    case 2:
+        return launch_small_rows<TV, TX, TD, 2, VL>(A, v, x, r, p, dinv, bc, bit, sc, count,
+                                                    parity, shm, s);
+    case 3:
+        return launch_small_rows<TV, TX, TD, 3, VL>(A, v, x, r, p, dinv, bc, bit, sc, count,
+                                                    parity, shm, s);
+    default:
+        return launch_small_rows<TV, TX, TD, 4, VL>(A, v, x, r, p, dinv, bc, bit, sc, count,
+                                                    parity, shm, s);
+    }
+}
+
 template <typename TV, typename TX, typename TD>
 void launch_small_lds(const SmallMat &A, const TV *v, TX *x, TX *r, TX *p, const TD *dinv,
                       const uint8_t *bc, int bit, Scalars *sc, int count, int parity,
                       hipStream_t s)
 {
-    const size_t shm = (size_t)A.n * sizeof(TX);
-    switch ((A.n + kSmallBlock - 1) / kSmallBlock) {
-    case 1:
-        k_cg_small_lds<TV, TX, TD, 1><<<1, kSmallBlock, shm, s>>>(A, v, x, r, p, dinv, bc, bit,
-                                                                  sc, count, parity);
-        break;
-    case 2:
-        k_cg_small_lds<TV, TX, TD, 2><<<1, kSmallBlock, shm, s>>>(A, v, x, r, p, dinv, bc, bit,
-                                                                  sc, count, parity);
-        break;
-    case 3:
-        k_cg_small_lds<TV, TX, TD, 3><<<1, kSmallBlock, shm, s>>>(A, v, x, r, p, dinv, bc, bit,
-                                                                  sc, count, parity);
-        break;
-    default:
-        k_cg_small_lds<TV, TX, TD, 4><<<1, kSmallBlock, shm, s>>>(A, v, x, r, p, dinv, bc, bit,
-                                                                  sc, count, parity);
-        break;
-    }
+    // the diagonal storage's values on chip too when they fit beside p
+    const size_t pbytes = (size_t)A.n * sizeof(TX);
+    const size_t vbytes = ((size_t)(A.ndiag + 1) * A.n * sizeof(TV) + 15) & ~size_t(15);
+    if (A.fmt == HNS_FMT_SDIA && vbytes + pbytes <= kSmallLdsBytes &&
+        launch_small_vl<TV, TX, TD, true>(A, v, x, r, p, dinv, bc, bit, sc, count, parity,
+                                          vbytes + pbytes, s) == hipSuccess)
+        return;
+    (void)hipGetLastError();
+    (void)launch_small_vl<TV, TX, TD, false>(A, v, x, r, p, dinv, bc, bit, sc, count, parity,
+                                             pbytes, s);
 }
 
 hns_status launch_cg_small(const IterArgs &a, int parity, int count, hipStream_t s)
