@@ -417,6 +417,17 @@ int hns_operator_assembly(const hns_operator *op);
  *                  diag(A)).  The scaled operator (FP64, and FP32 when the
  *                  operator keeps FP32 values) is computed on the device on
  *                  first use and stays resident.  0 = the unscaled recurrence.
+ *   "fuse_dir"     the Jacobi-scaled recurrence above in two launches per
+ *                  iteration instead of three: the direction update of an
+ *                  iteration rides in the product of the next, every
+ *                  neighbour's r + beta p recomputed where the product reads
+ *                  it, p alternating between two buffers (one more n-vector
+ *                  of FP64 size per workspace).  The iterates, scalars and
+ *                  iteration counts are bit for bit those of the three-launch
+ *                  form.  -1 (default) while one vector of the recurrence
+ *                  takes at most 4 MiB (524288 FP64 / 1048576 FP32 rows),
+ *                  0 never, 1 always.  Per-kernel timing then times the
+ *                  product (with the direction update) and the update.
  *   "session_mode" form of the batch sessions opened afterwards: 0 (default)
  *                  per-slot recurrences up to 2 slots, the shared block above;
  *                  1 always the shared block; 2 always per slot

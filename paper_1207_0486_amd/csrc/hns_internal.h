@@ -215,6 +215,10 @@ struct hns_operator {
     // FP32), with s = D^-1/2 and w = diag(A) in FP32; built on first use
     // (under line_mutex).
     int jacobi_scaling = 1;
+    // scaled point-Jacobi iterations in two launches (the direction update
+    // inside the next product, p in two buffers; the same arithmetic):
+    // -1 by vector size, 0 never, 1 always
+    int fuse_dir = -1;
     // batch sessions: 0 per-slot recurrences up to 2 slots, the shared
     // multi-right-hand-side block above; 1 always the block; 2 always per slot
     int session_mode = 0;

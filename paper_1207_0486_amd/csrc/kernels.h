@@ -101,6 +101,22 @@ struct IterArgs {
 // ev (optional, 6 events) brackets the three kernels for timing.
 hns_status launch_iteration(const IterArgs &a, int parity, hipStream_t s, hipEvent_t *ev);
 
+// Fused iterations of CG on the Jacobi-scaled operator (a.wjac set, the
+// unit-diagonal diagonal-storage operator): two launches per iteration, the
+// direction update of iteration k riding in the product of k + 1, with p in
+// two buffers (a.p and a spare).  A chunk is: step(po = nullptr) on a.p,
+// then step(po = the previous iteration's p buffer, pn = the other) per
+// further iteration, then close(po = the last buffer), which leaves p in a.p.
+// prev_token / prev_parity name the iteration the step completes, a.token /
+// parity the one it starts.  Same arithmetic as launch_iteration, bit for bit.
+// ev: optional 4 events (product, update).
+bool scaled_fusable(const IterArgs &a);
+hns_status launch_scaled_fused_step(const IterArgs &a, const void *po, void *pn,
+                                    uint32_t prev_token, int prev_parity, int parity,
+                                    hipStream_t s, hipEvent_t *ev);
+hns_status launch_scaled_fused_close(const IterArgs &a, const void *po, uint32_t token,
+                                     int parity, hipStream_t s);
+
 // `count` point-Jacobi CG iterations of a small system (n <= kSmallMaxN) in
 // one workgroup: the same recurrence, device scalars and stop rule as
 // `count` launch_iteration calls, with block barriers in place of the kernel

@@ -476,6 +476,205 @@ void k_spmv_sdia(int64_t n, int64_t rows, DiaOffsets offs,
     }
 }
 
+// Fused multiply-add in the vector type (the direction and x updates of the
+// scaled recurrence are written with it wherever they are evaluated, so that
+// every evaluation of p' = r + beta p gives the same bits)
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+// Completion of a scaled CG iteration by every block (the direction
+// update's prologue): rho', rr and the stopping decision from the update
+// partials, recorded by block 0.  False when the iteration's update did not
+// run (its tag is not the last recorded one).
+template <typename TX>
+__device__ __forceinline__ bool dir_prologue(Scalars *__restrict__ sc,
+                                             const double *__restrict__ part_in, int G_in,
+                                             int parity, uint32_t token, TX &alpha, TX &beta,
+                                             bool &dir)
+{
+    const uint32_t tag = sc->xtoken;
+    const double alpha_d = sc->alpha;
+    double v[2];
+    load_reduced<2>(part_in, G_in, v);
+    if (tag != token) return false;
+    const double rho_new = v[0], rr = v[1];
+    const bool bad = !isfinite(rho_new) || !isfinite(rr);
+    const bool conv = !bad && rr <= sc->tol2 * sc->bb;
+    const double beta_d = rho_new / sc->rho[parity];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc->rho[parity ^ 1] = rho_new;
+        sc->rr = rr;
+        sc->beta = beta_d;
+        sc->iter += 1;
+        if (bad)
+            sc->stop = 2;
+        else if (conv)
+            sc->stop = 1;
+    }
+    alpha = (TX)alpha_d;
+    beta = (TX)beta_d;
+    dir = !(bad || conv);
+    return true;
+}
+
+// Direction update and product in one launch, for CG on the Jacobi-scaled
+// operator (unit diagonal, M upper diagonals, z = r): completes iteration
+// k (the one tagged `token`) and starts k + 1.  Every block forms rho', rr,
+// beta and the stopping decision as the direction update does, then for its
+// own rows x += alpha p_k and p_{k+1} = r + beta p_k (stored into pn, the
+// other buffer), and forms q = A p_{k+1} with every neighbour value
+// p_{k+1}[j] recomputed from r[j] and p_k[j] by the same expression: the
+// products, the p^T q partials and all scalars are bit for bit those of the
+// separate direction update and product.  Rows, their order and the order
+// of the terms are those of k_spmv_sdia (UNIT, DOT).  On a stop
+// (convergence or a non-finite scalar) only x is updated, and p_k is copied
+// into pc, the buffer the caller reads p from after a chunk.
+template <typename TX, int M, int R>
+__global__ __launch_bounds__(kBlock)
+void k_sdia_dir(int64_t n, int64_t rows, DiaOffsets offs, const TX *__restrict__ dia,
+                const TX *__restrict__ po, const TX *__restrict__ r, TX *__restrict__ x,
+                TX *__restrict__ pn, TX *pc, TX *__restrict__ q,
+                const uint8_t *__restrict__ bc, int bit, Scalars *__restrict__ sc,
+                const double *__restrict__ part_in, int G_in, double *__restrict__ part_out,
+                int parity, uint32_t token)
+{
+    TX alpha = 0, beta = 0;
+    bool dir = true;
+    if (!dir_prologue<TX>(sc, part_in, G_in, parity, token, alpha, beta, dir)) return;
+    const int lb = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t r0 = (int64_t)lb * rows;
+    const int64_t r1 = r0 + rows < n ? r0 + rows : n;
+    if (!dir) {
+        for (int64_t i = r0 + threadIdx.x; i < r1; i += kBlock) {
+            const TX pi = po[i];
+            x[i] = fma_t(alpha, pi, x[i]);
+            if (pc != po) pc[i] = pi;
+        }
+        return;
+    }
+    double acc = 0.0;
+    if constexpr (R == 1) {
+        for (int64_t i = r0 + threadIdx.x; i < r1; i += kBlock) {
+            const TX pi = po[i];
+            const TX xo = fma_t(alpha, pi, x[i]);
+            const TX xi = fma_t(beta, pi, r[i]);
+            TX sum = xi;
+            TX up[M], lo[M], xu[M], xl[M];
+#pragma unroll
+            for (int k = 0; k < M; ++k) {
+                const int64_t o = offs.o[k];
+                const TX *u = dia + (int64_t)k * n;
+                const int64_t iu = i + o < n ? i + o : n - 1;
+                const int64_t il = i >= o ? i - o : 0;
+                up[k] = u[i];
+                xu[k] = fma_t(beta, po[iu], r[iu]);
+                lo[k] = u[il];
+                xl[k] = fma_t(beta, po[il], r[il]);
+            }
+#pragma unroll
+            for (int k = 0; k < M; ++k) {
+                const int64_t o = offs.o[k];
+                sum += (i + o < n) ? up[k] * xu[k] : (TX)0;
+                sum += (i >= o) ? lo[k] * xl[k] : (TX)0;
+            }
+            if (is_dirichlet(bc, bit, i)) sum = 0;
+            x[i] = xo;
+            pn[i] = xi;
+            q[i] = sum;
+            acc += (double)xi * (double)sum;
+        }
+    } else {
+        const int64_t omax = offs.o[M - 1];
+        for (int64_t i = r0 + (int64_t)threadIdx.x * R; i < r1; i += (int64_t)kBlock * R) {
+            if (i >= omax && i + (R - 1) + omax < n) {
+                bool dm[R];
+#pragma unroll
+                for (int e = 0; e < R; ++e) dm[e] = is_dirichlet(bc, bit, i + e);
+                // every load first (as in k_spmv_sdia), the stores last
+                const Run<R, TX> pi = ldrun<R>(po + i), ri = ldrun<R>(r + i);
+                Run<R, TX> xo = ldrun<R>(x + i);
+                Run<R, TX> up[M], lo[M], pu[M], ru[M], pl[M], rl[M];
+#pragma unroll
+                for (int k = 0; k < M; ++k) {
+                    const int64_t o = offs.o[k];
+                    const TX *u = dia + (int64_t)k * n;
+                    up[k] = ldrun<R>(u + i);
+                    pu[k] = ldrun<R>(po + i + o);
+                    ru[k] = ldrun<R>(r + i + o);
+                    lo[k] = ldrun<R>(u + i - o);
+                    pl[k] = ldrun<R>(po + i - o);
+                    rl[k] = ldrun<R>(r + i - o);
+                }
+                Run<R, TX> xi, out;
+#pragma unroll
+                for (int e = 0; e < R; ++e) {
+                    xo.v[e] = fma_t(alpha, pi.v[e], xo.v[e]);
+                    xi.v[e] = fma_t(beta, pi.v[e], ri.v[e]);
+                    TX sum = xi.v[e];
+#pragma unroll
+                    for (int k = 0; k < M; ++k) {
+                        sum += up[k].v[e] * fma_t(beta, pu[k].v[e], ru[k].v[e]);
+                        sum += lo[k].v[e] * fma_t(beta, pl[k].v[e], rl[k].v[e]);
+                    }
+                    if (dm[e]) sum = 0;
+                    out.v[e] = sum;
+                    acc += (double)xi.v[e] * (double)sum;
+                }
+                __builtin_memcpy(x + i, &xo, sizeof(xo));
+                __builtin_memcpy(pn + i, &xi, sizeof(xi));
+                __builtin_memcpy(q + i, &out, sizeof(out));
+            } else {
+                for (int e = 0; e < R; ++e) {
+                    const int64_t j = i + e;
+                    if (j >= r1) break;
+                    const TX pj = po[j];
+                    x[j] = fma_t(alpha, pj, x[j]);
+                    const TX xj = fma_t(beta, pj, r[j]);
+                    pn[j] = xj;
+                    TX sum = xj;
+                    for (int k = 0; k < M; ++k) {
+                        const int64_t o = offs.o[k];
+                        const TX *u = dia + (int64_t)k * n;
+                        if (j + o < n) sum += u[j] * fma_t(beta, po[j + o], r[j + o]);
+                        if (j >= o) sum += u[j - o] * fma_t(beta, po[j - o], r[j - o]);
+                    }
+                    if (is_dirichlet(bc, bit, j)) sum = 0;
+                    q[j] = sum;
+                    acc += (double)xj * (double)sum;
+                }
+            }
+        }
+    }
+    double w[1] = {acc};
+    store_block_partials<1>(w, part_out);
+}
+
+// The direction update that ends a chunk of fused iterations: completes the
+// iteration tagged `token` from p_k in po, writing x += alpha p_k and, unless
+// stopping, p_{k+1} = r + beta p_k into pc (po and pc may be one buffer:
+// each element is read and written by one thread); on a stop p_k is copied
+// into pc.  Rows as in k_sdia_dir.
+template <typename TX>
+__global__ __launch_bounds__(kBlock) void k_sdia_dir_close(int64_t n, int64_t rows,
+                                                           const TX *po, const TX *__restrict__ r,
+                                                           TX *__restrict__ x, TX *pc,
+                                                           Scalars *__restrict__ sc,
+                                                           const double *__restrict__ part_in,
+                                                           int G_in, int parity, uint32_t token)
+{
+    TX alpha = 0, beta = 0;
+    bool dir = true;
+    if (!dir_prologue<TX>(sc, part_in, G_in, parity, token, alpha, beta, dir)) return;
+    const int lb = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t r0 = (int64_t)lb * rows;
+    const int64_t r1 = r0 + rows < n ? r0 + rows : n;
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += kBlock) {
+        const TX pi = po[i];
+        x[i] = fma_t(alpha, pi, x[i]);
+        pc[i] = dir ? fma_t(beta, pi, r[i]) : pi;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Jacobi scaling: point-Jacobi PCG on A is plain CG on D^-1/2 A D^-1/2 with
 // the vectors x_S = D^1/2 x, r_S = D^-1/2 r, p_S = D^1/2 p (the same alpha,
@@ -912,8 +1111,12 @@ __global__ __launch_bounds__(kBlock) void k_pupdate(int64_t n, int64_t per, TX *
     auto body = [&](int64_t i, auto in) {
         constexpr int W = sizeof(in.p.v) / sizeof(TX);
 #pragma unroll
-        for (int e = 0; e < W; ++e)
-            in.p.v[e] = (SC ? in.r.v[e] : (TX)in.d.v[e] * in.r.v[e]) + beta * in.p.v[e];
+        for (int e = 0; e < W; ++e) {
+            if constexpr (SC)
+                in.p.v[e] = fma_t(beta, in.p.v[e], in.r.v[e]);
+            else
+                in.p.v[e] = (TX)in.d.v[e] * in.r.v[e] + beta * in.p.v[e];
+        }
         st<W>(p, i, in.p);
     };
     for_packs_ahead<V>(n, per, load, prologue, body);
@@ -975,12 +1178,21 @@ __global__ __launch_bounds__(kBlock) void k_pupdate_x(int64_t n, int64_t per,
     auto body = [&](int64_t i, auto in) {
         constexpr int W = sizeof(in.p.v) / sizeof(TX);
 #pragma unroll
-        for (int e = 0; e < W; ++e) in.x.v[e] = in.x.v[e] + alpha * in.p.v[e];
+        for (int e = 0; e < W; ++e) {
+            if constexpr (SC)
+                in.x.v[e] = fma_t(alpha, in.p.v[e], in.x.v[e]);
+            else
+                in.x.v[e] = in.x.v[e] + alpha * in.p.v[e];
+        }
         st<W>(x, i, in.x);
         if (dir) {
 #pragma unroll
-            for (int e = 0; e < W; ++e)
-                in.p.v[e] = (SC ? in.r.v[e] : (TX)in.d.v[e] * in.r.v[e]) + beta * in.p.v[e];
+            for (int e = 0; e < W; ++e) {
+                if constexpr (SC)
+                    in.p.v[e] = fma_t(beta, in.p.v[e], in.r.v[e]);
+                else
+                    in.p.v[e] = (TX)in.d.v[e] * in.r.v[e] + beta * in.p.v[e];
+            }
             st<W>(p, i, in.p);
         }
     };
@@ -2163,39 +2375,128 @@ hns_status iteration_impl(const IterArgs &a, int parity, hipStream_t s, hipEvent
 // diagonal, FP64 or FP32 values and vectors): the same three kernels without
 // the reads of D^-1; a.wjac (diag(A), FP32) weighs the unscaled residual norm.
 template <typename T>
+bool scaled_vec(const IterArgs &a)
+{
+    return aligned16(a.x) && aligned16(a.r) && aligned16(a.p) && aligned16(a.q) &&
+           aligned16(a.wjac);
+}
+
+template <typename T>
+hns_status scaled_values(const IterArgs &a)
+{
+    if ((sizeof(T) == 4 ? (const void *)a.A->dia32 : (const void *)a.A->dia) == nullptr) {
+        set_error("the Jacobi-scaled operator has no values in this precision");
+        return HNS_ERR_INVALID;
+    }
+    return HNS_OK;
+}
+
+// r -= alpha q with the partials of the scaled recurrence (Gs product partials in)
+template <typename T>
+hns_status launch_update_scaled(const IterArgs &a, int parity, int Gs, hipStream_t s,
+                                hipEvent_t *eu)
+{
+    constexpr int V = 16 / sizeof(T);
+    double *P1 = a.partials + kPartSpmv;
+    double *P2 = a.partials + kPartUpdate;
+    const bool vec = scaled_vec<T>(a);
+    const Chunks cu = chunks(vec ? a.n / V : a.n, (int64_t)kBlock * a.A->vec_it, kBlock);
+    if (vec)
+        HNS_TRY_HIP(launch_k(k_update<T, float, V, true>, cu.grid, kBlock, 0, s, eu, a.n, cu.per,
+                             (T *)a.r, (const T *)a.q, a.wjac, a.sc, (const double *)P1, Gs, P2,
+                             parity, a.token));
+    else
+        HNS_TRY_HIP(launch_k(k_update<T, float, 1, true>, cu.grid, kBlock, 0, s, eu, a.n, cu.per,
+                             (T *)a.r, (const T *)a.q, a.wjac, a.sc, (const double *)P1, Gs, P2,
+                             parity, a.token));
+    return HNS_OK;
+}
+
+template <typename T>
 hns_status iteration_scaled(const IterArgs &a, int parity, hipStream_t s, hipEvent_t *ev)
 {
     constexpr int V = 16 / sizeof(T);
     const uint8_t *bc = a.bit < 0 ? nullptr : a.bc;
     double *P1 = a.partials + kPartSpmv;
     double *P2 = a.partials + kPartUpdate;
-    const bool vec = aligned16(a.x) && aligned16(a.r) && aligned16(a.p) && aligned16(a.q) &&
-                     aligned16(a.wjac);
-    if ((sizeof(T) == 4 ? (const void *)a.A->dia32 : (const void *)a.A->dia) == nullptr) {
-        set_error("the Jacobi-scaled operator has no values in this precision");
-        return HNS_ERR_INVALID;
-    }
+    const bool vec = scaled_vec<T>(a);
+    HNS_TRY(scaled_values<T>(a));
     const Chunks cu = chunks(vec ? a.n / V : a.n, (int64_t)kBlock * a.A->vec_it, kBlock);
     const int Gs = spmv_dispatch<T, T, true>(*a.A, a.p, a.q, bc, a.bit, a.sc, P1, s,
                                              ev ? ev : nullptr, a.mf);
     if (Gs < 0) return spmv_failed("spmv (Jacobi-scaled)");
     hipEvent_t *eu = ev ? ev + 2 : nullptr, *ep = ev ? ev + 4 : nullptr;
-    if (vec) {
-        HNS_TRY_HIP(launch_k(k_update<T, float, V, true>, cu.grid, kBlock, 0, s, eu, a.n, cu.per,
-                             (T *)a.r, (const T *)a.q, a.wjac, a.sc, (const double *)P1, Gs, P2,
-                             parity, a.token));
+    HNS_TRY(launch_update_scaled<T>(a, parity, Gs, s, eu));
+    if (vec)
         HNS_TRY_HIP(launch_k(k_pupdate_x<T, float, V, true>, cu.grid, kBlock, 0, s, ep, a.n,
                              cu.per, (T *)a.x, (T *)a.p, (const T *)a.r, (const float *)nullptr,
                              a.sc, (const double *)P2, cu.grid, parity, a.token));
-    } else {
-        HNS_TRY_HIP(launch_k(k_update<T, float, 1, true>, cu.grid, kBlock, 0, s, eu, a.n, cu.per,
-                             (T *)a.r, (const T *)a.q, a.wjac, a.sc, (const double *)P1, Gs, P2,
-                             parity, a.token));
+    else
         HNS_TRY_HIP(launch_k(k_pupdate_x<T, float, 1, true>, cu.grid, kBlock, 0, s, ep, a.n,
                              cu.per, (T *)a.x, (T *)a.p, (const T *)a.r, (const float *)nullptr,
                              a.sc, (const double *)P2, cu.grid, parity, a.token));
-    }
     return check_launch("cg iteration (Jacobi-scaled)");
+}
+
+// The fused direction update + product for M upper diagonals (dispatch on M)
+template <typename T, int M = 1>
+hipError_t launch_sdia_dir(const IterArgs &a, const T *po, T *pn, uint32_t token, int parity,
+                           int G_in, hipStream_t s, hipEvent_t *ev2, int *grid)
+{
+    if constexpr (M <= kMaxDiag) {
+        if (a.A->ndiag != M)
+            return launch_sdia_dir<T, M + 1>(a, po, pn, token, parity, G_in, s, ev2, grid);
+        constexpr int R = sizeof(T) == 8 ? 2 : 1;
+        DiaOffsets offs;
+        for (int k = 0; k < kMaxDiag; ++k) offs.o[k] = k < a.A->ndiag ? a.A->off[k] : 0;
+        const Chunks c = sdia_chunks<T>(*a.A);
+        *grid = c.grid;
+        const T *dia = sizeof(T) == 4 ? (const T *)a.A->dia32 : (const T *)a.A->dia;
+        return launch_k(k_sdia_dir<T, M, R>, c.grid, kBlock, 0, s, ev2, a.n, c.per, offs, dia,
+                        po, (const T *)a.r, (T *)a.x, pn, (T *)a.p, (T *)a.q,
+                        a.bit < 0 ? (const uint8_t *)nullptr : a.bc, a.bit, a.sc,
+                        (const double *)(a.partials + kPartUpdate), G_in,
+                        a.partials + kPartSpmv, parity, token);
+    } else {
+        return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+hns_status scaled_fused_step_t(const IterArgs &a, const void *po, void *pn, uint32_t prev_token,
+                               int prev_parity, int parity, hipStream_t s, hipEvent_t *ev)
+{
+    HNS_TRY(scaled_values<T>(a));
+    int Gs = -1;
+    if (!po) {
+        // the chunk's first iteration: p is complete, the plain product
+        Gs = spmv_dispatch<T, T, true>(*a.A, a.p, a.q, a.bit < 0 ? nullptr : a.bc, a.bit, a.sc,
+                                       a.partials + kPartSpmv, s, ev, a.mf);
+        if (Gs < 0) return spmv_failed("spmv (Jacobi-scaled)");
+    } else {
+        constexpr int V = 16 / sizeof(T);
+        const bool vec = scaled_vec<T>(a);
+        const Chunks cu = chunks(vec ? a.n / V : a.n, (int64_t)kBlock * a.A->vec_it, kBlock);
+        if (launch_sdia_dir<T>(a, (const T *)po, (T *)pn, prev_token, prev_parity, cu.grid, s, ev,
+                               &Gs) != hipSuccess)
+            return spmv_failed("direction update + spmv (Jacobi-scaled)");
+    }
+    HNS_TRY(launch_update_scaled<T>(a, parity, Gs, s, ev ? ev + 2 : nullptr));
+    return check_launch("fused cg iteration (Jacobi-scaled)");
+}
+
+template <typename T>
+hns_status scaled_fused_close_t(const IterArgs &a, const void *po, uint32_t token, int parity,
+                                hipStream_t s)
+{
+    constexpr int V = 16 / sizeof(T);
+    const bool vec = scaled_vec<T>(a);
+    const Chunks cu = chunks(vec ? a.n / V : a.n, (int64_t)kBlock * a.A->vec_it, kBlock);
+    const Chunks c = sdia_chunks<T>(*a.A);
+    HNS_TRY_HIP(launch_k(k_sdia_dir_close<T>, c.grid, kBlock, 0, s, nullptr, a.n, c.per,
+                         (const T *)po, (const T *)a.r, (T *)a.x, (T *)a.p, a.sc,
+                         (const double *)(a.partials + kPartUpdate), cu.grid, parity, token));
+    return check_launch("direction update (Jacobi-scaled, end of chunk)");
 }
 
 }  // namespace
@@ -2729,6 +3030,37 @@ hns_status launch_iteration(const IterArgs &a, int parity, hipStream_t s, hipEve
     }
     set_error("unknown precision");
     return HNS_ERR_INVALID;
+}
+
+bool scaled_fusable(const IterArgs &a)
+{
+    return a.wjac && !a.lfac && !a.ic && a.A->unit && a.A->fmt == HNS_FMT_SDIA &&
+           a.A->ndiag >= 1 && a.A->ndiag <= kMaxDiag &&
+           (a.prec == Prec::F64 || a.prec == Prec::F32);
+}
+
+hns_status launch_scaled_fused_step(const IterArgs &a, const void *po, void *pn,
+                                    uint32_t prev_token, int prev_parity, int parity,
+                                    hipStream_t s, hipEvent_t *ev)
+{
+    if (!scaled_fusable(a)) {
+        set_error("the fused iteration runs CG on the unit-diagonal diagonal-storage operator");
+        return HNS_ERR_INVALID;
+    }
+    if (a.prec == Prec::F64)
+        return scaled_fused_step_t<double>(a, po, pn, prev_token, prev_parity, parity, s, ev);
+    return scaled_fused_step_t<float>(a, po, pn, prev_token, prev_parity, parity, s, ev);
+}
+
+hns_status launch_scaled_fused_close(const IterArgs &a, const void *po, uint32_t token,
+                                     int parity, hipStream_t s)
+{
+    if (!scaled_fusable(a)) {
+        set_error("the fused iteration runs CG on the unit-diagonal diagonal-storage operator");
+        return HNS_ERR_INVALID;
+    }
+    if (a.prec == Prec::F64) return scaled_fused_close_t<double>(a, po, token, parity, s);
+    return scaled_fused_close_t<float>(a, po, token, parity, s);
 }
 
 hns_status launch_bstats(int64_t n, const double *b, const uint8_t *bc, int bit, Scalars *sc,

@@ -42,6 +42,8 @@ struct Workspace {
     double *z = nullptr;          // M^-1 r of the line / IC(0) preconditioner (on first use)
     double *y = nullptr;          // scratch of the IC(0) triangular solves (on first use)
     double *mf = nullptr;         // element results of a matrix-free product (on first use)
+    double *p2 = nullptr;         // second direction buffer of the fused iterations (on first use)
+    bool fused = false;           // the last chunk ran fused iterations (two timed kernels)
     Scalars *sc = nullptr;        // [0] FP64 / outer loop, [1] inner FP32 loop
     Scalars *host = nullptr;      // pinned mirror of sc[0..1]
     std::vector<hipEvent_t> ev;   // timing events, a (start, end) pair per kernel of an iteration
@@ -157,10 +159,24 @@ struct Workspace {
         return HNS_OK;
     }
 
+    hns_status ensure_p2()
+    {
+        if (p2) return HNS_OK;
+        hipError_t e = hipMalloc(&p2, n * sizeof(double));
+        if (e != hipSuccess) {
+            p2 = nullptr;
+            set_error("allocation of the second direction buffer failed: %s",
+                      hipGetErrorString(e));
+            return e == hipErrorOutOfMemory ? HNS_ERR_OOM : HNS_ERR_HIP;
+        }
+        return HNS_OK;
+    }
+
     ~Workspace()
     {
         for (hipEvent_t e : ev) (void)hipEventDestroy(e);
         if (borrowed) return;
+        if (p2) (void)hipFree(p2);
         if (z) (void)hipFree(z);
         if (y) (void)hipFree(y);
         if (mf) (void)hipFree(mf);
@@ -267,6 +283,20 @@ static bool small_chunks(const hns_operator *op, const Workspace *w, Prec prec, 
            op->A.fmt != HNS_MATRIX_FREE && (prec == Prec::F64 || prec == Prec::F32);
 }
 
+// Fused scaled iterations (two launches each, the direction update inside the
+// next product): automatic ("fuse_dir" = -1) while one vector of the
+// recurrence is at most 4 MiB.  Measured on the basin operators (15-point
+// stencil, MI355X): 1.04-1.27x per iteration up to that size, where the
+// launch and the vector pass saved outweigh the neighbours' r and p loads
+// the product adds; even or slower beyond it (FP64 0.94x at 1.39M rows).
+constexpr size_t kFuseBytes = size_t(4) << 20;
+
+static bool fuse_wanted(const hns_operator *op, bool fp32)
+{
+    if (op->fuse_dir >= 0) return op->fuse_dir == 1;
+    return (size_t)op->n * (fp32 ? sizeof(float) : sizeof(double)) <= kFuseBytes;
+}
+
 static hns_status enqueue_iterations(hns_operator *op, Workspace *w, Prec prec, int bit, void *x,
                                      void *r, void *p, void *q, const void *dinv, Scalars *sc,
                                      int count, int parity0, hipStream_t s,
@@ -297,6 +327,27 @@ static hns_status enqueue_iterations(hns_operator *op, Workspace *w, Prec prec, 
     // sampled: the iteration in the middle of each period window, so a chunk's
     // first iteration (launched after the host's read of the previous chunk,
     // on an idle GPU) is never timed unless every iteration is
+    w->fused = scaled && fuse_wanted(op, prec == Prec::F32) && !w->borrowed && scaled_fusable(a);
+    if (w->fused) {
+        // two launches per iteration, p alternating between p and p2
+        if (count <= 0) return HNS_OK;
+        HNS_TRY(w->ensure_p2());
+        void *bufs[2] = {p, w->p2};
+        uint32_t prev_token = 0;
+        int prev_parity = 0;
+        for (int it = 0; it < count; ++it) {
+            const bool timed = period > 0 && (it % period) == period / 2;
+            if (++w->token == 0) w->token = 1;
+            a.token = w->token;
+            const int parity = (parity0 + it) & 1;
+            HNS_TRY(launch_scaled_fused_step(a, it == 0 ? nullptr : bufs[(it - 1) & 1],
+                                             bufs[it & 1], prev_token, prev_parity, parity, s,
+                                             timed ? &w->ev[6 * it] : nullptr));
+            prev_token = a.token;
+            prev_parity = parity;
+        }
+        return launch_scaled_fused_close(a, bufs[(count - 1) & 1], prev_token, prev_parity, s);
+    }
     for (int it = 0; it < count; ++it) {
         const bool timed = period > 0 && (it % period) == period / 2;
         if (++w->token == 0) w->token = 1;   // unique per workspace, never 0
@@ -314,8 +365,9 @@ static hns_status account_iterations(hns_operator *op, Workspace *w, bool fp32, 
     const int period = w->borrowed ? 0 : op->profile;
     if (period <= 0 || done <= 0) return HNS_OK;
     const int base = fp32 ? 3 : 0;
+    const int kernels = w->fused ? 2 : 3;   // fused: product (with the direction update), update
     for (int it = period / 2; it < done; it += period)
-        for (int k = 0; k < 3; ++k) {
+        for (int k = 0; k < kernels; ++k) {
             float ms = 0.0f;
             HNS_TRY_HIP(hipEventElapsedTime(&ms, w->ev[6 * it + 2 * k], w->ev[6 * it + 2 * k + 1]));
             op->prof_ms[base + k] += ms;
@@ -885,6 +937,8 @@ size_t slot_session_bytes(const hns_operator *op, int capacity, bool mixed)
         per += n * sizeof(double);                                          // z
     else if (session_scaled(op, mixed) && !mixed)
         per += n * sizeof(double);                                          // scaled correction
+    if (!session_line(op) && session_scaled(op, mixed) && fuse_wanted(op, mixed))
+        per += n * sizeof(double);                                          // second p buffer
     return per * (size_t)capacity + 256;
 }
 
@@ -1532,6 +1586,8 @@ hns_status hns_set_param(hns_operator *op, const char *name, double value)
         op->A.vec_it = op->S.vec_it = (int)value;
     } else if (k == "jacobi_scaling" && (value == 0 || value == 1)) {
         op->jacobi_scaling = (int)value;
+    } else if (k == "fuse_dir" && (value == -1 || value == 0 || value == 1)) {
+        op->fuse_dir = (int)value;
     } else if (k == "session_mode" && (value == 0 || value == 1 || value == 2)) {
         op->session_mode = (int)value;
     } else if (k == "small_n" && value >= 0 && value <= (double)kSmallMaxN &&
@@ -1570,6 +1626,11 @@ size_t hns_footprint_bytes(const hns_operator *op, int k, uint32_t mode, int inc
     if (k == 1 && op->precond == 1) b += (size_t)op->n * sizeof(double);       // z
     if (k == 1 && op->precond == 2) b += 2 * (size_t)op->n * sizeof(double);   // z, y
     if (k == 1) b += op->A.mf_scratch() * sizeof(double);   // matrix-free element results
+    // the second direction buffer of the fused scaled iterations
+    if (k == 1 && op->jacobi_scaling && op->precond == 0 && op->A.fmt == HNS_FMT_SDIA &&
+        op->A.ndiag >= 1 && op->A.ndiag <= kMaxDiag && op->n > op->small_n &&
+        fuse_wanted(op, mixed))
+        b += (size_t)op->n * sizeof(double);
     if (include_operator) {
         for (const double *f : op->line_fac)
             if (f) b += 2 * (size_t)op->n * sizeof(double);

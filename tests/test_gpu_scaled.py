@@ -195,3 +195,72 @@ def test_scaled_profiled_zero_rhs_and_bad_value(dev):
     with pytest.raises(HNSError):
         op.set_param("jacobi_scaling", 2)
     op.close()
+
+
+# The fused form (fuse_dir): two launches per iteration, the direction update
+# inside the next product with every neighbour's r + beta p recomputed where
+# it is read, p alternating between two buffers.  Same arithmetic: answers,
+# iteration counts and scalars equal the three-launch form's bit for bit,
+# whichever buffer a chunk or a stop ends in (odd and one-iteration chunks,
+# a budget that ends inside a chunk, the mixed recurrence whose direction is
+# kept across residual replacements).
+FUSE_CASES = [
+    # (bit, mode, check_every, max_iter)
+    (-1, "fp64", 32, 100000),
+    (-1, "mixed", 32, 100000),
+    (0, "fp64", 1, 100000),
+    (2, "fp64", 3, 100000),
+    (1, "mixed", 7, 100000),
+    (-1, "fp64", 32, 37),
+]
+
+
+@pytest.mark.parametrize("case", FUSE_CASES,
+                         ids=[f"bit{c[0]}-{c[1]}-ce{c[2]}-max{c[3]}" for c in FUSE_CASES])
+def test_fused_iterations_equal_three_launch_form(dev, case):
+    bit, mode, check_every, max_iter = case
+    m = basin.basin_mesh(23, 17, 5, seed=7)   # 2,592 rows: ragged against every tile
+    kind, A, d, b, w = _system(m, bit, 70 + bit)
+    op = _operator(m, kind, 0, 1, keep_fp32=True)
+    op.set_param("check_every", check_every)
+    got = {}
+    for fuse in (0, 1):
+        op.set_param("fuse_dir", fuse)
+        x, info = op.solve(_gpu(b, dev), tol=1e-10, mask_bit=bit, mode=mode, max_iter=max_iter,
+                           check=False)
+        got[fuse] = (x, info)
+    op.close()
+    (x0, i0), (x1, i1) = got[0], got[1]
+    assert i0.status == i1.status and i0.iterations == i1.iterations
+    assert i0.outer_iterations == i1.outer_iterations
+    assert torch.equal(x0, x1)
+    if max_iter < 100000:
+        assert i1.iterations == max_iter
+    else:
+        assert i1.status == 0
+        ref = oracle.pcg(A, b, dirichlet=d, singular=bit < 0, weights=w, tol=1e-10)
+        assert abs(i1.iterations - ref.iterations) <= max(1, 0.02 * ref.iterations)
+
+
+def test_fused_iterations_automatic_by_size(dev):
+    """fuse_dir = -1 fuses while a vector takes at most 4 MiB: the timed
+    kernels show two launches per iteration (no separate direction update)
+    on a small operator, three when fusion is off; a bad value is refused."""
+    from paper_1207_0486_amd.hns import HNSError
+    m = basin.basin_mesh(23, 17, 5, seed=7)
+    kind, A, d, b, w = _system(m, -1, 80)
+    op = _operator(m, kind, 0, 1)
+    counts = {}
+    for fuse in (-1, 0):
+        op.set_param("fuse_dir", fuse)
+        op.profile(1)
+        x, info = op.solve(_gpu(b, dev), tol=1e-10)
+        prof = op.profile_read()
+        op.profile(0)
+        counts[fuse] = (prof["spmv"][1], prof["pupdate"][1], info.iterations)
+    assert counts[-1][0] > 0 and counts[-1][1] == 0
+    assert counts[0][0] > 0 and counts[0][1] > 0
+    assert counts[-1][2] == counts[0][2]
+    with pytest.raises(HNSError):
+        op.set_param("fuse_dir", 2)
+    op.close()
