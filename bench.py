@@ -433,6 +433,54 @@ def bench_batched(torch, log, reps=3):
     return out
 
 
+def bench_formats(torch, log, m, b_q, sdia_us, iters=320, period=8):
+    """The headline pressure operator (256x256x20, K_nu, pure Neumann) stored
+    in CSR and in sliced ELL instead of symmetric diagonal storage: the same
+    point-Jacobi recurrence (unscaled: Jacobi scaling is for diagonal storage),
+    `iters` iterations from x0 = 0 (the step's pressure right-hand side) after
+    a 32-iteration warm-up.  Per format: the SpMV's average duration over the
+    sampled iterations (every `period`-th, HIP events on the solve stream),
+    its algorithmic bytes (values, column indices and row pointers of the nnz
+    entries plus p in and q out; sliced ELL also reads its padding, which is
+    not counted), GB/s and fraction of the 8 TB/s peak, and the wall time per
+    iteration of an unprofiled run."""
+    import basin
+    from paper_1207_0486_amd.hns import Operator
+    wl = basin.configs.BASIN_256x256x20
+    out = {"workload": wl.name, "iterations": iters,
+           "sdia_scaled_spmv_us": sdia_us}
+    for fmt in ("csr", "sell"):
+        t0 = time.time()
+        op = Operator(m, wl.nu_h, wl.nu_v, kind="poisson", fmt=fmt)
+        setup = time.time() - t0
+        assert op.format == fmt
+        op.solve(b_q, tol=1e-30, max_iter=32, check=False)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, info = op.solve(b_q, tol=1e-30, max_iter=iters, check=False)
+        torch.cuda.synchronize()
+        per_iter = (time.perf_counter() - t) / max(info.iterations, 1)
+        op.profile(period)
+        op.solve(b_q, tol=1e-30, max_iter=iters, check=False)
+        torch.cuda.synchronize()
+        prof = op.profile_read()
+        op.profile(0)
+        ms, cnt = prof["spmv"]
+        avg_us = 1e3 * ms / max(cnt, 1)
+        nb = bytes_spmv(fmt, op.n, op.nnz, 8)
+        gbs = nb / (avg_us * 1e-6) / 1e9
+        out[fmt] = {"spmv_avg_us": round(avg_us, 2), "spmv_launches_timed": cnt,
+                    "bytes_per_spmv": nb, "spmv_GBs": round(gbs, 1),
+                    "frac": round(gbs / 8000.0, 4),
+                    "us_per_iteration": round(1e6 * per_iter, 2),
+                    "update_us": round(1e3 * prof["update"][0] / max(prof["update"][1], 1), 2),
+                    "pupdate_us": round(1e3 * prof["pupdate"][0] / max(prof["pupdate"][1], 1), 2),
+                    "setup_s": round(setup, 2)}
+        op.close()
+    log(f"formats: {out}")
+    return out
+
+
 def bench_isotropic(torch, log, m, b_q, point_cap=3000):
     """The paper's isotropic pressure Laplacian (nu = 1) on the 256x256x20 basin
     with the projection step's pressure right-hand side: vertical-line block
@@ -932,6 +980,8 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-isotropic", action="store_true")
+    ap.add_argument("--no-formats", action="store_true",
+                    help="skip the CSR / sliced-ELL pressure operator section")
     ap.add_argument("--no-loop", action="store_true")
     ap.add_argument("--no-precond", action="store_true")
     ap.add_argument("--no-bricks", action="store_true")
@@ -1138,6 +1188,10 @@ def main():
         op_a.close()
     log(f"pressure operator set-up: {setup}")
 
+    formats = None
+    if not args.no_formats:
+        formats = bench_formats(torch, log, m, st.b_q.clone(), kern["spmv"]["avg_us"])
+
     isotropic = None
     if not args.no_isotropic:
         isotropic = bench_isotropic(torch, log, m, st.b_q.clone())
@@ -1235,6 +1289,7 @@ def main():
         "mixed": mixed,
         "line_pressure_step": line_step,
         "operator_setup": setup,
+        "pressure_formats": formats,
         "isotropic_pressure": isotropic,
         "velocity_preconditioners": precond,
         "small_box": small_box,
