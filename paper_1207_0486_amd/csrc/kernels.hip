@@ -40,12 +40,36 @@
 namespace hns {
 namespace {
 
-__device__ __forceinline__ double wave_sum(double v)
+// One DPP move of a double (both 32-bit halves): lanes whose source lies
+// outside the pattern (bound_ctrl) or whose row is masked off read 0.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_move(double v)
 {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROW_MASK, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROW_MASK, 0xf, true);
+    return __hiloint2double(hi, lo);
 }
+
+// Wavefront sum through the DPP network instead of LDS permutes (all 64
+// lanes active): row_shr 1, 2, 4, 8 leave each 16-lane row's sum in its
+// lane 15, row_bcast 15 adds row 0's into row 1 and row 2's into row 3, and
+// row_bcast 31 adds lane 31's into rows 2 and 3, so lane 63 holds the total,
+// which every lane then reads.  A fixed order, the same in every wavefront.
+__device__ __forceinline__ double wave_sum_dpp(double v)
+{
+    v += dpp_move<0x111, 0xf>(v);   // row_shr:1
+    v += dpp_move<0x112, 0xf>(v);   // row_shr:2
+    v += dpp_move<0x114, 0xf>(v);   // row_shr:4
+    v += dpp_move<0x118, 0xf>(v);   // row_shr:8
+    v += dpp_move<0x142, 0xa>(v);   // row_bcast:15
+    v += dpp_move<0x143, 0xc>(v);   // row_bcast:31
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+    return __hiloint2double(hi, lo);
+}
+
+// Every block reduction of the path calls this with all 64 lanes active.
+__device__ __forceinline__ double wave_sum(double v) { return wave_sum_dpp(v); }
 
 // Sums NV values over the block; the totals are valid in thread 0.
 template <int NV>
@@ -2635,14 +2659,17 @@ struct SmallMat {
 };
 
 // Sum over the 16 wavefronts of the workgroup; every thread reads the 16
-// wave sums in the same order, so all obtain bit-identical totals.
+// wave sums in the same order, so all obtain bit-identical totals.  No
+// barrier follows the reads: each call site of an iteration has its own
+// slots, and the block passes at least one other barrier before that site
+// writes them again.
 template <int NV>
 __device__ __forceinline__ void small_block_sum(double (&v)[NV], double *lds)
 {
     constexpr int NW = kSmallBlock / 64;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
-    for (int k = 0; k < NV; ++k) v[k] = wave_sum(v[k]);
+    for (int k = 0; k < NV; ++k) v[k] = wave_sum_dpp(v[k]);
     if (lane == 0) {
 #pragma unroll
         for (int k = 0; k < NV; ++k) lds[k * NW + wid] = v[k];
@@ -2654,7 +2681,6 @@ __device__ __forceinline__ void small_block_sum(double (&v)[NV], double *lds)
         for (int w = 0; w < NW; ++w) t += lds[k * NW + w];
         v[k] = t;
     }
-    __syncthreads();
 }
 
 // Row i of A p: diagonal storage in the order main, (upper, lower) per offset
@@ -2700,7 +2726,7 @@ __global__ __launch_bounds__(kSmallBlock) void k_cg_small(SmallMat A, const TV *
                                                           Scalars *__restrict__ sc, int count,
                                                           int parity)
 {
-    __shared__ double lds[2 * (kSmallBlock / 64)];
+    __shared__ double lds[3 * (kSmallBlock / 64)];   // p^T q, then r^T z and r^T r
     if (sc->stop) return;
     const int64_t n = A.n;
     double rho[2] = {sc->rho[0], sc->rho[1]};
@@ -2731,7 +2757,7 @@ __global__ __launch_bounds__(kSmallBlock) void k_cg_small(SmallMat A, const TV *
             v2[0] += (double)ri * (double)zi;
             v2[1] += (double)ri * (double)ri;
         }
-        small_block_sum<2>(v2, lds);
+        small_block_sum<2>(v2, lds + kSmallBlock / 64);
         const double rho_new = v2[0];
         rr = v2[1];
         const bool bad = !isfinite(rho_new) || !isfinite(rr);
@@ -2784,7 +2810,7 @@ __global__ __launch_bounds__(kSmallBlock) void k_cg_small_lds(
     const size_t vbytes = ((size_t)nv * sizeof(TV) + 15) & ~size_t(15);
     TV *svals = reinterpret_cast<TV *>(small_dyn);
     TX *sp = reinterpret_cast<TX *>(small_dyn + vbytes);
-    __shared__ double lds[2 * (kSmallBlock / 64)];
+    __shared__ double lds[3 * (kSmallBlock / 64)];   // p^T q, then r^T z and r^T r
     if (sc->stop) return;
     const int64_t n = A.n;
     if constexpr (VL)
@@ -2842,7 +2868,7 @@ __global__ __launch_bounds__(kSmallBlock) void k_cg_small_lds(
                 v2[1] += (double)ri * (double)ri;
             }
         }
-        small_block_sum<2>(v2, lds);
+        small_block_sum<2>(v2, lds + kSmallBlock / 64);
         const double rho_new = v2[0];
         rr = v2[1];
         const bool bad = !isfinite(rho_new) || !isfinite(rr);

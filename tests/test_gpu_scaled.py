@@ -242,6 +242,25 @@ def test_fused_iterations_equal_three_launch_form(dev, case):
         assert abs(i1.iterations - ref.iterations) <= max(1, 0.02 * ref.iterations)
 
 
+@pytest.mark.parametrize("mode", ["fp64", "mixed"])
+def test_fused_iterations_tiny_mesh(dev, mode):
+    """A mesh whose rows all lie within the largest offset of an end (every
+    row takes the per-row path of the product): the fused form still equals
+    the three-launch form bit for bit."""
+    m = basin.box_mesh(2, 2, 1)   # 18 rows, largest offset 9
+    kind, A, d, b, w = _system(m, -1, 90)
+    op = _operator(m, kind, 0, 1, keep_fp32=True)
+    assert op.format == "sdia" and op.n == 18
+    got = {}
+    for fuse in (0, 1):
+        op.set_param("fuse_dir", fuse)
+        got[fuse] = op.solve(_gpu(b, dev), tol=1e-10, mode=mode)
+    op.close()
+    (x0, i0), (x1, i1) = got[0], got[1]
+    assert i0.status == i1.status == 0 and i0.iterations == i1.iterations
+    assert torch.equal(x0, x1)
+
+
 def test_fused_iterations_automatic_by_size(dev):
     """fuse_dir = -1 fuses while a vector takes at most 4 MiB: the timed
     kernels show two launches per iteration (no separate direction update)
