@@ -230,13 +230,37 @@ __global__ __launch_bounds__(256) void k_inc_fill(int64_t ne, const int32_t *__r
 }
 
 // Each node's list in ascending tetrahedron order (insertion sort: a list
-// holds the few tetrahedra around one node).
+// holds the few tetrahedra around one node, 24 in the interior of a Kuhn
+// lattice).  A list of up to kSortSlot entries is sorted in the thread's
+// slot of LDS (entry k at buf[k * 256 + thread], so the lanes of a wavefront
+// hit distinct banks) and read and written once; a longer one is sorted in
+// place in global memory.  The result, ascending order of distinct values,
+// is unique either way.
+constexpr int kSortSlot = 48;
+
 __global__ __launch_bounds__(256) void k_inc_sort(int64_t n, const uint32_t *__restrict__ ptr,
                                                   int32_t *__restrict__ itet)
 {
+    __shared__ int32_t buf[kSortSlot * 256];
+    int32_t *mine = buf + threadIdx.x;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         const uint32_t lo = ptr[i], hi = ptr[i + 1];
+        const uint32_t len = hi - lo;
+        if (len <= (uint32_t)kSortSlot) {
+            for (uint32_t k = 0; k < len; ++k) mine[k * 256] = itet[lo + k];
+            for (uint32_t s = 1; s < len; ++s) {
+                const int32_t t = mine[s * 256];
+                uint32_t r = s;
+                while (r > 0 && mine[(r - 1) * 256] > t) {
+                    mine[r * 256] = mine[(r - 1) * 256];
+                    --r;
+                }
+                mine[r * 256] = t;
+            }
+            for (uint32_t k = 0; k < len; ++k) itet[lo + k] = mine[k * 256];
+            continue;
+        }
         for (uint32_t s = lo + 1; s < hi; ++s) {
             const int32_t t = itet[s];
             uint32_t r = s;
