@@ -56,7 +56,10 @@ def test_small_chunk_matches_multi_launch_and_oracle(dev, fmt, bit):
         b = basin.normal_rhs(m.n, 5 + bit, dirichlet=d, zero_mean=bit < 0)
         (xs, i_s), (xm, i_m) = _both(op, b, dev, tol=1e-10, mask_bit=bit)
         assert i_s.status == 0 and i_m.status == 0
-        assert abs(i_s.iterations - i_m.iterations) <= 1
+        # the two forms sum their dot products in different orders; on the
+        # singular pressure problems (400+ iterations) that moves the
+        # stopping iteration by a few, as against the oracle (2 % there)
+        assert abs(i_s.iterations - i_m.iterations) <= max(1, 0.01 * i_m.iterations)
         assert _rel(xs, xm) <= 1e-9
         A = (oracle.helmholtz(m, nu[0], nu[1], 3600.0) if kind == "helmholtz"
              else oracle.stiffness(m, nu[0], nu[1]))
