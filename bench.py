@@ -481,6 +481,41 @@ def bench_formats(torch, log, m, b_q, sdia_us, iters=320, period=8):
     return out
 
 
+def bench_shard_share(torch, log, iters=400, reps=3):
+    """One GPU's share of the 256x256x20 basin split over 8 GPUs by column
+    blocks, stood in for by a 128x64x20 basin (the same 176,085 rows and
+    15-point stencil; its cells are twice as long in x): the pressure recurrence's time
+    per iteration (`iters` iterations from x0 = 0, median of `reps`), FP64
+    and mixed, in two launches per iteration (the default at this size) and
+    in three: the per-GPU floor a multi-GPU split would add its halo
+    exchange and all-reduces to."""
+    import basin
+    from paper_1207_0486_amd.hns import Operator
+    wl = basin.configs.BASIN_256x256x20
+    m = basin.basin_mesh(128, 64, 20, L=wl.L, seed=wl.seed)
+    op = Operator(m, wl.nu_h, wl.nu_v, kind="poisson", keep_fp32=True)
+    b = torch.as_tensor(basin.normal_rhs(m.n, 0, zero_mean=True), device="cuda")
+    out = {"workload": "basin128x64x20 (the row count and stencil of one of 8 column blocks of "
+                       "basin256x256x20)",
+           "nodes": m.n, "iterations": iters}
+    for mode in ("fp64", "mixed"):
+        for label, fuse in (("two_launches", -1), ("three_launches", 0)):
+            op.set_param("fuse_dir", fuse)
+            ts = []
+            for k in range(reps + 1):
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                _, info = op.solve(b, tol=1e-30, max_iter=iters, mode=mode, check=False)
+                torch.cuda.synchronize()
+                if k:
+                    ts.append(time.perf_counter() - t)
+            out.setdefault(mode, {})[f"us_per_iteration_{label}"] = round(
+                1e6 * float(np.median(ts)) / max(info.iterations, 1), 2)
+    op.close()
+    log(f"shard share: {out}")
+    return out
+
+
 def bench_isotropic(torch, log, m, b_q, point_cap=3000):
     """The paper's isotropic pressure Laplacian (nu = 1) on the 256x256x20 basin
     with the projection step's pressure right-hand side: vertical-line block
@@ -982,6 +1017,8 @@ def main():
     ap.add_argument("--no-isotropic", action="store_true")
     ap.add_argument("--no-formats", action="store_true",
                     help="skip the CSR / sliced-ELL pressure operator section")
+    ap.add_argument("--no-share", action="store_true",
+                    help="skip the one-GPU-share (128x64x20) per-iteration section")
     ap.add_argument("--no-loop", action="store_true")
     ap.add_argument("--no-precond", action="store_true")
     ap.add_argument("--no-bricks", action="store_true")
@@ -1188,6 +1225,10 @@ def main():
         op_a.close()
     log(f"pressure operator set-up: {setup}")
 
+    share = None
+    if not args.no_share:
+        share = bench_shard_share(torch, log)
+
     formats = None
     if not args.no_formats:
         formats = bench_formats(torch, log, m, st.b_q.clone(), kern["spmv"]["avg_us"])
@@ -1290,6 +1331,7 @@ def main():
         "line_pressure_step": line_step,
         "operator_setup": setup,
         "pressure_formats": formats,
+        "shard_share": share,
         "isotropic_pressure": isotropic,
         "velocity_preconditioners": precond,
         "small_box": small_box,
