@@ -386,9 +386,10 @@ int hns_operator_assembly(const hns_operator *op);
  *   "spmv_it32"    FP64 / FP32 vectors: workgroup-sized row passes per block
  *                  (defaults 1 and 2; integers 1..64)
  *   "vec_it"       16-byte packs per thread of the single-vector CG updates
- *                  (default 3; integers 1..64).  The three change the grid
- *                  (and with it the summation order of the dot products),
- *                  not the arithmetic of a row or a pack.
+ *                  (integers 1..64; default 0 = by size: 1 below 250000
+ *                  rows, 2 below 1000000, 3 above).  The three change the
+ *                  grid (and with it the summation order of the dot
+ *                  products), not the arithmetic of a row or a pack.
  *   "small_n"      point-Jacobi FP64 / FP32 single right-hand-side solves of
  *                  operators with at most this many rows run each chunk of
  *                  iterations in one workgroup (one launch per chunk instead

@@ -87,7 +87,11 @@ struct DevMatrix {
     // 16-byte packs per thread of the vector updates
     int spmv_it64 = 1;
     int spmv_it32 = 2;
-    int vec_it = 3;
+    int vec_it = 0;   // 0: by size, vec_packs()
+    // packs per thread of the vector updates: vec_it when set, else more
+    // workgroups on smaller operators (measured per pressure iteration on the
+    // basin operators: 1 pack below 250K rows, 2 below 1M, 3 above)
+    int vec_packs() const { return vec_it > 0 ? vec_it : n < 250000 ? 1 : n < 1000000 ? 2 : 3; }
     // matrix-free bricks (fmt == HNS_MATRIX_FREE): the product is computed
     // element by element; per element its (order+1)^3 nodes (mf_nodes) and
     // its 8 corner coordinates (mf_corner, 24 doubles); the (element, local

@@ -2277,12 +2277,12 @@ hns_status launch_pupdate_line_x(const IterArgs &a, int parity, int G_in, hipStr
     constexpr int V = 16 / sizeof(T);
     double *P2 = a.partials + kPartUpdate;
     if (aligned16(a.x)) {
-        const Chunks cp = chunks(a.n / V, (int64_t)kBlock * a.A->vec_it, kBlock);
+        const Chunks cp = chunks(a.n / V, (int64_t)kBlock * a.A->vec_packs(), kBlock);
         HNS_TRY_HIP(launch_k(k_pupdate_line_x<T, V>, cp.grid, kBlock, 0, s, ev2, a.n, cp.per,
                              (T *)a.x, (T *)a.p, (const T *)a.z, a.sc, (const double *)P2, G_in,
                              parity, a.token));
     } else {
-        const Chunks cp = chunks(a.n, (int64_t)kBlock * a.A->vec_it, kBlock);
+        const Chunks cp = chunks(a.n, (int64_t)kBlock * a.A->vec_packs(), kBlock);
         HNS_TRY_HIP(launch_k(k_pupdate_line_x<T, 1>, cp.grid, kBlock, 0, s, ev2, a.n, cp.per,
                              (T *)a.x, (T *)a.p, (const T *)a.z, a.sc, (const double *)P2, G_in,
                              parity, a.token));
@@ -2337,7 +2337,7 @@ hns_status ic0_iteration(const IterArgs &a, int parity, hipStream_t s, hipEvent_
     double *P2 = a.partials + kPartUpdate;
     const bool vec = aligned16(a.x) && aligned16(a.r) && aligned16(a.p) && aligned16(a.q) &&
                      aligned16(a.z);
-    const Chunks cu = chunks(vec ? a.n / 2 : a.n, (int64_t)kBlock * a.A->vec_it, kBlock);
+    const Chunks cu = chunks(vec ? a.n / 2 : a.n, (int64_t)kBlock * a.A->vec_packs(), kBlock);
     const int Gs = spmv_dispatch<double, double, true>(*a.A, a.p, a.q, bc, a.bit, a.sc, P1, s,
                                                        ev ? ev : nullptr, a.mf);
     if (Gs < 0) return spmv_failed("spmv");
@@ -2372,7 +2372,7 @@ hns_status iteration_impl(const IterArgs &a, int parity, hipStream_t s, hipEvent
     // odd is not): fall back to one element per thread then
     const bool vec = aligned16(a.x) && aligned16(a.r) && aligned16(a.p) && aligned16(a.q) &&
                      aligned16(a.dinv);
-    const Chunks cu = chunks(vec ? a.n / V : a.n, (int64_t)kBlock * a.A->vec_it, kBlock);
+    const Chunks cu = chunks(vec ? a.n / V : a.n, (int64_t)kBlock * a.A->vec_packs(), kBlock);
     const int Gs = spmv_dispatch<TV, TX, true>(*a.A, a.p, a.q, bc, a.bit, a.sc, P1, s,
                                                ev ? ev : nullptr, a.mf);
     if (Gs < 0) return spmv_failed("spmv");
@@ -2424,7 +2424,7 @@ hns_status launch_update_scaled(const IterArgs &a, int parity, int Gs, hipStream
     double *P1 = a.partials + kPartSpmv;
     double *P2 = a.partials + kPartUpdate;
     const bool vec = scaled_vec<T>(a);
-    const Chunks cu = chunks(vec ? a.n / V : a.n, (int64_t)kBlock * a.A->vec_it, kBlock);
+    const Chunks cu = chunks(vec ? a.n / V : a.n, (int64_t)kBlock * a.A->vec_packs(), kBlock);
     if (vec)
         HNS_TRY_HIP(launch_k(k_update<T, float, V, true>, cu.grid, kBlock, 0, s, eu, a.n, cu.per,
                              (T *)a.r, (const T *)a.q, a.wjac, a.sc, (const double *)P1, Gs, P2,
@@ -2445,7 +2445,7 @@ hns_status iteration_scaled(const IterArgs &a, int parity, hipStream_t s, hipEve
     double *P2 = a.partials + kPartUpdate;
     const bool vec = scaled_vec<T>(a);
     HNS_TRY(scaled_values<T>(a));
-    const Chunks cu = chunks(vec ? a.n / V : a.n, (int64_t)kBlock * a.A->vec_it, kBlock);
+    const Chunks cu = chunks(vec ? a.n / V : a.n, (int64_t)kBlock * a.A->vec_packs(), kBlock);
     const int Gs = spmv_dispatch<T, T, true>(*a.A, a.p, a.q, bc, a.bit, a.sc, P1, s,
                                              ev ? ev : nullptr, a.mf);
     if (Gs < 0) return spmv_failed("spmv (Jacobi-scaled)");
@@ -2500,7 +2500,7 @@ hns_status scaled_fused_step_t(const IterArgs &a, const void *po, void *pn, uint
     } else {
         constexpr int V = 16 / sizeof(T);
         const bool vec = scaled_vec<T>(a);
-        const Chunks cu = chunks(vec ? a.n / V : a.n, (int64_t)kBlock * a.A->vec_it, kBlock);
+        const Chunks cu = chunks(vec ? a.n / V : a.n, (int64_t)kBlock * a.A->vec_packs(), kBlock);
         if (launch_sdia_dir<T>(a, (const T *)po, (T *)pn, prev_token, prev_parity, cu.grid, s, ev,
                                &Gs) != hipSuccess)
             return spmv_failed("direction update + spmv (Jacobi-scaled)");
@@ -2515,7 +2515,7 @@ hns_status scaled_fused_close_t(const IterArgs &a, const void *po, uint32_t toke
 {
     constexpr int V = 16 / sizeof(T);
     const bool vec = scaled_vec<T>(a);
-    const Chunks cu = chunks(vec ? a.n / V : a.n, (int64_t)kBlock * a.A->vec_it, kBlock);
+    const Chunks cu = chunks(vec ? a.n / V : a.n, (int64_t)kBlock * a.A->vec_packs(), kBlock);
     const Chunks c = sdia_chunks<T>(*a.A);
     HNS_TRY_HIP(launch_k(k_sdia_dir_close<T>, c.grid, kBlock, 0, s, nullptr, a.n, c.per,
                          (const T *)po, (const T *)a.r, (T *)a.x, (T *)a.p, a.sc,

@@ -662,7 +662,7 @@ struct ChunkedSolve {
             else if (c.lfac32)
                 HNS_TRY(launch_replace_line(op->n, op->line_len, w->r, w->r32, (float *)w->z,
                                             w->p32, c.lfac32, w->sc + 1, w->partials,
-                                            (since - 1) & 1, op->A.vec_it, c.s));
+                                            (since - 1) & 1, op->A.vec_packs(), c.s));
             else
                 HNS_TRY(launch_replace_residual(op->n, Prec::F32, w->r, w->r32, w->p32,
                                                 op->dinv32, w->sc + 1, w->partials,
@@ -1582,7 +1582,7 @@ hns_status hns_set_param(hns_operator *op, const char *name, double value)
         op->A.spmv_it64 = op->S.spmv_it64 = (int)value;
     } else if (k == "spmv_it32" && value >= 1 && value <= 64 && value == (int)value) {
         op->A.spmv_it32 = op->S.spmv_it32 = (int)value;
-    } else if (k == "vec_it" && value >= 1 && value <= 64 && value == (int)value) {
+    } else if (k == "vec_it" && value >= 0 && value <= 64 && value == (int)value) {
         op->A.vec_it = op->S.vec_it = (int)value;
     } else if (k == "jacobi_scaling" && (value == 0 || value == 1)) {
         op->jacobi_scaling = (int)value;
