@@ -385,11 +385,16 @@ int hns_operator_assembly(const hns_operator *op);
  *   "spmv_it64"    launch shape of the single-vector diagonal-storage SpMV with
  *   "spmv_it32"    FP64 / FP32 vectors: workgroup-sized row passes per block
  *                  (defaults 1 and 2; integers 1..64)
+ *   "spmv_rows64"  rows per lane of the FP64-vector diagonal-storage SpMV
+ *                  (1 or 2; default 0 = by size: 1 below 250000 rows, where
+ *                  the product is latency-bound and wants more workgroups,
+ *                  else 2 with 16-byte loads)
  *   "vec_it"       16-byte packs per thread of the single-vector CG updates
  *                  (integers 1..64; default 0 = by size: 1 below 250000
  *                  rows, 2 below 1000000, 3 above).  The three change the
  *                  grid (and with it the summation order of the dot
- *                  products), not the arithmetic of a row or a pack.
+ *                  products), not the arithmetic of a row or a pack; so
+ *                  does "spmv_rows64".
  *   "small_n"      point-Jacobi FP64 / FP32 single right-hand-side solves of
  *                  operators with at most this many rows run each chunk of
  *                  iterations in one workgroup (one launch per chunk instead

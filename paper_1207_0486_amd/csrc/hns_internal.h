@@ -52,6 +52,10 @@ struct HostCSR {
 // ---------------------------------------------------------------------------
 // Device matrix in one of the storage formats, FP64 and optional FP32 values.
 // ---------------------------------------------------------------------------
+// FP64-vector diagonal SpMV: one row per lane below this many rows (more
+// workgroups where the product is latency-bound), two at and above it
+constexpr int64_t kOneRowMax = 250000;
+
 struct DevMatrix {
     int64_t n = 0;
     int64_t nnz = 0;        // structural nonzeros (CSR)
@@ -88,6 +92,9 @@ struct DevMatrix {
     int spmv_it64 = 1;
     int spmv_it32 = 2;
     int vec_it = 0;   // 0: by size, vec_packs()
+    // rows per lane of the FP64-vector diagonal SpMV: 1 or 2, 0 by size
+    int spmv_rows64 = 0;
+    int rows_per_lane64() const { return spmv_rows64 > 0 ? spmv_rows64 : n < kOneRowMax ? 1 : 2; }
     // packs per thread of the vector updates: vec_it when set, else more
     // workgroups on smaller operators (measured per pressure iteration on the
     // basin operators: 1 pack below 250K rows, 2 below 1M, 3 above)

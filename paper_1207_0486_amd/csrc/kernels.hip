@@ -1869,18 +1869,23 @@ static hns_status spmv_failed(const char *what)
 // vectors), `it` workgroup-sized passes per block, more passes when the grid
 // would exceed the partials slots.
 template <typename TX>
+int sdia_rows(const DevMatrix &A)
+{
+    return sizeof(TX) == 8 ? A.rows_per_lane64() : 1;
+}
+
+template <typename TX>
 Chunks sdia_chunks(const DevMatrix &A)
 {
-    constexpr int R = sizeof(TX) == 8 ? 2 : 1;
+    const int R = sdia_rows<TX>(A);
     const int it = sizeof(TX) == 8 ? A.spmv_it64 : A.spmv_it32;
     return chunks(A.n, (int64_t)kBlock * R * (it > 0 ? it : 1), (int64_t)kBlock * R);
 }
 
-template <typename TV, typename TX, bool DOT, int M>
-int sdia_launch(const DevMatrix &A, const TV *vals, const void *p, void *q, const uint8_t *bc,
-                int bit, const Scalars *sc, double *part, hipStream_t s, hipEvent_t *ev2)
+template <typename TV, typename TX, bool DOT, int M, int R>
+int sdia_launch_r(const DevMatrix &A, const TV *vals, const void *p, void *q, const uint8_t *bc,
+                  int bit, const Scalars *sc, double *part, hipStream_t s, hipEvent_t *ev2)
 {
-    constexpr int R = sizeof(TX) == 8 ? 2 : 1;
     DiaOffsets offs;
     for (int k = 0; k < kMaxDiag; ++k) offs.o[k] = k < A.ndiag ? A.off[k] : 0;
     const Chunks c = sdia_chunks<TX>(A);
@@ -1900,19 +1905,33 @@ int sdia_launch(const DevMatrix &A, const TV *vals, const void *p, void *q, cons
     return c.grid;
 }
 
+template <typename TV, typename TX, bool DOT, int M>
+int sdia_launch(const DevMatrix &A, const TV *vals, const void *p, void *q, const uint8_t *bc,
+                int bit, const Scalars *sc, double *part, hipStream_t s, hipEvent_t *ev2)
+{
+    if constexpr (sizeof(TX) == 8) {
+        if (sdia_rows<TX>(A) == 2)
+            return sdia_launch_r<TV, TX, DOT, M, 2>(A, vals, p, q, bc, bit, sc, part, s, ev2);
+    }
+    return sdia_launch_r<TV, TX, DOT, M, 1>(A, vals, p, q, bc, bit, sc, part, s, ev2);
+}
+
 template <typename TV, typename TX, bool DOT>
 int sdia_wide_launch(const DevMatrix &A, const TV *vals, const void *p, void *q,
                      const uint8_t *bc, int bit, const Scalars *sc, double *part, hipStream_t s,
                      hipEvent_t *ev2)
 {
-    constexpr int R = sizeof(TX) == 8 ? 2 : 1;
     WideOffsets offs;
     for (int k = 0; k < kMaxDiagWide; ++k) offs.o[k] = k < A.ndiag ? A.off[k] : 0;
     const Chunks c = sdia_chunks<TX>(A);
-    if (launch_k(k_spmv_sdia_wide<TV, TX, DOT, R>, c.grid, kBlock, 0, s, ev2, A.n, c.per,
-                 A.ndiag, offs, vals, (const TX *)p, (TX *)q, bc, bit, sc, part) != hipSuccess)
-        return -1;
-    return c.grid;
+    hipError_t e;
+    if (sdia_rows<TX>(A) == 2)
+        e = launch_k(k_spmv_sdia_wide<TV, TX, DOT, 2>, c.grid, kBlock, 0, s, ev2, A.n, c.per,
+                     A.ndiag, offs, vals, (const TX *)p, (TX *)q, bc, bit, sc, part);
+    else
+        e = launch_k(k_spmv_sdia_wide<TV, TX, DOT, 1>, c.grid, kBlock, 0, s, ev2, A.n, c.per,
+                     A.ndiag, offs, vals, (const TX *)p, (TX *)q, bc, bit, sc, part);
+    return e == hipSuccess ? c.grid : -1;
 }
 
 template <typename TV, typename TX, bool DOT, int M = 1>
@@ -2470,13 +2489,13 @@ hipError_t launch_sdia_dir(const IterArgs &a, const T *po, T *pn, uint32_t token
     if constexpr (M <= kMaxDiag) {
         if (a.A->ndiag != M)
             return launch_sdia_dir<T, M + 1>(a, po, pn, token, parity, G_in, s, ev2, grid);
-        constexpr int R = sizeof(T) == 8 ? 2 : 1;
         DiaOffsets offs;
         for (int k = 0; k < kMaxDiag; ++k) offs.o[k] = k < a.A->ndiag ? a.A->off[k] : 0;
         const Chunks c = sdia_chunks<T>(*a.A);
         *grid = c.grid;
         const T *dia = sizeof(T) == 4 ? (const T *)a.A->dia32 : (const T *)a.A->dia;
-        return launch_k(k_sdia_dir<T, M, R>, c.grid, kBlock, 0, s, ev2, a.n, c.per, offs, dia,
+        auto k = sdia_rows<T>(*a.A) == 2 ? k_sdia_dir<T, M, 2> : k_sdia_dir<T, M, 1>;
+        return launch_k(k, c.grid, kBlock, 0, s, ev2, a.n, c.per, offs, dia,
                         po, (const T *)a.r, (T *)a.x, pn, (T *)a.p, (T *)a.q,
                         a.bit < 0 ? (const uint8_t *)nullptr : a.bc, a.bit, a.sc,
                         (const double *)(a.partials + kPartUpdate), G_in,

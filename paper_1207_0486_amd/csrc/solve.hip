@@ -848,6 +848,7 @@ static hns_status scaled_operator(hns_operator *op)
     S.spmv_it64 = A.spmv_it64;
     S.spmv_it32 = A.spmv_it32;
     S.vec_it = A.vec_it;
+    S.spmv_rows64 = A.spmv_rows64;
     double *sh = nullptr;
     float *w = nullptr;
     auto fail = [&](hipError_t e, const char *what) {
@@ -1582,6 +1583,8 @@ hns_status hns_set_param(hns_operator *op, const char *name, double value)
         op->A.spmv_it64 = op->S.spmv_it64 = (int)value;
     } else if (k == "spmv_it32" && value >= 1 && value <= 64 && value == (int)value) {
         op->A.spmv_it32 = op->S.spmv_it32 = (int)value;
+    } else if (k == "spmv_rows64" && (value == 0 || value == 1 || value == 2)) {
+        op->A.spmv_rows64 = op->S.spmv_rows64 = (int)value;
     } else if (k == "vec_it" && value >= 0 && value <= 64 && value == (int)value) {
         op->A.vec_it = op->S.vec_it = (int)value;
     } else if (k == "jacobi_scaling" && (value == 0 || value == 1)) {
