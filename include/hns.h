@@ -384,7 +384,8 @@ int hns_operator_assembly(const hns_operator *op);
  *                  other than -1 are not written to the plan file
  *   "spmv_it64"    launch shape of the single-vector diagonal-storage SpMV with
  *   "spmv_it32"    FP64 / FP32 vectors: workgroup-sized row passes per block
- *                  (defaults 1 and 2; integers 1..64)
+ *                  (integers 1..64; defaults 1, and 0 = by size for FP32: 1
+ *                  below 500000 rows, 2 above)
  *   "spmv_rows64"  rows per lane of the FP64-vector diagonal-storage SpMV
  *                  (1 or 2; default 0 = by size: 1 below 250000 rows, where
  *                  the product is latency-bound and wants more workgroups,

@@ -90,7 +90,11 @@ struct DevMatrix {
     // passes per block of the FP64-vector and FP32-vector diagonal SpMV, and
     // 16-byte packs per thread of the vector updates
     int spmv_it64 = 1;
-    int spmv_it32 = 2;
+    int spmv_it32 = 0;   // 0: by size, spmv_passes32()
+    // workgroup-sized passes per block of the FP32-vector diagonal SpMV:
+    // spmv_it32 when set, else 1 below 500K rows (more workgroups where the
+    // product is latency-bound), 2 above
+    int spmv_passes32() const { return spmv_it32 > 0 ? spmv_it32 : n < 500000 ? 1 : 2; }
     int vec_it = 0;   // 0: by size, vec_packs()
     // rows per lane of the FP64-vector diagonal SpMV: 1 or 2, 0 by size
     int spmv_rows64 = 0;

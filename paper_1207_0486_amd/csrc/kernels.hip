@@ -1878,7 +1878,7 @@ template <typename TX>
 Chunks sdia_chunks(const DevMatrix &A)
 {
     const int R = sdia_rows<TX>(A);
-    const int it = sizeof(TX) == 8 ? A.spmv_it64 : A.spmv_it32;
+    const int it = sizeof(TX) == 8 ? A.spmv_it64 : A.spmv_passes32();
     return chunks(A.n, (int64_t)kBlock * R * (it > 0 ? it : 1), (int64_t)kBlock * R);
 }
 

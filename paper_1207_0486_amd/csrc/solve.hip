@@ -1581,7 +1581,7 @@ hns_status hns_set_param(hns_operator *op, const char *name, double value)
         op->use_graph = (int)value;
     } else if (k == "spmv_it64" && value >= 1 && value <= 64 && value == (int)value) {
         op->A.spmv_it64 = op->S.spmv_it64 = (int)value;
-    } else if (k == "spmv_it32" && value >= 1 && value <= 64 && value == (int)value) {
+    } else if (k == "spmv_it32" && value >= 0 && value <= 64 && value == (int)value) {
         op->A.spmv_it32 = op->S.spmv_it32 = (int)value;
     } else if (k == "spmv_rows64" && (value == 0 || value == 1 || value == 2)) {
         op->A.spmv_rows64 = op->S.spmv_rows64 = (int)value;
