@@ -215,14 +215,16 @@ FUSE_CASES = [
 ]
 
 
+@pytest.mark.parametrize("rows", [1, 2])   # rows per lane of the FP64 products
 @pytest.mark.parametrize("case", FUSE_CASES,
                          ids=[f"bit{c[0]}-{c[1]}-ce{c[2]}-max{c[3]}" for c in FUSE_CASES])
-def test_fused_iterations_equal_three_launch_form(dev, case):
+def test_fused_iterations_equal_three_launch_form(dev, case, rows):
     bit, mode, check_every, max_iter = case
     m = basin.basin_mesh(23, 17, 5, seed=7)   # 2,592 rows: ragged against every tile
     kind, A, d, b, w = _system(m, bit, 70 + bit)
     op = _operator(m, kind, 0, 1, keep_fp32=True)
     op.set_param("check_every", check_every)
+    op.set_param("spmv_rows64", rows)
     got = {}
     for fuse in (0, 1):
         op.set_param("fuse_dir", fuse)
@@ -242,14 +244,16 @@ def test_fused_iterations_equal_three_launch_form(dev, case):
         assert abs(i1.iterations - ref.iterations) <= max(1, 0.02 * ref.iterations)
 
 
+@pytest.mark.parametrize("rows", [1, 2])
 @pytest.mark.parametrize("mode", ["fp64", "mixed"])
-def test_fused_iterations_tiny_mesh(dev, mode):
+def test_fused_iterations_tiny_mesh(dev, mode, rows):
     """A mesh whose rows all lie within the largest offset of an end (every
     row takes the per-row path of the product): the fused form still equals
     the three-launch form bit for bit."""
     m = basin.box_mesh(2, 2, 1)   # 18 rows, largest offset 9
     kind, A, d, b, w = _system(m, -1, 90)
     op = _operator(m, kind, 0, 1, keep_fp32=True)
+    op.set_param("spmv_rows64", rows)
     assert op.format == "sdia" and op.n == 18
     got = {}
     for fuse in (0, 1):
@@ -282,4 +286,34 @@ def test_fused_iterations_automatic_by_size(dev):
     assert counts[-1][2] == counts[0][2]
     with pytest.raises(HNSError):
         op.set_param("fuse_dir", 2)
+    op.close()
+
+
+def test_launch_shapes_keep_the_answer(dev):
+    """Rows per lane of the FP64 product, passes of the FP32 product and
+    packs of the vector updates change the grid (and the summation order of
+    the dot products) only: every shape converges in the oracle's
+    iteration count to the same answer within the parity tolerance, and bad
+    values are refused."""
+    from paper_1207_0486_amd.hns import HNSError
+    m = basin.basin_mesh(23, 17, 5, seed=7)
+    kind, A, d, b, w = _system(m, 0, 95)
+    ref = oracle.pcg(A, b, dirichlet=d, tol=1e-10)
+    op = _operator(m, kind, 0, 1, keep_fp32=True)
+    for mode in ("fp64", "mixed"):
+        xs = []
+        for rows, it32, vec in ((0, 0, 0), (2, 2, 3), (1, 1, 1), (2, 4, 2)):
+            op.set_param("spmv_rows64", rows)
+            op.set_param("spmv_it32", it32)
+            op.set_param("vec_it", vec)
+            x, info = op.solve(_gpu(b, dev), tol=1e-10, mask_bit=0, mode=mode)
+            assert info.status == 0
+            assert abs(info.iterations - ref.iterations) <= max(1, 0.02 * ref.iterations) \
+                or mode == "mixed"
+            xs.append(x.cpu().numpy())
+        for x in xs[1:]:
+            assert _rel(x, xs[0]) <= 1e-9
+    for name, bad in (("spmv_rows64", 3), ("spmv_it32", -1), ("vec_it", 65)):
+        with pytest.raises(HNSError):
+            op.set_param(name, bad)
     op.close()
