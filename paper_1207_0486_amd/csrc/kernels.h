@@ -28,11 +28,14 @@ struct Scalars {
     uint32_t xtoken; // tag of the last iteration whose update ran (x += alpha p pending)
 };
 
-// Layout of the per-workspace partial-sum buffer (doubles)
-constexpr int kPartSpmv = 0;                 // p^T q per SpMV block
-constexpr int kPartUpdate = kMaxPart;        // r^T z, r^T r per update block
-constexpr int kPartMisc = 3 * kMaxPart;      // one-off reductions (3 values)
-constexpr int kPartTotal = 6 * kMaxPart;
+// Layout of the per-workspace partial-sum buffer (doubles).  The FP32 SpMV
+// may take twice kMaxPart workgroups (kMaxPartSpmv32): on the largest
+// operators its rows per block stay at two workgroup passes.
+constexpr int kMaxPartSpmv32 = 2 * kMaxPart;
+constexpr int kPartSpmv = 0;                      // p^T q per SpMV block
+constexpr int kPartUpdate = kMaxPartSpmv32;       // r^T z, r^T r per update block
+constexpr int kPartMisc = kPartUpdate + 2 * kMaxPart;   // one-off reductions (3 values)
+constexpr int kPartTotal = kPartMisc + 3 * kMaxPart;
 
 // grid for a streaming kernel over n entries (multiple of 8 when >= 8)
 int stream_grid(int64_t n);
@@ -40,13 +43,13 @@ int stream_grid(int64_t n);
 int spmv_grid(const DevMatrix &A);
 
 // Contiguous chunks: `grid` workgroups (a multiple of 8 when >= 8, at most
-// kMaxPart) of `per` consecutive units each (a multiple of `quantum`, at
-// least the requested per) cover `units` units.
+// `cap`) of `per` consecutive units each (a multiple of `quantum`, at least
+// the requested per) cover `units` units.
 struct Chunks {
     int grid;
     int64_t per;
 };
-Chunks chunks(int64_t units, int64_t per, int64_t quantum);
+Chunks chunks(int64_t units, int64_t per, int64_t quantum, int64_t cap = kMaxPart);
 
 // Precision of one CG recurrence: matrix values / vectors / Jacobi diagonal
 enum class Prec {

@@ -1879,7 +1879,8 @@ Chunks sdia_chunks(const DevMatrix &A)
 {
     const int R = sdia_rows<TX>(A);
     const int it = sizeof(TX) == 8 ? A.spmv_it64 : A.spmv_passes32();
-    return chunks(A.n, (int64_t)kBlock * R * (it > 0 ? it : 1), (int64_t)kBlock * R);
+    return chunks(A.n, (int64_t)kBlock * R * (it > 0 ? it : 1), (int64_t)kBlock * R,
+                  sizeof(TX) == 8 ? kMaxPart : kMaxPartSpmv32);
 }
 
 template <typename TV, typename TX, bool DOT, int M, int R>
@@ -2564,13 +2565,13 @@ int spmv_grid(const DevMatrix &A)
     return (int)g;
 }
 
-Chunks chunks(int64_t units, int64_t per, int64_t quantum)
+Chunks chunks(int64_t units, int64_t per, int64_t quantum, int64_t cap)
 {
     per = per < quantum ? quantum : (per + quantum - 1) / quantum * quantum;
     int64_t g = (units + per - 1) / per;
-    if (g > kMaxPart) {
+    if (g > cap) {
         // more units per block (whole quanta) to stay within the slots
-        per = ((units + kMaxPart - 1) / kMaxPart + quantum - 1) / quantum * quantum;
+        per = ((units + cap - 1) / cap + quantum - 1) / quantum * quantum;
         g = (units + per - 1) / per;
     }
     if (g < 1) g = 1;
