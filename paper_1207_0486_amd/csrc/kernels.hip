@@ -562,12 +562,45 @@ void k_sdia_dir(int64_t n, int64_t rows, DiaOffsets offs, const TX *__restrict__
                 const double *__restrict__ part_in, int G_in, double *__restrict__ part_out,
                 int parity, uint32_t token)
 {
-    TX alpha = 0, beta = 0;
-    bool dir = true;
-    if (!dir_prologue<TX>(sc, part_in, G_in, parity, token, alpha, beta, dir)) return;
     const int lb = xcd_block(blockIdx.x, gridDim.x);
     const int64_t r0 = (int64_t)lb * rows;
     const int64_t r1 = r0 + rows < n ? r0 + rows : n;
+    // one row per lane: every load of a row (clamped indices, as in
+    // k_spmv_sdia) in one batch; the thread's first row is loaded before the
+    // prologue, so those loads overlap its wait for the update partials
+    struct RowLoads {
+        TX pi, ri, xi, up[M], lo[M], pu[M], ru[M], pl[M], rl[M];
+        bool dm;
+    };
+    auto load_row = [&](int64_t i) {
+        RowLoads L;
+        L.pi = po[i];
+        L.ri = r[i];
+        L.xi = x[i];
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            const int64_t o = offs.o[k];
+            const TX *u = dia + (int64_t)k * n;
+            const int64_t iu = i + o < n ? i + o : n - 1;
+            const int64_t il = i >= o ? i - o : 0;
+            L.up[k] = u[i];
+            L.pu[k] = po[iu];
+            L.ru[k] = r[iu];
+            L.lo[k] = u[il];
+            L.pl[k] = po[il];
+            L.rl[k] = r[il];
+        }
+        L.dm = is_dirichlet(bc, bit, i);
+        return L;
+    };
+    const int64_t i0 = r0 + threadIdx.x;
+    RowLoads first;
+    if constexpr (R == 1) {
+        if (i0 < r1) first = load_row(i0);
+    }
+    TX alpha = 0, beta = 0;
+    bool dir = true;
+    if (!dir_prologue<TX>(sc, part_in, G_in, parity, token, alpha, beta, dir)) return;
     if (!dir) {
         for (int64_t i = r0 + threadIdx.x; i < r1; i += kBlock) {
             const TX pi = po[i];
@@ -578,35 +611,26 @@ void k_sdia_dir(int64_t n, int64_t rows, DiaOffsets offs, const TX *__restrict__
     }
     double acc = 0.0;
     if constexpr (R == 1) {
-        for (int64_t i = r0 + threadIdx.x; i < r1; i += kBlock) {
-            const TX pi = po[i];
-            const TX xo = fma_t(alpha, pi, x[i]);
-            const TX xi = fma_t(beta, pi, r[i]);
+        auto row = [&](int64_t i, const RowLoads &L) {
+            const TX xo = fma_t(alpha, L.pi, L.xi);
+            const TX xi = fma_t(beta, L.pi, L.ri);
             TX sum = xi;
-            TX up[M], lo[M], xu[M], xl[M];
 #pragma unroll
             for (int k = 0; k < M; ++k) {
                 const int64_t o = offs.o[k];
-                const TX *u = dia + (int64_t)k * n;
-                const int64_t iu = i + o < n ? i + o : n - 1;
-                const int64_t il = i >= o ? i - o : 0;
-                up[k] = u[i];
-                xu[k] = fma_t(beta, po[iu], r[iu]);
-                lo[k] = u[il];
-                xl[k] = fma_t(beta, po[il], r[il]);
+                const TX xu = fma_t(beta, L.pu[k], L.ru[k]);
+                const TX xl = fma_t(beta, L.pl[k], L.rl[k]);
+                sum += (i + o < n) ? L.up[k] * xu : (TX)0;
+                sum += (i >= o) ? L.lo[k] * xl : (TX)0;
             }
-#pragma unroll
-            for (int k = 0; k < M; ++k) {
-                const int64_t o = offs.o[k];
-                sum += (i + o < n) ? up[k] * xu[k] : (TX)0;
-                sum += (i >= o) ? lo[k] * xl[k] : (TX)0;
-            }
-            if (is_dirichlet(bc, bit, i)) sum = 0;
+            if (L.dm) sum = 0;
             x[i] = xo;
             pn[i] = xi;
             q[i] = sum;
             acc += (double)xi * (double)sum;
-        }
+        };
+        if (i0 < r1) row(i0, first);
+        for (int64_t i = i0 + kBlock; i < r1; i += kBlock) row(i, load_row(i));
     } else {
         const int64_t omax = offs.o[M - 1];
         for (int64_t i = r0 + (int64_t)threadIdx.x * R; i < r1; i += (int64_t)kBlock * R) {
