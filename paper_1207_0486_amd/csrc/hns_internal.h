@@ -145,10 +145,17 @@ struct IC0Host {
 hns_status ic0_factor_host(const HostCSR &A, const uint8_t *bc, int bit, IC0Host &F);
 
 // IC(0) factor on the device
+// On the device the strict lower factor L and its transpose U are kept per
+// colour in column-major padded rows: colour c's rows r0..r1 (nc = r1 - r0)
+// hold entry k of row r0 + j at [base[c] + k nc + j] for k < width[c] (the
+// colour's longest row), in the order of the host rows; lptr / uptr give
+// each row's length.  Padding entries are column 0, value 0, never read.
 struct IC0Dev {
     int64_t n = 0;
     int ncolors = 0;
     std::vector<int64_t> cstart;   // host copy of the colour starts
+    std::vector<int64_t> lbase, ubase;   // host: start of each colour's block
+    std::vector<int32_t> lwidth, uwidth;  // host: each colour's longest row
     int32_t *perm = nullptr;
     int64_t *lptr = nullptr, *uptr = nullptr;
     int32_t *lcol = nullptr, *ucol = nullptr;

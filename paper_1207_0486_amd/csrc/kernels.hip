@@ -1568,41 +1568,83 @@ __global__ __launch_bounds__(kBlock) void k_pdir_line(int64_t n, int64_t per, T 
 // IC(0) in the multicolour order
 // ---------------------------------------------------------------------------
 // Rows of one colour are not coupled, so each triangular solve is one launch
-// per colour, one lane per row (permuted positions [r0, r1)).
+// per colour, one lane per row (permuted positions [r0, r1)).  The factor
+// rows of a colour are stored column-major (entry k of local row j at
+// k nc + j), so a lane issues the loads of all its entries, then all its
+// gathers of y, instead of one dependent index-then-value round trip per
+// entry; the entries are subtracted in the row's order.  WM entries are
+// held in registers; a longer row takes its remaining entries one by one.
 
-// forward: y_r = (r[perm_r] - sum_t L_rt y_t) / L_rr
+// v - sum_k a_k y[c_k] over the len entries of local row j of a colour block
+template <int WM>
+__device__ __forceinline__ double ic_row_sum(double v, int len, int64_t j, int64_t nc,
+                                             const int32_t *__restrict__ col,
+                                             const double *__restrict__ val,
+                                             const double *__restrict__ y)
+{
+    int32_t c[WM];
+    double a[WM], yv[WM];
+#pragma unroll
+    for (int k = 0; k < WM; ++k) {
+        c[k] = 0;
+        a[k] = 0.0;
+        if (k < len) {
+            c[k] = col[k * nc + j];
+            a[k] = val[k * nc + j];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < WM; ++k) {
+        yv[k] = 0.0;
+        if (k < len) yv[k] = y[c[k]];
+    }
+#pragma unroll
+    for (int k = 0; k < WM; ++k)
+        if (k < len) v -= a[k] * yv[k];
+    for (int k = WM; k < len; ++k) v -= val[k * nc + j] * y[col[k * nc + j]];
+    return v;
+}
+
+// forward: y_r = (r[perm_r] - sum_t L_rt y_t) / L_rr; col / val point at the
+// colour's block
+template <int WM>
 __global__ __launch_bounds__(kBlock) void k_ic_forward(int64_t r0, int64_t r1,
                                                        const int32_t *__restrict__ perm,
                                                        const int64_t *__restrict__ lptr,
-                                                       const int32_t *__restrict__ lcol,
-                                                       const double *__restrict__ lval,
+                                                       const int32_t *__restrict__ col,
+                                                       const double *__restrict__ val,
                                                        const double *__restrict__ diag,
                                                        const double *__restrict__ r,
                                                        double *__restrict__ y)
 {
-    for (int64_t row = r0 + blockIdx.x * (int64_t)kBlock + threadIdx.x; row < r1;
-         row += (int64_t)gridDim.x * kBlock) {
-        double v = r[perm[row]];
-        for (int64_t t = lptr[row]; t < lptr[row + 1]; ++t) v -= lval[t] * y[lcol[t]];
+    const int64_t nc = r1 - r0;
+    for (int64_t j = blockIdx.x * (int64_t)kBlock + threadIdx.x; j < nc;
+         j += (int64_t)gridDim.x * kBlock) {
+        const int64_t row = r0 + j;
+        const int len = (int)(lptr[row + 1] - lptr[row]);
+        const double v = ic_row_sum<WM>(r[perm[row]], len, j, nc, col, val, y);
         y[row] = v / diag[row];
     }
 }
 
 // backward: w_r = (y_r - sum_t U_rt w_t) / L_rr (U = L^T), in place in y;
 // z[perm_r] = w_r
+template <int WM>
 __global__ __launch_bounds__(kBlock) void k_ic_backward(int64_t r0, int64_t r1,
                                                         const int32_t *__restrict__ perm,
                                                         const int64_t *__restrict__ uptr,
-                                                        const int32_t *__restrict__ ucol,
-                                                        const double *__restrict__ uval,
+                                                        const int32_t *__restrict__ col,
+                                                        const double *__restrict__ val,
                                                         const double *__restrict__ diag,
                                                         double *__restrict__ y,
                                                         double *__restrict__ z)
 {
-    for (int64_t row = r0 + blockIdx.x * (int64_t)kBlock + threadIdx.x; row < r1;
-         row += (int64_t)gridDim.x * kBlock) {
-        double v = y[row];
-        for (int64_t t = uptr[row]; t < uptr[row + 1]; ++t) v -= uval[t] * y[ucol[t]];
+    const int64_t nc = r1 - r0;
+    for (int64_t j = blockIdx.x * (int64_t)kBlock + threadIdx.x; j < nc;
+         j += (int64_t)gridDim.x * kBlock) {
+        const int64_t row = r0 + j;
+        const int len = (int)(uptr[row + 1] - uptr[row]);
+        double v = ic_row_sum<WM>(y[row], len, j, nc, col, val, y);
         v /= diag[row];
         y[row] = v;
         z[perm[row]] = v;
@@ -2355,20 +2397,33 @@ hns_status line_iteration(const IterArgs &a, int parity, hipStream_t s, hipEvent
     return check_launch("line-preconditioned cg iteration");
 }
 
-// z = M^-1 r with the IC(0) factor: one launch per colour and direction
+// z = M^-1 r with the IC(0) factor: one launch per colour and direction,
+// rows of up to 8 entries (16 beyond) held in registers
 hns_status ic0_apply(const IC0Dev &F, const double *r, double *y, double *z, hipStream_t s)
 {
     for (int c = 0; c < F.ncolors; ++c) {
         const int64_t r0 = F.cstart[c], r1 = F.cstart[c + 1];
         if (r1 <= r0) continue;
-        k_ic_forward<<<stream_grid(r1 - r0), kBlock, 0, s>>>(r0, r1, F.perm, F.lptr, F.lcol,
-                                                              F.lval, F.diag, r, y);
+        const int32_t *col = F.lcol + F.lbase[c];
+        const double *val = F.lval + F.lbase[c];
+        if (F.lwidth[c] <= 8)
+            k_ic_forward<8><<<stream_grid(r1 - r0), kBlock, 0, s>>>(r0, r1, F.perm, F.lptr, col,
+                                                                     val, F.diag, r, y);
+        else
+            k_ic_forward<16><<<stream_grid(r1 - r0), kBlock, 0, s>>>(r0, r1, F.perm, F.lptr,
+                                                                      col, val, F.diag, r, y);
     }
     for (int c = F.ncolors - 1; c >= 0; --c) {
         const int64_t r0 = F.cstart[c], r1 = F.cstart[c + 1];
         if (r1 <= r0) continue;
-        k_ic_backward<<<stream_grid(r1 - r0), kBlock, 0, s>>>(r0, r1, F.perm, F.uptr, F.ucol,
-                                                               F.uval, F.diag, y, z);
+        const int32_t *col = F.ucol + F.ubase[c];
+        const double *val = F.uval + F.ubase[c];
+        if (F.uwidth[c] <= 8)
+            k_ic_backward<8><<<stream_grid(r1 - r0), kBlock, 0, s>>>(r0, r1, F.perm, F.uptr,
+                                                                      col, val, F.diag, y, z);
+        else
+            k_ic_backward<16><<<stream_grid(r1 - r0), kBlock, 0, s>>>(r0, r1, F.perm, F.uptr,
+                                                                       col, val, F.diag, y, z);
     }
     return check_launch("ic0 triangular solves");
 }

@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <thread>
 
 #include "kernels.h"
 
@@ -1798,6 +1799,42 @@ static hns_status ic0_factors(hns_operator *op, int bit, const IC0Dev **out)
         D->n = H.n;
         D->ncolors = H.ncolors;
         D->cstart = H.cstart;
+        // the factor rows of each colour in column-major padded blocks
+        std::vector<int32_t> lcol, ucol;
+        std::vector<double> lval, uval;
+        auto by_colour = [&](const std::vector<int64_t> &ptr, const std::vector<int32_t> &col,
+                             const std::vector<double> &val, std::vector<int64_t> &base,
+                             std::vector<int32_t> &width, std::vector<int32_t> &ecol,
+                             std::vector<double> &eval) {
+            base.assign(H.ncolors, 0);
+            width.assign(H.ncolors, 0);
+            int64_t total = 0;
+            for (int c = 0; c < H.ncolors; ++c) {
+                int64_t w = 0;
+                for (int64_t r = H.cstart[c]; r < H.cstart[c + 1]; ++r)
+                    w = std::max(w, ptr[r + 1] - ptr[r]);
+                base[c] = total;
+                width[c] = (int32_t)w;
+                total += w * (H.cstart[c + 1] - H.cstart[c]);
+            }
+            ecol.assign(total, 0);
+            eval.assign(total, 0.0);
+            // the colours' blocks are disjoint: one thread per colour
+            std::vector<std::thread> th;
+            for (int c = 0; c < H.ncolors; ++c)
+                th.emplace_back([&, c] {
+                    const int64_t r0 = H.cstart[c], nc = H.cstart[c + 1] - r0;
+                    for (int64_t j = 0; j < nc; ++j)
+                        for (int64_t t = ptr[r0 + j]; t < ptr[r0 + j + 1]; ++t) {
+                            const int64_t e = base[c] + (t - ptr[r0 + j]) * nc + j;
+                            ecol[e] = col[t];
+                            eval[e] = val[t];
+                        }
+                });
+            for (auto &t : th) t.join();
+        };
+        by_colour(H.lptr, H.lcol, H.lval, D->lbase, D->lwidth, lcol, lval);
+        by_colour(H.uptr, H.ucol, H.uval, D->ubase, D->uwidth, ucol, uval);
         auto up = [&](const void *src, size_t bytes, void **dst) -> hns_status {
             hipError_t e = hipMalloc(dst, bytes > 0 ? bytes : 8);
             if (e != hipSuccess) {
@@ -1814,10 +1851,10 @@ static hns_status ic0_factors(hns_operator *op, int bit, const IC0Dev **out)
             HNS_TRY(up(H.perm.data(), H.perm.size() * 4, (void **)&D->perm));
             HNS_TRY(up(H.lptr.data(), H.lptr.size() * 8, (void **)&D->lptr));
             HNS_TRY(up(H.uptr.data(), H.uptr.size() * 8, (void **)&D->uptr));
-            HNS_TRY(up(H.lcol.data(), H.lcol.size() * 4, (void **)&D->lcol));
-            HNS_TRY(up(H.ucol.data(), H.ucol.size() * 4, (void **)&D->ucol));
-            HNS_TRY(up(H.lval.data(), H.lval.size() * 8, (void **)&D->lval));
-            HNS_TRY(up(H.uval.data(), H.uval.size() * 8, (void **)&D->uval));
+            HNS_TRY(up(lcol.data(), lcol.size() * 4, (void **)&D->lcol));
+            HNS_TRY(up(ucol.data(), ucol.size() * 4, (void **)&D->ucol));
+            HNS_TRY(up(lval.data(), lval.size() * 8, (void **)&D->lval));
+            HNS_TRY(up(uval.data(), uval.size() * 8, (void **)&D->uval));
             HNS_TRY(up(H.diag.data(), H.diag.size() * 8, (void **)&D->diag));
             return HNS_OK;
         };
