@@ -372,7 +372,10 @@ int hns_operator_assembly(const hns_operator *op);
  *                    FP64 correction x += |r| d;
  *                  2 FP32 matrix and diagonal with FP64 vectors, with the same
  *                    FP64 residual replacement as 0
- *   "replace_drop" residual drop between FP64 replacements (default 0.1)
+ *   "replace_drop" residual drop between FP64 replacements, 0 < drop < 1
+ *                  (default: 1e-3 where the FP32 recurrence of hns_solve runs
+ *                  in one workgroup, up to "small_n" rows, since each
+ *                  replacement costs two host round trips there; else 0.1)
  *   "use_graph"    1 = replay captured HIP graphs for the iteration chunks of
  *                  hns_solve_batched (default 0)
  *   "bspmm_vec"    columns per thread of the batched kernels: 0 = autotune

@@ -1501,7 +1501,7 @@ hns_status solve_batched_impl(hns_operator *op, BWorkspace *w, int K, const int 
     BCtx c = bctx(op, w, K, V, B, X, s, mixed);
     const int64_t n = op->n;
     const int64_t ne = n * (int64_t)K;
-    const double drop2 = mixed ? op->replace_drop * op->replace_drop : 0.0;
+    const double drop2 = mixed ? replace_drop_of(op, false) * replace_drop_of(op, false) : 0.0;
     // per-column set-up
     for (int j = 0; j < K; ++j) {
         BCol &h = w->host[j];
@@ -1919,7 +1919,7 @@ hns_status session_service(hns_batch *bt, hipStream_t s)
     const int K = bt->K;
     const int64_t n = bt->op->n;
     BCtx c = bctx(bt->op, w, K, bt->V, bt->B, bt->X, s, bt->mixed);
-    const double drop2 = bt->mixed ? bt->op->replace_drop * bt->op->replace_drop : 0.0;
+    const double drop2 = bt->mixed ? replace_drop_of(bt->op, false) * replace_drop_of(bt->op, false) : 0.0;
     const int G1 = bgrid(n * (int64_t)K, K, 1);
     for (int round = 0; round < 4; ++round) {
         bool changed = false;
@@ -2133,7 +2133,7 @@ hns_status hns_batch_add(hns_batch *bt, int count, const int *slots, const int *
                                    hipMemcpyHostToDevice, s));
         k_bmark_list<<<1, kBlock, 0, s>>>(K, w->cols, bt->slot_buf, (int)ok.size());
         BCtx c = bctx(op, w, K, bt->V, bt->B, bt->X, s, bt->mixed);
-        const double drop2 = bt->mixed ? op->replace_drop * op->replace_drop : 0.0;
+        const double drop2 = bt->mixed ? replace_drop_of(op, false) * replace_drop_of(op, false) : 0.0;
         HNS_TRY(true_residual(c, drop2, 1));
         HNS_TRY(new_segment(c));
     }

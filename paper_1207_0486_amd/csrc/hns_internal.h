@@ -203,7 +203,7 @@ struct hns_operator {
     int max_outer = 30;
     int mixed_variant = 0;        // 0 FP32 + replacement, 1 restarted refinement,
                                   // 2 FP32 storage with FP64 vectors
-    double replace_drop = 0.1;    // FP32 residual drop that triggers a replacement
+    double replace_drop = 0;      // FP32 residual drop that triggers a replacement (0: by size)
     int use_graph = 0;
     // kernel timing (hns_profile_*)
     int profile = 0;
@@ -255,6 +255,16 @@ struct hns_operator {
 };
 
 namespace hns {
+
+// Drop of the FP32 recursive residual between FP64 residual replacements: the
+// "replace_drop" tunable when set, else 1e-3 where the FP32 recurrence runs in
+// one workgroup (the two host round trips of each replacement outweigh the
+// iterations between them there) and 0.1 elsewhere.
+inline double replace_drop_of(const hns_operator *op, bool one_workgroup)
+{
+    if (op->replace_drop > 0) return op->replace_drop;
+    return one_workgroup ? 1e-3 : 0.1;
+}
 
 // per-slot batch sessions (solve.hip)
 struct SlotSession;

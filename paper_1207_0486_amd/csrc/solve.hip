@@ -508,7 +508,9 @@ struct ChunkedSolve {
         }
         tol2 = c.tol * c.tol;
         if (mixed) {
-            drop2 = op->replace_drop * op->replace_drop;
+            const double drop = replace_drop_of(
+                op, small_chunks(op, w, Prec::F32, c.lfac32, nullptr, c.scaled));
+            drop2 = drop * drop;
             rr_prev = h.rr;
             if (!(h.rr > tol2 * h.bb)) {
                 status = HNS_OK;
@@ -517,7 +519,7 @@ struct ChunkedSolve {
         } else {
             const bool storage = (prec == Prec::F32Store);
             dinv = storage ? (const void *)op->dinv32 : (const void *)op->dinv;
-            drop2 = storage ? op->replace_drop * op->replace_drop : 0.0;
+            drop2 = storage ? replace_drop_of(op, false) * replace_drop_of(op, false) : 0.0;
             rr_true = h.rr;
             bb = h.bb;
             rr_prev = h.rr;
