@@ -1330,6 +1330,11 @@ struct LinePacks {
     Pack<T, W> p, z;
 };
 
+constexpr int kLineLds = 49152;   // bytes of LDS for the staged columns of one block
+// rows of a block's columns a thread stages at most: a block stages at most
+// kLineLds / (4 * 8) rows (4 FP64-sized arrays of its rows in LDS)
+constexpr int kLineStage = (kLineLds / (4 * 8) + kBlock - 1) / kBlock;
+
 // r -= alpha q; z = M^-1 r; partials of r^T z and r^T r.  Block 0 records
 // alpha and the iteration tag (x += alpha p is done by k_pupdate_line_x).
 template <typename T>
@@ -1339,6 +1344,27 @@ __global__ __launch_bounds__(kBlock) void k_update_line(
     int G_in, double *__restrict__ part_out, int parity, uint32_t token)
 {
     extern __shared__ double line_lds[];
+    const int span = NC * L;   // at most kLineStage * kBlock rows (NC from kLineLds)
+    T *sr = reinterpret_cast<T *>(line_lds), *se = sr + span, *sw = se + span, *sy = sw + span;
+    const int64_t row0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * span;
+    const int64_t left = n - row0;
+    const int rows = left <= 0 ? 0 : (left < span ? (int)left : span);
+    const T *le = lfac, *lw = lfac + n;
+    // every load of the thread's rows is issued first, ahead of the partials
+    // that alpha waits for (one round trip instead of one per row)
+    T rv[kLineStage], qv[kLineStage], ev[kLineStage], wv[kLineStage];
+#pragma unroll
+    for (int u = 0; u < kLineStage; ++u) {
+        const int t = threadIdx.x + u * kBlock;
+        rv[u] = qv[u] = ev[u] = wv[u] = (T)0;
+        if (t < rows) {
+            const int64_t i = row0 + t;
+            rv[u] = r[i];
+            qv[u] = q[i];
+            ev[u] = le[i];
+            wv[u] = lw[i];
+        }
+    }
     // the stop flag is read beside the partials rather than before them
     const int stopped = sc->stop;
     double g[1];
@@ -1359,21 +1385,18 @@ __global__ __launch_bounds__(kBlock) void k_update_line(
         sc->xtoken = token;
     }
     const T alpha = (T)alpha_d;
-    const int span = NC * L;
-    T *sr = reinterpret_cast<T *>(line_lds), *se = sr + span, *sw = se + span, *sy = sw + span;
-    const int64_t row0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * span;
-    const int64_t left = n - row0;
-    const int rows = left <= 0 ? 0 : (left < span ? (int)left : span);
-    const T *le = lfac, *lw = lfac + n;
     double rr = 0.0;
-    for (int t = threadIdx.x; t < rows; t += kBlock) {
-        const int64_t i = row0 + t;
-        const T ri = r[i] - alpha * q[i];
-        r[i] = ri;
-        sr[t] = ri;
-        se[t] = le[i];
-        sw[t] = lw[i];
-        rr += (double)ri * (double)ri;
+#pragma unroll
+    for (int u = 0; u < kLineStage; ++u) {
+        const int t = threadIdx.x + u * kBlock;
+        if (t < rows) {
+            const T ri = rv[u] - alpha * qv[u];
+            r[row0 + t] = ri;
+            sr[t] = ri;
+            se[t] = ev[u];
+            sw[t] = wv[u];
+            rr += (double)ri * (double)ri;
+        }
     }
     __syncthreads();
     const double rz = line_columns<T>(rows / L, L, sr, se, sw, sy);
@@ -2349,7 +2372,6 @@ int spmv_dispatch(const DevMatrix &A, const void *p, void *q, const uint8_t *bc,
 
 inline bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 
-constexpr int kLineLds = 49152;   // bytes of LDS for the staged columns of one block
 
 // Event pairs of a timed iteration: ev[0..1] SpMV, ev[2..3] update,
 // ev[4..5] direction update (each recorded by its kernel's dispatch).
