@@ -1595,8 +1595,9 @@ __global__ __launch_bounds__(kBlock) void k_pdir_line(int64_t n, int64_t per, T 
 // rows of a colour are stored column-major (entry k of local row j at
 // k nc + j), so a lane issues the loads of all its entries, then all its
 // gathers of y, instead of one dependent index-then-value round trip per
-// entry; the entries are subtracted in the row's order.  WM entries are
-// held in registers; a longer row takes its remaining entries one by one.
+// entry; the entries are subtracted in the row's order.  A row is taken in
+// groups of WM entries held in registers (one group for the P1 stencils; the
+// longer rows of the Q2 bricks take several).
 
 // v - sum_k a_k y[c_k] over the len entries of local row j of a colour block
 template <int WM>
@@ -1605,26 +1606,27 @@ __device__ __forceinline__ double ic_row_sum(double v, int len, int64_t j, int64
                                              const double *__restrict__ val,
                                              const double *__restrict__ y)
 {
-    int32_t c[WM];
-    double a[WM], yv[WM];
+    for (int k0 = 0; k0 < len; k0 += WM) {
+        int32_t c[WM];
+        double a[WM], yv[WM];
 #pragma unroll
-    for (int k = 0; k < WM; ++k) {
-        c[k] = 0;
-        a[k] = 0.0;
-        if (k < len) {
-            c[k] = col[k * nc + j];
-            a[k] = val[k * nc + j];
+        for (int k = 0; k < WM; ++k) {
+            c[k] = 0;
+            a[k] = 0.0;
+            if (k0 + k < len) {
+                c[k] = col[(int64_t)(k0 + k) * nc + j];
+                a[k] = val[(int64_t)(k0 + k) * nc + j];
+            }
         }
-    }
 #pragma unroll
-    for (int k = 0; k < WM; ++k) {
-        yv[k] = 0.0;
-        if (k < len) yv[k] = y[c[k]];
-    }
+        for (int k = 0; k < WM; ++k) {
+            yv[k] = 0.0;
+            if (k0 + k < len) yv[k] = y[c[k]];
+        }
 #pragma unroll
-    for (int k = 0; k < WM; ++k)
-        if (k < len) v -= a[k] * yv[k];
-    for (int k = WM; k < len; ++k) v -= val[k * nc + j] * y[col[k * nc + j]];
+        for (int k = 0; k < WM; ++k)
+            if (k0 + k < len) v -= a[k] * yv[k];
+    }
     return v;
 }
 
@@ -2420,7 +2422,8 @@ hns_status line_iteration(const IterArgs &a, int parity, hipStream_t s, hipEvent
 }
 
 // z = M^-1 r with the IC(0) factor: one launch per colour and direction,
-// rows of up to 8 entries (16 beyond) held in registers
+// rows taken 8 entries at a time where a colour's rows have at most 8, else
+// 16 at a time
 hns_status ic0_apply(const IC0Dev &F, const double *r, double *y, double *z, hipStream_t s)
 {
     for (int c = 0; c < F.ncolors; ++c) {
