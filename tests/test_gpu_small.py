@@ -100,6 +100,36 @@ def test_small_chunk_cap_zero_rhs_and_mixed(dev):
         assert _rel(x.cpu().numpy(), ref) <= 1e-9
 
 
+def test_mixed_replacement_drop_by_path(dev):
+    """The FP32 residual drop between FP64 replacements: 1e-3 by default where
+    the FP32 recurrence runs in one workgroup (the 16x16x4 box, 1,445 rows:
+    at most 5 replacements to 1e-10), 0.1 on the multi-launch path and when
+    set explicitly (about 10); every variant meets the tolerance by the
+    oracle's residual and lands within 1e-9 of the oracle's tight solution."""
+    from paper_1207_0486_amd.hns import Operator
+    m = basin.box_mesh(16, 16, 4, gamma0=basin.mesh.WALLS)
+    d = (m.bc & 1) == 1
+    b = basin.normal_rhs(m.n, 12, dirichlet=d, zero_mean=True)
+    A = oracle.stiffness(m, 1.0, 1e-4)
+    ref = oracle.pcg(A, b, dirichlet=d, tol=1e-13).x
+    outer = {}
+    for name, small, drop in (("one", DEFAULT_SMALL, None), ("multi", 0, None),
+                              ("one_set", DEFAULT_SMALL, 0.1)):
+        op = Operator(m, 1.0, 1e-4, kind="poisson", keep_fp32=True)
+        op.set_param("small_n", small)
+        if drop is not None:
+            op.set_param("replace_drop", drop)
+        x, info = op.solve(_gpu(b, dev), tol=1e-10, mask_bit=0, mode="mixed")
+        assert info.status == 0
+        xh = x.cpu().numpy()
+        assert oracle.relres(A, b, xh, d) <= 1.01e-10
+        assert _rel(xh, ref) <= 1e-9
+        outer[name] = info.outer_iterations
+        op.close()
+    assert outer["one"] <= 5
+    assert outer["multi"] >= 8 and outer["one_set"] >= 8
+
+
 @pytest.mark.parametrize("n_side", [(15, 15, 15), (31, 31, 15), (32, 32, 15)])
 def test_small_chunk_at_larger_sizes(dev, n_side):
     """The chunk kernel forced on 4096, 16384 and 17424 rows (4 to 18 rows
