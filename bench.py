@@ -954,6 +954,40 @@ def serving_check(torch, log, items, results, make, mode, tol, cache, line_press
     return {"ok": ok, "samples": rows}
 
 
+def batched_probe(torch, log, iters=6, k=48):
+    """Short run for hardware-counter passes over the batched product: a
+    plain 1 GiB device copy (the calibration kernel), then `iters` iterations
+    of the FP64 and of the mixed block solve of k seeded N(0,1) columns
+    (Dirichlet rows zeroed per column's set) on the 128x128x20 velocity
+    operator, with the grid-stride product at 4 columns per thread."""
+    import basin
+    from paper_1207_0486_amd.hns import Operator
+    dev = torch.device("cuda", 0)
+    a = torch.ones(1 << 27, dtype=torch.float64, device=dev)       # 1 GiB
+    c = torch.empty_like(a)
+    c.copy_(a)
+    torch.cuda.synchronize()
+    del a, c
+    wl = basin.configs.BASIN_128x128x20_BATCH
+    m = wl.mesh()
+    op = Operator(m, wl.nu_h, wl.nu_v, wl.dt, kind="helmholtz", keep_fp32=True)
+    op.set_param("bspmm_vec", 4)
+    op.set_param("bspmm_tile", 0)
+    bits = [j % 3 for j in range(k)]
+    B = np.random.default_rng(0).standard_normal((m.n, k))
+    for j, bit in enumerate(bits):
+        B[((m.bc >> bit) & 1) == 1, j] = 0.0
+    B = torch.as_tensor(B, device=dev)
+    out = {"probe": "batched", "nodes": m.n, "rhs": k, "copy_bytes": 2 * (1 << 27) * 8}
+    for mode in ("fp64", "mixed"):
+        X, infos = op.solve_batched(B, mask_bits=bits, tol=1e-10, max_iter=iters, mode=mode,
+                                    check=False)
+        torch.cuda.synchronize()
+        out[mode] = {"iterations": max(i.iterations for i in infos)}
+    op.close()
+    print(json.dumps(out), flush=True)
+
+
 def traffic_probe(torch, log, iters=64, q2_iters=16):
     """Short run for hardware-counter passes: a plain 1 GiB device copy (the
     calibration kernel of known size), 64 iterations of the 256x256x20
@@ -1025,6 +1059,9 @@ def main():
     ap.add_argument("--traffic-probe", action="store_true",
                     help="only a 1 GiB copy, 64 pressure iterations and 16 Q2 velocity "
                          "iterations (for counter passes)")
+    ap.add_argument("--batched-probe", action="store_true",
+                    help="only a 1 GiB copy and 6 iterations of the 48-column FP64 and mixed "
+                         "block solves on 128x128x20 (for counter passes)")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serve-budget-gb", type=float, default=1.5,
                     help="HBM budget of the serving stream (its ten operators hold 2.7-3.7 GB)")
@@ -1047,6 +1084,10 @@ def main():
     if args.traffic_probe:
         import torch
         traffic_probe(torch, log)
+        return
+    if args.batched_probe:
+        import torch
+        batched_probe(torch, log)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the solver "
